@@ -1,0 +1,184 @@
+/*
+ * mra.h -- C ABI of libmra: separated-operator apply on Legendre multiwavelet octrees
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the statement of the problem in the example of Sec. 3.1 of
+ * Harrison et al., "MADNESS: a multiresolution, adaptive numerical environment for
+ * scientific simulation" (arXiv:1507.01888): a cubic cell, an operator built from
+ * (lo, eps), the adaptive projection of a function with (k, thresh), op(g), and the
+ * trace / 2-norm / inner product of the result.
+ *
+ * Conventions
+ *  - Every call returns an mra_status: MRA_OK (0) or a negative error code.  Output
+ *    pointers are written only on success.  No C++ exception crosses the ABI.  The
+ *    message of the last failure on a context is returned by mra_last_error().
+ *  - Host pointers are plain host memory, read during the call and not retained.
+ *  - Device memory is obtained through the context's allocator callbacks (or
+ *    hipMalloc/hipFree when none are given) and released by the *_free calls.
+ *  - All device work is issued on the context's HIP stream.  Calls that return host
+ *    values (norms, exports, stats) synchronise that stream.
+ *  - A context is not thread-safe; handles belong to the context that made them.
+ *
+ * Error codes
+ *  MRA_E_INVALID      bad argument: k outside [2, 14] (non-standard apply: k <= 10),
+ *                     thresh <= 0, cell_hi <= cell_lo, ng < 1, M < 1, expnt <= 0, ...
+ *  MRA_E_NOMEM        the allocator returned NULL
+ *  MRA_E_DEVICE       a HIP runtime error (its text is in the message)
+ *  MRA_E_UNSUPPORTED  a combination this build does not implement
+ *  MRA_E_MISMATCH     operator and function disagree on k or context
+ */
+#ifndef MRA_H
+#define MRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int mra_status;
+#define MRA_OK 0
+#define MRA_E_INVALID (-1)
+#define MRA_E_NOMEM (-2)
+#define MRA_E_DEVICE (-3)
+#define MRA_E_UNSUPPORTED (-4)
+#define MRA_E_MISMATCH (-5)
+
+typedef struct mra_ctx mra_ctx;
+typedef struct mra_func mra_func;
+typedef struct mra_op mra_op;
+
+/* Device allocator callbacks: alloc returns a device pointer of at least nbytes (NULL on
+ * failure); free releases it.  user is passed through unchanged. */
+typedef void* (*mra_alloc_fn)(size_t nbytes, void* user);
+typedef void (*mra_free_fn)(void* ptr, void* user);
+
+/* One term coeff * exp(-expnt |x - center|^2) of a Gaussian-sum function. */
+typedef struct {
+  double coeff;
+  double expnt;
+  double center[3];
+} mra_gaussian;
+
+/* Adaptive projection parameters (Sec. 2.1): wavelet order k (number of Legendre
+ * polynomials per dimension), refinement threshold thresh on the Frobenius norm of a box's
+ * wavelet coefficients, uniform starting level and deepest level (<= 20). */
+typedef struct {
+  int k;
+  double thresh;
+  int initial_level;
+  int max_level;
+} mra_project_params;
+
+#define MRA_FORM_NONSTANDARD 0
+#define MRA_FORM_STANDARD 1
+
+/* Apply parameters.
+ *  form         MRA_FORM_NONSTANDARD: telescoped non-standard form of Sec. 2.2 on an
+ *               adaptive tree; MRA_FORM_STANDARD: level-n operator P^n T P^n on a uniform
+ *               tree with displacements |delta|_inf <= disp_radius, no screening.
+ *  tau_drop     non-standard form: a (box, displacement, term) triple is applied iff its
+ *               norm bound eta = |c_mu| N(delta) ||B_P||_F is >= tau_drop.
+ *  disp_radius  standard form only. */
+typedef struct {
+  int form;
+  int disp_radius;
+  double tau_drop;
+} mra_apply_params;
+
+/* Counters of the last mra_apply on a context. */
+typedef struct {
+  int64_t triples;        /* kept (box, displacement, term) triples                  */
+  int64_t targets;        /* distinct target boxes                                   */
+  int64_t in_leaves;      /* leaves of the input tree                                */
+  int64_t out_nodes;      /* nodes of the output tree                                */
+  int64_t out_leaves;     /* leaves of the output tree                               */
+  double useful_flops;    /* sum over triples of 6(2k)^4 + 6k^4 [n>0] (6k^4 standard) */
+  double ms_filter;       /* device time of filter-up                                */
+  double ms_plan;         /* host time of screening and planning (incl. copies)      */
+  double ms_apply;        /* device time of the transform-and-accumulate kernels     */
+  double ms_sumdown;      /* device time of sum-down                                 */
+  double ms_main_kernel;  /* device time of the non-standard (or standard) main kernel */
+} mra_apply_stats;
+
+/* Create a context on HIP device `device` using HIP stream `stream` (NULL: the null
+ * stream) and the cubic cell [cell_lo, cell_hi]^3 (Sec. 3.1, set_cubic_cell). alloc/free
+ * may both be NULL (hipMalloc/hipFree are used). */
+mra_status mra_ctx_create(int device, void* stream, mra_alloc_fn alloc, mra_free_fn free_fn,
+                          void* user, double cell_lo, double cell_hi, mra_ctx** out);
+mra_status mra_ctx_free(mra_ctx* ctx);
+/* Message of the last failure on ctx ("" if none).  Valid until the next call on ctx.
+ * With ctx == NULL: the message of the last failed mra_ctx_create on this thread. */
+const char* mra_last_error(const mra_ctx* ctx);
+
+/* Adaptive projection of sum_g coeff_g exp(-expnt_g |x - center_g|^2) (Sec. 2.1, eq.
+ * projection): exact separable 1D integrals, refinement of a box iff the norm of its
+ * wavelet coefficients exceeds thresh. The result lives in device memory. */
+mra_status mra_project(mra_ctx* ctx, const mra_gaussian* g, int ng,
+                       const mra_project_params* params, mra_func** out);
+
+/* Tree size of a function. */
+mra_status mra_func_info(const mra_func* f, int* k, int64_t* nodes, int64_t* leaves,
+                         int* max_level);
+/* Copy the leaves out: keys[i] is the level-prefixed Morton code
+ * (1 << 3n) | interleave(lx, ly, lz) (x in the highest bit of each triple), coeffs holds
+ * nleaves * k^3 doubles, each leaf row-major [i][j][m].  Leaves are ordered by level,
+ * then by key.  cap is the capacity of keys in leaves; *nleaves receives the count. */
+mra_status mra_func_export(mra_ctx* ctx, const mra_func* f, int64_t cap, uint64_t* keys,
+                           double* coeffs, int64_t* nleaves);
+mra_status mra_func_free(mra_func* f);
+
+/* Operators: sum_mu c_mu exp(-t_mu r^2), with the 1D operator blocks for wavelet order k
+ * cached per (level, displacement, term) on first use (Sec. 2.2 Toeplitz blocks).
+ *  mra_op_coulomb   1/r to relative eps on [lo, sqrt(3) W] (Sec. 2.3 quadrature).
+ *  mra_op_bsh       exp(-mu r)/r (kernel of eq. bshkernel without 1/(4 pi)), error eps/r.
+ *  mra_op_gaussians explicit terms (M >= 1, t > 0). */
+mra_status mra_op_coulomb(mra_ctx* ctx, int k, double lo, double eps, mra_op** out);
+mra_status mra_op_bsh(mra_ctx* ctx, int k, double mu, double lo, double eps, mra_op** out);
+mra_status mra_op_gaussians(mra_ctx* ctx, int k, int M, const double* c, const double* t,
+                            mra_op** out);
+/* Number of terms and the terms themselves (c, t may be NULL to query M only). */
+mra_status mra_op_terms(const mra_op* op, int* M, double* c, double* t);
+mra_status mra_op_free(mra_op* op);
+
+/* op(f) (Sec. 3.1 example; Sec. 2.2-2.3 method).  The result is a new function on the
+ * output tree (input tree, all targets with their children, their ancestors). */
+mra_status mra_apply(mra_ctx* ctx, const mra_op* op, const mra_func* f,
+                     const mra_apply_params* params, mra_func** out);
+
+/* 2-norm sqrt(sum over leaves ||s||^2) (orthonormal basis), FP64, fixed-order reduction. */
+mra_status mra_norm2(mra_ctx* ctx, const mra_func* f, double* out);
+/* Integral of f over the cell: sum over leaves s_000 h_n^{3/2}. */
+mra_status mra_trace(mra_ctx* ctx, const mra_func* f, double* out);
+/* <f, g> over the cell; both must have the same k. */
+mra_status mra_inner(mra_ctx* ctx, const mra_func* f, const mra_func* g, double* out);
+
+/* Counters of the last mra_apply on ctx. */
+mra_status mra_last_stats(const mra_ctx* ctx, mra_apply_stats* out);
+
+/* ---------------------------------------------------------------- host-only helpers
+ * These run on the host only (no device, no context) and expose the library's FP64 host
+ * numerics for testing.  Arrays are caller-owned host memory.
+ *
+ * mra_host_fit: kind 0 = Coulomb 1/r, 1 = exp(-mu r)/r; range [lo, r_hi], accuracy eps.
+ *   With c == t == NULL only *M is written; otherwise cap must be >= M.
+ * mra_host_block: the k x k block t^{n,delta} (row-major, rows = target index) of
+ *   exp(-texp r^2) between boxes of width h at displacement delta (Sec. 2.2 Toeplitz).
+ * mra_host_filters: two-scale filters h0, h1 (row-major k x k).
+ * mra_host_spectral_norm: largest singular value of a row-major m x m matrix.
+ * mra_host_project: adaptive projection on the host; leaves as in mra_func_export. */
+mra_status mra_host_fit(int kind, double mu, double lo, double eps, double r_hi, int cap,
+                        double* c, double* t, int* M);
+mra_status mra_host_block(int k, double h, int delta, double texp, double* out);
+mra_status mra_host_filters(int k, double* h0, double* h1);
+mra_status mra_host_spectral_norm(int m, const double* a, double* out);
+mra_status mra_host_project(double cell_lo, double cell_hi, const mra_gaussian* g, int ng,
+                            const mra_project_params* params, int64_t cap, uint64_t* keys,
+                            double* coeffs, int64_t* nleaves);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRA_H */

@@ -185,18 +185,24 @@ def screen_level(bf, lev, op, tau, k, target_codes=None):
     return groups
 
 
-def nonstandard_contributions(f, op, tau_drop, sample_targets=None):
+def nonstandard_contributions(f, op, tau_drop, sample_targets=None, only_levels=None,
+                              levels=None, blocks=None):
     """acc_T (children basis) and sub_T for every target (or for the sampled targets).
 
     Returns (levels, contrib, stats) where contrib[n] = (target_keys, acc, sub) with
-    acc of shape (NT, 2k, 2k, 2k) and sub of shape (NT, k, k, k).
+    acc of shape (NT, 2k, 2k, 2k) and sub of shape (NT, k, k, k).  only_levels restricts
+    the source levels that are processed; levels / blocks may pass a previous filter_up
+    result and BlockFactory.
     """
     k = f.k
-    bf = BlockFactory(k, f.width)
-    levels = filter_up(f)
+    bf = blocks if blocks is not None else BlockFactory(k, f.width)
+    if levels is None:
+        levels = filter_up(f)
     contrib = {}
     stats = {"triples": 0, "useful_flops": 0.0, "per_level": {}}
     for n, lev in levels.items():
+        if only_levels is not None and n not in only_levels:
+            continue
         tcodes = None
         if sample_targets is not None:
             want = np.array([kk[1:] for kk in sample_targets if kk[0] == n], dtype=np.int64).reshape(-1, 3)

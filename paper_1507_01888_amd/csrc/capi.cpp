@@ -1,0 +1,934 @@
+// C ABI of libmra: contexts, functions, operators, the apply planner and reductions.
+//
+// mra_apply (non-standard form, Sec. 2.2-2.3) runs these steps on the context's stream:
+//   1. filter-up (device): s_P and ||B_P||_F for every refined box, bottom-up;
+//   2. screening (host, from the norms): triples (P, delta, mu) with
+//      eta = |c_mu| N(delta) ||B_P||_F >= tau_drop, targets inside the cell;
+//   3. output tree (targets, their children, ancestors, closed under siblings) and the
+//      target-sorted work list; operator blocks missing from the cache are computed;
+//   4. transform-and-accumulate (device): children blocks of every target, and the level-n
+//      subtraction for targets below the root;
+//   5. sum-down (device), level by level.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "mra_internal.hpp"
+
+struct mra_ctx {
+  mra::Ctx c;
+};
+struct mra_func {
+  mra::Func f;
+};
+struct mra_op {
+  mra::Op o;
+};
+
+namespace mra {
+
+void fail(mra_status code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(MRA_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* Ctx::dalloc(size_t bytes) {
+  if (bytes == 0) return nullptr;
+  void* p = nullptr;
+  if (alloc) {
+    p = alloc(bytes, user);
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+  }
+  if (!p) fail(MRA_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  return p;
+}
+
+void Ctx::dfree(void* p) {
+  if (!p) return;
+  if (free_fn)
+    free_fn(p, user);
+  else
+    (void)hipFree(p);
+}
+
+void Ctx::sync() { hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+
+// ------------------------------------------------------------------------ block cache
+static void transpose_into(int m, const double* a, double* out) {
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) out[j * m + i] = a[i * m + j];
+}
+
+const BlockEntry& Op::ensure(int level, int mu, int D) {
+  BlockEntry& e = entries[{level, mu}];
+  if (e.D >= D) return e;
+  const int K2 = k * k, N = 2 * k, N2 = N * N;
+  double W = ctx->width();
+  double h = W / std::ldexp(1.0, level), hf = W / std::ldexp(1.0, level + 1);
+  double texp = t[mu];
+  // fine blocks t^{n+1, d} for d in [-2D-1, 2D+1] (t^{-d} = (t^d)^T)
+  int F = 2 * D + 1;
+  std::vector<double> fine((size_t)(2 * F + 1) * K2);
+  for (int d = 0; d <= F; ++d) {
+    block_t(k, hf, d, texp, &fine[(size_t)(d + F) * K2]);
+    if (d > 0) transpose_into(k, &fine[(size_t)(d + F) * K2], &fine[(size_t)(F - d) * K2]);
+  }
+  std::vector<double> coarse((size_t)(2 * D + 1) * K2);
+  for (int d = 0; d <= D; ++d) {
+    block_t(k, h, d, texp, &coarse[(size_t)(d + D) * K2]);
+    if (d > 0) transpose_into(k, &coarse[(size_t)(d + D) * K2], &coarse[(size_t)(D - d) * K2]);
+  }
+  std::vector<double> h0, h1;
+  two_scale_filters(k, h0, h1);
+  e.D = D;
+  e.a.assign(D + 1, 0.0);
+  e.e.assign(D + 1, 0.0);
+  e.r.assign(D + 1, 0.0);
+  e.r_base = (int64_t)(hR.size() / N2);
+  e.t_base = (int64_t)(hT.size() / K2);
+  std::vector<double> R(N2), P(N2), tmp(N2);
+  for (int d = -D; d <= D; ++d) {
+    // R rows (b, i) target child, columns (a, j) source child: block t^{n+1, 2d + b - a}
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) {
+        const double* src = &fine[(size_t)(2 * d + b - a + F) * K2];
+        for (int i = 0; i < k; ++i)
+          for (int j = 0; j < k; ++j) R[(b * k + i) * N + a * k + j] = src[i * k + j];
+      }
+    const double* tc = &coarse[(size_t)(d + D) * K2];
+    size_t off = hR.size();
+    hR.resize(off + N2);
+    transpose_into(N, R.data(), &hR[off]);
+    size_t offt = hT.size();
+    hT.resize(offt + K2);
+    transpose_into(k, tc, &hT[offt]);
+    if (d >= 0) {
+      // P = H^T t H with H = [h0 | h1] (k x 2k)
+      for (int X = 0; X < N; ++X)
+        for (int j = 0; j < k; ++j) {
+          double s = 0.0;
+          for (int i = 0; i < k; ++i) {
+            double hix = X < k ? h0[i * k + X] : h1[i * k + X - k];
+            s += hix * tc[i * k + j];
+          }
+          tmp[X * k + j] = s;   // (H^T t)[X][j]
+        }
+      for (int X = 0; X < N; ++X)
+        for (int Y = 0; Y < N; ++Y) {
+          double s = 0.0;
+          for (int j = 0; j < k; ++j) {
+            double hjy = Y < k ? h0[j * k + Y] : h1[j * k + Y - k];
+            s += tmp[X * k + j] * hjy;
+          }
+          P[X * N + Y] = R[X * N + Y] - s;
+        }
+      e.a[d] = spectral_norm(k, tc);
+      e.e[d] = spectral_norm(N, P.data());
+      e.r[d] = spectral_norm(N, R.data());
+    }
+  }
+  return e;
+}
+
+void Op::sync_device() {
+  const size_t N2 = (size_t)4 * k * k, K2 = (size_t)k * k;
+  size_t nR = hR.size() / N2, nT = hT.size() / K2;
+  if (nR == dR_blocks && nT == dT_blocks) return;
+  // grow: re-upload everything (blocks are appended; kernels in flight use the old copy,
+  // so synchronise before freeing it)
+  ctx->sync();
+  dR.upload(ctx, hR);
+  dT.upload(ctx, hT);
+  dR_blocks = nR;
+  dT_blocks = nT;
+}
+
+// ------------------------------------------------------------------------ helpers
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+static void decode(uint64_t code, int n, int64_t& x, int64_t& y, int64_t& z) {
+  x = y = z = 0;
+  for (int b = 0; b < n; ++b) {
+    x |= (int64_t)((code >> (3 * b + 2)) & 1) << b;
+    y |= (int64_t)((code >> (3 * b + 1)) & 1) << b;
+    z |= (int64_t)((code >> (3 * b)) & 1) << b;
+  }
+}
+
+static uint64_t encode(int n, int64_t x, int64_t y, int64_t z) {
+  uint64_t code = 0;
+  for (int b = 0; b < n; ++b) {
+    code |= (uint64_t)((x >> b) & 1) << (3 * b + 2);
+    code |= (uint64_t)((y >> b) & 1) << (3 * b + 1);
+    code |= (uint64_t)((z >> b) & 1) << (3 * b);
+  }
+  return code;
+}
+
+static int64_t find_node(const Func& f, int n, uint64_t code) {
+  if (n >= f.nlev) return -1;
+  auto beg = f.code.begin() + f.level_off[n], end = f.code.begin() + f.level_off[n + 1];
+  auto it = std::lower_bound(beg, end, code);
+  if (it == end || *it != code) return -1;
+  return it - f.code.begin();
+}
+
+struct Filters {
+  DevArray<double> h0, h1;
+};
+
+static void upload_filters(Ctx* ctx, int k, Filters& F) {
+  std::vector<double> h0, h1;
+  two_scale_filters(k, h0, h1);
+  F.h0.upload(ctx, h0);
+  F.h1.upload(ctx, h1);
+}
+
+// filter-up of f on device; returns ||B_P||_F^2 per interior node (in f.interior order)
+static void filter_up(Ctx* ctx, Func& f, const Filters& F, std::vector<double>* bnorm2) {
+  DevArray<double> dn;
+  dn.alloc(ctx, std::max<size_t>(1, f.interior.size()));
+  for (int n = f.nlev - 1; n >= 0; --n) {
+    int64_t b = f.inter_level_off[n], e = f.inter_level_off[n + 1];
+    if (e > b)
+      launch_filter_up(f.k, f.coeff.p, f.coeff.p, f.d_interior.p + b, f.d_inter_child.p + b,
+                       (int)(e - b), F.h0.p, F.h1.p, dn.p + b, ctx->stream);
+  }
+  f.interior_valid = true;
+  if (bnorm2) {
+    bnorm2->resize(f.interior.size());
+    if (!f.interior.empty())
+      hip_check(hipMemcpyAsync(bnorm2->data(), dn.p, f.interior.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream),
+                "hipMemcpyAsync D2H");
+    ctx->sync();
+  } else {
+    ctx->sync();  // keep dn alive until the kernels are done
+  }
+}
+
+// Every index a kernel will dereference is checked on the host before launch.
+static void validate_work(const Op& op, const Func& f, const Func& out,
+                          const std::vector<NSItem>& items, const std::vector<TargetRange>& tgt,
+                          bool nonstandard) {
+  const int64_t nin = f.nodes(), nout = out.nodes();
+  const int64_t nR = (int64_t)op.dR_blocks, nT = (int64_t)op.dT_blocks;
+  auto bad = [](const char* what) { fail(MRA_E_INVALID, std::string("internal plan error: ") + what); };
+  for (const NSItem& it : items) {
+    if (it.src < 0 || it.src >= nin) bad("source node");
+    if (it.mu < 0 || it.mu >= (int)op.c.size()) bad("term index");
+    if (it.tx < 0 || it.tx >= nT || it.ty < 0 || it.ty >= nT || it.tz < 0 || it.tz >= nT)
+      bad("t block");
+    if (nonstandard) {
+      if (it.src_fc < 0 || it.src_fc + 8 > nin) bad("source children");
+      if (it.rx < 0 || it.rx >= nR || it.ry < 0 || it.ry >= nR || it.rz < 0 || it.rz >= nR)
+        bad("R block");
+    }
+  }
+  for (const TargetRange& r : tgt) {
+    if (r.node < 0 || r.node >= nout) bad("target node");
+    if (r.beg < 0 || r.end < r.beg || r.end > (int32_t)items.size()) bad("item range");
+    if (nonstandard && (r.fc < 0 || r.fc + 8 > nout)) bad("target children");
+  }
+}
+
+struct Triple {
+  uint64_t tcode;    // (level << 58) | code of the target
+  int32_t src;       // index into f.interior
+  int16_t mu;
+  int8_t dx, dy, dz;
+};
+
+// ------------------------------------------------------------------------ apply (NS)
+static void apply_nonstandard(Ctx* ctx, Op& op, Func& f, double tau, Func& out) {
+  const int k = f.k;
+  Filters F;
+  upload_filters(ctx, k, F);
+  hip_check(hipEventRecord(ctx->ev[0], ctx->stream), "event");
+  std::vector<double> bn2;
+  filter_up(ctx, f, F, &bn2);
+  hip_check(hipEventRecord(ctx->ev[1], ctx->stream), "event");
+  double t_plan0 = now_ms();
+
+  // ---- screening
+  std::vector<Triple> triples;
+  const double W = ctx->width();
+  const int M = (int)op.c.size();
+  for (int n = 0; n < f.nlev; ++n) {
+    int64_t ib = f.inter_level_off[n], ie = f.inter_level_off[n + 1];
+    if (ie <= ib) continue;
+    int64_t np = ie - ib;
+    std::vector<double> bn(np);
+    std::vector<int64_t> px(np), py(np), pz(np);
+    double maxb = 0.0;
+    for (int64_t i = 0; i < np; ++i) {
+      bn[i] = std::sqrt(bn2[ib + i]);
+      maxb = std::max(maxb, bn[i]);
+      decode(f.code[f.interior[ib + i]], n, px[i], py[i], pz[i]);
+    }
+    std::vector<int64_t> order(np);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return bn[a] > bn[b]; });
+    const int64_t nb = (int64_t)1 << n;
+    const double h = W / std::ldexp(1.0, n);
+    for (int mu = 0; mu < M; ++mu) {
+      double c = std::fabs(op.c[mu]);
+      double beta = op.t[mu] * h * h;
+      double ab = 2.0 * h;
+      double fac = 1.0;
+      if (n > 0) {
+        if (c * maxb * 3.0 * e_bound(k, h, beta) * ab * ab < tau) continue;
+        fac = 3.0;
+      }
+      int D = 0;
+      while (D + 1 <= nb - 1 && c * maxb * fac * ab * ab * decay_bound(h, beta, D + 1) >= tau) ++D;
+      const BlockEntry& be = op.ensure(n, mu, D);
+      std::vector<double> ae(D + 1), aa(D + 1), rr(D + 1);
+      for (int d = 0; d <= D; ++d) {
+        ae[d] = be.a[d] + be.e[d];
+        aa[d] = be.a[d];
+        rr[d] = be.r[d];
+      }
+      for (int dx = -D; dx <= D; ++dx)
+        for (int dy = -D; dy <= D; ++dy)
+          for (int dz = -D; dz <= D; ++dz) {
+            int ax = std::abs(dx), ay = std::abs(dy), az = std::abs(dz);
+            double N = (n > 0) ? ae[ax] * ae[ay] * ae[az] - aa[ax] * aa[ay] * aa[az]
+                               : rr[ax] * rr[ay] * rr[az];
+            if (c * N * maxb < tau) continue;
+            for (int64_t oi = 0; oi < np; ++oi) {
+              int64_t p = order[oi];
+              if (!(c * N * bn[p] >= tau)) break;
+              int64_t tx = px[p] + dx, ty = py[p] + dy, tz = pz[p] + dz;
+              if (tx < 0 || ty < 0 || tz < 0 || tx >= nb || ty >= nb || tz >= nb) continue;
+              triples.push_back({((uint64_t)n << 58) | encode(n, tx, ty, tz), (int32_t)(ib + p),
+                                 (int16_t)mu, (int8_t)dx, (int8_t)dy, (int8_t)dz});
+            }
+          }
+    }
+  }
+  std::sort(triples.begin(), triples.end(), [](const Triple& a, const Triple& b) {
+    if (a.tcode != b.tcode) return a.tcode < b.tcode;
+    if (a.src != b.src) return a.src < b.src;
+    return a.mu < b.mu;
+  });
+
+  // ---- output tree
+  int maxlev = 0;
+  for (auto& t : triples) maxlev = std::max(maxlev, (int)(t.tcode >> 58) + 1);
+  std::vector<std::vector<uint64_t>> sets(std::max(maxlev + 1, 1));
+  for (size_t i = 0; i < triples.size(); ++i) {
+    if (i > 0 && triples[i].tcode == triples[i - 1].tcode) continue;
+    int n = (int)(triples[i].tcode >> 58);
+    uint64_t code = triples[i].tcode & ((1ULL << 58) - 1);
+    sets[n].push_back(code);
+    for (int c = 0; c < 8; ++c) sets[n + 1].push_back((code << 3) | c);
+  }
+  sets[0].push_back(0);
+  for (int n = (int)sets.size() - 1; n >= 1; --n) {
+    auto& s = sets[n];
+    std::sort(s.begin(), s.end());
+    s.erase(std::unique(s.begin(), s.end()), s.end());
+    std::vector<uint64_t> full;
+    full.reserve(s.size() * 2);
+    uint64_t lastp = ~0ULL;
+    for (uint64_t code : s) {
+      uint64_t p = code >> 3;
+      if (p == lastp) continue;
+      lastp = p;
+      for (int c = 0; c < 8; ++c) full.push_back((p << 3) | c);
+      sets[n - 1].push_back(p);
+    }
+    s.swap(full);
+  }
+  std::sort(sets[0].begin(), sets[0].end());
+  sets[0].erase(std::unique(sets[0].begin(), sets[0].end()), sets[0].end());
+  out.ctx = ctx;
+  out.k = k;
+  build_tree(out, sets);
+
+  // ---- work lists
+  std::vector<NSItem> items;
+  items.reserve(triples.size());
+  std::vector<TargetRange> tgt, tgt_sub;
+  double flops = 0.0;
+  const double f_ns = 6.0 * std::pow(2.0 * k, 4), f_sub = 6.0 * std::pow((double)k, 4);
+  for (size_t i = 0; i < triples.size();) {
+    size_t j = i;
+    while (j < triples.size() && triples[j].tcode == triples[i].tcode) ++j;
+    int n = (int)(triples[i].tcode >> 58);
+    uint64_t code = triples[i].tcode & ((1ULL << 58) - 1);
+    int64_t node = find_node(out, n, code);
+    TargetRange r{(int32_t)node, out.first_child[node], (int32_t)items.size(), 0};
+    for (size_t q = i; q < j; ++q) {
+      const Triple& t = triples[q];
+      const BlockEntry& be = op.entries.at({n, (int)t.mu});
+      NSItem it;
+      it.src = f.interior[t.src];
+      it.src_fc = f.first_child[it.src];
+      it.mu = t.mu;
+      it.rx = (int32_t)(be.r_base + t.dx + be.D);
+      it.ry = (int32_t)(be.r_base + t.dy + be.D);
+      it.rz = (int32_t)(be.r_base + t.dz + be.D);
+      it.tx = (int32_t)(be.t_base + t.dx + be.D);
+      it.ty = (int32_t)(be.t_base + t.dy + be.D);
+      it.tz = (int32_t)(be.t_base + t.dz + be.D);
+      items.push_back(it);
+      flops += f_ns + (n > 0 ? f_sub : 0.0);
+    }
+    r.end = (int32_t)items.size();
+    tgt.push_back(r);
+    if (n > 0) tgt_sub.push_back(r);
+    i = j;
+  }
+  // longest lists first
+  auto by_len = [](const TargetRange& a, const TargetRange& b) {
+    return (a.end - a.beg) > (b.end - b.beg);
+  };
+  std::stable_sort(tgt.begin(), tgt.end(), by_len);
+  std::stable_sort(tgt_sub.begin(), tgt_sub.end(), by_len);
+
+  op.sync_device();
+  validate_work(op, f, out, items, tgt, true);
+  DevArray<NSItem> d_items;
+  DevArray<TargetRange> d_tgt, d_tgt_sub;
+  d_items.upload(ctx, items);
+  d_tgt.upload(ctx, tgt);
+  d_tgt_sub.upload(ctx, tgt_sub);
+  out.coeff.alloc(ctx, (size_t)out.nodes() * k * k * k);
+  out.upload_structure();
+  // sum-down lists per level
+  std::vector<int32_t> sd_nodes, sd_child;
+  std::vector<int64_t> sd_off(out.nlev + 1, 0);
+  for (int n = 0; n < out.nlev; ++n) {
+    for (int64_t i = out.inter_level_off[n]; i < out.inter_level_off[n + 1]; ++i) {
+      sd_nodes.push_back(out.interior[i]);
+      sd_child.push_back(out.first_child[out.interior[i]]);
+    }
+    sd_off[n + 1] = (int64_t)sd_nodes.size();
+  }
+  DevArray<int32_t> d_sdn, d_sdc;
+  d_sdn.upload(ctx, sd_nodes);
+  d_sdc.upload(ctx, sd_child);
+  double t_plan1 = now_ms();
+
+  // ---- device: transform-and-accumulate, then sum-down
+  launch_zero(out.coeff.p, out.coeff.n, ctx->stream);
+  hip_check(hipEventRecord(ctx->ev[2], ctx->stream), "event");
+  launch_apply_ns(k, f.coeff.p, out.coeff.p, d_items.p, d_tgt.p, (int)tgt.size(), op.dR.p,
+                  op.d_c.p, ctx->stream);
+  hip_check(hipEventRecord(ctx->ev[3], ctx->stream), "event");
+  launch_apply_std(k, f.coeff.p, out.coeff.p, d_items.p, d_tgt_sub.p, (int)tgt_sub.size(),
+                   op.dT.p, op.d_c.p, -1.0, ctx->stream);
+  hip_check(hipEventRecord(ctx->ev[4], ctx->stream), "event");
+  for (int n = 0; n < out.nlev; ++n) {
+    int64_t b = sd_off[n], e = sd_off[n + 1];
+    if (e > b)
+      launch_sum_down(k, out.coeff.p, d_sdn.p + b, d_sdc.p + b, (int)(e - b), F.h0.p, F.h1.p,
+                      ctx->stream);
+  }
+  hip_check(hipEventRecord(ctx->ev[5], ctx->stream), "event");
+  ctx->sync();
+  out.interior_valid = false;
+
+  float ms_f = 0, ms_a = 0, ms_s = 0, ms_main = 0;
+  hip_check(hipEventElapsedTime(&ms_f, ctx->ev[0], ctx->ev[1]), "elapsed");
+  hip_check(hipEventElapsedTime(&ms_a, ctx->ev[2], ctx->ev[4]), "elapsed");
+  hip_check(hipEventElapsedTime(&ms_main, ctx->ev[2], ctx->ev[3]), "elapsed");
+  hip_check(hipEventElapsedTime(&ms_s, ctx->ev[4], ctx->ev[5]), "elapsed");
+  mra_apply_stats& st = ctx->stats;
+  st = mra_apply_stats{};
+  st.triples = (int64_t)triples.size();
+  st.targets = (int64_t)tgt.size();
+  st.in_leaves = (int64_t)f.leaves.size();
+  st.out_nodes = out.nodes();
+  st.out_leaves = (int64_t)out.leaves.size();
+  st.useful_flops = flops;
+  st.ms_filter = ms_f;
+  st.ms_plan = t_plan1 - t_plan0;
+  st.ms_apply = ms_a;
+  st.ms_main_kernel = ms_main;
+  st.ms_sumdown = ms_s;
+}
+
+// ------------------------------------------------------------------------ apply (std)
+static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
+  const int k = f.k;
+  if (f.leaves.empty()) fail(MRA_E_INVALID, "empty function");
+  int L = f.level_of(f.leaves[0]);
+  for (int32_t l : f.leaves)
+    if (f.level_of(l) != L) fail(MRA_E_INVALID, "standard form needs a uniform tree");
+  if (radius < 0) fail(MRA_E_INVALID, "disp_radius must be >= 0");
+  const int64_t nb = (int64_t)1 << L;
+  const int M = (int)op.c.size();
+  int D = (int)std::min<int64_t>(radius, nb - 1);
+  for (int mu = 0; mu < M; ++mu) op.ensure(L, mu, D);
+  double t_plan0 = now_ms();
+  // output: same structure
+  out.ctx = ctx;
+  out.k = k;
+  out.nlev = f.nlev;
+  out.level_off = f.level_off;
+  out.code = f.code;
+  out.first_child = f.first_child;
+  out.finalize_structure();
+  std::vector<NSItem> items;
+  std::vector<TargetRange> tgt;
+  for (int32_t T : f.leaves) {
+    int64_t x, y, z;
+    decode(f.code[T], L, x, y, z);
+    TargetRange r{T, -1, (int32_t)items.size(), 0};
+    for (int dx = -D; dx <= D; ++dx)
+      for (int dy = -D; dy <= D; ++dy)
+        for (int dz = -D; dz <= D; ++dz) {
+          int64_t sx = x - dx, sy = y - dy, sz = z - dz;
+          if (sx < 0 || sy < 0 || sz < 0 || sx >= nb || sy >= nb || sz >= nb) continue;
+          int64_t S = find_node(f, L, encode(L, sx, sy, sz));
+          if (S < 0) fail(MRA_E_INVALID, "standard form needs a complete uniform level");
+          for (int mu = 0; mu < M; ++mu) {
+            const BlockEntry& be = op.entries.at({L, mu});
+            NSItem it{};
+            it.src = (int32_t)S;
+            it.src_fc = -1;
+            it.mu = mu;
+            it.tx = (int32_t)(be.t_base + dx + be.D);
+            it.ty = (int32_t)(be.t_base + dy + be.D);
+            it.tz = (int32_t)(be.t_base + dz + be.D);
+            items.push_back(it);
+          }
+        }
+    r.end = (int32_t)items.size();
+    tgt.push_back(r);
+  }
+  op.sync_device();
+  validate_work(op, f, out, items, tgt, false);
+  DevArray<NSItem> d_items;
+  DevArray<TargetRange> d_tgt;
+  d_items.upload(ctx, items);
+  d_tgt.upload(ctx, tgt);
+  out.coeff.alloc(ctx, (size_t)out.nodes() * k * k * k);
+  out.upload_structure();
+  double t_plan1 = now_ms();
+  launch_zero(out.coeff.p, out.coeff.n, ctx->stream);
+  hip_check(hipEventRecord(ctx->ev[2], ctx->stream), "event");
+  launch_apply_std(k, f.coeff.p, out.coeff.p, d_items.p, d_tgt.p, (int)tgt.size(), op.dT.p,
+                   op.d_c.p, 1.0, ctx->stream);
+  hip_check(hipEventRecord(ctx->ev[3], ctx->stream), "event");
+  ctx->sync();
+  float ms_a = 0;
+  hip_check(hipEventElapsedTime(&ms_a, ctx->ev[2], ctx->ev[3]), "elapsed");
+  mra_apply_stats& st = ctx->stats;
+  st = mra_apply_stats{};
+  st.triples = (int64_t)items.size();
+  st.targets = (int64_t)tgt.size();
+  st.in_leaves = (int64_t)f.leaves.size();
+  st.out_nodes = out.nodes();
+  st.out_leaves = (int64_t)out.leaves.size();
+  st.useful_flops = (double)items.size() * 6.0 * std::pow((double)k, 4);
+  st.ms_plan = t_plan1 - t_plan0;
+  st.ms_apply = ms_a;
+  st.ms_main_kernel = ms_a;
+}
+
+// ------------------------------------------------------------------------ reductions
+static double reduce(Ctx* ctx, int k, const double* a, const double* b,
+                     const std::vector<int32_t>& la, const std::vector<int32_t>* lb,
+                     const std::vector<double>* w, int mode) {
+  if (la.empty()) return 0.0;
+  const int nblocks = 256;
+  DevArray<int32_t> d_la, d_lb;
+  DevArray<double> d_w, d_part;
+  d_la.upload(ctx, la);
+  if (lb) d_lb.upload(ctx, *lb);
+  if (w) d_w.upload(ctx, *w);
+  d_part.alloc(ctx, nblocks);
+  launch_leaf_reduce(k, a, b, d_la.p, lb ? d_lb.p : nullptr, w ? d_w.p : nullptr,
+                     (int)la.size(), mode, d_part.p, nblocks, ctx->stream);
+  std::vector<double> part(nblocks);
+  hip_check(hipMemcpyAsync(part.data(), d_part.p, nblocks * sizeof(double),
+                           hipMemcpyDeviceToHost, ctx->stream),
+            "hipMemcpyAsync D2H");
+  ctx->sync();
+  double s = 0.0;
+  for (double v : part) s += v;
+  return s;
+}
+
+}  // namespace mra
+
+// =========================================================================== C ABI
+using namespace mra;
+
+#define MRA_TRY(ctxptr, ...)                                   \
+  try {                                                        \
+    __VA_ARGS__;                                               \
+    return MRA_OK;                                             \
+  } catch (const Error& e) {                                   \
+    if (ctxptr) (ctxptr)->err = e.msg;                         \
+    return e.code;                                             \
+  } catch (const std::bad_alloc&) {                            \
+    if (ctxptr) (ctxptr)->err = "host allocation failed";      \
+    return MRA_E_NOMEM;                                        \
+  } catch (const std::exception& e) {                          \
+    if (ctxptr) (ctxptr)->err = e.what();                      \
+    return MRA_E_INVALID;                                      \
+  }
+
+extern "C" {
+
+static thread_local std::string g_create_error;
+
+mra_status mra_ctx_create(int device, void* stream, mra_alloc_fn alloc, mra_free_fn free_fn,
+                          void* user, double cell_lo, double cell_hi, mra_ctx** out) {
+  g_create_error.clear();
+  if (!out || !(cell_hi > cell_lo) || ((alloc == nullptr) != (free_fn == nullptr))) {
+    g_create_error = "mra_ctx_create: bad arguments";
+    return MRA_E_INVALID;
+  }
+  mra_ctx* h = nullptr;
+  try {
+    h = new mra_ctx();
+    Ctx& c = h->c;
+    c.device = device;
+    c.stream = (hipStream_t)stream;
+    c.alloc = alloc;
+    c.free_fn = free_fn;
+    c.user = user;
+    c.lo = cell_lo;
+    c.hi = cell_hi;
+    hip_check(hipSetDevice(device), "hipSetDevice");
+    for (auto& e : c.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+    *out = h;
+    return MRA_OK;
+  } catch (const Error& e) {
+    delete h;
+    g_create_error = e.msg;
+    return e.code;
+  } catch (...) {
+    delete h;
+    g_create_error = "mra_ctx_create: allocation failed";
+    return MRA_E_NOMEM;
+  }
+}
+
+mra_status mra_ctx_free(mra_ctx* ctx) {
+  if (!ctx) return MRA_E_INVALID;
+  for (auto& e : ctx->c.ev)
+    if (e) (void)hipEventDestroy(e);
+  delete ctx;
+  return MRA_OK;
+}
+
+const char* mra_last_error(const mra_ctx* ctx) {
+  return ctx ? ctx->c.err.c_str() : g_create_error.c_str();
+}
+
+mra_status mra_project(mra_ctx* ctx, const mra_gaussian* g, int ng,
+                       const mra_project_params* p, mra_func** out) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (!g || ng < 1 || !p || !out) fail(MRA_E_INVALID, "mra_project: bad arguments");
+    if (p->k < 2 || p->k > kMaxK) fail(MRA_E_INVALID, "k must be in [2, 14]");
+    if (!(p->thresh > 0.0)) fail(MRA_E_INVALID, "thresh must be > 0");
+    if (p->initial_level < 0 || p->max_level > kMaxLevel || p->initial_level > p->max_level)
+      fail(MRA_E_INVALID, "need 0 <= initial_level <= max_level <= 20");
+    for (int i = 0; i < ng; ++i)
+      if (!(g[i].expnt > 0.0)) fail(MRA_E_INVALID, "Gaussian exponents must be > 0");
+    std::unique_ptr<mra_func> h(new mra_func());
+    std::vector<double> coeffs;
+    project_gaussians(c, g, ng, p->k, p->thresh, p->initial_level, p->max_level, h->f, coeffs);
+    h->f.coeff.upload(c, coeffs);
+    h->f.upload_structure();
+    c->sync();
+    *out = h.release();
+  });
+}
+
+mra_status mra_func_info(const mra_func* f, int* k, int64_t* nodes, int64_t* leaves,
+                         int* max_level) {
+  if (!f) return MRA_E_INVALID;
+  if (k) *k = f->f.k;
+  if (nodes) *nodes = f->f.nodes();
+  if (leaves) *leaves = (int64_t)f->f.leaves.size();
+  if (max_level) *max_level = f->f.nlev - 1;
+  return MRA_OK;
+}
+
+mra_status mra_func_export(mra_ctx* ctx, const mra_func* fh, int64_t cap, uint64_t* keys,
+                           double* coeffs, int64_t* nleaves) {
+  if (!ctx || !fh) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    const Func& f = fh->f;
+    if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    int64_t nl = (int64_t)f.leaves.size();
+    if (nleaves) *nleaves = nl;
+    if (keys || coeffs) {
+      if (cap < nl) fail(MRA_E_INVALID, "export capacity too small");
+      const size_t k3 = (size_t)f.k * f.k * f.k;
+      std::vector<double> all;
+      if (coeffs) {
+        all.resize((size_t)f.nodes() * k3);
+        hip_check(hipMemcpyAsync(all.data(), f.coeff.p, all.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream),
+                  "hipMemcpyAsync D2H");
+        c->sync();
+      }
+      for (int64_t i = 0; i < nl; ++i) {
+        int32_t node = f.leaves[i];
+        int n = f.level_of(node);
+        if (keys) keys[i] = (1ULL << (3 * n)) | f.code[node];
+        if (coeffs) std::memcpy(coeffs + i * k3, all.data() + (size_t)node * k3, k3 * sizeof(double));
+      }
+    }
+  });
+}
+
+mra_status mra_func_free(mra_func* f) {
+  if (!f) return MRA_E_INVALID;
+  delete f;
+  return MRA_OK;
+}
+
+static mra_status make_op(mra_ctx* ctx, int k, const std::vector<double>& cc,
+                          const std::vector<double>& tt, mra_op** out) {
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (k < 2 || k > kMaxK) fail(MRA_E_INVALID, "k must be in [2, 14]");
+    if (cc.empty() || cc.size() > 32767) fail(MRA_E_INVALID, "need 1 <= M <= 32767 terms");
+    for (double t : tt)
+      if (!(t > 0.0)) fail(MRA_E_INVALID, "operator exponents must be > 0");
+    std::unique_ptr<mra_op> h(new mra_op());
+    h->o.ctx = c;
+    h->o.k = k;
+    h->o.c = cc;
+    h->o.t = tt;
+    h->o.d_c.upload(c, cc);
+    c->sync();
+    *out = h.release();
+  });
+}
+
+mra_status mra_op_coulomb(mra_ctx* ctx, int k, double lo, double eps, mra_op** out) {
+  if (!ctx || !out) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  std::vector<double> cc, tt;
+  try {
+    fit_coulomb(lo, eps, std::sqrt(3.0) * c->width(), cc, tt);
+  } catch (const Error& e) {
+    c->err = e.msg;
+    return e.code;
+  }
+  return make_op(ctx, k, cc, tt, out);
+}
+
+mra_status mra_op_bsh(mra_ctx* ctx, int k, double mu, double lo, double eps, mra_op** out) {
+  if (!ctx || !out) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  std::vector<double> cc, tt;
+  try {
+    fit_bsh(mu, lo, eps, std::sqrt(3.0) * c->width(), cc, tt);
+  } catch (const Error& e) {
+    c->err = e.msg;
+    return e.code;
+  }
+  return make_op(ctx, k, cc, tt, out);
+}
+
+mra_status mra_op_gaussians(mra_ctx* ctx, int k, int M, const double* cv, const double* tv,
+                            mra_op** out) {
+  if (!ctx || !out || M < 1 || !cv || !tv) {
+    if (ctx) ctx->c.err = "mra_op_gaussians: bad arguments";
+    return MRA_E_INVALID;
+  }
+  return make_op(ctx, k, std::vector<double>(cv, cv + M), std::vector<double>(tv, tv + M), out);
+}
+
+mra_status mra_op_terms(const mra_op* op, int* M, double* c, double* t) {
+  if (!op) return MRA_E_INVALID;
+  if (M) *M = (int)op->o.c.size();
+  if (c) std::copy(op->o.c.begin(), op->o.c.end(), c);
+  if (t) std::copy(op->o.t.begin(), op->o.t.end(), t);
+  return MRA_OK;
+}
+
+mra_status mra_op_free(mra_op* op) {
+  if (!op) return MRA_E_INVALID;
+  delete op;
+  return MRA_OK;
+}
+
+mra_status mra_apply(mra_ctx* ctx, const mra_op* oph, const mra_func* fh,
+                     const mra_apply_params* p, mra_func** out) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (!oph || !fh || !p || !out) fail(MRA_E_INVALID, "mra_apply: bad arguments");
+    Op& op = const_cast<mra_op*>(oph)->o;          // the block cache is mutable state
+    Func& f = const_cast<mra_func*>(fh)->f;        // refined-box slabs are workspace
+    if (op.ctx != c || f.ctx != c) fail(MRA_E_MISMATCH, "handles belong to another context");
+    if (op.k != f.k) fail(MRA_E_MISMATCH, "operator and function have different k");
+    std::unique_ptr<mra_func> h(new mra_func());
+    if (p->form == MRA_FORM_STANDARD) {
+      apply_standard(c, op, f, p->disp_radius, h->f);
+    } else if (p->form == MRA_FORM_NONSTANDARD) {
+      if (f.k > 10) fail(MRA_E_UNSUPPORTED, "non-standard apply is built for k <= 10");
+      if (!(p->tau_drop >= 0.0)) fail(MRA_E_INVALID, "tau_drop must be >= 0");
+      apply_nonstandard(c, op, f, p->tau_drop, h->f);
+    } else {
+      fail(MRA_E_INVALID, "unknown form");
+    }
+    *out = h.release();
+  });
+}
+
+mra_status mra_norm2(mra_ctx* ctx, const mra_func* fh, double* out) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (!fh || !out) fail(MRA_E_INVALID, "mra_norm2: bad arguments");
+    const Func& f = fh->f;
+    if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    double s = reduce(c, f.k, f.coeff.p, nullptr, f.leaves, nullptr, nullptr, 0);
+    *out = std::sqrt(s);
+  });
+}
+
+mra_status mra_trace(mra_ctx* ctx, const mra_func* fh, double* out) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (!fh || !out) fail(MRA_E_INVALID, "mra_trace: bad arguments");
+    const Func& f = fh->f;
+    if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    std::vector<double> w(f.leaves.size());
+    for (size_t i = 0; i < f.leaves.size(); ++i)
+      w[i] = std::pow(c->width() / std::ldexp(1.0, f.level_of(f.leaves[i])), 1.5);
+    *out = reduce(c, f.k, f.coeff.p, nullptr, f.leaves, nullptr, &w, 1);
+  });
+}
+
+mra_status mra_inner(mra_ctx* ctx, const mra_func* fh, const mra_func* gh, double* out) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (!fh || !gh || !out) fail(MRA_E_INVALID, "mra_inner: bad arguments");
+    Func& f = const_cast<mra_func*>(fh)->f;
+    Func& g = const_cast<mra_func*>(gh)->f;
+    if (f.ctx != c || g.ctx != c) fail(MRA_E_MISMATCH, "handles belong to another context");
+    if (f.k != g.k) fail(MRA_E_MISMATCH, "functions have different k");
+    Filters F;
+    upload_filters(c, f.k, F);
+    if (!f.interior_valid) filter_up(c, f, F, nullptr);
+    if (!g.interior_valid) filter_up(c, g, F, nullptr);
+    // pair the leaves of the intersection of the two trees: boxes present in both where at
+    // least one of the two is a leaf (the other side holds its filtered coefficients).
+    std::vector<int32_t> la, lb;
+    for (int n = 0; n < std::min(f.nlev, g.nlev); ++n) {
+      for (int64_t i = f.level_off[n]; i < f.level_off[n + 1]; ++i) {
+        int64_t j = find_node(g, n, f.code[i]);
+        if (j < 0) continue;
+        if (f.first_child[i] < 0 || g.first_child[j] < 0) {
+          la.push_back((int32_t)i);
+          lb.push_back((int32_t)j);
+        }
+      }
+    }
+    *out = reduce(c, f.k, f.coeff.p, g.coeff.p, la, &lb, nullptr, 2);
+  });
+}
+
+mra_status mra_last_stats(const mra_ctx* ctx, mra_apply_stats* out) {
+  if (!ctx || !out) return MRA_E_INVALID;
+  *out = ctx->c.stats;
+  return MRA_OK;
+}
+
+// ----------------------------------------------------------------- host-only helpers
+mra_status mra_host_fit(int kind, double mu, double lo, double eps, double r_hi, int cap,
+                        double* c, double* t, int* M) {
+  try {
+    std::vector<double> cc, tt;
+    if (kind == 0)
+      fit_coulomb(lo, eps, r_hi, cc, tt);
+    else
+      fit_bsh(mu, lo, eps, r_hi, cc, tt);
+    if (M) *M = (int)cc.size();
+    if (c || t) {
+      if (cap < (int)cc.size()) return MRA_E_INVALID;
+      if (c) std::copy(cc.begin(), cc.end(), c);
+      if (t) std::copy(tt.begin(), tt.end(), t);
+    }
+    return MRA_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+mra_status mra_host_block(int k, double h, int delta, double texp, double* out) {
+  if (k < 2 || k > kMaxK || !(h > 0) || !(texp > 0) || !out) return MRA_E_INVALID;
+  try {
+    block_t(k, h, delta, texp, out);
+    return MRA_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+mra_status mra_host_filters(int k, double* h0, double* h1) {
+  if (k < 2 || k > kMaxK || !h0 || !h1) return MRA_E_INVALID;
+  std::vector<double> a, b;
+  two_scale_filters(k, a, b);
+  std::copy(a.begin(), a.end(), h0);
+  std::copy(b.begin(), b.end(), h1);
+  return MRA_OK;
+}
+
+mra_status mra_host_spectral_norm(int m, const double* a, double* out) {
+  if (m < 1 || !a || !out) return MRA_E_INVALID;
+  *out = spectral_norm(m, a);
+  return MRA_OK;
+}
+
+mra_status mra_host_project(double cell_lo, double cell_hi, const mra_gaussian* g, int ng,
+                            const mra_project_params* p, int64_t cap, uint64_t* keys,
+                            double* coeffs, int64_t* nleaves) {
+  if (!g || ng < 1 || !p || !(cell_hi > cell_lo)) return MRA_E_INVALID;
+  if (p->k < 2 || p->k > kMaxK || !(p->thresh > 0) || p->initial_level < 0 ||
+      p->max_level > kMaxLevel || p->initial_level > p->max_level)
+    return MRA_E_INVALID;
+  try {
+    Ctx c;
+    c.lo = cell_lo;
+    c.hi = cell_hi;
+    Func f;
+    std::vector<double> coef;
+    project_gaussians(&c, g, ng, p->k, p->thresh, p->initial_level, p->max_level, f, coef);
+    int64_t nl = (int64_t)f.leaves.size();
+    if (nleaves) *nleaves = nl;
+    if (keys || coeffs) {
+      if (cap < nl) return MRA_E_INVALID;
+      const size_t k3 = (size_t)p->k * p->k * p->k;
+      for (int64_t i = 0; i < nl; ++i) {
+        int32_t node = f.leaves[i];
+        int n = f.level_of(node);
+        if (keys) keys[i] = (1ULL << (3 * n)) | f.code[node];
+        if (coeffs) std::memcpy(coeffs + i * k3, coef.data() + (size_t)node * k3, k3 * 8);
+      }
+    }
+    return MRA_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+// Internal declarations of libmra (host planner + device kernels).
+//
+// Layout of a function in HBM ("flat octree"): nodes are stored level by level (level 0
+// first); inside a level they are sorted by their Morton code (interleave(lx, ly, lz), x in
+// the highest bit of each bit triple).  Every node owns one k^3 FP64 slab, row-major
+// [i][j][m].  A refined node has all 8 children, and because their codes are
+// 8*parent + c (c = 4bx + 2by + bz) they are 8 consecutive nodes of the next level: the
+// (2k)^3 "children block" of a node is 8 consecutive slabs.  Leaves hold the function;
+// slabs of refined nodes are workspace (filtered scaling coefficients when valid).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mra.h"
+
+namespace mra {
+
+constexpr int kMaxK = 14;
+constexpr int kMaxLevel = 20;
+
+// ----------------------------------------------------------------------------- errors
+struct Error {
+  mra_status code;
+  std::string msg;
+};
+[[noreturn]] void fail(mra_status code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+
+// ------------------------------------------------------------------------- quadrature
+struct GLRule {
+  std::vector<double> x, w;  // on [0, 1]
+};
+const GLRule& gauss_legendre01(int n);
+// phi_i(x) = sqrt(2i+1) P_i(2x-1) on [0,1], 0 outside; out[0..k-1]
+void scaling_functions(int k, double x, double* out);
+// two-scale filters h0, h1 (row-major k x k): parent s = h0 s_left + h1 s_right
+void two_scale_filters(int k, std::vector<double>& h0, std::vector<double>& h1);
+
+// ------------------------------------------------------------------------ operator fit
+double erfc_inverse(double p);
+void fit_coulomb(double r_lo, double eps, double r_hi, std::vector<double>& c,
+                 std::vector<double>& t);
+void fit_bsh(double mu, double r_lo, double eps, double r_hi, std::vector<double>& c,
+             std::vector<double>& t);
+
+// ------------------------------------------------------------------------ 1D blocks
+// t^{n,delta} for the kernel exp(-texp r^2) on boxes of width h (row-major k x k,
+// rows = target index).
+void block_t(int k, double h, int delta, double texp, double* out);
+// Spectral norm of a row-major m x m matrix.
+double spectral_norm(int m, const double* a);
+// Rigorous bounds used to enumerate candidate displacements.
+double e_bound(int k, double h, double beta);
+double decay_bound(double h, double beta, int delta);
+
+// Per (level, term) cache entry: blocks for delta in [-D, D] and 1D norms for 0..D.
+struct BlockEntry {
+  int D = -1;
+  std::vector<double> a, e, r;   // size D+1
+  int64_t r_base = -1;           // index of the R block of delta = -D in the device R array
+  int64_t t_base = -1;           // index of the t block of delta = -D in the device t array
+};
+
+// ------------------------------------------------------------------------- context
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  mra_alloc_fn alloc = nullptr;
+  mra_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  double lo = 0, hi = 1;
+  std::string err;
+  mra_apply_stats stats{};
+  hipEvent_t ev[8]{};
+
+  double width() const { return hi - lo; }
+  void* dalloc(size_t bytes);
+  void dfree(void* p);
+  void sync();
+};
+
+template <class T>
+struct DevArray {
+  Ctx* ctx = nullptr;
+  T* p = nullptr;
+  size_t n = 0;
+  DevArray() = default;
+  DevArray(const DevArray&) = delete;
+  DevArray& operator=(const DevArray&) = delete;
+  ~DevArray() { reset(); }
+  void reset() {
+    if (p && ctx) ctx->dfree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(Ctx* c, size_t count) {
+    reset();
+    ctx = c;
+    n = count;
+    if (count) p = static_cast<T*>(c->dalloc(count * sizeof(T)));
+  }
+  void upload(Ctx* c, const std::vector<T>& v) {
+    alloc(c, v.size());
+    if (!v.empty())
+      hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice,
+                               c->stream),
+                "hipMemcpyAsync H2D");
+  }
+};
+
+// ------------------------------------------------------------------------- function
+struct Func {
+  Ctx* ctx = nullptr;
+  int k = 0;
+  int nlev = 0;                        // levels 0 .. nlev-1 are present
+  std::vector<int64_t> level_off;      // nlev + 1
+  std::vector<uint64_t> code;          // per node, sorted within level
+  std::vector<int32_t> first_child;    // per node, -1 for leaves
+  std::vector<int32_t> leaves;         // leaf node indices (level-major, sorted)
+  std::vector<int32_t> interior;       // refined node indices (level-major, sorted)
+  std::vector<int64_t> inter_level_off;  // nlev + 1 offsets into `interior`
+  DevArray<double> coeff;              // nodes * k^3
+  DevArray<int32_t> d_leaves, d_leaf_level, d_interior, d_inter_child;
+  bool interior_valid = false;
+
+  int64_t nodes() const { return (int64_t)code.size(); }
+  int level_of(int64_t node) const;
+  void finalize_structure();           // leaves / interior lists from first_child
+  void upload_structure();
+};
+
+// Build the node arrays of a full octree from per-level sorted codes.
+void build_tree(Func& f, const std::vector<std::vector<uint64_t>>& levels);
+
+// ------------------------------------------------------------------------- operator
+struct Op {
+  Ctx* ctx = nullptr;
+  int k = 0;
+  std::vector<double> c, t;
+  std::map<std::pair<int, int>, BlockEntry> entries;   // (level, mu)
+  std::vector<double> hR, hT;                          // host mirror of device blocks
+  DevArray<double> dR, dT;                             // transposed blocks
+  size_t dR_blocks = 0, dT_blocks = 0;                 // blocks resident on device
+  DevArray<double> d_c;
+  // Make sure (level, mu) has blocks and norms for |delta| <= D.  Returns the entry.
+  const BlockEntry& ensure(int level, int mu, int D);
+  void sync_device();                                  // upload blocks added since last call
+};
+
+// ------------------------------------------------------------------------- projection
+void project_gaussians(Ctx* ctx, const mra_gaussian* g, int ng, int k, double thresh,
+                       int initial_level, int max_level, Func& out,
+                       std::vector<double>& leaf_coeffs);
+
+// ------------------------------------------------------------------------- device side
+struct NSItem {          // one kept (source, displacement, term) triple of a target
+  int32_t src;           // input node P (its slab holds s_P)
+  int32_t src_fc;        // first child of P (children block B_P)
+  int32_t mu;
+  int32_t rx, ry, rz;    // R block indices (transposed (2k)^2 blocks)
+  int32_t tx, ty, tz;    // t block indices (transposed k^2 blocks)
+};
+struct TargetRange {
+  int32_t node;          // output node T (its slab gets the level-n part)
+  int32_t fc;            // first child of T in the output (children block)
+  int32_t beg, end;      // items
+};
+
+void launch_zero(double* p, size_t n, hipStream_t s);
+void launch_filter_up(int k, const double* coeff, double* coeff_out, const int32_t* nodes,
+                      const int32_t* fchild, int count, const double* h0, const double* h1,
+                      double* bnorm2, hipStream_t s);
+void launch_apply_ns(int k, const double* in_coeff, double* out_coeff, const NSItem* items,
+                     const TargetRange* targets, int ntargets, const double* dR,
+                     const double* dc, hipStream_t s);
+void launch_apply_std(int k, const double* in_coeff, double* out_coeff, const NSItem* items,
+                      const TargetRange* targets, int ntargets, const double* dT,
+                      const double* dc, double scale, hipStream_t s);
+void launch_sum_down(int k, double* coeff, const int32_t* nodes, const int32_t* fchild,
+                     int count, const double* h0, const double* h1, hipStream_t s);
+void launch_leaf_reduce(int k, const double* a, const double* b, const int32_t* leaves_a,
+                        const int32_t* leaves_b, const double* weight, int count, int mode,
+                        double* partial, int nblocks, hipStream_t s);
+
+}  // namespace mra

@@ -1,0 +1,301 @@
+// Flat octree construction and adaptive projection of Gaussian sums (Sec. 2.1).
+//
+// Projection: f = sum_g c_g exp(-a_g |x - X_g|^2) is separable, so a box's coefficients are
+// sum_g c_g X_i Y_j Z_m with exact 1D integrals (composite Gauss-Legendre, k+20 nodes per
+// panel of width <= min(1, beta^{-1/2}), beta = a h^2, over the Gaussian's numerical
+// support).  A box at level n < max_level is refined iff the Frobenius norm of its wavelet
+// coefficients d = B - unfilter(filter(B)) (B = children block) exceeds thresh; a box that
+// is not refined becomes a leaf holding its own projection.
+#include <algorithm>
+#include <cmath>
+#include <unordered_map>
+
+#include "mra_internal.hpp"
+
+namespace mra {
+
+int Func::level_of(int64_t node) const {
+  int n = (int)(std::upper_bound(level_off.begin(), level_off.end(), node) - level_off.begin()) - 1;
+  return n;
+}
+
+void build_tree(Func& f, const std::vector<std::vector<uint64_t>>& levels) {
+  f.nlev = (int)levels.size();
+  while (f.nlev > 0 && levels[f.nlev - 1].empty()) --f.nlev;
+  f.level_off.assign(f.nlev + 1, 0);
+  for (int n = 0; n < f.nlev; ++n) f.level_off[n + 1] = f.level_off[n] + (int64_t)levels[n].size();
+  int64_t total = f.level_off[f.nlev];
+  if (total > INT32_MAX / 2) fail(MRA_E_UNSUPPORTED, "tree too large");
+  f.code.resize(total);
+  f.first_child.assign(total, -1);
+  for (int n = 0; n < f.nlev; ++n)
+    std::copy(levels[n].begin(), levels[n].end(), f.code.begin() + f.level_off[n]);
+  for (int n = 0; n + 1 < f.nlev; ++n) {
+    const auto& kids = levels[n + 1];
+    for (int64_t i = f.level_off[n]; i < f.level_off[n + 1]; ++i) {
+      uint64_t c0 = f.code[i] << 3;
+      auto it = std::lower_bound(kids.begin(), kids.end(), c0);
+      if (it != kids.end() && *it == c0) {
+        int64_t j = it - kids.begin();
+        if (j + 7 >= (int64_t)kids.size() || kids[j + 7] != c0 + 7)
+          fail(MRA_E_INVALID, "tree is not a full octree");
+        f.first_child[i] = (int32_t)(f.level_off[n + 1] + j);
+      }
+    }
+  }
+  f.finalize_structure();
+}
+
+void Func::finalize_structure() {
+  leaves.clear();
+  interior.clear();
+  inter_level_off.assign(nlev + 1, 0);
+  for (int n = 0; n < nlev; ++n) {
+    for (int64_t i = level_off[n]; i < level_off[n + 1]; ++i) {
+      if (first_child[i] < 0)
+        leaves.push_back((int32_t)i);
+      else
+        interior.push_back((int32_t)i);
+    }
+    inter_level_off[n + 1] = (int64_t)interior.size();
+  }
+}
+
+void Func::upload_structure() {
+  std::vector<int32_t> lvl(leaves.size()), ich(interior.size());
+  for (size_t i = 0; i < leaves.size(); ++i) lvl[i] = level_of(leaves[i]);
+  for (size_t i = 0; i < interior.size(); ++i) ich[i] = first_child[interior[i]];
+  d_leaves.upload(ctx, leaves);
+  d_leaf_level.upload(ctx, lvl);
+  d_interior.upload(ctx, interior);
+  d_inter_child.upload(ctx, ich);
+}
+
+// ------------------------------------------------------------------ projection
+namespace {
+
+double support_halfwidth(double beta) {
+  if (beta <= 0.0) return INFINITY;
+  return std::sqrt((50.0 + 0.5 * std::log1p(beta)) / beta);
+}
+
+// int exp(-a (x - X)^2) phi^n_{l,i}(x) dx, i < k, for the box l of width h from cell start lo.
+void gaussian_1d(int k, double a, double X, double lo, double h, int64_t l, double* out) {
+  for (int i = 0; i < k; ++i) out[i] = 0.0;
+  double beta = a * h * h;
+  double u0 = (X - lo) / h - (double)l;
+  double half = support_halfwidth(beta);
+  double ua = std::max(0.0, u0 - half), ub = std::min(1.0, u0 + half);
+  if (ub <= ua) return;
+  double width = beta > 0.0 ? std::min(1.0, 1.0 / std::sqrt(beta)) : 1.0;
+  int npan = std::max(1, (int)std::ceil((ub - ua) / width));
+  double step = (ub - ua) / npan;
+  const GLRule& g = gauss_legendre01(k + 20);
+  double ph[kMaxK];
+  for (int p = 0; p < npan; ++p) {
+    double ea = ua + p * step, eb = (p + 1 == npan) ? ub : ua + (p + 1) * step;
+    for (size_t q = 0; q < g.x.size(); ++q) {
+      double u = ea + (eb - ea) * g.x[q];
+      double wt = (eb - ea) * g.w[q] * std::exp(-beta * (u - u0) * (u - u0));
+      scaling_functions(k, u, ph);
+      for (int i = 0; i < k; ++i) out[i] += wt * ph[i];
+    }
+  }
+  double sh = std::sqrt(h);
+  for (int i = 0; i < k; ++i) out[i] *= sh;
+}
+
+struct Projector {
+  const mra_gaussian* g;
+  int ng, k;
+  double lo, W;
+  std::vector<double> h0, h1;
+  // memo of 1D integrals per (gaussian, axis, level, l)
+  std::unordered_map<uint64_t, std::vector<double>> memo;
+
+  const std::vector<double>& one_d(int gi, int axis, int n, int64_t l) {
+    uint64_t key = ((uint64_t)gi << 50) | ((uint64_t)axis << 48) | ((uint64_t)n << 40) | (uint64_t)l;
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+    std::vector<double> v(k);
+    double h = W / std::ldexp(1.0, n);
+    gaussian_1d(k, g[gi].expnt, g[gi].center[axis], lo, h, l, v.data());
+    return memo.emplace(key, std::move(v)).first->second;
+  }
+
+  // coefficients of box (n, lx, ly, lz) into out[k^3]
+  void box(int n, int64_t lx, int64_t ly, int64_t lz, double* out) {
+    int k3 = k * k * k;
+    for (int i = 0; i < k3; ++i) out[i] = 0.0;
+    for (int gi = 0; gi < ng; ++gi) {
+      const auto& x = one_d(gi, 0, n, lx);
+      bool zx = true;
+      for (double v : x) zx = zx && v == 0.0;
+      if (zx) continue;
+      const auto& y = one_d(gi, 1, n, ly);
+      bool zy = true;
+      for (double v : y) zy = zy && v == 0.0;
+      if (zy) continue;
+      const auto& z = one_d(gi, 2, n, lz);
+      double c = g[gi].coeff;
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+          double cij = c * x[i] * y[j];
+          double* o = out + (i * k + j) * k;
+          for (int m = 0; m < k; ++m) o[m] += cij * z[m];
+        }
+    }
+  }
+
+  // Frobenius norm of the wavelet part of the 8 children of (n, lx, ly, lz).
+  double wavelet_norm(int n, int64_t lx, int64_t ly, int64_t lz, std::vector<double>& kids) {
+    int k3 = k * k * k;
+    kids.resize(8 * k3);
+    for (int c = 0; c < 8; ++c)
+      box(n + 1, 2 * lx + ((c >> 2) & 1), 2 * ly + ((c >> 1) & 1), 2 * lz + (c & 1),
+          kids.data() + c * k3);
+    // s = sum_c (h^{bx} x h^{by} x h^{bz}) child_c ; ||d||^2 = ||B||^2 - ||s||^2 is prone to
+    // cancellation, so form d = B - unfilter(s) explicitly.
+    std::vector<double> s(k3, 0.0), t1(k3), t2(k3);
+    for (int c = 0; c < 8; ++c) {
+      const double* hx = ((c >> 2) & 1) ? h1.data() : h0.data();
+      const double* hy = ((c >> 1) & 1) ? h1.data() : h0.data();
+      const double* hz = (c & 1) ? h1.data() : h0.data();
+      const double* src = kids.data() + c * k3;
+      // t1[i][j'][m'] = sum_i' hx[i][i'] src[i'][j'][m']
+      for (int i = 0; i < k; ++i)
+        for (int r = 0; r < k * k; ++r) {
+          double acc = 0.0;
+          for (int ip = 0; ip < k; ++ip) acc += hx[i * k + ip] * src[ip * k * k + r];
+          t1[i * k * k + r] = acc;
+        }
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j)
+          for (int m = 0; m < k; ++m) {
+            double acc = 0.0;
+            for (int jp = 0; jp < k; ++jp) acc += hy[j * k + jp] * t1[(i * k + jp) * k + m];
+            t2[(i * k + j) * k + m] = acc;
+          }
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j)
+          for (int m = 0; m < k; ++m) {
+            double acc = 0.0;
+            for (int mp = 0; mp < k; ++mp) acc += hz[m * k + mp] * t2[(i * k + j) * k + mp];
+            s[(i * k + j) * k + m] += acc;
+          }
+    }
+    double d2 = 0.0;
+    for (int c = 0; c < 8; ++c) {
+      const double* hx = ((c >> 2) & 1) ? h1.data() : h0.data();
+      const double* hy = ((c >> 1) & 1) ? h1.data() : h0.data();
+      const double* hz = (c & 1) ? h1.data() : h0.data();
+      // u = (hx^T x hy^T x hz^T) s
+      for (int ip = 0; ip < k; ++ip)
+        for (int r = 0; r < k * k; ++r) {
+          double acc = 0.0;
+          for (int i = 0; i < k; ++i) acc += hx[i * k + ip] * s[i * k * k + r];
+          t1[ip * k * k + r] = acc;
+        }
+      for (int ip = 0; ip < k; ++ip)
+        for (int jp = 0; jp < k; ++jp)
+          for (int m = 0; m < k; ++m) {
+            double acc = 0.0;
+            for (int j = 0; j < k; ++j) acc += hy[j * k + jp] * t1[(ip * k + j) * k + m];
+            t2[(ip * k + jp) * k + m] = acc;
+          }
+      const double* src = kids.data() + c * k3;
+      for (int ip = 0; ip < k; ++ip)
+        for (int jp = 0; jp < k; ++jp)
+          for (int mp = 0; mp < k; ++mp) {
+            double acc = 0.0;
+            for (int m = 0; m < k; ++m) acc += hz[m * k + mp] * t2[(ip * k + jp) * k + m];
+            double d = src[(ip * k + jp) * k + mp] - acc;
+            d2 += d * d;
+          }
+    }
+    return std::sqrt(d2);
+  }
+};
+
+uint64_t interleave(int n, int64_t lx, int64_t ly, int64_t lz) {
+  uint64_t code = 0;
+  for (int b = 0; b < n; ++b) {
+    code |= (uint64_t)((lx >> b) & 1) << (3 * b + 2);
+    code |= (uint64_t)((ly >> b) & 1) << (3 * b + 1);
+    code |= (uint64_t)((lz >> b) & 1) << (3 * b);
+  }
+  return code;
+}
+
+}  // namespace
+
+void project_gaussians(Ctx* ctx, const mra_gaussian* g, int ng, int k, double thresh,
+                       int initial_level, int max_level, Func& out,
+                       std::vector<double>& leaf_coeffs) {
+  Projector pr;
+  pr.g = g;
+  pr.ng = ng;
+  pr.k = k;
+  pr.lo = ctx->lo;
+  pr.W = ctx->width();
+  two_scale_filters(k, pr.h0, pr.h1);
+  int k3 = k * k * k;
+  struct Box {
+    int n;
+    int64_t lx, ly, lz;
+  };
+  std::vector<Box> stack;
+  int64_t nb = (int64_t)1 << initial_level;
+  for (int64_t x = 0; x < nb; ++x)
+    for (int64_t y = 0; y < nb; ++y)
+      for (int64_t z = 0; z < nb; ++z) stack.push_back({initial_level, x, y, z});
+  std::vector<std::vector<uint64_t>> levels(max_level + 1);
+  std::vector<std::pair<uint64_t, std::vector<double>>> leafvals;  // (prefixed code, coeffs)
+  std::vector<double> kids;
+  while (!stack.empty()) {
+    Box b = stack.back();
+    stack.pop_back();
+    if (b.n < max_level && pr.wavelet_norm(b.n, b.lx, b.ly, b.lz, kids) > thresh) {
+      for (int c = 0; c < 8; ++c)
+        stack.push_back({b.n + 1, 2 * b.lx + ((c >> 2) & 1), 2 * b.ly + ((c >> 1) & 1),
+                         2 * b.lz + (c & 1)});
+    } else {
+      std::vector<double> v(k3);
+      pr.box(b.n, b.lx, b.ly, b.lz, v.data());
+      uint64_t code = interleave(b.n, b.lx, b.ly, b.lz);
+      leafvals.push_back({((uint64_t)b.n << 58) | code, std::move(v)});
+    }
+  }
+  // node sets: leaves plus all ancestors
+  std::vector<std::vector<uint64_t>> sets(max_level + 1);
+  for (auto& lv : leafvals) {
+    int n = (int)(lv.first >> 58);
+    uint64_t code = lv.first & ((1ULL << 58) - 1);
+    sets[n].push_back(code);
+    for (int m = n - 1; m >= 0; --m) {
+      code >>= 3;
+      sets[m].push_back(code);
+    }
+  }
+  for (auto& s : sets) {
+    std::sort(s.begin(), s.end());
+    s.erase(std::unique(s.begin(), s.end()), s.end());
+  }
+  out.ctx = ctx;
+  out.k = k;
+  build_tree(out, sets);
+  // leaf coefficients in node order
+  std::sort(leafvals.begin(), leafvals.end(),
+            [](const auto& a, const auto& b) { return a.first < b.first; });
+  leaf_coeffs.assign((size_t)out.nodes() * k3, 0.0);
+  for (auto& lv : leafvals) {
+    int n = (int)(lv.first >> 58);
+    uint64_t code = lv.first & ((1ULL << 58) - 1);
+    auto beg = out.code.begin() + out.level_off[n], end = out.code.begin() + out.level_off[n + 1];
+    auto it = std::lower_bound(beg, end, code);
+    int64_t node = it - out.code.begin();
+    std::copy(lv.second.begin(), lv.second.end(), leaf_coeffs.begin() + node * k3);
+  }
+}
+
+}  // namespace mra

@@ -1,0 +1,210 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.  Needs an MI355X.
+
+Tolerances: the pure-FP64 path must agree with the oracle to relative L2 <= 1e-12 over the
+compared leaves (summation order differs; nothing else may).  Trees are compared exactly.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import mra_workloads as W
+from oracle.analytic import gaussian_convolution
+from oracle.apply import SeparatedOperator, apply_standard, apply_nonstandard, sampled_leaves
+from oracle.fit import coulomb_fit, bsh_fit, cell_r_hi
+from oracle.projection import GaussianSum, project_adaptive, project_uniform
+from oracle.tree import morton, inner
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _key_tuple(code):
+    code = int(code)
+    n = (code.bit_length() - 1) // 3
+    code ^= 1 << (3 * n)
+    x = y = z = 0
+    for b in range(n):
+        x |= ((code >> (3 * b + 2)) & 1) << b
+        y |= ((code >> (3 * b + 1)) & 1) << b
+        z |= ((code >> (3 * b)) & 1) << b
+    return (n, x, y, z)
+
+
+def _as_dict(func):
+    keys, co = func.export()
+    return {_key_tuple(q): co[i] for i, q in enumerate(keys)}
+
+
+def _rel_l2(got, ref, keys):
+    num = math.sqrt(sum(float(np.sum((got[q] - ref[q]) ** 2)) for q in keys))
+    den = math.sqrt(sum(float(np.sum(ref[q] ** 2)) for q in keys))
+    return num / den
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_1507_01888_amd as mod
+    mod.load()
+    return mod
+
+
+def test_standard_form_gaussian_k8(M):
+    """Single-term k=8 standard-form apply on the uniform level-4 tree (4096 boxes)."""
+    _say("case: standard form, k=8, level 4, 27 displacements")
+    w = W.WORKLOADS["gauss_std_k8"]
+    ctx = M.Context(0, W.CELL)
+    f = ctx.project([w["f_coeff"]], [w["f_expnt"]], [[0, 0, 0]], w["k"], 1.0,
+                    initial_level=w["level"], max_level=w["level"])
+    op = ctx.op_gaussians(w["k"], w["op_c"], w["op_t"])
+    g = ctx.apply(op, f, form="standard", disp_radius=w["disp_radius"])
+    st = ctx.last_stats()
+    assert st["triples"] == 46 ** 3
+    fo = project_uniform(GaussianSum([w["f_coeff"]], [w["f_expnt"]], [[0, 0, 0]]), w["k"],
+                         W.CELL, w["level"])
+    fin = _as_dict(f)
+    assert set(fin) == set(fo.leaves)
+    assert _rel_l2(fin, fo.leaves, fo.leaves) < 1e-13
+    go, _ = apply_standard(fo, SeparatedOperator(w["op_c"], w["op_t"]), w["level"], 1)
+    got = _as_dict(g)
+    assert set(got) == set(go.leaves)
+    err = _rel_l2(got, go.leaves, go.leaves)
+    _say("standard k=8 rel L2 vs oracle", err)
+    assert err <= TOL
+    # analytic check of the GPU result (27 displacements: truncation ~8e-3, see oracle test)
+    cc, ee = gaussian_convolution(w["f_expnt"], w["op_t"][0])
+    ex = project_uniform(GaussianSum([w["f_coeff"] * cc], [ee], [[0, 0, 0]]), w["k"], W.CELL, w["level"])
+    assert 5e-3 < _rel_l2(got, ex.leaves, ex.leaves) < 1.2e-2
+    # a wider displacement cube reaches the projection floor
+    g3 = ctx.apply(op, f, form="standard", disp_radius=3)
+    assert _rel_l2(_as_dict(g3), ex.leaves, ex.leaves) < 2e-6
+
+
+def test_paper_example_on_gpu(M):
+    """Sec. 3.1 example: trace, norm2 and self-energy of exp(-r^2), and leaf parity."""
+    _say("case: paper example, k=6, thresh 1e-4, Coulomb(1e-4, 1e-6)")
+    cell = (-6.0, 6.0)
+    ctx = M.Context(0, cell)
+    g = ctx.project([1.0], [1.0], [[0, 0, 0]], 6, 1e-4)
+    op = ctx.op_coulomb(6, 1e-4, 1e-6)
+    vg = ctx.apply(op, g, tau_drop=1e-8)
+    tr, nrm, en = ctx.trace(g), ctx.norm2(g), ctx.inner(g, vg)
+    _say("trace", tr, "norm2", nrm, "energy", en)
+    assert abs(tr - math.pi ** 1.5) < 1e-6 * math.pi ** 1.5
+    assert abs(nrm - (math.pi / 2) ** 0.75) < 1e-6
+    assert abs(en - math.pi ** 2.5 * math.sqrt(2)) < 1e-6 * 24.74
+    # full parity of the output tree against the oracle
+    go = project_adaptive(GaussianSum([1.0], [1.0], [[0, 0, 0]]), 6, 1e-4, cell, 2, 20)
+    c, t = coulomb_fit(1e-4, 1e-6, cell_r_hi(*cell))
+    ref, st = apply_nonstandard(go, SeparatedOperator(c, t), 1e-8)
+    got = _as_dict(vg)
+    assert set(got) == set(ref.leaves)
+    assert ctx.last_stats()["triples"] == st["triples"]
+    err = _rel_l2(got, ref.leaves, ref.leaves)
+    _say("paper example rel L2 vs oracle", err)
+    assert err <= TOL
+    assert abs(en - inner(go, ref)) < 1e-12 * en
+
+
+def test_coulomb_k10_reduced_full_parity(M):
+    """k=10 Coulomb non-standard apply, 2 Gaussians at thresh 1e-5: every leaf compared."""
+    _say("case: coulomb k=10 reduced (2 Gaussians, thresh 1e-5)")
+    c, a, x = W.unit_charge_gaussians(1, 7, 2, 1.0, 30.0)
+    ctx = M.Context(0, W.CELL)
+    f = ctx.project(c, a, x, 10, 1e-5)
+    op = ctx.op_coulomb(10, 1e-5, 1e-8)
+    g = ctx.apply(op, f, tau_drop=1e-9)
+    fo = project_adaptive(GaussianSum(c, a, x), 10, 1e-5, W.CELL, 2, 20)
+    assert set(_as_dict(f)) == set(fo.leaves)
+    cc, tt = coulomb_fit(1e-5, 1e-8, cell_r_hi(*W.CELL))
+    oc, ot = op.terms()
+    assert np.array_equal(oc.size, cc.size) and np.abs(oc / cc - 1).max() < 1e-14
+    ref, st = apply_nonstandard(fo, SeparatedOperator(cc, tt), 1e-9)
+    got = _as_dict(g)
+    assert set(got) == set(ref.leaves)
+    assert ctx.last_stats()["triples"] == st["triples"]
+    err = _rel_l2(got, ref.leaves, ref.leaves)
+    _say("coulomb k10 reduced rel L2 vs oracle", err, "triples", st["triples"])
+    assert err <= TOL
+    # norm2 through the reduction kernel
+    assert abs(ctx.norm2(g) - ref.norm2()) < 1e-12 * ref.norm2()
+
+
+def test_bsh_k10_reduced_full_parity(M):
+    """k=10 bound-state Helmholtz apply of one batched-workload function (reduced thresh)."""
+    c, a, x, mu = W.bsh_inputs(0)
+    _say("case: bsh k=10, mu=%.3f, %d Gaussians, thresh 1e-4" % (mu, len(c)))
+    ctx = M.Context(0, W.CELL)
+    f = ctx.project(c, a, x, 10, 1e-4)
+    op = ctx.op_bsh(10, mu, 1e-5, 1e-8)
+    g = ctx.apply(op, f, tau_drop=1e-8)
+    fo = project_adaptive(GaussianSum(c, a, x), 10, 1e-4, W.CELL, 2, 20)
+    cc, tt = bsh_fit(mu, 1e-5, 1e-8, cell_r_hi(*W.CELL))
+    ref, st = apply_nonstandard(fo, SeparatedOperator(cc, tt), 1e-8)
+    got = _as_dict(g)
+    assert set(got) == set(ref.leaves)
+    err = _rel_l2(got, ref.leaves, ref.leaves)
+    _say("bsh rel L2 vs oracle", err)
+    assert err <= TOL
+
+
+def test_coulomb_k10_full_size_sampled(M):
+    """The full k=10, thresh 1e-6 Coulomb workload (4 Gaussians, a in [1, 1e3]): leaves
+    sampled across levels are recomputed by the oracle along their root paths."""
+    w = W.WORKLOADS["coulomb_k10"]
+    _say("case: coulomb_k10 full size, sampled leaves")
+    c, a, x = W.coulomb_inputs("coulomb_k10", 0)
+    ctx = M.Context(0, W.CELL)
+    f = ctx.project(c, a, x, w["k"], w["thresh"])
+    op = ctx.op_coulomb(w["k"], w["r_lo"], w["eps"])
+    tau = w["tau_rel"] * w["thresh"]
+    g = ctx.apply(op, f, tau_drop=tau)
+    st = ctx.last_stats()
+    _say("gpu stats", st)
+    got = _as_dict(g)
+    rng = np.random.default_rng(5)
+    keys = sorted(got)
+    by_level = {}
+    for q in keys:
+        by_level.setdefault(q[0], []).append(q)
+    sample = []
+    for n, lst in sorted(by_level.items()):
+        for i in rng.choice(len(lst), min(3, len(lst)), replace=False):
+            sample.append(lst[i])
+    fo = project_adaptive(GaussianSum(c, a, x), w["k"], w["thresh"], W.CELL, 2, 20)
+    cc, tt = coulomb_fit(w["r_lo"], w["eps"], cell_r_hi(*W.CELL))
+    vals, has_acc, _ = sampled_leaves(fo, SeparatedOperator(cc, tt), tau, sample)
+    for q in sample:
+        assert not has_acc[q]          # the oracle agrees these are output leaves
+    err = _rel_l2(got, vals, sample)
+    _say("coulomb_k10 sampled (%d leaves) rel L2 vs oracle" % len(sample), err)
+    assert err <= TOL
+
+
+def test_deterministic_and_errors(M):
+    _say("case: determinism and error codes")
+    ctx = M.Context(0, W.CELL)
+    c, a, x = W.unit_charge_gaussians(1, 3, 1, 2.0, 2.0)
+    f = ctx.project(c, a, x, 8, 1e-4)
+    op = ctx.op_coulomb(8, 1e-4, 1e-6)
+    g1 = _as_dict(ctx.apply(op, f, tau_drop=1e-8))
+    g2 = _as_dict(ctx.apply(op, f, tau_drop=1e-8))
+    assert all(np.array_equal(g1[q], g2[q]) for q in g1)
+    op6 = ctx.op_coulomb(6, 1e-4, 1e-6)
+    with pytest.raises(M.MraError) as e:
+        ctx.apply(op6, f, tau_drop=1e-8)
+    assert e.value.code == -5
+    f12 = ctx.project(c, a, x, 12, 1e-3)
+    op12 = ctx.op_coulomb(12, 1e-4, 1e-6)
+    with pytest.raises(M.MraError) as e:
+        ctx.apply(op12, f12, tau_drop=1e-8)
+    assert e.value.code == -4
+    with pytest.raises(M.MraError) as e:
+        ctx.project(c, a, x, 15, 1e-3)
+    assert e.value.code == -1
