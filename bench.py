@@ -32,7 +32,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="coulomb_k10", choices=["coulomb_k10"])
+    p.add_argument("--workload", default="coulomb_k10",
+                   choices=["coulomb_k10", "coulomb_k12_fp64", "bsh_batch_k10"])
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="approximate CPU work of the oracle baseline sample (0 = skip)")
     return p.parse_args()
@@ -71,6 +72,34 @@ def cpu_baseline(name, budget_s):
                       "block quadrature included)" % (done, flops / 1e9, secs)}
 
 
+def setup(ctx, name):
+    """Functions, operators and tau for a workload; returns (funcs, ops, tau, k, config)."""
+    if name == "bsh_batch_k10":
+        w = W.WORKLOADS[name]
+        funcs, ops, mus, ng = [], [], [], []
+        for i in range(w["n_funcs"]):
+            c, a, x, mu = W.bsh_inputs(i)
+            funcs.append(ctx.project(c, a, x, w["k"], w["thresh"], initial_level=w["initial_level"]))
+            ops.append(ctx.op_bsh(w["k"], mu, w["r_lo"], w["eps"]))
+            mus.append(mu)
+            ng.append(len(c))
+        cfg = {"workload": name, "k": w["k"], "thresh": w["thresh"], "functions": w["n_funcs"],
+               "gaussians_per_function": [min(ng), max(ng)], "operator": "bsh exp(-mu r)/r",
+               "mu_range": [min(mus), max(mus)], "eps_fit": w["eps"], "r_lo": w["r_lo"],
+               "tau_drop": w["tau_rel"] * w["thresh"], "precision": "fp64",
+               "launch": "one batched apply (all functions per kernel launch)"}
+        return funcs, ops, w["tau_rel"] * w["thresh"], w["k"], cfg
+    base = "coulomb_k12_mixed" if name == "coulomb_k12_fp64" else name
+    w = W.WORKLOADS[base]
+    c, a, x = W.coulomb_inputs(base, 0)
+    f = ctx.project(c, a, x, w["k"], w["thresh"], initial_level=w["initial_level"])
+    op = ctx.op_coulomb(w["k"], w["r_lo"], w["eps"])
+    cfg = {"workload": name, "k": w["k"], "thresh": w["thresh"], "gaussians": w["n_gauss"],
+           "operator": "coulomb", "terms": int(op.terms()[0].size), "eps_fit": w["eps"],
+           "r_lo": w["r_lo"], "tau_drop": w["tau_rel"] * w["thresh"], "precision": "fp64"}
+    return [f], [op], w["tau_rel"] * w["thresh"], w["k"], cfg
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -81,18 +110,18 @@ def main():
     import torch
     import paper_1507_01888_amd as M
 
-    w = W.WORKLOADS[args.workload]
     ctx = M.Context(0, W.CELL)
-    c, a, x = W.coulomb_inputs(args.workload, 0)
-    f = ctx.project(c, a, x, w["k"], w["thresh"], initial_level=w["initial_level"])
-    op = ctx.op_coulomb(w["k"], w["r_lo"], w["eps"])
-    tau = w["tau_rel"] * w["thresh"]
+    funcs, ops, tau, k, cfg = setup(ctx, args.workload)
 
     def step():
-        g = ctx.apply(op, f, tau_drop=tau)
+        if len(funcs) == 1:
+            gs = [ctx.apply(ops[0], funcs[0], tau_drop=tau)]
+        else:
+            gs = ctx.apply_batch(ops, funcs, tau_drop=tau)
         st = ctx.last_stats()
-        nrm = ctx.norm2(g)
-        g.free()
+        nrm = [ctx.norm2(g) for g in gs]
+        for g in gs:
+            g.free()
         return st, nrm
 
     for _ in range(args.warmup):
@@ -107,10 +136,12 @@ def main():
     elapsed = time.perf_counter() - t0
 
     flops = sum(s["useful_flops"] for s in stats)
-    k = w["k"]
-    ns_flops_per_launch = stats[0]["triples"] * 6.0 * (2 * k) ** 4
+    # the main kernel applies the children blocks and (for k = 8, 10, 12) the fused level-n
+    # subtraction, so its algorithmic work is the full useful flop count of the step
+    fused = k in (8, 10, 12)
+    kernel_flops = stats[0]["useful_flops"] if fused else stats[0]["triples"] * 6.0 * (2 * k) ** 4
     main_ms = sum(s["ms_main_kernel"] for s in stats) / len(stats)
-    achieved = ns_flops_per_launch / (main_ms * 1e-3) / 1e12
+    achieved = kernel_flops / (main_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": flops / elapsed / 1e9,
@@ -124,22 +155,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "k": k, "thresh": w["thresh"],
-                   "gaussians": w["n_gauss"], "operator": "coulomb",
-                   "terms": int(op.terms()[0].size), "eps_fit": w["eps"], "r_lo": w["r_lo"],
-                   "tau_drop": tau, "precision": "fp64"},
+        "config": cfg,
         "boxes_per_s": stats[0]["in_leaves"] * args.steps / elapsed,
         "time_to_solution_ms": elapsed / args.steps * 1e3,
         "counts": {key: stats[0][key] for key in ("triples", "targets", "in_leaves", "out_nodes",
                                                    "out_leaves")},
         "stage_ms": {key: sum(s[key] for s in stats) / len(stats)
                      for key in ("ms_filter", "ms_plan", "ms_apply", "ms_main_kernel", "ms_sumdown")},
-        "norm2": nrm,
-        "roofline": {"kernel": "apply_ns_kernel", "bound": "alu", "achieved": achieved,
+        "norm2": nrm[0] if len(nrm) == 1 else sum(v * v for v in nrm) ** 0.5,
+        "roofline": {"kernel": {8: "apply_ns_mfma_kernel<8>", 10: "apply_ns_mfma_kernel<10>",
+                                12: "apply_ns_mfma_big_kernel<12>"}.get(k, "apply_ns_kernel<%d>" % k),
+                     "bound": "mfma" if k in (8, 10, 12) else "alu", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": None},
     }
-    if args.cpu_seconds > 0:
+    if args.cpu_seconds > 0 and args.workload == "coulomb_k10":
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(out))
 

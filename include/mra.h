@@ -147,6 +147,15 @@ mra_status mra_op_free(mra_op* op);
 mra_status mra_apply(mra_ctx* ctx, const mra_op* op, const mra_func* f,
                      const mra_apply_params* params, mra_func** out);
 
+/* op_i(f_i) for i < n in one pass: filter-up, screening, transform-and-accumulate and
+ * sum-down each run as one launch sequence over all functions (non-standard form only).
+ * Functions may have different trees and operators different terms, but all share k.
+ * outs receives n new functions (written only on success).  A function may appear only
+ * once (its refined-box slabs are workspace); operators may repeat. */
+mra_status mra_apply_batch(mra_ctx* ctx, int n, const mra_op* const* ops,
+                           const mra_func* const* fs, const mra_apply_params* params,
+                           mra_func** outs);
+
 /* 2-norm sqrt(sum over leaves ||s||^2) (orthonormal basis), FP64, fixed-order reduction. */
 mra_status mra_norm2(mra_ctx* ctx, const mra_func* f, double* out);
 /* Integral of f over the cell: sum over leaves s_000 h_n^{3/2}. */

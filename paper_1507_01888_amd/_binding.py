@@ -22,7 +22,8 @@ FORM_STANDARD = 1
 EXPORTED = [
     "mra_ctx_create", "mra_ctx_free", "mra_last_error", "mra_project", "mra_func_info",
     "mra_func_export", "mra_func_free", "mra_op_coulomb", "mra_op_bsh", "mra_op_gaussians",
-    "mra_op_terms", "mra_op_free", "mra_apply", "mra_norm2", "mra_trace", "mra_inner",
+    "mra_op_terms", "mra_op_free", "mra_apply", "mra_apply_batch", "mra_norm2", "mra_trace",
+    "mra_inner",
     "mra_last_stats", "mra_host_fit", "mra_host_block", "mra_host_filters",
     "mra_host_spectral_norm", "mra_host_project",
 ]
@@ -96,6 +97,7 @@ def load():
     lib.mra_op_terms.argtypes = [vp, P(ctypes.c_int), dp, dp]
     lib.mra_op_free.argtypes = [vp]
     lib.mra_apply.argtypes = [vp, vp, vp, P(ApplyParams), P(vp)]
+    lib.mra_apply_batch.argtypes = [vp, ctypes.c_int, P(vp), P(vp), P(ApplyParams), P(vp)]
     lib.mra_norm2.argtypes = [vp, vp, dp]
     lib.mra_trace.argtypes = [vp, vp, dp]
     lib.mra_inner.argtypes = [vp, vp, vp, dp]
@@ -286,6 +288,19 @@ class Context:
         self._check(self._lib.mra_apply(self.h, op.h, f.h, ctypes.byref(p), ctypes.byref(h)),
                     "mra_apply")
         return Function(self, h)
+
+    def apply_batch(self, ops, funcs, tau_drop=0.0):
+        """[op_i(f_i)] in one batched pass (non-standard form)."""
+        n = len(funcs)
+        if len(ops) != n:
+            raise ValueError("need one operator per function")
+        oarr = (ctypes.c_void_p * n)(*[o.h.value for o in ops])
+        farr = (ctypes.c_void_p * n)(*[f.h.value for f in funcs])
+        outs = (ctypes.c_void_p * n)()
+        p = ApplyParams(FORM_NONSTANDARD, 1, tau_drop)
+        self._check(self._lib.mra_apply_batch(self.h, n, oarr, farr, ctypes.byref(p), outs),
+                    "mra_apply_batch")
+        return [Function(self, ctypes.c_void_p(outs[i])) for i in range(n)]
 
     def norm2(self, f):
         v = ctypes.c_double()

@@ -1,0 +1,644 @@
+// Non-standard apply (Sec. 2.2-2.3) for one function or a batch of functions.
+//
+// Steps, all on the context's stream:
+//   1. filter-up (device): s_P and ||B_P||_F^2 of every refined box of every function, one
+//      launch per level for the whole batch; one copy of the norms to the host;
+//   2. screening (host, threads over (function, level, term) jobs): triples (P, delta, mu)
+//      with eta = |c_mu| N(delta) ||B_P||_F >= tau_drop and target inside the cell;
+//   3. per function (threads over functions): targets grouped by a counting sort, the
+//      output tree (targets, their children, ancestors, closed under siblings) and the
+//      target-sorted work list; long lists are split over several workgroups;
+//   4. transform-and-accumulate (device): one launch for all children blocks, one for the
+//      sum of split partials, one for the level-n subtractions (all functions together);
+//   5. sum-down (device), one launch per level for the whole batch.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <numeric>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+
+#include "mra_internal.hpp"
+
+namespace mra {
+
+namespace {
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+void decode(uint64_t code, int n, int64_t& x, int64_t& y, int64_t& z) {
+  x = y = z = 0;
+  for (int b = 0; b < n; ++b) {
+    x |= (int64_t)((code >> (3 * b + 2)) & 1) << b;
+    y |= (int64_t)((code >> (3 * b + 1)) & 1) << b;
+    z |= (int64_t)((code >> (3 * b)) & 1) << b;
+  }
+}
+
+uint64_t encode(int n, int64_t x, int64_t y, int64_t z) {
+  uint64_t code = 0;
+  for (int b = 0; b < n; ++b) {
+    code |= (uint64_t)((x >> b) & 1) << (3 * b + 2);
+    code |= (uint64_t)((y >> b) & 1) << (3 * b + 1);
+    code |= (uint64_t)((z >> b) & 1) << (3 * b);
+  }
+  return code;
+}
+
+int64_t find_node(const Func& f, int n, uint64_t code) {
+  if (n >= f.nlev) return -1;
+  auto beg = f.code.begin() + f.level_off[n], end = f.code.begin() + f.level_off[n + 1];
+  auto it = std::lower_bound(beg, end, code);
+  if (it == end || *it != code) return -1;
+  return it - f.code.begin();
+}
+
+unsigned worker_count(size_t jobs) {
+  unsigned n = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  return (unsigned)std::min<size_t>(n, std::max<size_t>(1, jobs));
+}
+
+template <class F>
+void parallel_for(size_t count, F&& fn) {
+  unsigned nthr = worker_count(count);
+  if (nthr <= 1) {
+    for (size_t i = 0; i < count; ++i) fn(i, 0u);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nthr; ++t)
+    th.emplace_back([&, t] {
+      for (size_t i = t; i < count; i += nthr) fn(i, t);
+    });
+  for (size_t i = 0; i < count; i += nthr) fn(i, 0u);
+  for (auto& t : th) t.join();
+}
+
+struct Triple {
+  uint64_t tcode;  // (level << 58) | code of the target
+  int32_t src;     // index into f.interior
+  int16_t mu;
+  int16_t dx, dy, dz;
+};
+
+struct LevelData {
+  int fn = 0, n = 0;
+  int64_t ib = 0, np = 0;
+  double maxb = 0.0;
+  std::vector<double> bn;
+  std::vector<int64_t> px, py, pz, order;
+};
+
+struct Job {
+  int lev, mu, D;
+  const BlockEntry* be;
+};
+
+// Host-side plan of one function.
+struct Plan {
+  Op* op = nullptr;
+  Func* f = nullptr;
+  Func* out = nullptr;
+  std::vector<const BlockEntry*> entry_tab;  // (level, mu) -> cache entry
+  std::vector<Triple> triples;                // grouped by target, then (source, term)
+  std::vector<NSItem> items;
+  std::vector<TargetRange> tgt, tgt_sub;
+  double flops = 0.0;
+};
+
+void validate(const Plan& p, int64_t nR, int64_t nT) {
+  const int64_t nin = p.f->nodes(), nout = p.out->nodes();
+  auto bad = [](const char* what) {
+    fail(MRA_E_INVALID, std::string("internal plan error: ") + what);
+  };
+  for (const NSItem& it : p.items) {
+    if (it.src < 0 || it.src >= nin) bad("source node");
+    if (it.src_fc < 0 || it.src_fc + 8 > nin) bad("source children");
+    if (it.mu < 0 || it.mu >= (int)p.op->c.size()) bad("term index");
+    if (it.rx < 0 || it.rx >= nR || it.ry < 0 || it.ry >= nR || it.rz < 0 || it.rz >= nR)
+      bad("R block");
+    if (it.tx < 0 || it.tx >= nT || it.ty < 0 || it.ty >= nT || it.tz < 0 || it.tz >= nT)
+      bad("t block");
+  }
+  for (const TargetRange& r : p.tgt) {
+    if (r.node < 0 || r.node >= nout || r.fc < 0 || r.fc + 8 > nout) bad("target node");
+    if (r.beg < 0 || r.end < r.beg || r.end > (int32_t)p.items.size()) bad("item range");
+  }
+}
+
+// Output tree, items and target ranges of one function from its grouped triples.
+void build_plan(Ctx* ctx, Plan& p) {
+  Func& f = *p.f;
+  Func& out = *p.out;
+  const int k = f.k;
+  const int M = (int)p.op->c.size();
+  const auto& triples = p.triples;
+  int maxlev = 0;
+  for (auto& t : triples) maxlev = std::max(maxlev, (int)(t.tcode >> 58) + 1);
+  std::vector<std::vector<uint64_t>> sets(std::max(maxlev + 1, 1));
+  for (size_t i = 0; i < triples.size(); ++i) {
+    if (i > 0 && triples[i].tcode == triples[i - 1].tcode) continue;
+    int n = (int)(triples[i].tcode >> 58);
+    uint64_t code = triples[i].tcode & ((1ULL << 58) - 1);
+    sets[n].push_back(code);
+    for (int c = 0; c < 8; ++c) sets[n + 1].push_back((code << 3) | c);
+  }
+  sets[0].push_back(0);
+  for (int n = (int)sets.size() - 1; n >= 1; --n) {
+    auto& s = sets[n];
+    std::sort(s.begin(), s.end());
+    s.erase(std::unique(s.begin(), s.end()), s.end());
+    std::vector<uint64_t> full;
+    full.reserve(s.size() * 2);
+    uint64_t lastp = ~0ULL;
+    for (uint64_t code : s) {
+      uint64_t par = code >> 3;
+      if (par == lastp) continue;
+      lastp = par;
+      for (int c = 0; c < 8; ++c) full.push_back((par << 3) | c);
+      sets[n - 1].push_back(par);
+    }
+    s.swap(full);
+  }
+  std::sort(sets[0].begin(), sets[0].end());
+  sets[0].erase(std::unique(sets[0].begin(), sets[0].end()), sets[0].end());
+  out.ctx = ctx;
+  out.k = k;
+  build_tree(out, sets);
+
+  p.items.clear();
+  p.items.reserve(triples.size());
+  p.tgt.clear();
+  p.tgt_sub.clear();
+  p.flops = 0.0;
+  const double f_ns = 6.0 * std::pow(2.0 * k, 4), f_sub = 6.0 * std::pow((double)k, 4);
+  for (size_t i = 0; i < triples.size();) {
+    size_t j = i;
+    while (j < triples.size() && triples[j].tcode == triples[i].tcode) ++j;
+    int n = (int)(triples[i].tcode >> 58);
+    uint64_t code = triples[i].tcode & ((1ULL << 58) - 1);
+    int64_t node = find_node(out, n, code);
+    // sub = 0 marks "has a level-n subtraction"; the slot is assigned when combining
+    TargetRange r{0, (int32_t)node, out.first_child[node], (int32_t)p.items.size(), 0, -1,
+                  n > 0 ? 0 : -1};
+    for (size_t q = i; q < j; ++q) {
+      const Triple& t = triples[q];
+      const BlockEntry& be = *p.entry_tab[(size_t)n * M + t.mu];
+      NSItem it;
+      it.src = f.interior[t.src];
+      it.src_fc = f.first_child[it.src];
+      it.mu = t.mu;
+      it.rx = (int32_t)(be.r_base + t.dx + be.D);
+      it.ry = (int32_t)(be.r_base + t.dy + be.D);
+      it.rz = (int32_t)(be.r_base + t.dz + be.D);
+      it.tx = (int32_t)(be.t_base + t.dx + be.D);
+      it.ty = (int32_t)(be.t_base + t.dy + be.D);
+      it.tz = (int32_t)(be.t_base + t.dz + be.D);
+      p.items.push_back(it);
+      p.flops += f_ns + (n > 0 ? f_sub : 0.0);
+    }
+    r.end = (int32_t)p.items.size();
+    p.tgt.push_back(r);
+    if (n > 0) p.tgt_sub.push_back(r);
+    i = j;
+  }
+}
+
+}  // namespace
+
+void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
+                             const std::vector<Func*>& funcs, double tau,
+                             const std::vector<Func*>& outs) {
+  const int nf = (int)funcs.size();
+  if (nf == 0) return;
+  const int k = funcs[0]->k;
+  const int K3 = k * k * k;
+  std::vector<double> h0v, h1v;
+  two_scale_filters(k, h0v, h1v);
+  DevArray<double> h0, h1;
+  h0.upload(ctx, h0v);
+  h1.upload(ctx, h1v);
+
+  // ---- 1. filter-up for the whole batch
+  hip_check(hipEventRecord(ctx->ev[0], ctx->stream), "event");
+  std::vector<double*> coeff_in(nf);
+  for (int i = 0; i < nf; ++i) coeff_in[i] = funcs[i]->coeff.p;
+  DevArray<double*> d_in_tab;
+  d_in_tab.upload(ctx, coeff_in);
+  int maxlev = 0;
+  for (Func* f : funcs) maxlev = std::max(maxlev, f->nlev);
+  std::vector<NodeRef> fu_refs;
+  std::vector<int64_t> fu_off(maxlev + 1, 0);        // refs of level maxlev-1-j
+  std::vector<std::vector<int64_t>> fu_index(nf);    // per function: entry of each interior
+  for (int i = 0; i < nf; ++i) fu_index[i].resize(funcs[i]->interior.size());
+  for (int n = maxlev - 1, j = 0; n >= 0; --n, ++j) {
+    for (int i = 0; i < nf; ++i) {
+      const Func& f = *funcs[i];
+      if (n >= f.nlev) continue;
+      for (int64_t q = f.inter_level_off[n]; q < f.inter_level_off[n + 1]; ++q) {
+        fu_index[i][q] = (int64_t)fu_refs.size();
+        fu_refs.push_back({i, f.interior[q], f.first_child[f.interior[q]], -1});
+      }
+    }
+    fu_off[j + 1] = (int64_t)fu_refs.size();
+  }
+  DevArray<NodeRef> d_fu;
+  d_fu.upload(ctx, fu_refs);
+  DevArray<double> d_bn2;
+  d_bn2.alloc(ctx, std::max<size_t>(1, fu_refs.size()));
+  for (int j = 0; j < maxlev; ++j) {
+    int64_t b = fu_off[j], e = fu_off[j + 1];
+    if (e > b)
+      launch_filter_up(k, d_in_tab.p, d_fu.p + b, (int)(e - b), h0.p, h1.p, d_bn2.p + b,
+                       ctx->stream);
+  }
+  std::vector<double> bn2_all(fu_refs.size());
+  if (!fu_refs.empty())
+    hip_check(hipMemcpyAsync(bn2_all.data(), d_bn2.p, fu_refs.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx->stream),
+              "hipMemcpyAsync D2H");
+  hip_check(hipEventRecord(ctx->ev[1], ctx->stream), "event");
+  ctx->sync();
+  for (Func* f : funcs) f->interior_valid = true;
+  double t_plan0 = now_ms();
+  const bool timing = std::getenv("MRA_TIMING") != nullptr;
+  double t_mark = t_plan0;
+  auto mark = [&](const char* what) {
+    if (!timing) return;
+    double t = now_ms();
+    std::fprintf(stderr, "[mra] %-28s %8.3f ms\n", what, t - t_mark);
+    t_mark = t;
+  };
+
+  // ---- 2a. levels and (level, term) jobs; the block cache is filled here (sequential)
+  const double W = ctx->width();
+  std::vector<Plan> plans(nf);
+  std::vector<LevelData> lv;
+  std::vector<Job> jobs;
+  for (int i = 0; i < nf; ++i) {
+    Func& f = *funcs[i];
+    Op& op = *ops[i];
+    plans[i].op = &op;
+    plans[i].f = &f;
+    plans[i].out = outs[i];
+    const int M = (int)op.c.size();
+    plans[i].entry_tab.assign((size_t)std::max(1, f.nlev) * M, nullptr);
+    for (int n = 0; n < f.nlev; ++n) {
+      int64_t ib = f.inter_level_off[n], ie = f.inter_level_off[n + 1];
+      if (ie <= ib) continue;
+      LevelData L;
+      L.fn = i;
+      L.n = n;
+      L.ib = ib;
+      L.np = ie - ib;
+      L.bn.resize(L.np);
+      L.px.resize(L.np);
+      L.py.resize(L.np);
+      L.pz.resize(L.np);
+      for (int64_t q = 0; q < L.np; ++q) {
+        L.bn[q] = std::sqrt(bn2_all[fu_index[i][ib + q]]);
+        L.maxb = std::max(L.maxb, L.bn[q]);
+        decode(f.code[f.interior[ib + q]], n, L.px[q], L.py[q], L.pz[q]);
+      }
+      L.order.resize(L.np);
+      std::iota(L.order.begin(), L.order.end(), 0);
+      std::stable_sort(L.order.begin(), L.order.end(),
+                       [&](int64_t a, int64_t b) { return L.bn[a] > L.bn[b]; });
+      const int li = (int)lv.size();
+      lv.push_back(std::move(L));
+      const LevelData& LL = lv.back();
+      const int64_t nb = (int64_t)1 << n;
+      const double h = W / std::ldexp(1.0, n);
+      for (int mu = 0; mu < M; ++mu) {
+        double c = std::fabs(op.c[mu]);
+        double beta = op.t[mu] * h * h;
+        double ab = 2.0 * h;
+        double fac = 1.0;
+        if (n > 0) {
+          if (c * LL.maxb * 3.0 * e_bound(k, h, beta) * ab * ab < tau) continue;
+          fac = 3.0;
+        }
+        int D = 0;
+        while (D + 1 <= nb - 1 && c * LL.maxb * fac * ab * ab * decay_bound(h, beta, D + 1) >= tau)
+          ++D;
+        if (D > 32000) fail(MRA_E_UNSUPPORTED, "displacement range too large");
+        jobs.push_back({li, mu, D, nullptr});
+      }
+    }
+  }
+  // Fill the block caches: distinct operators in parallel, each operator's entries in order.
+  {
+    std::vector<Op*> uops;
+    for (Op* op : ops)
+      if (std::find(uops.begin(), uops.end(), op) == uops.end()) uops.push_back(op);
+    std::vector<std::vector<size_t>> by_op(uops.size());
+    for (size_t j = 0; j < jobs.size(); ++j) {
+      Op* op = ops[lv[jobs[j].lev].fn];
+      by_op[std::find(uops.begin(), uops.end(), op) - uops.begin()].push_back(j);
+    }
+    std::vector<std::string> errs(uops.size());
+    parallel_for(uops.size(), [&](size_t u, unsigned) {
+      try {
+        for (size_t j : by_op[u]) {
+          Job& jb = jobs[j];
+          jb.be = &uops[u]->ensure(lv[jb.lev].n, jb.mu, jb.D);
+        }
+      } catch (const Error& e) {
+        errs[u] = e.msg;
+      }
+    });
+    for (auto& e : errs)
+      if (!e.empty()) fail(MRA_E_INVALID, e);
+    for (const Job& jb : jobs) {
+      const LevelData& L = lv[jb.lev];
+      plans[L.fn].entry_tab[(size_t)L.n * ops[L.fn]->c.size() + jb.mu] = jb.be;
+    }
+  }
+
+  mark("levels and jobs");
+  // ---- 2b. enumerate kept triples (threads over jobs)
+  const unsigned nthr = worker_count(jobs.size());
+  std::vector<std::vector<std::pair<int32_t, Triple>>> part(nthr);
+  parallel_for(jobs.size(), [&](size_t j, unsigned tno) {
+    const Job& jb = jobs[j];
+    const LevelData& L = lv[jb.lev];
+    const Op& op = *ops[L.fn];
+    const int n = L.n, D = jb.D, mu = jb.mu;
+    const int64_t nb = (int64_t)1 << n;
+    const double c = std::fabs(op.c[mu]);
+    std::vector<double> ae(D + 1), aa(D + 1), rr(D + 1);
+    for (int d = 0; d <= D; ++d) {
+      ae[d] = jb.be->a[d] + jb.be->e[d];
+      aa[d] = jb.be->a[d];
+      rr[d] = jb.be->r[d];
+    }
+    auto& outv = part[tno];
+    for (int dx = -D; dx <= D; ++dx)
+      for (int dy = -D; dy <= D; ++dy)
+        for (int dz = -D; dz <= D; ++dz) {
+          int ax = std::abs(dx), ay = std::abs(dy), az = std::abs(dz);
+          double N = (n > 0) ? ae[ax] * ae[ay] * ae[az] - aa[ax] * aa[ay] * aa[az]
+                             : rr[ax] * rr[ay] * rr[az];
+          if (c * N * L.maxb < tau) continue;
+          for (int64_t oi = 0; oi < L.np; ++oi) {
+            int64_t p = L.order[oi];
+            if (!(c * N * L.bn[p] >= tau)) break;
+            int64_t tx = L.px[p] + dx, ty = L.py[p] + dy, tz = L.pz[p] + dz;
+            if (tx < 0 || ty < 0 || tz < 0 || tx >= nb || ty >= nb || tz >= nb) continue;
+            outv.push_back({L.fn, {((uint64_t)n << 58) | encode(n, tx, ty, tz), (int32_t)(L.ib + p),
+                                   (int16_t)mu, (int16_t)dx, (int16_t)dy, (int16_t)dz}});
+          }
+        }
+  });
+  // bucket by function
+  {
+    std::vector<size_t> cnt(nf, 0);
+    for (auto& v : part)
+      for (auto& pr : v) ++cnt[pr.first];
+    std::vector<std::vector<Triple>> byfn(nf);
+    for (int i = 0; i < nf; ++i) byfn[i].reserve(cnt[i]);
+    for (auto& v : part) {
+      for (auto& pr : v) byfn[pr.first].push_back(pr.second);
+      std::vector<std::pair<int32_t, Triple>>().swap(v);
+    }
+    for (int i = 0; i < nf; ++i) plans[i].triples.swap(byfn[i]);
+  }
+
+  mark("enumerate + bucket");
+  // ---- 3. per function: group by target, output tree, work list (threads over functions)
+  parallel_for((size_t)nf, [&](size_t i, unsigned) {
+    Plan& p = plans[i];
+    auto& tr = p.triples;
+    std::vector<uint64_t> tcodes;
+    {
+      std::unordered_set<uint64_t> seen;
+      seen.reserve(tr.size() / 8 + 16);
+      for (auto& t : tr)
+        if (seen.insert(t.tcode).second) tcodes.push_back(t.tcode);
+      std::sort(tcodes.begin(), tcodes.end());
+    }
+    std::unordered_map<uint64_t, int32_t> tindex;
+    tindex.reserve(tcodes.size() * 2 + 16);
+    for (size_t q = 0; q < tcodes.size(); ++q) tindex.emplace(tcodes[q], (int32_t)q);
+    std::vector<int64_t> toff(tcodes.size() + 1, 0);
+    std::vector<int32_t> slot(tr.size());
+    for (size_t q = 0; q < tr.size(); ++q) {
+      slot[q] = tindex[tr[q].tcode];
+      ++toff[slot[q] + 1];
+    }
+    for (size_t q = 0; q < tcodes.size(); ++q) toff[q + 1] += toff[q];
+    std::vector<Triple> sorted(tr.size());
+    std::vector<int64_t> fillp(toff.begin(), toff.end() - 1);
+    for (size_t q = 0; q < tr.size(); ++q) sorted[fillp[slot[q]]++] = tr[q];
+    for (size_t q = 0; q < tcodes.size(); ++q)
+      std::sort(sorted.begin() + toff[q], sorted.begin() + toff[q + 1],
+                [](const Triple& a, const Triple& b) {
+                  if (a.src != b.src) return a.src < b.src;
+                  return a.mu < b.mu;
+                });
+    tr.swap(sorted);
+    build_plan(ctx, p);
+  });
+
+  mark("group + output tree + items");
+  // ---- 4. combine the batch
+  std::vector<Op*> uniq_ops;
+  for (Op* op : ops)
+    if (std::find(uniq_ops.begin(), uniq_ops.end(), op) == uniq_ops.end()) uniq_ops.push_back(op);
+  for (Op* op : uniq_ops) op->sync_device();
+  std::vector<NSItem> items;
+  std::vector<TargetRange> tgt_sub, work;
+  std::vector<SplitTarget> splits;
+  std::vector<NodeRef> sd_refs;
+  int out_maxlev = 0;
+  size_t total_items = 0;
+  for (auto& p : plans) total_items += p.items.size();
+  const int64_t chunk = std::max<int64_t>(24, ((int64_t)total_items + 1023) / 1024);
+  const bool fused = ns_kernel_fuses_subtraction(k);
+  int32_t npartials = 0, nsub = 0;
+  std::vector<std::vector<int32_t>> sub_of_node(nf);
+  double flops = 0.0;
+  int64_t ntriples = 0, ntargets = 0, in_leaves = 0, out_nodes = 0, out_leaves = 0;
+  for (int i = 0; i < nf; ++i) {
+    Plan& p = plans[i];
+    validate(p, (int64_t)p.op->dR_blocks, (int64_t)p.op->dT_blocks);
+    const int32_t base = (int32_t)items.size();
+    items.insert(items.end(), p.items.begin(), p.items.end());
+    sub_of_node[i].assign((size_t)p.out->nodes(), -1);
+    for (TargetRange r : p.tgt) {
+      r.fn = i;
+      r.beg += base;
+      r.end += base;
+      if (!fused || r.sub < 0) {
+        r.sub = -1;
+      } else {
+        r.sub = nsub++;
+        sub_of_node[i][r.node] = r.sub;
+      }
+      int64_t len = r.end - r.beg;
+      if (len <= chunk) {
+        work.push_back(r);
+        continue;
+      }
+      int32_t parts = (int32_t)((len + chunk - 1) / chunk);
+      for (int32_t q = 0; q < parts; ++q) {
+        int32_t b = r.beg + (int32_t)(q * len / parts), e = r.beg + (int32_t)((q + 1) * len / parts);
+        work.push_back({i, r.node, r.fc, b, e, npartials + q, r.sub});
+      }
+      splits.push_back({i, r.fc, npartials, parts, r.sub});
+      npartials += parts;
+    }
+    if (!fused)
+      for (TargetRange r : p.tgt_sub) {
+        r.fn = i;
+        r.beg += base;
+        r.end += base;
+        r.sub = -1;
+        tgt_sub.push_back(r);
+      }
+    flops += p.flops;
+    ntriples += (int64_t)p.triples.size();
+    ntargets += (int64_t)p.tgt.size();
+    in_leaves += (int64_t)p.f->leaves.size();
+    out_nodes += p.out->nodes();
+    out_leaves += (int64_t)p.out->leaves.size();
+    out_maxlev = std::max(out_maxlev, p.out->nlev);
+  }
+  for (const TargetRange& r : work)
+    if (r.sub >= nsub || r.partial >= npartials)
+      fail(MRA_E_INVALID, "internal plan error: slot index");
+  for (const SplitTarget& sp : splits)
+    if (sp.sub >= nsub || sp.first < 0 || sp.first + sp.count > npartials)
+      fail(MRA_E_INVALID, "internal plan error: split target");
+  // work with the longest lists first
+  auto by_len = [](const TargetRange& a, const TargetRange& b) {
+    return (a.end - a.beg) > (b.end - b.beg);
+  };
+  std::stable_sort(work.begin(), work.end(), by_len);
+  std::stable_sort(tgt_sub.begin(), tgt_sub.end(), by_len);
+  // sum-down entries, level-major over the batch
+  std::vector<int64_t> sd_off(out_maxlev + 1, 0);
+  for (int n = 0; n < out_maxlev; ++n) {
+    for (int i = 0; i < nf; ++i) {
+      const Func& o = *plans[i].out;
+      if (n >= o.nlev) continue;
+      for (int64_t q = o.inter_level_off[n]; q < o.inter_level_off[n + 1]; ++q)
+        sd_refs.push_back({i, o.interior[q], o.first_child[o.interior[q]],
+                           sub_of_node[i][o.interior[q]]});
+    }
+    sd_off[n + 1] = (int64_t)sd_refs.size();
+  }
+  // device pointer tables
+  std::vector<double*> out_tab(nf);
+  std::vector<const double*> r_tab(nf), t_tab(nf), c_tab(nf);
+  for (int i = 0; i < nf; ++i) {
+    Func& o = *plans[i].out;
+    o.coeff.alloc(ctx, (size_t)o.nodes() * K3);
+    o.upload_structure();
+    out_tab[i] = o.coeff.p;
+    r_tab[i] = plans[i].op->dR.p;
+    t_tab[i] = plans[i].op->dT.p;
+    c_tab[i] = plans[i].op->d_c.p;
+  }
+  DevArray<double*> d_out_tab;
+  DevArray<const double*> d_r_tab, d_t_tab, d_c_tab;
+  d_out_tab.upload(ctx, out_tab);
+  d_r_tab.upload(ctx, r_tab);
+  d_t_tab.upload(ctx, t_tab);
+  d_c_tab.upload(ctx, c_tab);
+  DevArray<NSItem> d_items;
+  DevArray<TargetRange> d_work, d_sub;
+  DevArray<SplitTarget> d_splits;
+  DevArray<NodeRef> d_sd;
+  DevArray<double> d_partials;
+  d_items.upload(ctx, items);
+  d_work.upload(ctx, work);
+  d_sub.upload(ctx, tgt_sub);
+  d_splits.upload(ctx, splits);
+  d_sd.upload(ctx, sd_refs);
+  d_partials.alloc(ctx, (size_t)npartials * 9 * K3);   // (2k)^3 + k^3 per slot
+  DevArray<double> d_subbuf;
+  d_subbuf.alloc(ctx, (size_t)nsub * K3);
+  mark("combine + uploads");
+  double t_plan1 = now_ms();
+
+  // ---- 5. device work
+  for (int i = 0; i < nf; ++i) launch_zero(out_tab[i], plans[i].out->coeff.n, ctx->stream);
+  hip_check(hipEventRecord(ctx->ev[2], ctx->stream), "event");
+  launch_apply_ns(k, d_in_tab.p, d_out_tab.p, d_items.p, d_work.p, (int)work.size(), d_r_tab.p,
+                  d_t_tab.p, d_c_tab.p, d_partials.p, d_subbuf.p, ctx->stream);
+  hip_check(hipEventRecord(ctx->ev[3], ctx->stream), "event");
+  launch_reduce_partials(k, d_partials.p, d_out_tab.p, d_subbuf.p, d_splits.p,
+                         (int)splits.size(), ctx->stream);
+  launch_apply_std(k, d_in_tab.p, d_out_tab.p, d_items.p, d_sub.p, (int)tgt_sub.size(),
+                   d_t_tab.p, d_c_tab.p, -1.0, ctx->stream);
+  hip_check(hipEventRecord(ctx->ev[4], ctx->stream), "event");
+  for (int n = 0; n < out_maxlev; ++n) {
+    int64_t b = sd_off[n], e = sd_off[n + 1];
+    if (e > b)
+      launch_sum_down(k, d_out_tab.p, d_sd.p + b, (int)(e - b), d_subbuf.p, h0.p, h1.p,
+                      ctx->stream);
+  }
+  hip_check(hipEventRecord(ctx->ev[5], ctx->stream), "event");
+  ctx->sync();
+  for (int i = 0; i < nf; ++i) plans[i].out->interior_valid = false;
+
+  float ms_f = 0, ms_a = 0, ms_s = 0, ms_main = 0;
+  hip_check(hipEventElapsedTime(&ms_f, ctx->ev[0], ctx->ev[1]), "elapsed");
+  hip_check(hipEventElapsedTime(&ms_a, ctx->ev[2], ctx->ev[4]), "elapsed");
+  hip_check(hipEventElapsedTime(&ms_main, ctx->ev[2], ctx->ev[3]), "elapsed");
+  hip_check(hipEventElapsedTime(&ms_s, ctx->ev[4], ctx->ev[5]), "elapsed");
+  mra_apply_stats& st = ctx->stats;
+  st = mra_apply_stats{};
+  st.triples = ntriples;
+  st.targets = ntargets;
+  st.in_leaves = in_leaves;
+  st.out_nodes = out_nodes;
+  st.out_leaves = out_leaves;
+  st.useful_flops = flops;
+  st.ms_filter = ms_f;
+  st.ms_plan = t_plan1 - t_plan0;
+  st.ms_apply = ms_a;
+  st.ms_main_kernel = ms_main;
+  st.ms_sumdown = ms_s;
+}
+
+// Filter-up of one function (used by mra_inner); returns nothing but marks it valid.
+void filter_up_function(Ctx* ctx, Func& f) {
+  if (f.interior_valid) return;
+  std::vector<double> h0v, h1v;
+  two_scale_filters(f.k, h0v, h1v);
+  DevArray<double> h0, h1;
+  h0.upload(ctx, h0v);
+  h1.upload(ctx, h1v);
+  std::vector<double*> tab{f.coeff.p};
+  DevArray<double*> d_tab;
+  d_tab.upload(ctx, tab);
+  std::vector<NodeRef> refs;
+  std::vector<int64_t> off;
+  off.push_back(0);
+  for (int n = f.nlev - 1; n >= 0; --n) {
+    for (int64_t q = f.inter_level_off[n]; q < f.inter_level_off[n + 1]; ++q)
+      refs.push_back({0, f.interior[q], f.first_child[f.interior[q]], -1});
+    off.push_back((int64_t)refs.size());
+  }
+  DevArray<NodeRef> d_refs;
+  d_refs.upload(ctx, refs);
+  DevArray<double> d_bn2;
+  d_bn2.alloc(ctx, std::max<size_t>(1, refs.size()));
+  for (size_t j = 0; j + 1 < off.size(); ++j)
+    if (off[j + 1] > off[j])
+      launch_filter_up(f.k, d_tab.p, d_refs.p + off[j], (int)(off[j + 1] - off[j]), h0.p, h1.p,
+                       d_bn2.p + off[j], ctx->stream);
+  ctx->sync();
+  f.interior_valid = true;
+}
+
+}  // namespace mra

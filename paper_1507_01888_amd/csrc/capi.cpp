@@ -14,6 +14,9 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
 
 #include "mra_internal.hpp"
 
@@ -181,284 +184,6 @@ static int64_t find_node(const Func& f, int n, uint64_t code) {
   return it - f.code.begin();
 }
 
-struct Filters {
-  DevArray<double> h0, h1;
-};
-
-static void upload_filters(Ctx* ctx, int k, Filters& F) {
-  std::vector<double> h0, h1;
-  two_scale_filters(k, h0, h1);
-  F.h0.upload(ctx, h0);
-  F.h1.upload(ctx, h1);
-}
-
-// filter-up of f on device; returns ||B_P||_F^2 per interior node (in f.interior order)
-static void filter_up(Ctx* ctx, Func& f, const Filters& F, std::vector<double>* bnorm2) {
-  DevArray<double> dn;
-  dn.alloc(ctx, std::max<size_t>(1, f.interior.size()));
-  for (int n = f.nlev - 1; n >= 0; --n) {
-    int64_t b = f.inter_level_off[n], e = f.inter_level_off[n + 1];
-    if (e > b)
-      launch_filter_up(f.k, f.coeff.p, f.coeff.p, f.d_interior.p + b, f.d_inter_child.p + b,
-                       (int)(e - b), F.h0.p, F.h1.p, dn.p + b, ctx->stream);
-  }
-  f.interior_valid = true;
-  if (bnorm2) {
-    bnorm2->resize(f.interior.size());
-    if (!f.interior.empty())
-      hip_check(hipMemcpyAsync(bnorm2->data(), dn.p, f.interior.size() * sizeof(double),
-                               hipMemcpyDeviceToHost, ctx->stream),
-                "hipMemcpyAsync D2H");
-    ctx->sync();
-  } else {
-    ctx->sync();  // keep dn alive until the kernels are done
-  }
-}
-
-// Every index a kernel will dereference is checked on the host before launch.
-static void validate_work(const Op& op, const Func& f, const Func& out,
-                          const std::vector<NSItem>& items, const std::vector<TargetRange>& tgt,
-                          bool nonstandard) {
-  const int64_t nin = f.nodes(), nout = out.nodes();
-  const int64_t nR = (int64_t)op.dR_blocks, nT = (int64_t)op.dT_blocks;
-  auto bad = [](const char* what) { fail(MRA_E_INVALID, std::string("internal plan error: ") + what); };
-  for (const NSItem& it : items) {
-    if (it.src < 0 || it.src >= nin) bad("source node");
-    if (it.mu < 0 || it.mu >= (int)op.c.size()) bad("term index");
-    if (it.tx < 0 || it.tx >= nT || it.ty < 0 || it.ty >= nT || it.tz < 0 || it.tz >= nT)
-      bad("t block");
-    if (nonstandard) {
-      if (it.src_fc < 0 || it.src_fc + 8 > nin) bad("source children");
-      if (it.rx < 0 || it.rx >= nR || it.ry < 0 || it.ry >= nR || it.rz < 0 || it.rz >= nR)
-        bad("R block");
-    }
-  }
-  for (const TargetRange& r : tgt) {
-    if (r.node < 0 || r.node >= nout) bad("target node");
-    if (r.beg < 0 || r.end < r.beg || r.end > (int32_t)items.size()) bad("item range");
-    if (nonstandard && (r.fc < 0 || r.fc + 8 > nout)) bad("target children");
-  }
-}
-
-struct Triple {
-  uint64_t tcode;    // (level << 58) | code of the target
-  int32_t src;       // index into f.interior
-  int16_t mu;
-  int8_t dx, dy, dz;
-};
-
-// ------------------------------------------------------------------------ apply (NS)
-static void apply_nonstandard(Ctx* ctx, Op& op, Func& f, double tau, Func& out) {
-  const int k = f.k;
-  Filters F;
-  upload_filters(ctx, k, F);
-  hip_check(hipEventRecord(ctx->ev[0], ctx->stream), "event");
-  std::vector<double> bn2;
-  filter_up(ctx, f, F, &bn2);
-  hip_check(hipEventRecord(ctx->ev[1], ctx->stream), "event");
-  double t_plan0 = now_ms();
-
-  // ---- screening
-  std::vector<Triple> triples;
-  const double W = ctx->width();
-  const int M = (int)op.c.size();
-  for (int n = 0; n < f.nlev; ++n) {
-    int64_t ib = f.inter_level_off[n], ie = f.inter_level_off[n + 1];
-    if (ie <= ib) continue;
-    int64_t np = ie - ib;
-    std::vector<double> bn(np);
-    std::vector<int64_t> px(np), py(np), pz(np);
-    double maxb = 0.0;
-    for (int64_t i = 0; i < np; ++i) {
-      bn[i] = std::sqrt(bn2[ib + i]);
-      maxb = std::max(maxb, bn[i]);
-      decode(f.code[f.interior[ib + i]], n, px[i], py[i], pz[i]);
-    }
-    std::vector<int64_t> order(np);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return bn[a] > bn[b]; });
-    const int64_t nb = (int64_t)1 << n;
-    const double h = W / std::ldexp(1.0, n);
-    for (int mu = 0; mu < M; ++mu) {
-      double c = std::fabs(op.c[mu]);
-      double beta = op.t[mu] * h * h;
-      double ab = 2.0 * h;
-      double fac = 1.0;
-      if (n > 0) {
-        if (c * maxb * 3.0 * e_bound(k, h, beta) * ab * ab < tau) continue;
-        fac = 3.0;
-      }
-      int D = 0;
-      while (D + 1 <= nb - 1 && c * maxb * fac * ab * ab * decay_bound(h, beta, D + 1) >= tau) ++D;
-      const BlockEntry& be = op.ensure(n, mu, D);
-      std::vector<double> ae(D + 1), aa(D + 1), rr(D + 1);
-      for (int d = 0; d <= D; ++d) {
-        ae[d] = be.a[d] + be.e[d];
-        aa[d] = be.a[d];
-        rr[d] = be.r[d];
-      }
-      for (int dx = -D; dx <= D; ++dx)
-        for (int dy = -D; dy <= D; ++dy)
-          for (int dz = -D; dz <= D; ++dz) {
-            int ax = std::abs(dx), ay = std::abs(dy), az = std::abs(dz);
-            double N = (n > 0) ? ae[ax] * ae[ay] * ae[az] - aa[ax] * aa[ay] * aa[az]
-                               : rr[ax] * rr[ay] * rr[az];
-            if (c * N * maxb < tau) continue;
-            for (int64_t oi = 0; oi < np; ++oi) {
-              int64_t p = order[oi];
-              if (!(c * N * bn[p] >= tau)) break;
-              int64_t tx = px[p] + dx, ty = py[p] + dy, tz = pz[p] + dz;
-              if (tx < 0 || ty < 0 || tz < 0 || tx >= nb || ty >= nb || tz >= nb) continue;
-              triples.push_back({((uint64_t)n << 58) | encode(n, tx, ty, tz), (int32_t)(ib + p),
-                                 (int16_t)mu, (int8_t)dx, (int8_t)dy, (int8_t)dz});
-            }
-          }
-    }
-  }
-  std::sort(triples.begin(), triples.end(), [](const Triple& a, const Triple& b) {
-    if (a.tcode != b.tcode) return a.tcode < b.tcode;
-    if (a.src != b.src) return a.src < b.src;
-    return a.mu < b.mu;
-  });
-
-  // ---- output tree
-  int maxlev = 0;
-  for (auto& t : triples) maxlev = std::max(maxlev, (int)(t.tcode >> 58) + 1);
-  std::vector<std::vector<uint64_t>> sets(std::max(maxlev + 1, 1));
-  for (size_t i = 0; i < triples.size(); ++i) {
-    if (i > 0 && triples[i].tcode == triples[i - 1].tcode) continue;
-    int n = (int)(triples[i].tcode >> 58);
-    uint64_t code = triples[i].tcode & ((1ULL << 58) - 1);
-    sets[n].push_back(code);
-    for (int c = 0; c < 8; ++c) sets[n + 1].push_back((code << 3) | c);
-  }
-  sets[0].push_back(0);
-  for (int n = (int)sets.size() - 1; n >= 1; --n) {
-    auto& s = sets[n];
-    std::sort(s.begin(), s.end());
-    s.erase(std::unique(s.begin(), s.end()), s.end());
-    std::vector<uint64_t> full;
-    full.reserve(s.size() * 2);
-    uint64_t lastp = ~0ULL;
-    for (uint64_t code : s) {
-      uint64_t p = code >> 3;
-      if (p == lastp) continue;
-      lastp = p;
-      for (int c = 0; c < 8; ++c) full.push_back((p << 3) | c);
-      sets[n - 1].push_back(p);
-    }
-    s.swap(full);
-  }
-  std::sort(sets[0].begin(), sets[0].end());
-  sets[0].erase(std::unique(sets[0].begin(), sets[0].end()), sets[0].end());
-  out.ctx = ctx;
-  out.k = k;
-  build_tree(out, sets);
-
-  // ---- work lists
-  std::vector<NSItem> items;
-  items.reserve(triples.size());
-  std::vector<TargetRange> tgt, tgt_sub;
-  double flops = 0.0;
-  const double f_ns = 6.0 * std::pow(2.0 * k, 4), f_sub = 6.0 * std::pow((double)k, 4);
-  for (size_t i = 0; i < triples.size();) {
-    size_t j = i;
-    while (j < triples.size() && triples[j].tcode == triples[i].tcode) ++j;
-    int n = (int)(triples[i].tcode >> 58);
-    uint64_t code = triples[i].tcode & ((1ULL << 58) - 1);
-    int64_t node = find_node(out, n, code);
-    TargetRange r{(int32_t)node, out.first_child[node], (int32_t)items.size(), 0};
-    for (size_t q = i; q < j; ++q) {
-      const Triple& t = triples[q];
-      const BlockEntry& be = op.entries.at({n, (int)t.mu});
-      NSItem it;
-      it.src = f.interior[t.src];
-      it.src_fc = f.first_child[it.src];
-      it.mu = t.mu;
-      it.rx = (int32_t)(be.r_base + t.dx + be.D);
-      it.ry = (int32_t)(be.r_base + t.dy + be.D);
-      it.rz = (int32_t)(be.r_base + t.dz + be.D);
-      it.tx = (int32_t)(be.t_base + t.dx + be.D);
-      it.ty = (int32_t)(be.t_base + t.dy + be.D);
-      it.tz = (int32_t)(be.t_base + t.dz + be.D);
-      items.push_back(it);
-      flops += f_ns + (n > 0 ? f_sub : 0.0);
-    }
-    r.end = (int32_t)items.size();
-    tgt.push_back(r);
-    if (n > 0) tgt_sub.push_back(r);
-    i = j;
-  }
-  // longest lists first
-  auto by_len = [](const TargetRange& a, const TargetRange& b) {
-    return (a.end - a.beg) > (b.end - b.beg);
-  };
-  std::stable_sort(tgt.begin(), tgt.end(), by_len);
-  std::stable_sort(tgt_sub.begin(), tgt_sub.end(), by_len);
-
-  op.sync_device();
-  validate_work(op, f, out, items, tgt, true);
-  DevArray<NSItem> d_items;
-  DevArray<TargetRange> d_tgt, d_tgt_sub;
-  d_items.upload(ctx, items);
-  d_tgt.upload(ctx, tgt);
-  d_tgt_sub.upload(ctx, tgt_sub);
-  out.coeff.alloc(ctx, (size_t)out.nodes() * k * k * k);
-  out.upload_structure();
-  // sum-down lists per level
-  std::vector<int32_t> sd_nodes, sd_child;
-  std::vector<int64_t> sd_off(out.nlev + 1, 0);
-  for (int n = 0; n < out.nlev; ++n) {
-    for (int64_t i = out.inter_level_off[n]; i < out.inter_level_off[n + 1]; ++i) {
-      sd_nodes.push_back(out.interior[i]);
-      sd_child.push_back(out.first_child[out.interior[i]]);
-    }
-    sd_off[n + 1] = (int64_t)sd_nodes.size();
-  }
-  DevArray<int32_t> d_sdn, d_sdc;
-  d_sdn.upload(ctx, sd_nodes);
-  d_sdc.upload(ctx, sd_child);
-  double t_plan1 = now_ms();
-
-  // ---- device: transform-and-accumulate, then sum-down
-  launch_zero(out.coeff.p, out.coeff.n, ctx->stream);
-  hip_check(hipEventRecord(ctx->ev[2], ctx->stream), "event");
-  launch_apply_ns(k, f.coeff.p, out.coeff.p, d_items.p, d_tgt.p, (int)tgt.size(), op.dR.p,
-                  op.d_c.p, ctx->stream);
-  hip_check(hipEventRecord(ctx->ev[3], ctx->stream), "event");
-  launch_apply_std(k, f.coeff.p, out.coeff.p, d_items.p, d_tgt_sub.p, (int)tgt_sub.size(),
-                   op.dT.p, op.d_c.p, -1.0, ctx->stream);
-  hip_check(hipEventRecord(ctx->ev[4], ctx->stream), "event");
-  for (int n = 0; n < out.nlev; ++n) {
-    int64_t b = sd_off[n], e = sd_off[n + 1];
-    if (e > b)
-      launch_sum_down(k, out.coeff.p, d_sdn.p + b, d_sdc.p + b, (int)(e - b), F.h0.p, F.h1.p,
-                      ctx->stream);
-  }
-  hip_check(hipEventRecord(ctx->ev[5], ctx->stream), "event");
-  ctx->sync();
-  out.interior_valid = false;
-
-  float ms_f = 0, ms_a = 0, ms_s = 0, ms_main = 0;
-  hip_check(hipEventElapsedTime(&ms_f, ctx->ev[0], ctx->ev[1]), "elapsed");
-  hip_check(hipEventElapsedTime(&ms_a, ctx->ev[2], ctx->ev[4]), "elapsed");
-  hip_check(hipEventElapsedTime(&ms_main, ctx->ev[2], ctx->ev[3]), "elapsed");
-  hip_check(hipEventElapsedTime(&ms_s, ctx->ev[4], ctx->ev[5]), "elapsed");
-  mra_apply_stats& st = ctx->stats;
-  st = mra_apply_stats{};
-  st.triples = (int64_t)triples.size();
-  st.targets = (int64_t)tgt.size();
-  st.in_leaves = (int64_t)f.leaves.size();
-  st.out_nodes = out.nodes();
-  st.out_leaves = (int64_t)out.leaves.size();
-  st.useful_flops = flops;
-  st.ms_filter = ms_f;
-  st.ms_plan = t_plan1 - t_plan0;
-  st.ms_apply = ms_a;
-  st.ms_main_kernel = ms_main;
-  st.ms_sumdown = ms_s;
-}
-
 // ------------------------------------------------------------------------ apply (std)
 static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
   const int k = f.k;
@@ -485,7 +210,7 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
   for (int32_t T : f.leaves) {
     int64_t x, y, z;
     decode(f.code[T], L, x, y, z);
-    TargetRange r{T, -1, (int32_t)items.size(), 0};
+    TargetRange r{0, T, -1, (int32_t)items.size(), 0, -1, -1};
     for (int dx = -D; dx <= D; ++dx)
       for (int dy = -D; dy <= D; ++dy)
         for (int dz = -D; dz <= D; ++dz) {
@@ -509,18 +234,30 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
     tgt.push_back(r);
   }
   op.sync_device();
-  validate_work(op, f, out, items, tgt, false);
+  for (const NSItem& it : items)
+    if (it.src < 0 || it.src >= f.nodes() || it.tx < 0 || it.ty < 0 || it.tz < 0 ||
+        it.tx >= (int64_t)op.dT_blocks || it.ty >= (int64_t)op.dT_blocks ||
+        it.tz >= (int64_t)op.dT_blocks || it.mu < 0 || it.mu >= M)
+      fail(MRA_E_INVALID, "internal plan error: standard-form item");
   DevArray<NSItem> d_items;
   DevArray<TargetRange> d_tgt;
   d_items.upload(ctx, items);
   d_tgt.upload(ctx, tgt);
   out.coeff.alloc(ctx, (size_t)out.nodes() * k * k * k);
   out.upload_structure();
+  std::vector<const double*> in_tab{f.coeff.p}, t_tab{op.dT.p}, c_tab{op.d_c.p};
+  std::vector<double*> out_tab{out.coeff.p};
+  DevArray<const double*> d_in, d_t, d_c;
+  DevArray<double*> d_out;
+  d_in.upload(ctx, in_tab);
+  d_t.upload(ctx, t_tab);
+  d_c.upload(ctx, c_tab);
+  d_out.upload(ctx, out_tab);
   double t_plan1 = now_ms();
   launch_zero(out.coeff.p, out.coeff.n, ctx->stream);
   hip_check(hipEventRecord(ctx->ev[2], ctx->stream), "event");
-  launch_apply_std(k, f.coeff.p, out.coeff.p, d_items.p, d_tgt.p, (int)tgt.size(), op.dT.p,
-                   op.d_c.p, 1.0, ctx->stream);
+  launch_apply_std(k, d_in.p, d_out.p, d_items.p, d_tgt.p, (int)tgt.size(), d_t.p, d_c.p, 1.0,
+                   ctx->stream);
   hip_check(hipEventRecord(ctx->ev[3], ctx->stream), "event");
   ctx->sync();
   float ms_a = 0;
@@ -781,13 +518,49 @@ mra_status mra_apply(mra_ctx* ctx, const mra_op* oph, const mra_func* fh,
     if (p->form == MRA_FORM_STANDARD) {
       apply_standard(c, op, f, p->disp_radius, h->f);
     } else if (p->form == MRA_FORM_NONSTANDARD) {
-      if (f.k > 10) fail(MRA_E_UNSUPPORTED, "non-standard apply is built for k <= 10");
+      if (f.k > 10 && f.k != 12)
+        fail(MRA_E_UNSUPPORTED, "non-standard apply is built for k <= 10 and k = 12");
       if (!(p->tau_drop >= 0.0)) fail(MRA_E_INVALID, "tau_drop must be >= 0");
-      apply_nonstandard(c, op, f, p->tau_drop, h->f);
+      apply_nonstandard_batch(c, {&op}, {&f}, p->tau_drop, {&h->f});
     } else {
       fail(MRA_E_INVALID, "unknown form");
     }
     *out = h.release();
+  });
+}
+
+mra_status mra_apply_batch(mra_ctx* ctx, int n, const mra_op* const* ophs,
+                           const mra_func* const* fhs, const mra_apply_params* p,
+                           mra_func** outs) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (n < 1 || !ophs || !fhs || !p || !outs) fail(MRA_E_INVALID, "mra_apply_batch: bad arguments");
+    if (p->form != MRA_FORM_NONSTANDARD) fail(MRA_E_UNSUPPORTED, "batches use the non-standard form");
+    if (!(p->tau_drop >= 0.0)) fail(MRA_E_INVALID, "tau_drop must be >= 0");
+    std::vector<Op*> ops(n);
+    std::vector<Func*> funcs(n);
+    for (int i = 0; i < n; ++i) {
+      if (!ophs[i] || !fhs[i]) fail(MRA_E_INVALID, "mra_apply_batch: null handle");
+      ops[i] = &const_cast<mra_op*>(ophs[i])->o;
+      funcs[i] = &const_cast<mra_func*>(fhs[i])->f;
+      if (ops[i]->ctx != c || funcs[i]->ctx != c)
+        fail(MRA_E_MISMATCH, "handles belong to another context");
+      if (ops[i]->k != funcs[i]->k || funcs[i]->k != funcs[0]->k)
+        fail(MRA_E_MISMATCH, "all operators and functions of a batch need the same k");
+      for (int j = 0; j < i; ++j)
+        if (funcs[j] == funcs[i]) fail(MRA_E_INVALID, "a function appears twice in the batch");
+    }
+    if (funcs[0]->k > 10 && funcs[0]->k != 12)
+      fail(MRA_E_UNSUPPORTED, "non-standard apply is built for k <= 10 and k = 12");
+    std::vector<std::unique_ptr<mra_func>> hs(n);
+    std::vector<Func*> outf(n);
+    for (int i = 0; i < n; ++i) {
+      hs[i].reset(new mra_func());
+      outf[i] = &hs[i]->f;
+    }
+    apply_nonstandard_batch(c, ops, funcs, p->tau_drop, outf);
+    for (int i = 0; i < n; ++i) outs[i] = hs[i].release();
   });
 }
 
@@ -826,10 +599,8 @@ mra_status mra_inner(mra_ctx* ctx, const mra_func* fh, const mra_func* gh, doubl
     Func& g = const_cast<mra_func*>(gh)->f;
     if (f.ctx != c || g.ctx != c) fail(MRA_E_MISMATCH, "handles belong to another context");
     if (f.k != g.k) fail(MRA_E_MISMATCH, "functions have different k");
-    Filters F;
-    upload_filters(c, f.k, F);
-    if (!f.interior_valid) filter_up(c, f, F, nullptr);
-    if (!g.interior_valid) filter_up(c, g, F, nullptr);
+    filter_up_function(c, f);
+    filter_up_function(c, g);
     // pair the leaves of the intersection of the two trees: boxes present in both where at
     // least one of the two is a leaf (the other side holds its filtered coefficients).
     std::vector<int32_t> la, lb;

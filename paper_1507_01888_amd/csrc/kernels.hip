@@ -34,95 +34,101 @@ __global__ void zero_kernel(double* __restrict__ p, size_t n) {
 }
 
 // --------------------------------------------------------------------------- filter-up
+// The children block is read straight from the 8 child slabs; the z-contraction happens
+// on the fly (each thread owns (X, Y) rows), so LDS only holds the two partially filtered
+// tensors ((2k)^2 k and (2k) k^2 doubles).
 template <int K>
-__global__ __launch_bounds__(round64(4 * K * K)) void filter_up_kernel(
-    const double* __restrict__ in, double* __restrict__ out, const int32_t* __restrict__ nodes,
-    const int32_t* __restrict__ fchild, const double* __restrict__ h0,
-    const double* __restrict__ h1, double* __restrict__ bnorm2) {
-  constexpr int N = 2 * K, K3 = K * K * K, ZP = N + 1;
-  __shared__ double B[N * N * ZP];
-  __shared__ double T[K * N * ZP];
+__global__ __launch_bounds__(256) void filter_up_kernel(
+    double* const* __restrict__ tab, const NodeRef* __restrict__ refs,
+    const double* __restrict__ h0, const double* __restrict__ h1, double* __restrict__ bnorm2) {
+  constexpr int N = 2 * K, K3 = K * K * K, KP1 = K + 1;
+  __shared__ double T1[N * N * KP1];   // [X][Y][m]
+  __shared__ double T2[N * K * KP1];   // [X][j][m]
   __shared__ double H[K * N];
-  __shared__ double red[round64(4 * K * K)];
+  __shared__ double red[256];
   const int tid = threadIdx.x;
-  const int node = nodes[blockIdx.x];
-  const int fc = fchild[blockIdx.x];
-  for (int e = tid; e < K * N; e += blockDim.x) {
+  const NodeRef ref = refs[blockIdx.x];
+  const int node = ref.node, fc = ref.fchild;
+  double* __restrict__ coeff = tab[ref.fn];
+  for (int e = tid; e < K * N; e += 256) {
     int i = e / N, X = e % N;
     H[e] = X < K ? h0[i * K + X] : h1[i * K + X - K];
   }
+  __syncthreads();
   double sq = 0.0;
-  for (int e = tid; e < 8 * K3; e += blockDim.x) {
-    int c = e / K3, r = e - c * K3;
-    int i = r / (K * K), j = (r / K) % K, m = r % K;
-    double v = in[(size_t)(fc + c) * K3 + r];
-    sq += v * v;
-    B[((((c >> 2) & 1) * K + i) * N + ((c >> 1) & 1) * K + j) * ZP + (c & 1) * K + m] = v;
+  // phase z: T1[X][Y][m] = sum_Z H[m][Z] B[X][Y][Z]; row (X, Y) = two contiguous child rows
+  for (int e = tid; e < N * N; e += 256) {
+    const int X = e / N, Y = e % N;
+    const int bx = X / K, i = X % K, by = Y / K, j = Y % K;
+    const double* r0 = coeff + (size_t)(fc + ((bx << 2) | (by << 1))) * K3 + (i * K + j) * K;
+    const double* r1 = r0 + K3;
+    double t[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) t[m] = 0.0;
+#pragma unroll
+    for (int z = 0; z < K; ++z) {
+      const double v0 = r0[z], v1 = r1[z];
+      sq += v0 * v0 + v1 * v1;
+#pragma unroll
+      for (int m = 0; m < K; ++m) t[m] += H[m * N + z] * v0 + H[m * N + K + z] * v1;
+    }
+#pragma unroll
+    for (int m = 0; m < K; ++m) T1[(X * N + Y) * KP1 + m] = t[m];
   }
   red[tid] = sq;
   __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {  // fixed-order tree; blockDim need not be a power of 2
-    if (tid < s && tid + s < (int)blockDim.x) red[tid] += red[tid + s];
+  for (int st = 128; st > 0; st >>= 1) {   // fixed-order tree
+    if (tid < st) red[tid] += red[tid + st];
     __syncthreads();
   }
   if (tid == 0) bnorm2[blockIdx.x] = red[0];
-  // phase x: thread (Y, Z): T[i][Y][Z] = sum_X H[i][X] B[X][Y][Z]
-  if (tid < N * N) {
-    int Y = tid / N, Z = tid % N;
-    double t[K];
-#pragma unroll
-    for (int i = 0; i < K; ++i) t[i] = 0.0;
-    for (int X = 0; X < N; ++X) {
-      double v = B[(X * N + Y) * ZP + Z];
-#pragma unroll
-      for (int i = 0; i < K; ++i) t[i] += H[i * N + X] * v;
-    }
-#pragma unroll
-    for (int i = 0; i < K; ++i) T[(i * N + Y) * ZP + Z] = t[i];
-  }
-  __syncthreads();
-  // phase y: thread (i, Z): B[i][j][Z] (reuse B as K x K x N) = sum_Y H[j][Y] T[i][Y][Z]
-  if (tid < K * N) {
-    int i = tid / N, Z = tid % N;
+  // phase y: T2[X][j][m] = sum_Y H[j][Y] T1[X][Y][m], thread (X, m)
+  for (int e = tid; e < N * K; e += 256) {
+    const int X = e / K, m = e % K;
     double t[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) t[j] = 0.0;
     for (int Y = 0; Y < N; ++Y) {
-      double v = T[(i * N + Y) * ZP + Z];
+      const double v = T1[(X * N + Y) * KP1 + m];
 #pragma unroll
       for (int j = 0; j < K; ++j) t[j] += H[j * N + Y] * v;
     }
 #pragma unroll
-    for (int j = 0; j < K; ++j) B[(i * K + j) * ZP + Z] = t[j];
+    for (int j = 0; j < K; ++j) T2[(X * K + j) * KP1 + m] = t[j];
   }
   __syncthreads();
-  // phase z: thread (i, j): s[i][j][m] = sum_Z H[m][Z] B[i][j][Z]
-  if (tid < K * K) {
-    int i = tid / K, j = tid % K;
+  // phase x: s[i][j][m] = sum_X H[i][X] T2[X][j][m], thread (j, m)
+  for (int e = tid; e < K * K; e += 256) {
+    const int j = e / K, m = e % K;
     double t[K];
 #pragma unroll
-    for (int m = 0; m < K; ++m) t[m] = 0.0;
-    for (int Z = 0; Z < N; ++Z) {
-      double v = B[(i * K + j) * ZP + Z];
+    for (int i = 0; i < K; ++i) t[i] = 0.0;
+    for (int X = 0; X < N; ++X) {
+      const double v = T2[(X * K + j) * KP1 + m];
 #pragma unroll
-      for (int m = 0; m < K; ++m) t[m] += H[m * N + Z] * v;
+      for (int i = 0; i < K; ++i) t[i] += H[i * N + X] * v;
     }
 #pragma unroll
-    for (int m = 0; m < K; ++m) out[(size_t)node * K3 + (i * K + j) * K + m] = t[m];
+    for (int i = 0; i < K; ++i) coeff[(size_t)node * K3 + (i * K + j) * K + m] = t[i];
   }
 }
 
 // --------------------------------------------------------------------------- apply (NS)
 template <int K>
 __global__ __launch_bounds__(round64(4 * K * K)) void apply_ns_kernel(
-    const double* __restrict__ in, double* __restrict__ out, const NSItem* __restrict__ items,
-    const TargetRange* __restrict__ targets, const double* __restrict__ dR,
-    const double* __restrict__ dc) {
+    const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
+    const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
+    const double* const* __restrict__ r_tab, const double* const* __restrict__ c_tab,
+    double* __restrict__ partials) {
   constexpr int N = 2 * K, N2 = N * N, K3 = K * K * K, ZP = N + 1;
   __shared__ double S[N * N * ZP];
   __shared__ double W[N * N * ZP];
   const int tid = threadIdx.x;
   const TargetRange tr = targets[blockIdx.x];
+  const double* __restrict__ in = in_tab[tr.fn];
+  double* __restrict__ out = out_tab[tr.fn];
+  const double* __restrict__ dR = r_tab[tr.fn];
+  const double* __restrict__ dc = c_tab[tr.fn];
   double acc[N];
 #pragma unroll
   for (int c = 0; c < N; ++c) acc[c] = 0.0;
@@ -190,11 +196,41 @@ __global__ __launch_bounds__(round64(4 * K * K)) void apply_ns_kernel(
   if (tid < N2) {
     int a = tid / N, b = tid % N;
     int ca = a / K, i = a % K, cb = b / K, j = b % K;
+    if (tr.partial >= 0) {
+      double* dst = partials + (size_t)tr.partial * (N * N2 + K3);
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-      int child = (ca << 2) | (cb << 1) | (c / K);
-      size_t idx = (size_t)(tr.fc + child) * K3 + (i * K + j) * K + (c % K);
-      out[idx] += acc[c];
+      for (int c = 0; c < N; ++c) dst[(a * N + b) * N + c] = acc[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        int child = (ca << 2) | (cb << 1) | (c / K);
+        size_t idx = (size_t)(tr.fc + child) * K3 + (i * K + j) * K + (c % K);
+        out[idx] += acc[c];
+      }
+    }
+  }
+}
+
+// Sum the partial children blocks of split targets in slot order and add them to the output.
+template <int K>
+__global__ __launch_bounds__(256) void reduce_partials_kernel(
+    const double* __restrict__ partials, double* const* __restrict__ out_tab,
+    double* __restrict__ subbuf, const SplitTarget* __restrict__ splits) {
+  constexpr int N = 2 * K, N3 = N * N * N, K3 = K * K * K, SLOT = N3 + K3;
+  const SplitTarget sp = splits[blockIdx.x];
+  double* __restrict__ out = out_tab[sp.fn];
+  for (int e = threadIdx.x; e < N3; e += 256) {
+    double s = 0.0;
+    for (int q = 0; q < sp.count; ++q) s += partials[(size_t)(sp.first + q) * SLOT + e];
+    int a = e / (N * N), b = (e / N) % N, c = e % N;
+    int child = ((a / K) << 2) | ((b / K) << 1) | (c / K);
+    out[(size_t)(sp.fc + child) * K3 + ((a % K) * K + (b % K)) * K + (c % K)] += s;
+  }
+  if (sp.sub >= 0) {
+    for (int e = threadIdx.x; e < K3; e += 256) {
+      double s = 0.0;
+      for (int q = 0; q < sp.count; ++q) s += partials[(size_t)(sp.first + q) * SLOT + N3 + e];
+      subbuf[(size_t)sp.sub * K3 + e] = s;
     }
   }
 }
@@ -212,9 +248,11 @@ __global__ __launch_bounds__(round64(4 * K * K)) void apply_ns_kernel(
 // triples of the target.
 template <int K>
 __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
-    const double* __restrict__ in, double* __restrict__ out, const NSItem* __restrict__ items,
-    const TargetRange* __restrict__ targets, const double* __restrict__ dR,
-    const double* __restrict__ dc) {
+    const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
+    const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
+    const double* const* __restrict__ r_tab, const double* const* __restrict__ t_tab,
+    const double* const* __restrict__ c_tab, double* __restrict__ partials,
+    double* __restrict__ subbuf) {
   constexpr int N = 2 * K, Q = N / 4, N2 = N * N, K3 = K * K * K, ZP = N + 1;
   static_assert(N % 4 == 0, "k must be even");
   static_assert(Q >= 4 && Q <= 5, "register budget sized for 2k = 16 or 20");
@@ -222,18 +260,34 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
   constexpr int EXTRA_PER_WAVE = (EXTRA + 3) / 4;
   constexpr int P3 = Q * Q;                          // step-3 (a-quad, b-quad) pairs
   constexpr int P3_PER_WAVE = (P3 + 3) / 4;
+  // level-n subtraction -c (t x t x t) s_P on k^3 padded to KP = 4 Q2
+  constexpr int Q2 = (K + 3) / 4, KP = 4 * Q2, ZP2 = KP + 1;
+  constexpr int S3 = Q2 * Q2;
+  constexpr int S3_PER_WAVE = (S3 + 3) / 4;
   __shared__ double Xs[N * N * ZP];
   __shared__ double Zs[N * N * ZP];
+  __shared__ double Z2[KP * KP * ZP2];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
   const TargetRange tr = targets[blockIdx.x];
+  const double* __restrict__ in = in_tab[tr.fn];
+  double* __restrict__ out = out_tab[tr.fn];
+  const double* __restrict__ dR = r_tab[tr.fn];
+  const double* __restrict__ dT = t_tab[tr.fn];
+  const double* __restrict__ dc = c_tab[tr.fn];
 
   double acc[P3_PER_WAVE][Q];
 #pragma unroll
   for (int p = 0; p < P3_PER_WAVE; ++p)
 #pragma unroll
     for (int c = 0; c < Q; ++c) acc[p][c] = 0.0;
+  double sacc[S3_PER_WAVE][Q2];
+#pragma unroll
+  for (int p = 0; p < S3_PER_WAVE; ++p)
+#pragma unroll
+    for (int c = 0; c < Q2; ++c) sacc[p][c] = 0.0;
+  const bool with_sub = tr.sub >= 0;
 
   int loaded = -1;
   for (int it = tr.beg; it < tr.end; ++it) {
@@ -327,7 +381,80 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
           Zs[((4 * at + lk) * N + 4 * bt + li) * ZP + 4 * zq + lb] = d2[bt];
       }
     }
+    // ---- subtraction, steps 1 and 2: (t_x, t_y) on s_P, one z-quad per wave
+    if (with_sub && wave < Q2) {
+      const int zq = wave;
+      const double* __restrict__ sp = in + (size_t)item.src * K3;
+      const double* TX = dT + (size_t)item.tx * K * K;   // transposed: TX[x*K + a] = t[a][x]
+      const double* TY = dT + (size_t)item.ty * K * K;
+      double tx[Q2][Q2], ty[Q2][Q2];
+#pragma unroll
+      for (int ks = 0; ks < Q2; ++ks)
+#pragma unroll
+        for (int t = 0; t < Q2; ++t) {
+          const int r = 4 * ks + lk, cc = 4 * t + li;
+          const bool ok = r < K && cc < K;
+          tx[ks][t] = ok ? TX[r * K + cc] : 0.0;
+          ty[ks][t] = ok ? TY[r * K + cc] : 0.0;
+        }
+      double d1[Q2][Q2];
+#pragma unroll
+      for (int at = 0; at < Q2; ++at)
+#pragma unroll
+        for (int yt = 0; yt < Q2; ++yt) d1[at][yt] = 0.0;
+      const int z = 4 * zq + lb;
+#pragma unroll
+      for (int xs = 0; xs < Q2; ++xs)
+#pragma unroll
+        for (int yt = 0; yt < Q2; ++yt) {
+          const int x = 4 * xs + lk, y = 4 * yt + li;
+          double a = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
+#pragma unroll
+          for (int at = 0; at < Q2; ++at)
+            d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, tx[xs][at], d1[at][yt], 0, 0, 0);
+        }
+#pragma unroll
+      for (int at = 0; at < Q2; ++at) {
+        double d2[Q2];
+#pragma unroll
+        for (int bt = 0; bt < Q2; ++bt) d2[bt] = 0.0;
+#pragma unroll
+        for (int ys = 0; ys < Q2; ++ys)
+#pragma unroll
+          for (int bt = 0; bt < Q2; ++bt)
+            d2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], ty[ys][bt], d2[bt], 0, 0, 0);
+#pragma unroll
+        for (int bt = 0; bt < Q2; ++bt)
+          Z2[((4 * at + lk) * KP + 4 * bt + li) * ZP2 + 4 * zq + lb] = d2[bt];
+      }
+    }
     __syncthreads();
+    // ---- subtraction, step 3: z-contraction with -c t_z
+    if (with_sub) {
+      const double* TZ = dT + (size_t)item.tz * K * K;
+      double tz[Q2][Q2];
+#pragma unroll
+      for (int ks = 0; ks < Q2; ++ks)
+#pragma unroll
+        for (int t = 0; t < Q2; ++t) {
+          const int r = 4 * ks + lk, cc = 4 * t + li;
+          tz[ks][t] = (r < K && cc < K) ? -cmu * TZ[r * K + cc] : 0.0;
+        }
+#pragma unroll
+      for (int e = 0; e < S3_PER_WAVE; ++e) {
+        const int p = (3 - wave) + 4 * e;
+        if (p < S3) {
+          const int at3 = p / Q2, bt3 = p % Q2;
+#pragma unroll
+          for (int zs = 0; zs < Q2; ++zs) {
+            double a = Z2[((4 * at3 + lb) * KP + 4 * bt3 + li) * ZP2 + 4 * zs + lk];
+#pragma unroll
+            for (int ct = 0; ct < Q2; ++ct)
+              sacc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, tz[zs][ct], sacc[e][ct], 0, 0, 0);
+          }
+        }
+      }
+    }
     // ---- step 3: z-contraction into the register accumulators
     double rz[Q][Q];
 #pragma unroll
@@ -357,11 +484,265 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
     if (p < P3) {
       const int at3 = p / Q, bt3 = p % Q;
       const int a = 4 * at3 + lb, b = 4 * bt3 + lk;
+      if (tr.partial >= 0) {
+        double* dst = partials + (size_t)tr.partial * (N * N2 + K3);
 #pragma unroll
-      for (int ct = 0; ct < Q; ++ct) {
-        const int c = 4 * ct + li;
+        for (int ct = 0; ct < Q; ++ct) dst[(a * N + b) * N + 4 * ct + li] = acc[e][ct];
+      } else {
+#pragma unroll
+        for (int ct = 0; ct < Q; ++ct) {
+          const int c = 4 * ct + li;
+          const int child = ((a / K) << 2) | ((b / K) << 1) | (c / K);
+          out[(size_t)(tr.fc + child) * K3 + ((a % K) * K + (b % K)) * K + (c % K)] += acc[e][ct];
+        }
+      }
+    }
+  }
+  if (with_sub) {
+#pragma unroll
+    for (int e = 0; e < S3_PER_WAVE; ++e) {
+      const int p = (3 - wave) + 4 * e;
+      if (p < S3) {
+        const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + lk;
+#pragma unroll
+        for (int ct = 0; ct < Q2; ++ct) {
+          const int c = 4 * ct + li;
+          if (a < K && b < K && c < K) {
+            if (tr.partial >= 0)
+              partials[(size_t)tr.partial * (N * N2 + K3) + N * N2 + (a * K + b) * K + c] = sacc[e][ct];
+            else
+              subbuf[(size_t)tr.sub * K3 + (a * K + b) * K + c] = sacc[e][ct];
+          }
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------- apply (NS, MFMA, large blocks)
+// FP64 matrix-core version for 2k = 4Q with Q = 6 (k = 12).  One LDS buffer holds the source
+// block for steps 1-2 and is then overwritten by the y-contracted tensor for the
+// z-exchange, so the source block is re-staged for every triple.  Steps 1+2 units are the
+// Q^2 (z-quad, a-quad) pairs, step 3 units the Q^2 (a-quad, b-quad) pairs, both split
+// evenly over the 4 waves; the y-contracted pairs wait in registers until every wave has
+// finished reading the source block.  The level-n subtraction is fused as in the k <= 10
+// kernel.
+template <int K>
+__global__ __launch_bounds__(256) void apply_ns_mfma_big_kernel(
+    const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
+    const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
+    const double* const* __restrict__ r_tab, const double* const* __restrict__ t_tab,
+    const double* const* __restrict__ c_tab, double* __restrict__ partials,
+    double* __restrict__ subbuf) {
+  constexpr int N = 2 * K, Q = N / 4, N2 = N * N, K3 = K * K * K, ZP = N + 1;
+  static_assert(N % 4 == 0 && (Q * Q) % 4 == 0, "pairs must split evenly over 4 waves");
+  constexpr int PW = Q * Q / 4;                      // pairs per wave (steps 1-2 and step 3)
+  constexpr int Q2 = (K + 3) / 4, KP = 4 * Q2, ZP2 = KP + 1;
+  constexpr int S3 = Q2 * Q2;
+  constexpr int S3_PER_WAVE = (S3 + 3) / 4;
+  __shared__ double Bs[N * N * ZP];
+  __shared__ double Z2[KP * KP * ZP2];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
+  const TargetRange tr = targets[blockIdx.x];
+  const double* __restrict__ in = in_tab[tr.fn];
+  double* __restrict__ out = out_tab[tr.fn];
+  const double* __restrict__ dR = r_tab[tr.fn];
+  const double* __restrict__ dT = t_tab[tr.fn];
+  const double* __restrict__ dc = c_tab[tr.fn];
+  const bool with_sub = tr.sub >= 0;
+
+  double acc[PW][Q];
+#pragma unroll
+  for (int p = 0; p < PW; ++p)
+#pragma unroll
+    for (int c = 0; c < Q; ++c) acc[p][c] = 0.0;
+  double sacc[S3_PER_WAVE][Q2];
+#pragma unroll
+  for (int p = 0; p < S3_PER_WAVE; ++p)
+#pragma unroll
+    for (int c = 0; c < Q2; ++c) sacc[p][c] = 0.0;
+
+  for (int it = tr.beg; it < tr.end; ++it) {
+    const NSItem item = items[it];
+    __syncthreads();   // previous triple's step 3 is done with Bs
+    for (int e = tid; e < 8 * K3; e += 256) {
+      int c = e / K3, r = e - c * K3;
+      int i = r / (K * K), j = (r / K) % K, m = r % K;
+      Bs[((((c >> 2) & 1) * K + i) * N + ((c >> 1) & 1) * K + j) * ZP + (c & 1) * K + m] =
+          in[(size_t)(item.src_fc + c) * K3 + r];
+    }
+    const double* RX = dR + (size_t)item.rx * N2;
+    const double* RY = dR + (size_t)item.ry * N2;
+    const double* RZ = dR + (size_t)item.rz * N2;
+    const double cmu = dc[item.mu];
+    double ry[Q][Q];
+#pragma unroll
+    for (int ks = 0; ks < Q; ++ks)
+#pragma unroll
+      for (int t = 0; t < Q; ++t) ry[ks][t] = RY[(4 * ks + lk) * N + 4 * t + li];
+    __syncthreads();
+    // ---- steps 1 and 2 for this wave's (z-quad, a-quad) pairs; results stay in registers
+    double zr[PW][Q];
+#pragma unroll
+    for (int e = 0; e < PW; ++e) {
+      const int p = wave * PW + e;
+      const int zq = p / Q, at = p % Q;
+      double rx[Q];
+#pragma unroll
+      for (int xs = 0; xs < Q; ++xs) rx[xs] = RX[(4 * xs + lk) * N + 4 * at + li];
+      double d1[Q];
+#pragma unroll
+      for (int yt = 0; yt < Q; ++yt) d1[yt] = 0.0;
+#pragma unroll
+      for (int xs = 0; xs < Q; ++xs)
+#pragma unroll
+        for (int yt = 0; yt < Q; ++yt) {
+          double a = Bs[((4 * xs + lk) * N + 4 * yt + li) * ZP + 4 * zq + lb];
+          d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rx[xs], d1[yt], 0, 0, 0);
+        }
+#pragma unroll
+      for (int bt = 0; bt < Q; ++bt) zr[e][bt] = 0.0;
+#pragma unroll
+      for (int ys = 0; ys < Q; ++ys)
+#pragma unroll
+        for (int bt = 0; bt < Q; ++bt)
+          zr[e][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ry[ys][bt], zr[e][bt], 0, 0, 0);
+    }
+    // ---- subtraction, steps 1 and 2
+    if (with_sub && wave < Q2) {
+      const int zq = wave;
+      const double* __restrict__ sp = in + (size_t)item.src * K3;
+      const double* TX = dT + (size_t)item.tx * K * K;
+      const double* TY = dT + (size_t)item.ty * K * K;
+      double tx[Q2][Q2], ty[Q2][Q2];
+#pragma unroll
+      for (int ks = 0; ks < Q2; ++ks)
+#pragma unroll
+        for (int t = 0; t < Q2; ++t) {
+          const int r = 4 * ks + lk, cc = 4 * t + li;
+          const bool ok = r < K && cc < K;
+          tx[ks][t] = ok ? TX[r * K + cc] : 0.0;
+          ty[ks][t] = ok ? TY[r * K + cc] : 0.0;
+        }
+      double d1[Q2][Q2];
+#pragma unroll
+      for (int at = 0; at < Q2; ++at)
+#pragma unroll
+        for (int yt = 0; yt < Q2; ++yt) d1[at][yt] = 0.0;
+      const int z = 4 * zq + lb;
+#pragma unroll
+      for (int xs = 0; xs < Q2; ++xs)
+#pragma unroll
+        for (int yt = 0; yt < Q2; ++yt) {
+          const int x = 4 * xs + lk, y = 4 * yt + li;
+          double a = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
+#pragma unroll
+          for (int at = 0; at < Q2; ++at)
+            d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, tx[xs][at], d1[at][yt], 0, 0, 0);
+        }
+#pragma unroll
+      for (int at = 0; at < Q2; ++at) {
+        double d2[Q2];
+#pragma unroll
+        for (int bt = 0; bt < Q2; ++bt) d2[bt] = 0.0;
+#pragma unroll
+        for (int ys = 0; ys < Q2; ++ys)
+#pragma unroll
+          for (int bt = 0; bt < Q2; ++bt)
+            d2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], ty[ys][bt], d2[bt], 0, 0, 0);
+#pragma unroll
+        for (int bt = 0; bt < Q2; ++bt)
+          Z2[((4 * at + lk) * KP + 4 * bt + li) * ZP2 + 4 * zq + lb] = d2[bt];
+      }
+    }
+    __syncthreads();   // every wave has finished reading the source block
+#pragma unroll
+    for (int e = 0; e < PW; ++e) {
+      const int p = wave * PW + e;
+      const int zq = p / Q, at = p % Q;
+#pragma unroll
+      for (int bt = 0; bt < Q; ++bt)
+        Bs[((4 * at + lk) * N + 4 * bt + li) * ZP + 4 * zq + lb] = zr[e][bt];
+    }
+    __syncthreads();
+    // ---- step 3: z-contraction, this wave's (a-quad, b-quad) pairs
+#pragma unroll
+    for (int zs = 0; zs < Q; ++zs) {
+      double rz[Q];
+#pragma unroll
+      for (int ct = 0; ct < Q; ++ct) rz[ct] = cmu * RZ[(4 * zs + lk) * N + 4 * ct + li];
+#pragma unroll
+      for (int e = 0; e < PW; ++e) {
+        const int p = wave * PW + e;
+        const int at3 = p / Q, bt3 = p % Q;
+        double a = Bs[((4 * at3 + lb) * N + 4 * bt3 + li) * ZP + 4 * zs + lk];
+#pragma unroll
+        for (int ct = 0; ct < Q; ++ct)
+          acc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rz[ct], acc[e][ct], 0, 0, 0);
+      }
+    }
+    // ---- subtraction, step 3
+    if (with_sub) {
+      const double* TZ = dT + (size_t)item.tz * K * K;
+      double tz[Q2][Q2];
+#pragma unroll
+      for (int ks = 0; ks < Q2; ++ks)
+#pragma unroll
+        for (int t = 0; t < Q2; ++t) {
+          const int r = 4 * ks + lk, cc = 4 * t + li;
+          tz[ks][t] = (r < K && cc < K) ? -cmu * TZ[r * K + cc] : 0.0;
+        }
+#pragma unroll
+      for (int e = 0; e < S3_PER_WAVE; ++e) {
+        const int p = (3 - wave) + 4 * e;
+        if (p < S3) {
+          const int at3 = p / Q2, bt3 = p % Q2;
+#pragma unroll
+          for (int zs = 0; zs < Q2; ++zs) {
+            double a = Z2[((4 * at3 + lb) * KP + 4 * bt3 + li) * ZP2 + 4 * zs + lk];
+#pragma unroll
+            for (int ct = 0; ct < Q2; ++ct)
+              sacc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, tz[zs][ct], sacc[e][ct], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  // ---- write the children block (and the level-n part) of the target
+#pragma unroll
+  for (int e = 0; e < PW; ++e) {
+    const int p = wave * PW + e;
+    const int at3 = p / Q, bt3 = p % Q;
+    const int a = 4 * at3 + lb, b = 4 * bt3 + lk;
+#pragma unroll
+    for (int ct = 0; ct < Q; ++ct) {
+      const int c = 4 * ct + li;
+      if (tr.partial >= 0) {
+        partials[(size_t)tr.partial * (N * N2 + K3) + (a * N + b) * N + c] = acc[e][ct];
+      } else {
         const int child = ((a / K) << 2) | ((b / K) << 1) | (c / K);
         out[(size_t)(tr.fc + child) * K3 + ((a % K) * K + (b % K)) * K + (c % K)] += acc[e][ct];
+      }
+    }
+  }
+  if (with_sub) {
+#pragma unroll
+    for (int e = 0; e < S3_PER_WAVE; ++e) {
+      const int p = (3 - wave) + 4 * e;
+      if (p < S3) {
+        const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + lk;
+#pragma unroll
+        for (int ct = 0; ct < Q2; ++ct) {
+          const int c = 4 * ct + li;
+          if (a < K && b < K && c < K) {
+            if (tr.partial >= 0)
+              partials[(size_t)tr.partial * (N * N2 + K3) + N * N2 + (a * K + b) * K + c] = sacc[e][ct];
+            else
+              subbuf[(size_t)tr.sub * K3 + (a * K + b) * K + c] = sacc[e][ct];
+          }
+        }
       }
     }
   }
@@ -370,14 +751,19 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
 // --------------------------------------------------------------------------- apply (std)
 template <int K>
 __global__ __launch_bounds__(round64(K * K)) void apply_std_kernel(
-    const double* __restrict__ in, double* __restrict__ out, const NSItem* __restrict__ items,
-    const TargetRange* __restrict__ targets, const double* __restrict__ dT,
-    const double* __restrict__ dc, double scale) {
+    const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
+    const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
+    const double* const* __restrict__ t_tab, const double* const* __restrict__ c_tab,
+    double scale) {
   constexpr int K2 = K * K, K3 = K * K * K, ZP = K + 1;
   __shared__ double S[K * K * ZP];
   __shared__ double W[K * K * ZP];
   const int tid = threadIdx.x;
   const TargetRange tr = targets[blockIdx.x];
+  const double* __restrict__ in = in_tab[tr.fn];
+  double* __restrict__ out = out_tab[tr.fn];
+  const double* __restrict__ dT = t_tab[tr.fn];
+  const double* __restrict__ dc = c_tab[tr.fn];
   double acc[K];
 #pragma unroll
   for (int c = 0; c < K; ++c) acc[c] = 0.0;
@@ -450,22 +836,23 @@ __global__ __launch_bounds__(round64(K * K)) void apply_std_kernel(
 // --------------------------------------------------------------------------- sum-down
 template <int K>
 __global__ __launch_bounds__(round64(4 * K * K)) void sum_down_kernel(
-    double* __restrict__ coeff, const int32_t* __restrict__ nodes,
-    const int32_t* __restrict__ fchild, const double* __restrict__ h0,
+    double* const* __restrict__ tab, const NodeRef* __restrict__ refs,
+    const double* __restrict__ subbuf, const double* __restrict__ h0,
     const double* __restrict__ h1) {
   constexpr int N = 2 * K, K3 = K * K * K, ZP = N + 1;
-  __shared__ double V[K3];
   __shared__ double T1[K * K * ZP];
   __shared__ double T2[K * N * ZP];
   __shared__ double H[K * N];
   const int tid = threadIdx.x;
-  const int node = nodes[blockIdx.x];
-  const int fc = fchild[blockIdx.x];
+  const NodeRef ref = refs[blockIdx.x];
+  const int node = ref.node, fc = ref.fchild;
+  double* __restrict__ coeff = tab[ref.fn];
   for (int e = tid; e < K * N; e += blockDim.x) {
     int i = e / N, X = e % N;
     H[e] = X < K ? h0[i * K + X] : h1[i * K + X - K];
   }
-  for (int e = tid; e < K3; e += blockDim.x) V[e] = coeff[(size_t)node * K3 + e];
+  const double* __restrict__ V = coeff + (size_t)node * K3;
+  const double* __restrict__ VS = ref.sub >= 0 ? subbuf + (size_t)ref.sub * K3 : nullptr;
   __syncthreads();
   if (tid < K * K) {  // T1[i][j][Z] = sum_m H[m][Z] V[i][j][m]
     int i = tid / K, j = tid % K;
@@ -474,6 +861,7 @@ __global__ __launch_bounds__(round64(4 * K * K)) void sum_down_kernel(
     for (int Z = 0; Z < N; ++Z) t[Z] = 0.0;
     for (int m = 0; m < K; ++m) {
       double v = V[(i * K + j) * K + m];
+      if (VS) v += VS[(i * K + j) * K + m];
 #pragma unroll
       for (int Z = 0; Z < N; ++Z) t[Z] += H[m * N + Z] * v;
     }
@@ -575,50 +963,65 @@ void launch_zero(double* p, size_t n, hipStream_t s) {
   hip_check(hipGetLastError(), "zero_kernel");
 }
 
-void launch_filter_up(int k, const double* coeff, double* coeff_out, const int32_t* nodes,
-                      const int32_t* fchild, int count, const double* h0, const double* h1,
-                      double* bnorm2, hipStream_t s) {
+void launch_filter_up(int k, double* const* coeff_tab, const NodeRef* refs, int count,
+                      const double* h0, const double* h1, double* bnorm2, hipStream_t s) {
   if (count <= 0) return;
-  MRA_DISPATCH_K(k, hipLaunchKernelGGL(filter_up_kernel<KK>, dim3(count),
-                                       dim3(round64(4 * KK * KK)), 0, s, coeff, coeff_out, nodes,
-                                       fchild, h0, h1, bnorm2));
+  MRA_DISPATCH_K14(k, hipLaunchKernelGGL(filter_up_kernel<KK>, dim3(count), dim3(256), 0, s,
+                                         coeff_tab, refs, h0, h1, bnorm2));
   hip_check(hipGetLastError(), "filter_up_kernel");
 }
 
-void launch_apply_ns(int k, const double* in_coeff, double* out_coeff, const NSItem* items,
-                     const TargetRange* targets, int ntargets, const double* dR,
-                     const double* dc, hipStream_t s) {
+bool ns_kernel_fuses_subtraction(int k) { return k == 8 || k == 10 || k == 12; }
+
+void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
+                     const NSItem* items, const TargetRange* targets, int ntargets,
+                     const double* const* r_tab, const double* const* t_tab,
+                     const double* const* c_tab, double* partials, double* subbuf,
+                     hipStream_t s) {
   if (ntargets <= 0) return;
   if (k == 8) {
-    hipLaunchKernelGGL(apply_ns_mfma_kernel<8>, dim3(ntargets), dim3(256), 0, s, in_coeff,
-                       out_coeff, items, targets, dR, dc);
+    hipLaunchKernelGGL(apply_ns_mfma_kernel<8>, dim3(ntargets), dim3(256), 0, s, in_tab,
+                       out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
   } else if (k == 10) {
-    hipLaunchKernelGGL(apply_ns_mfma_kernel<10>, dim3(ntargets), dim3(256), 0, s, in_coeff,
-                       out_coeff, items, targets, dR, dc);
+    hipLaunchKernelGGL(apply_ns_mfma_kernel<10>, dim3(ntargets), dim3(256), 0, s, in_tab,
+                       out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
+  } else if (k == 12) {
+    hipLaunchKernelGGL(apply_ns_mfma_big_kernel<12>, dim3(ntargets), dim3(256), 0, s, in_tab,
+                       out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
   } else {
     MRA_DISPATCH_K(k, hipLaunchKernelGGL(apply_ns_kernel<KK>, dim3(ntargets),
-                                         dim3(round64(4 * KK * KK)), 0, s, in_coeff, out_coeff,
-                                         items, targets, dR, dc));
+                                         dim3(round64(4 * KK * KK)), 0, s, in_tab, out_tab,
+                                         items, targets, r_tab, c_tab, partials));
   }
   hip_check(hipGetLastError(), "apply_ns_kernel");
 }
 
-void launch_apply_std(int k, const double* in_coeff, double* out_coeff, const NSItem* items,
-                      const TargetRange* targets, int ntargets, const double* dT,
-                      const double* dc, double scale, hipStream_t s) {
+void launch_reduce_partials(int k, const double* partials, double* const* out_tab,
+                            double* subbuf, const SplitTarget* splits, int nsplits,
+                            hipStream_t s) {
+  if (nsplits <= 0) return;
+  MRA_DISPATCH_K14(k, hipLaunchKernelGGL(reduce_partials_kernel<KK>, dim3(nsplits), dim3(256),
+                                         0, s, partials, out_tab, subbuf, splits));
+  hip_check(hipGetLastError(), "reduce_partials_kernel");
+}
+
+void launch_apply_std(int k, const double* const* in_tab, double* const* out_tab,
+                      const NSItem* items, const TargetRange* targets, int ntargets,
+                      const double* const* t_tab, const double* const* c_tab, double scale,
+                      hipStream_t s) {
   if (ntargets <= 0) return;
   MRA_DISPATCH_K14(k, hipLaunchKernelGGL(apply_std_kernel<KK>, dim3(ntargets),
-                                         dim3(round64(KK * KK)), 0, s, in_coeff, out_coeff,
-                                         items, targets, dT, dc, scale));
+                                         dim3(round64(KK * KK)), 0, s, in_tab, out_tab, items,
+                                         targets, t_tab, c_tab, scale));
   hip_check(hipGetLastError(), "apply_std_kernel");
 }
 
-void launch_sum_down(int k, double* coeff, const int32_t* nodes, const int32_t* fchild,
-                     int count, const double* h0, const double* h1, hipStream_t s) {
+void launch_sum_down(int k, double* const* coeff_tab, const NodeRef* refs, int count,
+                     const double* subbuf, const double* h0, const double* h1, hipStream_t s) {
   if (count <= 0) return;
-  MRA_DISPATCH_K(k, hipLaunchKernelGGL(sum_down_kernel<KK>, dim3(count),
-                                       dim3(round64(4 * KK * KK)), 0, s, coeff, nodes, fchild,
-                                       h0, h1));
+  MRA_DISPATCH_K14(k, hipLaunchKernelGGL(sum_down_kernel<KK>, dim3(count),
+                                         dim3(round64(4 * KK * KK)), 0, s, coeff_tab, refs,
+                                         subbuf, h0, h1));
   hip_check(hipGetLastError(), "sum_down_kernel");
 }
 

@@ -168,25 +168,53 @@ struct NSItem {          // one kept (source, displacement, term) triple of a ta
   int32_t tx, ty, tz;    // t block indices (transposed k^2 blocks)
 };
 struct TargetRange {
+  int32_t fn;            // function of the batch (index into the pointer tables)
   int32_t node;          // output node T (its slab gets the level-n part)
   int32_t fc;            // first child of T in the output (children block)
   int32_t beg, end;      // items
+  int32_t partial;       // -1: accumulate into the output; else slot of a partial block
+  int32_t sub;           // >= 0: slot (k^3 doubles) receiving the level-n subtraction of T
+};
+struct SplitTarget {     // a target whose list was split over several workgroups
+  int32_t fn;
+  int32_t fc;            // first child of T in the output
+  int32_t first, count;  // partial slots ((2k)^3 + k^3 doubles each), summed in this order
+  int32_t sub;           // >= 0: level-n subtraction slot of T
+};
+// A refined node for filter-up / sum-down.  The level-n subtraction of a target is kept in
+// a slot of its own (sub >= 0) and added by sum-down, because the same slab receives the
+// parent target's children block in the same launch.
+struct NodeRef {
+  int32_t fn, node, fchild, sub;
 };
 
 void launch_zero(double* p, size_t n, hipStream_t s);
-void launch_filter_up(int k, const double* coeff, double* coeff_out, const int32_t* nodes,
-                      const int32_t* fchild, int count, const double* h0, const double* h1,
-                      double* bnorm2, hipStream_t s);
-void launch_apply_ns(int k, const double* in_coeff, double* out_coeff, const NSItem* items,
-                     const TargetRange* targets, int ntargets, const double* dR,
-                     const double* dc, hipStream_t s);
-void launch_apply_std(int k, const double* in_coeff, double* out_coeff, const NSItem* items,
-                      const TargetRange* targets, int ntargets, const double* dT,
-                      const double* dc, double scale, hipStream_t s);
-void launch_sum_down(int k, double* coeff, const int32_t* nodes, const int32_t* fchild,
-                     int count, const double* h0, const double* h1, hipStream_t s);
+void launch_filter_up(int k, double* const* coeff_tab, const NodeRef* refs, int count,
+                      const double* h0, const double* h1, double* bnorm2, hipStream_t s);
+// True when the non-standard kernel for this k also applies the level-n subtraction.
+bool ns_kernel_fuses_subtraction(int k);
+void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
+                     const NSItem* items, const TargetRange* targets, int ntargets,
+                     const double* const* r_tab, const double* const* t_tab,
+                     const double* const* c_tab, double* partials, double* subbuf,
+                     hipStream_t s);
+void launch_reduce_partials(int k, const double* partials, double* const* out_tab,
+                            double* subbuf, const SplitTarget* splits, int nsplits,
+                            hipStream_t s);
+void launch_apply_std(int k, const double* const* in_tab, double* const* out_tab,
+                      const NSItem* items, const TargetRange* targets, int ntargets,
+                      const double* const* t_tab, const double* const* c_tab, double scale,
+                      hipStream_t s);
+void launch_sum_down(int k, double* const* coeff_tab, const NodeRef* refs, int count,
+                     const double* subbuf, const double* h0, const double* h1, hipStream_t s);
 void launch_leaf_reduce(int k, const double* a, const double* b, const int32_t* leaves_a,
                         const int32_t* leaves_b, const double* weight, int count, int mode,
                         double* partial, int nblocks, hipStream_t s);
+
+// Host drivers
+void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
+                             const std::vector<Func*>& funcs, double tau,
+                             const std::vector<Func*>& outs);
+void filter_up_function(Ctx* ctx, Func& f);
 
 }  // namespace mra

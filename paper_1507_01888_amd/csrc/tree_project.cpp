@@ -8,6 +8,7 @@
 // is not refined becomes a leaf holding its own projection.
 #include <algorithm>
 #include <cmath>
+#include <thread>
 #include <unordered_map>
 
 #include "mra_internal.hpp"
@@ -110,11 +111,20 @@ struct Projector {
   int ng, k;
   double lo, W;
   std::vector<double> h0, h1;
-  // memo of 1D integrals per (gaussian, axis, level, l)
+  // 1D integrals per (gaussian, axis, level, l): a shared read-only table filled before each
+  // parallel level, and a private memo for anything not in it
+  const std::unordered_map<uint64_t, std::vector<double>>* shared = nullptr;
   std::unordered_map<uint64_t, std::vector<double>> memo;
 
+  static uint64_t key_of(int gi, int axis, int n, int64_t l) {
+    return ((uint64_t)gi << 50) | ((uint64_t)axis << 48) | ((uint64_t)n << 40) | (uint64_t)l;
+  }
   const std::vector<double>& one_d(int gi, int axis, int n, int64_t l) {
-    uint64_t key = ((uint64_t)gi << 50) | ((uint64_t)axis << 48) | ((uint64_t)n << 40) | (uint64_t)l;
+    uint64_t key = key_of(gi, axis, n, l);
+    if (shared) {
+      auto it = shared->find(key);
+      if (it != shared->end()) return it->second;
+    }
     auto it = memo.find(key);
     if (it != memo.end()) return it->second;
     std::vector<double> v(k);
@@ -232,39 +242,102 @@ uint64_t interleave(int n, int64_t lx, int64_t ly, int64_t lz) {
 void project_gaussians(Ctx* ctx, const mra_gaussian* g, int ng, int k, double thresh,
                        int initial_level, int max_level, Func& out,
                        std::vector<double>& leaf_coeffs) {
-  Projector pr;
-  pr.g = g;
-  pr.ng = ng;
-  pr.k = k;
-  pr.lo = ctx->lo;
-  pr.W = ctx->width();
-  two_scale_filters(k, pr.h0, pr.h1);
-  int k3 = k * k * k;
+  // Level by level: the refinement tests of one level run in parallel host threads, each
+  // with its own memo of 1D integrals.
+  std::vector<double> h0, h1;
+  two_scale_filters(k, h0, h1);
+  const int k3 = k * k * k;
+  unsigned nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<Projector> pr(nthr);
+  for (auto& p : pr) {
+    p.g = g;
+    p.ng = ng;
+    p.k = k;
+    p.lo = ctx->lo;
+    p.W = ctx->width();
+    p.h0 = h0;
+    p.h1 = h1;
+  }
   struct Box {
-    int n;
     int64_t lx, ly, lz;
   };
-  std::vector<Box> stack;
+  std::vector<Box> frontier;
   int64_t nb = (int64_t)1 << initial_level;
   for (int64_t x = 0; x < nb; ++x)
     for (int64_t y = 0; y < nb; ++y)
-      for (int64_t z = 0; z < nb; ++z) stack.push_back({initial_level, x, y, z});
-  std::vector<std::vector<uint64_t>> levels(max_level + 1);
+      for (int64_t z = 0; z < nb; ++z) frontier.push_back({x, y, z});
   std::vector<std::pair<uint64_t, std::vector<double>>> leafvals;  // (prefixed code, coeffs)
-  std::vector<double> kids;
-  while (!stack.empty()) {
-    Box b = stack.back();
-    stack.pop_back();
-    if (b.n < max_level && pr.wavelet_norm(b.n, b.lx, b.ly, b.lz, kids) > thresh) {
-      for (int c = 0; c < 8; ++c)
-        stack.push_back({b.n + 1, 2 * b.lx + ((c >> 2) & 1), 2 * b.ly + ((c >> 1) & 1),
-                         2 * b.lz + (c & 1)});
-    } else {
-      std::vector<double> v(k3);
-      pr.box(b.n, b.lx, b.ly, b.lz, v.data());
-      uint64_t code = interleave(b.n, b.lx, b.ly, b.lz);
-      leafvals.push_back({((uint64_t)b.n << 58) | code, std::move(v)});
+  std::unordered_map<uint64_t, std::vector<double>> table;
+  for (int n = initial_level; n <= max_level && !frontier.empty(); ++n) {
+    // the 1D integrals this level needs (boxes at n, children at n+1), computed once
+    {
+      std::vector<uint64_t> need;
+      for (const Box& b : frontier) {
+        const int64_t l3[3] = {b.lx, b.ly, b.lz};
+        for (int gi = 0; gi < ng; ++gi)
+          for (int ax = 0; ax < 3; ++ax) {
+            need.push_back(Projector::key_of(gi, ax, n, l3[ax]));
+            if (n < max_level) {
+              need.push_back(Projector::key_of(gi, ax, n + 1, 2 * l3[ax]));
+              need.push_back(Projector::key_of(gi, ax, n + 1, 2 * l3[ax] + 1));
+            }
+          }
+      }
+      std::sort(need.begin(), need.end());
+      need.erase(std::unique(need.begin(), need.end()), need.end());
+      std::vector<std::vector<double>> vals1(need.size(), std::vector<double>(k));
+      const unsigned nt1 = (unsigned)std::max<size_t>(1, std::min<size_t>(nthr, need.size()));
+      auto fill = [&](unsigned t) {
+        for (size_t i = t; i < need.size(); i += nt1) {
+          uint64_t key = need[i];
+          int gi = (int)(key >> 50), ax = (int)((key >> 48) & 3), lev = (int)((key >> 40) & 255);
+          int64_t l = (int64_t)(key & ((1ULL << 40) - 1));
+          gaussian_1d(k, g[gi].expnt, g[gi].center[ax], ctx->lo, ctx->width() / std::ldexp(1.0, lev),
+                      l, vals1[i].data());
+        }
+      };
+      std::vector<std::thread> th1;
+      for (unsigned t = 1; t < nt1; ++t) th1.emplace_back(fill, t);
+      fill(0);
+      for (auto& t : th1) t.join();
+      table.clear();
+      table.reserve(need.size() * 2);
+      for (size_t i = 0; i < need.size(); ++i) table.emplace(need[i], std::move(vals1[i]));
+      for (auto& p : pr) {
+        p.shared = &table;
+        p.memo.clear();
+      }
     }
+    std::vector<char> refine(frontier.size(), 0);
+    std::vector<std::vector<double>> vals(frontier.size());
+    const unsigned nt = (unsigned)std::min<size_t>(nthr, frontier.size());
+    auto work = [&](unsigned t) {
+      std::vector<double> kids;
+      for (size_t i = t; i < frontier.size(); i += nt) {
+        const Box& b = frontier[i];
+        if (n < max_level && pr[t].wavelet_norm(n, b.lx, b.ly, b.lz, kids) > thresh) {
+          refine[i] = 1;
+        } else {
+          vals[i].resize(k3);
+          pr[t].box(n, b.lx, b.ly, b.lz, vals[i].data());
+        }
+      }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nt; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto& t : th) t.join();
+    std::vector<Box> next;
+    for (size_t i = 0; i < frontier.size(); ++i) {
+      const Box& b = frontier[i];
+      if (refine[i]) {
+        for (int c = 0; c < 8; ++c)
+          next.push_back({2 * b.lx + ((c >> 2) & 1), 2 * b.ly + ((c >> 1) & 1), 2 * b.lz + (c & 1)});
+      } else {
+        leafvals.push_back({((uint64_t)n << 58) | interleave(n, b.lx, b.ly, b.lz), std::move(vals[i])});
+      }
+    }
+    frontier.swap(next);
   }
   // node sets: leaves plus all ancestors
   std::vector<std::vector<uint64_t>> sets(max_level + 1);
@@ -285,8 +358,6 @@ void project_gaussians(Ctx* ctx, const mra_gaussian* g, int ng, int k, double th
   out.k = k;
   build_tree(out, sets);
   // leaf coefficients in node order
-  std::sort(leafvals.begin(), leafvals.end(),
-            [](const auto& a, const auto& b) { return a.first < b.first; });
   leaf_coeffs.assign((size_t)out.nodes() * k3, 0.0);
   for (auto& lv : leafvals) {
     int n = (int)(lv.first >> 58);

@@ -200,11 +200,64 @@ def test_deterministic_and_errors(M):
     with pytest.raises(M.MraError) as e:
         ctx.apply(op6, f, tau_drop=1e-8)
     assert e.value.code == -5
-    f12 = ctx.project(c, a, x, 12, 1e-3)
-    op12 = ctx.op_coulomb(12, 1e-4, 1e-6)
+    f13 = ctx.project(c, a, x, 13, 1e-3)
+    op13 = ctx.op_coulomb(13, 1e-4, 1e-6)
     with pytest.raises(M.MraError) as e:
-        ctx.apply(op12, f12, tau_drop=1e-8)
+        ctx.apply(op13, f13, tau_drop=1e-8)
     assert e.value.code == -4
     with pytest.raises(M.MraError) as e:
         ctx.project(c, a, x, 15, 1e-3)
     assert e.value.code == -1
+
+
+def test_batched_bsh_matches_single_and_oracle(M):
+    """Several functions with their own Helmholtz kernels in one batched apply: the same
+    triples and trees as the one-at-a-time applies, values equal up to the summation order
+    of split target lists (the split size depends on the batch), and parity with the oracle."""
+    _say("case: batched bsh, 4 functions, k=10, thresh 1e-4")
+    ctx = M.Context(0, W.CELL)
+    funcs, ops, params = [], [], []
+    for i in range(4):
+        c, a, x, mu = W.bsh_inputs(i)
+        funcs.append(ctx.project(c, a, x, 10, 1e-4))
+        ops.append(ctx.op_bsh(10, mu, 1e-5, 1e-8))
+        params.append((c, a, x, mu))
+    outs = ctx.apply_batch(ops, funcs, tau_drop=1e-8)
+    st = ctx.last_stats()
+    tot = 0
+    for i in range(4):
+        single = ctx.apply(ops[i], funcs[i], tau_drop=1e-8)
+        tot += ctx.last_stats()["triples"]
+        a, b = _as_dict(outs[i]), _as_dict(single)
+        assert set(a) == set(b)
+        assert _rel_l2(a, b, b) <= 1e-14
+    assert st["triples"] == tot
+    c, a, x, mu = params[2]
+    fo = project_adaptive(GaussianSum(c, a, x), 10, 1e-4, W.CELL, 2, 20)
+    cc, tt = bsh_fit(mu, 1e-5, 1e-8, cell_r_hi(*W.CELL))
+    ref, _ = apply_nonstandard(fo, SeparatedOperator(cc, tt), 1e-8)
+    got = _as_dict(outs[2])
+    assert set(got) == set(ref.leaves)
+    err = _rel_l2(got, ref.leaves, ref.leaves)
+    _say("batched bsh function 2 rel L2 vs oracle", err)
+    assert err <= TOL
+
+
+def test_coulomb_k12_reduced_full_parity(M):
+    """k=12 non-standard apply (the mixed-precision workload's order) in FP64, every leaf."""
+    _say("case: coulomb k=12 reduced (1 Gaussian, thresh 1e-6)")
+    c, a, x = W.unit_charge_gaussians(2, 7, 1, 3.0, 3.0)
+    ctx = M.Context(0, W.CELL)
+    f = ctx.project(c, a, x, 12, 1e-6)
+    op = ctx.op_coulomb(12, 1e-5, 1e-8)
+    g = ctx.apply(op, f, tau_drop=1e-10)
+    fo = project_adaptive(GaussianSum(c, a, x), 12, 1e-6, W.CELL, 2, 20)
+    assert set(_as_dict(f)) == set(fo.leaves)
+    cc, tt = coulomb_fit(1e-5, 1e-8, cell_r_hi(*W.CELL))
+    ref, st = apply_nonstandard(fo, SeparatedOperator(cc, tt), 1e-10)
+    got = _as_dict(g)
+    assert set(got) == set(ref.leaves)
+    assert ctx.last_stats()["triples"] == st["triples"]
+    err = _rel_l2(got, ref.leaves, ref.leaves)
+    _say("coulomb k12 reduced rel L2 vs oracle", err, "triples", st["triples"])
+    assert err <= TOL
