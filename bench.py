@@ -36,7 +36,21 @@ def parse():
                    choices=["coulomb_k10", "coulomb_k12_fp64", "bsh_batch_k10"])
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="approximate CPU work of the oracle baseline sample (0 = skip)")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run a device-to-device copy of MIB MiB (for calibrating HBM "
+                        "byte counters of a profiler against a transfer of known size)")
     return p.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "check": float(b[n // 2].item())}))
 
 
 def cpu_baseline(name, budget_s):
@@ -100,8 +114,28 @@ def setup(ctx, name):
     return [f], [op], w["tau_rel"] * w["thresh"], w["k"], cfg
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when the summary was taken on a different version of the kernel source."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1507_01888_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_pmc.md")):
+        for line in open(path):
+            if line.startswith("pmc: "):
+                rec = json.loads(line[5:])
+                if rec.get("kernel") == kernel and rec.get("kernels_hip_sha256_16") == sha:
+                    return 1024.0 * (rec["fetch_kib"] * rec["fetch_factor"]
+                                     + rec["write_kib"] * rec["write_factor"])
+    return None
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU; --gpus %d is not supported by this build "
               "(the multi-GPU sharding is a design note, not an implementation)" % args.gpus,
@@ -141,6 +175,8 @@ def main():
     fused = k in (8, 10, 12)
     kernel_flops = stats[0]["useful_flops"] if fused else stats[0]["triples"] * 6.0 * (2 * k) ** 4
     main_ms = sum(s["ms_main_kernel"] for s in stats) / len(stats)
+    kname = {8: "apply_ns_mfma_kernel<8>", 10: "apply_ns_mfma_kernel<10>",
+             12: "apply_ns_mfma_big_kernel<12>"}.get(k, "apply_ns_kernel<%d>" % k)
     achieved = kernel_flops / (main_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -163,11 +199,10 @@ def main():
         "stage_ms": {key: sum(s[key] for s in stats) / len(stats)
                      for key in ("ms_filter", "ms_plan", "ms_apply", "ms_main_kernel", "ms_sumdown")},
         "norm2": nrm[0] if len(nrm) == 1 else sum(v * v for v in nrm) ** 0.5,
-        "roofline": {"kernel": {8: "apply_ns_mfma_kernel<8>", 10: "apply_ns_mfma_kernel<10>",
-                                12: "apply_ns_mfma_big_kernel<12>"}.get(k, "apply_ns_kernel<%d>" % k),
+        "roofline": {"kernel": kname,
                      "bound": "mfma" if k in (8, 10, 12) else "alu", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": None},
+                     "traffic": measured_traffic(kname)},
     }
     if args.cpu_seconds > 0 and args.workload == "coulomb_k10":
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
