@@ -107,8 +107,8 @@ struct Plan {
   Func* f = nullptr;
   Func* out = nullptr;
   std::vector<const BlockEntry*> entry_tab;  // (level, mu) -> cache entry
-  std::vector<Triple> triples;                // grouped by target, then (source, term)
   std::vector<NSItem> items;
+  int64_t ntriples = 0;
   std::vector<TargetRange> tgt, tgt_sub;
   double flops = 0.0;
 };
@@ -133,20 +133,16 @@ void validate(const Plan& p, int64_t nR, int64_t nT) {
   }
 }
 
-// Output tree, items and target ranges of one function from its grouped triples.
-void build_plan(Ctx* ctx, Plan& p) {
-  Func& f = *p.f;
+// Output tree of one function from its sorted target codes: targets, their children,
+// ancestors, closed under siblings (full octree).
+void build_output_tree(Ctx* ctx, Plan& p, const std::vector<uint64_t>& tcodes) {
   Func& out = *p.out;
-  const int k = f.k;
-  const int M = (int)p.op->c.size();
-  const auto& triples = p.triples;
   int maxlev = 0;
-  for (auto& t : triples) maxlev = std::max(maxlev, (int)(t.tcode >> 58) + 1);
+  for (uint64_t t : tcodes) maxlev = std::max(maxlev, (int)(t >> 58) + 1);
   std::vector<std::vector<uint64_t>> sets(std::max(maxlev + 1, 1));
-  for (size_t i = 0; i < triples.size(); ++i) {
-    if (i > 0 && triples[i].tcode == triples[i - 1].tcode) continue;
-    int n = (int)(triples[i].tcode >> 58);
-    uint64_t code = triples[i].tcode & ((1ULL << 58) - 1);
+  for (uint64_t t : tcodes) {
+    int n = (int)(t >> 58);
+    uint64_t code = t & ((1ULL << 58) - 1);
     sets[n].push_back(code);
     for (int c = 0; c < 8; ++c) sets[n + 1].push_back((code << 3) | c);
   }
@@ -170,44 +166,103 @@ void build_plan(Ctx* ctx, Plan& p) {
   std::sort(sets[0].begin(), sets[0].end());
   sets[0].erase(std::unique(sets[0].begin(), sets[0].end()), sets[0].end());
   out.ctx = ctx;
-  out.k = k;
+  out.k = p.f->k;
   build_tree(out, sets);
+}
 
-  p.items.clear();
-  p.items.reserve(triples.size());
-  p.tgt.clear();
-  p.tgt_sub.clear();
-  p.flops = 0.0;
+// The kept triples of one (function, level) unit, grouped by target and, within a target,
+// ordered by source then term (so that a source block is staged once per run of terms).
+struct Unit {
+  int fn = 0, n = 0;
+  size_t jb = 0, je = 0;               // jobs of this unit
+  std::vector<Triple> sorted;
+  std::vector<uint64_t> tcodes;        // ascending
+  std::vector<int64_t> toff;           // tcodes.size() + 1
+  std::vector<NSItem> items;
+  std::vector<TargetRange> tgt;
+  double flops = 0.0;
+};
+
+void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const LevelData& L) {
+  size_t m = 0;
+  for (size_t j = u.jb; j < u.je; ++j) m += jobout[j].size();
+  // distinct targets
+  std::vector<uint64_t> codes;
+  codes.reserve(m / 4 + 16);
+  for (size_t j = u.jb; j < u.je; ++j)
+    for (const Triple& t : jobout[j]) codes.push_back(t.tcode);
+  std::sort(codes.begin(), codes.end());
+  codes.erase(std::unique(codes.begin(), codes.end()), codes.end());
+  u.tcodes = codes;
+  const int64_t nt = (int64_t)codes.size(), np = L.np;
+  if (nt * np > (int64_t)1 << 22) {
+    // large unit: comparison sort on (target, source, term)
+    u.sorted.clear();
+    u.sorted.reserve(m);
+    for (size_t j = u.jb; j < u.je; ++j)
+      u.sorted.insert(u.sorted.end(), jobout[j].begin(), jobout[j].end());
+    std::sort(u.sorted.begin(), u.sorted.end(), [](const Triple& a, const Triple& b) {
+      if (a.tcode != b.tcode) return a.tcode < b.tcode;
+      if (a.src != b.src) return a.src < b.src;
+      return a.mu < b.mu;
+    });
+    u.toff.assign(nt + 1, 0);
+    int64_t r = 0;
+    for (size_t q = 0; q < m; ++q) {
+      while (u.sorted[q].tcode != codes[r]) u.toff[++r] = (int64_t)q;
+    }
+    while (r < nt) u.toff[++r] = (int64_t)m;
+    return;
+  }
+  // counting sort on (target rank, source) — stable, so terms stay ascending
+  std::vector<int64_t> cnt((size_t)nt * np + 1, 0);
+  std::vector<int64_t> key(m);
+  size_t q = 0;
+  for (size_t j = u.jb; j < u.je; ++j)
+    for (const Triple& t : jobout[j]) {
+      int64_t r = std::lower_bound(codes.begin(), codes.end(), t.tcode) - codes.begin();
+      int64_t kk = r * np + (t.src - L.ib);
+      key[q++] = kk;
+      ++cnt[kk + 1];
+    }
+  for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+  u.toff.assign(nt + 1, 0);
+  for (int64_t r = 0; r <= nt; ++r) u.toff[r] = cnt[r * np];
+  u.sorted.resize(m);
+  q = 0;
+  for (size_t j = u.jb; j < u.je; ++j)
+    for (const Triple& t : jobout[j]) u.sorted[cnt[key[q++]]++] = t;
+}
+
+void unit_items(Unit& u, const Plan& p) {
+  const Func& f = *p.f;
+  const Func& out = *p.out;
+  const int k = f.k, n = u.n;
+  const int M = (int)p.op->c.size();
   const double f_ns = 6.0 * std::pow(2.0 * k, 4), f_sub = 6.0 * std::pow((double)k, 4);
-  for (size_t i = 0; i < triples.size();) {
-    size_t j = i;
-    while (j < triples.size() && triples[j].tcode == triples[i].tcode) ++j;
-    int n = (int)(triples[i].tcode >> 58);
-    uint64_t code = triples[i].tcode & ((1ULL << 58) - 1);
+  u.items.resize(u.sorted.size());
+  u.tgt.resize(u.tcodes.size());
+  u.flops = (double)u.sorted.size() * (f_ns + (n > 0 ? f_sub : 0.0));
+  for (size_t r = 0; r < u.tcodes.size(); ++r) {
+    uint64_t code = u.tcodes[r] & ((1ULL << 58) - 1);
     int64_t node = find_node(out, n, code);
     // sub = 0 marks "has a level-n subtraction"; the slot is assigned when combining
-    TargetRange r{0, (int32_t)node, out.first_child[node], (int32_t)p.items.size(), 0, -1,
-                  n > 0 ? 0 : -1};
-    for (size_t q = i; q < j; ++q) {
-      const Triple& t = triples[q];
-      const BlockEntry& be = *p.entry_tab[(size_t)n * M + t.mu];
-      NSItem it;
-      it.src = f.interior[t.src];
-      it.src_fc = f.first_child[it.src];
-      it.mu = t.mu;
-      it.rx = (int32_t)(be.r_base + t.dx + be.D);
-      it.ry = (int32_t)(be.r_base + t.dy + be.D);
-      it.rz = (int32_t)(be.r_base + t.dz + be.D);
-      it.tx = (int32_t)(be.t_base + t.dx + be.D);
-      it.ty = (int32_t)(be.t_base + t.dy + be.D);
-      it.tz = (int32_t)(be.t_base + t.dz + be.D);
-      p.items.push_back(it);
-      p.flops += f_ns + (n > 0 ? f_sub : 0.0);
-    }
-    r.end = (int32_t)p.items.size();
-    p.tgt.push_back(r);
-    if (n > 0) p.tgt_sub.push_back(r);
-    i = j;
+    u.tgt[r] = {0, (int32_t)node, out.first_child[node], (int32_t)u.toff[r], (int32_t)u.toff[r + 1],
+                -1, n > 0 ? 0 : -1};
+  }
+  for (size_t q = 0; q < u.sorted.size(); ++q) {
+    const Triple& t = u.sorted[q];
+    const BlockEntry& be = *p.entry_tab[(size_t)n * M + t.mu];
+    NSItem& it = u.items[q];
+    it.src = f.interior[t.src];
+    it.src_fc = f.first_child[it.src];
+    it.mu = t.mu;
+    it.rx = (int32_t)(be.r_base + t.dx + be.D);
+    it.ry = (int32_t)(be.r_base + t.dy + be.D);
+    it.rz = (int32_t)(be.r_base + t.dz + be.D);
+    it.tx = (int32_t)(be.t_base + t.dx + be.D);
+    it.ty = (int32_t)(be.t_base + t.dy + be.D);
+    it.tz = (int32_t)(be.t_base + t.dz + be.D);
   }
 }
 
@@ -363,10 +418,9 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   }
 
   mark("levels and jobs");
-  // ---- 2b. enumerate kept triples (threads over jobs)
-  const unsigned nthr = worker_count(jobs.size());
-  std::vector<std::vector<std::pair<int32_t, Triple>>> part(nthr);
-  parallel_for(jobs.size(), [&](size_t j, unsigned tno) {
+  // ---- 2b. enumerate kept triples (threads over jobs; one output vector per job)
+  std::vector<std::vector<Triple>> jobout(jobs.size());
+  parallel_for(jobs.size(), [&](size_t j, unsigned) {
     const Job& jb = jobs[j];
     const LevelData& L = lv[jb.lev];
     const Op& op = *ops[L.fn];
@@ -379,7 +433,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       aa[d] = jb.be->a[d];
       rr[d] = jb.be->r[d];
     }
-    auto& outv = part[tno];
+    auto& outv = jobout[j];
     for (int dx = -D; dx <= D; ++dx)
       for (int dy = -D; dy <= D; ++dy)
         for (int dz = -D; dz <= D; ++dz) {
@@ -392,61 +446,54 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
             if (!(c * N * L.bn[p] >= tau)) break;
             int64_t tx = L.px[p] + dx, ty = L.py[p] + dy, tz = L.pz[p] + dz;
             if (tx < 0 || ty < 0 || tz < 0 || tx >= nb || ty >= nb || tz >= nb) continue;
-            outv.push_back({L.fn, {((uint64_t)n << 58) | encode(n, tx, ty, tz), (int32_t)(L.ib + p),
-                                   (int16_t)mu, (int16_t)dx, (int16_t)dy, (int16_t)dz}});
+            outv.push_back({((uint64_t)n << 58) | encode(n, tx, ty, tz), (int32_t)(L.ib + p),
+                            (int16_t)mu, (int16_t)dx, (int16_t)dy, (int16_t)dz});
           }
         }
   });
-  // bucket by function
-  {
-    std::vector<size_t> cnt(nf, 0);
-    for (auto& v : part)
-      for (auto& pr : v) ++cnt[pr.first];
-    std::vector<std::vector<Triple>> byfn(nf);
-    for (int i = 0; i < nf; ++i) byfn[i].reserve(cnt[i]);
-    for (auto& v : part) {
-      for (auto& pr : v) byfn[pr.first].push_back(pr.second);
-      std::vector<std::pair<int32_t, Triple>>().swap(v);
-    }
-    for (int i = 0; i < nf; ++i) plans[i].triples.swap(byfn[i]);
+  mark("enumerate");
+  // ---- 3. group by target per (function, level) unit (threads over units), output tree
+  // per function, then items per unit (threads over units)
+  std::vector<Unit> units;
+  std::vector<int> unit_lev;
+  for (size_t j = 0; j < jobs.size();) {
+    size_t e = j;
+    while (e < jobs.size() && jobs[e].lev == jobs[j].lev) ++e;
+    Unit u;
+    u.fn = lv[jobs[j].lev].fn;
+    u.n = lv[jobs[j].lev].n;
+    u.jb = j;
+    u.je = e;
+    units.push_back(std::move(u));
+    unit_lev.push_back(jobs[j].lev);
+    j = e;
   }
-
-  mark("enumerate + bucket");
-  // ---- 3. per function: group by target, output tree, work list (threads over functions)
-  parallel_for((size_t)nf, [&](size_t i, unsigned) {
-    Plan& p = plans[i];
-    auto& tr = p.triples;
-    std::vector<uint64_t> tcodes;
-    {
-      std::unordered_set<uint64_t> seen;
-      seen.reserve(tr.size() / 8 + 16);
-      for (auto& t : tr)
-        if (seen.insert(t.tcode).second) tcodes.push_back(t.tcode);
-      std::sort(tcodes.begin(), tcodes.end());
-    }
-    std::unordered_map<uint64_t, int32_t> tindex;
-    tindex.reserve(tcodes.size() * 2 + 16);
-    for (size_t q = 0; q < tcodes.size(); ++q) tindex.emplace(tcodes[q], (int32_t)q);
-    std::vector<int64_t> toff(tcodes.size() + 1, 0);
-    std::vector<int32_t> slot(tr.size());
-    for (size_t q = 0; q < tr.size(); ++q) {
-      slot[q] = tindex[tr[q].tcode];
-      ++toff[slot[q] + 1];
-    }
-    for (size_t q = 0; q < tcodes.size(); ++q) toff[q + 1] += toff[q];
-    std::vector<Triple> sorted(tr.size());
-    std::vector<int64_t> fillp(toff.begin(), toff.end() - 1);
-    for (size_t q = 0; q < tr.size(); ++q) sorted[fillp[slot[q]]++] = tr[q];
-    for (size_t q = 0; q < tcodes.size(); ++q)
-      std::sort(sorted.begin() + toff[q], sorted.begin() + toff[q + 1],
-                [](const Triple& a, const Triple& b) {
-                  if (a.src != b.src) return a.src < b.src;
-                  return a.mu < b.mu;
-                });
-    tr.swap(sorted);
-    build_plan(ctx, p);
+  parallel_for(units.size(), [&](size_t i, unsigned) {
+    group_unit(units[i], jobout, lv[unit_lev[i]]);
   });
-
+  std::vector<std::vector<Triple>>().swap(jobout);
+  parallel_for((size_t)nf, [&](size_t i, unsigned) {
+    std::vector<uint64_t> tc;
+    for (const Unit& u : units)
+      if (u.fn == (int)i) tc.insert(tc.end(), u.tcodes.begin(), u.tcodes.end());
+    build_output_tree(ctx, plans[i], tc);
+  });
+  parallel_for(units.size(), [&](size_t i, unsigned) { unit_items(units[i], plans[units[i].fn]); });
+  // concatenate the units of each function in level order (jobs are function-major,
+  // level-major, so units already are)
+  for (Unit& u : units) {
+    Plan& p = plans[u.fn];
+    const int32_t base = (int32_t)p.items.size();
+    p.items.insert(p.items.end(), u.items.begin(), u.items.end());
+    for (TargetRange r : u.tgt) {
+      r.beg += base;
+      r.end += base;
+      p.tgt.push_back(r);
+      if (u.n > 0) p.tgt_sub.push_back(r);
+    }
+    p.flops += u.flops;
+    p.ntriples += (int64_t)u.sorted.size();
+  }
   mark("group + output tree + items");
   // ---- 4. combine the batch
   std::vector<Op*> uniq_ops;
@@ -504,7 +551,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
         tgt_sub.push_back(r);
       }
     flops += p.flops;
-    ntriples += (int64_t)p.triples.size();
+    ntriples += p.ntriples;
     ntargets += (int64_t)p.tgt.size();
     in_leaves += (int64_t)p.f->leaves.size();
     out_nodes += p.out->nodes();
