@@ -245,7 +245,10 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(
 // The z-contraction needs the full z range, so the y-contracted tensor is exchanged through
 // LDS.  Work split for 4 waves: step 1+2 units are (a-quad, z-quad) pairs grouped by
 // z-quad, step 3 units are (a-quad, b-quad) pairs; results stay in registers across all
-// triples of the target.
+// triples of the target.  The operator blocks of a triple (three (2k)^2 and three k^2
+// blocks) sit in LDS; those of the next triple are loaded into registers while the current
+// one finishes and written to LDS after it.  The quad-structured LDS accesses are
+// bank-conflict free without padding.
 template <int K>
 __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
     const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
@@ -253,7 +256,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
     const double* const* __restrict__ r_tab, const double* const* __restrict__ t_tab,
     const double* const* __restrict__ c_tab, double* __restrict__ partials,
     double* __restrict__ subbuf) {
-  constexpr int N = 2 * K, Q = N / 4, N2 = N * N, K3 = K * K * K, ZP = N + 1;
+  constexpr int N = 2 * K, Q = N / 4, N2 = N * N, N3 = N * N * N, K2 = K * K, K3 = K * K * K;
   static_assert(N % 4 == 0, "k must be even");
   static_assert(Q >= 4 && Q <= 5, "register budget sized for 2k = 16 or 20");
   constexpr int EXTRA = (Q - 4) * Q;                 // (z-quad >= 4) pairs, round robin
@@ -261,12 +264,15 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
   constexpr int P3 = Q * Q;                          // step-3 (a-quad, b-quad) pairs
   constexpr int P3_PER_WAVE = (P3 + 3) / 4;
   // level-n subtraction -c (t x t x t) s_P on k^3 padded to KP = 4 Q2
-  constexpr int Q2 = (K + 3) / 4, KP = 4 * Q2, ZP2 = KP + 1;
+  constexpr int Q2 = (K + 3) / 4, KP = 4 * Q2;
   constexpr int S3 = Q2 * Q2;
   constexpr int S3_PER_WAVE = (S3 + 3) / 4;
-  __shared__ double Xs[N * N * ZP];
-  __shared__ double Zs[N * N * ZP];
-  __shared__ double Z2[KP * KP * ZP2];
+  constexpr int OPS = 3 * N2 + 3 * K2;               // operator doubles per triple
+  constexpr int OPS_PER_LANE = (OPS + 255) / 256;
+  __shared__ double Xs[N3];
+  __shared__ double Zs[N3];
+  __shared__ double Z2[KP * KP * KP];
+  __shared__ double Os[OPS];                          // Rx^T, Ry^T, Rz^T, tx^T, ty^T, tz^T
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
@@ -276,6 +282,39 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
   const double* __restrict__ dR = r_tab[tr.fn];
   const double* __restrict__ dT = t_tab[tr.fn];
   const double* __restrict__ dc = c_tab[tr.fn];
+  const double* RXs = Os;
+  const double* RYs = Os + N2;
+  const double* RZs = Os + 2 * N2;
+  const double* TXs = Os + 3 * N2;
+  const double* TYs = Os + 3 * N2 + K2;
+  const double* TZs = Os + 3 * N2 + 2 * K2;
+
+  // operator blocks of item `it` into registers (this thread's share)
+  auto fetch_ops = [&](int it, double* reg) {
+    const NSItem nx = items[it];
+#pragma unroll
+    for (int q = 0; q < OPS_PER_LANE; ++q) {
+      const int e = tid + 256 * q;
+      double v = 0.0;
+      if (e < 3 * N2) {
+        const int w = e / N2, r = e - w * N2;
+        const int blk = w == 0 ? nx.rx : (w == 1 ? nx.ry : nx.rz);
+        v = dR[(size_t)blk * N2 + r];
+      } else if (e < OPS) {
+        const int e2 = e - 3 * N2, w = e2 / K2, r = e2 - w * K2;
+        const int blk = w == 0 ? nx.tx : (w == 1 ? nx.ty : nx.tz);
+        v = dT[(size_t)blk * K2 + r];
+      }
+      reg[q] = v;
+    }
+  };
+  auto store_ops = [&](const double* reg) {
+#pragma unroll
+    for (int q = 0; q < OPS_PER_LANE; ++q) {
+      const int e = tid + 256 * q;
+      if (e < OPS) Os[e] = reg[q];
+    }
+  };
 
   double acc[P3_PER_WAVE][Q];
 #pragma unroll
@@ -289,6 +328,11 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
     for (int c = 0; c < Q2; ++c) sacc[p][c] = 0.0;
   const bool with_sub = tr.sub >= 0;
 
+  double pre[OPS_PER_LANE];
+  if (tr.beg < tr.end) {
+    fetch_ops(tr.beg, pre);
+    store_ops(pre);
+  }
   int loaded = -1;
   for (int it = tr.beg; it < tr.end; ++it) {
     const NSItem item = items[it];
@@ -296,25 +340,22 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
       __syncthreads();
       for (int e = tid; e < 8 * K3; e += 256) {
         int c = e / K3, r = e - c * K3;
-        int i = r / (K * K), j = (r / K) % K, m = r % K;
-        Xs[((((c >> 2) & 1) * K + i) * N + ((c >> 1) & 1) * K + j) * ZP + (c & 1) * K + m] =
+        int i = r / K2, j = (r / K) % K, m = r % K;
+        Xs[((((c >> 2) & 1) * K + i) * N + ((c >> 1) & 1) * K + j) * N + (c & 1) * K + m] =
             in[(size_t)(item.src_fc + c) * K3 + r];
       }
       loaded = item.src_fc;
-      __syncthreads();
     }
-    const double* RX = dR + (size_t)item.rx * N2;   // transposed: RX[x*N + a] = R[a][x]
-    const double* RY = dR + (size_t)item.ry * N2;
-    const double* RZ = dR + (size_t)item.rz * N2;
+    __syncthreads();   // Xs and Os of this triple are in place
     const double cmu = dc[item.mu];
-    // B fragments: frag(ks, t) = R[4t + li][4ks + lk]
+    // B fragments: frag(ks, t) = R[4t + li][4ks + lk] = R^T[4ks + lk][4t + li]
     double rx[Q][Q], ry[Q][Q];
 #pragma unroll
     for (int ks = 0; ks < Q; ++ks)
 #pragma unroll
       for (int t = 0; t < Q; ++t) {
-        rx[ks][t] = RX[(4 * ks + lk) * N + 4 * t + li];
-        ry[ks][t] = RY[(4 * ks + lk) * N + 4 * t + li];
+        rx[ks][t] = RXs[(4 * ks + lk) * N + 4 * t + li];
+        ry[ks][t] = RYs[(4 * ks + lk) * N + 4 * t + li];
       }
     // ---- steps 1 and 2 for the main z-quad of this wave (all a-quads)
     if (wave < Q) {
@@ -328,7 +369,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
       for (int xs = 0; xs < Q; ++xs)
 #pragma unroll
         for (int yt = 0; yt < Q; ++yt) {
-          double a = Xs[((4 * xs + lk) * N + 4 * yt + li) * ZP + 4 * zq + lb];
+          double a = Xs[((4 * xs + lk) * N + 4 * yt + li) * N + 4 * zq + lb];
 #pragma unroll
           for (int at = 0; at < Q; ++at)
             d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rx[xs][at], d1[at][yt], 0, 0, 0);
@@ -345,7 +386,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
             d2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], ry[ys][bt], d2[bt], 0, 0, 0);
 #pragma unroll
         for (int bt = 0; bt < Q; ++bt)
-          Zs[((4 * at + lk) * N + 4 * bt + li) * ZP + 4 * zq + lb] = d2[bt];
+          Zs[((4 * at + lk) * N + 4 * bt + li) * N + 4 * zq + lb] = d2[bt];
       }
     }
     // ---- leftover (z-quad >= 4) pairs, round robin over the waves
@@ -358,16 +399,14 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
 #pragma unroll
         for (int yt = 0; yt < Q; ++yt) d1[yt] = 0.0;
 #pragma unroll
-        for (int xs = 0; xs < Q; ++xs)
+        for (int xs = 0; xs < Q; ++xs) {
+          const double b = RXs[(4 * xs + lk) * N + 4 * at + li];
 #pragma unroll
           for (int yt = 0; yt < Q; ++yt) {
-            double a = Xs[((4 * xs + lk) * N + 4 * yt + li) * ZP + 4 * zq + lb];
-            double b = 0.0;
-#pragma unroll
-            for (int t = 0; t < Q; ++t)
-              if (t == at) b = rx[xs][t];
+            double a = Xs[((4 * xs + lk) * N + 4 * yt + li) * N + 4 * zq + lb];
             d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, d1[yt], 0, 0, 0);
           }
+        }
         double d2[Q];
 #pragma unroll
         for (int bt = 0; bt < Q; ++bt) d2[bt] = 0.0;
@@ -378,15 +417,13 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
             d2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ry[ys][bt], d2[bt], 0, 0, 0);
 #pragma unroll
         for (int bt = 0; bt < Q; ++bt)
-          Zs[((4 * at + lk) * N + 4 * bt + li) * ZP + 4 * zq + lb] = d2[bt];
+          Zs[((4 * at + lk) * N + 4 * bt + li) * N + 4 * zq + lb] = d2[bt];
       }
     }
     // ---- subtraction, steps 1 and 2: (t_x, t_y) on s_P, one z-quad per wave
     if (with_sub && wave < Q2) {
       const int zq = wave;
       const double* __restrict__ sp = in + (size_t)item.src * K3;
-      const double* TX = dT + (size_t)item.tx * K * K;   // transposed: TX[x*K + a] = t[a][x]
-      const double* TY = dT + (size_t)item.ty * K * K;
       double tx[Q2][Q2], ty[Q2][Q2];
 #pragma unroll
       for (int ks = 0; ks < Q2; ++ks)
@@ -394,8 +431,8 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
         for (int t = 0; t < Q2; ++t) {
           const int r = 4 * ks + lk, cc = 4 * t + li;
           const bool ok = r < K && cc < K;
-          tx[ks][t] = ok ? TX[r * K + cc] : 0.0;
-          ty[ks][t] = ok ? TY[r * K + cc] : 0.0;
+          tx[ks][t] = ok ? TXs[r * K + cc] : 0.0;
+          ty[ks][t] = ok ? TYs[r * K + cc] : 0.0;
         }
       double d1[Q2][Q2];
 #pragma unroll
@@ -425,20 +462,22 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
             d2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], ty[ys][bt], d2[bt], 0, 0, 0);
 #pragma unroll
         for (int bt = 0; bt < Q2; ++bt)
-          Z2[((4 * at + lk) * KP + 4 * bt + li) * ZP2 + 4 * zq + lb] = d2[bt];
+          Z2[((4 * at + lk) * KP + 4 * bt + li) * KP + 4 * zq + lb] = d2[bt];
       }
     }
+    // the next triple's operator blocks travel while step 3 runs
+    const bool more = it + 1 < tr.end;
+    if (more) fetch_ops(it + 1, pre);
     __syncthreads();
     // ---- subtraction, step 3: z-contraction with -c t_z
     if (with_sub) {
-      const double* TZ = dT + (size_t)item.tz * K * K;
       double tz[Q2][Q2];
 #pragma unroll
       for (int ks = 0; ks < Q2; ++ks)
 #pragma unroll
         for (int t = 0; t < Q2; ++t) {
           const int r = 4 * ks + lk, cc = 4 * t + li;
-          tz[ks][t] = (r < K && cc < K) ? -cmu * TZ[r * K + cc] : 0.0;
+          tz[ks][t] = (r < K && cc < K) ? -cmu * TZs[r * K + cc] : 0.0;
         }
 #pragma unroll
       for (int e = 0; e < S3_PER_WAVE; ++e) {
@@ -447,7 +486,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
           const int at3 = p / Q2, bt3 = p % Q2;
 #pragma unroll
           for (int zs = 0; zs < Q2; ++zs) {
-            double a = Z2[((4 * at3 + lb) * KP + 4 * bt3 + li) * ZP2 + 4 * zs + lk];
+            double a = Z2[((4 * at3 + lb) * KP + 4 * bt3 + li) * KP + 4 * zs + lk];
 #pragma unroll
             for (int ct = 0; ct < Q2; ++ct)
               sacc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, tz[zs][ct], sacc[e][ct], 0, 0, 0);
@@ -456,26 +495,29 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
       }
     }
     // ---- step 3: z-contraction into the register accumulators
-    double rz[Q][Q];
+    {
+      double rz[Q][Q];
 #pragma unroll
-    for (int ks = 0; ks < Q; ++ks)
+      for (int ks = 0; ks < Q; ++ks)
 #pragma unroll
-      for (int t = 0; t < Q; ++t) rz[ks][t] = cmu * RZ[(4 * ks + lk) * N + 4 * t + li];
+        for (int t = 0; t < Q; ++t) rz[ks][t] = cmu * RZs[(4 * ks + lk) * N + 4 * t + li];
 #pragma unroll
-    for (int e = 0; e < P3_PER_WAVE; ++e) {
-      const int p = (3 - wave) + 4 * e;
-      if (p < P3) {
-        const int at3 = p / Q, bt3 = p % Q;
+      for (int e = 0; e < P3_PER_WAVE; ++e) {
+        const int p = (3 - wave) + 4 * e;
+        if (p < P3) {
+          const int at3 = p / Q, bt3 = p % Q;
 #pragma unroll
-        for (int zs = 0; zs < Q; ++zs) {
-          double a = Zs[((4 * at3 + lb) * N + 4 * bt3 + li) * ZP + 4 * zs + lk];
+          for (int zs = 0; zs < Q; ++zs) {
+            double a = Zs[((4 * at3 + lb) * N + 4 * bt3 + li) * N + 4 * zs + lk];
 #pragma unroll
-          for (int ct = 0; ct < Q; ++ct)
-            acc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rz[zs][ct], acc[e][ct], 0, 0, 0);
+            for (int ct = 0; ct < Q; ++ct)
+              acc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rz[zs][ct], acc[e][ct], 0, 0, 0);
+          }
         }
       }
     }
-    __syncthreads();
+    __syncthreads();   // Zs, Z2 and Os are free
+    if (more) store_ops(pre);
   }
   // ---- write the children block of the target
 #pragma unroll
@@ -485,7 +527,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
       const int at3 = p / Q, bt3 = p % Q;
       const int a = 4 * at3 + lb, b = 4 * bt3 + lk;
       if (tr.partial >= 0) {
-        double* dst = partials + (size_t)tr.partial * (N * N2 + K3);
+        double* dst = partials + (size_t)tr.partial * (N3 + K3);
 #pragma unroll
         for (int ct = 0; ct < Q; ++ct) dst[(a * N + b) * N + 4 * ct + li] = acc[e][ct];
       } else {
@@ -509,7 +551,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
           const int c = 4 * ct + li;
           if (a < K && b < K && c < K) {
             if (tr.partial >= 0)
-              partials[(size_t)tr.partial * (N * N2 + K3) + N * N2 + (a * K + b) * K + c] = sacc[e][ct];
+              partials[(size_t)tr.partial * (N3 + K3) + N3 + (a * K + b) * K + c] = sacc[e][ct];
             else
               subbuf[(size_t)tr.sub * K3 + (a * K + b) * K + c] = sacc[e][ct];
           }
