@@ -1,14 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark of the separated-operator apply on one MI355X.
 
-One step = one pass of the whole hot path over one synthetic function: filter-up with
-block norms, norm screening and planning, transform-and-accumulate, sum-down, and the
-norm2 reduction of the result.  Inputs (the projected function and the operator with its
-block cache, built during warm-up) are resident in HBM when the timed region starts.
+One step = one pass of the whole hot path over one synthetic function (or batch): filter-up
+with block norms, norm screening and planning, transform-and-accumulate, sum-down, and the
+norm2 reduction of the result.  Inputs (the projected functions and the operators with
+their block caches, built during warm-up) are resident in HBM when the timed region starts.
 
 Prints one JSON line: useful GFLOP/s (sum over kept triples of 6(2k)^4 + 6k^4 [n>0]),
 boxes/s, the roofline of the dominant kernel (timed with HIP events on the library's
-stream) and the FP64 oracle timed on a bounded sample on the host cores.
+stream) and the FP64 oracle timed on a bounded sample on the host cores.  The mixed
+workload (low-precision tier for triples with eta < 1e-3 thresh) also times the all-FP64
+path on the same input and reports the difference between the two results.
 """
 import argparse
 import json
@@ -24,6 +26,7 @@ if ROOT not in sys.path:
 import mra_workloads as W  # noqa: E402
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 (vector and matrix), AMD published
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix, AMD published
 METRIC = "useful operator-apply GFLOP/s and boxes/s, mixed-prec batched vs FP64 @ err≤10*thresh"
 
 
@@ -33,7 +36,8 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="coulomb_k10",
-                   choices=["coulomb_k10", "coulomb_k12_fp64", "bsh_batch_k10"])
+                   choices=["coulomb_k10", "coulomb_k12_fp64", "coulomb_k12_mixed",
+                            "bsh_batch_k10"])
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="approximate CPU work of the oracle baseline sample (0 = skip)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -62,8 +66,9 @@ def cpu_baseline(name, budget_s):
     from oracle.fit import coulomb_fit, cell_r_hi
     from oracle.projection import GaussianSum, project_adaptive
 
-    w = W.WORKLOADS[name]
-    c, a, x = W.coulomb_inputs(name, 0)
+    base = "coulomb_k12_mixed" if name.startswith("coulomb_k12") else name
+    w = W.WORKLOADS[base]
+    c, a, x = W.coulomb_inputs(base, 0)
     fo = project_adaptive(GaussianSum(c, a, x), w["k"], w["thresh"], W.CELL, w["initial_level"], 20)
     cc, tt = coulomb_fit(w["r_lo"], w["eps"], cell_r_hi(*W.CELL))
     op = SeparatedOperator(cc, tt)
@@ -103,7 +108,7 @@ def setup(ctx, name):
                "tau_drop": w["tau_rel"] * w["thresh"], "precision": "fp64",
                "launch": "one batched apply (all functions per kernel launch)"}
         return funcs, ops, w["tau_rel"] * w["thresh"], w["k"], cfg
-    base = "coulomb_k12_mixed" if name == "coulomb_k12_fp64" else name
+    base = "coulomb_k12_mixed" if name.startswith("coulomb_k12") else name
     w = W.WORKLOADS[base]
     c, a, x = W.coulomb_inputs(base, 0)
     f = ctx.project(c, a, x, w["k"], w["thresh"], initial_level=w["initial_level"])
@@ -111,6 +116,9 @@ def setup(ctx, name):
     cfg = {"workload": name, "k": w["k"], "thresh": w["thresh"], "gaussians": w["n_gauss"],
            "operator": "coulomb", "terms": int(op.terms()[0].size), "eps_fit": w["eps"],
            "r_lo": w["r_lo"], "tau_drop": w["tau_rel"] * w["thresh"], "precision": "fp64"}
+    if name == "coulomb_k12_mixed":
+        cfg["precision"] = "fp64 + bf16 tier (eta < tau_tier), fp32 accumulation"
+        cfg["tau_tier"] = w["tier_rel"] * w["thresh"]
     return [f], [op], w["tau_rel"] * w["thresh"], w["k"], cfg
 
 
@@ -146,38 +154,61 @@ def main():
 
     ctx = M.Context(0, W.CELL)
     funcs, ops, tau, k, cfg = setup(ctx, args.workload)
+    tier = cfg.get("tau_tier", 0.0)
 
-    def step():
+    def step(tau_tier, keep=False):
         if len(funcs) == 1:
-            gs = [ctx.apply(ops[0], funcs[0], tau_drop=tau)]
+            gs = [ctx.apply(ops[0], funcs[0], tau_drop=tau, tau_tier=tau_tier)]
         else:
-            gs = ctx.apply_batch(ops, funcs, tau_drop=tau)
+            gs = ctx.apply_batch(ops, funcs, tau_drop=tau, tau_tier=tau_tier)
         st = ctx.last_stats()
         nrm = [ctx.norm2(g) for g in gs]
+        if keep:
+            return st, nrm, gs
         for g in gs:
             g.free()
         return st, nrm
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for _ in range(args.steps):
-        st, nrm = step()
-        stats.append(st)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    def timed(tau_tier):
+        for _ in range(args.warmup):
+            step(tau_tier)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = []
+        for _ in range(args.steps):
+            st, nrm = step(tau_tier)
+            stats.append(st)
+        torch.cuda.synchronize()
+        return stats, nrm, time.perf_counter() - t0
+
+    stats, nrm, elapsed = timed(tier)
+    fp64_cmp = None
+    if tier > 0:
+        # the all-FP64 path on the same input, and the difference of the two results
+        st64, _, el64 = timed(0.0)
+        _, _, g_mix = step(tier, keep=True)
+        _, _, g_64 = step(0.0, keep=True)
+        import numpy as np
+        km, cm = g_mix[0].export()
+        k6, c6 = g_64[0].export()
+        assert np.array_equal(km, k6)
+        fp64_cmp = {"value": sum(s["useful_flops"] for s in st64) / el64 / 1e9,
+                    "ms_per_step": el64 / args.steps * 1e3,
+                    "ms_main_kernel": sum(s["ms_main_kernel"] for s in st64) / len(st64),
+                    "speedup_mixed_vs_fp64": el64 / elapsed,
+                    "rel_l2_mixed_vs_fp64": float(np.linalg.norm(cm - c6) / np.linalg.norm(c6))}
 
     flops = sum(s["useful_flops"] for s in stats)
     # the main kernel applies the children blocks and (for k = 8, 10, 12) the fused level-n
     # subtraction, so its algorithmic work is the full useful flop count of the step
     fused = k in (8, 10, 12)
-    kernel_flops = stats[0]["useful_flops"] if fused else stats[0]["triples"] * 6.0 * (2 * k) ** 4
+    kernel_flops = (stats[0]["useful_flops"] - stats[0]["flops_low"] if fused
+                    else (stats[0]["triples"] - stats[0]["triples_low"]) * 6.0 * (2 * k) ** 4)
     main_ms = sum(s["ms_main_kernel"] for s in stats) / len(stats)
     kname = {8: "apply_ns_mfma_kernel<8>", 10: "apply_ns_mfma_kernel<10>",
              12: "apply_ns_mfma_big_kernel<12>"}.get(k, "apply_ns_kernel<%d>" % k)
     achieved = kernel_flops / (main_ms * 1e-3) / 1e12
+    low_ms = sum(s["ms_low_kernel"] for s in stats) / len(stats)
     out = {
         "metric": METRIC,
         "value": flops / elapsed / 1e9,
@@ -204,7 +235,20 @@ def main():
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(kname)},
     }
-    if args.cpu_seconds > 0 and args.workload == "coulomb_k10":
+    if tier > 0:
+        s0 = stats[0]
+        # the BF16 kernel evaluates 7 mode products of (2k)^3 x 2k per triple (E R R + P E R
+        # + P P E with the shared R_z and E_z products) and writes nothing but the target
+        low_alg = s0["triples_low"] * 14.0 * (2 * k) ** 4
+        out["tiers"] = {"triples_fp64": s0["triples"] - s0["triples_low"],
+                        "triples_low": s0["triples_low"],
+                        "useful_flop_fraction_low": s0["flops_low"] / s0["useful_flops"],
+                        "eta_low_sum": s0["eta_low"], "ms_low_kernel": low_ms,
+                        "low_kernel": "apply_low_kernel<%d>" % k,
+                        "low_kernel_tflops_executed": low_alg / (low_ms * 1e-3) / 1e12 if low_ms > 0 else None,
+                        "low_kernel_frac_bf16_peak": (low_alg / (low_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS) if low_ms > 0 else None}
+        out["fp64_path"] = fp64_cmp
+    if args.cpu_seconds > 0 and args.workload.startswith("coulomb"):
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(out))
 

@@ -74,17 +74,31 @@ typedef struct {
 #define MRA_FORM_NONSTANDARD 0
 #define MRA_FORM_STANDARD 1
 
+#define MRA_LOW_NONE 0
+#define MRA_LOW_BF16 1
+
 /* Apply parameters.
  *  form         MRA_FORM_NONSTANDARD: telescoped non-standard form of Sec. 2.2 on an
  *               adaptive tree; MRA_FORM_STANDARD: level-n operator P^n T P^n on a uniform
  *               tree with displacements |delta|_inf <= disp_radius, no screening.
  *  tau_drop     non-standard form: a (box, displacement, term) triple is applied iff its
  *               norm bound eta = |c_mu| N(delta) ||B_P||_F is >= tau_drop.
- *  disp_radius  standard form only. */
+ *  disp_radius  standard form only.
+ *  tau_tier     non-standard form, levels n > 0: a kept triple with eta < tau_tier runs in
+ *               the low-precision tier (0: every triple runs in FP64).  The low tier
+ *               evaluates the triple's whole contribution c_mu [(R x R x R) - (P x P x P)] B_P,
+ *               P = H^T t H, in the cancellation-free form
+ *               E x R x R + P x E x R + P x P x E (E = R - P, Sec. 2.2 two-scale relation),
+ *               so its rounding error is a small multiple of u_low * eta.
+ *  low_precision MRA_LOW_BF16: BF16 inputs and operator blocks, FP32 accumulation per
+ *               target, FP64 addition into the result (built for k = 10, 12, 14).
+ *               Ignored when tau_tier == 0. */
 typedef struct {
   int form;
   int disp_radius;
   double tau_drop;
+  double tau_tier;
+  int low_precision;
 } mra_apply_params;
 
 /* Counters of the last mra_apply on a context. */
@@ -100,6 +114,10 @@ typedef struct {
   double ms_apply;        /* device time of the transform-and-accumulate kernels     */
   double ms_sumdown;      /* device time of sum-down                                 */
   double ms_main_kernel;  /* device time of the non-standard (or standard) main kernel */
+  int64_t triples_low;    /* triples run in the low-precision tier (part of triples)   */
+  double flops_low;       /* useful flops of those triples (part of useful_flops)      */
+  double eta_low;         /* sum of eta over those triples                             */
+  double ms_low_kernel;   /* device time of the low-precision transform kernel         */
 } mra_apply_stats;
 
 /* Create a context on HIP device `device` using HIP stream `stream` (NULL: the null

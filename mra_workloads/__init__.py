@@ -46,7 +46,8 @@ WORKLOADS = {
                         r_lo=1e-5, eps=1e-8, tau_rel=1e-4, initial_level=2),
     # mixed precision Coulomb, k=12, thresh 1e-8
     "coulomb_k12_mixed": dict(id=2, k=12, thresh=1e-8, n_gauss=4, a_lo=1.0, a_hi=1e3,
-                              r_lo=1e-5, eps=1e-8, tau_rel=1e-4, initial_level=2),
+                              r_lo=1e-5, eps=1e-8, tau_rel=1e-4, tier_rel=1e-3,
+                              initial_level=2),
     # batched bound-state Helmholtz, 64 functions of 1-8 Gaussians, k=10
     "bsh_batch_k10": dict(id=3, k=10, thresh=1e-6, n_funcs=64, n_gauss_lo=1, n_gauss_hi=8,
                           a_lo=1.0, a_hi=1e3, r_lo=1e-5, eps=1e-8, tau_rel=1e-4,

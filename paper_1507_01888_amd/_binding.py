@@ -45,9 +45,13 @@ class ProjectParams(ctypes.Structure):
                 ("initial_level", ctypes.c_int), ("max_level", ctypes.c_int)]
 
 
+LOW_BF16 = 1
+
+
 class ApplyParams(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int), ("disp_radius", ctypes.c_int),
-                ("tau_drop", ctypes.c_double)]
+                ("tau_drop", ctypes.c_double), ("tau_tier", ctypes.c_double),
+                ("low_precision", ctypes.c_int)]
 
 
 class ApplyStats(ctypes.Structure):
@@ -56,7 +60,9 @@ class ApplyStats(ctypes.Structure):
                 ("out_leaves", ctypes.c_int64), ("useful_flops", ctypes.c_double),
                 ("ms_filter", ctypes.c_double), ("ms_plan", ctypes.c_double),
                 ("ms_apply", ctypes.c_double), ("ms_sumdown", ctypes.c_double),
-                ("ms_main_kernel", ctypes.c_double)]
+                ("ms_main_kernel", ctypes.c_double), ("triples_low", ctypes.c_int64),
+                ("flops_low", ctypes.c_double), ("eta_low", ctypes.c_double),
+                ("ms_low_kernel", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -281,15 +287,16 @@ class Context:
         return Operator(self, h)
 
     # -- apply and reductions
-    def apply(self, op, f, form="nonstandard", tau_drop=0.0, disp_radius=1):
+    def apply(self, op, f, form="nonstandard", tau_drop=0.0, disp_radius=1, tau_tier=0.0):
+        """op(f).  tau_tier > 0: triples at levels n > 0 with eta < tau_tier run in BF16."""
         p = ApplyParams(FORM_STANDARD if form == "standard" else FORM_NONSTANDARD,
-                        disp_radius, tau_drop)
+                        disp_radius, tau_drop, tau_tier, LOW_BF16)
         h = ctypes.c_void_p()
         self._check(self._lib.mra_apply(self.h, op.h, f.h, ctypes.byref(p), ctypes.byref(h)),
                     "mra_apply")
         return Function(self, h)
 
-    def apply_batch(self, ops, funcs, tau_drop=0.0):
+    def apply_batch(self, ops, funcs, tau_drop=0.0, tau_tier=0.0):
         """[op_i(f_i)] in one batched pass (non-standard form)."""
         n = len(funcs)
         if len(ops) != n:
@@ -297,7 +304,7 @@ class Context:
         oarr = (ctypes.c_void_p * n)(*[o.h.value for o in ops])
         farr = (ctypes.c_void_p * n)(*[f.h.value for f in funcs])
         outs = (ctypes.c_void_p * n)()
-        p = ApplyParams(FORM_NONSTANDARD, 1, tau_drop)
+        p = ApplyParams(FORM_NONSTANDARD, 1, tau_drop, tau_tier, LOW_BF16)
         self._check(self._lib.mra_apply_batch(self.h, n, oarr, farr, ctypes.byref(p), outs),
                     "mra_apply_batch")
         return [Function(self, ctypes.c_void_p(outs[i])) for i in range(n)]

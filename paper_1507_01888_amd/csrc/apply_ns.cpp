@@ -4,12 +4,14 @@
 //   1. filter-up (device): s_P and ||B_P||_F^2 of every refined box of every function, one
 //      launch per level for the whole batch; one copy of the norms to the host;
 //   2. screening (host, threads over (function, level, term) jobs): triples (P, delta, mu)
-//      with eta = |c_mu| N(delta) ||B_P||_F >= tau_drop and target inside the cell;
+//      with eta = |c_mu| N(delta) ||B_P||_F >= tau_drop and target inside the cell; at
+//      levels n > 0 a triple with eta < tau_tier goes to the low-precision tier;
 //   3. per function (threads over functions): targets grouped by a counting sort, the
 //      output tree (targets, their children, ancestors, closed under siblings) and the
 //      target-sorted work list; long lists are split over several workgroups;
 //   4. transform-and-accumulate (device): one launch for all children blocks, one for the
-//      sum of split partials, one for the level-n subtractions (all functions together);
+//      sum of split partials, one for the level-n subtractions (all functions together),
+//      one for the low-precision tier (which adds after the FP64 results);
 //   5. sum-down (device), one launch per level for the whole batch.
 #include <algorithm>
 #include <chrono>
@@ -86,6 +88,7 @@ struct Triple {
   int32_t src;     // index into f.interior
   int16_t mu;
   int16_t dx, dy, dz;
+  int8_t low;      // 1: low-precision tier
 };
 
 struct LevelData {
@@ -108,12 +111,13 @@ struct Plan {
   Func* out = nullptr;
   std::vector<const BlockEntry*> entry_tab;  // (level, mu) -> cache entry
   std::vector<NSItem> items;
-  int64_t ntriples = 0;
-  std::vector<TargetRange> tgt, tgt_sub;
-  double flops = 0.0;
+  std::vector<LowItem> low_items;
+  int64_t ntriples = 0, nlow = 0;
+  std::vector<TargetRange> tgt, tgt_sub, low_tgt;
+  double flops = 0.0, flops_low = 0.0, eta_low = 0.0;
 };
 
-void validate(const Plan& p, int64_t nR, int64_t nT) {
+void validate(const Plan& p, int64_t nR, int64_t nT, int64_t nL, int64_t nslots) {
   const int64_t nin = p.f->nodes(), nout = p.out->nodes();
   auto bad = [](const char* what) {
     fail(MRA_E_INVALID, std::string("internal plan error: ") + what);
@@ -130,6 +134,16 @@ void validate(const Plan& p, int64_t nR, int64_t nT) {
   for (const TargetRange& r : p.tgt) {
     if (r.node < 0 || r.node >= nout || r.fc < 0 || r.fc + 8 > nout) bad("target node");
     if (r.beg < 0 || r.end < r.beg || r.end > (int32_t)p.items.size()) bad("item range");
+  }
+  for (const LowItem& it : p.low_items) {
+    if (it.slot < 0 || it.slot >= nslots) bad("low-tier source block");
+    if (it.mu < 0 || it.mu >= (int)p.op->c.size()) bad("term index");
+    if (it.rx < 0 || it.rx >= nL || it.ry < 0 || it.ry >= nL || it.rz < 0 || it.rz >= nL)
+      bad("low-tier block");
+  }
+  for (const TargetRange& r : p.low_tgt) {
+    if (r.node < 0 || r.node >= nout || r.fc < 0 || r.fc + 8 > nout) bad("target node");
+    if (r.beg < 0 || r.end < r.beg || r.end > (int32_t)p.low_items.size()) bad("item range");
   }
 }
 
@@ -178,115 +192,179 @@ struct Unit {
   std::vector<Triple> sorted;
   std::vector<uint64_t> tcodes;        // ascending
   std::vector<int64_t> toff;           // tcodes.size() + 1
+  std::vector<int64_t> tmid;           // per target: first low-tier triple
   std::vector<NSItem> items;
-  std::vector<TargetRange> tgt;
-  double flops = 0.0;
+  std::vector<LowItem> low_items;
+  std::vector<TargetRange> tgt, low_tgt;
+  int64_t nlow = 0;
+  double flops = 0.0, flops_low = 0.0, eta_low = 0.0;
 };
 
 void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const LevelData& L) {
   size_t m = 0;
   for (size_t j = u.jb; j < u.je; ++j) m += jobout[j].size();
-  // distinct targets
-  std::vector<uint64_t> codes;
-  codes.reserve(m / 4 + 16);
-  for (size_t j = u.jb; j < u.je; ++j)
-    for (const Triple& t : jobout[j]) codes.push_back(t.tcode);
-  std::sort(codes.begin(), codes.end());
-  codes.erase(std::unique(codes.begin(), codes.end()), codes.end());
-  u.tcodes = codes;
-  const int64_t nt = (int64_t)codes.size(), np = L.np;
-  if (nt * np > (int64_t)1 << 22) {
-    // large unit: comparison sort on (target, source, term)
+  // composite key (target code, tier, source rank); an LSD radix sort on it is stable, and
+  // the jobs of a unit are in ascending term order, so terms stay ascending per source
+  int sbits = 1;
+  while (((int64_t)1 << sbits) <= L.np) ++sbits;
+  const int bits = 3 * u.n + 1 + sbits;
+  if (bits > 64) {   // very deep level with many boxes: stable comparison sort
     u.sorted.clear();
     u.sorted.reserve(m);
     for (size_t j = u.jb; j < u.je; ++j)
       u.sorted.insert(u.sorted.end(), jobout[j].begin(), jobout[j].end());
-    std::sort(u.sorted.begin(), u.sorted.end(), [](const Triple& a, const Triple& b) {
+    std::stable_sort(u.sorted.begin(), u.sorted.end(), [](const Triple& a, const Triple& b) {
       if (a.tcode != b.tcode) return a.tcode < b.tcode;
-      if (a.src != b.src) return a.src < b.src;
-      return a.mu < b.mu;
+      if (a.low != b.low) return a.low < b.low;
+      return a.src < b.src;
     });
-    u.toff.assign(nt + 1, 0);
-    int64_t r = 0;
+    u.tcodes.clear();
+    u.toff.clear();
+    u.tmid.clear();
     for (size_t q = 0; q < m; ++q) {
-      while (u.sorted[q].tcode != codes[r]) u.toff[++r] = (int64_t)q;
+      const Triple& t = u.sorted[q];
+      if (q == 0 || t.tcode != u.sorted[q - 1].tcode) {
+        u.tcodes.push_back(t.tcode);
+        u.toff.push_back((int64_t)q);
+        u.tmid.push_back(-1);
+      }
+      if (t.low && u.tmid.back() < 0) u.tmid.back() = (int64_t)q;
     }
-    while (r < nt) u.toff[++r] = (int64_t)m;
+    u.toff.push_back((int64_t)m);
+    for (size_t r = 0; r < u.tmid.size(); ++r)
+      if (u.tmid[r] < 0) u.tmid[r] = u.toff[r + 1];
     return;
   }
-  // counting sort on (target rank, source) — stable, so terms stay ascending
-  std::vector<int64_t> cnt((size_t)nt * np + 1, 0);
-  std::vector<int64_t> key(m);
-  size_t q = 0;
-  for (size_t j = u.jb; j < u.je; ++j)
-    for (const Triple& t : jobout[j]) {
-      int64_t r = std::lower_bound(codes.begin(), codes.end(), t.tcode) - codes.begin();
-      int64_t kk = r * np + (t.src - L.ib);
-      key[q++] = kk;
-      ++cnt[kk + 1];
+  const uint64_t cmask = (1ULL << (3 * u.n)) - 1;
+  std::vector<uint64_t> key(m), key2(m);
+  std::vector<uint32_t> idx(m), idx2(m);
+  std::vector<const Triple*> ptr(m);
+  {
+    size_t q = 0;
+    for (size_t j = u.jb; j < u.je; ++j)
+      for (const Triple& t : jobout[j]) {
+        key[q] = ((t.tcode & cmask) << (1 + sbits)) | ((uint64_t)t.low << sbits) |
+                 (uint64_t)(t.src - L.ib);
+        idx[q] = (uint32_t)q;
+        ptr[q] = &t;
+        ++q;
+      }
+  }
+  constexpr int RB = 11;
+  std::vector<uint32_t> cnt(1u << RB);
+  for (int sh = 0; sh < bits; sh += RB) {
+    std::fill(cnt.begin(), cnt.end(), 0u);
+    for (size_t q = 0; q < m; ++q) ++cnt[(key[q] >> sh) & ((1u << RB) - 1)];
+    uint32_t run = 0;
+    for (auto& c : cnt) {
+      uint32_t v = c;
+      c = run;
+      run += v;
     }
-  for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
-  u.toff.assign(nt + 1, 0);
-  for (int64_t r = 0; r <= nt; ++r) u.toff[r] = cnt[r * np];
+    for (size_t q = 0; q < m; ++q) {
+      uint32_t d = cnt[(key[q] >> sh) & ((1u << RB) - 1)]++;
+      key2[d] = key[q];
+      idx2[d] = idx[q];
+    }
+    key.swap(key2);
+    idx.swap(idx2);
+  }
   u.sorted.resize(m);
-  q = 0;
-  for (size_t j = u.jb; j < u.je; ++j)
-    for (const Triple& t : jobout[j]) u.sorted[cnt[key[q++]]++] = t;
+  u.tcodes.clear();
+  u.toff.clear();
+  u.tmid.clear();
+  const uint64_t lev = (uint64_t)u.n << 58;
+  uint64_t last = ~0ULL;
+  for (size_t q = 0; q < m; ++q) {
+    const Triple& t = *ptr[idx[q]];
+    u.sorted[q] = t;
+    const uint64_t code = key[q] >> (1 + sbits);
+    if (code != last) {
+      u.tcodes.push_back(lev | code);
+      u.toff.push_back((int64_t)q);
+      u.tmid.push_back(-1);
+      last = code;
+    }
+    if (t.low && u.tmid.back() < 0) u.tmid.back() = (int64_t)q;
+  }
+  u.toff.push_back((int64_t)m);
+  for (size_t r = 0; r < u.tmid.size(); ++r)
+    if (u.tmid[r] < 0) u.tmid[r] = u.toff[r + 1];
 }
 
-void unit_items(Unit& u, const Plan& p) {
+// Work items of one unit: per target the FP64 triples (NSItem) and the low-tier triples
+// (LowItem, source block addressed by its filter-up slot).
+void unit_items(Unit& u, const Plan& p, const LevelData& L, const std::vector<int64_t>& slot) {
   const Func& f = *p.f;
   const Func& out = *p.out;
   const int k = f.k, n = u.n;
   const int M = (int)p.op->c.size();
   const double f_ns = 6.0 * std::pow(2.0 * k, 4), f_sub = 6.0 * std::pow((double)k, 4);
-  u.items.resize(u.sorted.size());
-  u.tgt.resize(u.tcodes.size());
-  u.flops = (double)u.sorted.size() * (f_ns + (n > 0 ? f_sub : 0.0));
+  const double per = f_ns + (n > 0 ? f_sub : 0.0);
+  u.items.clear();
+  u.low_items.clear();
+  u.tgt.clear();
+  u.low_tgt.clear();
+  u.items.reserve(u.sorted.size());
+  u.flops = (double)u.sorted.size() * per;
   for (size_t r = 0; r < u.tcodes.size(); ++r) {
     uint64_t code = u.tcodes[r] & ((1ULL << 58) - 1);
     int64_t node = find_node(out, n, code);
+    const int32_t fc = out.first_child[node];
+    const int32_t b0 = (int32_t)u.items.size(), l0 = (int32_t)u.low_items.size();
+    for (int64_t q = u.toff[r]; q < u.toff[r + 1]; ++q) {
+      const Triple& t = u.sorted[q];
+      const BlockEntry& be = *p.entry_tab[(size_t)n * M + t.mu];
+      const int32_t rx = (int32_t)(be.r_base + t.dx + be.D);
+      const int32_t ry = (int32_t)(be.r_base + t.dy + be.D);
+      const int32_t rz = (int32_t)(be.r_base + t.dz + be.D);
+      if (!t.low) {
+        NSItem it;
+        it.src = f.interior[t.src];
+        it.src_fc = f.first_child[it.src];
+        it.mu = t.mu;
+        it.rx = rx;
+        it.ry = ry;
+        it.rz = rz;
+        it.tx = (int32_t)(be.t_base + t.dx + be.D);
+        it.ty = (int32_t)(be.t_base + t.dy + be.D);
+        it.tz = (int32_t)(be.t_base + t.dz + be.D);
+        u.items.push_back(it);
+      } else {
+        u.low_items.push_back({(int32_t)slot[t.src], (int32_t)t.mu, rx, ry, rz});
+        const int ax = std::abs(t.dx), ay = std::abs(t.dy), az = std::abs(t.dz);
+        const double N = (be.a[ax] + be.e[ax]) * (be.a[ay] + be.e[ay]) * (be.a[az] + be.e[az]) -
+                         be.a[ax] * be.a[ay] * be.a[az];
+        u.eta_low += std::fabs(p.op->c[t.mu]) * N * L.bn[t.src - L.ib];
+      }
+    }
+    const int32_t b1 = (int32_t)u.items.size(), l1 = (int32_t)u.low_items.size();
     // sub = 0 marks "has a level-n subtraction"; the slot is assigned when combining
-    u.tgt[r] = {0, (int32_t)node, out.first_child[node], (int32_t)u.toff[r], (int32_t)u.toff[r + 1],
-                -1, n > 0 ? 0 : -1};
+    if (b1 > b0) u.tgt.push_back({0, (int32_t)node, fc, b0, b1, -1, n > 0 ? 0 : -1});
+    if (l1 > l0) u.low_tgt.push_back({0, (int32_t)node, fc, l0, l1, -1, -1});
   }
-  for (size_t q = 0; q < u.sorted.size(); ++q) {
-    const Triple& t = u.sorted[q];
-    const BlockEntry& be = *p.entry_tab[(size_t)n * M + t.mu];
-    NSItem& it = u.items[q];
-    it.src = f.interior[t.src];
-    it.src_fc = f.first_child[it.src];
-    it.mu = t.mu;
-    it.rx = (int32_t)(be.r_base + t.dx + be.D);
-    it.ry = (int32_t)(be.r_base + t.dy + be.D);
-    it.rz = (int32_t)(be.r_base + t.dz + be.D);
-    it.tx = (int32_t)(be.t_base + t.dx + be.D);
-    it.ty = (int32_t)(be.t_base + t.dy + be.D);
-    it.tz = (int32_t)(be.t_base + t.dz + be.D);
-  }
+  u.nlow = (int64_t)u.low_items.size();
+  u.flops_low = (double)u.nlow * per;
 }
 
 }  // namespace
 
 void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
-                             const std::vector<Func*>& funcs, double tau,
+                             const std::vector<Func*>& funcs, double tau, double tau_tier,
                              const std::vector<Func*>& outs) {
   const int nf = (int)funcs.size();
   if (nf == 0) return;
   const int k = funcs[0]->k;
   const int K3 = k * k * k;
+  const bool tiers = tau_tier > 0.0;
+  const size_t XB = (size_t)4 * k * k * low_up(k);   // BF16 per mirrored children block
   std::vector<double> h0v, h1v;
   two_scale_filters(k, h0v, h1v);
-  DevArray<double> h0, h1;
-  h0.upload(ctx, h0v);
-  h1.upload(ctx, h1v);
 
   // ---- 1. filter-up for the whole batch
   hip_check(hipEventRecord(ctx->ev[0], ctx->stream), "event");
   std::vector<double*> coeff_in(nf);
   for (int i = 0; i < nf; ++i) coeff_in[i] = funcs[i]->coeff.p;
-  DevArray<double*> d_in_tab;
-  d_in_tab.upload(ctx, coeff_in);
   int maxlev = 0;
   for (Func* f : funcs) maxlev = std::max(maxlev, f->nlev);
   std::vector<NodeRef> fu_refs;
@@ -304,19 +382,28 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
     }
     fu_off[j + 1] = (int64_t)fu_refs.size();
   }
-  DevArray<NodeRef> d_fu;
-  d_fu.upload(ctx, fu_refs);
-  DevArray<double> d_bn2;
-  d_bn2.alloc(ctx, std::max<size_t>(1, fu_refs.size()));
+  Arena& A0 = ctx->arena[0];
+  A0.begin(ctx);
+  const size_t o_h0 = A0.put(h0v), o_h1 = A0.put(h1v), o_in = A0.put(coeff_in);
+  const size_t o_fu = A0.put(fu_refs);
+  const size_t o_bn2 = A0.scratch(std::max<size_t>(1, fu_refs.size()) * sizeof(double));
+  const size_t o_mir = A0.scratch(tiers ? fu_refs.size() * XB * sizeof(uint16_t) : 0);
+  A0.commit();
+  const double* h0p = A0.at<double>(o_h0);
+  const double* h1p = A0.at<double>(o_h1);
+  double* const* in_tab_d = A0.at<double*>(o_in);
+  const NodeRef* fu_d = A0.at<NodeRef>(o_fu);
+  double* bn2_d = A0.scr_at<double>(o_bn2);
+  uint16_t* mirror_d = tiers ? A0.scr_at<uint16_t>(o_mir) : nullptr;
   for (int j = 0; j < maxlev; ++j) {
     int64_t b = fu_off[j], e = fu_off[j + 1];
     if (e > b)
-      launch_filter_up(k, d_in_tab.p, d_fu.p + b, (int)(e - b), h0.p, h1.p, d_bn2.p + b,
-                       ctx->stream);
+      launch_filter_up(k, in_tab_d, fu_d + b, (int)(e - b), h0p, h1p, bn2_d + b,
+                       tiers ? mirror_d + (size_t)b * XB : nullptr, ctx->stream);
   }
   std::vector<double> bn2_all(fu_refs.size());
   if (!fu_refs.empty())
-    hip_check(hipMemcpyAsync(bn2_all.data(), d_bn2.p, fu_refs.size() * sizeof(double),
+    hip_check(hipMemcpyAsync(bn2_all.data(), bn2_d, fu_refs.size() * sizeof(double),
                              hipMemcpyDeviceToHost, ctx->stream),
               "hipMemcpyAsync D2H");
   hip_check(hipEventRecord(ctx->ev[1], ctx->stream), "event");
@@ -405,6 +492,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
           Job& jb = jobs[j];
           jb.be = &uops[u]->ensure(lv[jb.lev].n, jb.mu, jb.D);
         }
+        if (tiers) uops[u]->ensure_low();
       } catch (const Error& e) {
         errs[u] = e.msg;
       }
@@ -443,11 +531,13 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
           if (c * N * L.maxb < tau) continue;
           for (int64_t oi = 0; oi < L.np; ++oi) {
             int64_t p = L.order[oi];
-            if (!(c * N * L.bn[p] >= tau)) break;
+            const double eta = c * N * L.bn[p];
+            if (!(eta >= tau)) break;
             int64_t tx = L.px[p] + dx, ty = L.py[p] + dy, tz = L.pz[p] + dz;
             if (tx < 0 || ty < 0 || tz < 0 || tx >= nb || ty >= nb || tz >= nb) continue;
+            const int8_t low = (tiers && n > 0 && eta < tau_tier) ? 1 : 0;
             outv.push_back({((uint64_t)n << 58) | encode(n, tx, ty, tz), (int32_t)(L.ib + p),
-                            (int16_t)mu, (int16_t)dx, (int16_t)dy, (int16_t)dz});
+                            (int16_t)mu, (int16_t)dx, (int16_t)dy, (int16_t)dz, low});
           }
         }
   });
@@ -471,6 +561,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   parallel_for(units.size(), [&](size_t i, unsigned) {
     group_unit(units[i], jobout, lv[unit_lev[i]]);
   });
+  mark("group by target");
   std::vector<std::vector<Triple>>().swap(jobout);
   parallel_for((size_t)nf, [&](size_t i, unsigned) {
     std::vector<uint64_t> tc;
@@ -478,7 +569,10 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       if (u.fn == (int)i) tc.insert(tc.end(), u.tcodes.begin(), u.tcodes.end());
     build_output_tree(ctx, plans[i], tc);
   });
-  parallel_for(units.size(), [&](size_t i, unsigned) { unit_items(units[i], plans[units[i].fn]); });
+  mark("output trees");
+  parallel_for(units.size(), [&](size_t i, unsigned) {
+    unit_items(units[i], plans[units[i].fn], lv[unit_lev[i]], fu_index[units[i].fn]);
+  });
   // concatenate the units of each function in level order (jobs are function-major,
   // level-major, so units already are)
   for (Unit& u : units) {
@@ -491,17 +585,28 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       p.tgt.push_back(r);
       if (u.n > 0) p.tgt_sub.push_back(r);
     }
+    const int32_t lbase = (int32_t)p.low_items.size();
+    p.low_items.insert(p.low_items.end(), u.low_items.begin(), u.low_items.end());
+    for (TargetRange r : u.low_tgt) {
+      r.beg += lbase;
+      r.end += lbase;
+      p.low_tgt.push_back(r);
+    }
     p.flops += u.flops;
+    p.flops_low += u.flops_low;
+    p.eta_low += u.eta_low;
+    p.nlow += u.nlow;
     p.ntriples += (int64_t)u.sorted.size();
   }
-  mark("group + output tree + items");
+  mark("work items");
   // ---- 4. combine the batch
   std::vector<Op*> uniq_ops;
   for (Op* op : ops)
     if (std::find(uniq_ops.begin(), uniq_ops.end(), op) == uniq_ops.end()) uniq_ops.push_back(op);
   for (Op* op : uniq_ops) op->sync_device();
   std::vector<NSItem> items;
-  std::vector<TargetRange> tgt_sub, work;
+  std::vector<LowItem> low_items;
+  std::vector<TargetRange> tgt_sub, work, low_work;
   std::vector<SplitTarget> splits;
   std::vector<NodeRef> sd_refs;
   int out_maxlev = 0;
@@ -511,11 +616,23 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   const bool fused = ns_kernel_fuses_subtraction(k);
   int32_t npartials = 0, nsub = 0;
   std::vector<std::vector<int32_t>> sub_of_node(nf);
-  double flops = 0.0;
-  int64_t ntriples = 0, ntargets = 0, in_leaves = 0, out_nodes = 0, out_leaves = 0;
+  double flops = 0.0, flops_low = 0.0, eta_low = 0.0;
+  int64_t ntriples = 0, nlow = 0, ntargets = 0, in_leaves = 0, out_nodes = 0, out_leaves = 0;
   for (int i = 0; i < nf; ++i) {
     Plan& p = plans[i];
-    validate(p, (int64_t)p.op->dR_blocks, (int64_t)p.op->dT_blocks);
+    validate(p, (int64_t)p.op->dR_blocks, (int64_t)p.op->dT_blocks,
+             tiers ? (int64_t)p.op->dL_blocks : 0, (int64_t)fu_refs.size());
+    const int32_t lbase = (int32_t)low_items.size();
+    low_items.insert(low_items.end(), p.low_items.begin(), p.low_items.end());
+    for (TargetRange r : p.low_tgt) {
+      r.fn = i;
+      r.beg += lbase;
+      r.end += lbase;
+      low_work.push_back(r);
+    }
+    flops_low += p.flops_low;
+    eta_low += p.eta_low;
+    nlow += p.nlow;
     const int32_t base = (int32_t)items.size();
     items.insert(items.end(), p.items.begin(), p.items.end());
     sub_of_node[i].assign((size_t)p.out->nodes(), -1);
@@ -570,6 +687,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   };
   std::stable_sort(work.begin(), work.end(), by_len);
   std::stable_sort(tgt_sub.begin(), tgt_sub.end(), by_len);
+  std::stable_sort(low_work.begin(), low_work.end(), by_len);
   // sum-down entries, level-major over the batch
   std::vector<int64_t> sd_off(out_maxlev + 1, 0);
   for (int n = 0; n < out_maxlev; ++n) {
@@ -585,63 +703,73 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   // device pointer tables
   std::vector<double*> out_tab(nf);
   std::vector<const double*> r_tab(nf), t_tab(nf), c_tab(nf);
+  std::vector<const uint16_t*> l_tab(nf);
   for (int i = 0; i < nf; ++i) {
     Func& o = *plans[i].out;
     o.coeff.alloc(ctx, (size_t)o.nodes() * K3);
-    o.upload_structure();
     out_tab[i] = o.coeff.p;
     r_tab[i] = plans[i].op->dR.p;
     t_tab[i] = plans[i].op->dT.p;
     c_tab[i] = plans[i].op->d_c.p;
+    l_tab[i] = plans[i].op->dL.p;
   }
-  DevArray<double*> d_out_tab;
-  DevArray<const double*> d_r_tab, d_t_tab, d_c_tab;
-  d_out_tab.upload(ctx, out_tab);
-  d_r_tab.upload(ctx, r_tab);
-  d_t_tab.upload(ctx, t_tab);
-  d_c_tab.upload(ctx, c_tab);
-  DevArray<NSItem> d_items;
-  DevArray<TargetRange> d_work, d_sub;
-  DevArray<SplitTarget> d_splits;
-  DevArray<NodeRef> d_sd;
-  DevArray<double> d_partials;
-  d_items.upload(ctx, items);
-  d_work.upload(ctx, work);
-  d_sub.upload(ctx, tgt_sub);
-  d_splits.upload(ctx, splits);
-  d_sd.upload(ctx, sd_refs);
-  d_partials.alloc(ctx, (size_t)npartials * 9 * K3);   // (2k)^3 + k^3 per slot
-  DevArray<double> d_subbuf;
-  d_subbuf.alloc(ctx, (size_t)nsub * K3);
+  Arena& A1 = ctx->arena[1];
+  A1.begin(ctx);
+  const size_t o_out = A1.put(out_tab), o_r = A1.put(r_tab), o_t = A1.put(t_tab),
+               o_c = A1.put(c_tab), o_l = A1.put(l_tab), o_items = A1.put(items),
+               o_work = A1.put(work), o_sub = A1.put(tgt_sub), o_spl = A1.put(splits),
+               o_sd = A1.put(sd_refs), o_litems = A1.put(low_items), o_lwork = A1.put(low_work);
+  const size_t o_part = A1.scratch((size_t)npartials * 9 * K3 * sizeof(double));  // (2k)^3 + k^3
+  const size_t o_subb = A1.scratch((size_t)nsub * K3 * sizeof(double));
+  A1.commit();
+  double* const* out_tab_d = A1.at<double*>(o_out);
+  const double* const* r_tab_d = A1.at<const double*>(o_r);
+  const double* const* t_tab_d = A1.at<const double*>(o_t);
+  const double* const* c_tab_d = A1.at<const double*>(o_c);
+  const uint16_t* const* l_tab_d = A1.at<const uint16_t*>(o_l);
+  const NSItem* items_d = A1.at<NSItem>(o_items);
+  const TargetRange* work_d = A1.at<TargetRange>(o_work);
+  const TargetRange* sub_d = A1.at<TargetRange>(o_sub);
+  const SplitTarget* splits_d = A1.at<SplitTarget>(o_spl);
+  const NodeRef* sd_d = A1.at<NodeRef>(o_sd);
+  const LowItem* low_items_d = A1.at<LowItem>(o_litems);
+  const TargetRange* low_work_d = A1.at<TargetRange>(o_lwork);
+  double* partials_d = A1.scr_at<double>(o_part);
+  double* subbuf_d = A1.scr_at<double>(o_subb);
   mark("combine + uploads");
   double t_plan1 = now_ms();
 
   // ---- 5. device work
   for (int i = 0; i < nf; ++i) launch_zero(out_tab[i], plans[i].out->coeff.n, ctx->stream);
   hip_check(hipEventRecord(ctx->ev[2], ctx->stream), "event");
-  launch_apply_ns(k, d_in_tab.p, d_out_tab.p, d_items.p, d_work.p, (int)work.size(), d_r_tab.p,
-                  d_t_tab.p, d_c_tab.p, d_partials.p, d_subbuf.p, ctx->stream);
+  launch_apply_ns(k, in_tab_d, out_tab_d, items_d, work_d, (int)work.size(), r_tab_d,
+                  t_tab_d, c_tab_d, partials_d, subbuf_d, ctx->stream);
   hip_check(hipEventRecord(ctx->ev[3], ctx->stream), "event");
-  launch_reduce_partials(k, d_partials.p, d_out_tab.p, d_subbuf.p, d_splits.p,
+  launch_reduce_partials(k, partials_d, out_tab_d, subbuf_d, splits_d,
                          (int)splits.size(), ctx->stream);
-  launch_apply_std(k, d_in_tab.p, d_out_tab.p, d_items.p, d_sub.p, (int)tgt_sub.size(),
-                   d_t_tab.p, d_c_tab.p, -1.0, ctx->stream);
+  launch_apply_std(k, in_tab_d, out_tab_d, items_d, sub_d, (int)tgt_sub.size(),
+                   t_tab_d, c_tab_d, -1.0, ctx->stream);
+  hip_check(hipEventRecord(ctx->ev[6], ctx->stream), "event");
+  if (!low_work.empty())
+    launch_apply_low(k, mirror_d, out_tab_d, low_items_d, low_work_d,
+                     (int)low_work.size(), l_tab_d, c_tab_d, ctx->stream);
   hip_check(hipEventRecord(ctx->ev[4], ctx->stream), "event");
   for (int n = 0; n < out_maxlev; ++n) {
     int64_t b = sd_off[n], e = sd_off[n + 1];
     if (e > b)
-      launch_sum_down(k, d_out_tab.p, d_sd.p + b, (int)(e - b), d_subbuf.p, h0.p, h1.p,
+      launch_sum_down(k, out_tab_d, sd_d + b, (int)(e - b), subbuf_d, h0p, h1p,
                       ctx->stream);
   }
   hip_check(hipEventRecord(ctx->ev[5], ctx->stream), "event");
   ctx->sync();
   for (int i = 0; i < nf; ++i) plans[i].out->interior_valid = false;
 
-  float ms_f = 0, ms_a = 0, ms_s = 0, ms_main = 0;
+  float ms_f = 0, ms_a = 0, ms_s = 0, ms_main = 0, ms_low = 0;
   hip_check(hipEventElapsedTime(&ms_f, ctx->ev[0], ctx->ev[1]), "elapsed");
   hip_check(hipEventElapsedTime(&ms_a, ctx->ev[2], ctx->ev[4]), "elapsed");
   hip_check(hipEventElapsedTime(&ms_main, ctx->ev[2], ctx->ev[3]), "elapsed");
   hip_check(hipEventElapsedTime(&ms_s, ctx->ev[4], ctx->ev[5]), "elapsed");
+  hip_check(hipEventElapsedTime(&ms_low, ctx->ev[6], ctx->ev[4]), "elapsed");
   mra_apply_stats& st = ctx->stats;
   st = mra_apply_stats{};
   st.triples = ntriples;
@@ -655,6 +783,10 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   st.ms_apply = ms_a;
   st.ms_main_kernel = ms_main;
   st.ms_sumdown = ms_s;
+  st.triples_low = nlow;
+  st.flops_low = flops_low;
+  st.eta_low = eta_low;
+  st.ms_low_kernel = low_work.empty() ? 0.0 : ms_low;
 }
 
 // Filter-up of one function (used by mra_inner); returns nothing but marks it valid.
@@ -683,7 +815,7 @@ void filter_up_function(Ctx* ctx, Func& f) {
   for (size_t j = 0; j + 1 < off.size(); ++j)
     if (off[j + 1] > off[j])
       launch_filter_up(f.k, d_tab.p, d_refs.p + off[j], (int)(off[j + 1] - off[j]), h0.p, h1.p,
-                       d_bn2.p + off[j], ctx->stream);
+                       d_bn2.p + off[j], nullptr, ctx->stream);
   ctx->sync();
   f.interior_valid = true;
 }

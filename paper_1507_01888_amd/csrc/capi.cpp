@@ -60,6 +60,63 @@ void Ctx::dfree(void* p) {
 
 void Ctx::sync() { hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
 
+// ------------------------------------------------------------------------------ arena
+Arena::~Arena() {
+  if (host) (void)hipHostFree(host);
+  if (ctx) {
+    ctx->dfree(dev);
+    ctx->dfree(scr);
+  }
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t Arena::put_bytes(const void* src, size_t bytes) {
+  const size_t off = used;
+  const size_t end = align256(off + bytes);
+  if (end > host_cap) {
+    size_t cap = std::max<size_t>(end, host_cap + host_cap / 2);
+    cap = std::max<size_t>(cap, (size_t)1 << 20);
+    void* p = nullptr;
+    hip_check(hipHostMalloc(&p, cap, hipHostMallocDefault), "hipHostMalloc");
+    if (host) {
+      std::memcpy(p, host, used);
+      (void)hipHostFree(host);
+    }
+    host = static_cast<char*>(p);
+    host_cap = cap;
+  }
+  if (bytes) std::memcpy(host + off, src, bytes);
+  used = end;
+  pending.push_back({off, bytes});
+  return off;
+}
+
+size_t Arena::scratch(size_t bytes) {
+  const size_t off = scr_used;
+  scr_used = align256(off + bytes);
+  return off;
+}
+
+void Arena::commit() {
+  auto grow = [&](char*& buf, size_t& cap, size_t need) {
+    if (need <= cap) return;
+    ctx->sync();   // nothing may still use the old buffer
+    ctx->dfree(buf);
+    buf = nullptr;
+    cap = 0;
+    size_t c = std::max<size_t>(need, (size_t)1 << 20);
+    buf = static_cast<char*>(ctx->dalloc(c));
+    cap = c;
+  };
+  grow(dev, dev_cap, used);
+  grow(scr, scr_cap, scr_used);
+  if (used)
+    hip_check(hipMemcpyAsync(dev, host, used, hipMemcpyHostToDevice, ctx->stream),
+              "hipMemcpyAsync H2D");
+  pending.clear();
+}
+
 // ------------------------------------------------------------------------ block cache
 static void transpose_into(int m, const double* a, double* out) {
   for (int i = 0; i < m; ++i)
@@ -137,17 +194,100 @@ const BlockEntry& Op::ensure(int level, int mu, int D) {
   return e;
 }
 
+uint16_t bf16_bits(double v) {
+  const float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, sizeof u);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Slot s of a permuted row holds column 4g + j (j < 4) or 16 + 4g + j - 4 (j >= 4),
+// g = s / 8, j = s % 8: the row order of two stacked 16-row results of a BF16 matrix-core
+// product, so that such a result can be fed back as the contracted operand unchanged.
+static int low_perm(int s) {
+  const int g = s / 8, j = s % 8;
+  return j < 4 ? 4 * g + j : 16 + 4 * g + j - 4;
+}
+
+void Op::ensure_low() {
+  const int N = 2 * k, K2 = k * k, N2 = N * N, UP = low_up(k);
+  const size_t REC = low_record(k);
+  const size_t nb = hR.size() / N2;
+  if (hL_blocks >= nb) return;
+  std::vector<double> h0, h1;
+  two_scale_filters(k, h0, h1);
+  std::vector<double> H((size_t)k * N);   // H[i][X] = [h0 | h1]
+  for (int i = 0; i < k; ++i)
+    for (int X = 0; X < N; ++X) H[i * N + X] = X < k ? h0[i * k + X] : h1[i * k + X - k];
+  hL.resize(nb * REC);
+  const size_t first = hL_blocks;
+  auto one = [&](size_t b) {
+    std::vector<double> R(N2), P(N2), E(N2), Ht((size_t)N * k);
+    const double* RT = &hR[b * N2];   // RT[i][a] = R[a][i]
+    const double* tT = &hT[b * K2];   // tT[j][i] = t[i][j]
+    for (int a = 0; a < N; ++a)
+      for (int i = 0; i < N; ++i) R[a * N + i] = RT[i * N + a];
+    for (int X = 0; X < N; ++X)       // (H^T t)[X][j]
+      for (int j = 0; j < k; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < k; ++i) s += H[i * N + X] * tT[j * k + i];
+        Ht[X * k + j] = s;
+      }
+    for (int X = 0; X < N; ++X)
+      for (int Y = 0; Y < N; ++Y) {
+        double s = 0.0;
+        for (int j = 0; j < k; ++j) s += Ht[X * k + j] * H[j * N + Y];
+        P[X * N + Y] = s;
+        E[X * N + Y] = R[X * N + Y] - s;
+      }
+    const double* mats[3] = {R.data(), E.data(), P.data()};
+    uint16_t* rec = &hL[b * REC];
+    for (int m = 0; m < 3; ++m) {
+      uint16_t* u = rec + (size_t)m * N * UP;
+      uint16_t* v = rec + (size_t)3 * N * UP + (size_t)m * N * 32;
+      for (int row = 0; row < N; ++row) {
+        for (int col = 0; col < UP; ++col)
+          u[row * UP + col] = col < N ? bf16_bits(mats[m][row * N + col]) : 0;
+        for (int sl = 0; sl < 32; ++sl) {
+          const int col = low_perm(sl);
+          v[row * 32 + sl] = col < N ? bf16_bits(mats[m][row * N + col]) : 0;
+        }
+      }
+    }
+  };
+  const size_t count = nb - first;
+  const unsigned nthr = (unsigned)std::max<size_t>(
+      1, std::min<size_t>({(size_t)16, (size_t)std::max(1u, std::thread::hardware_concurrency()),
+                           count / 64 + 1}));
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nthr; ++t)
+    th.emplace_back([&, t] {
+      for (size_t b = first + t; b < nb; b += nthr) one(b);
+    });
+  for (size_t b = first; b < nb; b += nthr) one(b);
+  for (auto& t : th) t.join();
+  hL_blocks = nb;
+}
+
 void Op::sync_device() {
   const size_t N2 = (size_t)4 * k * k, K2 = (size_t)k * k;
   size_t nR = hR.size() / N2, nT = hT.size() / K2;
-  if (nR == dR_blocks && nT == dT_blocks) return;
+  if (nR == dR_blocks && nT == dT_blocks && hL_blocks == dL_blocks) return;
   // grow: re-upload everything (blocks are appended; kernels in flight use the old copy,
   // so synchronise before freeing it)
   ctx->sync();
-  dR.upload(ctx, hR);
-  dT.upload(ctx, hT);
-  dR_blocks = nR;
-  dT_blocks = nT;
+  if (nR != dR_blocks || nT != dT_blocks) {
+    dR.upload(ctx, hR);
+    dT.upload(ctx, hT);
+    dR_blocks = nR;
+    dT_blocks = nT;
+  }
+  if (hL_blocks != dL_blocks) {
+    std::vector<uint16_t> part(hL.begin(), hL.begin() + hL_blocks * low_record(k));
+    dL.upload(ctx, part);
+    dL_blocks = hL_blocks;
+  }
 }
 
 // ------------------------------------------------------------------------ helpers
@@ -244,7 +384,6 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
   d_items.upload(ctx, items);
   d_tgt.upload(ctx, tgt);
   out.coeff.alloc(ctx, (size_t)out.nodes() * k * k * k);
-  out.upload_structure();
   std::vector<const double*> in_tab{f.coeff.p}, t_tab{op.dT.p}, c_tab{op.d_c.p};
   std::vector<double*> out_tab{out.coeff.p};
   DevArray<const double*> d_in, d_t, d_c;
@@ -276,21 +415,26 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
 }
 
 // ------------------------------------------------------------------------ reductions
+// Fixed-order reduction over leaves: 256 workgroup partials, summed in order on the host.
+// la_dev (optional) is a device copy of la.
 static double reduce(Ctx* ctx, int k, const double* a, const double* b,
                      const std::vector<int32_t>& la, const std::vector<int32_t>* lb,
-                     const std::vector<double>* w, int mode) {
+                     const std::vector<double>* w, int mode, const int32_t* la_dev = nullptr) {
   if (la.empty()) return 0.0;
   const int nblocks = 256;
   DevArray<int32_t> d_la, d_lb;
-  DevArray<double> d_w, d_part;
-  d_la.upload(ctx, la);
+  DevArray<double> d_w;
+  if (!la_dev) {
+    d_la.upload(ctx, la);
+    la_dev = d_la.p;
+  }
   if (lb) d_lb.upload(ctx, *lb);
   if (w) d_w.upload(ctx, *w);
-  d_part.alloc(ctx, nblocks);
-  launch_leaf_reduce(k, a, b, d_la.p, lb ? d_lb.p : nullptr, w ? d_w.p : nullptr,
-                     (int)la.size(), mode, d_part.p, nblocks, ctx->stream);
+  if (!ctx->red_part) ctx->red_part = static_cast<double*>(ctx->dalloc(nblocks * sizeof(double)));
+  launch_leaf_reduce(k, a, b, la_dev, lb ? d_lb.p : nullptr, w ? d_w.p : nullptr,
+                     (int)la.size(), mode, ctx->red_part, nblocks, ctx->stream);
   std::vector<double> part(nblocks);
-  hip_check(hipMemcpyAsync(part.data(), d_part.p, nblocks * sizeof(double),
+  hip_check(hipMemcpyAsync(part.data(), ctx->red_part, nblocks * sizeof(double),
                            hipMemcpyDeviceToHost, ctx->stream),
             "hipMemcpyAsync D2H");
   ctx->sync();
@@ -360,6 +504,7 @@ mra_status mra_ctx_free(mra_ctx* ctx) {
   if (!ctx) return MRA_E_INVALID;
   for (auto& e : ctx->c.ev)
     if (e) (void)hipEventDestroy(e);
+  ctx->c.dfree(ctx->c.red_part);
   delete ctx;
   return MRA_OK;
 }
@@ -384,7 +529,6 @@ mra_status mra_project(mra_ctx* ctx, const mra_gaussian* g, int ng,
     std::vector<double> coeffs;
     project_gaussians(c, g, ng, p->k, p->thresh, p->initial_level, p->max_level, h->f, coeffs);
     h->f.coeff.upload(c, coeffs);
-    h->f.upload_structure();
     c->sync();
     *out = h.release();
   });
@@ -504,6 +648,21 @@ mra_status mra_op_free(mra_op* op) {
   return MRA_OK;
 }
 
+namespace {
+void check_nonstandard(int k, const mra_apply_params& p) {
+  using namespace mra;
+  if (k > 10 && k != 12)
+    fail(MRA_E_UNSUPPORTED, "non-standard apply is built for k <= 10 and k = 12");
+  if (!(p.tau_drop >= 0.0)) fail(MRA_E_INVALID, "tau_drop must be >= 0");
+  if (!(p.tau_tier >= 0.0)) fail(MRA_E_INVALID, "tau_tier must be >= 0");
+  if (p.tau_tier > 0.0) {
+    if (p.low_precision != MRA_LOW_BF16) fail(MRA_E_INVALID, "unknown low_precision");
+    if (!low_kernel_available(k))
+      fail(MRA_E_UNSUPPORTED, "the low-precision tier is built for k = 10, 12, 14");
+  }
+}
+}  // namespace
+
 mra_status mra_apply(mra_ctx* ctx, const mra_op* oph, const mra_func* fh,
                      const mra_apply_params* p, mra_func** out) {
   if (!ctx) return MRA_E_INVALID;
@@ -518,10 +677,8 @@ mra_status mra_apply(mra_ctx* ctx, const mra_op* oph, const mra_func* fh,
     if (p->form == MRA_FORM_STANDARD) {
       apply_standard(c, op, f, p->disp_radius, h->f);
     } else if (p->form == MRA_FORM_NONSTANDARD) {
-      if (f.k > 10 && f.k != 12)
-        fail(MRA_E_UNSUPPORTED, "non-standard apply is built for k <= 10 and k = 12");
-      if (!(p->tau_drop >= 0.0)) fail(MRA_E_INVALID, "tau_drop must be >= 0");
-      apply_nonstandard_batch(c, {&op}, {&f}, p->tau_drop, {&h->f});
+      check_nonstandard(f.k, *p);
+      apply_nonstandard_batch(c, {&op}, {&f}, p->tau_drop, p->tau_tier, {&h->f});
     } else {
       fail(MRA_E_INVALID, "unknown form");
     }
@@ -537,7 +694,6 @@ mra_status mra_apply_batch(mra_ctx* ctx, int n, const mra_op* const* ophs,
   MRA_TRY(c, {
     if (n < 1 || !ophs || !fhs || !p || !outs) fail(MRA_E_INVALID, "mra_apply_batch: bad arguments");
     if (p->form != MRA_FORM_NONSTANDARD) fail(MRA_E_UNSUPPORTED, "batches use the non-standard form");
-    if (!(p->tau_drop >= 0.0)) fail(MRA_E_INVALID, "tau_drop must be >= 0");
     std::vector<Op*> ops(n);
     std::vector<Func*> funcs(n);
     for (int i = 0; i < n; ++i) {
@@ -551,15 +707,14 @@ mra_status mra_apply_batch(mra_ctx* ctx, int n, const mra_op* const* ophs,
       for (int j = 0; j < i; ++j)
         if (funcs[j] == funcs[i]) fail(MRA_E_INVALID, "a function appears twice in the batch");
     }
-    if (funcs[0]->k > 10 && funcs[0]->k != 12)
-      fail(MRA_E_UNSUPPORTED, "non-standard apply is built for k <= 10 and k = 12");
+    check_nonstandard(funcs[0]->k, *p);
     std::vector<std::unique_ptr<mra_func>> hs(n);
     std::vector<Func*> outf(n);
     for (int i = 0; i < n; ++i) {
       hs[i].reset(new mra_func());
       outf[i] = &hs[i]->f;
     }
-    apply_nonstandard_batch(c, ops, funcs, p->tau_drop, outf);
+    apply_nonstandard_batch(c, ops, funcs, p->tau_drop, p->tau_tier, outf);
     for (int i = 0; i < n; ++i) outs[i] = hs[i].release();
   });
 }
@@ -571,7 +726,9 @@ mra_status mra_norm2(mra_ctx* ctx, const mra_func* fh, double* out) {
     if (!fh || !out) fail(MRA_E_INVALID, "mra_norm2: bad arguments");
     const Func& f = fh->f;
     if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
-    double s = reduce(c, f.k, f.coeff.p, nullptr, f.leaves, nullptr, nullptr, 0);
+    Func& fm = const_cast<mra_func*>(fh)->f;   // device leaf list is made on first use
+    double s = reduce(c, f.k, f.coeff.p, nullptr, f.leaves, nullptr, nullptr, 0,
+                      fm.device_leaves());
     *out = std::sqrt(s);
   });
 }

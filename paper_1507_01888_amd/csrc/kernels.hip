@@ -33,15 +33,31 @@ __global__ void zero_kernel(double* __restrict__ p, size_t n) {
   for (; i < n; i += stride) p[i] = 0.0;
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// FP64 -> FP32 -> BF16, both steps rounding to nearest even (bits of the BF16 value).
+__device__ inline uint32_t bf16_bits_dev(float v) {
+  return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)v);
+}
+__device__ inline uint32_t bf16_pair(float lo, float hi) {
+  return bf16_bits_dev(lo) | (bf16_bits_dev(hi) << 16);
+}
+
 // --------------------------------------------------------------------------- filter-up
 // The children block is read straight from the 8 child slabs; the z-contraction happens
 // on the fly (each thread owns (X, Y) rows), so LDS only holds the two partially filtered
-// tensors ((2k)^2 k and (2k) k^2 doubles).
+// tensors ((2k)^2 k and (2k) k^2 doubles).  With mirror != nullptr each row is also written
+// as BF16 (layout [X][Y][Z], Z padded with zeros to UP = 8 ceil(2k/8)) for the
+// low-precision tier.
 template <int K>
 __global__ __launch_bounds__(256) void filter_up_kernel(
     double* const* __restrict__ tab, const NodeRef* __restrict__ refs,
-    const double* __restrict__ h0, const double* __restrict__ h1, double* __restrict__ bnorm2) {
+    const double* __restrict__ h0, const double* __restrict__ h1, double* __restrict__ bnorm2,
+    uint16_t* __restrict__ mirror) {
   constexpr int N = 2 * K, K3 = K * K * K, KP1 = K + 1;
+  constexpr int UP = (N + 7) / 8 * 8;
   __shared__ double T1[N * N * KP1];   // [X][Y][m]
   __shared__ double T2[N * K * KP1];   // [X][j][m]
   __shared__ double H[K * N];
@@ -63,17 +79,34 @@ __global__ __launch_bounds__(256) void filter_up_kernel(
     const double* r0 = coeff + (size_t)(fc + ((bx << 2) | (by << 1))) * K3 + (i * K + j) * K;
     const double* r1 = r0 + K3;
     double t[K];
+    double row[UP];
 #pragma unroll
     for (int m = 0; m < K; ++m) t[m] = 0.0;
 #pragma unroll
+    for (int z = N; z < UP; ++z) row[z] = 0.0;
+#pragma unroll
     for (int z = 0; z < K; ++z) {
       const double v0 = r0[z], v1 = r1[z];
+      row[z] = v0;
+      row[K + z] = v1;
       sq += v0 * v0 + v1 * v1;
 #pragma unroll
       for (int m = 0; m < K; ++m) t[m] += H[m * N + z] * v0 + H[m * N + K + z] * v1;
     }
 #pragma unroll
     for (int m = 0; m < K; ++m) T1[(X * N + Y) * KP1 + m] = t[m];
+    if (mirror) {
+      u32x4* dst = reinterpret_cast<u32x4*>(mirror + (size_t)blockIdx.x * N * N * UP +
+                                            (size_t)(X * N + Y) * UP);
+#pragma unroll
+      for (int c = 0; c < UP / 8; ++c) {
+        u32x4 w;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          w[q] = bf16_pair((float)row[8 * c + 2 * q], (float)row[8 * c + 2 * q + 1]);
+        dst[c] = w;
+      }
+    }
   }
   red[tid] = sq;
   __syncthreads();
@@ -972,6 +1005,190 @@ __global__ __launch_bounds__(256) void leaf_reduce_kernel(
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// ------------------------------------------------------------- apply (low tier, BF16)
+// Triples whose norm bound eta is far below thresh.  Each adds its whole contribution to
+// the target's children block,
+//   c_mu [(R_x x R_y x R_z) - (P_x x P_y x P_z)] B_P,   P = H^T t H  (level n > 0),
+// which equals the FP64 path's children term plus the unfiltered level-n subtraction.
+// It is evaluated in the cancellation-free form
+//   E_x R_y R_z + P_x E_y R_z + P_x P_y E_z = E_x (R_y (R_z B)) + P_x (E_y (R_z B) + P_y (E_z B)),
+// E = R - P, so each rounding error is relative to a term whose norm is bounded by a part
+// of N(delta) = prod(a + e) - prod(a) (Sec. 2.2 decay of the difference operators).
+// Operands are BF16 (inputs rounded from FP64), products accumulate in FP32 on
+// v_mfma_f32_16x16x32_bf16, the target's block is added to the FP64 output once.
+//
+// Matrix-core layout (16x16x32): lane l = 16 g + r holds A[r][8g + j] and B[8g + j][r]
+// (j < 8) and receives D[4g + i][r] (i < 4).  Tensors are [a][b][c] (x, y, z), each index
+// < N = 2k <= 32, i.e. two 16-wide tiles.  For a fixed a, step z (contract c) takes the
+// source rows X[a][b][.] as A and R_z / E_z rows as B; its two row tiles (b < 16, b >= 16)
+// stacked lane-wise are the B operand of step y (contract b) if the contraction slots of
+// step y are permuted accordingly (the V layout of the operator records).  Step x (contract
+// a) needs all a of a column (b', c'): each wave handles pairs of a, writes the two results
+// of step y (R_y-part and E_y/P_y-part, scaled by c_mu, BF16) to LDS rows q = (b', c') with
+// a innermost, and after a barrier every wave contracts its share of the q tiles with
+// E_x and P_x, accumulating in registers over all triples of the target.
+template <int K>
+__global__ __launch_bounds__(256) void apply_low_kernel(
+    const uint16_t* __restrict__ mirror, double* const* __restrict__ out_tab,
+    const LowItem* __restrict__ items, const TargetRange* __restrict__ targets,
+    const uint16_t* const* __restrict__ l_tab, const double* const* __restrict__ c_tab) {
+  constexpr int N = 2 * K, N2 = N * N, K3 = K * K * K;
+  constexpr int UP = (N + 7) / 8 * 8;          // padded contraction length (U layout)
+  constexpr int XB = N * N * UP;               // BF16 per mirrored children block
+  constexpr int LU = N * UP, LV = N * 32, REC = 3 * LU + 3 * LV;
+  constexpr int NPAIR = N / 2, PPW = (NPAIR + 3) / 4;
+  constexpr int NQ = N2 / 16, QPW = (NQ + 3) / 4;
+  constexpr int TSZ = N2 * UP + N * 8;         // 16 bytes of padding after every N rows
+  static_assert(N > 16 && N <= 32 && N2 % 16 == 0, "two 16-wide tiles per index, even k");
+  __shared__ __attribute__((aligned(16))) uint16_t T1s[TSZ];
+  __shared__ __attribute__((aligned(16))) uint16_t T2s[TSZ];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const bool kin = 8 * g < UP;
+  const TargetRange tr = targets[blockIdx.x];
+  double* __restrict__ out = out_tab[tr.fn];
+  const uint16_t* __restrict__ L = l_tab[tr.fn];
+  const double* __restrict__ dc = c_tab[tr.fn];
+  const bf16x8 zero8 = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
+  auto ld8 = [&](const uint16_t* p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p)); };
+  // slots a in [N, UP) of the T rows are never written: clear everything once
+  for (int e = tid; e < TSZ / 8; e += 256) {
+    reinterpret_cast<u32x4*>(T1s)[e] = u32x4{0u, 0u, 0u, 0u};
+    reinterpret_cast<u32x4*>(T2s)[e] = u32x4{0u, 0u, 0u, 0u};
+  }
+  __syncthreads();
+
+  f32x4 acc[QPW][2];
+#pragma unroll
+  for (int e = 0; e < QPW; ++e)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) acc[e][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 xr[PPW][2][2];   // [pair of this wave][a in pair][b tile]: A operand of step z
+  int loaded = -1;
+  for (int it = tr.beg; it < tr.end; ++it) {
+    const LowItem item = items[it];
+    if (item.slot != loaded) {
+      const uint16_t* xb = mirror + (size_t)item.slot * XB;
+#pragma unroll
+      for (int p = 0; p < PPW; ++p)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            const int pair = wave + 4 * p, a = 2 * pair + s2, b = 16 * mt + r;
+            xr[p][s2][mt] = (pair < NPAIR && b < N && kin) ? ld8(xb + (a * N + b) * UP + 8 * g) : zero8;
+          }
+      loaded = item.slot;
+    }
+    const uint16_t* Lz = L + (size_t)item.rz * REC;
+    const uint16_t* Ly = L + (size_t)item.ry * REC;
+    const uint16_t* Lx = L + (size_t)item.rx * REC;
+    bf16x8 oz[2][2], oy[3][2], ox[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int row = 16 * t + r;
+      const bool ok = row < N, oku = ok && kin;
+      oz[0][t] = oku ? ld8(Lz + row * UP + 8 * g) : zero8;              // U(R_z)
+      oz[1][t] = oku ? ld8(Lz + LU + row * UP + 8 * g) : zero8;         // U(E_z)
+#pragma unroll
+      for (int m = 0; m < 3; ++m)                                       // V(R_y), V(E_y), V(P_y)
+        oy[m][t] = ok ? ld8(Ly + 3 * LU + m * LV + row * 32 + 8 * g) : zero8;
+      ox[0][t] = oku ? ld8(Lx + LU + row * UP + 8 * g) : zero8;         // U(E_x)
+      ox[1][t] = oku ? ld8(Lx + 2 * LU + row * UP + 8 * g) : zero8;     // U(P_x)
+    }
+    const float cmu = (float)dc[item.mu];
+    // ---- steps z and y for this wave's pairs of a
+#pragma unroll
+    for (int p = 0; p < PPW; ++p) {
+      const int pair = wave + 4 * p;
+      if (pair < NPAIR) {
+        f32x4 u[2][2][2], v[2][2][2];   // [a in pair][b' tile][c' tile]
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          f32x4 y1[2][2], y2[2][2];
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+              const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+              y1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[p][s2][mt], oz[0][nt], z4, 0, 0, 0);
+              y2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[p][s2][mt], oz[1][nt], z4, 0, 0, 0);
+            }
+#pragma unroll
+          for (int nt = 0; nt < 2; ++nt) {
+            bf16x8 b1, b2;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              b1[i] = (__bf16)y1[0][nt][i];
+              b1[4 + i] = (__bf16)y1[1][nt][i];
+              b2[i] = (__bf16)y2[0][nt][i];
+              b2[4 + i] = (__bf16)y2[1][nt][i];
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+              const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+              u[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[0][mt], b1, z4, 0, 0, 0);
+              v[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[1][mt], b1, z4, 0, 0, 0);
+              v[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[2][mt], b2, v[s2][mt][nt], 0, 0, 0);
+            }
+          }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int bp = 16 * mt + 4 * g + i, cp = 16 * nt + r;
+              if (bp < N && cp < N) {
+                const int off = (bp * N + cp) * UP + bp * 8 + 2 * pair;
+                *reinterpret_cast<uint32_t*>(&T1s[off]) =
+                    bf16_pair(cmu * u[0][mt][nt][i], cmu * u[1][mt][nt][i]);
+                *reinterpret_cast<uint32_t*>(&T2s[off]) =
+                    bf16_pair(cmu * v[0][mt][nt][i], cmu * v[1][mt][nt][i]);
+              }
+            }
+      }
+    }
+    __syncthreads();
+    // ---- step x: acc[a'][q] += E_x T1 + P_x T2 over this wave's q tiles
+#pragma unroll
+    for (int e = 0; e < QPW; ++e) {
+      const int qt = wave + 4 * e;
+      if (qt < NQ) {
+        const int q = 16 * qt + r, off = q * UP + (q / N) * 8 + 8 * g;
+        const bf16x8 t1 = kin ? ld8(T1s + off) : zero8;
+        const bf16x8 t2 = kin ? ld8(T2s + off) : zero8;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          acc[e][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ox[0][mt], t1, acc[e][mt], 0, 0, 0);
+          acc[e][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ox[1][mt], t2, acc[e][mt], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // ---- add the target's block to the FP64 output (each element owned by one lane)
+#pragma unroll
+  for (int e = 0; e < QPW; ++e) {
+    const int qt = wave + 4 * e;
+    if (qt < NQ) {
+      const int q = 16 * qt + r, bp = q / N, cp = q % N;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int ap = 16 * mt + 4 * g + i;
+          if (ap < N) {
+            const int child = ((ap / K) << 2) | ((bp / K) << 1) | (cp / K);
+            out[(size_t)(tr.fc + child) * K3 + ((ap % K) * K + (bp % K)) * K + (cp % K)] +=
+                (double)acc[e][mt][i];
+          }
+        }
+    }
+  }
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------- launchers
@@ -1006,11 +1223,33 @@ void launch_zero(double* p, size_t n, hipStream_t s) {
 }
 
 void launch_filter_up(int k, double* const* coeff_tab, const NodeRef* refs, int count,
-                      const double* h0, const double* h1, double* bnorm2, hipStream_t s) {
+                      const double* h0, const double* h1, double* bnorm2, uint16_t* mirror,
+                      hipStream_t s) {
   if (count <= 0) return;
   MRA_DISPATCH_K14(k, hipLaunchKernelGGL(filter_up_kernel<KK>, dim3(count), dim3(256), 0, s,
-                                         coeff_tab, refs, h0, h1, bnorm2));
+                                         coeff_tab, refs, h0, h1, bnorm2, mirror));
   hip_check(hipGetLastError(), "filter_up_kernel");
+}
+
+bool low_kernel_available(int k) { return k == 10 || k == 12 || k == 14; }
+
+void launch_apply_low(int k, const uint16_t* mirror, double* const* out_tab,
+                      const LowItem* items, const TargetRange* targets, int ntargets,
+                      const uint16_t* const* l_tab, const double* const* c_tab, hipStream_t s) {
+  if (ntargets <= 0) return;
+  if (k == 10) {
+    hipLaunchKernelGGL(apply_low_kernel<10>, dim3(ntargets), dim3(256), 0, s, mirror, out_tab,
+                       items, targets, l_tab, c_tab);
+  } else if (k == 12) {
+    hipLaunchKernelGGL(apply_low_kernel<12>, dim3(ntargets), dim3(256), 0, s, mirror, out_tab,
+                       items, targets, l_tab, c_tab);
+  } else if (k == 14) {
+    hipLaunchKernelGGL(apply_low_kernel<14>, dim3(ntargets), dim3(256), 0, s, mirror, out_tab,
+                       items, targets, l_tab, c_tab);
+  } else {
+    fail(MRA_E_UNSUPPORTED, "the low-precision tier is built for k = 10, 12, 14");
+  }
+  hip_check(hipGetLastError(), "apply_low_kernel");
 }
 
 bool ns_kernel_fuses_subtraction(int k) { return k == 8 || k == 10 || k == 12; }

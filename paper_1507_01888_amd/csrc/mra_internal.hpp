@@ -69,6 +69,39 @@ struct BlockEntry {
 };
 
 // ------------------------------------------------------------------------- context
+struct Ctx;
+// Reusable staging of the per-apply arrays: host arrays are packed into one pinned buffer
+// and copied with a single asynchronous transfer into one device buffer; scratch regions
+// (no host contents) live in a second device buffer.  Both grow on demand and are reused
+// by the next apply on the context, which may start only after the previous one has been
+// synchronised (every apply ends with a stream synchronisation).
+struct Arena {
+  Ctx* ctx = nullptr;
+  char* host = nullptr;
+  size_t host_cap = 0;
+  char* dev = nullptr;
+  size_t dev_cap = 0;
+  char* scr = nullptr;
+  size_t scr_cap = 0;
+  size_t used = 0, scr_used = 0;
+  std::vector<std::pair<size_t, size_t>> pending;   // (offset, bytes) awaiting the copy
+  ~Arena();
+  void begin(Ctx* c) {
+    ctx = c;
+    used = scr_used = 0;
+    pending.clear();
+  }
+  size_t put_bytes(const void* src, size_t bytes);    // returns the device offset
+  template <class T>
+  size_t put(const std::vector<T>& v) { return put_bytes(v.data(), v.size() * sizeof(T)); }
+  size_t scratch(size_t bytes);                       // device-only region, offset
+  void commit();                                      // grow device buffers, copy
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(dev + off); }
+  template <class T>
+  T* scr_at(size_t off) const { return reinterpret_cast<T*>(scr + off); }
+};
+
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -79,6 +112,8 @@ struct Ctx {
   std::string err;
   mra_apply_stats stats{};
   hipEvent_t ev[8]{};
+  Arena arena[2];                      // filter-up phase, plan phase
+  double* red_part = nullptr;          // 256 partial sums of the leaf reductions
 
   double width() const { return hi - lo; }
   void* dalloc(size_t bytes);
@@ -127,13 +162,13 @@ struct Func {
   std::vector<int32_t> interior;       // refined node indices (level-major, sorted)
   std::vector<int64_t> inter_level_off;  // nlev + 1 offsets into `interior`
   DevArray<double> coeff;              // nodes * k^3
-  DevArray<int32_t> d_leaves, d_leaf_level, d_interior, d_inter_child;
+  DevArray<int32_t> d_leaves;          // device copy of `leaves`, made on first use
   bool interior_valid = false;
 
   int64_t nodes() const { return (int64_t)code.size(); }
   int level_of(int64_t node) const;
   void finalize_structure();           // leaves / interior lists from first_child
-  void upload_structure();
+  const int32_t* device_leaves();
 };
 
 // Build the node arrays of a full octree from per-level sorted codes.
@@ -149,10 +184,25 @@ struct Op {
   DevArray<double> dR, dT;                             // transposed blocks
   size_t dR_blocks = 0, dT_blocks = 0;                 // blocks resident on device
   DevArray<double> d_c;
+  // Low-precision tier: per R block index b one record of BF16 matrices (rows = output
+  // index) in the lane order of the BF16 matrix-core operands, built from hR[b], hT[b]:
+  //   U(R), U(E), U(P): N x UP rows, UP = 8 ceil(N/8) columns, zero padded;
+  //   V(R), V(E), V(P): N x 32, column slot s holds column perm(s), where slot 8g + j
+  //   is column 4g + j (j < 4) or 16 + 4g + j - 4 (j >= 4), zero where that is >= N;
+  // N = 2k, P = H^T t H, E = R - P.
+  std::vector<uint16_t> hL;
+  DevArray<uint16_t> dL;
+  size_t hL_blocks = 0, dL_blocks = 0;
   // Make sure (level, mu) has blocks and norms for |delta| <= D.  Returns the entry.
   const BlockEntry& ensure(int level, int mu, int D);
+  void ensure_low();                                   // BF16 records for every R block
   void sync_device();                                  // upload blocks added since last call
 };
+// BF16 record geometry of the low tier for wavelet order k.
+inline int low_up(int k) { return (2 * k + 7) / 8 * 8; }
+inline size_t low_record(int k) { return (size_t)3 * 2 * k * low_up(k) + (size_t)3 * 2 * k * 32; }
+// FP64 -> FP32 (round to nearest even) -> BF16 (round to nearest even), finite inputs.
+uint16_t bf16_bits(double v);
 
 // ------------------------------------------------------------------------- projection
 void project_gaussians(Ctx* ctx, const mra_gaussian* g, int ng, int k, double thresh,
@@ -166,6 +216,11 @@ struct NSItem {          // one kept (source, displacement, term) triple of a ta
   int32_t mu;
   int32_t rx, ry, rz;    // R block indices (transposed (2k)^2 blocks)
   int32_t tx, ty, tz;    // t block indices (transposed k^2 blocks)
+};
+struct LowItem {         // one kept triple of the low-precision tier
+  int32_t slot;          // BF16 copy of the children block B_P (filter-up order)
+  int32_t mu;
+  int32_t rx, ry, rz;    // R block indices (BF16 records)
 };
 struct TargetRange {
   int32_t fn;            // function of the batch (index into the pointer tables)
@@ -189,8 +244,16 @@ struct NodeRef {
 };
 
 void launch_zero(double* p, size_t n, hipStream_t s);
+// mirror != nullptr: also writes the BF16 copy of each children block, layout
+// [a][b][c] with c padded to low_up(k), one block per ref.
 void launch_filter_up(int k, double* const* coeff_tab, const NodeRef* refs, int count,
-                      const double* h0, const double* h1, double* bnorm2, hipStream_t s);
+                      const double* h0, const double* h1, double* bnorm2, uint16_t* mirror,
+                      hipStream_t s);
+// True when the low-precision transform kernel is built for this k.
+bool low_kernel_available(int k);
+void launch_apply_low(int k, const uint16_t* mirror, double* const* out_tab,
+                      const LowItem* items, const TargetRange* targets, int ntargets,
+                      const uint16_t* const* l_tab, const double* const* c_tab, hipStream_t s);
 // True when the non-standard kernel for this k also applies the level-n subtraction.
 bool ns_kernel_fuses_subtraction(int k);
 void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
@@ -213,7 +276,7 @@ void launch_leaf_reduce(int k, const double* a, const double* b, const int32_t* 
 
 // Host drivers
 void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
-                             const std::vector<Func*>& funcs, double tau,
+                             const std::vector<Func*>& funcs, double tau, double tau_tier,
                              const std::vector<Func*>& outs);
 void filter_up_function(Ctx* ctx, Func& f);
 

@@ -62,14 +62,9 @@ void Func::finalize_structure() {
   }
 }
 
-void Func::upload_structure() {
-  std::vector<int32_t> lvl(leaves.size()), ich(interior.size());
-  for (size_t i = 0; i < leaves.size(); ++i) lvl[i] = level_of(leaves[i]);
-  for (size_t i = 0; i < interior.size(); ++i) ich[i] = first_child[interior[i]];
-  d_leaves.upload(ctx, leaves);
-  d_leaf_level.upload(ctx, lvl);
-  d_interior.upload(ctx, interior);
-  d_inter_child.upload(ctx, ich);
+const int32_t* Func::device_leaves() {
+  if (d_leaves.n != leaves.size() || !d_leaves.p) d_leaves.upload(ctx, leaves);
+  return d_leaves.p;
 }
 
 // ------------------------------------------------------------------ projection
