@@ -199,14 +199,15 @@ def main():
                     "rel_l2_mixed_vs_fp64": float(np.linalg.norm(cm - c6) / np.linalg.norm(c6))}
 
     flops = sum(s["useful_flops"] for s in stats)
-    # the main kernel applies the children blocks and (for k = 8, 10, 12) the fused level-n
-    # subtraction, so its algorithmic work is the full useful flop count of the step
-    fused = k in (8, 10, 12)
+    # the main kernel applies the children blocks and (for k = 8, 10, 12, 14) the fused
+    # level-n subtraction, so its algorithmic work is the useful flop count of its triples
+    fused = k in (8, 10, 12, 14)
     kernel_flops = (stats[0]["useful_flops"] - stats[0]["flops_low"] if fused
                     else (stats[0]["triples"] - stats[0]["triples_low"]) * 6.0 * (2 * k) ** 4)
     main_ms = sum(s["ms_main_kernel"] for s in stats) / len(stats)
     kname = {8: "apply_ns_mfma_kernel<8>", 10: "apply_ns_mfma_kernel<10>",
-             12: "apply_ns_mfma_big_kernel<12>"}.get(k, "apply_ns_kernel<%d>" % k)
+             12: "apply_ns_own_kernel<12>", 14: "apply_ns_stream_kernel<14>"}.get(
+                 k, "apply_ns_kernel<%d>" % k)
     achieved = kernel_flops / (main_ms * 1e-3) / 1e12
     low_ms = sum(s["ms_low_kernel"] for s in stats) / len(stats)
     out = {
@@ -231,7 +232,7 @@ def main():
                      for key in ("ms_filter", "ms_plan", "ms_apply", "ms_main_kernel", "ms_sumdown")},
         "norm2": nrm[0] if len(nrm) == 1 else sum(v * v for v in nrm) ** 0.5,
         "roofline": {"kernel": kname,
-                     "bound": "mfma" if k in (8, 10, 12) else "alu", "achieved": achieved,
+                     "bound": "mfma" if fused else "alu", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(kname)},
     }

@@ -20,11 +20,12 @@
  *  - A context is not thread-safe; handles belong to the context that made them.
  *
  * Error codes
- *  MRA_E_INVALID      bad argument: k outside [2, 14] (non-standard apply: k <= 10),
- *                     thresh <= 0, cell_hi <= cell_lo, ng < 1, M < 1, expnt <= 0, ...
+ *  MRA_E_INVALID      bad argument: k outside [2, 14], thresh <= 0, cell_hi <= cell_lo,
+ *                     ng < 1, M < 1, expnt <= 0, tau_drop < 0, tau_tier < 0, ...
  *  MRA_E_NOMEM        the allocator returned NULL
  *  MRA_E_DEVICE       a HIP runtime error (its text is in the message)
- *  MRA_E_UNSUPPORTED  a combination this build does not implement
+ *  MRA_E_UNSUPPORTED  a combination this build does not implement (non-standard apply with
+ *                     k = 11 or 13; the low-precision tier with k other than 10, 12, 14)
  *  MRA_E_MISMATCH     operator and function disagree on k or context
  */
 #ifndef MRA_H

@@ -651,8 +651,8 @@ mra_status mra_op_free(mra_op* op) {
 namespace {
 void check_nonstandard(int k, const mra_apply_params& p) {
   using namespace mra;
-  if (k > 10 && k != 12)
-    fail(MRA_E_UNSUPPORTED, "non-standard apply is built for k <= 10 and k = 12");
+  if (k > 10 && k != 12 && k != 14)
+    fail(MRA_E_UNSUPPORTED, "non-standard apply is built for k <= 10, 12 and 14");
   if (!(p.tau_drop >= 0.0)) fail(MRA_E_INVALID, "tau_drop must be >= 0");
   if (!(p.tau_tier >= 0.0)) fail(MRA_E_INVALID, "tau_tier must be >= 0");
   if (p.tau_tier > 0.0) {

@@ -594,235 +594,6 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
   }
 }
 
-// ------------------------------------------------------- apply (NS, MFMA, large blocks)
-// FP64 matrix-core version for 2k = 4Q with Q = 6 (k = 12).  One LDS buffer holds the source
-// block for steps 1-2 and is then overwritten by the y-contracted tensor for the
-// z-exchange, so the source block is re-staged for every triple.  Steps 1+2 units are the
-// Q^2 (z-quad, a-quad) pairs, step 3 units the Q^2 (a-quad, b-quad) pairs, both split
-// evenly over the 4 waves; the y-contracted pairs wait in registers until every wave has
-// finished reading the source block.  The level-n subtraction is fused as in the k <= 10
-// kernel.
-template <int K>
-__global__ __launch_bounds__(256) void apply_ns_mfma_big_kernel(
-    const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
-    const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
-    const double* const* __restrict__ r_tab, const double* const* __restrict__ t_tab,
-    const double* const* __restrict__ c_tab, double* __restrict__ partials,
-    double* __restrict__ subbuf) {
-  constexpr int N = 2 * K, Q = N / 4, N2 = N * N, K3 = K * K * K, ZP = N + 1;
-  static_assert(N % 4 == 0 && (Q * Q) % 4 == 0, "pairs must split evenly over 4 waves");
-  constexpr int PW = Q * Q / 4;                      // pairs per wave (steps 1-2 and step 3)
-  constexpr int Q2 = (K + 3) / 4, KP = 4 * Q2, ZP2 = KP + 1;
-  constexpr int S3 = Q2 * Q2;
-  constexpr int S3_PER_WAVE = (S3 + 3) / 4;
-  __shared__ double Bs[N * N * ZP];
-  __shared__ double Z2[KP * KP * ZP2];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
-  const TargetRange tr = targets[blockIdx.x];
-  const double* __restrict__ in = in_tab[tr.fn];
-  double* __restrict__ out = out_tab[tr.fn];
-  const double* __restrict__ dR = r_tab[tr.fn];
-  const double* __restrict__ dT = t_tab[tr.fn];
-  const double* __restrict__ dc = c_tab[tr.fn];
-  const bool with_sub = tr.sub >= 0;
-
-  double acc[PW][Q];
-#pragma unroll
-  for (int p = 0; p < PW; ++p)
-#pragma unroll
-    for (int c = 0; c < Q; ++c) acc[p][c] = 0.0;
-  double sacc[S3_PER_WAVE][Q2];
-#pragma unroll
-  for (int p = 0; p < S3_PER_WAVE; ++p)
-#pragma unroll
-    for (int c = 0; c < Q2; ++c) sacc[p][c] = 0.0;
-
-  for (int it = tr.beg; it < tr.end; ++it) {
-    const NSItem item = items[it];
-    __syncthreads();   // previous triple's step 3 is done with Bs
-    for (int e = tid; e < 8 * K3; e += 256) {
-      int c = e / K3, r = e - c * K3;
-      int i = r / (K * K), j = (r / K) % K, m = r % K;
-      Bs[((((c >> 2) & 1) * K + i) * N + ((c >> 1) & 1) * K + j) * ZP + (c & 1) * K + m] =
-          in[(size_t)(item.src_fc + c) * K3 + r];
-    }
-    const double* RX = dR + (size_t)item.rx * N2;
-    const double* RY = dR + (size_t)item.ry * N2;
-    const double* RZ = dR + (size_t)item.rz * N2;
-    const double cmu = dc[item.mu];
-    double ry[Q][Q];
-#pragma unroll
-    for (int ks = 0; ks < Q; ++ks)
-#pragma unroll
-      for (int t = 0; t < Q; ++t) ry[ks][t] = RY[(4 * ks + lk) * N + 4 * t + li];
-    __syncthreads();
-    // ---- steps 1 and 2 for this wave's (z-quad, a-quad) pairs; results stay in registers
-    double zr[PW][Q];
-#pragma unroll
-    for (int e = 0; e < PW; ++e) {
-      const int p = wave * PW + e;
-      const int zq = p / Q, at = p % Q;
-      double rx[Q];
-#pragma unroll
-      for (int xs = 0; xs < Q; ++xs) rx[xs] = RX[(4 * xs + lk) * N + 4 * at + li];
-      double d1[Q];
-#pragma unroll
-      for (int yt = 0; yt < Q; ++yt) d1[yt] = 0.0;
-#pragma unroll
-      for (int xs = 0; xs < Q; ++xs)
-#pragma unroll
-        for (int yt = 0; yt < Q; ++yt) {
-          double a = Bs[((4 * xs + lk) * N + 4 * yt + li) * ZP + 4 * zq + lb];
-          d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rx[xs], d1[yt], 0, 0, 0);
-        }
-#pragma unroll
-      for (int bt = 0; bt < Q; ++bt) zr[e][bt] = 0.0;
-#pragma unroll
-      for (int ys = 0; ys < Q; ++ys)
-#pragma unroll
-        for (int bt = 0; bt < Q; ++bt)
-          zr[e][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ry[ys][bt], zr[e][bt], 0, 0, 0);
-    }
-    // ---- subtraction, steps 1 and 2
-    if (with_sub && wave < Q2) {
-      const int zq = wave;
-      const double* __restrict__ sp = in + (size_t)item.src * K3;
-      const double* TX = dT + (size_t)item.tx * K * K;
-      const double* TY = dT + (size_t)item.ty * K * K;
-      double tx[Q2][Q2], ty[Q2][Q2];
-#pragma unroll
-      for (int ks = 0; ks < Q2; ++ks)
-#pragma unroll
-        for (int t = 0; t < Q2; ++t) {
-          const int r = 4 * ks + lk, cc = 4 * t + li;
-          const bool ok = r < K && cc < K;
-          tx[ks][t] = ok ? TX[r * K + cc] : 0.0;
-          ty[ks][t] = ok ? TY[r * K + cc] : 0.0;
-        }
-      double d1[Q2][Q2];
-#pragma unroll
-      for (int at = 0; at < Q2; ++at)
-#pragma unroll
-        for (int yt = 0; yt < Q2; ++yt) d1[at][yt] = 0.0;
-      const int z = 4 * zq + lb;
-#pragma unroll
-      for (int xs = 0; xs < Q2; ++xs)
-#pragma unroll
-        for (int yt = 0; yt < Q2; ++yt) {
-          const int x = 4 * xs + lk, y = 4 * yt + li;
-          double a = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
-#pragma unroll
-          for (int at = 0; at < Q2; ++at)
-            d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, tx[xs][at], d1[at][yt], 0, 0, 0);
-        }
-#pragma unroll
-      for (int at = 0; at < Q2; ++at) {
-        double d2[Q2];
-#pragma unroll
-        for (int bt = 0; bt < Q2; ++bt) d2[bt] = 0.0;
-#pragma unroll
-        for (int ys = 0; ys < Q2; ++ys)
-#pragma unroll
-          for (int bt = 0; bt < Q2; ++bt)
-            d2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], ty[ys][bt], d2[bt], 0, 0, 0);
-#pragma unroll
-        for (int bt = 0; bt < Q2; ++bt)
-          Z2[((4 * at + lk) * KP + 4 * bt + li) * ZP2 + 4 * zq + lb] = d2[bt];
-      }
-    }
-    __syncthreads();   // every wave has finished reading the source block
-#pragma unroll
-    for (int e = 0; e < PW; ++e) {
-      const int p = wave * PW + e;
-      const int zq = p / Q, at = p % Q;
-#pragma unroll
-      for (int bt = 0; bt < Q; ++bt)
-        Bs[((4 * at + lk) * N + 4 * bt + li) * ZP + 4 * zq + lb] = zr[e][bt];
-    }
-    __syncthreads();
-    // ---- step 3: z-contraction, this wave's (a-quad, b-quad) pairs
-#pragma unroll
-    for (int zs = 0; zs < Q; ++zs) {
-      double rz[Q];
-#pragma unroll
-      for (int ct = 0; ct < Q; ++ct) rz[ct] = cmu * RZ[(4 * zs + lk) * N + 4 * ct + li];
-#pragma unroll
-      for (int e = 0; e < PW; ++e) {
-        const int p = wave * PW + e;
-        const int at3 = p / Q, bt3 = p % Q;
-        double a = Bs[((4 * at3 + lb) * N + 4 * bt3 + li) * ZP + 4 * zs + lk];
-#pragma unroll
-        for (int ct = 0; ct < Q; ++ct)
-          acc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rz[ct], acc[e][ct], 0, 0, 0);
-      }
-    }
-    // ---- subtraction, step 3
-    if (with_sub) {
-      const double* TZ = dT + (size_t)item.tz * K * K;
-      double tz[Q2][Q2];
-#pragma unroll
-      for (int ks = 0; ks < Q2; ++ks)
-#pragma unroll
-        for (int t = 0; t < Q2; ++t) {
-          const int r = 4 * ks + lk, cc = 4 * t + li;
-          tz[ks][t] = (r < K && cc < K) ? -cmu * TZ[r * K + cc] : 0.0;
-        }
-#pragma unroll
-      for (int e = 0; e < S3_PER_WAVE; ++e) {
-        const int p = (3 - wave) + 4 * e;
-        if (p < S3) {
-          const int at3 = p / Q2, bt3 = p % Q2;
-#pragma unroll
-          for (int zs = 0; zs < Q2; ++zs) {
-            double a = Z2[((4 * at3 + lb) * KP + 4 * bt3 + li) * ZP2 + 4 * zs + lk];
-#pragma unroll
-            for (int ct = 0; ct < Q2; ++ct)
-              sacc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, tz[zs][ct], sacc[e][ct], 0, 0, 0);
-          }
-        }
-      }
-    }
-  }
-  // ---- write the children block (and the level-n part) of the target
-#pragma unroll
-  for (int e = 0; e < PW; ++e) {
-    const int p = wave * PW + e;
-    const int at3 = p / Q, bt3 = p % Q;
-    const int a = 4 * at3 + lb, b = 4 * bt3 + lk;
-#pragma unroll
-    for (int ct = 0; ct < Q; ++ct) {
-      const int c = 4 * ct + li;
-      if (tr.partial >= 0) {
-        partials[(size_t)tr.partial * (N * N2 + K3) + (a * N + b) * N + c] = acc[e][ct];
-      } else {
-        const int child = ((a / K) << 2) | ((b / K) << 1) | (c / K);
-        out[(size_t)(tr.fc + child) * K3 + ((a % K) * K + (b % K)) * K + (c % K)] += acc[e][ct];
-      }
-    }
-  }
-  if (with_sub) {
-#pragma unroll
-    for (int e = 0; e < S3_PER_WAVE; ++e) {
-      const int p = (3 - wave) + 4 * e;
-      if (p < S3) {
-        const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + lk;
-#pragma unroll
-        for (int ct = 0; ct < Q2; ++ct) {
-          const int c = 4 * ct + li;
-          if (a < K && b < K && c < K) {
-            if (tr.partial >= 0)
-              partials[(size_t)tr.partial * (N * N2 + K3) + N * N2 + (a * K + b) * K + c] = sacc[e][ct];
-            else
-              subbuf[(size_t)tr.sub * K3 + (a * K + b) * K + c] = sacc[e][ct];
-          }
-        }
-      }
-    }
-  }
-}
-
 // --------------------------------------------------------------------------- apply (std)
 template <int K>
 __global__ __launch_bounds__(round64(K * K)) void apply_std_kernel(
@@ -1003,6 +774,628 @@ __global__ __launch_bounds__(256) void leaf_reduce_kernel(
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------- apply (NS, MFMA, a-quad ownership per wave)
+// LDS strides of a tensor T[x][y][z] (z contiguous) read as the A operand of the 4x4x4
+// matrix-core product (lane = 16 kk + 4 bb + ii reads T[4xs + kk][4yt + ii][4zq + bb]):
+// the 64 lanes hit every 8-byte slot of the 32-slot bank cycle exactly twice, the minimum.
+constexpr bool lds_spread(int sx, int sy) {
+  int cnt[32] = {};
+  for (int l = 0; l < 64; ++l) ++cnt[((l >> 4) * sx + (l & 3) * sy + ((l >> 2) & 3)) % 32];
+  for (int c = 0; c < 32; ++c)
+    if (cnt[c] != 2) return false;
+  return true;
+}
+constexpr int lds_sy(int n) {
+  for (int sy = n; sy < n + 16; ++sy)
+    for (int sx = n * sy; sx < n * sy + 64; ++sx)
+      if (lds_spread(sx, sy)) return sy;
+  return -1;
+}
+constexpr int lds_sx(int n) {
+  const int sy = lds_sy(n);
+  for (int sx = n * sy; sx < n * sy + 64; ++sx)
+    if (lds_spread(sx, sy)) return sx;
+  return -1;
+}
+
+// FP64 matrix-core kernel for even k in [8, 12] (2k = 4Q).  Same 4x4x4 (four blocks)
+// product chain as apply_ns_mfma_kernel: step 1 contracts x (block index = z inside a
+// z-quad), step 2 contracts y in registers.  The work of a triple is split into (a-quad,
+// z-quad) units handed to the four waves in contiguous a-major runs, so a wave owns at most
+// two a-quads and finishes the z-contraction (step 3) of its units itself: the step-2 result
+// (block = z, row = a) is turned into the step-3 A operand (block = a, k = z) by an in-wave
+// lane permutation (ds_bpermute, no LDS storage) and accumulated per z-quad.  There is no
+// exchange tensor, so a triple needs one workgroup barrier (for the double-buffered operator
+// blocks) and the source block stays resident in LDS for all triples of a source.  a-quads
+// shared by two neighbouring waves are summed through LDS once at the end, and the children
+// block is written out coalesced.
+template <int K>
+__global__ __launch_bounds__(256) void apply_ns_own_kernel(
+    const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
+    const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
+    const double* const* __restrict__ r_tab, const double* const* __restrict__ t_tab,
+    const double* const* __restrict__ c_tab, double* __restrict__ partials,
+    double* __restrict__ subbuf) {
+  constexpr int N = 2 * K, Q = N / 4, N2 = N * N, N3 = N * N * N, K2 = K * K, K3 = K * K * K;
+  static_assert(N % 4 == 0 && Q >= 4 && Q <= 6, "even k in [8, 12]");
+  constexpr int NU = Q * Q;                              // (a-quad, z-quad) units
+  constexpr int Q2 = (K + 3) / 4, KP = 4 * Q2, SU = Q2 * Q2;
+  constexpr int XSY = lds_sy(N), XSX = lds_sx(N), SSY = lds_sy(KP), SSX = lds_sx(KP);
+  static_assert(XSY > 0 && XSX > 0 && SSY > 0 && SSX > 0, "stride search");
+  static_assert(N * XSX >= N3 && KP * SSX >= K3, "end-of-target sums reuse the tensors");
+  constexpr int OPS = 3 * N2 + 3 * K2, OPS_PER_LANE = (OPS + 255) / 256;
+  __shared__ double Xs[N * XSX];    // children block B_P [x][y][z]; at the end: sum buffer
+  __shared__ double Ss[KP * SSX];   // s_P zero-padded to KP^3; at the end: sum buffer
+  __shared__ double Os[2][OPS];     // R_x^T, R_y^T, R_z^T, t_x^T, t_y^T, t_z^T
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
+  const int swap = (16 * lb + 4 * lk + li) * 4;          // lane with kk and bb exchanged
+  const TargetRange tr = targets[blockIdx.x];
+  const double* __restrict__ in = in_tab[tr.fn];
+  double* __restrict__ out = out_tab[tr.fn];
+  const double* __restrict__ dR = r_tab[tr.fn];
+  const double* __restrict__ dT = t_tab[tr.fn];
+  const double* __restrict__ dc = c_tab[tr.fn];
+  const bool with_sub = tr.sub >= 0;
+  const int u0 = wave * NU / 4, u1 = (wave + 1) * NU / 4, at0 = u0 / Q;
+  const int v0 = wave * SU / 4, v1 = (wave + 1) * SU / 4, sat0 = v0 / Q2;
+
+  auto fetch_ops = [&](int it, double* reg) {
+    const NSItem nx = items[it];
+#pragma unroll
+    for (int q = 0; q < OPS_PER_LANE; ++q) {
+      const int e = tid + 256 * q;
+      double v = 0.0;
+      if (e < 3 * N2) {
+        const int w = e / N2, r = e - w * N2;
+        const int blk = w == 0 ? nx.rx : (w == 1 ? nx.ry : nx.rz);
+        v = dR[(size_t)blk * N2 + r];
+      } else if (e < OPS) {
+        const int e2 = e - 3 * N2, w = e2 / K2, r = e2 - w * K2;
+        const int blk = w == 0 ? nx.tx : (w == 1 ? nx.ty : nx.tz);
+        v = dT[(size_t)blk * K2 + r];
+      }
+      reg[q] = v;
+    }
+  };
+  auto store_ops = [&](const double* reg, double* dst) {
+#pragma unroll
+    for (int q = 0; q < OPS_PER_LANE; ++q) {
+      const int e = tid + 256 * q;
+      if (e < OPS) dst[e] = reg[q];
+    }
+  };
+  auto lane_swap = [&](double v) {
+    const int2 w = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_ds_bpermute(swap, w.x);
+    r.y = __builtin_amdgcn_ds_bpermute(swap, w.y);
+    return __builtin_bit_cast(double, r);
+  };
+
+  double acc[2][Q][Q];    // [a-quad at0 + slot][b-quad][c-quad]
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+    for (int b = 0; b < Q; ++b)
+#pragma unroll
+      for (int c = 0; c < Q; ++c) acc[s2][b][c] = 0.0;
+  double sacc[2][Q2][Q2];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+    for (int b = 0; b < Q2; ++b)
+#pragma unroll
+      for (int c = 0; c < Q2; ++c) sacc[s2][b][c] = 0.0;
+
+  double pre[OPS_PER_LANE];
+  if (tr.beg < tr.end) {
+    fetch_ops(tr.beg, pre);
+    store_ops(pre, Os[tr.beg & 1]);
+  }
+  int loaded = -1;
+  for (int it = tr.beg; it < tr.end; ++it) {
+    const NSItem item = items[it];
+    const bool more = it + 1 < tr.end;
+    if (item.src_fc != loaded) {
+      __syncthreads();   // every wave is done with the previous source block
+      for (int e = tid; e < 8 * K3; e += 256) {
+        const int c = e / K3, r = e - c * K3;
+        const int i = r / K2, j = (r / K) % K, m = r % K;
+        Xs[(((c >> 2) & 1) * K + i) * XSX + (((c >> 1) & 1) * K + j) * XSY + (c & 1) * K + m] =
+            in[(size_t)(item.src_fc + c) * K3 + r];
+      }
+      if (with_sub) {
+        const double* __restrict__ sp = in + (size_t)item.src * K3;
+        for (int e = tid; e < KP * KP * KP; e += 256) {
+          const int x = e / (KP * KP), y = (e / KP) % KP, z = e % KP;
+          Ss[x * SSX + y * SSY + z] = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
+        }
+      }
+      loaded = item.src_fc;
+    }
+    __syncthreads();     // source block and this triple's operators are in place
+    if (more) fetch_ops(it + 1, pre);
+    const double* Ob = Os[it & 1];
+    const double* RXs = Ob;
+    const double* RYs = Ob + N2;
+    const double* RZs = Ob + 2 * N2;
+    const double* TXs = Ob + 3 * N2;
+    const double* TYs = Ob + 3 * N2 + K2;
+    const double* TZs = Ob + 3 * N2 + 2 * K2;
+    const double cmu = dc[item.mu];
+    {
+      double ry[Q][Q];
+#pragma unroll
+      for (int ys = 0; ys < Q; ++ys)
+#pragma unroll
+        for (int bt = 0; bt < Q; ++bt) ry[ys][bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+      // both a-quads of the wave share the step-1 reads of the source block where their
+      // z-quad ranges overlap
+      const int zl0 = max(0, u0 - at0 * Q), zh0 = min(Q, u1 - at0 * Q);
+      const int zl1 = max(0, u0 - (at0 + 1) * Q), zh1 = min(Q, u1 - (at0 + 1) * Q);
+      double rx[2][Q];
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int xs = 0; xs < Q; ++xs)
+          rx[s2][xs] = (at0 + s2 < Q) ? RXs[(4 * xs + lk) * N + 4 * (at0 + s2) + li] : 0.0;
+      // steps 2 and 3 of one a-quad slot from its step-1 result
+      auto finish = [&](double (&d1)[Q], double (&ac)[Q][Q], int zq) {
+        double zr[Q];
+#pragma unroll
+        for (int bt = 0; bt < Q; ++bt) zr[bt] = 0.0;
+#pragma unroll
+        for (int ys = 0; ys < Q; ++ys)
+#pragma unroll
+          for (int bt = 0; bt < Q; ++bt)
+            zr[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ry[ys][bt], zr[bt], 0, 0, 0);
+        double rz[Q];
+#pragma unroll
+        for (int ct = 0; ct < Q; ++ct) rz[ct] = cmu * RZs[(4 * zq + lk) * N + 4 * ct + li];
+#pragma unroll
+        for (int bt = 0; bt < Q; ++bt) {
+          const double zt = lane_swap(zr[bt]);
+#pragma unroll
+          for (int ct = 0; ct < Q; ++ct)
+            ac[bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(zt, rz[ct], ac[bt][ct], 0, 0, 0);
+        }
+      };
+      const int zfirst = min(zl0 < zh0 ? zl0 : Q, zl1 < zh1 ? zl1 : Q);
+      const int zlast = max(zh0, zh1);
+#pragma unroll 1
+      for (int zq = zfirst; zq < zlast; ++zq) {
+        const bool on0 = zq >= zl0 && zq < zh0, on1 = zq >= zl1 && zq < zh1;
+        if (!on0 && !on1) continue;
+        if (on0 && on1) {
+          double d1a[Q], d1b[Q];
+#pragma unroll
+          for (int yt = 0; yt < Q; ++yt) d1a[yt] = d1b[yt] = 0.0;
+#pragma unroll
+          for (int xs = 0; xs < Q; ++xs)
+#pragma unroll
+            for (int yt = 0; yt < Q; ++yt) {
+              const double xv = Xs[(4 * xs + lk) * XSX + (4 * yt + li) * XSY + 4 * zq + lb];
+              d1a[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xv, rx[0][xs], d1a[yt], 0, 0, 0);
+              d1b[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xv, rx[1][xs], d1b[yt], 0, 0, 0);
+            }
+          finish(d1a, acc[0], zq);
+          finish(d1b, acc[1], zq);
+        } else {
+          // one slot: select its operator column without dynamic register indexing
+          double rxs[Q];
+#pragma unroll
+          for (int xs = 0; xs < Q; ++xs) rxs[xs] = on0 ? rx[0][xs] : rx[1][xs];
+          double d1[Q];
+#pragma unroll
+          for (int yt = 0; yt < Q; ++yt) d1[yt] = 0.0;
+#pragma unroll
+          for (int xs = 0; xs < Q; ++xs)
+#pragma unroll
+            for (int yt = 0; yt < Q; ++yt)
+              d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                  Xs[(4 * xs + lk) * XSX + (4 * yt + li) * XSY + 4 * zq + lb], rxs[xs], d1[yt],
+                  0, 0, 0);
+          if (on0)
+            finish(d1, acc[0], zq);
+          else
+            finish(d1, acc[1], zq);
+        }
+      }
+    }
+    // ---- level-n subtraction -c (t_x x t_y x t_z) s_P, same scheme on the KP^3 grid
+    if (with_sub) {
+      double ty[Q2][Q2];
+#pragma unroll
+      for (int ys = 0; ys < Q2; ++ys)
+#pragma unroll
+        for (int bt = 0; bt < Q2; ++bt) {
+          const int r = 4 * ys + lk, cc = 4 * bt + li;
+          ty[ys][bt] = (r < K && cc < K) ? TYs[r * K + cc] : 0.0;
+        }
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const int at = sat0 + s2;
+        const int z_lo = max(0, v0 - at * Q2), z_hi = min(Q2, v1 - at * Q2);
+        if (z_lo < z_hi) {
+          double tx[Q2];
+#pragma unroll
+          for (int xs = 0; xs < Q2; ++xs) {
+            const int r = 4 * xs + lk, cc = 4 * at + li;
+            tx[xs] = (r < K && cc < K) ? TXs[r * K + cc] : 0.0;
+          }
+#pragma unroll 1
+          for (int zq = z_lo; zq < z_hi; ++zq) {
+            double d1[Q2];
+#pragma unroll
+            for (int yt = 0; yt < Q2; ++yt) d1[yt] = 0.0;
+#pragma unroll
+            for (int xs = 0; xs < Q2; ++xs)
+#pragma unroll
+              for (int yt = 0; yt < Q2; ++yt)
+                d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                    Ss[(4 * xs + lk) * SSX + (4 * yt + li) * SSY + 4 * zq + lb], tx[xs], d1[yt],
+                    0, 0, 0);
+            double zr[Q2];
+#pragma unroll
+            for (int bt = 0; bt < Q2; ++bt) zr[bt] = 0.0;
+#pragma unroll
+            for (int ys = 0; ys < Q2; ++ys)
+#pragma unroll
+              for (int bt = 0; bt < Q2; ++bt)
+                zr[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ty[ys][bt], zr[bt], 0, 0, 0);
+            double tz[Q2];
+#pragma unroll
+            for (int ct = 0; ct < Q2; ++ct) {
+              const int r = 4 * zq + lk, cc = 4 * ct + li;
+              tz[ct] = (r < K && cc < K) ? -cmu * TZs[r * K + cc] : 0.0;
+            }
+#pragma unroll
+            for (int bt = 0; bt < Q2; ++bt) {
+              const double zt = lane_swap(zr[bt]);
+#pragma unroll
+              for (int ct = 0; ct < Q2; ++ct)
+                sacc[s2][bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(zt, tz[ct], sacc[s2][bt][ct], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    if (more) store_ops(pre, Os[(it + 1) & 1]);
+  }
+  // ---- sum the waves' partial blocks in LDS (even waves, then odd waves: the a-quads of
+  // waves two apart are disjoint), then write the target's blocks coalesced
+  __syncthreads();
+  double* Bsum = Xs;    // [a][b][c], N^3
+  double* Ssum = Ss;    // [a][b][c], K^3
+  for (int e = tid; e < N3; e += 256) Bsum[e] = 0.0;
+  if (with_sub)
+    for (int e = tid; e < K3; e += 256) Ssum[e] = 0.0;
+  __syncthreads();
+  for (int par = 0; par < 2; ++par) {
+    if ((wave & 1) == par) {
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const int at = at0 + s2;
+        if (max(0, u0 - at * Q) < min(Q, u1 - at * Q)) {
+          const int a = 4 * at + lb;
+#pragma unroll
+          for (int bt = 0; bt < Q; ++bt)
+#pragma unroll
+            for (int ct = 0; ct < Q; ++ct)
+              Bsum[(a * N + 4 * bt + lk) * N + 4 * ct + li] += acc[s2][bt][ct];
+        }
+      }
+      if (with_sub) {
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const int at = sat0 + s2;
+          if (max(0, v0 - at * Q2) < min(Q2, v1 - at * Q2)) {
+            const int a = 4 * at + lb;
+#pragma unroll
+            for (int bt = 0; bt < Q2; ++bt)
+#pragma unroll
+              for (int ct = 0; ct < Q2; ++ct) {
+                const int b = 4 * bt + lk, c = 4 * ct + li;
+                if (a < K && b < K && c < K) Ssum[(a * K + b) * K + c] += sacc[s2][bt][ct];
+              }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (tr.partial >= 0) {
+    double* dst = partials + (size_t)tr.partial * (N3 + K3);
+    for (int e = tid; e < N3; e += 256) dst[e] = Bsum[e];
+    if (with_sub)
+      for (int e = tid; e < K3; e += 256) dst[N3 + e] = Ssum[e];
+  } else {
+    // child slab c gets rows (a, b) of its octant: element e of the slab is (i, j, m)
+    for (int e = tid; e < 8 * K3; e += 256) {
+      const int c = e / K3, r = e - c * K3;
+      const int i = r / K2, j = (r / K) % K, m = r % K;
+      const int a = ((c >> 2) & 1) * K + i, b = ((c >> 1) & 1) * K + j, cc = (c & 1) * K + m;
+      out[(size_t)(tr.fc + c) * K3 + r] += Bsum[(a * N + b) * N + cc];
+    }
+    if (with_sub)
+      for (int e = tid; e < K3; e += 256) subbuf[(size_t)tr.sub * K3 + e] = Ssum[e];
+  }
+}
+
+// ----------------------------------------- apply (NS, MFMA, source streamed in z-slabs)
+// FP64 matrix-core kernel for k = 14 (2k = 28 = 4Q, Q = 7), whose (2k)^3 children block
+// (172 KB) does not fit in LDS.  Each wave owns whole a-quads (sets of 2, 2, 2, 1), so it
+// completes the three contractions of its a-quads itself (the step-2 result is permuted
+// in-wave into the step-3 operand as in apply_ns_own_kernel) and accumulates step 3 one
+// z-quad at a time.  A triple is therefore processed in Q stages, one per z-quad: stage zq
+// needs only the slab B_P[.][.][4zq .. 4zq+3] (25 KB), which is double buffered in LDS and
+// loaded from L2 one stage ahead (the next triple's first slab during the last stage).  The
+// subtraction (KP = 16, one a-quad per wave) runs in the first KP/4 stages on s_P, resident
+// in LDS per source.  One workgroup barrier per stage.
+template <int K>
+__global__ __launch_bounds__(256) void apply_ns_stream_kernel(
+    const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
+    const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
+    const double* const* __restrict__ r_tab, const double* const* __restrict__ t_tab,
+    const double* const* __restrict__ c_tab, double* __restrict__ partials,
+    double* __restrict__ subbuf) {
+  constexpr int N = 2 * K, Q = N / 4, N2 = N * N, N3 = N * N * N, K2 = K * K, K3 = K * K * K;
+  static_assert(N % 4 == 0 && Q == 7, "k = 14");
+  constexpr int Q2 = (K + 3) / 4, KP = 4 * Q2;
+  static_assert(Q2 == 4, "one subtraction a-quad per wave");
+  constexpr int SLY = 4, SLX = N * SLY, SLAB = N * SLX;     // slab [x][y][z in quad]
+  static_assert(lds_spread(SLX, SLY), "slab strides");
+  constexpr int SLAB_PER_LANE = (SLAB + 255) / 256;
+  constexpr int SSY = lds_sy(KP), SSX = lds_sx(KP);
+  constexpr int OPS = 3 * N2 + 3 * K2, OPS_PER_LANE = (OPS + 255) / 256;
+  __shared__ double Xl[2][SLAB];
+  __shared__ double Ss[KP * SSX];
+  __shared__ double Os[2][OPS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
+  const int swap = (16 * lb + 4 * lk + li) * 4;
+  const TargetRange tr = targets[blockIdx.x];
+  const double* __restrict__ in = in_tab[tr.fn];
+  double* __restrict__ out = out_tab[tr.fn];
+  const double* __restrict__ dR = r_tab[tr.fn];
+  const double* __restrict__ dT = t_tab[tr.fn];
+  const double* __restrict__ dc = c_tab[tr.fn];
+  const bool with_sub = tr.sub >= 0;
+  const int at_lo = 2 * wave, at_n = wave < 3 ? 2 : 1;     // a-quads of this wave
+  const int sat = wave;                                    // subtraction a-quad
+
+  auto fetch_ops = [&](int it, double* reg) {
+    const NSItem nx = items[it];
+#pragma unroll
+    for (int q = 0; q < OPS_PER_LANE; ++q) {
+      const int e = tid + 256 * q;
+      double v = 0.0;
+      if (e < 3 * N2) {
+        const int w = e / N2, r = e - w * N2;
+        const int blk = w == 0 ? nx.rx : (w == 1 ? nx.ry : nx.rz);
+        v = dR[(size_t)blk * N2 + r];
+      } else if (e < OPS) {
+        const int e2 = e - 3 * N2, w = e2 / K2, r = e2 - w * K2;
+        const int blk = w == 0 ? nx.tx : (w == 1 ? nx.ty : nx.tz);
+        v = dT[(size_t)blk * K2 + r];
+      }
+      reg[q] = v;
+    }
+  };
+  auto fetch_slab = [&](int fc, int zq, double* reg) {
+#pragma unroll
+    for (int q = 0; q < SLAB_PER_LANE; ++q) {
+      const int e = tid + 256 * q;
+      double v = 0.0;
+      if (e < SLAB) {
+        const int x = e / SLX, y = (e / SLY) % N, z = 4 * zq + e % SLY;
+        const int child = ((x / K) << 2) | ((y / K) << 1) | (z / K);
+        v = in[(size_t)(fc + child) * K3 + ((x % K) * K + (y % K)) * K + (z % K)];
+      }
+      reg[q] = v;
+    }
+  };
+  auto store_slab = [&](const double* reg, double* dst) {
+#pragma unroll
+    for (int q = 0; q < SLAB_PER_LANE; ++q) {
+      const int e = tid + 256 * q;
+      if (e < SLAB) dst[e] = reg[q];
+    }
+  };
+  auto lane_swap = [&](double v) {
+    const int2 w = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_ds_bpermute(swap, w.x);
+    r.y = __builtin_amdgcn_ds_bpermute(swap, w.y);
+    return __builtin_bit_cast(double, r);
+  };
+
+  double acc[2][Q][Q];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+    for (int b = 0; b < Q; ++b)
+#pragma unroll
+      for (int c = 0; c < Q; ++c) acc[s2][b][c] = 0.0;
+  double sacc[Q2][Q2];
+#pragma unroll
+  for (int b = 0; b < Q2; ++b)
+#pragma unroll
+    for (int c = 0; c < Q2; ++c) sacc[b][c] = 0.0;
+
+  double opre[OPS_PER_LANE], spre[SLAB_PER_LANE];
+  if (tr.beg < tr.end) {
+    fetch_ops(tr.beg, opre);
+    fetch_slab(items[tr.beg].src_fc, 0, spre);
+#pragma unroll
+    for (int q = 0; q < OPS_PER_LANE; ++q) {
+      const int e = tid + 256 * q;
+      if (e < OPS) Os[tr.beg & 1][e] = opre[q];
+    }
+    store_slab(spre, Xl[0]);
+  }
+  int sloaded = -1, buf = 0;
+  for (int it = tr.beg; it < tr.end; ++it) {
+    const NSItem item = items[it];
+    const bool more = it + 1 < tr.end;
+    const int next_fc = more ? items[it + 1].src_fc : -1;
+    if (with_sub && item.src_fc != sloaded) {
+      __syncthreads();   // nobody reads the previous s_P any more
+      const double* __restrict__ sp = in + (size_t)item.src * K3;
+      for (int e = tid; e < KP * KP * KP; e += 256) {
+        const int x = e / (KP * KP), y = (e / KP) % KP, z = e % KP;
+        Ss[x * SSX + y * SSY + z] = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
+      }
+      sloaded = item.src_fc;
+    }
+    if (more) fetch_ops(it + 1, opre);
+    const double* Ob = Os[it & 1];
+    const double* RXs = Ob;
+    const double* RYs = Ob + N2;
+    const double* RZs = Ob + 2 * N2;
+    const double* TXs = Ob + 3 * N2;
+    const double* TYs = Ob + 3 * N2 + K2;
+    const double* TZs = Ob + 3 * N2 + 2 * K2;
+    const double cmu = dc[item.mu];
+#pragma unroll 1
+    for (int zq = 0; zq < Q; ++zq) {
+      __syncthreads();   // slab zq (and this triple's operators, s_P) are in place
+      // next stage's slab: this triple's zq + 1, or the next triple's first slab
+      const bool pf = zq + 1 < Q || more;
+      if (pf) fetch_slab(zq + 1 < Q ? item.src_fc : next_fc, zq + 1 < Q ? zq + 1 : 0, spre);
+      const double* X = Xl[buf];
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        if (s2 < at_n) {
+          const int at = at_lo + s2;
+          double rx[Q];
+#pragma unroll
+          for (int xs = 0; xs < Q; ++xs) rx[xs] = RXs[(4 * xs + lk) * N + 4 * at + li];
+          double d1[Q];
+#pragma unroll
+          for (int yt = 0; yt < Q; ++yt) d1[yt] = 0.0;
+#pragma unroll
+          for (int xs = 0; xs < Q; ++xs)
+#pragma unroll
+            for (int yt = 0; yt < Q; ++yt)
+              d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                  X[(4 * xs + lk) * SLX + (4 * yt + li) * SLY + lb], rx[xs], d1[yt], 0, 0, 0);
+          double zr[Q];
+#pragma unroll
+          for (int bt = 0; bt < Q; ++bt) zr[bt] = 0.0;
+#pragma unroll
+          for (int ys = 0; ys < Q; ++ys) {
+            double ry[Q];
+#pragma unroll
+            for (int bt = 0; bt < Q; ++bt) ry[bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+#pragma unroll
+            for (int bt = 0; bt < Q; ++bt)
+              zr[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ry[bt], zr[bt], 0, 0, 0);
+          }
+          double rz[Q];
+#pragma unroll
+          for (int ct = 0; ct < Q; ++ct) rz[ct] = cmu * RZs[(4 * zq + lk) * N + 4 * ct + li];
+#pragma unroll
+          for (int bt = 0; bt < Q; ++bt) {
+            const double zt = lane_swap(zr[bt]);
+#pragma unroll
+            for (int ct = 0; ct < Q; ++ct)
+              acc[s2][bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(zt, rz[ct], acc[s2][bt][ct], 0, 0, 0);
+          }
+        }
+      }
+      if (with_sub && zq < Q2) {
+        double tx[Q2];
+#pragma unroll
+        for (int xs = 0; xs < Q2; ++xs) {
+          const int r = 4 * xs + lk, cc = 4 * sat + li;
+          tx[xs] = (r < K && cc < K) ? TXs[r * K + cc] : 0.0;
+        }
+        double d1[Q2];
+#pragma unroll
+        for (int yt = 0; yt < Q2; ++yt) d1[yt] = 0.0;
+#pragma unroll
+        for (int xs = 0; xs < Q2; ++xs)
+#pragma unroll
+          for (int yt = 0; yt < Q2; ++yt)
+            d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                Ss[(4 * xs + lk) * SSX + (4 * yt + li) * SSY + 4 * zq + lb], tx[xs], d1[yt], 0, 0, 0);
+        double zr[Q2];
+#pragma unroll
+        for (int bt = 0; bt < Q2; ++bt) zr[bt] = 0.0;
+#pragma unroll
+        for (int ys = 0; ys < Q2; ++ys)
+#pragma unroll
+          for (int bt = 0; bt < Q2; ++bt) {
+            const int r = 4 * ys + lk, cc = 4 * bt + li;
+            const double ty = (r < K && cc < K) ? TYs[r * K + cc] : 0.0;
+            zr[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ty, zr[bt], 0, 0, 0);
+          }
+        double tz[Q2];
+#pragma unroll
+        for (int ct = 0; ct < Q2; ++ct) {
+          const int r = 4 * zq + lk, cc = 4 * ct + li;
+          tz[ct] = (r < K && cc < K) ? -cmu * TZs[r * K + cc] : 0.0;
+        }
+#pragma unroll
+        for (int bt = 0; bt < Q2; ++bt) {
+          const double zt = lane_swap(zr[bt]);
+#pragma unroll
+          for (int ct = 0; ct < Q2; ++ct)
+            sacc[bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(zt, tz[ct], sacc[bt][ct], 0, 0, 0);
+        }
+      }
+      if (pf) store_slab(spre, Xl[buf ^ 1]);
+      if (zq + 1 == Q && more) {
+#pragma unroll
+        for (int q = 0; q < OPS_PER_LANE; ++q) {
+          const int e = tid + 256 * q;
+          if (e < OPS) Os[(it + 1) & 1][e] = opre[q];
+        }
+      }
+      buf ^= 1;
+    }
+  }
+  // ---- each element of the target's blocks is owned by exactly one lane
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2) {
+    if (s2 < at_n) {
+      const int a = 4 * (at_lo + s2) + lb;
+#pragma unroll
+      for (int bt = 0; bt < Q; ++bt)
+#pragma unroll
+        for (int ct = 0; ct < Q; ++ct) {
+          const int b = 4 * bt + lk, c = 4 * ct + li;
+          if (tr.partial >= 0) {
+            partials[(size_t)tr.partial * (N3 + K3) + (a * N + b) * N + c] = acc[s2][bt][ct];
+          } else {
+            const int child = ((a / K) << 2) | ((b / K) << 1) | (c / K);
+            out[(size_t)(tr.fc + child) * K3 + ((a % K) * K + (b % K)) * K + (c % K)] +=
+                acc[s2][bt][ct];
+          }
+        }
+    }
+  }
+  if (with_sub) {
+    const int a = 4 * sat + lb;
+#pragma unroll
+    for (int bt = 0; bt < Q2; ++bt)
+#pragma unroll
+      for (int ct = 0; ct < Q2; ++ct) {
+        const int b = 4 * bt + lk, c = 4 * ct + li;
+        if (a < K && b < K && c < K) {
+          if (tr.partial >= 0)
+            partials[(size_t)tr.partial * (N3 + K3) + N3 + (a * K + b) * K + c] = sacc[bt][ct];
+          else
+            subbuf[(size_t)tr.sub * K3 + (a * K + b) * K + c] = sacc[bt][ct];
+        }
+      }
+  }
 }
 
 // ------------------------------------------------------------- apply (low tier, BF16)
@@ -1252,7 +1645,7 @@ void launch_apply_low(int k, const uint16_t* mirror, double* const* out_tab,
   hip_check(hipGetLastError(), "apply_low_kernel");
 }
 
-bool ns_kernel_fuses_subtraction(int k) { return k == 8 || k == 10 || k == 12; }
+bool ns_kernel_fuses_subtraction(int k) { return k == 8 || k == 10 || k == 12 || k == 14; }
 
 void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
                      const NSItem* items, const TargetRange* targets, int ntargets,
@@ -1267,7 +1660,10 @@ void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
     hipLaunchKernelGGL(apply_ns_mfma_kernel<10>, dim3(ntargets), dim3(256), 0, s, in_tab,
                        out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
   } else if (k == 12) {
-    hipLaunchKernelGGL(apply_ns_mfma_big_kernel<12>, dim3(ntargets), dim3(256), 0, s, in_tab,
+    hipLaunchKernelGGL(apply_ns_own_kernel<12>, dim3(ntargets), dim3(256), 0, s, in_tab,
+                       out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
+  } else if (k == 14) {
+    hipLaunchKernelGGL(apply_ns_stream_kernel<14>, dim3(ntargets), dim3(256), 0, s, in_tab,
                        out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
   } else {
     MRA_DISPATCH_K(k, hipLaunchKernelGGL(apply_ns_kernel<KK>, dim3(ntargets),

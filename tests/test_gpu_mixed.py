@@ -152,3 +152,60 @@ def test_low_tier_errors(M):
     with pytest.raises(M.MraError) as e:
         ctx.apply(op, f, tau_drop=1e-8, tau_tier=-1.0)
     assert e.value.code == -1
+
+
+def test_batched_k14_mixed_sampled(M):
+    """The large batched mixed workload's shape at a coarse threshold: two functions of 32
+    Gaussians (exponents log-uniform in [1, 1e4]), k = 14, one batched apply with the BF16
+    tier at 1e-3 thresh and one in FP64.  Output leaves sampled across levels are recomputed
+    by the oracle along their root paths (FP64 path: 1e-12; mixed path: 10 thresh and the
+    error model)."""
+    from oracle.apply import sampled_leaves
+    thresh = 1e-2
+    tau = 1e-4 * thresh
+    _say("case: batched k=14, 2 x 32 Gaussians, thresh %g, tiers at 1e-3 thresh" % thresh)
+    ctx = M.Context(0, W.CELL)
+    params = [W.coulomb_inputs("coulomb_batch_k14", i) for i in range(2)]
+    funcs = [ctx.project(c, a, x, 14, thresh) for (c, a, x) in params]
+    op = ctx.op_coulomb(14, 1e-5, 1e-8)
+    g64 = ctx.apply_batch([op, op], funcs, tau_drop=tau)
+    st64 = ctx.last_stats()
+    gmx = ctx.apply_batch([op, op], funcs, tau_drop=tau, tau_tier=1e-3 * thresh)
+    stmx = ctx.last_stats()
+    _say("k14 batch: triples %d, low %d, useful GFLOP %.1f, main kernel %.1f ms, low kernel %.2f ms"
+         % (stmx["triples"], stmx["triples_low"], stmx["useful_flops"] / 1e9,
+            stmx["ms_main_kernel"], stmx["ms_low_kernel"]))
+    assert stmx["triples"] == st64["triples"] and stmx["triples_low"] > 0
+    d64 = [_as_dict(g) for g in g64]
+    dmx = [_as_dict(g) for g in gmx]
+    total_diff2 = 0.0
+    for i in range(2):
+        assert set(d64[i]) == set(dmx[i])
+        keys = list(d64[i])
+        total_diff2 += _diff(dmx[i], d64[i], keys) ** 2
+    bound = 1.1 * (3 + 3 * math.sqrt(28)) * U_BF16 * stmx["eta_low"]
+    _say("k14 batch: |mixed - fp64| %.3e <= bound %.3e" % (math.sqrt(total_diff2), bound))
+    assert math.sqrt(total_diff2) <= bound
+    # oracle on sampled output leaves of function 0
+    c, a, x = params[0]
+    fo = project_adaptive(GaussianSum(c, a, x), 14, thresh, W.CELL, 2, 20)
+    cc, tt = coulomb_fit(1e-5, 1e-8, cell_r_hi(*W.CELL))
+    keys = sorted(d64[0])
+    rng = np.random.default_rng(11)
+    by_level = {}
+    for q in keys:
+        by_level.setdefault(q[0], []).append(q)
+    sample = []
+    for n, lst in sorted(by_level.items()):
+        for j in rng.choice(len(lst), min(2, len(lst)), replace=False):
+            sample.append(lst[j])
+    vals, has_acc, _ = sampled_leaves(fo, SeparatedOperator(cc, tt), tau, sample)
+    for q in sample:
+        assert not has_acc[q]
+    num64 = math.sqrt(sum(float(np.sum((d64[0][q] - vals[q]) ** 2)) for q in sample))
+    nummx = math.sqrt(sum(float(np.sum((dmx[0][q] - vals[q]) ** 2)) for q in sample))
+    den = math.sqrt(sum(float(np.sum(vals[q] ** 2)) for q in sample))
+    _say("k14 batch sampled (%d leaves): fp64 rel L2 %.3e, mixed rel L2 %.3e"
+         % (len(sample), num64 / den, nummx / den))
+    assert num64 / den <= 1e-12
+    assert nummx / den <= 10 * thresh

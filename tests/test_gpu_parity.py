@@ -261,3 +261,24 @@ def test_coulomb_k12_reduced_full_parity(M):
     err = _rel_l2(got, ref.leaves, ref.leaves)
     _say("coulomb k12 reduced rel L2 vs oracle", err, "triples", st["triples"])
     assert err <= TOL
+
+
+def test_coulomb_k14_reduced_full_parity(M):
+    """k=14 non-standard apply (the order of the large batched workload) in FP64, every
+    leaf: the source block is streamed through LDS in z-quad slabs."""
+    _say("case: coulomb k=14 reduced (2 Gaussians, thresh 1e-5)")
+    c, a, x = W.unit_charge_gaussians(4, 3, 2, 1.0, 30.0)
+    ctx = M.Context(0, W.CELL)
+    f = ctx.project(c, a, x, 14, 1e-5)
+    op = ctx.op_coulomb(14, 1e-5, 1e-8)
+    g = ctx.apply(op, f, tau_drop=1e-9)
+    fo = project_adaptive(GaussianSum(c, a, x), 14, 1e-5, W.CELL, 2, 20)
+    assert set(_as_dict(f)) == set(fo.leaves)
+    cc, tt = coulomb_fit(1e-5, 1e-8, cell_r_hi(*W.CELL))
+    ref, st = apply_nonstandard(fo, SeparatedOperator(cc, tt), 1e-9)
+    got = _as_dict(g)
+    assert set(got) == set(ref.leaves)
+    assert ctx.last_stats()["triples"] == st["triples"]
+    err = _rel_l2(got, ref.leaves, ref.leaves)
+    _say("coulomb k14 reduced rel L2 vs oracle", err, "triples", st["triples"])
+    assert err <= TOL
