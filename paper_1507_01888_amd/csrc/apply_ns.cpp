@@ -62,25 +62,9 @@ int64_t find_node(const Func& f, int n, uint64_t code) {
   return it - f.code.begin();
 }
 
-unsigned worker_count(size_t jobs) {
-  unsigned n = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  return (unsigned)std::min<size_t>(n, std::max<size_t>(1, jobs));
-}
-
 template <class F>
 void parallel_for(size_t count, F&& fn) {
-  unsigned nthr = worker_count(count);
-  if (nthr <= 1) {
-    for (size_t i = 0; i < count; ++i) fn(i, 0u);
-    return;
-  }
-  std::vector<std::thread> th;
-  for (unsigned t = 1; t < nthr; ++t)
-    th.emplace_back([&, t] {
-      for (size_t i = t; i < count; i += nthr) fn(i, t);
-    });
-  for (size_t i = 0; i < count; i += nthr) fn(i, 0u);
-  for (auto& t : th) t.join();
+  Pool::get().run(count, std::function<void(size_t, unsigned)>(fn));
 }
 
 struct Triple {
@@ -110,42 +94,7 @@ struct Plan {
   Func* f = nullptr;
   Func* out = nullptr;
   std::vector<const BlockEntry*> entry_tab;  // (level, mu) -> cache entry
-  std::vector<NSItem> items;
-  std::vector<LowItem> low_items;
-  int64_t ntriples = 0, nlow = 0;
-  std::vector<TargetRange> tgt, tgt_sub, low_tgt;
-  double flops = 0.0, flops_low = 0.0, eta_low = 0.0;
 };
-
-void validate(const Plan& p, int64_t nR, int64_t nT, int64_t nL, int64_t nslots) {
-  const int64_t nin = p.f->nodes(), nout = p.out->nodes();
-  auto bad = [](const char* what) {
-    fail(MRA_E_INVALID, std::string("internal plan error: ") + what);
-  };
-  for (const NSItem& it : p.items) {
-    if (it.src < 0 || it.src >= nin) bad("source node");
-    if (it.src_fc < 0 || it.src_fc + 8 > nin) bad("source children");
-    if (it.mu < 0 || it.mu >= (int)p.op->c.size()) bad("term index");
-    if (it.rx < 0 || it.rx >= nR || it.ry < 0 || it.ry >= nR || it.rz < 0 || it.rz >= nR)
-      bad("R block");
-    if (it.tx < 0 || it.tx >= nT || it.ty < 0 || it.ty >= nT || it.tz < 0 || it.tz >= nT)
-      bad("t block");
-  }
-  for (const TargetRange& r : p.tgt) {
-    if (r.node < 0 || r.node >= nout || r.fc < 0 || r.fc + 8 > nout) bad("target node");
-    if (r.beg < 0 || r.end < r.beg || r.end > (int32_t)p.items.size()) bad("item range");
-  }
-  for (const LowItem& it : p.low_items) {
-    if (it.slot < 0 || it.slot >= nslots) bad("low-tier source block");
-    if (it.mu < 0 || it.mu >= (int)p.op->c.size()) bad("term index");
-    if (it.rx < 0 || it.rx >= nL || it.ry < 0 || it.ry >= nL || it.rz < 0 || it.rz >= nL)
-      bad("low-tier block");
-  }
-  for (const TargetRange& r : p.low_tgt) {
-    if (r.node < 0 || r.node >= nout || r.fc < 0 || r.fc + 8 > nout) bad("target node");
-    if (r.beg < 0 || r.end < r.beg || r.end > (int32_t)p.low_items.size()) bad("item range");
-  }
-}
 
 // Output tree of one function from its sorted target codes: targets, their children,
 // ancestors, closed under siblings (full octree).
@@ -193,11 +142,9 @@ struct Unit {
   std::vector<uint64_t> tcodes;        // ascending
   std::vector<int64_t> toff;           // tcodes.size() + 1
   std::vector<int64_t> tmid;           // per target: first low-tier triple
-  std::vector<NSItem> items;
-  std::vector<LowItem> low_items;
-  std::vector<TargetRange> tgt, low_tgt;
-  int64_t nlow = 0;
-  double flops = 0.0, flops_low = 0.0, eta_low = 0.0;
+  std::vector<int64_t> fpre, lpre;     // per target: prefix counts of FP64 / low items
+  std::vector<int32_t> node;           // per target: output node
+  size_t item_base = 0, low_base = 0;  // offsets of this unit's items in the batch arrays
 };
 
 void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const LevelData& L) {
@@ -292,59 +239,67 @@ void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const L
     if (u.tmid[r] < 0) u.tmid[r] = u.toff[r + 1];
 }
 
-// Work items of one unit: per target the FP64 triples (NSItem) and the low-tier triples
-// (LowItem, source block addressed by its filter-up slot).
-void unit_items(Unit& u, const Plan& p, const LevelData& L, const std::vector<int64_t>& slot) {
+// Work items of the targets [r0, r1) of one unit, written at their final positions: per
+// target the FP64 triples (NSItem), then the low-tier triples (LowItem, source block by its
+// filter-up slot).  Every index is checked against the arrays it will address; returns the
+// sum of eta over the low-tier triples, or throws on an inconsistent plan.
+double fill_items(Unit& u, const Plan& p, const LevelData& L, const std::vector<int64_t>& slot,
+                  int64_t r0, int64_t r1, NSItem* items, LowItem* low, int64_t nR, int64_t nT,
+                  int64_t nL, int64_t nslots) {
   const Func& f = *p.f;
   const Func& out = *p.out;
-  const int k = f.k, n = u.n;
+  const int n = u.n;
   const int M = (int)p.op->c.size();
-  const double f_ns = 6.0 * std::pow(2.0 * k, 4), f_sub = 6.0 * std::pow((double)k, 4);
-  const double per = f_ns + (n > 0 ? f_sub : 0.0);
-  u.items.clear();
-  u.low_items.clear();
-  u.tgt.clear();
-  u.low_tgt.clear();
-  u.items.reserve(u.sorted.size());
-  u.flops = (double)u.sorted.size() * per;
-  for (size_t r = 0; r < u.tcodes.size(); ++r) {
-    uint64_t code = u.tcodes[r] & ((1ULL << 58) - 1);
-    int64_t node = find_node(out, n, code);
-    const int32_t fc = out.first_child[node];
-    const int32_t b0 = (int32_t)u.items.size(), l0 = (int32_t)u.low_items.size();
+  const int64_t nin = f.nodes(), nout = out.nodes();
+  auto bad = [](const char* what) {
+    fail(MRA_E_INVALID, std::string("internal plan error: ") + what);
+  };
+  double eta = 0.0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const uint64_t code = u.tcodes[r] & ((1ULL << 58) - 1);
+    const int64_t node = find_node(out, n, code);
+    if (node < 0 || node >= nout || out.first_child[node] < 0 ||
+        out.first_child[node] + 8 > nout)
+      bad("target node");
+    u.node[r] = (int32_t)node;
+    NSItem* fi = items + u.item_base + u.fpre[r];
+    LowItem* li = low + u.low_base + u.lpre[r];
     for (int64_t q = u.toff[r]; q < u.toff[r + 1]; ++q) {
       const Triple& t = u.sorted[q];
+      if (t.mu < 0 || t.mu >= M) bad("term index");
       const BlockEntry& be = *p.entry_tab[(size_t)n * M + t.mu];
-      const int32_t rx = (int32_t)(be.r_base + t.dx + be.D);
-      const int32_t ry = (int32_t)(be.r_base + t.dy + be.D);
-      const int32_t rz = (int32_t)(be.r_base + t.dz + be.D);
+      const int64_t rx = be.r_base + t.dx + be.D, ry = be.r_base + t.dy + be.D,
+                    rz = be.r_base + t.dz + be.D;
       if (!t.low) {
         NSItem it;
         it.src = f.interior[t.src];
         it.src_fc = f.first_child[it.src];
         it.mu = t.mu;
-        it.rx = rx;
-        it.ry = ry;
-        it.rz = rz;
+        it.rx = (int32_t)rx;
+        it.ry = (int32_t)ry;
+        it.rz = (int32_t)rz;
         it.tx = (int32_t)(be.t_base + t.dx + be.D);
         it.ty = (int32_t)(be.t_base + t.dy + be.D);
         it.tz = (int32_t)(be.t_base + t.dz + be.D);
-        u.items.push_back(it);
+        if (it.src < 0 || it.src >= nin || it.src_fc < 0 || it.src_fc + 8 > nin)
+          bad("source node");
+        if (std::min({rx, ry, rz}) < 0 || std::max({rx, ry, rz}) >= nR) bad("R block");
+        if (std::min({it.tx, it.ty, it.tz}) < 0 || std::max({it.tx, it.ty, it.tz}) >= nT)
+          bad("t block");
+        *fi++ = it;
       } else {
-        u.low_items.push_back({(int32_t)slot[t.src], (int32_t)t.mu, rx, ry, rz});
+        const int64_t sl = slot[t.src];
+        if (sl < 0 || sl >= nslots) bad("low-tier source block");
+        if (std::min({rx, ry, rz}) < 0 || std::max({rx, ry, rz}) >= nL) bad("low-tier block");
+        *li++ = {(int32_t)sl, (int32_t)t.mu, (int32_t)rx, (int32_t)ry, (int32_t)rz};
         const int ax = std::abs(t.dx), ay = std::abs(t.dy), az = std::abs(t.dz);
         const double N = (be.a[ax] + be.e[ax]) * (be.a[ay] + be.e[ay]) * (be.a[az] + be.e[az]) -
                          be.a[ax] * be.a[ay] * be.a[az];
-        u.eta_low += std::fabs(p.op->c[t.mu]) * N * L.bn[t.src - L.ib];
+        eta += std::fabs(p.op->c[t.mu]) * N * L.bn[t.src - L.ib];
       }
     }
-    const int32_t b1 = (int32_t)u.items.size(), l1 = (int32_t)u.low_items.size();
-    // sub = 0 marks "has a level-n subtraction"; the slot is assigned when combining
-    if (b1 > b0) u.tgt.push_back({0, (int32_t)node, fc, b0, b1, -1, n > 0 ? 0 : -1});
-    if (l1 > l0) u.low_tgt.push_back({0, (int32_t)node, fc, l0, l1, -1, -1});
   }
-  u.nlow = (int64_t)u.low_items.size();
-  u.flops_low = (double)u.nlow * per;
+  return eta;
 }
 
 }  // namespace
@@ -492,13 +447,14 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
           Job& jb = jobs[j];
           jb.be = &uops[u]->ensure(lv[jb.lev].n, jb.mu, jb.D);
         }
-        if (tiers) uops[u]->ensure_low();
       } catch (const Error& e) {
         errs[u] = e.msg;
       }
     });
     for (auto& e : errs)
       if (!e.empty()) fail(MRA_E_INVALID, e);
+    if (tiers)
+      for (Op* op : uops) op->ensure_low();   // data-parallel over blocks inside
     for (const Job& jb : jobs) {
       const LevelData& L = lv[jb.lev];
       plans[L.fn].entry_tab[(size_t)L.n * ops[L.fn]->c.size() + jb.mu] = jb.be;
@@ -570,117 +526,120 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
     build_output_tree(ctx, plans[i], tc);
   });
   mark("output trees");
-  parallel_for(units.size(), [&](size_t i, unsigned) {
-    unit_items(units[i], plans[units[i].fn], lv[unit_lev[i]], fu_index[units[i].fn]);
-  });
-  // concatenate the units of each function in level order (jobs are function-major,
-  // level-major, so units already are)
-  for (Unit& u : units) {
-    Plan& p = plans[u.fn];
-    const int32_t base = (int32_t)p.items.size();
-    p.items.insert(p.items.end(), u.items.begin(), u.items.end());
-    for (TargetRange r : u.tgt) {
-      r.beg += base;
-      r.end += base;
-      p.tgt.push_back(r);
-      if (u.n > 0) p.tgt_sub.push_back(r);
-    }
-    const int32_t lbase = (int32_t)p.low_items.size();
-    p.low_items.insert(p.low_items.end(), u.low_items.begin(), u.low_items.end());
-    for (TargetRange r : u.low_tgt) {
-      r.beg += lbase;
-      r.end += lbase;
-      p.low_tgt.push_back(r);
-    }
-    p.flops += u.flops;
-    p.flops_low += u.flops_low;
-    p.eta_low += u.eta_low;
-    p.nlow += u.nlow;
-    p.ntriples += (int64_t)u.sorted.size();
-  }
-  mark("work items");
-  // ---- 4. combine the batch
+  // ---- 4. item offsets (per unit and target: FP64 items, then BF16 items), filled in
+  // parallel over target chunks directly into the pinned upload buffer
   std::vector<Op*> uniq_ops;
   for (Op* op : ops)
     if (std::find(uniq_ops.begin(), uniq_ops.end(), op) == uniq_ops.end()) uniq_ops.push_back(op);
   for (Op* op : uniq_ops) op->sync_device();
-  std::vector<NSItem> items;
-  std::vector<LowItem> low_items;
+  size_t n_items = 0, n_low = 0;
+  int64_t ntriples = 0, ntargets = 0;
+  double flops = 0.0, flops_low = 0.0;
+  const double f_ns = 6.0 * std::pow(2.0 * k, 4), f_sub = 6.0 * std::pow((double)k, 4);
+  for (Unit& u : units) {
+    const size_t nt = u.tcodes.size();
+    u.fpre.assign(nt + 1, 0);
+    u.lpre.assign(nt + 1, 0);
+    u.node.assign(nt, -1);
+    for (size_t r = 0; r < nt; ++r) {
+      u.fpre[r + 1] = u.fpre[r] + (u.tmid[r] - u.toff[r]);
+      u.lpre[r + 1] = u.lpre[r] + (u.toff[r + 1] - u.tmid[r]);
+    }
+    u.item_base = n_items;
+    u.low_base = n_low;
+    n_items += (size_t)u.fpre[nt];
+    n_low += (size_t)u.lpre[nt];
+    const double per = f_ns + (u.n > 0 ? f_sub : 0.0);
+    ntriples += (int64_t)u.sorted.size();
+    ntargets += (int64_t)nt;
+    flops += (double)u.sorted.size() * per;
+    flops_low += (double)u.lpre[nt] * per;
+  }
+  if (n_items > (size_t)INT32_MAX || n_low > (size_t)INT32_MAX)
+    fail(MRA_E_UNSUPPORTED, "too many triples for one apply");
+  Arena& A1 = ctx->arena[1];
+  A1.begin(ctx);
+  const size_t o_items = A1.reserve(n_items * sizeof(NSItem));
+  const size_t o_litems = A1.reserve(n_low * sizeof(LowItem));
+  NSItem* items_h = A1.host_at<NSItem>(o_items);
+  LowItem* low_h = A1.host_at<LowItem>(o_litems);
+  struct Task {
+    size_t u;
+    int64_t r0, r1;
+  };
+  std::vector<Task> tasks;
+  for (size_t ui = 0; ui < units.size(); ++ui) {
+    const Unit& u = units[ui];
+    const int64_t nt = (int64_t)u.tcodes.size();
+    for (int64_t r = 0; r < nt;) {
+      int64_t e = r, cnt = 0;
+      while (e < nt && cnt < 4096) cnt += u.toff[e + 1] - u.toff[e], ++e;
+      tasks.push_back({ui, r, e});
+      r = e;
+    }
+  }
+  std::vector<double> task_eta(tasks.size(), 0.0);
+  parallel_for(tasks.size(), [&](size_t ti, unsigned) {
+    const Task& t = tasks[ti];
+    Unit& u = units[t.u];
+    const Plan& p = plans[u.fn];
+    task_eta[ti] = fill_items(u, p, lv[unit_lev[t.u]], fu_index[u.fn], t.r0, t.r1, items_h,
+                              low_h, (int64_t)p.op->dR_blocks, (int64_t)p.op->dT_blocks,
+                              tiers ? (int64_t)p.op->dL_blocks : 0, (int64_t)fu_refs.size());
+  });
+  double eta_low = 0.0;
+  for (double e : task_eta) eta_low += e;   // fixed order
+  mark("work items");
+  // ---- 5. target ranges of the batch: level-n slots, split long lists, longest first
   std::vector<TargetRange> tgt_sub, work, low_work;
   std::vector<SplitTarget> splits;
   std::vector<NodeRef> sd_refs;
   int out_maxlev = 0;
-  size_t total_items = 0;
-  for (auto& p : plans) total_items += p.items.size();
-  const int64_t chunk = std::max<int64_t>(24, ((int64_t)total_items + 1023) / 1024);
+  const int64_t chunk = std::max<int64_t>(24, ((int64_t)n_items + 1023) / 1024);
   const bool fused = ns_kernel_fuses_subtraction(k);
   int32_t npartials = 0, nsub = 0;
   std::vector<std::vector<int32_t>> sub_of_node(nf);
-  double flops = 0.0, flops_low = 0.0, eta_low = 0.0;
-  int64_t ntriples = 0, nlow = 0, ntargets = 0, in_leaves = 0, out_nodes = 0, out_leaves = 0;
-  for (int i = 0; i < nf; ++i) {
-    Plan& p = plans[i];
-    validate(p, (int64_t)p.op->dR_blocks, (int64_t)p.op->dT_blocks,
-             tiers ? (int64_t)p.op->dL_blocks : 0, (int64_t)fu_refs.size());
-    const int32_t lbase = (int32_t)low_items.size();
-    low_items.insert(low_items.end(), p.low_items.begin(), p.low_items.end());
-    for (TargetRange r : p.low_tgt) {
-      r.fn = i;
-      r.beg += lbase;
-      r.end += lbase;
-      low_work.push_back(r);
-    }
-    flops_low += p.flops_low;
-    eta_low += p.eta_low;
-    nlow += p.nlow;
-    const int32_t base = (int32_t)items.size();
-    items.insert(items.end(), p.items.begin(), p.items.end());
-    sub_of_node[i].assign((size_t)p.out->nodes(), -1);
-    for (TargetRange r : p.tgt) {
-      r.fn = i;
-      r.beg += base;
-      r.end += base;
-      if (!fused || r.sub < 0) {
-        r.sub = -1;
-      } else {
-        r.sub = nsub++;
-        sub_of_node[i][r.node] = r.sub;
+  int64_t in_leaves = 0, out_nodes = 0, out_leaves = 0;
+  for (int i = 0; i < nf; ++i) sub_of_node[i].assign((size_t)plans[i].out->nodes(), -1);
+  for (const Unit& u : units) {
+    const int i = u.fn;
+    const Func& o = *plans[i].out;
+    for (size_t r = 0; r < u.tcodes.size(); ++r) {
+      const int32_t node = u.node[r], fc = o.first_child[node];
+      const int32_t lb = (int32_t)(u.low_base + u.lpre[r]), le = (int32_t)(u.low_base + u.lpre[r + 1]);
+      if (le > lb) low_work.push_back({i, node, fc, lb, le, -1, -1});
+      const int32_t b = (int32_t)(u.item_base + u.fpre[r]), e = (int32_t)(u.item_base + u.fpre[r + 1]);
+      if (e == b) continue;
+      int32_t sub = -1;
+      if (u.n > 0) {
+        if (fused) {
+          sub = nsub++;
+          sub_of_node[i][node] = sub;
+        } else {
+          tgt_sub.push_back({i, node, fc, b, e, -1, -1});
+        }
       }
-      int64_t len = r.end - r.beg;
+      const int64_t len = e - b;
       if (len <= chunk) {
-        work.push_back(r);
+        work.push_back({i, node, fc, b, e, -1, sub});
         continue;
       }
-      int32_t parts = (int32_t)((len + chunk - 1) / chunk);
+      const int32_t parts = (int32_t)((len + chunk - 1) / chunk);
       for (int32_t q = 0; q < parts; ++q) {
-        int32_t b = r.beg + (int32_t)(q * len / parts), e = r.beg + (int32_t)((q + 1) * len / parts);
-        work.push_back({i, r.node, r.fc, b, e, npartials + q, r.sub});
+        const int32_t qb = b + (int32_t)(q * len / parts), qe = b + (int32_t)((q + 1) * len / parts);
+        work.push_back({i, node, fc, qb, qe, npartials + q, sub});
       }
-      splits.push_back({i, r.fc, npartials, parts, r.sub});
+      splits.push_back({i, fc, npartials, parts, sub});
       npartials += parts;
     }
-    if (!fused)
-      for (TargetRange r : p.tgt_sub) {
-        r.fn = i;
-        r.beg += base;
-        r.end += base;
-        r.sub = -1;
-        tgt_sub.push_back(r);
-      }
-    flops += p.flops;
-    ntriples += p.ntriples;
-    ntargets += (int64_t)p.tgt.size();
-    in_leaves += (int64_t)p.f->leaves.size();
-    out_nodes += p.out->nodes();
-    out_leaves += (int64_t)p.out->leaves.size();
-    out_maxlev = std::max(out_maxlev, p.out->nlev);
   }
-  for (const TargetRange& r : work)
-    if (r.sub >= nsub || r.partial >= npartials)
-      fail(MRA_E_INVALID, "internal plan error: slot index");
-  for (const SplitTarget& sp : splits)
-    if (sp.sub >= nsub || sp.first < 0 || sp.first + sp.count > npartials)
-      fail(MRA_E_INVALID, "internal plan error: split target");
+  for (int i = 0; i < nf; ++i) {
+    in_leaves += (int64_t)plans[i].f->leaves.size();
+    out_nodes += plans[i].out->nodes();
+    out_leaves += (int64_t)plans[i].out->leaves.size();
+    out_maxlev = std::max(out_maxlev, plans[i].out->nlev);
+  }
+  const int64_t nlow = (int64_t)n_low;
   // work with the longest lists first
   auto by_len = [](const TargetRange& a, const TargetRange& b) {
     return (a.end - a.beg) > (b.end - b.beg);
@@ -713,12 +672,10 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
     c_tab[i] = plans[i].op->d_c.p;
     l_tab[i] = plans[i].op->dL.p;
   }
-  Arena& A1 = ctx->arena[1];
-  A1.begin(ctx);
   const size_t o_out = A1.put(out_tab), o_r = A1.put(r_tab), o_t = A1.put(t_tab),
-               o_c = A1.put(c_tab), o_l = A1.put(l_tab), o_items = A1.put(items),
-               o_work = A1.put(work), o_sub = A1.put(tgt_sub), o_spl = A1.put(splits),
-               o_sd = A1.put(sd_refs), o_litems = A1.put(low_items), o_lwork = A1.put(low_work);
+               o_c = A1.put(c_tab), o_l = A1.put(l_tab), o_work = A1.put(work),
+               o_sub = A1.put(tgt_sub), o_spl = A1.put(splits), o_sd = A1.put(sd_refs),
+               o_lwork = A1.put(low_work);
   const size_t o_part = A1.scratch((size_t)npartials * 9 * K3 * sizeof(double));  // (2k)^3 + k^3
   const size_t o_subb = A1.scratch((size_t)nsub * K3 * sizeof(double));
   A1.commit();
@@ -739,7 +696,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   mark("combine + uploads");
   double t_plan1 = now_ms();
 
-  // ---- 5. device work
+  // ---- 6. device work
   for (int i = 0; i < nf; ++i) launch_zero(out_tab[i], plans[i].out->coeff.n, ctx->stream);
   hip_check(hipEventRecord(ctx->ev[2], ctx->stream), "event");
   launch_apply_ns(k, in_tab_d, out_tab_d, items_d, work_d, (int)work.size(), r_tab_d,

@@ -60,6 +60,101 @@ void Ctx::dfree(void* p) {
 
 void Ctx::sync() { hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
 
+// ------------------------------------------------------------------------------- pool
+namespace {
+thread_local bool t_in_pool = false;   // set on pool workers and on a caller inside run()
+}
+
+Pool& Pool::get() {
+  static Pool pool;
+  return pool;
+}
+
+Pool::Pool() {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned n = std::min(16u, hw);
+  for (unsigned i = 1; i < n; ++i) th_.emplace_back([this, i] { loop(i); });
+}
+
+Pool::~Pool() {
+  {
+    std::lock_guard<std::mutex> lk(m_);
+    stop_.store(true);
+  }
+  cv_.notify_all();
+  for (auto& t : th_) t.join();
+}
+
+void Pool::work(unsigned id) {
+  for (;;) {
+    const size_t i = next_.fetch_add(1, std::memory_order_relaxed);
+    if (i >= count_) break;
+    try {
+      (*fn_)(i, id);
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(m_);
+      if (!err_) err_ = std::current_exception();
+    }
+  }
+}
+
+// Workers spin briefly on the generation counter before sleeping, because the planner
+// issues its loops in quick succession.
+void Pool::loop(unsigned id) {
+  t_in_pool = true;
+  uint64_t seen = 0;
+  for (;;) {
+    for (int spin = 0; spin < 4000 && gen_.load(std::memory_order_acquire) == seen &&
+                       !stop_.load(std::memory_order_relaxed);
+         ++spin)
+      std::this_thread::yield();
+    if (gen_.load(std::memory_order_acquire) == seen) {
+      std::unique_lock<std::mutex> lk(m_);
+      cv_.wait(lk, [&] { return stop_.load() || gen_.load() != seen; });
+    }
+    if (stop_.load()) return;
+    seen = gen_.load(std::memory_order_acquire);
+    work(id);
+    if (busy_.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+      std::lock_guard<std::mutex> lk(m_);
+      done_.notify_one();
+    }
+  }
+}
+
+void Pool::run(size_t count, const std::function<void(size_t, unsigned)>& fn) {
+  if (count == 0) return;
+  if (th_.empty() || count == 1 || t_in_pool) {   // nested calls run serially
+    for (size_t i = 0; i < count; ++i) fn(i, 0);
+    return;
+  }
+  struct Flag {
+    Flag() { t_in_pool = true; }
+    ~Flag() { t_in_pool = false; }
+  } flag;
+  {
+    std::lock_guard<std::mutex> lk(m_);
+    fn_ = &fn;
+    count_ = count;
+    next_.store(0, std::memory_order_relaxed);
+    busy_.store((unsigned)th_.size(), std::memory_order_relaxed);
+    err_ = nullptr;
+    gen_.fetch_add(1, std::memory_order_release);
+  }
+  cv_.notify_all();
+  work(0);
+  for (int spin = 0; spin < 4000 && busy_.load(std::memory_order_acquire) != 0; ++spin)
+    std::this_thread::yield();
+  std::exception_ptr e;
+  {
+    std::unique_lock<std::mutex> lk(m_);
+    done_.wait(lk, [&] { return busy_.load() == 0; });
+    e = err_;
+    fn_ = nullptr;
+  }
+  if (e) std::rethrow_exception(e);
+}
+
 // ------------------------------------------------------------------------------ arena
 Arena::~Arena() {
   if (host) (void)hipHostFree(host);
@@ -71,10 +166,11 @@ Arena::~Arena() {
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-size_t Arena::put_bytes(const void* src, size_t bytes) {
+size_t Arena::reserve(size_t bytes) {
   const size_t off = used;
   const size_t end = align256(off + bytes);
   if (end > host_cap) {
+    // host regions handed out earlier keep their offsets; their contents move with the buffer
     size_t cap = std::max<size_t>(end, host_cap + host_cap / 2);
     cap = std::max<size_t>(cap, (size_t)1 << 20);
     void* p = nullptr;
@@ -86,9 +182,13 @@ size_t Arena::put_bytes(const void* src, size_t bytes) {
     host = static_cast<char*>(p);
     host_cap = cap;
   }
-  if (bytes) std::memcpy(host + off, src, bytes);
   used = end;
-  pending.push_back({off, bytes});
+  return off;
+}
+
+size_t Arena::put_bytes(const void* src, size_t bytes) {
+  const size_t off = reserve(bytes);
+  if (bytes) std::memcpy(host + off, src, bytes);
   return off;
 }
 
@@ -114,7 +214,6 @@ void Arena::commit() {
   if (used)
     hip_check(hipMemcpyAsync(dev, host, used, hipMemcpyHostToDevice, ctx->stream),
               "hipMemcpyAsync H2D");
-  pending.clear();
 }
 
 // ------------------------------------------------------------------------ block cache
@@ -256,17 +355,10 @@ void Op::ensure_low() {
       }
     }
   };
-  const size_t count = nb - first;
-  const unsigned nthr = (unsigned)std::max<size_t>(
-      1, std::min<size_t>({(size_t)16, (size_t)std::max(1u, std::thread::hardware_concurrency()),
-                           count / 64 + 1}));
-  std::vector<std::thread> th;
-  for (unsigned t = 1; t < nthr; ++t)
-    th.emplace_back([&, t] {
-      for (size_t b = first + t; b < nb; b += nthr) one(b);
-    });
-  for (size_t b = first; b < nb; b += nthr) one(b);
-  for (auto& t : th) t.join();
+  const size_t count = nb - first, per = 64;
+  Pool::get().run((count + per - 1) / per, [&](size_t c, unsigned) {
+    for (size_t b = first + c * per; b < std::min(nb, first + (c + 1) * per); ++b) one(b);
+  });
   hL_blocks = nb;
 }
 

@@ -11,11 +11,16 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <condition_variable>
 #include <cstdint>
+#include <exception>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/mra.h"
@@ -32,6 +37,34 @@ struct Error {
 };
 [[noreturn]] void fail(mra_status code, const std::string& msg);
 void hip_check(hipError_t e, const char* what);
+
+// ------------------------------------------------------------------------ host threads
+// Persistent workers for the planner's data-parallel loops (created once per process, at
+// most 16 including the calling thread).  run(count, fn) calls fn(i, worker) for every
+// i < count, the caller taking part as worker 0, and returns when all calls are done; the
+// first exception thrown by fn is rethrown on the caller.  Not reentrant.
+class Pool {
+ public:
+  static Pool& get();
+  unsigned workers() const { return (unsigned)th_.size() + 1; }
+  void run(size_t count, const std::function<void(size_t, unsigned)>& fn);
+  ~Pool();
+
+ private:
+  Pool();
+  void loop(unsigned id);
+  std::vector<std::thread> th_;
+  std::mutex m_;
+  std::condition_variable cv_, done_;
+  const std::function<void(size_t, unsigned)>* fn_ = nullptr;
+  size_t count_ = 0;
+  std::atomic<size_t> next_{0};
+  std::atomic<unsigned> busy_{0};
+  std::atomic<uint64_t> gen_{0};
+  std::atomic<bool> stop_{false};
+  std::exception_ptr err_;
+  void work(unsigned id);
+};
 
 // ------------------------------------------------------------------------- quadrature
 struct GLRule {
@@ -84,14 +117,15 @@ struct Arena {
   char* scr = nullptr;
   size_t scr_cap = 0;
   size_t used = 0, scr_used = 0;
-  std::vector<std::pair<size_t, size_t>> pending;   // (offset, bytes) awaiting the copy
   ~Arena();
   void begin(Ctx* c) {
     ctx = c;
     used = scr_used = 0;
-    pending.clear();
   }
   size_t put_bytes(const void* src, size_t bytes);    // returns the device offset
+  size_t reserve(size_t bytes);                       // host region filled by the caller
+  template <class T>
+  T* host_at(size_t off) const { return reinterpret_cast<T*>(host + off); }
   template <class T>
   size_t put(const std::vector<T>& v) { return put_bytes(v.data(), v.size() * sizeof(T)); }
   size_t scratch(size_t bytes);                       // device-only region, offset
