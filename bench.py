@@ -36,8 +36,8 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="coulomb_k10",
-                   choices=["coulomb_k10", "coulomb_k12_fp64", "coulomb_k12_mixed",
-                            "bsh_batch_k10"])
+                   choices=["gauss_std_k8", "coulomb_k10", "coulomb_k12_fp64",
+                            "coulomb_k12_mixed", "bsh_batch_k10"])
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="approximate CPU work of the oracle baseline sample (0 = skip)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -93,6 +93,15 @@ def cpu_baseline(name, budget_s):
 
 def setup(ctx, name):
     """Functions, operators and tau for a workload; returns (funcs, ops, tau, k, config)."""
+    if name == "gauss_std_k8":
+        w = W.WORKLOADS[name]
+        f = ctx.project([w["f_coeff"]], [w["f_expnt"]], [[0.0, 0.0, 0.0]], w["k"], 1.0,
+                        initial_level=w["level"], max_level=w["level"])
+        op = ctx.op_gaussians(w["k"], w["op_c"], w["op_t"])
+        cfg = {"workload": name, "k": w["k"], "level": w["level"], "boxes": 8 ** w["level"],
+               "operator": "exp(-2 x^2)", "displacements": (2 * w["disp_radius"] + 1) ** 3,
+               "form": "standard", "precision": "fp64"}
+        return [f], [op], None, w["k"], cfg
     if name == "bsh_batch_k10":
         w = W.WORKLOADS[name]
         funcs, ops, mus, ng = [], [], [], []
@@ -122,18 +131,30 @@ def setup(ctx, name):
     return [f], [op], w["tau_rel"] * w["thresh"], w["k"], cfg
 
 
+def kernel_source_sha(kernel):
+    """sha256[:16] of the source of `kernel` (its definition up to the next section rule in
+    kernels.hip), so that counters stay valid while other kernels of the file change."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1507_01888_amd", "csrc", "kernels.hip")).read()
+    base = kernel.split("<")[0]
+    i = src.find(" void %s(" % base)
+    if i < 0:
+        return None
+    i = src.rfind("\ntemplate", 0, i)
+    j = src.find("\n// ---", i)
+    return hashlib.sha256(src[i:j].encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when the summary was taken on a different version of the kernel source."""
+    when the summary was taken on a different version of the kernel's source."""
     import glob
-    import hashlib
-    src = os.path.join(ROOT, "paper_1507_01888_amd", "csrc", "kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = kernel_source_sha(kernel)
     for path in glob.glob(os.path.join(ROOT, "profiles", "*_pmc.md")):
         for line in open(path):
             if line.startswith("pmc: "):
                 rec = json.loads(line[5:])
-                if rec.get("kernel") == kernel and rec.get("kernels_hip_sha256_16") == sha:
+                if rec.get("kernel") == kernel and rec.get("kernel_src_sha256_16") == sha:
                     return 1024.0 * (rec["fetch_kib"] * rec["fetch_factor"]
                                      + rec["write_kib"] * rec["write_factor"])
     return None
@@ -157,7 +178,10 @@ def main():
     tier = cfg.get("tau_tier", 0.0)
 
     def step(tau_tier, keep=False):
-        if len(funcs) == 1:
+        if tau is None:     # standard form on a uniform tree, no screening
+            gs = [ctx.apply(ops[0], funcs[0], form="standard",
+                            disp_radius=W.WORKLOADS[args.workload]["disp_radius"])]
+        elif len(funcs) == 1:
             gs = [ctx.apply(ops[0], funcs[0], tau_drop=tau, tau_tier=tau_tier)]
         else:
             gs = ctx.apply_batch(ops, funcs, tau_drop=tau, tau_tier=tau_tier)
@@ -208,6 +232,8 @@ def main():
     kname = {8: "apply_ns_mfma_kernel<8>", 10: "apply_ns_mfma_kernel<10>",
              12: "apply_ns_own_kernel<12>", 14: "apply_ns_stream_kernel<14>"}.get(
                  k, "apply_ns_kernel<%d>" % k)
+    if tau is None:        # standard form: the VALU kernel does 6 k^4 flop per triple
+        fused, kernel_flops, kname = False, stats[0]["useful_flops"], "apply_std_kernel<%d>" % k
     achieved = kernel_flops / (main_ms * 1e-3) / 1e12
     low_ms = sum(s["ms_low_kernel"] for s in stats) / len(stats)
     out = {

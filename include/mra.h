@@ -166,6 +166,10 @@ mra_status mra_op_free(mra_op* op);
 mra_status mra_apply(mra_ctx* ctx, const mra_op* op, const mra_func* f,
                      const mra_apply_params* params, mra_func** out);
 
+/* (The non-standard form needs at least one refined box: an input whose root is a leaf is
+ * rejected with MRA_E_INVALID.  A result without any kept triple is the zero function on
+ * the root box.) */
+
 /* op_i(f_i) for i < n in one pass: filter-up, screening, transform-and-accumulate and
  * sum-down each run as one launch sequence over all functions (non-standard form only).
  * Functions may have different trees and operators different terms, but all share k.

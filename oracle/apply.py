@@ -242,8 +242,10 @@ def nonstandard_contributions(f, op, tau_drop, sample_targets=None, only_levels=
 
 
 def output_tree_nodes(contrib):
-    """Nodes of the output tree: targets, their 8 children, ancestors, closed under siblings."""
-    nodes = set()
+    """Nodes of the output tree: targets, their 8 children, ancestors, closed under siblings.
+    The root is always present (it is the ancestor of every box; with no target at all the
+    result is the zero function on the root)."""
+    nodes = {(0, 0, 0, 0)}
     for n, (keys, acc, sub) in contrib.items():
         for kk in keys:
             nodes.add(kk)

@@ -96,29 +96,60 @@ struct Plan {
   std::vector<const BlockEntry*> entry_tab;  // (level, mu) -> cache entry
 };
 
-// Output tree of one function from its sorted target codes: targets, their children,
-// ancestors, closed under siblings (full octree).
+// Output tree of one function from its target codes (ascending by level, then code):
+// targets, their children, ancestors, closed under siblings (full octree).  Every level's
+// code list is built from at most three ascending runs (children of the level above, the
+// level's own targets, parents of the level below), which are merged rather than sorted.
 void build_output_tree(Ctx* ctx, Plan& p, const std::vector<uint64_t>& tcodes) {
   Func& out = *p.out;
   int maxlev = 0;
   for (uint64_t t : tcodes) maxlev = std::max(maxlev, (int)(t >> 58) + 1);
-  std::vector<std::vector<uint64_t>> sets(std::max(maxlev + 1, 1));
+  const int L = std::max(maxlev + 1, 1);
+  std::vector<std::vector<uint64_t>> sets(L);
+  std::vector<std::vector<size_t>> runs(L);   // start offsets of ascending runs
+  auto start_run = [&](int n) {
+    if (runs[n].empty() || runs[n].back() != sets[n].size()) runs[n].push_back(sets[n].size());
+  };
+  int cur = -1;
   for (uint64_t t : tcodes) {
-    int n = (int)(t >> 58);
-    uint64_t code = t & ((1ULL << 58) - 1);
+    const int n = (int)(t >> 58);
+    const uint64_t code = t & ((1ULL << 58) - 1);
+    if (n != cur) {
+      start_run(n);
+      start_run(n + 1);
+      cur = n;
+    }
     sets[n].push_back(code);
     for (int c = 0; c < 8; ++c) sets[n + 1].push_back((code << 3) | c);
   }
+  // level n + 1 received the children of level n before level n + 1's own targets, so the
+  // runs are recorded in push order; merge them pairwise
+  auto merge_runs = [&](int n) {
+    auto& v = sets[n];
+    auto& r = runs[n];
+    r.push_back(v.size());
+    while (r.size() > 2) {
+      std::vector<size_t> nr{r[0]};
+      for (size_t i = 0; i + 2 < r.size(); i += 2) {
+        std::inplace_merge(v.begin() + r[i], v.begin() + r[i + 1], v.begin() + r[i + 2]);
+        nr.push_back(r[i + 2]);
+      }
+      if ((r.size() - 1) % 2 == 1) nr.push_back(r.back());
+      r.swap(nr);
+    }
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  };
   sets[0].push_back(0);
-  for (int n = (int)sets.size() - 1; n >= 1; --n) {
+  if (runs[0].empty() || runs[0].front() != 0) runs[0].insert(runs[0].begin(), 0);
+  for (int n = L - 1; n >= 1; --n) {
+    merge_runs(n);
     auto& s = sets[n];
-    std::sort(s.begin(), s.end());
-    s.erase(std::unique(s.begin(), s.end()), s.end());
     std::vector<uint64_t> full;
     full.reserve(s.size() * 2);
     uint64_t lastp = ~0ULL;
+    start_run(n - 1);
     for (uint64_t code : s) {
-      uint64_t par = code >> 3;
+      const uint64_t par = code >> 3;
       if (par == lastp) continue;
       lastp = par;
       for (int c = 0; c < 8; ++c) full.push_back((par << 3) | c);
@@ -126,8 +157,7 @@ void build_output_tree(Ctx* ctx, Plan& p, const std::vector<uint64_t>& tcodes) {
     }
     s.swap(full);
   }
-  std::sort(sets[0].begin(), sets[0].end());
-  sets[0].erase(std::unique(sets[0].begin(), sets[0].end()), sets[0].end());
+  merge_runs(0);
   out.ctx = ctx;
   out.k = p.f->k;
   build_tree(out, sets);
@@ -309,6 +339,9 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
                              const std::vector<Func*>& outs) {
   const int nf = (int)funcs.size();
   if (nf == 0) return;
+  for (Func* f : funcs)
+    if (f->interior.empty())
+      fail(MRA_E_INVALID, "non-standard apply needs a refined root (project with initial_level >= 1)");
   const int k = funcs[0]->k;
   const int K3 = k * k * k;
   const bool tiers = tau_tier > 0.0;
@@ -663,9 +696,13 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   std::vector<double*> out_tab(nf);
   std::vector<const double*> r_tab(nf), t_tab(nf), c_tab(nf);
   std::vector<const uint16_t*> l_tab(nf);
+  std::vector<int64_t> out_len(nf);
+  size_t max_len = 0;
   for (int i = 0; i < nf; ++i) {
     Func& o = *plans[i].out;
     o.coeff.alloc(ctx, (size_t)o.nodes() * K3);
+    out_len[i] = (int64_t)o.coeff.n;
+    max_len = std::max(max_len, o.coeff.n);
     out_tab[i] = o.coeff.p;
     r_tab[i] = plans[i].op->dR.p;
     t_tab[i] = plans[i].op->dT.p;
@@ -675,7 +712,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   const size_t o_out = A1.put(out_tab), o_r = A1.put(r_tab), o_t = A1.put(t_tab),
                o_c = A1.put(c_tab), o_l = A1.put(l_tab), o_work = A1.put(work),
                o_sub = A1.put(tgt_sub), o_spl = A1.put(splits), o_sd = A1.put(sd_refs),
-               o_lwork = A1.put(low_work);
+               o_lwork = A1.put(low_work), o_olen = A1.put(out_len);
   const size_t o_part = A1.scratch((size_t)npartials * 9 * K3 * sizeof(double));  // (2k)^3 + k^3
   const size_t o_subb = A1.scratch((size_t)nsub * K3 * sizeof(double));
   A1.commit();
@@ -697,7 +734,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   double t_plan1 = now_ms();
 
   // ---- 6. device work
-  for (int i = 0; i < nf; ++i) launch_zero(out_tab[i], plans[i].out->coeff.n, ctx->stream);
+  launch_zero_batch(out_tab_d, A1.at<int64_t>(o_olen), nf, max_len, ctx->stream);
   hip_check(hipEventRecord(ctx->ev[2], ctx->stream), "event");
   launch_apply_ns(k, in_tab_d, out_tab_d, items_d, work_d, (int)work.size(), r_tab_d,
                   t_tab_d, c_tab_d, partials_d, subbuf_d, ctx->stream);

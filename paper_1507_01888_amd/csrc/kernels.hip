@@ -33,6 +33,15 @@ __global__ void zero_kernel(double* __restrict__ p, size_t n) {
   for (; i < n; i += stride) p[i] = 0.0;
 }
 
+// Clears arrays tab[y][0 .. len[y]) for every y = blockIdx.y.
+__global__ void zero_batch_kernel(double* const* __restrict__ tab, const int64_t* __restrict__ len) {
+  double* __restrict__ p = tab[blockIdx.y];
+  const size_t n = (size_t)len[blockIdx.y];
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0.0;
+}
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -268,6 +277,36 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(
   }
 }
 
+// ------------------------------------------------------- LDS layouts of the 4x4x4 operands
+// The 64-bit LDS reads of gfx950 are served a quarter wave (16 lanes, fixed kk = lane >> 4)
+// at a time; they are conflict free when those 16 lanes address 16 distinct 8-byte slots
+// modulo 16.  A tensor read as a 4x4x4 A operand (lane 16 kk + 4 bb + ii reads
+// T[4xs + kk][4yt + ii][4zq + bb]) is therefore stored quad-blocked,
+// [x][y/4][z/4][y%4][z%4]; the exchange tensor, written with (b, z) and read with (a, b)
+// varying inside a quarter wave, is stored in 4x4x4 cubes with the z slot rotated by a%4.
+template <int Q>
+__device__ __forceinline__ int qb_off(int x, int y, int z) {
+  return x * (16 * Q * Q) + ((y >> 2) * Q + (z >> 2)) * 16 + (y & 3) * 4 + (z & 3);
+}
+template <int Q>
+__device__ __forceinline__ int sk_off(int a, int b, int z) {
+  return (((a >> 2) * Q + (b >> 2)) * Q + (z >> 2)) * 64 + (a & 3) * 16 + (b & 3) * 4 +
+         (((z & 3) + (a & 3)) & 3);
+}
+// True when T[x][y][z] with strides (sx, sy, 1) is read conflict free as such an operand.
+constexpr bool quarter_distinct(int sx, int sy) {
+  for (int kk = 0; kk < 4; ++kk) {
+    bool seen[16] = {};
+    for (int ii = 0; ii < 4; ++ii)
+      for (int bb = 0; bb < 4; ++bb) {
+        const int slot = (kk * sx + ii * sy + bb) % 16;
+        if (seen[slot]) return false;
+        seen[slot] = true;
+      }
+  }
+  return true;
+}
+
 // ------------------------------------------------------------------- apply (NS, MFMA)
 // FP64 matrix-core version for even k (2k = 4Q).  Uses v_mfma_f64_4x4x4f64, which performs
 // four independent 4x4x4 products ("blocks") per instruction at the full FP64 matrix rate
@@ -374,7 +413,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
       for (int e = tid; e < 8 * K3; e += 256) {
         int c = e / K3, r = e - c * K3;
         int i = r / K2, j = (r / K) % K, m = r % K;
-        Xs[((((c >> 2) & 1) * K + i) * N + ((c >> 1) & 1) * K + j) * N + (c & 1) * K + m] =
+        Xs[qb_off<Q>(((c >> 2) & 1) * K + i, ((c >> 1) & 1) * K + j, (c & 1) * K + m)] =
             in[(size_t)(item.src_fc + c) * K3 + r];
       }
       loaded = item.src_fc;
@@ -402,7 +441,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
       for (int xs = 0; xs < Q; ++xs)
 #pragma unroll
         for (int yt = 0; yt < Q; ++yt) {
-          double a = Xs[((4 * xs + lk) * N + 4 * yt + li) * N + 4 * zq + lb];
+          double a = Xs[qb_off<Q>(4 * xs + lk, 4 * yt + li, 4 * zq + lb)];
 #pragma unroll
           for (int at = 0; at < Q; ++at)
             d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rx[xs][at], d1[at][yt], 0, 0, 0);
@@ -419,7 +458,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
             d2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], ry[ys][bt], d2[bt], 0, 0, 0);
 #pragma unroll
         for (int bt = 0; bt < Q; ++bt)
-          Zs[((4 * at + lk) * N + 4 * bt + li) * N + 4 * zq + lb] = d2[bt];
+          Zs[sk_off<Q>(4 * at + lk, 4 * bt + li, 4 * zq + lb)] = d2[bt];
       }
     }
     // ---- leftover (z-quad >= 4) pairs, round robin over the waves
@@ -436,7 +475,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
           const double b = RXs[(4 * xs + lk) * N + 4 * at + li];
 #pragma unroll
           for (int yt = 0; yt < Q; ++yt) {
-            double a = Xs[((4 * xs + lk) * N + 4 * yt + li) * N + 4 * zq + lb];
+            double a = Xs[qb_off<Q>(4 * xs + lk, 4 * yt + li, 4 * zq + lb)];
             d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, d1[yt], 0, 0, 0);
           }
         }
@@ -450,7 +489,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
             d2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ry[ys][bt], d2[bt], 0, 0, 0);
 #pragma unroll
         for (int bt = 0; bt < Q; ++bt)
-          Zs[((4 * at + lk) * N + 4 * bt + li) * N + 4 * zq + lb] = d2[bt];
+          Zs[sk_off<Q>(4 * at + lk, 4 * bt + li, 4 * zq + lb)] = d2[bt];
       }
     }
     // ---- subtraction, steps 1 and 2: (t_x, t_y) on s_P, one z-quad per wave
@@ -495,7 +534,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
             d2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], ty[ys][bt], d2[bt], 0, 0, 0);
 #pragma unroll
         for (int bt = 0; bt < Q2; ++bt)
-          Z2[((4 * at + lk) * KP + 4 * bt + li) * KP + 4 * zq + lb] = d2[bt];
+          Z2[sk_off<Q2>(4 * at + lk, 4 * bt + li, 4 * zq + lb)] = d2[bt];
       }
     }
     // the next triple's operator blocks travel while step 3 runs
@@ -519,7 +558,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
           const int at3 = p / Q2, bt3 = p % Q2;
 #pragma unroll
           for (int zs = 0; zs < Q2; ++zs) {
-            double a = Z2[((4 * at3 + lb) * KP + 4 * bt3 + li) * KP + 4 * zs + lk];
+            double a = Z2[sk_off<Q2>(4 * at3 + lb, 4 * bt3 + li, 4 * zs + lk)];
 #pragma unroll
             for (int ct = 0; ct < Q2; ++ct)
               sacc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, tz[zs][ct], sacc[e][ct], 0, 0, 0);
@@ -541,7 +580,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
           const int at3 = p / Q, bt3 = p % Q;
 #pragma unroll
           for (int zs = 0; zs < Q; ++zs) {
-            double a = Zs[((4 * at3 + lb) * N + 4 * bt3 + li) * N + 4 * zs + lk];
+            double a = Zs[sk_off<Q>(4 * at3 + lb, 4 * bt3 + li, 4 * zs + lk)];
 #pragma unroll
             for (int ct = 0; ct < Q; ++ct)
               acc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rz[zs][ct], acc[e][ct], 0, 0, 0);
@@ -777,29 +816,6 @@ __global__ __launch_bounds__(256) void leaf_reduce_kernel(
 }
 
 // ---------------------------------------------- apply (NS, MFMA, a-quad ownership per wave)
-// LDS strides of a tensor T[x][y][z] (z contiguous) read as the A operand of the 4x4x4
-// matrix-core product (lane = 16 kk + 4 bb + ii reads T[4xs + kk][4yt + ii][4zq + bb]):
-// the 64 lanes hit every 8-byte slot of the 32-slot bank cycle exactly twice, the minimum.
-constexpr bool lds_spread(int sx, int sy) {
-  int cnt[32] = {};
-  for (int l = 0; l < 64; ++l) ++cnt[((l >> 4) * sx + (l & 3) * sy + ((l >> 2) & 3)) % 32];
-  for (int c = 0; c < 32; ++c)
-    if (cnt[c] != 2) return false;
-  return true;
-}
-constexpr int lds_sy(int n) {
-  for (int sy = n; sy < n + 16; ++sy)
-    for (int sx = n * sy; sx < n * sy + 64; ++sx)
-      if (lds_spread(sx, sy)) return sy;
-  return -1;
-}
-constexpr int lds_sx(int n) {
-  const int sy = lds_sy(n);
-  for (int sx = n * sy; sx < n * sy + 64; ++sx)
-    if (lds_spread(sx, sy)) return sx;
-  return -1;
-}
-
 // FP64 matrix-core kernel for even k in [8, 12] (2k = 4Q).  Same 4x4x4 (four blocks)
 // product chain as apply_ns_mfma_kernel: step 1 contracts x (block index = z inside a
 // z-quad), step 2 contracts y in registers.  The work of a triple is split into (a-quad,
@@ -822,12 +838,9 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
   static_assert(N % 4 == 0 && Q >= 4 && Q <= 6, "even k in [8, 12]");
   constexpr int NU = Q * Q;                              // (a-quad, z-quad) units
   constexpr int Q2 = (K + 3) / 4, KP = 4 * Q2, SU = Q2 * Q2;
-  constexpr int XSY = lds_sy(N), XSX = lds_sx(N), SSY = lds_sy(KP), SSX = lds_sx(KP);
-  static_assert(XSY > 0 && XSX > 0 && SSY > 0 && SSX > 0, "stride search");
-  static_assert(N * XSX >= N3 && KP * SSX >= K3, "end-of-target sums reuse the tensors");
   constexpr int OPS = 3 * N2 + 3 * K2, OPS_PER_LANE = (OPS + 255) / 256;
-  __shared__ double Xs[N * XSX];    // children block B_P [x][y][z]; at the end: sum buffer
-  __shared__ double Ss[KP * SSX];   // s_P zero-padded to KP^3; at the end: sum buffer
+  __shared__ double Xs[N3];          // children block B_P, quad-blocked; at the end: sums
+  __shared__ double Ss[KP * KP * KP]; // s_P zero-padded to KP^3, quad-blocked; at the end: sums
   __shared__ double Os[2][OPS];     // R_x^T, R_y^T, R_z^T, t_x^T, t_y^T, t_z^T
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -905,14 +918,14 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
       for (int e = tid; e < 8 * K3; e += 256) {
         const int c = e / K3, r = e - c * K3;
         const int i = r / K2, j = (r / K) % K, m = r % K;
-        Xs[(((c >> 2) & 1) * K + i) * XSX + (((c >> 1) & 1) * K + j) * XSY + (c & 1) * K + m] =
+        Xs[qb_off<Q>(((c >> 2) & 1) * K + i, ((c >> 1) & 1) * K + j, (c & 1) * K + m)] =
             in[(size_t)(item.src_fc + c) * K3 + r];
       }
       if (with_sub) {
         const double* __restrict__ sp = in + (size_t)item.src * K3;
         for (int e = tid; e < KP * KP * KP; e += 256) {
           const int x = e / (KP * KP), y = (e / KP) % KP, z = e % KP;
-          Ss[x * SSX + y * SSY + z] = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
+          Ss[qb_off<Q2>(x, y, z)] = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
         }
       }
       loaded = item.src_fc;
@@ -978,7 +991,7 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
           for (int xs = 0; xs < Q; ++xs)
 #pragma unroll
             for (int yt = 0; yt < Q; ++yt) {
-              const double xv = Xs[(4 * xs + lk) * XSX + (4 * yt + li) * XSY + 4 * zq + lb];
+              const double xv = Xs[qb_off<Q>(4 * xs + lk, 4 * yt + li, 4 * zq + lb)];
               d1a[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xv, rx[0][xs], d1a[yt], 0, 0, 0);
               d1b[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xv, rx[1][xs], d1b[yt], 0, 0, 0);
             }
@@ -997,7 +1010,7 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
 #pragma unroll
             for (int yt = 0; yt < Q; ++yt)
               d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
-                  Xs[(4 * xs + lk) * XSX + (4 * yt + li) * XSY + 4 * zq + lb], rxs[xs], d1[yt],
+                  Xs[qb_off<Q>(4 * xs + lk, 4 * yt + li, 4 * zq + lb)], rxs[xs], d1[yt],
                   0, 0, 0);
           if (on0)
             finish(d1, acc[0], zq);
@@ -1037,7 +1050,7 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
 #pragma unroll
               for (int yt = 0; yt < Q2; ++yt)
                 d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
-                    Ss[(4 * xs + lk) * SSX + (4 * yt + li) * SSY + 4 * zq + lb], tx[xs], d1[yt],
+                    Ss[qb_off<Q2>(4 * xs + lk, 4 * yt + li, 4 * zq + lb)], tx[xs], d1[yt],
                     0, 0, 0);
             double zr[Q2];
 #pragma unroll
@@ -1148,12 +1161,11 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   constexpr int Q2 = (K + 3) / 4, KP = 4 * Q2;
   static_assert(Q2 == 4, "one subtraction a-quad per wave");
   constexpr int SLY = 4, SLX = N * SLY, SLAB = N * SLX;     // slab [x][y][z in quad]
-  static_assert(lds_spread(SLX, SLY), "slab strides");
+  static_assert(quarter_distinct(SLX, SLY), "slab strides");
   constexpr int SLAB_PER_LANE = (SLAB + 255) / 256;
-  constexpr int SSY = lds_sy(KP), SSX = lds_sx(KP);
   constexpr int OPS = 3 * N2 + 3 * K2, OPS_PER_LANE = (OPS + 255) / 256;
   __shared__ double Xl[2][SLAB];
-  __shared__ double Ss[KP * SSX];
+  __shared__ double Ss[KP * KP * KP];   // s_P zero-padded, quad-blocked
   __shared__ double Os[2][OPS];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -1249,7 +1261,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
       const double* __restrict__ sp = in + (size_t)item.src * K3;
       for (int e = tid; e < KP * KP * KP; e += 256) {
         const int x = e / (KP * KP), y = (e / KP) % KP, z = e % KP;
-        Ss[x * SSX + y * SSY + z] = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
+        Ss[qb_off<Q2>(x, y, z)] = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
       }
       sloaded = item.src_fc;
     }
@@ -1324,7 +1336,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 #pragma unroll
           for (int yt = 0; yt < Q2; ++yt)
             d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
-                Ss[(4 * xs + lk) * SSX + (4 * yt + li) * SSY + 4 * zq + lb], tx[xs], d1[yt], 0, 0, 0);
+                Ss[qb_off<Q2>(4 * xs + lk, 4 * yt + li, 4 * zq + lb)], tx[xs], d1[yt], 0, 0, 0);
         double zr[Q2];
 #pragma unroll
         for (int bt = 0; bt < Q2; ++bt) zr[bt] = 0.0;
@@ -1607,6 +1619,14 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
     case 14: { constexpr int KK = 14; __VA_ARGS__; } break;                    \
     default: MRA_DISPATCH_K(k, __VA_ARGS__);                                   \
   }
+
+void launch_zero_batch(double* const* tab, const int64_t* len, int count, size_t maxlen,
+                       hipStream_t s) {
+  if (count <= 0 || maxlen == 0) return;
+  const int blocks = (int)std::min<size_t>((maxlen + 255) / 256, 1024);
+  hipLaunchKernelGGL(zero_batch_kernel, dim3(blocks, count), dim3(256), 0, s, tab, len);
+  hip_check(hipGetLastError(), "zero_batch_kernel");
+}
 
 void launch_zero(double* p, size_t n, hipStream_t s) {
   if (!n) return;

@@ -278,6 +278,9 @@ struct NodeRef {
 };
 
 void launch_zero(double* p, size_t n, hipStream_t s);
+// Clears tab[i][0 .. len[i]) for i < count (device pointer table and lengths).
+void launch_zero_batch(double* const* tab, const int64_t* len, int count, size_t maxlen,
+                       hipStream_t s);
 // mirror != nullptr: also writes the BF16 copy of each children block, layout
 // [a][b][c] with c padded to low_up(k), one block per ref.
 void launch_filter_up(int k, double* const* coeff_tab, const NodeRef* refs, int count,

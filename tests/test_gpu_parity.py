@@ -282,3 +282,37 @@ def test_coulomb_k14_reduced_full_parity(M):
     err = _rel_l2(got, ref.leaves, ref.leaves)
     _say("coulomb k14 reduced rel L2 vs oracle", err, "triples", st["triples"])
     assert err <= TOL
+
+
+def test_degenerate_inputs(M):
+    """Edge cases of the non-standard apply: an input whose root is a leaf is rejected; with
+    every triple screened out the result is the zero function on the root box (as in the
+    oracle); a single refined root (level-1 leaves only) is applied exactly."""
+    _say("case: degenerate inputs")
+    ctx = M.Context(0, W.CELL)
+    c, a, x = W.unit_charge_gaussians(1, 3, 1, 2.0, 2.0)
+    op = ctx.op_coulomb(6, 1e-4, 1e-6)
+    root_leaf = ctx.project(c, a, x, 6, 1e3, initial_level=0)
+    assert root_leaf.info()["leaves"] == 1
+    with pytest.raises(M.MraError) as e:
+        ctx.apply(op, root_leaf, tau_drop=1e-8)
+    assert e.value.code == -1
+    f = ctx.project(c, a, x, 6, 1e-3)
+    g = ctx.apply(op, f, tau_drop=1e30)
+    assert ctx.last_stats()["triples"] == 0
+    got = _as_dict(g)
+    assert list(got) == [(0, 0, 0, 0)] and not np.any(got[(0, 0, 0, 0)])
+    fo = project_adaptive(GaussianSum(c, a, x), 6, 1e-3, W.CELL, 2, 20)
+    cc, tt = coulomb_fit(1e-4, 1e-6, cell_r_hi(*W.CELL))
+    ref, st = apply_nonstandard(fo, SeparatedOperator(cc, tt), 1e30)
+    assert st["triples"] == 0 and set(ref.leaves) == {(0, 0, 0, 0)}
+    # refined root only: every box at level 1 is a leaf
+    f1 = ctx.project(c, a, x, 6, 1e3, initial_level=1, max_level=1)
+    g1 = ctx.apply(op, f1, tau_drop=0.0)
+    fo1 = project_adaptive(GaussianSum(c, a, x), 6, 1e3, W.CELL, 1, 1)
+    ref1, st1 = apply_nonstandard(fo1, SeparatedOperator(cc, tt), 0.0)
+    got1 = _as_dict(g1)
+    assert set(got1) == set(ref1.leaves) and ctx.last_stats()["triples"] == st1["triples"]
+    err = _rel_l2(got1, ref1.leaves, ref1.leaves)
+    _say("refined root only: rel L2 vs oracle", err, "triples", st1["triples"])
+    assert err <= TOL
