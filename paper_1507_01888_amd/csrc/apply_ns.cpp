@@ -495,275 +495,330 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   }
 
   mark("levels and jobs");
-  // ---- 2b. enumerate kept triples (threads over jobs; one output vector per job)
-  std::vector<std::vector<Triple>> jobout(jobs.size());
-  parallel_for(jobs.size(), [&](size_t j, unsigned) {
-    const Job& jb = jobs[j];
-    const LevelData& L = lv[jb.lev];
-    const Op& op = *ops[L.fn];
-    const int n = L.n, D = jb.D, mu = jb.mu;
-    const int64_t nb = (int64_t)1 << n;
-    const double c = std::fabs(op.c[mu]);
-    std::vector<double> ae(D + 1), aa(D + 1), rr(D + 1);
-    for (int d = 0; d <= D; ++d) {
-      ae[d] = jb.be->a[d] + jb.be->e[d];
-      aa[d] = jb.be->a[d];
-      rr[d] = jb.be->r[d];
-    }
-    auto& outv = jobout[j];
-    for (int dx = -D; dx <= D; ++dx)
-      for (int dy = -D; dy <= D; ++dy)
-        for (int dz = -D; dz <= D; ++dz) {
-          int ax = std::abs(dx), ay = std::abs(dy), az = std::abs(dz);
-          double N = (n > 0) ? ae[ax] * ae[ay] * ae[az] - aa[ax] * aa[ay] * aa[az]
-                             : rr[ax] * rr[ay] * rr[az];
-          if (c * N * L.maxb < tau) continue;
-          for (int64_t oi = 0; oi < L.np; ++oi) {
-            int64_t p = L.order[oi];
-            const double eta = c * N * L.bn[p];
-            if (!(eta >= tau)) break;
-            int64_t tx = L.px[p] + dx, ty = L.py[p] + dy, tz = L.pz[p] + dz;
-            if (tx < 0 || ty < 0 || tz < 0 || tx >= nb || ty >= nb || tz >= nb) continue;
-            const int8_t low = (tiers && n > 0 && eta < tau_tier) ? 1 : 0;
-            outv.push_back({((uint64_t)n << 58) | encode(n, tx, ty, tz), (int32_t)(L.ib + p),
-                            (int16_t)mu, (int16_t)dx, (int16_t)dy, (int16_t)dz, low});
-          }
-        }
-  });
-  mark("enumerate");
-  // ---- 3. group by target per (function, level) unit (threads over units), output tree
-  // per function, then items per unit (threads over units)
-  std::vector<Unit> units;
-  std::vector<int> unit_lev;
-  for (size_t j = 0; j < jobs.size();) {
-    size_t e = j;
-    while (e < jobs.size() && jobs[e].lev == jobs[j].lev) ++e;
-    Unit u;
-    u.fn = lv[jobs[j].lev].fn;
-    u.n = lv[jobs[j].lev].n;
-    u.jb = j;
-    u.je = e;
-    units.push_back(std::move(u));
-    unit_lev.push_back(jobs[j].lev);
-    j = e;
-  }
-  parallel_for(units.size(), [&](size_t i, unsigned) {
-    group_unit(units[i], jobout, lv[unit_lev[i]]);
-  });
-  mark("group by target");
-  std::vector<std::vector<Triple>>().swap(jobout);
-  parallel_for((size_t)nf, [&](size_t i, unsigned) {
-    std::vector<uint64_t> tc;
-    for (const Unit& u : units)
-      if (u.fn == (int)i) tc.insert(tc.end(), u.tcodes.begin(), u.tcodes.end());
-    build_output_tree(ctx, plans[i], tc);
-  });
-  mark("output trees");
-  // ---- 4. item offsets (per unit and target: FP64 items, then BF16 items), filled in
-  // parallel over target chunks directly into the pinned upload buffer
+  // every job's blocks are in the caches now: one upload before the first launch
   std::vector<Op*> uniq_ops;
   for (Op* op : ops)
     if (std::find(uniq_ops.begin(), uniq_ops.end(), op) == uniq_ops.end()) uniq_ops.push_back(op);
   for (Op* op : uniq_ops) op->sync_device();
-  size_t n_items = 0, n_low = 0;
-  int64_t ntriples = 0, ntargets = 0;
-  double flops = 0.0, flops_low = 0.0;
-  const double f_ns = 6.0 * std::pow(2.0 * k, 4), f_sub = 6.0 * std::pow((double)k, 4);
-  for (Unit& u : units) {
-    const size_t nt = u.tcodes.size();
-    u.fpre.assign(nt + 1, 0);
-    u.lpre.assign(nt + 1, 0);
-    u.node.assign(nt, -1);
-    for (size_t r = 0; r < nt; ++r) {
-      u.fpre[r + 1] = u.fpre[r] + (u.tmid[r] - u.toff[r]);
-      u.lpre[r + 1] = u.lpre[r] + (u.toff[r + 1] - u.tmid[r]);
-    }
-    u.item_base = n_items;
-    u.low_base = n_low;
-    n_items += (size_t)u.fpre[nt];
-    n_low += (size_t)u.lpre[nt];
-    const double per = f_ns + (u.n > 0 ? f_sub : 0.0);
-    ntriples += (int64_t)u.sorted.size();
-    ntargets += (int64_t)nt;
-    flops += (double)u.sorted.size() * per;
-    flops_low += (double)u.lpre[nt] * per;
-  }
-  if (n_items > (size_t)INT32_MAX || n_low > (size_t)INT32_MAX)
-    fail(MRA_E_UNSUPPORTED, "too many triples for one apply");
-  Arena& A1 = ctx->arena[1];
-  A1.begin(ctx);
-  const size_t o_items = A1.reserve(n_items * sizeof(NSItem));
-  const size_t o_litems = A1.reserve(n_low * sizeof(LowItem));
-  NSItem* items_h = A1.host_at<NSItem>(o_items);
-  LowItem* low_h = A1.host_at<LowItem>(o_litems);
-  struct Task {
-    size_t u;
-    int64_t r0, r1;
-  };
-  std::vector<Task> tasks;
-  for (size_t ui = 0; ui < units.size(); ++ui) {
-    const Unit& u = units[ui];
-    const int64_t nt = (int64_t)u.tcodes.size();
-    for (int64_t r = 0; r < nt;) {
-      int64_t e = r, cnt = 0;
-      while (e < nt && cnt < 4096) cnt += u.toff[e + 1] - u.toff[e], ++e;
-      tasks.push_back({ui, r, e});
-      r = e;
-    }
-  }
-  std::vector<double> task_eta(tasks.size(), 0.0);
-  parallel_for(tasks.size(), [&](size_t ti, unsigned) {
-    const Task& t = tasks[ti];
-    Unit& u = units[t.u];
-    const Plan& p = plans[u.fn];
-    task_eta[ti] = fill_items(u, p, lv[unit_lev[t.u]], fu_index[u.fn], t.r0, t.r1, items_h,
-                              low_h, (int64_t)p.op->dR_blocks, (int64_t)p.op->dT_blocks,
-                              tiers ? (int64_t)p.op->dL_blocks : 0, (int64_t)fu_refs.size());
-  });
-  double eta_low = 0.0;
-  for (double e : task_eta) eta_low += e;   // fixed order
-  mark("work items");
-  // ---- 5. target ranges of the batch: level-n slots, split long lists, longest first
-  std::vector<TargetRange> tgt_sub, work, low_work;
-  std::vector<SplitTarget> splits;
-  std::vector<NodeRef> sd_refs;
-  int out_maxlev = 0;
-  const int64_t chunk = std::max<int64_t>(24, ((int64_t)n_items + 1023) / 1024);
-  const bool fused = ns_kernel_fuses_subtraction(k);
-  int32_t npartials = 0, nsub = 0;
-  std::vector<std::vector<int32_t>> sub_of_node(nf);
-  int64_t in_leaves = 0, out_nodes = 0, out_leaves = 0;
-  for (int i = 0; i < nf; ++i) sub_of_node[i].assign((size_t)plans[i].out->nodes(), -1);
-  for (const Unit& u : units) {
-    const int i = u.fn;
-    const Func& o = *plans[i].out;
-    for (size_t r = 0; r < u.tcodes.size(); ++r) {
-      const int32_t node = u.node[r], fc = o.first_child[node];
-      const int32_t lb = (int32_t)(u.low_base + u.lpre[r]), le = (int32_t)(u.low_base + u.lpre[r + 1]);
-      if (le > lb) low_work.push_back({i, node, fc, lb, le, -1, -1});
-      const int32_t b = (int32_t)(u.item_base + u.fpre[r]), e = (int32_t)(u.item_base + u.fpre[r + 1]);
-      if (e == b) continue;
-      int32_t sub = -1;
-      if (u.n > 0) {
-        if (fused) {
-          sub = nsub++;
-          sub_of_node[i][node] = sub;
-        } else {
-          tgt_sub.push_back({i, node, fc, b, e, -1, -1});
-        }
-      }
-      const int64_t len = e - b;
-      if (len <= chunk) {
-        work.push_back({i, node, fc, b, e, -1, sub});
-        continue;
-      }
-      const int32_t parts = (int32_t)((len + chunk - 1) / chunk);
-      for (int32_t q = 0; q < parts; ++q) {
-        const int32_t qb = b + (int32_t)(q * len / parts), qe = b + (int32_t)((q + 1) * len / parts);
-        work.push_back({i, node, fc, qb, qe, npartials + q, sub});
-      }
-      splits.push_back({i, fc, npartials, parts, sub});
-      npartials += parts;
-    }
-  }
-  for (int i = 0; i < nf; ++i) {
-    in_leaves += (int64_t)plans[i].f->leaves.size();
-    out_nodes += plans[i].out->nodes();
-    out_leaves += (int64_t)plans[i].out->leaves.size();
-    out_maxlev = std::max(out_maxlev, plans[i].out->nlev);
-  }
-  const int64_t nlow = (int64_t)n_low;
-  // work with the longest lists first
-  auto by_len = [](const TargetRange& a, const TargetRange& b) {
-    return (a.end - a.beg) > (b.end - b.beg);
-  };
-  std::stable_sort(work.begin(), work.end(), by_len);
-  std::stable_sort(tgt_sub.begin(), tgt_sub.end(), by_len);
-  std::stable_sort(low_work.begin(), low_work.end(), by_len);
-  // sum-down entries, level-major over the batch
-  std::vector<int64_t> sd_off(out_maxlev + 1, 0);
-  for (int n = 0; n < out_maxlev; ++n) {
-    for (int i = 0; i < nf; ++i) {
-      const Func& o = *plans[i].out;
-      if (n >= o.nlev) continue;
-      for (int64_t q = o.inter_level_off[n]; q < o.inter_level_off[n + 1]; ++q)
-        sd_refs.push_back({i, o.interior[q], o.first_child[o.interior[q]],
-                           sub_of_node[i][o.interior[q]]});
-    }
-    sd_off[n + 1] = (int64_t)sd_refs.size();
-  }
-  // device pointer tables
-  std::vector<double*> out_tab(nf);
-  std::vector<const double*> r_tab(nf), t_tab(nf), c_tab(nf);
-  std::vector<const uint16_t*> l_tab(nf);
-  std::vector<int64_t> out_len(nf);
-  size_t max_len = 0;
-  for (int i = 0; i < nf; ++i) {
-    Func& o = *plans[i].out;
-    o.coeff.alloc(ctx, (size_t)o.nodes() * K3);
-    out_len[i] = (int64_t)o.coeff.n;
-    max_len = std::max(max_len, o.coeff.n);
-    out_tab[i] = o.coeff.p;
-    r_tab[i] = plans[i].op->dR.p;
-    t_tab[i] = plans[i].op->dT.p;
-    c_tab[i] = plans[i].op->d_c.p;
-    l_tab[i] = plans[i].op->dL.p;
-  }
-  const size_t o_out = A1.put(out_tab), o_r = A1.put(r_tab), o_t = A1.put(t_tab),
-               o_c = A1.put(c_tab), o_l = A1.put(l_tab), o_work = A1.put(work),
-               o_sub = A1.put(tgt_sub), o_spl = A1.put(splits), o_sd = A1.put(sd_refs),
-               o_lwork = A1.put(low_work), o_olen = A1.put(out_len);
-  const size_t o_part = A1.scratch((size_t)npartials * 9 * K3 * sizeof(double));  // (2k)^3 + k^3
-  const size_t o_subb = A1.scratch((size_t)nsub * K3 * sizeof(double));
-  A1.commit();
-  double* const* out_tab_d = A1.at<double*>(o_out);
-  const double* const* r_tab_d = A1.at<const double*>(o_r);
-  const double* const* t_tab_d = A1.at<const double*>(o_t);
-  const double* const* c_tab_d = A1.at<const double*>(o_c);
-  const uint16_t* const* l_tab_d = A1.at<const uint16_t*>(o_l);
-  const NSItem* items_d = A1.at<NSItem>(o_items);
-  const TargetRange* work_d = A1.at<TargetRange>(o_work);
-  const TargetRange* sub_d = A1.at<TargetRange>(o_sub);
-  const SplitTarget* splits_d = A1.at<SplitTarget>(o_spl);
-  const NodeRef* sd_d = A1.at<NodeRef>(o_sd);
-  const LowItem* low_items_d = A1.at<LowItem>(o_litems);
-  const TargetRange* low_work_d = A1.at<TargetRange>(o_lwork);
-  double* partials_d = A1.scr_at<double>(o_part);
-  double* subbuf_d = A1.scr_at<double>(o_subb);
-  mark("combine + uploads");
-  double t_plan1 = now_ms();
+  const double t_prep = now_ms() - t_plan0;
 
-  // ---- 6. device work
-  launch_zero_batch(out_tab_d, A1.at<int64_t>(o_olen), nf, max_len, ctx->stream);
-  hip_check(hipEventRecord(ctx->ev[2], ctx->stream), "event");
-  launch_apply_ns(k, in_tab_d, out_tab_d, items_d, work_d, (int)work.size(), r_tab_d,
-                  t_tab_d, c_tab_d, partials_d, subbuf_d, ctx->stream);
-  hip_check(hipEventRecord(ctx->ev[3], ctx->stream), "event");
-  launch_reduce_partials(k, partials_d, out_tab_d, subbuf_d, splits_d,
-                         (int)splits.size(), ctx->stream);
-  launch_apply_std(k, in_tab_d, out_tab_d, items_d, sub_d, (int)tgt_sub.size(),
-                   t_tab_d, c_tab_d, -1.0, ctx->stream);
-  hip_check(hipEventRecord(ctx->ev[6], ctx->stream), "event");
-  if (!low_work.empty())
-    launch_apply_low(k, mirror_d, out_tab_d, low_items_d, low_work_d,
-                     (int)low_work.size(), l_tab_d, c_tab_d, ctx->stream);
-  hip_check(hipEventRecord(ctx->ev[4], ctx->stream), "event");
-  for (int n = 0; n < out_maxlev; ++n) {
-    int64_t b = sd_off[n], e = sd_off[n + 1];
-    if (e > b)
-      launch_sum_down(k, out_tab_d, sd_d + b, (int)(e - b), subbuf_d, h0p, h1p,
-                      ctx->stream);
+  // ---- sub-batches: contiguous ranges of functions, balanced by (refined boxes x terms).
+  // Sub-batch s is planned on the host while the device runs sub-batch s - 1; its upload
+  // arena alternates between two, and is reused only after the device has finished the
+  // sub-batch that used it before.
+  std::vector<size_t> job_begin(nf + 1, jobs.size());
+  for (size_t j = jobs.size(); j-- > 0;) job_begin[lv[jobs[j].lev].fn] = j;
+  for (int i = nf - 1; i >= 0; --i) job_begin[i] = std::min(job_begin[i], job_begin[i + 1]);
+  std::vector<double> weight(nf, 0.0);
+  for (const Job& jb : jobs) weight[lv[jb.lev].fn] += (double)lv[jb.lev].np;
+  const int S = nf >= 8 ? 4 : (nf >= 2 ? 2 : 1);
+  std::vector<int> fb{0};
+  {
+    double total = 0.0, acc = 0.0;
+    for (double w : weight) total += w;
+    for (int i = 0; i < nf && (int)fb.size() < S; ++i) {
+      acc += weight[i];
+      if (acc >= total * (double)fb.size() / S && i + 1 < nf) fb.push_back(i + 1);
+    }
+    fb.push_back(nf);
   }
-  hip_check(hipEventRecord(ctx->ev[5], ctx->stream), "event");
+  const int nsb = (int)fb.size() - 1;
+  struct Events {
+    hipEvent_t e[5]{};   // apply start, main kernel end, low start, apply end, sum-down end
+    ~Events() {
+      for (auto& x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  };
+  std::vector<Events> sev(nsb);
+  for (auto& se : sev)
+    for (auto& x : se.e) hip_check(hipEventCreate(&x), "hipEventCreate");
+
+  const double f_ns = 6.0 * std::pow(2.0 * k, 4), f_sub = 6.0 * std::pow((double)k, 4);
+  const bool fused = ns_kernel_fuses_subtraction(k);
+  int64_t ntriples = 0, ntargets = 0, nlow = 0, in_leaves = 0, out_nodes = 0, out_leaves = 0;
+  double flops = 0.0, flops_low = 0.0, eta_low = 0.0, plan_ms = t_prep;
+  bool any_low = false;
+
+  for (int sb = 0; sb < nsb; ++sb) {
+    const int f0 = fb[sb], f1 = fb[sb + 1];
+    const size_t j0 = job_begin[f0], j1 = job_begin[f1];
+    if (sb >= 2) hip_check(hipEventSynchronize(sev[sb - 2].e[4]), "hipEventSynchronize");
+    const double t_sb0 = now_ms();
+    t_mark = t_sb0;
+    // ---- 2b. enumerate kept triples (threads over jobs; one output vector per job)
+    std::vector<std::vector<Triple>> jobout(j1 - j0);
+    parallel_for(j1 - j0, [&](size_t jj, unsigned) {
+      const Job& jb = jobs[j0 + jj];
+      const LevelData& L = lv[jb.lev];
+      const Op& op = *ops[L.fn];
+      const int n = L.n, D = jb.D, mu = jb.mu;
+      const int64_t nb = (int64_t)1 << n;
+      const double c = std::fabs(op.c[mu]);
+      std::vector<double> ae(D + 1), aa(D + 1), rr(D + 1);
+      for (int d = 0; d <= D; ++d) {
+        ae[d] = jb.be->a[d] + jb.be->e[d];
+        aa[d] = jb.be->a[d];
+        rr[d] = jb.be->r[d];
+      }
+      auto& outv = jobout[jj];
+      for (int dx = -D; dx <= D; ++dx)
+        for (int dy = -D; dy <= D; ++dy)
+          for (int dz = -D; dz <= D; ++dz) {
+            int ax = std::abs(dx), ay = std::abs(dy), az = std::abs(dz);
+            double N = (n > 0) ? ae[ax] * ae[ay] * ae[az] - aa[ax] * aa[ay] * aa[az]
+                               : rr[ax] * rr[ay] * rr[az];
+            if (c * N * L.maxb < tau) continue;
+            for (int64_t oi = 0; oi < L.np; ++oi) {
+              int64_t p = L.order[oi];
+              const double eta = c * N * L.bn[p];
+              if (!(eta >= tau)) break;
+              int64_t tx = L.px[p] + dx, ty = L.py[p] + dy, tz = L.pz[p] + dz;
+              if (tx < 0 || ty < 0 || tz < 0 || tx >= nb || ty >= nb || tz >= nb) continue;
+              const int8_t low = (tiers && n > 0 && eta < tau_tier) ? 1 : 0;
+              outv.push_back({((uint64_t)n << 58) | encode(n, tx, ty, tz), (int32_t)(L.ib + p),
+                              (int16_t)mu, (int16_t)dx, (int16_t)dy, (int16_t)dz, low});
+            }
+          }
+    });
+    mark("enumerate");
+    // ---- 3. group by target per (function, level) unit, output tree per function
+    std::vector<Unit> units;
+    std::vector<int> unit_lev;
+    for (size_t j = j0; j < j1;) {
+      size_t e = j;
+      while (e < j1 && jobs[e].lev == jobs[j].lev) ++e;
+      Unit u;
+      u.fn = lv[jobs[j].lev].fn;
+      u.n = lv[jobs[j].lev].n;
+      u.jb = j - j0;
+      u.je = e - j0;
+      units.push_back(std::move(u));
+      unit_lev.push_back(jobs[j].lev);
+      j = e;
+    }
+    parallel_for(units.size(), [&](size_t i, unsigned) {
+      group_unit(units[i], jobout, lv[unit_lev[i]]);
+    });
+    mark("group by target");
+    std::vector<std::vector<Triple>>().swap(jobout);
+    parallel_for((size_t)(f1 - f0), [&](size_t ii, unsigned) {
+      const int i = f0 + (int)ii;
+      std::vector<uint64_t> tc;
+      for (const Unit& u : units)
+        if (u.fn == i) tc.insert(tc.end(), u.tcodes.begin(), u.tcodes.end());
+      build_output_tree(ctx, plans[i], tc);
+    });
+    mark("output trees");
+    // ---- 4. item offsets (per unit and target: FP64 items, then BF16 items), filled in
+    // parallel over target chunks directly into the pinned upload buffer
+    size_t n_items = 0, n_low = 0;
+    for (Unit& u : units) {
+      const size_t nt = u.tcodes.size();
+      u.fpre.assign(nt + 1, 0);
+      u.lpre.assign(nt + 1, 0);
+      u.node.assign(nt, -1);
+      for (size_t r = 0; r < nt; ++r) {
+        u.fpre[r + 1] = u.fpre[r] + (u.tmid[r] - u.toff[r]);
+        u.lpre[r + 1] = u.lpre[r] + (u.toff[r + 1] - u.tmid[r]);
+      }
+      u.item_base = n_items;
+      u.low_base = n_low;
+      n_items += (size_t)u.fpre[nt];
+      n_low += (size_t)u.lpre[nt];
+      const double per = f_ns + (u.n > 0 ? f_sub : 0.0);
+      ntriples += (int64_t)u.sorted.size();
+      ntargets += (int64_t)nt;
+      flops += (double)u.sorted.size() * per;
+      flops_low += (double)u.lpre[nt] * per;
+    }
+    if (n_items > (size_t)INT32_MAX || n_low > (size_t)INT32_MAX)
+      fail(MRA_E_UNSUPPORTED, "too many triples for one apply");
+    nlow += (int64_t)n_low;
+    Arena& A1 = ctx->arena[1 + (sb & 1)];
+    A1.begin(ctx);
+    const size_t o_items = A1.reserve(n_items * sizeof(NSItem));
+    const size_t o_litems = A1.reserve(n_low * sizeof(LowItem));
+    NSItem* items_h = A1.host_at<NSItem>(o_items);
+    LowItem* low_h = A1.host_at<LowItem>(o_litems);
+    struct Task {
+      size_t u;
+      int64_t r0, r1;
+    };
+    std::vector<Task> tasks;
+    for (size_t ui = 0; ui < units.size(); ++ui) {
+      const Unit& u = units[ui];
+      const int64_t nt = (int64_t)u.tcodes.size();
+      for (int64_t r = 0; r < nt;) {
+        int64_t e = r, cnt = 0;
+        while (e < nt && cnt < 4096) cnt += u.toff[e + 1] - u.toff[e], ++e;
+        tasks.push_back({ui, r, e});
+        r = e;
+      }
+    }
+    std::vector<double> task_eta(tasks.size(), 0.0);
+    parallel_for(tasks.size(), [&](size_t ti, unsigned) {
+      const Task& t = tasks[ti];
+      Unit& u = units[t.u];
+      const Plan& p = plans[u.fn];
+      task_eta[ti] = fill_items(u, p, lv[unit_lev[t.u]], fu_index[u.fn], t.r0, t.r1, items_h,
+                                low_h, (int64_t)p.op->dR_blocks, (int64_t)p.op->dT_blocks,
+                                tiers ? (int64_t)p.op->dL_blocks : 0, (int64_t)fu_refs.size());
+    });
+    for (double e : task_eta) eta_low += e;   // fixed order
+    mark("work items");
+    // ---- 5. target ranges: level-n slots, split long lists, longest first
+    std::vector<TargetRange> tgt_sub, work, low_work;
+    std::vector<SplitTarget> splits;
+    std::vector<NodeRef> sd_refs;
+    int out_maxlev = 0;
+    const int64_t chunk = std::max<int64_t>(24, ((int64_t)n_items + 1023) / 1024);
+    int32_t npartials = 0, nsub = 0;
+    std::vector<std::vector<int32_t>> sub_of_node(f1 - f0);
+    for (int i = f0; i < f1; ++i) sub_of_node[i - f0].assign((size_t)plans[i].out->nodes(), -1);
+    for (const Unit& u : units) {
+      const int i = u.fn;
+      const Func& o = *plans[i].out;
+      for (size_t r = 0; r < u.tcodes.size(); ++r) {
+        const int32_t node = u.node[r], fc = o.first_child[node];
+        const int32_t lb = (int32_t)(u.low_base + u.lpre[r]), le = (int32_t)(u.low_base + u.lpre[r + 1]);
+        if (le > lb) low_work.push_back({i, node, fc, lb, le, -1, -1});
+        const int32_t b = (int32_t)(u.item_base + u.fpre[r]), e = (int32_t)(u.item_base + u.fpre[r + 1]);
+        if (e == b) continue;
+        int32_t sub = -1;
+        if (u.n > 0) {
+          if (fused) {
+            sub = nsub++;
+            sub_of_node[i - f0][node] = sub;
+          } else {
+            tgt_sub.push_back({i, node, fc, b, e, -1, -1});
+          }
+        }
+        const int64_t len = e - b;
+        if (len <= chunk) {
+          work.push_back({i, node, fc, b, e, -1, sub});
+          continue;
+        }
+        const int32_t parts = (int32_t)((len + chunk - 1) / chunk);
+        for (int32_t q = 0; q < parts; ++q) {
+          const int32_t qb = b + (int32_t)(q * len / parts), qe = b + (int32_t)((q + 1) * len / parts);
+          work.push_back({i, node, fc, qb, qe, npartials + q, sub});
+        }
+        splits.push_back({i, fc, npartials, parts, sub});
+        npartials += parts;
+      }
+    }
+    for (int i = f0; i < f1; ++i) {
+      in_leaves += (int64_t)plans[i].f->leaves.size();
+      out_nodes += plans[i].out->nodes();
+      out_leaves += (int64_t)plans[i].out->leaves.size();
+      out_maxlev = std::max(out_maxlev, plans[i].out->nlev);
+    }
+    auto by_len = [](const TargetRange& a, const TargetRange& b) {
+      return (a.end - a.beg) > (b.end - b.beg);
+    };
+    std::stable_sort(work.begin(), work.end(), by_len);
+    std::stable_sort(tgt_sub.begin(), tgt_sub.end(), by_len);
+    std::stable_sort(low_work.begin(), low_work.end(), by_len);
+    // sum-down entries, level-major over the sub-batch
+    std::vector<int64_t> sd_off(out_maxlev + 1, 0);
+    for (int n = 0; n < out_maxlev; ++n) {
+      for (int i = f0; i < f1; ++i) {
+        const Func& o = *plans[i].out;
+        if (n >= o.nlev) continue;
+        for (int64_t q = o.inter_level_off[n]; q < o.inter_level_off[n + 1]; ++q)
+          sd_refs.push_back({i, o.interior[q], o.first_child[o.interior[q]],
+                             sub_of_node[i - f0][o.interior[q]]});
+      }
+      sd_off[n + 1] = (int64_t)sd_refs.size();
+    }
+    // device pointer tables (indexed by the batch position of a function; entries of other
+    // sub-batches are not read)
+    std::vector<double*> out_tab(nf, nullptr);
+    std::vector<const double*> r_tab(nf), t_tab(nf), c_tab(nf);
+    std::vector<const uint16_t*> l_tab(nf);
+    std::vector<int64_t> out_len(nf, 0);
+    size_t max_len = 0;
+    for (int i = 0; i < nf; ++i) {
+      r_tab[i] = plans[i].op->dR.p;
+      t_tab[i] = plans[i].op->dT.p;
+      c_tab[i] = plans[i].op->d_c.p;
+      l_tab[i] = plans[i].op->dL.p;
+    }
+    for (int i = f0; i < f1; ++i) {
+      Func& o = *plans[i].out;
+      o.coeff.alloc(ctx, (size_t)o.nodes() * K3);
+      out_tab[i] = o.coeff.p;
+      out_len[i] = (int64_t)o.coeff.n;
+      max_len = std::max(max_len, o.coeff.n);
+    }
+    const size_t o_out = A1.put(out_tab), o_r = A1.put(r_tab), o_t = A1.put(t_tab),
+                 o_c = A1.put(c_tab), o_l = A1.put(l_tab), o_work = A1.put(work),
+                 o_sub = A1.put(tgt_sub), o_spl = A1.put(splits), o_sd = A1.put(sd_refs),
+                 o_lwork = A1.put(low_work), o_olen = A1.put(out_len);
+    const size_t o_part = A1.scratch((size_t)npartials * 9 * K3 * sizeof(double));  // (2k)^3 + k^3
+    const size_t o_subb = A1.scratch((size_t)nsub * K3 * sizeof(double));
+    A1.commit();
+    double* const* out_tab_d = A1.at<double*>(o_out);
+    const double* const* r_tab_d = A1.at<const double*>(o_r);
+    const double* const* t_tab_d = A1.at<const double*>(o_t);
+    const double* const* c_tab_d = A1.at<const double*>(o_c);
+    const uint16_t* const* l_tab_d = A1.at<const uint16_t*>(o_l);
+    const NSItem* items_d = A1.at<NSItem>(o_items);
+    const TargetRange* work_d = A1.at<TargetRange>(o_work);
+    const TargetRange* sub_d = A1.at<TargetRange>(o_sub);
+    const SplitTarget* splits_d = A1.at<SplitTarget>(o_spl);
+    const NodeRef* sd_d = A1.at<NodeRef>(o_sd);
+    const LowItem* low_items_d = A1.at<LowItem>(o_litems);
+    const TargetRange* low_work_d = A1.at<TargetRange>(o_lwork);
+    double* partials_d = A1.scr_at<double>(o_part);
+    double* subbuf_d = A1.scr_at<double>(o_subb);
+    mark("combine + uploads");
+    plan_ms += now_ms() - t_sb0;
+
+    // ---- 6. device work of the sub-batch
+    hipEvent_t* E = sev[sb].e;
+    launch_zero_batch(out_tab_d + f0, A1.at<int64_t>(o_olen) + f0, f1 - f0, max_len, ctx->stream);
+    hip_check(hipEventRecord(E[0], ctx->stream), "event");
+    launch_apply_ns(k, in_tab_d, out_tab_d, items_d, work_d, (int)work.size(), r_tab_d,
+                    t_tab_d, c_tab_d, partials_d, subbuf_d, ctx->stream);
+    hip_check(hipEventRecord(E[1], ctx->stream), "event");
+    launch_reduce_partials(k, partials_d, out_tab_d, subbuf_d, splits_d,
+                           (int)splits.size(), ctx->stream);
+    launch_apply_std(k, in_tab_d, out_tab_d, items_d, sub_d, (int)tgt_sub.size(),
+                     t_tab_d, c_tab_d, -1.0, ctx->stream);
+    hip_check(hipEventRecord(E[2], ctx->stream), "event");
+    if (!low_work.empty()) {
+      any_low = true;
+      launch_apply_low(k, mirror_d, out_tab_d, low_items_d, low_work_d,
+                       (int)low_work.size(), l_tab_d, c_tab_d, ctx->stream);
+    }
+    hip_check(hipEventRecord(E[3], ctx->stream), "event");
+    for (int n = 0; n < out_maxlev; ++n) {
+      int64_t b = sd_off[n], e = sd_off[n + 1];
+      if (e > b)
+        launch_sum_down(k, out_tab_d, sd_d + b, (int)(e - b), subbuf_d, h0p, h1p,
+                        ctx->stream);
+    }
+    hip_check(hipEventRecord(E[4], ctx->stream), "event");
+  }
   ctx->sync();
   for (int i = 0; i < nf; ++i) plans[i].out->interior_valid = false;
 
-  float ms_f = 0, ms_a = 0, ms_s = 0, ms_main = 0, ms_low = 0;
+  float ms_f = 0;
+  double ms_a = 0, ms_s = 0, ms_main = 0, ms_low = 0;
   hip_check(hipEventElapsedTime(&ms_f, ctx->ev[0], ctx->ev[1]), "elapsed");
-  hip_check(hipEventElapsedTime(&ms_a, ctx->ev[2], ctx->ev[4]), "elapsed");
-  hip_check(hipEventElapsedTime(&ms_main, ctx->ev[2], ctx->ev[3]), "elapsed");
-  hip_check(hipEventElapsedTime(&ms_s, ctx->ev[4], ctx->ev[5]), "elapsed");
-  hip_check(hipEventElapsedTime(&ms_low, ctx->ev[6], ctx->ev[4]), "elapsed");
+  for (const Events& se : sev) {
+    float a = 0, m = 0, l = 0, d = 0;
+    hip_check(hipEventElapsedTime(&a, se.e[0], se.e[3]), "elapsed");
+    hip_check(hipEventElapsedTime(&m, se.e[0], se.e[1]), "elapsed");
+    hip_check(hipEventElapsedTime(&l, se.e[2], se.e[3]), "elapsed");
+    hip_check(hipEventElapsedTime(&d, se.e[3], se.e[4]), "elapsed");
+    ms_a += a;
+    ms_main += m;
+    ms_low += l;
+    ms_s += d;
+  }
   mra_apply_stats& st = ctx->stats;
   st = mra_apply_stats{};
   st.triples = ntriples;
@@ -773,14 +828,14 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   st.out_leaves = out_leaves;
   st.useful_flops = flops;
   st.ms_filter = ms_f;
-  st.ms_plan = t_plan1 - t_plan0;
+  st.ms_plan = plan_ms;
   st.ms_apply = ms_a;
   st.ms_main_kernel = ms_main;
   st.ms_sumdown = ms_s;
   st.triples_low = nlow;
   st.flops_low = flops_low;
   st.eta_low = eta_low;
-  st.ms_low_kernel = low_work.empty() ? 0.0 : ms_low;
+  st.ms_low_kernel = any_low ? ms_low : 0.0;
 }
 
 // Filter-up of one function (used by mra_inner); returns nothing but marks it valid.

@@ -146,7 +146,7 @@ struct Ctx {
   std::string err;
   mra_apply_stats stats{};
   hipEvent_t ev[8]{};
-  Arena arena[2];                      // filter-up phase, plan phase
+  Arena arena[3];                      // filter-up phase, plans of alternate sub-batches
   double* red_part = nullptr;          // 256 partial sums of the leaf reductions
 
   double width() const { return hi - lo; }
