@@ -27,6 +27,16 @@ namespace {
 
 constexpr int round64(int x) { return (x + 63) / 64 * 64; }
 
+// Pointers read from the per-function tables are generic to the compiler, which then emits
+// flat loads; those count against the LDS counter too, so every LDS wait would also wait for
+// in-flight global prefetches.  The tables only hold device memory: cast to the global
+// address space.
+#define MRA_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ MRA_GLOBAL T* as_global(T* p) {
+  return (MRA_GLOBAL T*)p;
+}
+
 __global__ void zero_kernel(double* __restrict__ p, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -35,7 +45,7 @@ __global__ void zero_kernel(double* __restrict__ p, size_t n) {
 
 // Clears arrays tab[y][0 .. len[y]) for every y = blockIdx.y.
 __global__ void zero_batch_kernel(double* const* __restrict__ tab, const int64_t* __restrict__ len) {
-  double* __restrict__ p = tab[blockIdx.y];
+  MRA_GLOBAL double* __restrict__ p = as_global(tab[blockIdx.y]);
   const size_t n = (size_t)len[blockIdx.y];
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -74,7 +84,7 @@ __global__ __launch_bounds__(256) void filter_up_kernel(
   const int tid = threadIdx.x;
   const NodeRef ref = refs[blockIdx.x];
   const int node = ref.node, fc = ref.fchild;
-  double* __restrict__ coeff = tab[ref.fn];
+  MRA_GLOBAL double* __restrict__ coeff = as_global(tab[ref.fn]);
   for (int e = tid; e < K * N; e += 256) {
     int i = e / N, X = e % N;
     H[e] = X < K ? h0[i * K + X] : h1[i * K + X - K];
@@ -85,8 +95,8 @@ __global__ __launch_bounds__(256) void filter_up_kernel(
   for (int e = tid; e < N * N; e += 256) {
     const int X = e / N, Y = e % N;
     const int bx = X / K, i = X % K, by = Y / K, j = Y % K;
-    const double* r0 = coeff + (size_t)(fc + ((bx << 2) | (by << 1))) * K3 + (i * K + j) * K;
-    const double* r1 = r0 + K3;
+    const MRA_GLOBAL double* r0 = coeff + (size_t)(fc + ((bx << 2) | (by << 1))) * K3 + (i * K + j) * K;
+    const MRA_GLOBAL double* r1 = r0 + K3;
     double t[K];
     double row[UP];
 #pragma unroll
@@ -167,10 +177,10 @@ __global__ __launch_bounds__(round64(4 * K * K)) void apply_ns_kernel(
   __shared__ double W[N * N * ZP];
   const int tid = threadIdx.x;
   const TargetRange tr = targets[blockIdx.x];
-  const double* __restrict__ in = in_tab[tr.fn];
-  double* __restrict__ out = out_tab[tr.fn];
-  const double* __restrict__ dR = r_tab[tr.fn];
-  const double* __restrict__ dc = c_tab[tr.fn];
+  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
+  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dR = as_global(r_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
   double acc[N];
 #pragma unroll
   for (int c = 0; c < N; ++c) acc[c] = 0.0;
@@ -188,9 +198,9 @@ __global__ __launch_bounds__(round64(4 * K * K)) void apply_ns_kernel(
       loaded = item.src_fc;
     }
     __syncthreads();
-    const double* RX = dR + (size_t)item.rx * N2;
-    const double* RY = dR + (size_t)item.ry * N2;
-    const double* RZ = dR + (size_t)item.rz * N2;
+    const MRA_GLOBAL double* RX = dR + (size_t)item.rx * N2;
+    const MRA_GLOBAL double* RY = dR + (size_t)item.ry * N2;
+    const MRA_GLOBAL double* RZ = dR + (size_t)item.rz * N2;
     const double cmu = dc[item.mu];
     if (tid < N2) {  // phase x: thread (Y, Z)
       int Y = tid / N, Z = tid % N;
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(
     double* __restrict__ subbuf, const SplitTarget* __restrict__ splits) {
   constexpr int N = 2 * K, N3 = N * N * N, K3 = K * K * K, SLOT = N3 + K3;
   const SplitTarget sp = splits[blockIdx.x];
-  double* __restrict__ out = out_tab[sp.fn];
+  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[sp.fn]);
   for (int e = threadIdx.x; e < N3; e += 256) {
     double s = 0.0;
     for (int q = 0; q < sp.count; ++q) s += partials[(size_t)(sp.first + q) * SLOT + e];
@@ -307,6 +317,55 @@ constexpr bool quarter_distinct(int sx, int sy) {
   return true;
 }
 
+// Global -> LDS staging: a thread issues its loads in chunks of CH before the matching LDS
+// stores, so that a chunk costs one memory latency instead of one per element.  load(e) is
+// called with a clamped index (no branch between the loads of a chunk); store(e, v) only
+// for e = tid + 256 q < TOT.
+template <int TOT, int CH, typename Ld, typename St>
+__device__ __forceinline__ void stage_chunks(int tid, Ld load, St store) {
+  constexpr int PER = (TOT + 255) / 256;
+#pragma unroll
+  for (int q0 = 0; q0 < PER; q0 += CH) {
+    double v[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) v[q] = load(min(tid + 256 * (q0 + q), TOT - 1));
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int e = tid + 256 * (q0 + q);
+      if (q0 + q < PER && e < TOT) store(e, v[q]);
+    }
+  }
+}
+// The children block B_P (8 consecutive child slabs of k^3, i.e. one contiguous run of
+// 8 k^3 doubles) into LDS, quad-blocked over the (2k)^3 index space.
+template <int K, int Q, int CH, typename P>
+__device__ __forceinline__ void stage_children_qb(double* __restrict__ Xs, P src, int tid) {
+  constexpr int K2 = K * K, K3 = K * K * K;
+  stage_chunks<8 * K3, CH>(
+      tid, [&](int e) { return src[e]; },
+      [&](int e, double v) {
+        const int c = e / K3, r = e - c * K3;
+        const int i = r / K2, j = (r / K) % K, m = r % K;
+        Xs[qb_off<Q>(((c >> 2) & 1) * K + i, ((c >> 1) & 1) * K + j, (c & 1) * K + m)] = v;
+      });
+}
+// s_P (k^3) into LDS zero-padded to KP^3 = (4 Q2)^3, quad-blocked.
+template <int K, int Q2, int CH, typename P>
+__device__ __forceinline__ void stage_scaling_qb(double* __restrict__ Ss, P sp, int tid) {
+  constexpr int KP = 4 * Q2;
+  stage_chunks<KP * KP * KP, CH>(
+      tid,
+      [&](int e) {
+        const int x = e / (KP * KP), y = (e / KP) % KP, z = e % KP;
+        const bool ok = x < K && y < K && z < K;
+        return sp[ok ? (x * K + y) * K + z : 0];
+      },
+      [&](int e, double v) {
+        const int x = e / (KP * KP), y = (e / KP) % KP, z = e % KP;
+        Ss[qb_off<Q2>(x, y, z)] = (x < K && y < K && z < K) ? v : 0.0;
+      });
+}
+
 // ------------------------------------------------------------------- apply (NS, MFMA)
 // FP64 matrix-core version for even k (2k = 4Q).  Uses v_mfma_f64_4x4x4f64, which performs
 // four independent 4x4x4 products ("blocks") per instruction at the full FP64 matrix rate
@@ -338,9 +397,12 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
   // level-n subtraction -c (t x t x t) s_P on k^3 padded to KP = 4 Q2
   constexpr int Q2 = (K + 3) / 4, KP = 4 * Q2;
   constexpr int S3 = Q2 * Q2;
-  constexpr int S3_PER_WAVE = (S3 + 3) / 4;
+  // subtraction step-3 pairs go to the waves with fewer main step-3 pairs
+  constexpr int SW = (P3 % 4 == 0) ? 4 : 3;
+  constexpr int S3_PER_WAVE = (S3 + SW - 1) / SW;
   constexpr int OPS = 3 * N2 + 3 * K2;               // operator doubles per triple
   constexpr int OPS_PER_LANE = (OPS + 255) / 256;
+  constexpr int CHUNK = 16;                          // children-block loads in flight
   __shared__ double Xs[N3];
   __shared__ double Zs[N3];
   __shared__ double Z2[KP * KP * KP];
@@ -349,11 +411,11 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
   const TargetRange tr = targets[blockIdx.x];
-  const double* __restrict__ in = in_tab[tr.fn];
-  double* __restrict__ out = out_tab[tr.fn];
-  const double* __restrict__ dR = r_tab[tr.fn];
-  const double* __restrict__ dT = t_tab[tr.fn];
-  const double* __restrict__ dc = c_tab[tr.fn];
+  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
+  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dR = as_global(r_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
   const double* RXs = Os;
   const double* RYs = Os + N2;
   const double* RZs = Os + 2 * N2;
@@ -362,8 +424,7 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
   const double* TZs = Os + 3 * N2 + 2 * K2;
 
   // operator blocks of item `it` into registers (this thread's share)
-  auto fetch_ops = [&](int it, double* reg) {
-    const NSItem nx = items[it];
+  auto fetch_ops = [&](const NSItem nx, double* reg) {
 #pragma unroll
     for (int q = 0; q < OPS_PER_LANE; ++q) {
       const int e = tid + 256 * q;
@@ -400,26 +461,48 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
     for (int c = 0; c < Q2; ++c) sacc[p][c] = 0.0;
   const bool with_sub = tr.sub >= 0;
 
-  double pre[OPS_PER_LANE];
+  double spv[Q2][Q2];   // s_P fragment of the current source (waves < Q2)
+#pragma unroll
+  for (int xs = 0; xs < Q2; ++xs)
+#pragma unroll
+    for (int yt = 0; yt < Q2; ++yt) spv[xs][yt] = 0.0;
+
+  // the item record of triple it + 1 is loaded at the start of triple it, long before the
+  // operator prefetch needs it
+  NSItem nxt{};
+  double pre[OPS_PER_LANE], c_cur = 0.0, c_pre = 0.0;   // c_mu travels with the operators
   if (tr.beg < tr.end) {
-    fetch_ops(tr.beg, pre);
+    nxt = items[tr.beg];
+    fetch_ops(nxt, pre);
+    c_cur = dc[nxt.mu];
     store_ops(pre);
   }
   int loaded = -1;
   for (int it = tr.beg; it < tr.end; ++it) {
-    const NSItem item = items[it];
+    const NSItem item = nxt;
+    const bool more = it + 1 < tr.end;
+    if (more) nxt = items[it + 1];
     if (item.src_fc != loaded) {
       __syncthreads();
-      for (int e = tid; e < 8 * K3; e += 256) {
-        int c = e / K3, r = e - c * K3;
-        int i = r / K2, j = (r / K) % K, m = r % K;
-        Xs[qb_off<Q>(((c >> 2) & 1) * K + i, ((c >> 1) & 1) * K + j, (c & 1) * K + m)] =
-            in[(size_t)(item.src_fc + c) * K3 + r];
+      stage_children_qb<K, Q, CHUNK>(Xs, in + (size_t)item.src_fc * K3, tid);
+      if (with_sub && wave < Q2) {
+        // this wave's z-quad of s_P as step-1 A operands, zero outside k^3
+        const MRA_GLOBAL double* __restrict__ sp = in + (size_t)item.src * K3;
+        const int z = 4 * wave + lb;
+#pragma unroll
+        for (int xs = 0; xs < Q2; ++xs)
+#pragma unroll
+          for (int yt = 0; yt < Q2; ++yt) {
+            const int x = 4 * xs + lk, y = 4 * yt + li;
+            const bool ok = x < K && y < K && z < K;
+            const double v = sp[ok ? (x * K + y) * K + z : 0];
+            spv[xs][yt] = ok ? v : 0.0;
+          }
       }
       loaded = item.src_fc;
     }
     __syncthreads();   // Xs and Os of this triple are in place
-    const double cmu = dc[item.mu];
+    const double cmu = c_cur;
     // B fragments: frag(ks, t) = R[4t + li][4ks + lk] = R^T[4ks + lk][4t + li]
     double rx[Q][Q], ry[Q][Q];
 #pragma unroll
@@ -461,10 +544,11 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
           Zs[sk_off<Q>(4 * at + lk, 4 * bt + li, 4 * zq + lb)] = d2[bt];
       }
     }
-    // ---- leftover (z-quad >= 4) pairs, round robin over the waves
+    // ---- leftover (z-quad >= 4) pairs, round robin from the last wave (the first Q2 waves
+    // also run the subtraction's steps 1 and 2)
 #pragma unroll
     for (int e = 0; e < EXTRA_PER_WAVE; ++e) {
-      const int p = wave + 4 * e;
+      const int p = (3 - wave) + 4 * e;
       if (p < EXTRA) {
         const int zq = 4 + p / Q, at = p % Q;
         double d1[Q];
@@ -495,7 +579,6 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
     // ---- subtraction, steps 1 and 2: (t_x, t_y) on s_P, one z-quad per wave
     if (with_sub && wave < Q2) {
       const int zq = wave;
-      const double* __restrict__ sp = in + (size_t)item.src * K3;
       double tx[Q2][Q2], ty[Q2][Q2];
 #pragma unroll
       for (int ks = 0; ks < Q2; ++ks)
@@ -511,16 +594,13 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
       for (int at = 0; at < Q2; ++at)
 #pragma unroll
         for (int yt = 0; yt < Q2; ++yt) d1[at][yt] = 0.0;
-      const int z = 4 * zq + lb;
 #pragma unroll
       for (int xs = 0; xs < Q2; ++xs)
 #pragma unroll
         for (int yt = 0; yt < Q2; ++yt) {
-          const int x = 4 * xs + lk, y = 4 * yt + li;
-          double a = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
 #pragma unroll
           for (int at = 0; at < Q2; ++at)
-            d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, tx[xs][at], d1[at][yt], 0, 0, 0);
+            d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(spv[xs][yt], tx[xs][at], d1[at][yt], 0, 0, 0);
         }
 #pragma unroll
       for (int at = 0; at < Q2; ++at) {
@@ -538,8 +618,10 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
       }
     }
     // the next triple's operator blocks travel while step 3 runs
-    const bool more = it + 1 < tr.end;
-    if (more) fetch_ops(it + 1, pre);
+    if (more) {
+      fetch_ops(nxt, pre);
+      c_pre = dc[nxt.mu];
+    }
     __syncthreads();
     // ---- subtraction, step 3: z-contraction with -c t_z
     if (with_sub) {
@@ -553,8 +635,8 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
         }
 #pragma unroll
       for (int e = 0; e < S3_PER_WAVE; ++e) {
-        const int p = (3 - wave) + 4 * e;
-        if (p < S3) {
+        const int p = wave + SW * e;
+        if (wave < SW && p < S3) {
           const int at3 = p / Q2, bt3 = p % Q2;
 #pragma unroll
           for (int zs = 0; zs < Q2; ++zs) {
@@ -589,7 +671,10 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
       }
     }
     __syncthreads();   // Zs, Z2 and Os are free
-    if (more) store_ops(pre);
+    if (more) {
+      store_ops(pre);
+      c_cur = c_pre;
+    }
   }
   // ---- write the children block of the target
 #pragma unroll
@@ -615,8 +700,8 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
   if (with_sub) {
 #pragma unroll
     for (int e = 0; e < S3_PER_WAVE; ++e) {
-      const int p = (3 - wave) + 4 * e;
-      if (p < S3) {
+      const int p = wave + SW * e;
+      if (wave < SW && p < S3) {
         const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + lk;
 #pragma unroll
         for (int ct = 0; ct < Q2; ++ct) {
@@ -645,10 +730,10 @@ __global__ __launch_bounds__(round64(K * K)) void apply_std_kernel(
   __shared__ double W[K * K * ZP];
   const int tid = threadIdx.x;
   const TargetRange tr = targets[blockIdx.x];
-  const double* __restrict__ in = in_tab[tr.fn];
-  double* __restrict__ out = out_tab[tr.fn];
-  const double* __restrict__ dT = t_tab[tr.fn];
-  const double* __restrict__ dc = c_tab[tr.fn];
+  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
+  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
   double acc[K];
 #pragma unroll
   for (int c = 0; c < K; ++c) acc[c] = 0.0;
@@ -664,9 +749,9 @@ __global__ __launch_bounds__(round64(K * K)) void apply_std_kernel(
       loaded = item.src;
     }
     __syncthreads();
-    const double* TX = dT + (size_t)item.tx * K2;
-    const double* TY = dT + (size_t)item.ty * K2;
-    const double* TZ = dT + (size_t)item.tz * K2;
+    const MRA_GLOBAL double* TX = dT + (size_t)item.tx * K2;
+    const MRA_GLOBAL double* TY = dT + (size_t)item.ty * K2;
+    const MRA_GLOBAL double* TZ = dT + (size_t)item.tz * K2;
     const double cmu = dc[item.mu] * scale;
     if (tid < K2) {
       int Y = tid / K, Z = tid % K;
@@ -731,12 +816,12 @@ __global__ __launch_bounds__(round64(4 * K * K)) void sum_down_kernel(
   const int tid = threadIdx.x;
   const NodeRef ref = refs[blockIdx.x];
   const int node = ref.node, fc = ref.fchild;
-  double* __restrict__ coeff = tab[ref.fn];
+  MRA_GLOBAL double* __restrict__ coeff = as_global(tab[ref.fn]);
   for (int e = tid; e < K * N; e += blockDim.x) {
     int i = e / N, X = e % N;
     H[e] = X < K ? h0[i * K + X] : h1[i * K + X - K];
   }
-  const double* __restrict__ V = coeff + (size_t)node * K3;
+  const MRA_GLOBAL double* __restrict__ V = coeff + (size_t)node * K3;
   const double* __restrict__ VS = ref.sub >= 0 ? subbuf + (size_t)ref.sub * K3 : nullptr;
   __syncthreads();
   if (tid < K * K) {  // T1[i][j][Z] = sum_m H[m][Z] V[i][j][m]
@@ -847,17 +932,16 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
   const int swap = (16 * lb + 4 * lk + li) * 4;          // lane with kk and bb exchanged
   const TargetRange tr = targets[blockIdx.x];
-  const double* __restrict__ in = in_tab[tr.fn];
-  double* __restrict__ out = out_tab[tr.fn];
-  const double* __restrict__ dR = r_tab[tr.fn];
-  const double* __restrict__ dT = t_tab[tr.fn];
-  const double* __restrict__ dc = c_tab[tr.fn];
+  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
+  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dR = as_global(r_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
   const bool with_sub = tr.sub >= 0;
   const int u0 = wave * NU / 4, u1 = (wave + 1) * NU / 4, at0 = u0 / Q;
   const int v0 = wave * SU / 4, v1 = (wave + 1) * SU / 4, sat0 = v0 / Q2;
 
-  auto fetch_ops = [&](int it, double* reg) {
-    const NSItem nx = items[it];
+  auto fetch_ops = [&](const NSItem nx, double* reg) {
 #pragma unroll
     for (int q = 0; q < OPS_PER_LANE; ++q) {
       const int e = tid + 256 * q;
@@ -904,34 +988,32 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
 #pragma unroll
       for (int c = 0; c < Q2; ++c) sacc[s2][b][c] = 0.0;
 
-  double pre[OPS_PER_LANE];
+  NSItem cur{}, nxt{};   // item records of this and the next triple, loaded ahead
+  double pre[OPS_PER_LANE], c_cur = 0.0, c_pre = 0.0;   // c_mu travels with the operators
   if (tr.beg < tr.end) {
-    fetch_ops(tr.beg, pre);
+    cur = items[tr.beg];
+    fetch_ops(cur, pre);
+    c_cur = dc[cur.mu];
     store_ops(pre, Os[tr.beg & 1]);
+    if (tr.beg + 1 < tr.end) nxt = items[tr.beg + 1];
   }
   int loaded = -1;
   for (int it = tr.beg; it < tr.end; ++it) {
-    const NSItem item = items[it];
+    const NSItem item = cur;
     const bool more = it + 1 < tr.end;
     if (item.src_fc != loaded) {
       __syncthreads();   // every wave is done with the previous source block
-      for (int e = tid; e < 8 * K3; e += 256) {
-        const int c = e / K3, r = e - c * K3;
-        const int i = r / K2, j = (r / K) % K, m = r % K;
-        Xs[qb_off<Q>(((c >> 2) & 1) * K + i, ((c >> 1) & 1) * K + j, (c & 1) * K + m)] =
-            in[(size_t)(item.src_fc + c) * K3 + r];
-      }
-      if (with_sub) {
-        const double* __restrict__ sp = in + (size_t)item.src * K3;
-        for (int e = tid; e < KP * KP * KP; e += 256) {
-          const int x = e / (KP * KP), y = (e / KP) % KP, z = e % KP;
-          Ss[qb_off<Q2>(x, y, z)] = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
-        }
-      }
+      stage_children_qb<K, Q, 18>(Xs, in + (size_t)item.src_fc * K3, tid);
+      if (with_sub) stage_scaling_qb<K, Q2, 8>(Ss, in + (size_t)item.src * K3, tid);
       loaded = item.src_fc;
     }
     __syncthreads();     // source block and this triple's operators are in place
-    if (more) fetch_ops(it + 1, pre);
+    if (more) {
+      fetch_ops(nxt, pre);
+      c_pre = dc[nxt.mu];
+    }
+    cur = nxt;
+    if (it + 2 < tr.end) nxt = items[it + 2];
     const double* Ob = Os[it & 1];
     const double* RXs = Ob;
     const double* RYs = Ob + N2;
@@ -939,7 +1021,7 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
     const double* TXs = Ob + 3 * N2;
     const double* TYs = Ob + 3 * N2 + K2;
     const double* TZs = Ob + 3 * N2 + 2 * K2;
-    const double cmu = dc[item.mu];
+    const double cmu = c_cur;
     {
       double ry[Q][Q];
 #pragma unroll
@@ -1077,7 +1159,10 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
         }
       }
     }
-    if (more) store_ops(pre, Os[(it + 1) & 1]);
+    if (more) {
+      store_ops(pre, Os[(it + 1) & 1]);
+      c_cur = c_pre;
+    }
   }
   // ---- sum the waves' partial blocks in LDS (even waves, then odd waves: the a-quads of
   // waves two apart are disjoint), then write the target's blocks coalesced
@@ -1127,13 +1212,17 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
     if (with_sub)
       for (int e = tid; e < K3; e += 256) dst[N3 + e] = Ssum[e];
   } else {
-    // child slab c gets rows (a, b) of its octant: element e of the slab is (i, j, m)
-    for (int e = tid; e < 8 * K3; e += 256) {
-      const int c = e / K3, r = e - c * K3;
-      const int i = r / K2, j = (r / K) % K, m = r % K;
-      const int a = ((c >> 2) & 1) * K + i, b = ((c >> 1) & 1) * K + j, cc = (c & 1) * K + m;
-      out[(size_t)(tr.fc + c) * K3 + r] += Bsum[(a * N + b) * N + cc];
-    }
+    // child slab c gets rows (a, b) of its octant: element e of the slab is (i, j, m);
+    // the 8 k^3 output elements are one contiguous run starting at the first child
+    MRA_GLOBAL double* __restrict__ dst = out + (size_t)tr.fc * K3;
+    stage_chunks<8 * K3, 18>(
+        tid, [&](int e) { return dst[e]; },
+        [&](int e, double v) {
+          const int c = e / K3, r = e - c * K3;
+          const int i = r / K2, j = (r / K) % K, m = r % K;
+          const int a = ((c >> 2) & 1) * K + i, b = ((c >> 1) & 1) * K + j, cc = (c & 1) * K + m;
+          dst[e] = v + Bsum[(a * N + b) * N + cc];
+        });
     if (with_sub)
       for (int e = tid; e < K3; e += 256) subbuf[(size_t)tr.sub * K3 + e] = Ssum[e];
   }
@@ -1172,17 +1261,16 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
   const int swap = (16 * lb + 4 * lk + li) * 4;
   const TargetRange tr = targets[blockIdx.x];
-  const double* __restrict__ in = in_tab[tr.fn];
-  double* __restrict__ out = out_tab[tr.fn];
-  const double* __restrict__ dR = r_tab[tr.fn];
-  const double* __restrict__ dT = t_tab[tr.fn];
-  const double* __restrict__ dc = c_tab[tr.fn];
+  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
+  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dR = as_global(r_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
   const bool with_sub = tr.sub >= 0;
   const int at_lo = 2 * wave, at_n = wave < 3 ? 2 : 1;     // a-quads of this wave
   const int sat = wave;                                    // subtraction a-quad
 
-  auto fetch_ops = [&](int it, double* reg) {
-    const NSItem nx = items[it];
+  auto fetch_ops = [&](const NSItem nx, double* reg) {
 #pragma unroll
     for (int q = 0; q < OPS_PER_LANE; ++q) {
       const int e = tid + 256 * q;
@@ -1242,7 +1330,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 
   double opre[OPS_PER_LANE], spre[SLAB_PER_LANE];
   if (tr.beg < tr.end) {
-    fetch_ops(tr.beg, opre);
+    fetch_ops(items[tr.beg], opre);
     fetch_slab(items[tr.beg].src_fc, 0, spre);
 #pragma unroll
     for (int q = 0; q < OPS_PER_LANE; ++q) {
@@ -1252,20 +1340,30 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
     store_slab(spre, Xl[0]);
   }
   int sloaded = -1, buf = 0;
+  NSItem cur{};   // item record and c_mu of this triple, loaded one triple ahead
+  double c_cur = 0.0, c_pre = 0.0;
+  if (tr.beg < tr.end) {
+    cur = items[tr.beg];
+    c_cur = dc[cur.mu];
+  }
   for (int it = tr.beg; it < tr.end; ++it) {
-    const NSItem item = items[it];
+    const NSItem item = cur;
     const bool more = it + 1 < tr.end;
-    const int next_fc = more ? items[it + 1].src_fc : -1;
+    const NSItem nxt = more ? items[it + 1] : item;
+    const int next_fc = more ? nxt.src_fc : -1;
     if (with_sub && item.src_fc != sloaded) {
       __syncthreads();   // nobody reads the previous s_P any more
-      const double* __restrict__ sp = in + (size_t)item.src * K3;
+      const MRA_GLOBAL double* __restrict__ sp = in + (size_t)item.src * K3;
       for (int e = tid; e < KP * KP * KP; e += 256) {
         const int x = e / (KP * KP), y = (e / KP) % KP, z = e % KP;
         Ss[qb_off<Q2>(x, y, z)] = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
       }
       sloaded = item.src_fc;
     }
-    if (more) fetch_ops(it + 1, opre);
+    if (more) {
+      fetch_ops(nxt, opre);
+      c_pre = dc[nxt.mu];
+    }
     const double* Ob = Os[it & 1];
     const double* RXs = Ob;
     const double* RYs = Ob + N2;
@@ -1273,7 +1371,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
     const double* TXs = Ob + 3 * N2;
     const double* TYs = Ob + 3 * N2 + K2;
     const double* TZs = Ob + 3 * N2 + 2 * K2;
-    const double cmu = dc[item.mu];
+    const double cmu = c_cur;
 #pragma unroll 1
     for (int zq = 0; zq < Q; ++zq) {
       __syncthreads();   // slab zq (and this triple's operators, s_P) are in place
@@ -1372,6 +1470,8 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
       }
       buf ^= 1;
     }
+    cur = nxt;
+    c_cur = c_pre;
   }
   // ---- each element of the target's blocks is owned by exactly one lane
 #pragma unroll
@@ -1451,11 +1551,14 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
   const int g = lane >> 4, r = lane & 15;
   const bool kin = 8 * g < UP;
   const TargetRange tr = targets[blockIdx.x];
-  double* __restrict__ out = out_tab[tr.fn];
-  const uint16_t* __restrict__ L = l_tab[tr.fn];
-  const double* __restrict__ dc = c_tab[tr.fn];
+  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
+  const MRA_GLOBAL uint16_t* __restrict__ L = as_global(l_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
   const bf16x8 zero8 = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
   auto ld8 = [&](const uint16_t* p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p)); };
+  auto ld8g = [&](const MRA_GLOBAL uint16_t* p) {
+    return __builtin_bit_cast(bf16x8, *(const MRA_GLOBAL u32x4*)p);
+  };
   // slots a in [N, UP) of the T rows are never written: clear everything once
   for (int e = tid; e < TSZ / 8; e += 256) {
     reinterpret_cast<u32x4*>(T1s)[e] = u32x4{0u, 0u, 0u, 0u};
@@ -1485,21 +1588,21 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
           }
       loaded = item.slot;
     }
-    const uint16_t* Lz = L + (size_t)item.rz * REC;
-    const uint16_t* Ly = L + (size_t)item.ry * REC;
-    const uint16_t* Lx = L + (size_t)item.rx * REC;
+    const MRA_GLOBAL uint16_t* Lz = L + (size_t)item.rz * REC;
+    const MRA_GLOBAL uint16_t* Ly = L + (size_t)item.ry * REC;
+    const MRA_GLOBAL uint16_t* Lx = L + (size_t)item.rx * REC;
     bf16x8 oz[2][2], oy[3][2], ox[2][2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int row = 16 * t + r;
       const bool ok = row < N, oku = ok && kin;
-      oz[0][t] = oku ? ld8(Lz + row * UP + 8 * g) : zero8;              // U(R_z)
-      oz[1][t] = oku ? ld8(Lz + LU + row * UP + 8 * g) : zero8;         // U(E_z)
+      oz[0][t] = oku ? ld8g(Lz + row * UP + 8 * g) : zero8;              // U(R_z)
+      oz[1][t] = oku ? ld8g(Lz + LU + row * UP + 8 * g) : zero8;         // U(E_z)
 #pragma unroll
       for (int m = 0; m < 3; ++m)                                       // V(R_y), V(E_y), V(P_y)
-        oy[m][t] = ok ? ld8(Ly + 3 * LU + m * LV + row * 32 + 8 * g) : zero8;
-      ox[0][t] = oku ? ld8(Lx + LU + row * UP + 8 * g) : zero8;         // U(E_x)
-      ox[1][t] = oku ? ld8(Lx + 2 * LU + row * UP + 8 * g) : zero8;     // U(P_x)
+        oy[m][t] = ok ? ld8g(Ly + 3 * LU + m * LV + row * 32 + 8 * g) : zero8;
+      ox[0][t] = oku ? ld8g(Lx + LU + row * UP + 8 * g) : zero8;         // U(E_x)
+      ox[1][t] = oku ? ld8g(Lx + 2 * LU + row * UP + 8 * g) : zero8;     // U(P_x)
     }
     const float cmu = (float)dc[item.mu];
     // ---- steps z and y for this wave's pairs of a
