@@ -119,6 +119,12 @@ typedef struct {
   double flops_low;       /* useful flops of those triples (part of useful_flops)      */
   double eta_low;         /* sum of eta over those triples                             */
   double ms_low_kernel;   /* device time of the low-precision transform kernel         */
+  double flops_kernel;    /* FP64 flops the main kernel executes, unpadded: 2(2k)^4 per
+                             mode product of a children block and 2k^4 per mode product
+                             of a scaling block.  Equals useful_flops - flops_low unless
+                             the kernel shares contractions between triples (k = 10: one
+                             y-product per (term, dz, dy) group and one z-product per
+                             (term, dz) group of a target's list instead of per triple)  */
 } mra_apply_stats;
 
 /* Create a context on HIP device `device` using HIP stream `stream` (NULL: the null

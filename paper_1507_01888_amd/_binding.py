@@ -62,7 +62,7 @@ class ApplyStats(ctypes.Structure):
                 ("ms_apply", ctypes.c_double), ("ms_sumdown", ctypes.c_double),
                 ("ms_main_kernel", ctypes.c_double), ("triples_low", ctypes.c_int64),
                 ("flops_low", ctypes.c_double), ("eta_low", ctypes.c_double),
-                ("ms_low_kernel", ctypes.c_double)]
+                ("ms_low_kernel", ctypes.c_double), ("flops_kernel", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

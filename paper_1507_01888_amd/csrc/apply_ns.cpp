@@ -177,11 +177,14 @@ struct Unit {
   size_t item_base = 0, low_base = 0;  // offsets of this unit's items in the batch arrays
 };
 
-void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const LevelData& L) {
+void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const LevelData& L,
+                bool factored) {
   size_t m = 0;
   for (size_t j = u.jb; j < u.je; ++j) m += jobout[j].size();
   // composite key (target code, tier, source rank); an LSD radix sort on it is stable, and
-  // the jobs of a unit are in ascending term order, so terms stay ascending per source
+  // the jobs of a unit are in ascending term order, so terms stay ascending per source.
+  // For a factored kernel the FP64 triples leave the source rank out of the key: they keep
+  // the enumeration order, which per target is (term, dz, dy, dx).
   int sbits = 1;
   while (((int64_t)1 << sbits) <= L.np) ++sbits;
   const int bits = 3 * u.n + 1 + sbits;
@@ -190,9 +193,10 @@ void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const L
     u.sorted.reserve(m);
     for (size_t j = u.jb; j < u.je; ++j)
       u.sorted.insert(u.sorted.end(), jobout[j].begin(), jobout[j].end());
-    std::stable_sort(u.sorted.begin(), u.sorted.end(), [](const Triple& a, const Triple& b) {
+    std::stable_sort(u.sorted.begin(), u.sorted.end(), [factored](const Triple& a, const Triple& b) {
       if (a.tcode != b.tcode) return a.tcode < b.tcode;
       if (a.low != b.low) return a.low < b.low;
+      if (factored && !a.low) return false;
       return a.src < b.src;
     });
     u.tcodes.clear();
@@ -221,7 +225,7 @@ void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const L
     for (size_t j = u.jb; j < u.je; ++j)
       for (const Triple& t : jobout[j]) {
         key[q] = ((t.tcode & cmask) << (1 + sbits)) | ((uint64_t)t.low << sbits) |
-                 (uint64_t)(t.src - L.ib);
+                 ((t.low || !factored) ? (uint64_t)(t.src - L.ib) : 0);
         idx[q] = (uint32_t)q;
         ptr[q] = &t;
         ++q;
@@ -536,8 +540,9 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
 
   const double f_ns = 6.0 * std::pow(2.0 * k, 4), f_sub = 6.0 * std::pow((double)k, 4);
   const bool fused = ns_kernel_fuses_subtraction(k);
+  const bool factored = ns_kernel_factored(k);
   int64_t ntriples = 0, ntargets = 0, nlow = 0, in_leaves = 0, out_nodes = 0, out_leaves = 0;
-  double flops = 0.0, flops_low = 0.0, eta_low = 0.0, plan_ms = t_prep;
+  double flops = 0.0, flops_low = 0.0, eta_low = 0.0, flops_kernel = 0.0, plan_ms = t_prep;
   bool any_low = false;
 
   for (int sb = 0; sb < nsb; ++sb) {
@@ -562,9 +567,10 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
         rr[d] = jb.be->r[d];
       }
       auto& outv = jobout[jj];
-      for (int dx = -D; dx <= D; ++dx)
+      // dz outermost: per target the triples of a term come in (dz, dy, dx) order
+      for (int dz = -D; dz <= D; ++dz)
         for (int dy = -D; dy <= D; ++dy)
-          for (int dz = -D; dz <= D; ++dz) {
+          for (int dx = -D; dx <= D; ++dx) {
             int ax = std::abs(dx), ay = std::abs(dy), az = std::abs(dz);
             double N = (n > 0) ? ae[ax] * ae[ay] * ae[az] - aa[ax] * aa[ay] * aa[az]
                                : rr[ax] * rr[ay] * rr[az];
@@ -598,7 +604,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       j = e;
     }
     parallel_for(units.size(), [&](size_t i, unsigned) {
-      group_unit(units[i], jobout, lv[unit_lev[i]]);
+      group_unit(units[i], jobout, lv[unit_lev[i]], factored);
     });
     mark("group by target");
     std::vector<std::vector<Triple>>().swap(jobout);
@@ -719,6 +725,31 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
     };
     std::stable_sort(work.begin(), work.end(), by_len);
     std::stable_sort(tgt_sub.begin(), tgt_sub.end(), by_len);
+    // mode products the main kernel executes (threads over chunks of ranges, fixed-order sum)
+    {
+      const double fm = 2.0 * std::pow(2.0 * k, 4), fs = 2.0 * std::pow((double)k, 4);
+      const size_t nck = (work.size() + 255) / 256;
+      std::vector<double> part(nck, 0.0);
+      parallel_for(nck, [&](size_t ci, unsigned) {
+        double acc = 0.0;
+        for (size_t wi = ci * 256; wi < std::min(work.size(), (ci + 1) * 256); ++wi) {
+          const TargetRange& w = work[wi];
+          int64_t prods = w.end - w.beg;
+          if (factored)
+            for (int32_t q = w.beg; q < w.end; ++q) {
+              const bool last = q + 1 == w.end;
+              const NSItem& a = items_h[q];
+              if (last || items_h[q + 1].rz != a.rz || items_h[q + 1].ry != a.ry) ++prods;
+              if (last || items_h[q + 1].rz != a.rz) ++prods;
+            }
+          else
+            prods *= 3;
+          acc += (double)prods * (fm + (w.sub >= 0 ? fs : 0.0));
+        }
+        part[ci] = acc;
+      });
+      for (double v : part) flops_kernel += v;
+    }
     std::stable_sort(low_work.begin(), low_work.end(), by_len);
     // sum-down entries, level-major over the sub-batch
     std::vector<int64_t> sd_off(out_maxlev + 1, 0);
@@ -834,6 +865,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   st.ms_sumdown = ms_s;
   st.triples_low = nlow;
   st.flops_low = flops_low;
+  st.flops_kernel = flops_kernel;
   st.eta_low = eta_low;
   st.ms_low_kernel = any_low ? ms_low : 0.0;
 }

@@ -501,6 +501,7 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
   st.out_nodes = out.nodes();
   st.out_leaves = (int64_t)out.leaves.size();
   st.useful_flops = (double)items.size() * 6.0 * std::pow((double)k, 4);
+  st.flops_kernel = st.useful_flops;
   st.ms_plan = t_plan1 - t_plan0;
   st.ms_apply = ms_a;
   st.ms_main_kernel = ms_a;

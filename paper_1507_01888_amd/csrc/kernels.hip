@@ -32,6 +32,7 @@ constexpr int round64(int x) { return (x + 63) / 64 * 64; }
 // in-flight global prefetches.  The tables only hold device memory: cast to the global
 // address space.
 #define MRA_GLOBAL __attribute__((address_space(1)))
+#define MRA_LDS __attribute__((address_space(3)))
 template <typename T>
 __device__ __forceinline__ MRA_GLOBAL T* as_global(T* p) {
   return (MRA_GLOBAL T*)p;
@@ -700,6 +701,427 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
   if (with_sub) {
 #pragma unroll
     for (int e = 0; e < S3_PER_WAVE; ++e) {
+      const int p = wave + SW * e;
+      if (wave < SW && p < S3) {
+        const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + lk;
+#pragma unroll
+        for (int ct = 0; ct < Q2; ++ct) {
+          const int c = 4 * ct + li;
+          if (a < K && b < K && c < K) {
+            if (tr.partial >= 0)
+              partials[(size_t)tr.partial * (N3 + K3) + N3 + (a * K + b) * K + c] = sacc[e][ct];
+            else
+              subbuf[(size_t)tr.sub * K3 + (a * K + b) * K + c] = sacc[e][ct];
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int B>
+struct BufTag {
+  static constexpr int value = B;
+};
+// ------------------------------------------------------------ apply (NS, MFMA, factored)
+// FP64 matrix-core kernel for k = 10 that shares contractions between the triples of a
+// target.  Mode products along different axes commute and a target's result is a sum over
+// its triples, so with the triples ordered by (term mu, dz, dy, dx)
+//   acc_T = sum_{mu, dz} c_mu R_z x_z [ sum_{dy} R_y x_y [ sum_{dx} R_x x_x B_{T - d} ] ]
+// (R_x = R^{n, dx}_mu etc.): step 1 (contract x) runs once per triple and accumulates in
+// registers, step 2 (contract y) once per (mu, dz, dy) group, step 3 (contract z, through
+// the LDS exchange tensor) once per (mu, dz) group.  The level-n subtraction -c (t x t x t)
+// s_P is factored the same way.  The lane mapping of each step is that of
+// apply_ns_mfma_kernel (block index = z inside a z-quad for steps 1 and 2).
+// The children block of the next triple and its operator blocks are copied into the other
+// half of two LDS buffers by direct global->LDS loads (16 bytes per lane, no registers)
+// while the current triple runs; the source block is stored row-major [x][y][z], whose
+// row stride 2k = 20 (= 4 mod 16) keeps the step-1 reads bank-conflict free.  The buffer a
+// triple has finished with holds the exchange tensors of step 3.
+template <int K>
+__global__ __launch_bounds__(256) void apply_ns_fac_kernel(
+    const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
+    const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
+    const double* const* __restrict__ r_tab, const double* const* __restrict__ t_tab,
+    const double* const* __restrict__ c_tab, double* __restrict__ partials,
+    double* __restrict__ subbuf) {
+  constexpr int N = 2 * K, Q = N / 4, N2 = N * N, N3 = N * N * N, K2 = K * K, K3 = K * K * K;
+  static_assert(Q == 5, "row stride 2k = 20 and the wave split below are for k = 10");
+  constexpr int EXTRA = (Q - 4) * Q, EPW = (EXTRA + 3) / 4;   // (z-quad 4, a-quad) units
+  constexpr int P3 = Q * Q, P3PW = (P3 + 3) / 4;              // step-3 (a-quad, b-quad) pairs
+  constexpr int Q2 = (K + 3) / 4, S3 = Q2 * Q2;               // subtraction on KP = 4 Q2
+  constexpr int SW = (P3 % 4 == 0) ? 4 : 3, S3PW = (S3 + SW - 1) / SW;
+  // direct-load geometry, in 16-byte granules (two doubles)
+  constexpr int XG = N3 / 2, XI = (XG + 63) / 64, XQ = (XI + 3) / 4, XPAD = 128 * XI;
+  constexpr int OPS = 3 * N2 + 3 * K2, OG = OPS / 2, OI = (OG + 63) / 64, OQ = (OI + 3) / 4,
+                OPAD = 128 * OI;
+  static_assert(N2 % 2 == 0 && K2 % 2 == 0 && K % 2 == 0, "granules never straddle rows");
+  static_assert(P3 <= XPAD && 64 * Q2 * Q2 * Q2 <= XPAD && 64 * Q * Q * Q <= XPAD, "exchange fits");
+  // the two halves of each double buffer are separate objects, so that the compiler can
+  // tell reads of one from the direct loads into the other
+  __shared__ __attribute__((aligned(16))) double Xs0[XPAD];
+  __shared__ __attribute__((aligned(16))) double Xs1[XPAD];
+  __shared__ __attribute__((aligned(16))) double Os0[OPAD];
+  __shared__ __attribute__((aligned(16))) double Os1[OPAD];
+  __shared__ double Z2s[K3];   // exchange tensor of the subtraction, [a][b][z], unpadded
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
+  const TargetRange tr = targets[blockIdx.x];
+  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
+  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dR = as_global(r_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
+  const bool with_sub = tr.sub >= 0;
+
+  // granule g of the row-major source block is (x, y, z = 2 zp), g = (x N + y) N/2 + zp;
+  // this lane's offsets (doubles, from the first child's slab) for its wave's instructions
+  int xoff[XQ];
+#pragma unroll
+  for (int q = 0; q < XQ; ++q) {
+    const int g = min(64 * (wave + 4 * q) + lane, XG - 1);
+    const int x = g / (N2 / 2), r = g - x * (N2 / 2), y = r / (N / 2), z = 2 * (r - y * (N / 2));
+    const int child = ((x / K) << 2) | ((y / K) << 1) | (z / K);
+    xoff[q] = child * K3 + ((x % K) * K + y % K) * K + z % K;
+  }
+  // operator granules: [R_x^T | R_y^T | R_z^T] (N^2 each), then [t_x^T | t_y^T | t_z^T] (k^2)
+  int osel[OQ], ooff[OQ];
+#pragma unroll
+  for (int q = 0; q < OQ; ++q) {
+    const int g = min(64 * (wave + 4 * q) + lane, OG - 1);
+    if (g < 3 * N2 / 2) {
+      osel[q] = g / (N2 / 2);
+      ooff[q] = 2 * (g - osel[q] * (N2 / 2));
+    } else {
+      const int g2 = g - 3 * N2 / 2;
+      osel[q] = 3 + g2 / (K2 / 2);
+      ooff[q] = 2 * (g2 - (osel[q] - 3) * (K2 / 2));
+    }
+  }
+  auto dma_source = [&](int src_fc, double* dst) {
+    const MRA_GLOBAL double* base = in + (size_t)src_fc * K3;
+#pragma unroll
+    for (int q = 0; q < XQ; ++q) {
+      const int j = wave + 4 * q;
+      if (j < XI)
+        __builtin_amdgcn_global_load_lds((const MRA_GLOBAL void*)(base + xoff[q]),
+                                         (MRA_LDS void*)(dst + 128 * j), 16, 0, 0);
+    }
+  };
+  auto dma_ops = [&](const NSItem nx, double* dst) {
+#pragma unroll
+    for (int q = 0; q < OQ; ++q) {
+      const int j = wave + 4 * q;
+      if (j < OI) {
+        const int sel = osel[q];
+        const int blk = sel == 0 ? nx.rx : sel == 1 ? nx.ry : sel == 2 ? nx.rz
+                      : sel == 3 ? nx.tx : sel == 4 ? nx.ty : nx.tz;
+        const MRA_GLOBAL double* src =
+            sel < 3 ? dR + (size_t)blk * N2 + ooff[q] : dT + (size_t)blk * K2 + ooff[q];
+        __builtin_amdgcn_global_load_lds((const MRA_GLOBAL void*)src,
+                                         (MRA_LDS void*)(dst + 128 * j), 16, 0, 0);
+      }
+    }
+  };
+  // this wave's z-quad of s_P as step-1 A operands of the subtraction (waves < Q2); the
+  // values outside k^3 are zeroed where they are used, so that nothing waits for the loads
+  auto sp_ok = [&](int xs, int yt) {
+    return 4 * xs + lk < K && 4 * yt + li < K && 4 * wave + lb < K;
+  };
+  auto load_sp = [&](const NSItem nx, double (&v)[Q2][Q2]) {
+    const MRA_GLOBAL double* __restrict__ sp = in + (size_t)nx.src * K3;
+    const int z = 4 * wave + lb;
+#pragma unroll
+    for (int xs = 0; xs < Q2; ++xs)
+#pragma unroll
+      for (int yt = 0; yt < Q2; ++yt) {
+        const int x = 4 * xs + lk, y = 4 * yt + li;
+        v[xs][yt] = sp[sp_ok(xs, yt) ? (x * K + y) * K + z : 0];
+      }
+  };
+
+  double d1[Q][Q], d2[Q][Q], d1e[EPW][Q], d2e[EPW][Q], acc[P3PW][Q];
+  double d1s[Q2][Q2], d2s[Q2][Q2], sacc[S3PW][Q2], spv[Q2][Q2], spn[Q2][Q2];
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+#pragma unroll
+    for (int j = 0; j < Q; ++j) d1[i][j] = d2[i][j] = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPW; ++e)
+#pragma unroll
+    for (int j = 0; j < Q; ++j) d1e[e][j] = d2e[e][j] = 0.0;
+#pragma unroll
+  for (int e = 0; e < P3PW; ++e)
+#pragma unroll
+    for (int j = 0; j < Q; ++j) acc[e][j] = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q2; ++i)
+#pragma unroll
+    for (int j = 0; j < Q2; ++j) d1s[i][j] = d2s[i][j] = spv[i][j] = spn[i][j] = 0.0;
+#pragma unroll
+  for (int e = 0; e < S3PW; ++e)
+#pragma unroll
+    for (int j = 0; j < Q2; ++j) sacc[e][j] = 0.0;
+
+  // item records two triples ahead: the next one is in registers when its loads are issued
+  NSItem cur{}, nxt{};
+  double c_cur = 0.0, c_pre = 0.0;
+  if (tr.beg < tr.end) {
+    cur = items[tr.beg];
+    c_cur = dc[cur.mu];
+    dma_source(cur.src_fc, Xs0);
+    dma_ops(cur, Os0);
+    if (with_sub && wave < Q2) load_sp(cur, spv);
+    nxt = items[min(tr.beg + 1, tr.end - 1)];
+  }
+  // one triple; BUF is a compile-time constant so that the compiler can tell the reads of
+  // this triple's buffer halves from the direct loads into the other halves
+  auto triple = [&](const int it, auto buf_tag) {
+    constexpr int buf = decltype(buf_tag)::value;
+    double* const Xc = buf == 0 ? Xs0 : Xs1;   // this triple's halves
+    double* const Oc = buf == 0 ? Os0 : Os1;
+    double* const Xn = buf == 0 ? Xs1 : Xs0;   // the next triple's halves
+    double* const On = buf == 0 ? Os1 : Os0;
+    const NSItem item = cur;
+    const bool more = it + 1 < tr.end;
+    const NSItem nn = items[min(it + 2, tr.end - 1)];   // uniform address: scalar loads
+    // this wave's direct loads of triple it are complete; after the barrier all of them
+    // are, and every wave is done with triple it - 1 (the other buffer halves are free)
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    __syncthreads();
+    if (more) {
+      dma_source(nxt.src_fc, Xn);
+      dma_ops(nxt, On);
+      if (with_sub && wave < Q2) load_sp(nxt, spn);
+      c_pre = dc[nxt.mu];
+    }
+    const bool dy_end = !more || nxt.rz != item.rz || nxt.ry != item.ry;
+    const bool dz_end = !more || nxt.rz != item.rz;
+    const double cmu = c_cur;
+    const double* X = Xc;
+    const double* RXs = Oc;
+    const double* RYs = Oc + N2;
+    const double* RZs = Oc + 2 * N2;
+    const double* TXs = Oc + 3 * N2;
+    const double* TYs = Oc + 3 * N2 + K2;
+    const double* TZs = Oc + 3 * N2 + 2 * K2;
+    // ---- step 1: the main z-quad of this wave (all a-quads), then the z-quad-4 units
+    {
+      const int zq = wave;
+#pragma unroll
+      for (int xs = 0; xs < Q; ++xs) {
+        double rx[Q];
+#pragma unroll
+        for (int at = 0; at < Q; ++at) rx[at] = RXs[(4 * xs + lk) * N + 4 * at + li];
+#pragma unroll
+        for (int yt = 0; yt < Q; ++yt) {
+          const double a = X[((4 * xs + lk) * N + 4 * yt + li) * N + 4 * zq + lb];
+#pragma unroll
+          for (int at = 0; at < Q; ++at)
+            d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rx[at], d1[at][yt], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPW; ++e) {
+      const int p = (3 - wave) + 4 * e;
+      if (p < EXTRA) {
+        const int zq = 4 + p / Q, at = p % Q;
+#pragma unroll
+        for (int xs = 0; xs < Q; ++xs) {
+          const double b = RXs[(4 * xs + lk) * N + 4 * at + li];
+#pragma unroll
+          for (int yt = 0; yt < Q; ++yt) {
+            const double a = X[((4 * xs + lk) * N + 4 * yt + li) * N + 4 * zq + lb];
+            d1e[e][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, d1e[e][yt], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if (with_sub && wave < Q2) {
+#pragma unroll
+      for (int xs = 0; xs < Q2; ++xs)
+#pragma unroll
+        for (int at = 0; at < Q2; ++at) {
+          const int r = 4 * xs + lk, cc = 4 * at + li;
+          const double t = TXs[(r < K && cc < K) ? r * K + cc : 0];
+          const double b = (r < K && cc < K) ? t : 0.0;
+#pragma unroll
+          for (int yt = 0; yt < Q2; ++yt)
+            d1s[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(sp_ok(xs, yt) ? spv[xs][yt] : 0.0, b,
+                                                             d1s[at][yt], 0, 0, 0);
+        }
+    }
+    // ---- step 2 at the end of a (mu, dz, dy) group
+    if (dy_end) {
+#pragma unroll
+      for (int ys = 0; ys < Q; ++ys) {
+        double ry[Q];
+#pragma unroll
+        for (int bt = 0; bt < Q; ++bt) ry[bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+#pragma unroll
+        for (int at = 0; at < Q; ++at)
+#pragma unroll
+          for (int bt = 0; bt < Q; ++bt)
+            d2[at][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], ry[bt], d2[at][bt], 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < EPW; ++e)
+          if ((3 - wave) + 4 * e < EXTRA)
+#pragma unroll
+            for (int bt = 0; bt < Q; ++bt)
+              d2e[e][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1e[e][ys], ry[bt], d2e[e][bt], 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int j = 0; j < Q; ++j) d1[i][j] = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPW; ++e)
+#pragma unroll
+        for (int j = 0; j < Q; ++j) d1e[e][j] = 0.0;
+      if (with_sub && wave < Q2) {
+#pragma unroll
+        for (int ys = 0; ys < Q2; ++ys)
+#pragma unroll
+          for (int bt = 0; bt < Q2; ++bt) {
+            const int r = 4 * ys + lk, cc = 4 * bt + li;
+            const double t = TYs[(r < K && cc < K) ? r * K + cc : 0];
+            const double b = (r < K && cc < K) ? t : 0.0;
+#pragma unroll
+            for (int at = 0; at < Q2; ++at)
+              d2s[at][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1s[at][ys], b, d2s[at][bt], 0, 0, 0);
+          }
+#pragma unroll
+        for (int i = 0; i < Q2; ++i)
+#pragma unroll
+          for (int j = 0; j < Q2; ++j) d1s[i][j] = 0.0;
+      }
+    }
+    // ---- step 3 at the end of a (mu, dz) group, through this triple's source buffer
+    if (dz_end) {
+      double* Zs = Xc;
+      __syncthreads();   // every wave is done reading the source block and Z2s
+      {
+        const int zq = wave;
+#pragma unroll
+        for (int at = 0; at < Q; ++at)
+#pragma unroll
+          for (int bt = 0; bt < Q; ++bt) {
+            Zs[sk_off<Q>(4 * at + lk, 4 * bt + li, 4 * zq + lb)] = d2[at][bt];
+            d2[at][bt] = 0.0;
+          }
+      }
+#pragma unroll
+      for (int e = 0; e < EPW; ++e) {
+        const int p = (3 - wave) + 4 * e;
+        if (p < EXTRA) {
+          const int zq = 4 + p / Q, at = p % Q;
+#pragma unroll
+          for (int bt = 0; bt < Q; ++bt) {
+            Zs[sk_off<Q>(4 * at + lk, 4 * bt + li, 4 * zq + lb)] = d2e[e][bt];
+            d2e[e][bt] = 0.0;
+          }
+        }
+      }
+      if (with_sub && wave < Q2) {
+        const int zq = wave;
+#pragma unroll
+        for (int at = 0; at < Q2; ++at)
+#pragma unroll
+          for (int bt = 0; bt < Q2; ++bt) {
+            const int a = 4 * at + lk, b = 4 * bt + li, z = 4 * zq + lb;
+            if (a < K && b < K && z < K) Z2s[(a * K + b) * K + z] = d2s[at][bt];
+            d2s[at][bt] = 0.0;
+          }
+      }
+      __syncthreads();
+      {
+        double rz[Q][Q];
+#pragma unroll
+        for (int zs = 0; zs < Q; ++zs)
+#pragma unroll
+          for (int ct = 0; ct < Q; ++ct) rz[zs][ct] = cmu * RZs[(4 * zs + lk) * N + 4 * ct + li];
+#pragma unroll
+        for (int e = 0; e < P3PW; ++e) {
+          const int p = (3 - wave) + 4 * e;
+          if (p < P3) {
+            const int at3 = p / Q, bt3 = p % Q;
+#pragma unroll
+            for (int zs = 0; zs < Q; ++zs) {
+              const double a = Zs[sk_off<Q>(4 * at3 + lb, 4 * bt3 + li, 4 * zs + lk)];
+#pragma unroll
+              for (int ct = 0; ct < Q; ++ct)
+                acc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rz[zs][ct], acc[e][ct], 0, 0, 0);
+            }
+          }
+        }
+      }
+      if (with_sub) {
+        double tz[Q2][Q2];
+#pragma unroll
+        for (int zs = 0; zs < Q2; ++zs)
+#pragma unroll
+          for (int ct = 0; ct < Q2; ++ct) {
+            const int r = 4 * zs + lk, cc = 4 * ct + li;
+            const double t = TZs[(r < K && cc < K) ? r * K + cc : 0];
+            tz[zs][ct] = (r < K && cc < K) ? -cmu * t : 0.0;
+          }
+#pragma unroll
+        for (int e = 0; e < S3PW; ++e) {
+          const int p = wave + SW * e;
+          if (wave < SW && p < S3) {
+            const int at3 = p / Q2, bt3 = p % Q2;
+#pragma unroll
+            for (int zs = 0; zs < Q2; ++zs) {
+              const int a = 4 * at3 + lb, b = 4 * bt3 + li, z = 4 * zs + lk;
+              const bool ok = a < K && b < K && z < K;
+              const double t = Z2s[ok ? (a * K + b) * K + z : 0];
+              const double v = ok ? t : 0.0;
+#pragma unroll
+              for (int ct = 0; ct < Q2; ++ct)
+                sacc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(v, tz[zs][ct], sacc[e][ct], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < Q2; ++i)
+#pragma unroll
+      for (int j = 0; j < Q2; ++j) spv[i][j] = spn[i][j];
+    c_cur = c_pre;
+    cur = nxt;
+    nxt = nn;
+  };
+  for (int it = tr.beg; it < tr.end; it += 2) {
+    triple(it, BufTag<0>{});
+    if (it + 1 < tr.end) triple(it + 1, BufTag<1>{});
+  }
+  // ---- write the children block of the target (each element owned by one lane)
+#pragma unroll
+  for (int e = 0; e < P3PW; ++e) {
+    const int p = (3 - wave) + 4 * e;
+    if (p < P3) {
+      const int at3 = p / Q, bt3 = p % Q;
+      const int a = 4 * at3 + lb, b = 4 * bt3 + lk;
+      if (tr.partial >= 0) {
+        double* dst = partials + (size_t)tr.partial * (N3 + K3);
+#pragma unroll
+        for (int ct = 0; ct < Q; ++ct) dst[(a * N + b) * N + 4 * ct + li] = acc[e][ct];
+      } else {
+#pragma unroll
+        for (int ct = 0; ct < Q; ++ct) {
+          const int c = 4 * ct + li;
+          const int child = ((a / K) << 2) | ((b / K) << 1) | (c / K);
+          out[(size_t)(tr.fc + child) * K3 + ((a % K) * K + (b % K)) * K + (c % K)] += acc[e][ct];
+        }
+      }
+    }
+  }
+  if (with_sub) {
+#pragma unroll
+    for (int e = 0; e < S3PW; ++e) {
       const int p = wave + SW * e;
       if (wave < SW && p < S3) {
         const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + lk;
@@ -1770,6 +2192,8 @@ void launch_apply_low(int k, const uint16_t* mirror, double* const* out_tab,
 
 bool ns_kernel_fuses_subtraction(int k) { return k == 8 || k == 10 || k == 12 || k == 14; }
 
+bool ns_kernel_factored(int k) { return k == 10; }
+
 void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
                      const NSItem* items, const TargetRange* targets, int ntargets,
                      const double* const* r_tab, const double* const* t_tab,
@@ -1780,7 +2204,7 @@ void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
     hipLaunchKernelGGL(apply_ns_mfma_kernel<8>, dim3(ntargets), dim3(256), 0, s, in_tab,
                        out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
   } else if (k == 10) {
-    hipLaunchKernelGGL(apply_ns_mfma_kernel<10>, dim3(ntargets), dim3(256), 0, s, in_tab,
+    hipLaunchKernelGGL(apply_ns_fac_kernel<10>, dim3(ntargets), dim3(256), 0, s, in_tab,
                        out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
   } else if (k == 12) {
     hipLaunchKernelGGL(apply_ns_own_kernel<12>, dim3(ntargets), dim3(256), 0, s, in_tab,

@@ -293,6 +293,9 @@ void launch_apply_low(int k, const uint16_t* mirror, double* const* out_tab,
                       const uint16_t* const* l_tab, const double* const* c_tab, hipStream_t s);
 // True when the non-standard kernel for this k also applies the level-n subtraction.
 bool ns_kernel_fuses_subtraction(int k);
+// True when the non-standard kernel for this k shares the y- and z-contractions between
+// triples: it needs the FP64 triples of a target ordered by (term, dz, dy, dx).
+bool ns_kernel_factored(int k);
 void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
                      const NSItem* items, const TargetRange* targets, int ntargets,
                      const double* const* r_tab, const double* const* t_tab,
