@@ -731,8 +731,8 @@ struct BufTag {
 // (R_x = R^{n, dx}_mu etc.): step 1 (contract x) runs once per triple and accumulates in
 // registers, step 2 (contract y) once per (mu, dz, dy) group, step 3 (contract z, through
 // the LDS exchange tensor) once per (mu, dz) group.  The level-n subtraction -c (t x t x t)
-// s_P is factored the same way.  The lane mapping of each step is that of
-// apply_ns_mfma_kernel (block index = z inside a z-quad for steps 1 and 2).
+// s_P is factored the same way by apply_ns_fac_sub_kernel.  The lane mapping of each step
+// is that of apply_ns_mfma_kernel (block index = z inside a z-quad for steps 1 and 2).
 // The children block of the next triple and its operator blocks are copied into the other
 // half of two LDS buffers by direct global->LDS loads (16 bytes per lane, no registers)
 // while the current triple runs; the source block is stored row-major [x][y][z], whose
@@ -749,21 +749,18 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
   static_assert(Q == 5, "row stride 2k = 20 and the wave split below are for k = 10");
   constexpr int EXTRA = (Q - 4) * Q, EPW = (EXTRA + 3) / 4;   // (z-quad 4, a-quad) units
   constexpr int P3 = Q * Q, P3PW = (P3 + 3) / 4;              // step-3 (a-quad, b-quad) pairs
-  constexpr int Q2 = (K + 3) / 4, S3 = Q2 * Q2;               // subtraction on KP = 4 Q2
-  constexpr int SW = (P3 % 4 == 0) ? 4 : 3, S3PW = (S3 + SW - 1) / SW;
   // direct-load geometry, in 16-byte granules (two doubles)
   constexpr int XG = N3 / 2, XI = (XG + 63) / 64, XQ = (XI + 3) / 4, XPAD = 128 * XI;
-  constexpr int OPS = 3 * N2 + 3 * K2, OG = OPS / 2, OI = (OG + 63) / 64, OQ = (OI + 3) / 4,
+  constexpr int OPS = 3 * N2, OG = OPS / 2, OI = (OG + 63) / 64, OQ = (OI + 3) / 4,
                 OPAD = 128 * OI;
   static_assert(N2 % 2 == 0 && K2 % 2 == 0 && K % 2 == 0, "granules never straddle rows");
-  static_assert(P3 <= XPAD && 64 * Q2 * Q2 * Q2 <= XPAD && 64 * Q * Q * Q <= XPAD, "exchange fits");
+  static_assert(64 * Q * Q * Q <= XPAD, "the exchange tensor fits in a source buffer");
   // the two halves of each double buffer are separate objects, so that the compiler can
   // tell reads of one from the direct loads into the other
   __shared__ __attribute__((aligned(16))) double Xs0[XPAD];
   __shared__ __attribute__((aligned(16))) double Xs1[XPAD];
   __shared__ __attribute__((aligned(16))) double Os0[OPAD];
   __shared__ __attribute__((aligned(16))) double Os1[OPAD];
-  __shared__ double Z2s[K3];   // exchange tensor of the subtraction, [a][b][z], unpadded
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
@@ -771,9 +768,7 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
   const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
   MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
   const MRA_GLOBAL double* __restrict__ dR = as_global(r_tab[tr.fn]);
-  const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
   const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
-  const bool with_sub = tr.sub >= 0;
 
   // granule g of the row-major source block is (x, y, z = 2 zp), g = (x N + y) N/2 + zp;
   // this lane's offsets (doubles, from the first child's slab) for its wave's instructions
@@ -785,19 +780,13 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     const int child = ((x / K) << 2) | ((y / K) << 1) | (z / K);
     xoff[q] = child * K3 + ((x % K) * K + y % K) * K + z % K;
   }
-  // operator granules: [R_x^T | R_y^T | R_z^T] (N^2 each), then [t_x^T | t_y^T | t_z^T] (k^2)
+  // operator granules: [R_x^T | R_y^T | R_z^T] (N^2 each)
   int osel[OQ], ooff[OQ];
 #pragma unroll
   for (int q = 0; q < OQ; ++q) {
     const int g = min(64 * (wave + 4 * q) + lane, OG - 1);
-    if (g < 3 * N2 / 2) {
-      osel[q] = g / (N2 / 2);
-      ooff[q] = 2 * (g - osel[q] * (N2 / 2));
-    } else {
-      const int g2 = g - 3 * N2 / 2;
-      osel[q] = 3 + g2 / (K2 / 2);
-      ooff[q] = 2 * (g2 - (osel[q] - 3) * (K2 / 2));
-    }
+    osel[q] = g / (N2 / 2);
+    ooff[q] = 2 * (g - osel[q] * (N2 / 2));
   }
   auto dma_source = [&](int src_fc, double* dst) {
     const MRA_GLOBAL double* base = in + (size_t)src_fc * K3;
@@ -815,34 +804,14 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
       const int j = wave + 4 * q;
       if (j < OI) {
         const int sel = osel[q];
-        const int blk = sel == 0 ? nx.rx : sel == 1 ? nx.ry : sel == 2 ? nx.rz
-                      : sel == 3 ? nx.tx : sel == 4 ? nx.ty : nx.tz;
-        const MRA_GLOBAL double* src =
-            sel < 3 ? dR + (size_t)blk * N2 + ooff[q] : dT + (size_t)blk * K2 + ooff[q];
+        const int blk = sel == 0 ? nx.rx : sel == 1 ? nx.ry : nx.rz;
+        const MRA_GLOBAL double* src = dR + (size_t)blk * N2 + ooff[q];
         __builtin_amdgcn_global_load_lds((const MRA_GLOBAL void*)src,
                                          (MRA_LDS void*)(dst + 128 * j), 16, 0, 0);
       }
     }
   };
-  // this wave's z-quad of s_P as step-1 A operands of the subtraction (waves < Q2); the
-  // values outside k^3 are zeroed where they are used, so that nothing waits for the loads
-  auto sp_ok = [&](int xs, int yt) {
-    return 4 * xs + lk < K && 4 * yt + li < K && 4 * wave + lb < K;
-  };
-  auto load_sp = [&](const NSItem nx, double (&v)[Q2][Q2]) {
-    const MRA_GLOBAL double* __restrict__ sp = in + (size_t)nx.src * K3;
-    const int z = 4 * wave + lb;
-#pragma unroll
-    for (int xs = 0; xs < Q2; ++xs)
-#pragma unroll
-      for (int yt = 0; yt < Q2; ++yt) {
-        const int x = 4 * xs + lk, y = 4 * yt + li;
-        v[xs][yt] = sp[sp_ok(xs, yt) ? (x * K + y) * K + z : 0];
-      }
-  };
-
   double d1[Q][Q], d2[Q][Q], d1e[EPW][Q], d2e[EPW][Q], acc[P3PW][Q];
-  double d1s[Q2][Q2], d2s[Q2][Q2], sacc[S3PW][Q2], spv[Q2][Q2], spn[Q2][Q2];
 #pragma unroll
   for (int i = 0; i < Q; ++i)
 #pragma unroll
@@ -855,14 +824,6 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
   for (int e = 0; e < P3PW; ++e)
 #pragma unroll
     for (int j = 0; j < Q; ++j) acc[e][j] = 0.0;
-#pragma unroll
-  for (int i = 0; i < Q2; ++i)
-#pragma unroll
-    for (int j = 0; j < Q2; ++j) d1s[i][j] = d2s[i][j] = spv[i][j] = spn[i][j] = 0.0;
-#pragma unroll
-  for (int e = 0; e < S3PW; ++e)
-#pragma unroll
-    for (int j = 0; j < Q2; ++j) sacc[e][j] = 0.0;
 
   // item records two triples ahead: the next one is in registers when its loads are issued
   NSItem cur{}, nxt{};
@@ -872,7 +833,6 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     c_cur = dc[cur.mu];
     dma_source(cur.src_fc, Xs0);
     dma_ops(cur, Os0);
-    if (with_sub && wave < Q2) load_sp(cur, spv);
     nxt = items[min(tr.beg + 1, tr.end - 1)];
   }
   // one triple; BUF is a compile-time constant so that the compiler can tell the reads of
@@ -893,7 +853,6 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     if (more) {
       dma_source(nxt.src_fc, Xn);
       dma_ops(nxt, On);
-      if (with_sub && wave < Q2) load_sp(nxt, spn);
       c_pre = dc[nxt.mu];
     }
     const bool dy_end = !more || nxt.rz != item.rz || nxt.ry != item.ry;
@@ -903,9 +862,6 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     const double* RXs = Oc;
     const double* RYs = Oc + N2;
     const double* RZs = Oc + 2 * N2;
-    const double* TXs = Oc + 3 * N2;
-    const double* TYs = Oc + 3 * N2 + K2;
-    const double* TZs = Oc + 3 * N2 + 2 * K2;
     // ---- step 1: the main z-quad of this wave (all a-quads), then the z-quad-4 units
     {
       const int zq = wave;
@@ -939,20 +895,6 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
         }
       }
     }
-    if (with_sub && wave < Q2) {
-#pragma unroll
-      for (int xs = 0; xs < Q2; ++xs)
-#pragma unroll
-        for (int at = 0; at < Q2; ++at) {
-          const int r = 4 * xs + lk, cc = 4 * at + li;
-          const double t = TXs[(r < K && cc < K) ? r * K + cc : 0];
-          const double b = (r < K && cc < K) ? t : 0.0;
-#pragma unroll
-          for (int yt = 0; yt < Q2; ++yt)
-            d1s[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(sp_ok(xs, yt) ? spv[xs][yt] : 0.0, b,
-                                                             d1s[at][yt], 0, 0, 0);
-        }
-    }
     // ---- step 2 at the end of a (mu, dz, dy) group
     if (dy_end) {
 #pragma unroll
@@ -980,28 +922,11 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
       for (int e = 0; e < EPW; ++e)
 #pragma unroll
         for (int j = 0; j < Q; ++j) d1e[e][j] = 0.0;
-      if (with_sub && wave < Q2) {
-#pragma unroll
-        for (int ys = 0; ys < Q2; ++ys)
-#pragma unroll
-          for (int bt = 0; bt < Q2; ++bt) {
-            const int r = 4 * ys + lk, cc = 4 * bt + li;
-            const double t = TYs[(r < K && cc < K) ? r * K + cc : 0];
-            const double b = (r < K && cc < K) ? t : 0.0;
-#pragma unroll
-            for (int at = 0; at < Q2; ++at)
-              d2s[at][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1s[at][ys], b, d2s[at][bt], 0, 0, 0);
-          }
-#pragma unroll
-        for (int i = 0; i < Q2; ++i)
-#pragma unroll
-          for (int j = 0; j < Q2; ++j) d1s[i][j] = 0.0;
-      }
     }
     // ---- step 3 at the end of a (mu, dz) group, through this triple's source buffer
     if (dz_end) {
       double* Zs = Xc;
-      __syncthreads();   // every wave is done reading the source block and Z2s
+      __syncthreads();   // every wave is done reading the source block
       {
         const int zq = wave;
 #pragma unroll
@@ -1023,17 +948,6 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
             d2e[e][bt] = 0.0;
           }
         }
-      }
-      if (with_sub && wave < Q2) {
-        const int zq = wave;
-#pragma unroll
-        for (int at = 0; at < Q2; ++at)
-#pragma unroll
-          for (int bt = 0; bt < Q2; ++bt) {
-            const int a = 4 * at + lk, b = 4 * bt + li, z = 4 * zq + lb;
-            if (a < K && b < K && z < K) Z2s[(a * K + b) * K + z] = d2s[at][bt];
-            d2s[at][bt] = 0.0;
-          }
       }
       __syncthreads();
       {
@@ -1057,39 +971,7 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
           }
         }
       }
-      if (with_sub) {
-        double tz[Q2][Q2];
-#pragma unroll
-        for (int zs = 0; zs < Q2; ++zs)
-#pragma unroll
-          for (int ct = 0; ct < Q2; ++ct) {
-            const int r = 4 * zs + lk, cc = 4 * ct + li;
-            const double t = TZs[(r < K && cc < K) ? r * K + cc : 0];
-            tz[zs][ct] = (r < K && cc < K) ? -cmu * t : 0.0;
-          }
-#pragma unroll
-        for (int e = 0; e < S3PW; ++e) {
-          const int p = wave + SW * e;
-          if (wave < SW && p < S3) {
-            const int at3 = p / Q2, bt3 = p % Q2;
-#pragma unroll
-            for (int zs = 0; zs < Q2; ++zs) {
-              const int a = 4 * at3 + lb, b = 4 * bt3 + li, z = 4 * zs + lk;
-              const bool ok = a < K && b < K && z < K;
-              const double t = Z2s[ok ? (a * K + b) * K + z : 0];
-              const double v = ok ? t : 0.0;
-#pragma unroll
-              for (int ct = 0; ct < Q2; ++ct)
-                sacc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(v, tz[zs][ct], sacc[e][ct], 0, 0, 0);
-            }
-          }
-        }
-      }
     }
-#pragma unroll
-    for (int i = 0; i < Q2; ++i)
-#pragma unroll
-      for (int j = 0; j < Q2; ++j) spv[i][j] = spn[i][j];
     c_cur = c_pre;
     cur = nxt;
     nxt = nn;
@@ -1119,22 +1001,187 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
       }
     }
   }
-  if (with_sub) {
+}
+
+// Level-n subtraction of the factored kernel: sub_T = -sum c_mu (t_x x t_y x t_z) s_P over
+// the triples of a target, with the same grouping (step 1 per triple, step 2 per (mu, dz, dy)
+// group, step 3 per (mu, dz) group) on the k^3 scaling blocks, zero-padded to KP = 4 Q2.
+// Three waves: wave w owns z-quad w in steps 1 and 2; the nine step-3 (a-quad, b-quad) pairs
+// are split three per wave.  The t blocks of the next triple travel into the other half of
+// an LDS double buffer by direct loads; s_P fragments go to registers one triple ahead.
+template <int K>
+__global__ __launch_bounds__(192) void apply_ns_fac_sub_kernel(
+    const double* const* __restrict__ in_tab, const NSItem* __restrict__ items,
+    const TargetRange* __restrict__ targets, const double* const* __restrict__ t_tab,
+    const double* const* __restrict__ c_tab, double* __restrict__ partials,
+    double* __restrict__ subbuf) {
+  constexpr int N = 2 * K, N3 = N * N * N, K2 = K * K, K3 = K * K * K;
+  constexpr int Q2 = (K + 3) / 4, S3 = Q2 * Q2;
+  static_assert(Q2 == 3, "three waves own the three z-quads of KP = 12");
+  constexpr int S3PW = S3 / 3;
+  constexpr int TG = 3 * K2 / 2, TPAD = 128 * 3;   // t granules, padded to 3 x 64
+  static_assert(K2 % 2 == 0 && TG <= 192, "granules");
+  __shared__ __attribute__((aligned(16))) double Ts0[TPAD];
+  __shared__ __attribute__((aligned(16))) double Ts1[TPAD];
+  __shared__ double Z2s[K3];   // exchange tensor, [a][b][z], unpadded
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
+  const TargetRange tr = targets[blockIdx.x];
+  if (tr.sub < 0) return;   // level 0: no subtraction (uniform over the workgroup)
+  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
+  // this lane's granule of [t_x^T | t_y^T | t_z^T]
+  const int tg = min(64 * wave + lane, TG - 1);
+  const int tsel = tg / (K2 / 2), toff = 2 * (tg - tsel * (K2 / 2));
+  auto dma_t = [&](const NSItem nx, double* dst) {
+    const int blk = tsel == 0 ? nx.tx : tsel == 1 ? nx.ty : nx.tz;
+    __builtin_amdgcn_global_load_lds((const MRA_GLOBAL void*)(dT + (size_t)blk * K2 + toff),
+                                     (MRA_LDS void*)(dst + 128 * wave), 16, 0, 0);
+  };
+  // this wave's z-quad of s_P as step-1 A operands; zeroed outside k^3 where used
+  auto sp_ok = [&](int xs, int yt) {
+    return 4 * xs + lk < K && 4 * yt + li < K && 4 * wave + lb < K;
+  };
+  auto load_sp = [&](const NSItem nx, double (&v)[Q2][Q2]) {
+    const MRA_GLOBAL double* __restrict__ sp = in + (size_t)nx.src * K3;
 #pragma unroll
-    for (int e = 0; e < S3PW; ++e) {
-      const int p = wave + SW * e;
-      if (wave < SW && p < S3) {
-        const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + lk;
+    for (int xs = 0; xs < Q2; ++xs)
 #pragma unroll
-        for (int ct = 0; ct < Q2; ++ct) {
-          const int c = 4 * ct + li;
-          if (a < K && b < K && c < K) {
-            if (tr.partial >= 0)
-              partials[(size_t)tr.partial * (N3 + K3) + N3 + (a * K + b) * K + c] = sacc[e][ct];
-            else
-              subbuf[(size_t)tr.sub * K3 + (a * K + b) * K + c] = sacc[e][ct];
-          }
+      for (int yt = 0; yt < Q2; ++yt)
+        v[xs][yt] = sp[sp_ok(xs, yt) ? ((4 * xs + lk) * K + 4 * yt + li) * K + 4 * wave + lb : 0];
+  };
+  // t^T[r][c] as a B fragment, zero outside k x k
+  auto tfrag = [&](const double* T, int rq, int cq) {
+    const int r = 4 * rq + lk, c = 4 * cq + li;
+    const bool ok = r < K && c < K;
+    const double v = T[ok ? r * K + c : 0];
+    return ok ? v : 0.0;
+  };
+
+  double d1[Q2][Q2], d2[Q2][Q2], acc[S3PW][Q2], spv[Q2][Q2], spn[Q2][Q2];
+#pragma unroll
+  for (int i = 0; i < Q2; ++i)
+#pragma unroll
+    for (int j = 0; j < Q2; ++j) d1[i][j] = d2[i][j] = spv[i][j] = spn[i][j] = 0.0;
+#pragma unroll
+  for (int e = 0; e < S3PW; ++e)
+#pragma unroll
+    for (int j = 0; j < Q2; ++j) acc[e][j] = 0.0;
+
+  NSItem cur{}, nxt{};
+  double c_cur = 0.0, c_pre = 0.0;
+  if (tr.beg < tr.end) {
+    cur = items[tr.beg];
+    c_cur = dc[cur.mu];
+    dma_t(cur, Ts0);
+    load_sp(cur, spv);
+    nxt = items[min(tr.beg + 1, tr.end - 1)];
+  }
+  auto triple = [&](const int it, auto buf_tag) {
+    constexpr int buf = decltype(buf_tag)::value;
+    const double* const Tc = buf == 0 ? Ts0 : Ts1;
+    double* const Tn = buf == 0 ? Ts1 : Ts0;
+    const NSItem item = cur;
+    const bool more = it + 1 < tr.end;
+    const NSItem nn = items[min(it + 2, tr.end - 1)];
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads of triple it
+    __syncthreads();
+    if (more) {
+      dma_t(nxt, Tn);
+      load_sp(nxt, spn);
+      c_pre = dc[nxt.mu];
+    }
+    const bool dy_end = !more || nxt.rz != item.rz || nxt.ry != item.ry;
+    const bool dz_end = !more || nxt.rz != item.rz;
+    const double* TXs = Tc;
+    const double* TYs = Tc + K2;
+    const double* TZs = Tc + 2 * K2;
+    // step 1 (contract x) for this wave's z-quad
+#pragma unroll
+    for (int xs = 0; xs < Q2; ++xs)
+#pragma unroll
+      for (int at = 0; at < Q2; ++at) {
+        const double b = tfrag(TXs, xs, at);
+#pragma unroll
+        for (int yt = 0; yt < Q2; ++yt)
+          d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(sp_ok(xs, yt) ? spv[xs][yt] : 0.0, b,
+                                                          d1[at][yt], 0, 0, 0);
+      }
+    // step 2 (contract y) at the end of a (mu, dz, dy) group
+    if (dy_end) {
+#pragma unroll
+      for (int ys = 0; ys < Q2; ++ys)
+#pragma unroll
+        for (int bt = 0; bt < Q2; ++bt) {
+          const double b = tfrag(TYs, ys, bt);
+#pragma unroll
+          for (int at = 0; at < Q2; ++at)
+            d2[at][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], b, d2[at][bt], 0, 0, 0);
         }
+#pragma unroll
+      for (int i = 0; i < Q2; ++i)
+#pragma unroll
+        for (int j = 0; j < Q2; ++j) d1[i][j] = 0.0;
+    }
+    // step 3 (contract z) at the end of a (mu, dz) group; Z2s was last read before the
+    // barrier at the top of this triple
+    if (dz_end) {
+#pragma unroll
+      for (int at = 0; at < Q2; ++at)
+#pragma unroll
+        for (int bt = 0; bt < Q2; ++bt) {
+          const int a = 4 * at + lk, b = 4 * bt + li, z = 4 * wave + lb;
+          if (a < K && b < K && z < K) Z2s[(a * K + b) * K + z] = d2[at][bt];
+          d2[at][bt] = 0.0;
+        }
+      __syncthreads();
+      double tz[Q2][Q2];
+#pragma unroll
+      for (int zs = 0; zs < Q2; ++zs)
+#pragma unroll
+        for (int ct = 0; ct < Q2; ++ct) tz[zs][ct] = -c_cur * tfrag(TZs, zs, ct);
+#pragma unroll
+      for (int e = 0; e < S3PW; ++e) {
+        const int p = wave + 3 * e;
+        const int at3 = p / Q2, bt3 = p % Q2;
+#pragma unroll
+        for (int zs = 0; zs < Q2; ++zs) {
+          const int a = 4 * at3 + lb, b = 4 * bt3 + li, z = 4 * zs + lk;
+          const bool ok = a < K && b < K && z < K;
+          const double t = Z2s[ok ? (a * K + b) * K + z : 0];
+          const double v = ok ? t : 0.0;
+#pragma unroll
+          for (int ct = 0; ct < Q2; ++ct)
+            acc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(v, tz[zs][ct], acc[e][ct], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < Q2; ++i)
+#pragma unroll
+      for (int j = 0; j < Q2; ++j) spv[i][j] = spn[i][j];
+    c_cur = c_pre;
+    cur = nxt;
+    nxt = nn;
+  };
+  for (int it = tr.beg; it < tr.end; it += 2) {
+    triple(it, BufTag<0>{});
+    if (it + 1 < tr.end) triple(it + 1, BufTag<1>{});
+  }
+#pragma unroll
+  for (int e = 0; e < S3PW; ++e) {
+    const int p = wave + 3 * e;
+    const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + lk;
+#pragma unroll
+    for (int ct = 0; ct < Q2; ++ct) {
+      const int c = 4 * ct + li;
+      if (a < K && b < K && c < K) {
+        if (tr.partial >= 0)
+          partials[(size_t)tr.partial * (N3 + K3) + N3 + (a * K + b) * K + c] = acc[e][ct];
+        else
+          subbuf[(size_t)tr.sub * K3 + (a * K + b) * K + c] = acc[e][ct];
       }
     }
   }
@@ -2206,6 +2253,9 @@ void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
   } else if (k == 10) {
     hipLaunchKernelGGL(apply_ns_fac_kernel<10>, dim3(ntargets), dim3(256), 0, s, in_tab,
                        out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
+    hip_check(hipGetLastError(), "apply_ns_fac_kernel");
+    hipLaunchKernelGGL(apply_ns_fac_sub_kernel<10>, dim3(ntargets), dim3(192), 0, s, in_tab,
+                       items, targets, t_tab, c_tab, partials, subbuf);
   } else if (k == 12) {
     hipLaunchKernelGGL(apply_ns_own_kernel<12>, dim3(ntargets), dim3(256), 0, s, in_tab,
                        out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
