@@ -508,13 +508,13 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
 }
 
 // ------------------------------------------------------------------------ reductions
-// Fixed-order reduction over leaves: 256 workgroup partials, summed in order on the host.
+// Fixed-order reduction over leaves: 2048 workgroup partials, summed in order on the host.
 // la_dev (optional) is a device copy of la.
 static double reduce(Ctx* ctx, int k, const double* a, const double* b,
                      const std::vector<int32_t>& la, const std::vector<int32_t>* lb,
                      const std::vector<double>* w, int mode, const int32_t* la_dev = nullptr) {
   if (la.empty()) return 0.0;
-  const int nblocks = 256;
+  const int nblocks = 2048;
   DevArray<int32_t> d_la, d_lb;
   DevArray<double> d_w;
   if (!la_dev) {

@@ -98,23 +98,24 @@ __global__ __launch_bounds__(256) void filter_up_kernel(
     const int bx = X / K, i = X % K, by = Y / K, j = Y % K;
     const MRA_GLOBAL double* r0 = coeff + (size_t)(fc + ((bx << 2) | (by << 1))) * K3 + (i * K + j) * K;
     const MRA_GLOBAL double* r1 = r0 + K3;
-    double t[K];
     double row[UP];
 #pragma unroll
-    for (int m = 0; m < K; ++m) t[m] = 0.0;
+    for (int z = 0; z < K; ++z) {
+      row[z] = r0[z];
+      row[K + z] = r1[z];
+    }
 #pragma unroll
     for (int z = N; z < UP; ++z) row[z] = 0.0;
 #pragma unroll
-    for (int z = 0; z < K; ++z) {
-      const double v0 = r0[z], v1 = r1[z];
-      row[z] = v0;
-      row[K + z] = v1;
-      sq += v0 * v0 + v1 * v1;
+    for (int z = 0; z < K; ++z) sq += row[z] * row[z] + row[K + z] * row[K + z];
+    // one output at a time: the row stays in registers, H is read from LDS (broadcast)
+#pragma unroll 1
+    for (int m = 0; m < K; ++m) {
+      double t = 0.0;
 #pragma unroll
-      for (int m = 0; m < K; ++m) t[m] += H[m * N + z] * v0 + H[m * N + K + z] * v1;
+      for (int z = 0; z < N; ++z) t += H[m * N + z] * row[z];
+      T1[(X * N + Y) * KP1 + m] = t;
     }
-#pragma unroll
-    for (int m = 0; m < K; ++m) T1[(X * N + Y) * KP1 + m] = t[m];
     if (mirror) {
       u32x4* dst = reinterpret_cast<u32x4*>(mirror + (size_t)blockIdx.x * N * N * UP +
                                             (size_t)(X * N + Y) * UP);
@@ -141,6 +142,7 @@ __global__ __launch_bounds__(256) void filter_up_kernel(
     double t[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) t[j] = 0.0;
+#pragma unroll 1
     for (int Y = 0; Y < N; ++Y) {
       const double v = T1[(X * N + Y) * KP1 + m];
 #pragma unroll
@@ -156,6 +158,7 @@ __global__ __launch_bounds__(256) void filter_up_kernel(
     double t[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) t[i] = 0.0;
+#pragma unroll 1
     for (int X = 0; X < N; ++X) {
       const double v = T2[(X * K + j) * KP1 + m];
 #pragma unroll
@@ -265,6 +268,8 @@ __global__ __launch_bounds__(round64(4 * K * K)) void apply_ns_kernel(
 }
 
 // Sum the partial children blocks of split targets in slot order and add them to the output.
+// blockIdx.y selects a chunk of the target's elements; each thread sums its element over the
+// slots in ascending order (loads of four slots in flight), so the result is fixed.
 template <int K>
 __global__ __launch_bounds__(256) void reduce_partials_kernel(
     const double* __restrict__ partials, double* const* __restrict__ out_tab,
@@ -272,20 +277,30 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(
   constexpr int N = 2 * K, N3 = N * N * N, K3 = K * K * K, SLOT = N3 + K3;
   const SplitTarget sp = splits[blockIdx.x];
   MRA_GLOBAL double* __restrict__ out = as_global(out_tab[sp.fn]);
-  for (int e = threadIdx.x; e < N3; e += 256) {
+  const int e0 = blockIdx.y * blockDim.x + threadIdx.x, stride = gridDim.y * blockDim.x;
+  auto slot_sum = [&](int e) {
+    const double* p = partials + (size_t)sp.first * SLOT + e;
     double s = 0.0;
-    for (int q = 0; q < sp.count; ++q) s += partials[(size_t)(sp.first + q) * SLOT + e];
-    int a = e / (N * N), b = (e / N) % N, c = e % N;
-    int child = ((a / K) << 2) | ((b / K) << 1) | (c / K);
+    int q = 0;
+    for (; q + 4 <= sp.count; q += 4) {
+      const double v0 = p[(size_t)q * SLOT], v1 = p[(size_t)(q + 1) * SLOT],
+                   v2 = p[(size_t)(q + 2) * SLOT], v3 = p[(size_t)(q + 3) * SLOT];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; q < sp.count; ++q) s += p[(size_t)q * SLOT];
+    return s;
+  };
+  for (int e = e0; e < N3; e += stride) {
+    const double s = slot_sum(e);
+    const int a = e / (N * N), b = (e / N) % N, c = e % N;
+    const int child = ((a / K) << 2) | ((b / K) << 1) | (c / K);
     out[(size_t)(sp.fc + child) * K3 + ((a % K) * K + (b % K)) * K + (c % K)] += s;
   }
-  if (sp.sub >= 0) {
-    for (int e = threadIdx.x; e < K3; e += 256) {
-      double s = 0.0;
-      for (int q = 0; q < sp.count; ++q) s += partials[(size_t)(sp.first + q) * SLOT + N3 + e];
-      subbuf[(size_t)sp.sub * K3 + e] = s;
-    }
-  }
+  if (sp.sub >= 0)
+    for (int e = e0; e < K3; e += stride) subbuf[(size_t)sp.sub * K3 + e] = slot_sum(N3 + e);
 }
 
 // ------------------------------------------------------- LDS layouts of the 4x4x4 operands
@@ -1273,8 +1288,11 @@ __global__ __launch_bounds__(round64(K * K)) void apply_std_kernel(
 }
 
 // --------------------------------------------------------------------------- sum-down
+// One workgroup of 256 threads per interior output box: three mode products with the
+// unfilter matrix [h0 | h1]^T, each thread owning output columns; the contraction loops stay
+// rolled so that a thread keeps one column (2k doubles) in registers, not the matrix.
 template <int K>
-__global__ __launch_bounds__(round64(4 * K * K)) void sum_down_kernel(
+__global__ __launch_bounds__(256) void sum_down_kernel(
     double* const* __restrict__ tab, const NodeRef* __restrict__ refs,
     const double* __restrict__ subbuf, const double* __restrict__ h0,
     const double* __restrict__ h1) {
@@ -1286,21 +1304,23 @@ __global__ __launch_bounds__(round64(4 * K * K)) void sum_down_kernel(
   const NodeRef ref = refs[blockIdx.x];
   const int node = ref.node, fc = ref.fchild;
   MRA_GLOBAL double* __restrict__ coeff = as_global(tab[ref.fn]);
-  for (int e = tid; e < K * N; e += blockDim.x) {
+  for (int e = tid; e < K * N; e += 256) {
     int i = e / N, X = e % N;
     H[e] = X < K ? h0[i * K + X] : h1[i * K + X - K];
   }
   const MRA_GLOBAL double* __restrict__ V = coeff + (size_t)node * K3;
   const double* __restrict__ VS = ref.sub >= 0 ? subbuf + (size_t)ref.sub * K3 : nullptr;
+  double* Vs = T2;   // the box's coefficients (plus its level-n part), until phase 2
+  for (int e = tid; e < K3; e += 256) Vs[e] = VS ? V[e] + VS[e] : V[e];
   __syncthreads();
-  if (tid < K * K) {  // T1[i][j][Z] = sum_m H[m][Z] V[i][j][m]
-    int i = tid / K, j = tid % K;
+  for (int col = tid; col < K * K; col += 256) {  // T1[i][j][Z] = sum_m H[m][Z] V[i][j][m]
+    const int i = col / K, j = col % K;
     double t[N];
 #pragma unroll
     for (int Z = 0; Z < N; ++Z) t[Z] = 0.0;
+#pragma unroll 1
     for (int m = 0; m < K; ++m) {
-      double v = V[(i * K + j) * K + m];
-      if (VS) v += VS[(i * K + j) * K + m];
+      const double v = Vs[(i * K + j) * K + m];
 #pragma unroll
       for (int Z = 0; Z < N; ++Z) t[Z] += H[m * N + Z] * v;
     }
@@ -1308,13 +1328,14 @@ __global__ __launch_bounds__(round64(4 * K * K)) void sum_down_kernel(
     for (int Z = 0; Z < N; ++Z) T1[(i * K + j) * ZP + Z] = t[Z];
   }
   __syncthreads();
-  if (tid < K * N) {  // T2[i][Y][Z] = sum_j H[j][Y] T1[i][j][Z]
-    int i = tid / N, Z = tid % N;
+  for (int col = tid; col < K * N; col += 256) {  // T2[i][Y][Z] = sum_j H[j][Y] T1[i][j][Z]
+    const int i = col / N, Z = col % N;
     double t[N];
 #pragma unroll
     for (int Y = 0; Y < N; ++Y) t[Y] = 0.0;
+#pragma unroll 1
     for (int j = 0; j < K; ++j) {
-      double v = T1[(i * K + j) * ZP + Z];
+      const double v = T1[(i * K + j) * ZP + Z];
 #pragma unroll
       for (int Y = 0; Y < N; ++Y) t[Y] += H[j * N + Y] * v;
     }
@@ -1322,43 +1343,73 @@ __global__ __launch_bounds__(round64(4 * K * K)) void sum_down_kernel(
     for (int Y = 0; Y < N; ++Y) T2[(i * N + Y) * ZP + Z] = t[Y];
   }
   __syncthreads();
-  if (tid < N * N) {  // child[X][Y][Z] += sum_i H[i][X] T2[i][Y][Z]
-    int Y = tid / N, Z = tid % N;
-    double t[N];
+  for (int col = tid; col < N * N; col += 256) {  // child[X][Y][Z] += sum_i H[i][X] T2[i][Y][Z]
+    const int Y = col / N, Z = col % N;
+    const int cy = Y / K, j = Y % K, cz = Z / K, m = Z % K;
+    double old[N], t[N];   // the children's values are loaded first, added after the sum
 #pragma unroll
-    for (int X = 0; X < N; ++X) t[X] = 0.0;
+    for (int X = 0; X < N; ++X) {
+      old[X] = coeff[(size_t)(fc + ((X / K) << 2 | (cy << 1) | cz)) * K3 + ((X % K) * K + j) * K + m];
+      t[X] = 0.0;
+    }
+#pragma unroll 1
     for (int i = 0; i < K; ++i) {
-      double v = T2[(i * N + Y) * ZP + Z];
+      const double v = T2[(i * N + Y) * ZP + Z];
 #pragma unroll
       for (int X = 0; X < N; ++X) t[X] += H[i * N + X] * v;
     }
-    int cy = Y / K, j = Y % K, cz = Z / K, m = Z % K;
 #pragma unroll
-    for (int X = 0; X < N; ++X) {
-      int child = ((X / K) << 2) | (cy << 1) | cz;
-      coeff[(size_t)(fc + child) * K3 + ((X % K) * K + j) * K + m] += t[X];
-    }
+    for (int X = 0; X < N; ++X)
+      coeff[(size_t)(fc + ((X / K) << 2 | (cy << 1) | cz)) * K3 + ((X % K) * K + j) * K + m] =
+          old[X] + t[X];
   }
 }
 
 // --------------------------------------------------------------------------- reductions
-// mode 0: sum ||a_leaf||^2; mode 1: sum a_leaf[0] * weight[leaf]; mode 2: sum <a_la, b_lb>
+// mode 0: sum ||a_leaf||^2; mode 1: sum a_leaf[0] * weight[leaf]; mode 2: sum <a_la, b_lb>.
+// Workgroup g takes leaves g, g + G, g + 2G, ... (G = gridDim.x) in that order, its threads
+// the elements e = t, t + 256, ... of each leaf, and the partials are combined in a fixed
+// tree: the result does not depend on scheduling.  The next leaf's index is loaded before
+// the current leaf's elements so that consecutive leaves overlap their latencies.
 __global__ __launch_bounds__(256) void leaf_reduce_kernel(
     int k3, const double* __restrict__ a, const double* __restrict__ b,
     const int32_t* __restrict__ la, const int32_t* __restrict__ lb,
     const double* __restrict__ weight, int count, int mode, double* __restrict__ partial) {
   __shared__ double red[256];
   double s = 0.0;
-  for (int l = blockIdx.x; l < count; l += gridDim.x) {
-    const double* pa = a + (size_t)la[l] * k3;
+  int l = blockIdx.x;
+  int ia = l < count ? la[l] : 0, ib = (mode == 2 && l < count) ? lb[l] : 0;
+  for (; l < count; l += gridDim.x) {
+    const int ln = l + gridDim.x;
+    const int na = ln < count ? la[ln] : 0, nb = (mode == 2 && ln < count) ? lb[ln] : 0;
+    const double* pa = a + (size_t)ia * k3;
     if (mode == 0) {
-      for (int e = threadIdx.x; e < k3; e += blockDim.x) s += pa[e] * pa[e];
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        v[q] = e < k3 ? pa[e] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s += v[q] * v[q];
+      for (int e = threadIdx.x + 1024; e < k3; e += 256) s += pa[e] * pa[e];
     } else if (mode == 1) {
       if (threadIdx.x == 0) s += pa[0] * weight[l];
     } else {
-      const double* pb = b + (size_t)lb[l] * k3;
-      for (int e = threadIdx.x; e < k3; e += blockDim.x) s += pa[e] * pb[e];
+      const double* pb = b + (size_t)ib * k3;
+      double v[4], w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        v[q] = e < k3 ? pa[e] : 0.0;
+        w[q] = e < k3 ? pb[e] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s += v[q] * w[q];
+      for (int e = threadIdx.x + 1024; e < k3; e += 256) s += pa[e] * pb[e];
     }
+    ia = na;
+    ib = nb;
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -2274,7 +2325,7 @@ void launch_reduce_partials(int k, const double* partials, double* const* out_ta
                             double* subbuf, const SplitTarget* splits, int nsplits,
                             hipStream_t s) {
   if (nsplits <= 0) return;
-  MRA_DISPATCH_K14(k, hipLaunchKernelGGL(reduce_partials_kernel<KK>, dim3(nsplits), dim3(256),
+  MRA_DISPATCH_K14(k, hipLaunchKernelGGL(reduce_partials_kernel<KK>, dim3(nsplits, 8), dim3(256),
                                          0, s, partials, out_tab, subbuf, splits));
   hip_check(hipGetLastError(), "reduce_partials_kernel");
 }
@@ -2293,9 +2344,8 @@ void launch_apply_std(int k, const double* const* in_tab, double* const* out_tab
 void launch_sum_down(int k, double* const* coeff_tab, const NodeRef* refs, int count,
                      const double* subbuf, const double* h0, const double* h1, hipStream_t s) {
   if (count <= 0) return;
-  MRA_DISPATCH_K14(k, hipLaunchKernelGGL(sum_down_kernel<KK>, dim3(count),
-                                         dim3(round64(4 * KK * KK)), 0, s, coeff_tab, refs,
-                                         subbuf, h0, h1));
+  MRA_DISPATCH_K14(k, hipLaunchKernelGGL(sum_down_kernel<KK>, dim3(count), dim3(256), 0, s,
+                                         coeff_tab, refs, subbuf, h0, h1));
   hip_check(hipGetLastError(), "sum_down_kernel");
 }
 

@@ -147,7 +147,7 @@ struct Ctx {
   mra_apply_stats stats{};
   hipEvent_t ev[8]{};
   Arena arena[3];                      // filter-up phase, plans of alternate sub-batches
-  double* red_part = nullptr;          // 256 partial sums of the leaf reductions
+  double* red_part = nullptr;          // 2048 partial sums of the leaf reductions
 
   double width() const { return hi - lo; }
   void* dalloc(size_t bytes);
