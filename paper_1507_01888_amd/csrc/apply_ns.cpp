@@ -165,9 +165,19 @@ void build_output_tree(Ctx* ctx, Plan& p, const std::vector<uint64_t>& tcodes) {
 
 // The kept triples of one (function, level) unit, grouped by target and, within a target,
 // ordered by source then term (so that a source block is staged once per run of terms).
+// Triples of a level are split by the top bits of the target's Morton code into kBuckets
+// buckets (ascending code ranges) so that grouping runs in parallel on small pieces; the
+// units of a level, in bucket order, list the targets in ascending code order.
+constexpr int kBuckets = 16;
+inline int target_bucket(int n, uint64_t code) {
+  const int bits = 3 * n;
+  return bits > 4 ? (int)(code >> (bits - 4)) : (int)code;
+}
+
 struct Unit {
   int fn = 0, n = 0;
   size_t jb = 0, je = 0;               // jobs of this unit
+  int bucket = 0;                      // target-code bucket of this unit
   std::vector<Triple> sorted;
   std::vector<uint64_t> tcodes;        // ascending
   std::vector<int64_t> toff;           // tcodes.size() + 1
@@ -179,8 +189,9 @@ struct Unit {
 
 void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const LevelData& L,
                 bool factored) {
+  auto piece = [&](size_t j) -> const std::vector<Triple>& { return jobout[j * kBuckets + u.bucket]; };
   size_t m = 0;
-  for (size_t j = u.jb; j < u.je; ++j) m += jobout[j].size();
+  for (size_t j = u.jb; j < u.je; ++j) m += piece(j).size();
   // composite key (target code, tier, source rank); an LSD radix sort on it is stable, and
   // the jobs of a unit are in ascending term order, so terms stay ascending per source.
   // For a factored kernel the FP64 triples leave the source rank out of the key: they keep
@@ -192,7 +203,7 @@ void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const L
     u.sorted.clear();
     u.sorted.reserve(m);
     for (size_t j = u.jb; j < u.je; ++j)
-      u.sorted.insert(u.sorted.end(), jobout[j].begin(), jobout[j].end());
+      u.sorted.insert(u.sorted.end(), piece(j).begin(), piece(j).end());
     std::stable_sort(u.sorted.begin(), u.sorted.end(), [factored](const Triple& a, const Triple& b) {
       if (a.tcode != b.tcode) return a.tcode < b.tcode;
       if (a.low != b.low) return a.low < b.low;
@@ -223,7 +234,7 @@ void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const L
   {
     size_t q = 0;
     for (size_t j = u.jb; j < u.je; ++j)
-      for (const Triple& t : jobout[j]) {
+      for (const Triple& t : piece(j)) {
         key[q] = ((t.tcode & cmask) << (1 + sbits)) | ((uint64_t)t.low << sbits) |
                  ((t.low || !factored) ? (uint64_t)(t.src - L.ib) : 0);
         idx[q] = (uint32_t)q;
@@ -552,7 +563,13 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
     const double t_sb0 = now_ms();
     t_mark = t_sb0;
     // ---- 2b. enumerate kept triples (threads over jobs; one output vector per job)
-    std::vector<std::vector<Triple>> jobout(j1 - j0);
+    // per (job, bucket) outputs; the vectors keep their capacity across applies on this host
+    // thread, so enumeration neither allocates nor frees in steady state
+    static thread_local std::vector<std::vector<Triple>> t_jobout;
+    std::vector<std::vector<Triple>>& jobout = t_jobout;
+    const size_t njb = (j1 - j0) * kBuckets;
+    if (jobout.size() < njb) jobout.resize(njb);
+    for (size_t q = 0; q < njb; ++q) jobout[q].clear();
     parallel_for(j1 - j0, [&](size_t jj, unsigned) {
       const Job& jb = jobs[j0 + jj];
       const LevelData& L = lv[jb.lev];
@@ -566,7 +583,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
         aa[d] = jb.be->a[d];
         rr[d] = jb.be->r[d];
       }
-      auto& outv = jobout[jj];
+      std::vector<Triple>* outv = &jobout[jj * kBuckets];
       // dz outermost: per target the triples of a term come in (dz, dy, dx) order
       for (int dz = -D; dz <= D; ++dz)
         for (int dy = -D; dy <= D; ++dy)
@@ -582,32 +599,51 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
               int64_t tx = L.px[p] + dx, ty = L.py[p] + dy, tz = L.pz[p] + dz;
               if (tx < 0 || ty < 0 || tz < 0 || tx >= nb || ty >= nb || tz >= nb) continue;
               const int8_t low = (tiers && n > 0 && eta < tau_tier) ? 1 : 0;
-              outv.push_back({((uint64_t)n << 58) | encode(n, tx, ty, tz), (int32_t)(L.ib + p),
-                              (int16_t)mu, (int16_t)dx, (int16_t)dy, (int16_t)dz, low});
+              const uint64_t code = encode(n, tx, ty, tz);
+              outv[target_bucket(n, code)].push_back({((uint64_t)n << 58) | code,
+                                                      (int32_t)(L.ib + p), (int16_t)mu,
+                                                      (int16_t)dx, (int16_t)dy, (int16_t)dz, low});
             }
           }
     });
     mark("enumerate");
-    // ---- 3. group by target per (function, level) unit, output tree per function
+    // ---- 3. group by target per (function, level, bucket) unit, output tree per function
     std::vector<Unit> units;
     std::vector<int> unit_lev;
     for (size_t j = j0; j < j1;) {
       size_t e = j;
       while (e < j1 && jobs[e].lev == jobs[j].lev) ++e;
-      Unit u;
-      u.fn = lv[jobs[j].lev].fn;
-      u.n = lv[jobs[j].lev].n;
-      u.jb = j - j0;
-      u.je = e - j0;
-      units.push_back(std::move(u));
-      unit_lev.push_back(jobs[j].lev);
+      for (int b = 0; b < kBuckets; ++b) {
+        bool any = false;
+        for (size_t q = j; q < e && !any; ++q) any = !jobout[(q - j0) * kBuckets + b].empty();
+        if (!any) continue;
+        Unit u;
+        u.fn = lv[jobs[j].lev].fn;
+        u.n = lv[jobs[j].lev].n;
+        u.jb = j - j0;
+        u.je = e - j0;
+        u.bucket = b;
+        units.push_back(std::move(u));
+        unit_lev.push_back(jobs[j].lev);
+      }
       j = e;
     }
-    parallel_for(units.size(), [&](size_t i, unsigned) {
+    // largest units first on the pool
+    std::vector<size_t> uorder(units.size());
+    std::iota(uorder.begin(), uorder.end(), 0);
+    {
+      std::vector<size_t> usize(units.size(), 0);
+      for (size_t i = 0; i < units.size(); ++i)
+        for (size_t q = units[i].jb; q < units[i].je; ++q)
+          usize[i] += jobout[q * kBuckets + units[i].bucket].size();
+      std::stable_sort(uorder.begin(), uorder.end(),
+                       [&](size_t a, size_t b) { return usize[a] > usize[b]; });
+    }
+    parallel_for(units.size(), [&](size_t ii, unsigned) {
+      const size_t i = uorder[ii];
       group_unit(units[i], jobout, lv[unit_lev[i]], factored);
     });
     mark("group by target");
-    std::vector<std::vector<Triple>>().swap(jobout);
     parallel_for((size_t)(f1 - f0), [&](size_t ii, unsigned) {
       const int i = f0 + (int)ii;
       std::vector<uint64_t> tc;

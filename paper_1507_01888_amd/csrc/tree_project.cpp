@@ -32,14 +32,15 @@ void build_tree(Func& f, const std::vector<std::vector<uint64_t>>& levels) {
   for (int n = 0; n < f.nlev; ++n)
     std::copy(levels[n].begin(), levels[n].end(), f.code.begin() + f.level_off[n]);
   for (int n = 0; n + 1 < f.nlev; ++n) {
+    // both code lists are ascending: one merge walk links every parent to its first child
     const auto& kids = levels[n + 1];
+    const int64_t nk = (int64_t)kids.size();
+    int64_t j = 0;
     for (int64_t i = f.level_off[n]; i < f.level_off[n + 1]; ++i) {
-      uint64_t c0 = f.code[i] << 3;
-      auto it = std::lower_bound(kids.begin(), kids.end(), c0);
-      if (it != kids.end() && *it == c0) {
-        int64_t j = it - kids.begin();
-        if (j + 7 >= (int64_t)kids.size() || kids[j + 7] != c0 + 7)
-          fail(MRA_E_INVALID, "tree is not a full octree");
+      const uint64_t c0 = f.code[i] << 3;
+      while (j < nk && kids[j] < c0) ++j;
+      if (j < nk && kids[j] == c0) {
+        if (j + 7 >= nk || kids[j + 7] != c0 + 7) fail(MRA_E_INVALID, "tree is not a full octree");
         f.first_child[i] = (int32_t)(f.level_off[n + 1] + j);
       }
     }
