@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <memory>
 #include <numeric>
 #include <thread>
 #include <unordered_map>
@@ -65,6 +66,40 @@ int64_t find_node(const Func& f, int n, uint64_t code) {
 template <class F>
 void parallel_for(size_t count, F&& fn) {
   Pool::get().run(count, std::function<void(size_t, unsigned)>(fn));
+}
+
+// |c| N(delta) of the screening bound (N = prod(a + e) - prod(a) at n > 0, prod(r) at n = 0).
+// One definition with contraction off, so that the target pre-pass and the enumeration
+// compare bit-identical values (and the same values as an evaluation without fused
+// multiply-adds).
+inline double screen_cn(double c, int n, const double* ae, const double* aa, const double* rr,
+                        int ax, int ay, int az) {
+#pragma clang fp contract(off)
+  const double N = n > 0 ? ae[ax] * ae[ay] * ae[az] - aa[ax] * aa[ay] * aa[az]
+                         : rr[ax] * rr[ay] * rr[az];
+  return c * N;
+}
+
+// Sorts codes below 2^bits ascending and removes duplicates (LSD radix, 11-bit digits).
+void radix_sort_unique(std::vector<uint64_t>& v, int bits) {
+  if (v.size() > 1 && bits > 0) {
+    constexpr int RB = 11;
+    std::vector<uint64_t> tmp(v.size());
+    std::vector<uint32_t> cnt(1u << RB);
+    for (int sh = 0; sh < bits; sh += RB) {
+      std::fill(cnt.begin(), cnt.end(), 0u);
+      for (uint64_t x : v) ++cnt[(x >> sh) & ((1u << RB) - 1)];
+      uint32_t run = 0;
+      for (auto& c : cnt) {
+        const uint32_t t = c;
+        c = run;
+        run += t;
+      }
+      for (uint64_t x : v) tmp[cnt[(x >> sh) & ((1u << RB) - 1)]++] = x;
+      v.swap(tmp);
+    }
+  }
+  v.erase(std::unique(v.begin(), v.end()), v.end());
 }
 
 struct Triple {
@@ -539,15 +574,18 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   }
   const int nsb = (int)fb.size() - 1;
   struct Events {
-    hipEvent_t e[5]{};   // apply start, main kernel end, low start, apply end, sum-down end
+    hipEvent_t e[4]{};
+    Events() {
+      for (auto& x : e) hip_check(hipEventCreate(&x), "hipEventCreate");
+    }
     ~Events() {
       for (auto& x : e)
         if (x) (void)hipEventDestroy(x);
     }
   };
-  std::vector<Events> sev(nsb);
-  for (auto& se : sev)
-    for (auto& x : se.e) hip_check(hipEventCreate(&x), "hipEventCreate");
+  // per chunk: transform start, main kernel end, low-tier start, chunk end;
+  // per sub-batch: sum-down start, sum-down end
+  std::vector<std::unique_ptr<Events>> cev, sev;
 
   const double f_ns = 6.0 * std::pow(2.0 * k, 4), f_sub = 6.0 * std::pow((double)k, 4);
   const bool fused = ns_kernel_fuses_subtraction(k);
@@ -555,239 +593,201 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   int64_t ntriples = 0, ntargets = 0, nlow = 0, in_leaves = 0, out_nodes = 0, out_leaves = 0;
   double flops = 0.0, flops_low = 0.0, eta_low = 0.0, flops_kernel = 0.0, plan_ms = t_prep;
   bool any_low = false;
+  // per (job, bucket) outputs; the vectors keep their capacity across applies on this host
+  // thread, so enumeration neither allocates nor frees in steady state
+  static thread_local std::vector<std::vector<Triple>> t_jobout;
+  std::vector<std::vector<Triple>>& jobout = t_jobout;
 
   for (int sb = 0; sb < nsb; ++sb) {
     const int f0 = fb[sb], f1 = fb[sb + 1];
     const size_t j0 = job_begin[f0], j1 = job_begin[f1];
-    if (sb >= 2) hip_check(hipEventSynchronize(sev[sb - 2].e[4]), "hipEventSynchronize");
-    const double t_sb0 = now_ms();
+    if (sb >= 2) hip_check(hipEventSynchronize(sev[sb - 2]->e[1]), "hipEventSynchronize");
+    double t_sb0 = now_ms();
     t_mark = t_sb0;
-    // ---- 2b. enumerate kept triples (threads over jobs; one output vector per job)
-    // per (job, bucket) outputs; the vectors keep their capacity across applies on this host
-    // thread, so enumeration neither allocates nor frees in steady state
-    static thread_local std::vector<std::vector<Triple>> t_jobout;
-    std::vector<std::vector<Triple>>& jobout = t_jobout;
-    const size_t njb = (j1 - j0) * kBuckets;
-    if (jobout.size() < njb) jobout.resize(njb);
-    for (size_t q = 0; q < njb; ++q) jobout[q].clear();
-    parallel_for(j1 - j0, [&](size_t jj, unsigned) {
-      const Job& jb = jobs[j0 + jj];
-      const LevelData& L = lv[jb.lev];
-      const Op& op = *ops[L.fn];
-      const int n = L.n, D = jb.D, mu = jb.mu;
-      const int64_t nb = (int64_t)1 << n;
-      const double c = std::fabs(op.c[mu]);
-      std::vector<double> ae(D + 1), aa(D + 1), rr(D + 1);
-      for (int d = 0; d <= D; ++d) {
-        ae[d] = jb.be->a[d] + jb.be->e[d];
-        aa[d] = jb.be->a[d];
-        rr[d] = jb.be->r[d];
-      }
-      std::vector<Triple>* outv = &jobout[jj * kBuckets];
-      // dz outermost: per target the triples of a term come in (dz, dy, dx) order
-      for (int dz = -D; dz <= D; ++dz)
-        for (int dy = -D; dy <= D; ++dy)
-          for (int dx = -D; dx <= D; ++dx) {
-            int ax = std::abs(dx), ay = std::abs(dy), az = std::abs(dz);
-            double N = (n > 0) ? ae[ax] * ae[ay] * ae[az] - aa[ax] * aa[ay] * aa[az]
-                               : rr[ax] * rr[ay] * rr[az];
-            if (c * N * L.maxb < tau) continue;
-            for (int64_t oi = 0; oi < L.np; ++oi) {
-              int64_t p = L.order[oi];
-              const double eta = c * N * L.bn[p];
-              if (!(eta >= tau)) break;
-              int64_t tx = L.px[p] + dx, ty = L.py[p] + dy, tz = L.pz[p] + dz;
-              if (tx < 0 || ty < 0 || tz < 0 || tx >= nb || ty >= nb || tz >= nb) continue;
-              const int8_t low = (tiers && n > 0 && eta < tau_tier) ? 1 : 0;
-              const uint64_t code = encode(n, tx, ty, tz);
-              outv[target_bucket(n, code)].push_back({((uint64_t)n << 58) | code,
-                                                      (int32_t)(L.ib + p), (int16_t)mu,
-                                                      (int16_t)dx, (int16_t)dy, (int16_t)dz, low});
-            }
-          }
-    });
-    mark("enumerate");
-    // ---- 3. group by target per (function, level, bucket) unit, output tree per function
+    // ---- 2b. target sets of the (function, level) level-units, exact and term-independent:
+    // T = P + d is a target iff max_mu c_mu N_mu(d) ||B_P|| >= tau over the terms whose
+    // displacement range contains d, the same products the enumeration compares
+    std::vector<size_t> lu_j;   // level-unit u = jobs [lu_j[u], lu_j[u + 1])
+    for (size_t j = j0; j < j1; ++j)
+      if (j == j0 || jobs[j].lev != jobs[j - 1].lev) lu_j.push_back(j);
+    lu_j.push_back(j1);
+    const size_t nlu = lu_j.size() - 1;
+    std::vector<std::vector<uint64_t>> lu_codes(nlu);
+    std::vector<double> lu_weight(nlu, 0.0);
+    // Pipelining pays only when planning is long against its fixed costs (a pre-pass, more and
+    // smaller launches): large sub-batches are planned and launched in chunks of level-units,
+    // small ones in one piece (targets then come from the grouping itself).
+    double est = 0.0;
+    for (size_t j = j0; j < j1; ++j) est += (double)lv[jobs[j].lev].np;
+    const bool pipelined = est >= 1.0e5;
+    // enumerate and group the jobs of level-units [ua, ub) (the chunk's units, in order)
     std::vector<Unit> units;
     std::vector<int> unit_lev;
-    for (size_t j = j0; j < j1;) {
-      size_t e = j;
-      while (e < j1 && jobs[e].lev == jobs[j].lev) ++e;
-      for (int b = 0; b < kBuckets; ++b) {
-        bool any = false;
-        for (size_t q = j; q < e && !any; ++q) any = !jobout[(q - j0) * kBuckets + b].empty();
-        if (!any) continue;
-        Unit u;
-        u.fn = lv[jobs[j].lev].fn;
-        u.n = lv[jobs[j].lev].n;
-        u.jb = j - j0;
-        u.je = e - j0;
-        u.bucket = b;
-        units.push_back(std::move(u));
-        unit_lev.push_back(jobs[j].lev);
+    auto enumerate_group = [&](size_t ua, size_t ub) {
+      const size_t ja = lu_j[ua], jz = lu_j[ub];
+      const size_t njb = (jz - ja) * kBuckets;
+      if (jobout.size() < njb) jobout.resize(njb);
+      for (size_t q = 0; q < njb; ++q) jobout[q].clear();
+      parallel_for(jz - ja, [&](size_t jj, unsigned) {
+        const Job& jb = jobs[ja + jj];
+        const LevelData& L = lv[jb.lev];
+        const Op& op = *ops[L.fn];
+        const int n = L.n, D = jb.D, mu = jb.mu;
+        const int64_t nb = (int64_t)1 << n;
+        const double c = std::fabs(op.c[mu]);
+        std::vector<double> ae(D + 1), aa(D + 1), rr(D + 1);
+        for (int d = 0; d <= D; ++d) {
+          ae[d] = jb.be->a[d] + jb.be->e[d];
+          aa[d] = jb.be->a[d];
+          rr[d] = jb.be->r[d];
+        }
+        std::vector<Triple>* outv = &jobout[jj * kBuckets];
+        // dz outermost: per target the triples of a term come in (dz, dy, dx) order
+        for (int dz = -D; dz <= D; ++dz)
+          for (int dy = -D; dy <= D; ++dy)
+            for (int dx = -D; dx <= D; ++dx) {
+              const double cN = screen_cn(c, n, ae.data(), aa.data(), rr.data(), std::abs(dx),
+                                          std::abs(dy), std::abs(dz));
+              if (cN * L.maxb < tau) continue;
+              for (int64_t oi = 0; oi < L.np; ++oi) {
+                int64_t p = L.order[oi];
+                const double eta = cN * L.bn[p];
+                if (!(eta >= tau)) break;
+                int64_t tx = L.px[p] + dx, ty = L.py[p] + dy, tz = L.pz[p] + dz;
+                if (tx < 0 || ty < 0 || tz < 0 || tx >= nb || ty >= nb || tz >= nb) continue;
+                const int8_t low = (tiers && n > 0 && eta < tau_tier) ? 1 : 0;
+                const uint64_t code = encode(n, tx, ty, tz);
+                outv[target_bucket(n, code)].push_back({((uint64_t)n << 58) | code,
+                                                        (int32_t)(L.ib + p), (int16_t)mu,
+                                                        (int16_t)dx, (int16_t)dy, (int16_t)dz, low});
+              }
+            }
+      });
+      mark("enumerate");
+      // group by target per (function, level, bucket) unit, largest units first
+      units.clear();
+      unit_lev.clear();
+      for (size_t u = ua; u < ub; ++u) {
+        const size_t jb0 = lu_j[u], je0 = lu_j[u + 1];
+        for (int b = 0; b < kBuckets; ++b) {
+          bool any = false;
+          for (size_t q = jb0; q < je0 && !any; ++q) any = !jobout[(q - ja) * kBuckets + b].empty();
+          if (!any) continue;
+          Unit un;
+          un.fn = lv[jobs[jb0].lev].fn;
+          un.n = lv[jobs[jb0].lev].n;
+          un.jb = jb0 - ja;
+          un.je = je0 - ja;
+          un.bucket = b;
+          units.push_back(std::move(un));
+          unit_lev.push_back(jobs[jb0].lev);
+        }
       }
-      j = e;
-    }
-    // largest units first on the pool
-    std::vector<size_t> uorder(units.size());
-    std::iota(uorder.begin(), uorder.end(), 0);
-    {
-      std::vector<size_t> usize(units.size(), 0);
-      for (size_t i = 0; i < units.size(); ++i)
-        for (size_t q = units[i].jb; q < units[i].je; ++q)
-          usize[i] += jobout[q * kBuckets + units[i].bucket].size();
-      std::stable_sort(uorder.begin(), uorder.end(),
-                       [&](size_t a, size_t b) { return usize[a] > usize[b]; });
-    }
-    parallel_for(units.size(), [&](size_t ii, unsigned) {
-      const size_t i = uorder[ii];
-      group_unit(units[i], jobout, lv[unit_lev[i]], factored);
+      std::vector<size_t> uorder(units.size());
+      std::iota(uorder.begin(), uorder.end(), 0);
+      {
+        std::vector<size_t> usize(units.size(), 0);
+        for (size_t i = 0; i < units.size(); ++i)
+          for (size_t q = units[i].jb; q < units[i].je; ++q)
+            usize[i] += jobout[q * kBuckets + units[i].bucket].size();
+        std::stable_sort(uorder.begin(), uorder.end(),
+                         [&](size_t a, size_t b) { return usize[a] > usize[b]; });
+      }
+      parallel_for(units.size(), [&](size_t ii, unsigned) {
+        const size_t i = uorder[ii];
+        group_unit(units[i], jobout, lv[unit_lev[i]], factored);
+      });
+      mark("group by target");
+    };
+    if (!pipelined) {
+      enumerate_group(0, nlu);
+      // the targets of each level-unit are the grouped target codes, in bucket order
+      size_t u = 0;
+      for (size_t q = 0; q < units.size(); ++q) {
+        while (lu_j[u + 1] - j0 <= units[q].jb) ++u;
+        for (uint64_t t : units[q].tcodes) lu_codes[u].push_back(t & ((1ULL << 58) - 1));
+      }
+    } else
+    parallel_for(nlu, [&](size_t u, unsigned) {
+      const LevelData& L = lv[jobs[lu_j[u]].lev];
+      const Op& op = *ops[L.fn];
+      const int n = L.n;
+      const int64_t nb = (int64_t)1 << n;
+      int Dm = 0;
+      for (size_t j = lu_j[u]; j < lu_j[u + 1]; ++j) Dm = std::max(Dm, jobs[j].D);
+      const size_t S1 = (size_t)Dm + 1;
+      std::vector<double> cn(S1 * S1 * S1, 0.0);   // [ax][ay][az]
+      for (size_t j = lu_j[u]; j < lu_j[u + 1]; ++j) {
+        const Job& jb = jobs[j];
+        const double c = std::fabs(op.c[jb.mu]);
+        const int D = jb.D;
+        std::vector<double> ae(D + 1), aa(D + 1), rr(D + 1);
+        for (int d = 0; d <= D; ++d) {
+          ae[d] = jb.be->a[d] + jb.be->e[d];
+          aa[d] = jb.be->a[d];
+          rr[d] = jb.be->r[d];
+        }
+        for (int ax = 0; ax <= D; ++ax)
+          for (int ay = 0; ay <= D; ++ay)
+            for (int az = 0; az <= D; ++az) {
+              double& m = cn[((size_t)ax * S1 + ay) * S1 + az];
+              m = std::max(m, screen_cn(c, n, ae.data(), aa.data(), rr.data(), ax, ay, az));
+            }
+      }
+      std::vector<uint64_t> codes;
+      for (int dz = -Dm; dz <= Dm; ++dz)
+        for (int dy = -Dm; dy <= Dm; ++dy)
+          for (int dx = -Dm; dx <= Dm; ++dx) {
+            const double cN = cn[((size_t)std::abs(dx) * S1 + std::abs(dy)) * S1 + std::abs(dz)];
+            if (cN * L.maxb < tau) continue;
+            for (int64_t oi = 0; oi < L.np; ++oi) {
+              const int64_t p = L.order[oi];
+              if (!(cN * L.bn[p] >= tau)) break;
+              const int64_t tx = L.px[p] + dx, ty = L.py[p] + dy, tz = L.pz[p] + dz;
+              if (tx < 0 || ty < 0 || tz < 0 || tx >= nb || ty >= nb || tz >= nb) continue;
+              codes.push_back(encode(n, tx, ty, tz));
+            }
+          }
+      lu_weight[u] = (double)codes.size();
+      radix_sort_unique(codes, 3 * n);
+      lu_codes[u].swap(codes);
     });
-    mark("group by target");
+    mark("target sets");
+    // ---- 3. output trees of the sub-batch's functions
     parallel_for((size_t)(f1 - f0), [&](size_t ii, unsigned) {
       const int i = f0 + (int)ii;
       std::vector<uint64_t> tc;
-      for (const Unit& u : units)
-        if (u.fn == i) tc.insert(tc.end(), u.tcodes.begin(), u.tcodes.end());
+      for (size_t u = 0; u < nlu; ++u) {
+        const LevelData& L = lv[jobs[lu_j[u]].lev];
+        if (L.fn != i) continue;
+        for (uint64_t c : lu_codes[u]) tc.push_back(((uint64_t)L.n << 58) | c);
+      }
       build_output_tree(ctx, plans[i], tc);
     });
     mark("output trees");
-    // ---- 4. item offsets (per unit and target: FP64 items, then BF16 items), filled in
-    // parallel over target chunks directly into the pinned upload buffer
-    size_t n_items = 0, n_low = 0;
-    for (Unit& u : units) {
-      const size_t nt = u.tcodes.size();
-      u.fpre.assign(nt + 1, 0);
-      u.lpre.assign(nt + 1, 0);
-      u.node.assign(nt, -1);
-      for (size_t r = 0; r < nt; ++r) {
-        u.fpre[r + 1] = u.fpre[r] + (u.tmid[r] - u.toff[r]);
-        u.lpre[r + 1] = u.lpre[r] + (u.toff[r + 1] - u.tmid[r]);
-      }
-      u.item_base = n_items;
-      u.low_base = n_low;
-      n_items += (size_t)u.fpre[nt];
-      n_low += (size_t)u.lpre[nt];
-      const double per = f_ns + (u.n > 0 ? f_sub : 0.0);
-      ntriples += (int64_t)u.sorted.size();
-      ntargets += (int64_t)nt;
-      flops += (double)u.sorted.size() * per;
-      flops_low += (double)u.lpre[nt] * per;
-    }
-    if (n_items > (size_t)INT32_MAX || n_low > (size_t)INT32_MAX)
-      fail(MRA_E_UNSUPPORTED, "too many triples for one apply");
-    nlow += (int64_t)n_low;
-    Arena& A1 = ctx->arena[1 + (sb & 1)];
-    A1.begin(ctx);
-    const size_t o_items = A1.reserve(n_items * sizeof(NSItem));
-    const size_t o_litems = A1.reserve(n_low * sizeof(LowItem));
-    NSItem* items_h = A1.host_at<NSItem>(o_items);
-    LowItem* low_h = A1.host_at<LowItem>(o_litems);
-    struct Task {
-      size_t u;
-      int64_t r0, r1;
-    };
-    std::vector<Task> tasks;
-    for (size_t ui = 0; ui < units.size(); ++ui) {
-      const Unit& u = units[ui];
-      const int64_t nt = (int64_t)u.tcodes.size();
-      for (int64_t r = 0; r < nt;) {
-        int64_t e = r, cnt = 0;
-        while (e < nt && cnt < 4096) cnt += u.toff[e + 1] - u.toff[e], ++e;
-        tasks.push_back({ui, r, e});
-        r = e;
-      }
-    }
-    std::vector<double> task_eta(tasks.size(), 0.0);
-    parallel_for(tasks.size(), [&](size_t ti, unsigned) {
-      const Task& t = tasks[ti];
-      Unit& u = units[t.u];
-      const Plan& p = plans[u.fn];
-      task_eta[ti] = fill_items(u, p, lv[unit_lev[t.u]], fu_index[u.fn], t.r0, t.r1, items_h,
-                                low_h, (int64_t)p.op->dR_blocks, (int64_t)p.op->dT_blocks,
-                                tiers ? (int64_t)p.op->dL_blocks : 0, (int64_t)fu_refs.size());
-    });
-    for (double e : task_eta) eta_low += e;   // fixed order
-    mark("work items");
-    // ---- 5. target ranges: level-n slots, split long lists, longest first
-    std::vector<TargetRange> tgt_sub, work, low_work;
-    std::vector<SplitTarget> splits;
-    std::vector<NodeRef> sd_refs;
-    int out_maxlev = 0;
-    const int64_t chunk = std::max<int64_t>(24, ((int64_t)n_items + 1023) / 1024);
-    int32_t npartials = 0, nsub = 0;
+    // ---- 4. sub-batch data: level-n slots of the targets, sum-down entries, pointer tables
     std::vector<std::vector<int32_t>> sub_of_node(f1 - f0);
+    int32_t nsub = 0;
     for (int i = f0; i < f1; ++i) sub_of_node[i - f0].assign((size_t)plans[i].out->nodes(), -1);
-    for (const Unit& u : units) {
-      const int i = u.fn;
-      const Func& o = *plans[i].out;
-      for (size_t r = 0; r < u.tcodes.size(); ++r) {
-        const int32_t node = u.node[r], fc = o.first_child[node];
-        const int32_t lb = (int32_t)(u.low_base + u.lpre[r]), le = (int32_t)(u.low_base + u.lpre[r + 1]);
-        if (le > lb) low_work.push_back({i, node, fc, lb, le, -1, -1});
-        const int32_t b = (int32_t)(u.item_base + u.fpre[r]), e = (int32_t)(u.item_base + u.fpre[r + 1]);
-        if (e == b) continue;
-        int32_t sub = -1;
-        if (u.n > 0) {
-          if (fused) {
-            sub = nsub++;
-            sub_of_node[i - f0][node] = sub;
-          } else {
-            tgt_sub.push_back({i, node, fc, b, e, -1, -1});
-          }
+    if (fused)
+      for (size_t u = 0; u < nlu; ++u) {
+        const LevelData& L = lv[jobs[lu_j[u]].lev];
+        if (L.n == 0) continue;
+        const Func& o = *plans[L.fn].out;
+        for (uint64_t c : lu_codes[u]) {
+          const int64_t node = find_node(o, L.n, c);
+          if (node < 0) fail(MRA_E_INVALID, "internal plan error: target node");
+          sub_of_node[L.fn - f0][node] = nsub++;
         }
-        const int64_t len = e - b;
-        if (len <= chunk) {
-          work.push_back({i, node, fc, b, e, -1, sub});
-          continue;
-        }
-        const int32_t parts = (int32_t)((len + chunk - 1) / chunk);
-        for (int32_t q = 0; q < parts; ++q) {
-          const int32_t qb = b + (int32_t)(q * len / parts), qe = b + (int32_t)((q + 1) * len / parts);
-          work.push_back({i, node, fc, qb, qe, npartials + q, sub});
-        }
-        splits.push_back({i, fc, npartials, parts, sub});
-        npartials += parts;
       }
-    }
+    int out_maxlev = 0;
     for (int i = f0; i < f1; ++i) {
       in_leaves += (int64_t)plans[i].f->leaves.size();
       out_nodes += plans[i].out->nodes();
       out_leaves += (int64_t)plans[i].out->leaves.size();
       out_maxlev = std::max(out_maxlev, plans[i].out->nlev);
     }
-    auto by_len = [](const TargetRange& a, const TargetRange& b) {
-      return (a.end - a.beg) > (b.end - b.beg);
-    };
-    std::stable_sort(work.begin(), work.end(), by_len);
-    std::stable_sort(tgt_sub.begin(), tgt_sub.end(), by_len);
-    // mode products the main kernel executes (threads over chunks of ranges, fixed-order sum)
-    {
-      const double fm = 2.0 * std::pow(2.0 * k, 4), fs = 2.0 * std::pow((double)k, 4);
-      const size_t nck = (work.size() + 255) / 256;
-      std::vector<double> part(nck, 0.0);
-      parallel_for(nck, [&](size_t ci, unsigned) {
-        double acc = 0.0;
-        for (size_t wi = ci * 256; wi < std::min(work.size(), (ci + 1) * 256); ++wi) {
-          const TargetRange& w = work[wi];
-          int64_t prods = w.end - w.beg;
-          if (factored)
-            for (int32_t q = w.beg; q < w.end; ++q) {
-              const bool last = q + 1 == w.end;
-              const NSItem& a = items_h[q];
-              if (last || items_h[q + 1].rz != a.rz || items_h[q + 1].ry != a.ry) ++prods;
-              if (last || items_h[q + 1].rz != a.rz) ++prods;
-            }
-          else
-            prods *= 3;
-          acc += (double)prods * (fm + (w.sub >= 0 ? fs : 0.0));
-        }
-        part[ci] = acc;
-      });
-      for (double v : part) flops_kernel += v;
-    }
-    std::stable_sort(low_work.begin(), low_work.end(), by_len);
-    // sum-down entries, level-major over the sub-batch
+    std::vector<NodeRef> sd_refs;
     std::vector<int64_t> sd_off(out_maxlev + 1, 0);
     for (int n = 0; n < out_maxlev; ++n) {
       for (int i = f0; i < f1; ++i) {
@@ -819,55 +819,219 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       out_len[i] = (int64_t)o.coeff.n;
       max_len = std::max(max_len, o.coeff.n);
     }
-    const size_t o_out = A1.put(out_tab), o_r = A1.put(r_tab), o_t = A1.put(t_tab),
-                 o_c = A1.put(c_tab), o_l = A1.put(l_tab), o_work = A1.put(work),
-                 o_sub = A1.put(tgt_sub), o_spl = A1.put(splits), o_sd = A1.put(sd_refs),
-                 o_lwork = A1.put(low_work), o_olen = A1.put(out_len);
-    const size_t o_part = A1.scratch((size_t)npartials * 9 * K3 * sizeof(double));  // (2k)^3 + k^3
-    const size_t o_subb = A1.scratch((size_t)nsub * K3 * sizeof(double));
-    A1.commit();
-    double* const* out_tab_d = A1.at<double*>(o_out);
-    const double* const* r_tab_d = A1.at<const double*>(o_r);
-    const double* const* t_tab_d = A1.at<const double*>(o_t);
-    const double* const* c_tab_d = A1.at<const double*>(o_c);
-    const uint16_t* const* l_tab_d = A1.at<const uint16_t*>(o_l);
-    const NSItem* items_d = A1.at<NSItem>(o_items);
-    const TargetRange* work_d = A1.at<TargetRange>(o_work);
-    const TargetRange* sub_d = A1.at<TargetRange>(o_sub);
-    const SplitTarget* splits_d = A1.at<SplitTarget>(o_spl);
-    const NodeRef* sd_d = A1.at<NodeRef>(o_sd);
-    const LowItem* low_items_d = A1.at<LowItem>(o_litems);
-    const TargetRange* low_work_d = A1.at<TargetRange>(o_lwork);
-    double* partials_d = A1.scr_at<double>(o_part);
-    double* subbuf_d = A1.scr_at<double>(o_subb);
-    mark("combine + uploads");
+    Arena& AS = ctx->arena[1 + (sb & 1)];
+    AS.begin(ctx);
+    const size_t o_out = AS.put(out_tab), o_r = AS.put(r_tab), o_t = AS.put(t_tab),
+                 o_c = AS.put(c_tab), o_l = AS.put(l_tab), o_sd = AS.put(sd_refs),
+                 o_olen = AS.put(out_len);
+    const size_t o_subb = AS.scratch((size_t)nsub * K3 * sizeof(double));
+    AS.commit();
+    double* const* out_tab_d = AS.at<double*>(o_out);
+    const double* const* r_tab_d = AS.at<const double*>(o_r);
+    const double* const* t_tab_d = AS.at<const double*>(o_t);
+    const double* const* c_tab_d = AS.at<const double*>(o_c);
+    const uint16_t* const* l_tab_d = AS.at<const uint16_t*>(o_l);
+    const NodeRef* sd_d = AS.at<NodeRef>(o_sd);
+    double* subbuf_d = AS.scr_at<double>(o_subb);
+    // outputs start at zero; so do the level-n slots (a target whose triples all run in the
+    // low tier leaves its slot untouched)
+    launch_zero_batch(out_tab_d + f0, AS.at<int64_t>(o_olen) + f0, f1 - f0, max_len, ctx->stream);
+    launch_zero(subbuf_d, (size_t)nsub * K3, ctx->stream);
+    mark("tables and zero fill");
     plan_ms += now_ms() - t_sb0;
 
-    // ---- 6. device work of the sub-batch
-    hipEvent_t* E = sev[sb].e;
-    launch_zero_batch(out_tab_d + f0, A1.at<int64_t>(o_olen) + f0, f1 - f0, max_len, ctx->stream);
-    hip_check(hipEventRecord(E[0], ctx->stream), "event");
-    launch_apply_ns(k, in_tab_d, out_tab_d, items_d, work_d, (int)work.size(), r_tab_d,
-                    t_tab_d, c_tab_d, partials_d, subbuf_d, ctx->stream);
-    hip_check(hipEventRecord(E[1], ctx->stream), "event");
-    launch_reduce_partials(k, partials_d, out_tab_d, subbuf_d, splits_d,
-                           (int)splits.size(), ctx->stream);
-    launch_apply_std(k, in_tab_d, out_tab_d, items_d, sub_d, (int)tgt_sub.size(),
-                     t_tab_d, c_tab_d, -1.0, ctx->stream);
-    hip_check(hipEventRecord(E[2], ctx->stream), "event");
-    if (!low_work.empty()) {
-      any_low = true;
-      launch_apply_low(k, mirror_d, out_tab_d, low_items_d, low_work_d,
-                       (int)low_work.size(), l_tab_d, c_tab_d, ctx->stream);
+    // ---- 5. chunks of level-units: enumerate, group, fill, upload and launch one chunk while
+    // the device runs the previous ones.  A small first chunk starts the device early.
+    std::vector<size_t> cb{0};
+    if (pipelined) {
+      double total = 0.0;
+      for (double w : lu_weight) total += w;
+      const double first = total / 8.0, rest = (total - first) / 3.0;
+      double acc = 0.0, next = first;
+      for (size_t u = 0; u < nlu; ++u) {
+        acc += lu_weight[u];
+        if (acc >= next && u + 1 < nlu && cb.size() < 4) {
+          cb.push_back(u + 1);
+          next = acc + rest;
+        }
+      }
+      cb.push_back(nlu);
+    } else {
+      cb.push_back(nlu);
     }
-    hip_check(hipEventRecord(E[3], ctx->stream), "event");
+    for (size_t ch = 0; ch + 1 < cb.size(); ++ch) {
+      const size_t gc = cev.size();
+      if (gc >= 2) hip_check(hipEventSynchronize(cev[gc - 2]->e[3]), "hipEventSynchronize");
+      const double t_c0 = now_ms();
+      t_mark = t_c0;
+      if (pipelined) enumerate_group(cb[ch], cb[ch + 1]);
+      // item offsets (per unit and target: FP64 items, then BF16 items), filled in parallel
+      // over target chunks directly into the pinned upload buffer
+      size_t n_items = 0, n_low = 0;
+      for (Unit& u : units) {
+        const size_t nt = u.tcodes.size();
+        u.fpre.assign(nt + 1, 0);
+        u.lpre.assign(nt + 1, 0);
+        u.node.assign(nt, -1);
+        for (size_t r = 0; r < nt; ++r) {
+          u.fpre[r + 1] = u.fpre[r] + (u.tmid[r] - u.toff[r]);
+          u.lpre[r + 1] = u.lpre[r] + (u.toff[r + 1] - u.tmid[r]);
+        }
+        u.item_base = n_items;
+        u.low_base = n_low;
+        n_items += (size_t)u.fpre[nt];
+        n_low += (size_t)u.lpre[nt];
+        const double per = f_ns + (u.n > 0 ? f_sub : 0.0);
+        ntriples += (int64_t)u.sorted.size();
+        ntargets += (int64_t)nt;
+        flops += (double)u.sorted.size() * per;
+        flops_low += (double)u.lpre[nt] * per;
+      }
+      if (n_items > (size_t)INT32_MAX || n_low > (size_t)INT32_MAX)
+        fail(MRA_E_UNSUPPORTED, "too many triples for one apply");
+      nlow += (int64_t)n_low;
+      Arena& A1 = ctx->arena[3 + (gc & 1)];
+      A1.begin(ctx);
+      const size_t o_items = A1.reserve(n_items * sizeof(NSItem));
+      const size_t o_litems = A1.reserve(n_low * sizeof(LowItem));
+      NSItem* items_h = A1.host_at<NSItem>(o_items);
+      LowItem* low_h = A1.host_at<LowItem>(o_litems);
+      struct Task {
+        size_t u;
+        int64_t r0, r1;
+      };
+      std::vector<Task> tasks;
+      for (size_t ui = 0; ui < units.size(); ++ui) {
+        const Unit& u = units[ui];
+        const int64_t nt = (int64_t)u.tcodes.size();
+        for (int64_t r = 0; r < nt;) {
+          int64_t e = r, cnt = 0;
+          while (e < nt && cnt < 4096) cnt += u.toff[e + 1] - u.toff[e], ++e;
+          tasks.push_back({ui, r, e});
+          r = e;
+        }
+      }
+      std::vector<double> task_eta(tasks.size(), 0.0);
+      parallel_for(tasks.size(), [&](size_t ti, unsigned) {
+        const Task& t = tasks[ti];
+        Unit& u = units[t.u];
+        const Plan& p = plans[u.fn];
+        task_eta[ti] = fill_items(u, p, lv[unit_lev[t.u]], fu_index[u.fn], t.r0, t.r1, items_h,
+                                  low_h, (int64_t)p.op->dR_blocks, (int64_t)p.op->dT_blocks,
+                                  tiers ? (int64_t)p.op->dL_blocks : 0, (int64_t)fu_refs.size());
+      });
+      for (double e : task_eta) eta_low += e;   // fixed order
+      mark("work items");
+      // target ranges: split long lists, longest first
+      std::vector<TargetRange> tgt_sub, work, low_work;
+      std::vector<SplitTarget> splits;
+      const int64_t chunk = std::max<int64_t>(24, ((int64_t)n_items + 511) / 512);
+      int32_t npartials = 0;
+      for (const Unit& u : units) {
+        const int i = u.fn;
+        const Func& o = *plans[i].out;
+        for (size_t r = 0; r < u.tcodes.size(); ++r) {
+          const int32_t node = u.node[r], fc = o.first_child[node];
+          const int32_t lb = (int32_t)(u.low_base + u.lpre[r]), le = (int32_t)(u.low_base + u.lpre[r + 1]);
+          if (le > lb) low_work.push_back({i, node, fc, lb, le, -1, -1});
+          const int32_t b = (int32_t)(u.item_base + u.fpre[r]), e = (int32_t)(u.item_base + u.fpre[r + 1]);
+          if (e == b) continue;
+          int32_t sub = -1;
+          if (u.n > 0) {
+            if (fused) {
+              sub = sub_of_node[i - f0][node];
+              if (sub < 0) fail(MRA_E_INVALID, "internal plan error: target outside the target set");
+            } else {
+              tgt_sub.push_back({i, node, fc, b, e, -1, -1});
+            }
+          }
+          const int64_t len = e - b;
+          if (len <= chunk) {
+            work.push_back({i, node, fc, b, e, -1, sub});
+            continue;
+          }
+          const int32_t parts = (int32_t)((len + chunk - 1) / chunk);
+          for (int32_t q = 0; q < parts; ++q) {
+            const int32_t qb = b + (int32_t)(q * len / parts), qe = b + (int32_t)((q + 1) * len / parts);
+            work.push_back({i, node, fc, qb, qe, npartials + q, sub});
+          }
+          splits.push_back({i, fc, npartials, parts, sub});
+          npartials += parts;
+        }
+      }
+      auto by_len = [](const TargetRange& a, const TargetRange& b) {
+        return (a.end - a.beg) > (b.end - b.beg);
+      };
+      std::stable_sort(work.begin(), work.end(), by_len);
+      std::stable_sort(tgt_sub.begin(), tgt_sub.end(), by_len);
+      std::stable_sort(low_work.begin(), low_work.end(), by_len);
+      // mode products the main kernel executes (threads over chunks of ranges, fixed order)
+      {
+        const double fm = 2.0 * std::pow(2.0 * k, 4), fs = 2.0 * std::pow((double)k, 4);
+        const size_t nck = (work.size() + 255) / 256;
+        std::vector<double> part(nck, 0.0);
+        parallel_for(nck, [&](size_t ci, unsigned) {
+          double acc = 0.0;
+          for (size_t wi = ci * 256; wi < std::min(work.size(), (ci + 1) * 256); ++wi) {
+            const TargetRange& w = work[wi];
+            int64_t prods = w.end - w.beg;
+            if (factored)
+              for (int32_t q = w.beg; q < w.end; ++q) {
+                const bool last = q + 1 == w.end;
+                const NSItem& a = items_h[q];
+                if (last || items_h[q + 1].rz != a.rz || items_h[q + 1].ry != a.ry) ++prods;
+                if (last || items_h[q + 1].rz != a.rz) ++prods;
+              }
+            else
+              prods *= 3;
+            acc += (double)prods * (fm + (w.sub >= 0 ? fs : 0.0));
+          }
+          part[ci] = acc;
+        });
+        for (double v : part) flops_kernel += v;
+      }
+      const size_t o_work = A1.put(work), o_sub = A1.put(tgt_sub), o_spl = A1.put(splits),
+                   o_lwork = A1.put(low_work);
+      const size_t o_part = A1.scratch((size_t)npartials * 9 * K3 * sizeof(double));  // (2k)^3 + k^3
+      A1.commit();
+      const NSItem* items_d = A1.at<NSItem>(o_items);
+      const TargetRange* work_d = A1.at<TargetRange>(o_work);
+      const TargetRange* sub_d = A1.at<TargetRange>(o_sub);
+      const SplitTarget* splits_d = A1.at<SplitTarget>(o_spl);
+      const LowItem* low_items_d = A1.at<LowItem>(o_litems);
+      const TargetRange* low_work_d = A1.at<TargetRange>(o_lwork);
+      double* partials_d = A1.scr_at<double>(o_part);
+      mark("ranges + uploads");
+      plan_ms += now_ms() - t_c0;
+      // device work of the chunk
+      cev.push_back(std::make_unique<Events>());
+      hipEvent_t* E = cev.back()->e;
+      hip_check(hipEventRecord(E[0], ctx->stream), "event");
+      launch_apply_ns(k, in_tab_d, out_tab_d, items_d, work_d, (int)work.size(), r_tab_d,
+                      t_tab_d, c_tab_d, partials_d, subbuf_d, ctx->stream);
+      hip_check(hipEventRecord(E[1], ctx->stream), "event");
+      launch_reduce_partials(k, partials_d, out_tab_d, subbuf_d, splits_d,
+                             (int)splits.size(), ctx->stream);
+      launch_apply_std(k, in_tab_d, out_tab_d, items_d, sub_d, (int)tgt_sub.size(),
+                       t_tab_d, c_tab_d, -1.0, ctx->stream);
+      hip_check(hipEventRecord(E[2], ctx->stream), "event");
+      if (!low_work.empty()) {
+        any_low = true;
+        launch_apply_low(k, mirror_d, out_tab_d, low_items_d, low_work_d,
+                         (int)low_work.size(), l_tab_d, c_tab_d, ctx->stream);
+      }
+      hip_check(hipEventRecord(E[3], ctx->stream), "event");
+    }
+    // ---- 6. sum-down of the sub-batch
+    sev.push_back(std::make_unique<Events>());
+    hipEvent_t* ES = sev.back()->e;
+    hip_check(hipEventRecord(ES[0], ctx->stream), "event");
     for (int n = 0; n < out_maxlev; ++n) {
       int64_t b = sd_off[n], e = sd_off[n + 1];
       if (e > b)
-        launch_sum_down(k, out_tab_d, sd_d + b, (int)(e - b), subbuf_d, h0p, h1p,
-                        ctx->stream);
+        launch_sum_down(k, out_tab_d, sd_d + b, (int)(e - b), subbuf_d, h0p, h1p, ctx->stream);
     }
-    hip_check(hipEventRecord(E[4], ctx->stream), "event");
+    hip_check(hipEventRecord(ES[1], ctx->stream), "event");
   }
   ctx->sync();
   for (int i = 0; i < nf; ++i) plans[i].out->interior_valid = false;
@@ -875,15 +1039,18 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   float ms_f = 0;
   double ms_a = 0, ms_s = 0, ms_main = 0, ms_low = 0;
   hip_check(hipEventElapsedTime(&ms_f, ctx->ev[0], ctx->ev[1]), "elapsed");
-  for (const Events& se : sev) {
-    float a = 0, m = 0, l = 0, d = 0;
-    hip_check(hipEventElapsedTime(&a, se.e[0], se.e[3]), "elapsed");
-    hip_check(hipEventElapsedTime(&m, se.e[0], se.e[1]), "elapsed");
-    hip_check(hipEventElapsedTime(&l, se.e[2], se.e[3]), "elapsed");
-    hip_check(hipEventElapsedTime(&d, se.e[3], se.e[4]), "elapsed");
+  for (const auto& ce : cev) {
+    float a = 0, m = 0, l = 0;
+    hip_check(hipEventElapsedTime(&a, ce->e[0], ce->e[3]), "elapsed");
+    hip_check(hipEventElapsedTime(&m, ce->e[0], ce->e[1]), "elapsed");
+    hip_check(hipEventElapsedTime(&l, ce->e[2], ce->e[3]), "elapsed");
     ms_a += a;
     ms_main += m;
     ms_low += l;
+  }
+  for (const auto& se : sev) {
+    float d = 0;
+    hip_check(hipEventElapsedTime(&d, se->e[0], se->e[1]), "elapsed");
     ms_s += d;
   }
   mra_apply_stats& st = ctx->stats;

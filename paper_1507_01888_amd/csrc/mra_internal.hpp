@@ -146,7 +146,7 @@ struct Ctx {
   std::string err;
   mra_apply_stats stats{};
   hipEvent_t ev[8]{};
-  Arena arena[3];                      // filter-up phase, plans of alternate sub-batches
+  Arena arena[5];                      // filter-up; tables of alternate sub-batches; alternate chunks
   double* red_part = nullptr;          // 2048 partial sums of the leaf reductions
 
   double width() const { return hi - lo; }
