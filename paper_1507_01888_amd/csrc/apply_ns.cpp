@@ -619,7 +619,9 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
     // small ones in one piece (targets then come from the grouping itself).
     double est = 0.0;
     for (size_t j = j0; j < j1; ++j) est += (double)lv[jobs[j].lev].np;
-    const bool pipelined = est >= 1.0e5;
+    const char* pm = std::getenv("MRA_PIPELINE_MIN");   // in sources x terms; tests lower it
+    const double pipe_min = pm ? std::atof(pm) : 1.0e5;
+    const bool pipelined = est >= pipe_min;
     // enumerate and group the jobs of level-units [ua, ub) (the chunk's units, in order)
     std::vector<Unit> units;
     std::vector<int> unit_lev;

@@ -243,6 +243,45 @@ def test_batched_bsh_matches_single_and_oracle(M):
     assert err <= TOL
 
 
+def test_pipelined_batch_plan(M, monkeypatch):
+    """The chunked plan (target sets from the screening pre-pass, level-units planned and
+    launched in chunks) forced on the small batched Helmholtz case: the same triples and
+    trees as the one-piece plan, values equal up to the summation order of split lists, and
+    parity with the oracle."""
+    _say("case: batched bsh, 4 functions, chunked plan forced")
+    ctx = M.Context(0, W.CELL)
+    funcs, ops, params = [], [], []
+    for i in range(4):
+        c, a, x, mu = W.bsh_inputs(i)
+        funcs.append(ctx.project(c, a, x, 10, 1e-4))
+        ops.append(ctx.op_bsh(10, mu, 1e-5, 1e-8))
+        params.append((c, a, x, mu))
+    monkeypatch.setenv("MRA_PIPELINE_MIN", "1e30")
+    one = ctx.apply_batch(ops, funcs, tau_drop=1e-8)
+    st1 = ctx.last_stats()
+    monkeypatch.setenv("MRA_PIPELINE_MIN", "0")
+    piped = ctx.apply_batch(ops, funcs, tau_drop=1e-8)
+    st2 = ctx.last_stats()
+    monkeypatch.delenv("MRA_PIPELINE_MIN")
+    assert st1["triples"] == st2["triples"] and st1["out_nodes"] == st2["out_nodes"]
+    worst = 0.0
+    for i in range(4):
+        a, b = _as_dict(piped[i]), _as_dict(one[i])
+        assert set(a) == set(b)
+        worst = max(worst, _rel_l2(a, b, b))
+    _say("chunked vs one-piece plan: worst rel L2 %.3e over 4 functions" % worst)
+    assert worst <= 1e-14
+    c, a, x, mu = params[1]
+    fo = project_adaptive(GaussianSum(c, a, x), 10, 1e-4, W.CELL, 2, 20)
+    cc, tt = bsh_fit(mu, 1e-5, 1e-8, cell_r_hi(*W.CELL))
+    ref, _ = apply_nonstandard(fo, SeparatedOperator(cc, tt), 1e-8)
+    got = _as_dict(piped[1])
+    assert set(got) == set(ref.leaves)
+    err = _rel_l2(got, ref.leaves, ref.leaves)
+    _say("chunked plan, function 1 rel L2 vs oracle", err)
+    assert err <= TOL
+
+
 def test_coulomb_k12_reduced_full_parity(M):
     """k=12 non-standard apply (the mixed-precision workload's order) in FP64, every leaf."""
     _say("case: coulomb k=12 reduced (1 Gaussian, thresh 1e-6)")
