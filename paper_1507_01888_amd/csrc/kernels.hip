@@ -56,6 +56,7 @@ __global__ void zero_batch_kernel(double* const* __restrict__ tab, const int64_t
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // FP64 -> FP32 -> BF16, both steps rounding to nearest even (bits of the BF16 value).
 __device__ inline uint32_t bf16_bits_dev(float v) {
@@ -734,6 +735,33 @@ __global__ __launch_bounds__(256) void apply_ns_mfma_kernel(
   }
 }
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS accesses and meets the
+// other waves, but, unlike __syncthreads, not for global loads still in flight (those
+// stage the next triple's blocks and are waited for where they are stored to LDS).  The
+// memory clobber keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Scheduling pattern for a group of matrix products and the memory instructions issued
+// beside them (LDS reads of the next group's operands, global loads and LDS stores of the
+// next triple's blocks): rounds of PM products followed by at most one instruction of each
+// kind (NR LDS reads, NV global loads, NW LDS stores in all), then the remaining products.
+// The memory instructions trickle out behind the products instead of holding up the
+// in-order wave in one burst.
+template <int NR, int NV, int NW, int PM>
+__device__ __forceinline__ void interleave_mem() {
+  constexpr int NI = NR > NV ? (NR > NW ? NR : NW) : (NV > NW ? NV : NW);
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, PM, 0);              // matrix products
+    if (i < NR) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+    if (i < NV) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global load
+    if (i < NW) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // LDS store
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, 64, 0);
+}
+
 template <int B>
 struct BufTag {
   static constexpr int value = B;
@@ -749,10 +777,13 @@ struct BufTag {
 // s_P is factored the same way by apply_ns_fac_sub_kernel.  The lane mapping of each step
 // is that of apply_ns_mfma_kernel (block index = z inside a z-quad for steps 1 and 2).
 // The children block of the next triple and its operator blocks are copied into the other
-// half of two LDS buffers by direct global->LDS loads (16 bytes per lane, no registers)
-// while the current triple runs; the source block is stored row-major [x][y][z], whose
-// row stride 2k = 20 (= 4 mod 16) keeps the step-1 reads bank-conflict free.  The buffer a
-// triple has finished with holds the exchange tensors of step 3.
+// half of two LDS buffers (16-byte granules through registers) while the current triple
+// runs; the source block is stored row-major [x][y][z], whose row stride 2k = 20 (= 4 mod
+// 16) keeps the step-1 reads bank-conflict free.  The buffer a triple has finished with
+// holds the exchange tensors of step 3.  One wave per SIMD hides no latency by switching
+// waves, so each step is software-pipelined by hand (operands of the next group read into
+// a register double buffer) and its memory instructions are interleaved with the matrix
+// products by scheduling-group hints.
 template <int K>
 __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
@@ -763,15 +794,19 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
   constexpr int N = 2 * K, Q = N / 4, N2 = N * N, N3 = N * N * N, K2 = K * K, K3 = K * K * K;
   static_assert(Q == 5, "row stride 2k = 20 and the wave split below are for k = 10");
   constexpr int EXTRA = (Q - 4) * Q, EPW = (EXTRA + 3) / 4;   // (z-quad 4, a-quad) units
+  static_assert(EXTRA == Q && EPW == 2, "the z-quad-4 units are a-quads 3 - wave and 7 - wave");
   constexpr int P3 = Q * Q, P3PW = (P3 + 3) / 4;              // step-3 (a-quad, b-quad) pairs
-  // direct-load geometry, in 16-byte granules (two doubles)
-  constexpr int XG = N3 / 2, XI = (XG + 63) / 64, XQ = (XI + 3) / 4, XPAD = 128 * XI;
+  // staging geometry, in 16-byte granules (two doubles)
+  // (every wave moves XQ + OQ granule rows per triple; the buffers are padded so that the
+  // rows past the end of a block are written to padding instead of being branched around)
+  constexpr int XG = N3 / 2, XI = (XG + 63) / 64, XQ = (XI + 3) / 4, XPAD = 128 * 4 * XQ;
   constexpr int OPS = 3 * N2, OG = OPS / 2, OI = (OG + 63) / 64, OQ = (OI + 3) / 4,
-                OPAD = 128 * OI;
+                OPAD = 128 * 4 * OQ;
+  static_assert(XQ == 16 && OQ == 3, "the staging schedule below moves 4 x 4 + 3 rows");
   static_assert(N2 % 2 == 0 && K2 % 2 == 0 && K % 2 == 0, "granules never straddle rows");
   static_assert(64 * Q * Q * Q <= XPAD, "the exchange tensor fits in a source buffer");
   // the two halves of each double buffer are separate objects, so that the compiler can
-  // tell reads of one from the direct loads into the other
+  // tell reads of one from the stores into the other
   __shared__ __attribute__((aligned(16))) double Xs0[XPAD];
   __shared__ __attribute__((aligned(16))) double Xs1[XPAD];
   __shared__ __attribute__((aligned(16))) double Os0[OPAD];
@@ -803,27 +838,36 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     osel[q] = g / (N2 / 2);
     ooff[q] = 2 * (g - osel[q] * (N2 / 2));
   }
-  auto dma_source = [&](int src_fc, double* dst) {
-    const MRA_GLOBAL double* base = in + (size_t)src_fc * K3;
+  // The next triple's blocks travel global -> registers -> LDS in five parts (four of the
+  // source block, one of the operators): fetch_part() issues a part's loads and
+  // commit_part() stores it into the free buffer halves.  Both are spread over the
+  // x-quad groups of step 1, interleaved with the matrix products, because a burst of
+  // memory instructions stalls the in-order wave until the memory pipeline takes them.
+  // (Direct global->LDS loads would count against the LDS wait counter as well, and every
+  // LDS read of the triple would then have to wait for them to land.)
+  f64x2 sx[XQ], so[OQ];
+  auto fetch_part = [&](const NSItem nx, const int part) {
+    if (part < 4) {
+      const MRA_GLOBAL double* base = in + (size_t)nx.src_fc * K3;
 #pragma unroll
-    for (int q = 0; q < XQ; ++q) {
-      const int j = wave + 4 * q;
-      if (j < XI)
-        __builtin_amdgcn_global_load_lds((const MRA_GLOBAL void*)(base + xoff[q]),
-                                         (MRA_LDS void*)(dst + 128 * j), 16, 0, 0);
-    }
-  };
-  auto dma_ops = [&](const NSItem nx, double* dst) {
+      for (int q = 4 * part; q < 4 * part + 4; ++q) sx[q] = *(const MRA_GLOBAL f64x2*)(base + xoff[q]);
+    } else {
 #pragma unroll
-    for (int q = 0; q < OQ; ++q) {
-      const int j = wave + 4 * q;
-      if (j < OI) {
+      for (int q = 0; q < OQ; ++q) {
         const int sel = osel[q];
         const int blk = sel == 0 ? nx.rx : sel == 1 ? nx.ry : nx.rz;
-        const MRA_GLOBAL double* src = dR + (size_t)blk * N2 + ooff[q];
-        __builtin_amdgcn_global_load_lds((const MRA_GLOBAL void*)src,
-                                         (MRA_LDS void*)(dst + 128 * j), 16, 0, 0);
+        so[q] = *(const MRA_GLOBAL f64x2*)(dR + (size_t)blk * N2 + ooff[q]);
       }
+    }
+  };
+  auto commit_part = [&](const int part, double* dst, double* dop) {
+    if (part < 4) {
+#pragma unroll
+      for (int q = 4 * part; q < 4 * part + 4; ++q)
+        *(f64x2*)(dst + 128 * (wave + 4 * q) + 2 * lane) = sx[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < OQ; ++q) *(f64x2*)(dop + 128 * (wave + 4 * q) + 2 * lane) = so[q];
     }
   };
   double d1[Q][Q], d2[Q][Q], d1e[EPW][Q], d2e[EPW][Q], acc[P3PW][Q];
@@ -846,12 +890,15 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
   if (tr.beg < tr.end) {
     cur = items[tr.beg];
     c_cur = dc[cur.mu];
-    dma_source(cur.src_fc, Xs0);
-    dma_ops(cur, Os0);
+#pragma unroll
+    for (int part = 0; part < 5; ++part) {
+      fetch_part(cur, part);
+      commit_part(part, Xs0, Os0);
+    }
     nxt = items[min(tr.beg + 1, tr.end - 1)];
   }
   // one triple; BUF is a compile-time constant so that the compiler can tell the reads of
-  // this triple's buffer halves from the direct loads into the other halves
+  // this triple's buffer halves from the stores into the other halves
   auto triple = [&](const int it, auto buf_tag) {
     constexpr int buf = decltype(buf_tag)::value;
     double* const Xc = buf == 0 ? Xs0 : Xs1;   // this triple's halves
@@ -860,14 +907,11 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     double* const On = buf == 0 ? Os1 : Os0;
     const NSItem item = cur;
     const bool more = it + 1 < tr.end;
-    const NSItem nn = items[min(it + 2, tr.end - 1)];   // uniform address: scalar loads
-    // this wave's direct loads of triple it are complete; after the barrier all of them
-    // are, and every wave is done with triple it - 1 (the other buffer halves are free)
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    // after the barrier the blocks of triple it are in LDS and every wave is done with
+    // triple it - 1 (the other buffer halves are free)
     __syncthreads();
+    const NSItem nn = items[min(it + 2, tr.end - 1)];   // uniform address: scalar loads
     if (more) {
-      dma_source(nxt.src_fc, Xn);
-      dma_ops(nxt, On);
       c_pre = dc[nxt.mu];
     }
     const bool dy_end = !more || nxt.rz != item.rz || nxt.ry != item.ry;
@@ -877,57 +921,83 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     const double* RXs = Oc;
     const double* RYs = Oc + N2;
     const double* RZs = Oc + 2 * N2;
-    // ---- step 1: the main z-quad of this wave (all a-quads), then the z-quad-4 units
+    // One wave per SIMD hides no latency by switching waves, so every step is software-
+    // pipelined by hand: the LDS operands of group g + 1 are read into the other half of a
+    // register double buffer before the matrix products of group g, and scheduling
+    // barriers keep the compiler from sinking those reads next to their uses.
+    // ---- step 1, per x-quad xs: the main z-quad of this wave (all a-quads) and the
+    // z-quad-4 units.  Every wave runs EPW = 2 of those units, so that the block has no
+    // wave-dependent branch; a wave with one real unit repeats it into an accumulator that
+    // is never stored (it would otherwise wait for the busiest wave anyway).
     {
       const int zq = wave;
+      const int ate[EPW] = {min(3 - wave, EXTRA - 1), min(7 - wave, EXTRA - 1)};
+      double opA[2][Q], opE[2][Q], opR[2][Q], opB[2][EPW];
+      auto load1 = [&](const int xs, const int b) {
+        const double* Rr = RXs + (4 * xs + lk) * N + li;
+        const double* Xr = X + ((4 * xs + lk) * N + li) * N + lb;
+#pragma unroll
+        for (int at = 0; at < Q; ++at) opR[b][at] = Rr[4 * at];
+#pragma unroll
+        for (int yt = 0; yt < Q; ++yt) opA[b][yt] = Xr[4 * yt * N + 4 * zq];
+#pragma unroll
+        for (int yt = 0; yt < Q; ++yt) opE[b][yt] = Xr[4 * yt * N + 16];
+#pragma unroll
+        for (int e = 0; e < EPW; ++e) opB[b][e] = Rr[4 * ate[e]];
+      };
+      load1(0, 0);
 #pragma unroll
       for (int xs = 0; xs < Q; ++xs) {
-        double rx[Q];
+        const int b = xs & 1;
+        if (xs + 1 < Q) load1(xs + 1, b ^ 1);
+        // the next triple's blocks (for the last triple of the list, nxt repeats the
+        // current item: harmless loads into the free halves)
+        if (xs == 0) { fetch_part(nxt, 0); fetch_part(nxt, 1); }
+        if (xs == 1) { fetch_part(nxt, 2); fetch_part(nxt, 3); }
+        if (xs == 2) { fetch_part(nxt, 4); commit_part(0, Xn, On); }
+        if (xs == 3) { commit_part(1, Xn, On); commit_part(2, Xn, On); }
+        if (xs == 4) { commit_part(3, Xn, On); commit_part(4, Xn, On); }
 #pragma unroll
-        for (int at = 0; at < Q; ++at) rx[at] = RXs[(4 * xs + lk) * N + 4 * at + li];
-#pragma unroll
-        for (int yt = 0; yt < Q; ++yt) {
-          const double a = X[((4 * xs + lk) * N + 4 * yt + li) * N + 4 * zq + lb];
+        for (int yt = 0; yt < Q; ++yt)
 #pragma unroll
           for (int at = 0; at < Q; ++at)
-            d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rx[at], d1[at][yt], 0, 0, 0);
-        }
-      }
-    }
+            d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(opA[b][yt], opR[b][at], d1[at][yt], 0, 0, 0);
 #pragma unroll
-    for (int e = 0; e < EPW; ++e) {
-      const int p = (3 - wave) + 4 * e;
-      if (p < EXTRA) {
-        const int zq = 4 + p / Q, at = p % Q;
+        for (int e = 0; e < EPW; ++e)
 #pragma unroll
-        for (int xs = 0; xs < Q; ++xs) {
-          const double b = RXs[(4 * xs + lk) * N + 4 * at + li];
-#pragma unroll
-          for (int yt = 0; yt < Q; ++yt) {
-            const double a = X[((4 * xs + lk) * N + 4 * yt + li) * N + 4 * zq + lb];
-            d1e[e][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, d1e[e][yt], 0, 0, 0);
-          }
-        }
+          for (int yt = 0; yt < Q; ++yt)
+            d1e[e][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(opE[b][yt], opB[b][e], d1e[e][yt], 0, 0, 0);
+        if (xs == 0 || xs == 1) interleave_mem<11, 8, 0, 2>();
+        if (xs == 2) interleave_mem<11, 3, 4, 2>();
+        if (xs == 3) interleave_mem<11, 0, 8, 2>();
+        if (xs == 4) interleave_mem<0, 0, 7, 3>();
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     // ---- step 2 at the end of a (mu, dz, dy) group
     if (dy_end) {
+      double ry[2][Q];
+      auto load2 = [&](const int ys, const int b) {
+#pragma unroll
+        for (int bt = 0; bt < Q; ++bt) ry[b][bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+      };
+      load2(0, 0);
 #pragma unroll
       for (int ys = 0; ys < Q; ++ys) {
-        double ry[Q];
-#pragma unroll
-        for (int bt = 0; bt < Q; ++bt) ry[bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+        const int b = ys & 1;
+        if (ys + 1 < Q) load2(ys + 1, b ^ 1);
 #pragma unroll
         for (int at = 0; at < Q; ++at)
 #pragma unroll
           for (int bt = 0; bt < Q; ++bt)
-            d2[at][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], ry[bt], d2[at][bt], 0, 0, 0);
+            d2[at][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], ry[b][bt], d2[at][bt], 0, 0, 0);
 #pragma unroll
         for (int e = 0; e < EPW; ++e)
-          if ((3 - wave) + 4 * e < EXTRA)
 #pragma unroll
-            for (int bt = 0; bt < Q; ++bt)
-              d2e[e][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1e[e][ys], ry[bt], d2e[e][bt], 0, 0, 0);
+          for (int bt = 0; bt < Q; ++bt)
+            d2e[e][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1e[e][ys], ry[b][bt], d2e[e][bt], 0, 0, 0);
+        if (ys + 1 < Q) interleave_mem<5, 0, 0, 4>();
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int i = 0; i < Q; ++i)
@@ -941,7 +1011,12 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     // ---- step 3 at the end of a (mu, dz) group, through this triple's source buffer
     if (dz_end) {
       double* Zs = Xc;
-      __syncthreads();   // every wave is done reading the source block
+      double rz[Q][Q];   // c_mu R_z^T fragments, loaded while the waves meet
+#pragma unroll
+      for (int zs = 0; zs < Q; ++zs)
+#pragma unroll
+        for (int ct = 0; ct < Q; ++ct) rz[zs][ct] = cmu * RZs[(4 * zs + lk) * N + 4 * ct + li];
+      lds_barrier();   // every wave is done reading the source block
       {
         const int zq = wave;
 #pragma unroll
@@ -964,27 +1039,27 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
           }
         }
       }
-      __syncthreads();
-      {
-        double rz[Q][Q];
+      lds_barrier();
+      // as in step 1, a wave with fewer real pairs repeats its last one (never stored)
+      double za[2][Q];
+      auto load3 = [&](const int e, const int b) {
+        const int p = min((3 - wave) + 4 * e, P3 - 1);
+        const int at3 = p / Q, bt3 = p % Q;
+#pragma unroll
+        for (int zs = 0; zs < Q; ++zs) za[b][zs] = Zs[sk_off<Q>(4 * at3 + lb, 4 * bt3 + li, 4 * zs + lk)];
+      };
+      load3(0, 0);
+#pragma unroll
+      for (int e = 0; e < P3PW; ++e) {
+        const int b = e & 1;
+        if (e + 1 < P3PW) load3(e + 1, b ^ 1);
 #pragma unroll
         for (int zs = 0; zs < Q; ++zs)
 #pragma unroll
-          for (int ct = 0; ct < Q; ++ct) rz[zs][ct] = cmu * RZs[(4 * zs + lk) * N + 4 * ct + li];
-#pragma unroll
-        for (int e = 0; e < P3PW; ++e) {
-          const int p = (3 - wave) + 4 * e;
-          if (p < P3) {
-            const int at3 = p / Q, bt3 = p % Q;
-#pragma unroll
-            for (int zs = 0; zs < Q; ++zs) {
-              const double a = Zs[sk_off<Q>(4 * at3 + lb, 4 * bt3 + li, 4 * zs + lk)];
-#pragma unroll
-              for (int ct = 0; ct < Q; ++ct)
-                acc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, rz[zs][ct], acc[e][ct], 0, 0, 0);
-            }
-          }
-        }
+          for (int ct = 0; ct < Q; ++ct)
+            acc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(za[b][zs], rz[zs][ct], acc[e][ct], 0, 0, 0);
+        if (e + 1 < P3PW) interleave_mem<5, 0, 0, 3>();
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     c_cur = c_pre;
