@@ -80,6 +80,47 @@ inline double screen_cn(double c, int n, const double* ae, const double* aa, con
   return c * N;
 }
 
+// Exact pruning of a job's displacement cube.  Every factor of screen_cn's products is
+// non-negative and rounding is monotone, so raising one factor can only raise the computed
+// c N (and c N maxb), while dropping the subtracted term of the n > 0 form can only raise
+// it too.  With S[d] = max over |delta| >= d of the 1D factor (a + e, or r at n = 0), the
+// product with S[d] in place of an axis' factor bounds every displacement at distance >= d
+// along that axis; a line of the cube ends where that bound falls below tau.  The visited
+// candidates keep their order, and every candidate that passes the test is visited.
+struct ScreenBound {
+  double c = 0.0, maxb = 0.0, tau = 0.0;
+  const double* f = nullptr;   // 1D factors, 0..D
+  std::vector<double> S;       // suffix maxima, 0..D
+  int D = 0;
+  ScreenBound(double c_, double maxb_, double tau_, const double* f_, int D_)
+      : c(c_), maxb(maxb_), tau(tau_), f(f_), S(D_ + 2, 0.0), D(D_) {
+    for (int d = D; d >= 0; --d) S[d] = std::max(f[d], S[d + 1]);
+  }
+  // the products in screen_cn's order ((x y) z); passes iff the bound reaches tau
+  bool pass(double fx, double fy, double fz) const {
+#pragma clang fp contract(off)
+    return c * (fx * fy * fz) * maxb >= tau;
+  }
+  // largest |dz| whose plane can hold a kept candidate (-1: none)
+  int rz() const {
+    int r = D;
+    while (r >= 0 && !pass(S[0], S[0], S[r])) --r;
+    return r;
+  }
+  // largest |dy| in plane |dz| = az
+  int ry(int az) const {
+    int r = D;
+    while (r >= 0 && !pass(S[0], S[r], f[az])) --r;
+    return r;
+  }
+  // largest |dx| on line (|dy|, |dz|) = (ay, az)
+  int rx(int ay, int az) const {
+    int r = D;
+    while (r >= 0 && !pass(S[r], f[ay], f[az])) --r;
+    return r;
+  }
+};
+
 // Sorts codes below 2^bits ascending and removes duplicates (LSD radix, 11-bit digits).
 void radix_sort_unique(std::vector<uint64_t>& v, int bits) {
   if (v.size() > 1 && bits > 0) {
@@ -266,20 +307,26 @@ void group_unit(Unit& u, const std::vector<std::vector<Triple>>& jobout, const L
   std::vector<uint64_t> key(m), key2(m);
   std::vector<uint32_t> idx(m), idx2(m);
   std::vector<const Triple*> ptr(m);
+  bool any_low = false;
   {
     size_t q = 0;
     for (size_t j = u.jb; j < u.je; ++j)
       for (const Triple& t : piece(j)) {
         key[q] = ((t.tcode & cmask) << (1 + sbits)) | ((uint64_t)t.low << sbits) |
                  ((t.low || !factored) ? (uint64_t)(t.src - L.ib) : 0);
+        any_low |= t.low != 0;
         idx[q] = (uint32_t)q;
         ptr[q] = &t;
         ++q;
       }
   }
+  // only key bits that vary are sorted on: without low-tier triples a factored unit's keys
+  // have zero tier and source fields, and the bucket fixes the top 4 bits of the code
+  const int lo_bit = (factored && !any_low) ? 1 + sbits : 0;
+  const int hi_bit = 3 * u.n > 4 ? bits - 4 : 1 + sbits;
   constexpr int RB = 11;
   std::vector<uint32_t> cnt(1u << RB);
-  for (int sh = 0; sh < bits; sh += RB) {
+  for (int sh = lo_bit; sh < hi_bit; sh += RB) {
     std::fill(cnt.begin(), cnt.end(), 0u);
     for (size_t q = 0; q < m; ++q) ++cnt[(key[q] >> sh) & ((1u << RB) - 1)];
     uint32_t run = 0;
@@ -478,25 +525,40 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       L.n = n;
       L.ib = ib;
       L.np = ie - ib;
-      L.bn.resize(L.np);
-      L.px.resize(L.np);
-      L.py.resize(L.np);
-      L.pz.resize(L.np);
-      for (int64_t q = 0; q < L.np; ++q) {
-        L.bn[q] = std::sqrt(bn2_all[fu_index[i][ib + q]]);
-        L.maxb = std::max(L.maxb, L.bn[q]);
-        decode(f.code[f.interior[ib + q]], n, L.px[q], L.py[q], L.pz[q]);
-      }
-      L.order.resize(L.np);
-      std::iota(L.order.begin(), L.order.end(), 0);
-      std::stable_sort(L.order.begin(), L.order.end(),
-                       [&](int64_t a, int64_t b) { return L.bn[a] > L.bn[b]; });
-      const int li = (int)lv.size();
       lv.push_back(std::move(L));
-      const LevelData& LL = lv.back();
+    }
+  }
+  // per level: source norms, positions, and the sources by descending norm (in parallel)
+  parallel_for(lv.size(), [&](size_t li, unsigned) {
+    LevelData& L = lv[li];
+    const Func& f = *funcs[L.fn];
+    L.bn.resize(L.np);
+    L.px.resize(L.np);
+    L.py.resize(L.np);
+    L.pz.resize(L.np);
+    for (int64_t q = 0; q < L.np; ++q) {
+      L.bn[q] = std::sqrt(bn2_all[fu_index[L.fn][L.ib + q]]);
+      L.maxb = std::max(L.maxb, L.bn[q]);
+      decode(f.code[f.interior[L.ib + q]], L.n, L.px[q], L.py[q], L.pz[q]);
+    }
+    L.order.resize(L.np);
+    std::iota(L.order.begin(), L.order.end(), 0);
+    std::stable_sort(L.order.begin(), L.order.end(),
+                     [&](int64_t a, int64_t b) { return L.bn[a] > L.bn[b]; });
+  });
+  // displacement ranges of the (level, term) jobs, in parallel; -1 marks a dropped term
+  {
+    std::vector<size_t> lv_off(lv.size() + 1, 0);
+    for (size_t li = 0; li < lv.size(); ++li)
+      lv_off[li + 1] = lv_off[li] + ops[lv[li].fn]->c.size();
+    std::vector<int> jobD(lv_off.back(), -1);
+    parallel_for(lv.size(), [&](size_t li, unsigned) {
+      const LevelData& LL = lv[li];
+      const Op& op = *ops[LL.fn];
+      const int n = LL.n;
       const int64_t nb = (int64_t)1 << n;
       const double h = W / std::ldexp(1.0, n);
-      for (int mu = 0; mu < M; ++mu) {
+      for (size_t mu = 0; mu < op.c.size(); ++mu) {
         double c = std::fabs(op.c[mu]);
         double beta = op.t[mu] * h * h;
         double ab = 2.0 * h;
@@ -508,10 +570,16 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
         int D = 0;
         while (D + 1 <= nb - 1 && c * LL.maxb * fac * ab * ab * decay_bound(h, beta, D + 1) >= tau)
           ++D;
-        if (D > 32000) fail(MRA_E_UNSUPPORTED, "displacement range too large");
-        jobs.push_back({li, mu, D, nullptr});
+        jobD[lv_off[li] + mu] = D;
       }
-    }
+    });
+    for (size_t li = 0; li < lv.size(); ++li)
+      for (size_t mu = 0; mu < lv_off[li + 1] - lv_off[li]; ++mu) {
+        const int D = jobD[lv_off[li] + mu];
+        if (D < 0) continue;
+        if (D > 32000) fail(MRA_E_UNSUPPORTED, "displacement range too large");
+        jobs.push_back({(int)li, (int)mu, D, nullptr});
+      }
   }
   // Fill the block caches: distinct operators in parallel, each operator's entries in order.
   {
@@ -644,10 +712,14 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
           rr[d] = jb.be->r[d];
         }
         std::vector<Triple>* outv = &jobout[jj * kBuckets];
+        const ScreenBound sb(c, L.maxb, tau, n > 0 ? ae.data() : rr.data(), D);
         // dz outermost: per target the triples of a term come in (dz, dy, dx) order
-        for (int dz = -D; dz <= D; ++dz)
-          for (int dy = -D; dy <= D; ++dy)
-            for (int dx = -D; dx <= D; ++dx) {
+        const int Rz = sb.rz();
+        for (int dz = -Rz; dz <= Rz; ++dz) {
+          const int Ry = sb.ry(std::abs(dz));
+          for (int dy = -Ry; dy <= Ry; ++dy) {
+            const int Rx = sb.rx(std::abs(dy), std::abs(dz));
+            for (int dx = -Rx; dx <= Rx; ++dx) {
               const double cN = screen_cn(c, n, ae.data(), aa.data(), rr.data(), std::abs(dx),
                                           std::abs(dy), std::abs(dz));
               if (cN * L.maxb < tau) continue;
@@ -664,6 +736,8 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
                                                         (int16_t)dx, (int16_t)dy, (int16_t)dz, low});
               }
             }
+          }
+        }
       });
       mark("enumerate");
       // group by target per (function, level, bucket) unit, largest units first
@@ -718,7 +792,12 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       int Dm = 0;
       for (size_t j = lu_j[u]; j < lu_j[u + 1]; ++j) Dm = std::max(Dm, jobs[j].D);
       const size_t S1 = (size_t)Dm + 1;
+      // max over the terms of c N, filled only where a term's pruning bound (ScreenBound)
+      // can pass; the other entries stay 0 and would fail the test anyway.  lim_* record
+      // the reach of the filled entries, so the scan below skips only zeros.
       std::vector<double> cn(S1 * S1 * S1, 0.0);   // [ax][ay][az]
+      int lim_z = -1;
+      std::vector<int> lim_y(S1, -1), lim_x(S1 * S1, -1);   // [az], [az][ay]
       for (size_t j = lu_j[u]; j < lu_j[u + 1]; ++j) {
         const Job& jb = jobs[j];
         const double c = std::fabs(op.c[jb.mu]);
@@ -729,17 +808,27 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
           aa[d] = jb.be->a[d];
           rr[d] = jb.be->r[d];
         }
-        for (int ax = 0; ax <= D; ++ax)
-          for (int ay = 0; ay <= D; ++ay)
-            for (int az = 0; az <= D; ++az) {
+        const ScreenBound sb(c, L.maxb, tau, n > 0 ? ae.data() : rr.data(), D);
+        const int Rz = sb.rz();
+        lim_z = std::max(lim_z, Rz);
+        for (int az = 0; az <= Rz; ++az) {
+          const int Ry = sb.ry(az);
+          lim_y[az] = std::max(lim_y[az], Ry);
+          for (int ay = 0; ay <= Ry; ++ay) {
+            const int Rx = sb.rx(ay, az);
+            lim_x[(size_t)az * S1 + ay] = std::max(lim_x[(size_t)az * S1 + ay], Rx);
+            for (int ax = 0; ax <= Rx; ++ax) {
               double& m = cn[((size_t)ax * S1 + ay) * S1 + az];
               m = std::max(m, screen_cn(c, n, ae.data(), aa.data(), rr.data(), ax, ay, az));
             }
+          }
+        }
       }
       std::vector<uint64_t> codes;
-      for (int dz = -Dm; dz <= Dm; ++dz)
-        for (int dy = -Dm; dy <= Dm; ++dy)
-          for (int dx = -Dm; dx <= Dm; ++dx) {
+      for (int dz = -lim_z; dz <= lim_z; ++dz)
+        for (int dy = -lim_y[std::abs(dz)]; dy <= lim_y[std::abs(dz)]; ++dy)
+          for (int dx = -lim_x[(size_t)std::abs(dz) * S1 + std::abs(dy)];
+               dx <= lim_x[(size_t)std::abs(dz) * S1 + std::abs(dy)]; ++dx) {
             const double cN = cn[((size_t)std::abs(dx) * S1 + std::abs(dy)) * S1 + std::abs(dz)];
             if (cN * L.maxb < tau) continue;
             for (int64_t oi = 0; oi < L.np; ++oi) {
@@ -995,6 +1084,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       const size_t o_work = A1.put(work), o_sub = A1.put(tgt_sub), o_spl = A1.put(splits),
                    o_lwork = A1.put(low_work);
       const size_t o_part = A1.scratch((size_t)npartials * 9 * K3 * sizeof(double));  // (2k)^3 + k^3
+      const size_t o_cnt = A1.scratch(256);   // work counter of the persistent kernel
       A1.commit();
       const NSItem* items_d = A1.at<NSItem>(o_items);
       const TargetRange* work_d = A1.at<TargetRange>(o_work);
@@ -1003,6 +1093,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       const LowItem* low_items_d = A1.at<LowItem>(o_litems);
       const TargetRange* low_work_d = A1.at<TargetRange>(o_lwork);
       double* partials_d = A1.scr_at<double>(o_part);
+      int* counter_d = A1.scr_at<int>(o_cnt);
       mark("ranges + uploads");
       plan_ms += now_ms() - t_c0;
       // device work of the chunk
@@ -1010,7 +1101,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       hipEvent_t* E = cev.back()->e;
       hip_check(hipEventRecord(E[0], ctx->stream), "event");
       launch_apply_ns(k, in_tab_d, out_tab_d, items_d, work_d, (int)work.size(), r_tab_d,
-                      t_tab_d, c_tab_d, partials_d, subbuf_d, ctx->stream);
+                      t_tab_d, c_tab_d, partials_d, subbuf_d, counter_d, ctx->stream);
       hip_check(hipEventRecord(E[1], ctx->stream), "event");
       launch_reduce_partials(k, partials_d, out_tab_d, subbuf_d, splits_d,
                              (int)splits.size(), ctx->stream);

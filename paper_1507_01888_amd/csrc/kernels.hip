@@ -44,6 +44,11 @@ __global__ void zero_kernel(double* __restrict__ p, size_t n) {
   for (; i < n; i += stride) p[i] = 0.0;
 }
 
+// Sets the work counter of a persistent kernel (one lane, vector store).
+__global__ void set_counter_kernel(int* __restrict__ c, int v) {
+  if (threadIdx.x == 0) *as_global(c) = v;
+}
+
 // Clears arrays tab[y][0 .. len[y]) for every y = blockIdx.y.
 __global__ void zero_batch_kernel(double* const* __restrict__ tab, const int64_t* __restrict__ len) {
   MRA_GLOBAL double* __restrict__ p = as_global(tab[blockIdx.y]);
@@ -762,6 +767,16 @@ __device__ __forceinline__ void interleave_mem() {
   __builtin_amdgcn_sched_group_barrier(0x008, 64, 0);
 }
 
+// Copies 16 bytes per lane from base + voff (bytes) into LDS at dst + 16 * lane with a buffer
+// load that writes LDS directly; the descriptor bounds the read to nbytes from base (lanes
+// past the end read zeros).  The copy completes on the vector-memory counter only.
+__device__ __forceinline__ void lds_copy16(const double* base, int nbytes, MRA_LDS void* dst,
+                                           int voff) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, nbytes, 0x00020000);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 16, voff, 0, 0, 0);
+}
+
 template <int B>
 struct BufTag {
   static constexpr int value = B;
@@ -790,19 +805,20 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
     const double* const* __restrict__ r_tab, const double* const* __restrict__ t_tab,
     const double* const* __restrict__ c_tab, double* __restrict__ partials,
-    double* __restrict__ subbuf) {
+    double* __restrict__ subbuf, const int ntargets, int* __restrict__ next_target) {
   constexpr int N = 2 * K, Q = N / 4, N2 = N * N, N3 = N * N * N, K2 = K * K, K3 = K * K * K;
   static_assert(Q == 5, "row stride 2k = 20 and the wave split below are for k = 10");
   constexpr int EXTRA = (Q - 4) * Q, EPW = (EXTRA + 3) / 4;   // (z-quad 4, a-quad) units
   static_assert(EXTRA == Q && EPW == 2, "the z-quad-4 units are a-quads 3 - wave and 7 - wave");
   constexpr int P3 = Q * Q, P3PW = (P3 + 3) / 4;              // step-3 (a-quad, b-quad) pairs
-  // staging geometry, in 16-byte granules (two doubles)
-  // (every wave moves XQ + OQ granule rows per triple; the buffers are padded so that the
-  // rows past the end of a block are written to padding instead of being branched around)
+  // copy geometry, in rows of 64 granules of 16 bytes (two doubles): every wave copies XQ
+  // source rows and one row of each operator block per triple; the buffers are padded so
+  // that rows past the end of a block land in padding instead of being branched around.
+  // An operator block (N^2 doubles) takes OB = 4 rows, so that each copy instruction reads
+  // one block: R_x^T, R_y^T, R_z^T start at 0, OBD and 2 OBD doubles.
   constexpr int XG = N3 / 2, XI = (XG + 63) / 64, XQ = (XI + 3) / 4, XPAD = 128 * 4 * XQ;
-  constexpr int OPS = 3 * N2, OG = OPS / 2, OI = (OG + 63) / 64, OQ = (OI + 3) / 4,
-                OPAD = 128 * 4 * OQ;
-  static_assert(XQ == 16 && OQ == 3, "the staging schedule below moves 4 x 4 + 3 rows");
+  constexpr int OB = (N2 / 2 + 63) / 64, OBD = 128 * OB, OPAD = 3 * OBD;
+  static_assert(XQ == 16 && OB == 4, "the copy schedule below moves 4 x 4 + 3 rows per wave");
   static_assert(N2 % 2 == 0 && K2 % 2 == 0 && K % 2 == 0, "granules never straddle rows");
   static_assert(64 * Q * Q * Q <= XPAD, "the exchange tensor fits in a source buffer");
   // the two halves of each double buffer are separate objects, so that the compiler can
@@ -814,12 +830,6 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
-  const TargetRange tr = targets[blockIdx.x];
-  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
-  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
-  const MRA_GLOBAL double* __restrict__ dR = as_global(r_tab[tr.fn]);
-  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
-
   // granule g of the row-major source block is (x, y, z = 2 zp), g = (x N + y) N/2 + zp;
   // this lane's offsets (doubles, from the first child's slab) for its wave's instructions
   int xoff[XQ];
@@ -830,44 +840,42 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     const int child = ((x / K) << 2) | ((y / K) << 1) | (z / K);
     xoff[q] = child * K3 + ((x % K) * K + y % K) * K + z % K;
   }
-  // operator granules: [R_x^T | R_y^T | R_z^T] (N^2 each)
-  int osel[OQ], ooff[OQ];
-#pragma unroll
-  for (int q = 0; q < OQ; ++q) {
-    const int g = min(64 * (wave + 4 * q) + lane, OG - 1);
-    osel[q] = g / (N2 / 2);
-    ooff[q] = 2 * (g - osel[q] * (N2 / 2));
-  }
-  // The next triple's blocks travel global -> registers -> LDS in five parts (four of the
-  // source block, one of the operators): fetch_part() issues a part's loads and
-  // commit_part() stores it into the free buffer halves.  Both are spread over the
-  // x-quad groups of step 1, interleaved with the matrix products, because a burst of
-  // memory instructions stalls the in-order wave until the memory pipeline takes them.
-  // (Direct global->LDS loads would count against the LDS wait counter as well, and every
-  // LDS read of the triple would then have to wait for them to land.)
-  f64x2 sx[XQ], so[OQ];
-  auto fetch_part = [&](const NSItem nx, const int part) {
-    if (part < 4) {
-      const MRA_GLOBAL double* base = in + (size_t)nx.src_fc * K3;
-#pragma unroll
-      for (int q = 4 * part; q < 4 * part + 4; ++q) sx[q] = *(const MRA_GLOBAL f64x2*)(base + xoff[q]);
-    } else {
-#pragma unroll
-      for (int q = 0; q < OQ; ++q) {
-        const int sel = osel[q];
-        const int blk = sel == 0 ? nx.rx : sel == 1 ? nx.ry : nx.rz;
-        so[q] = *(const MRA_GLOBAL f64x2*)(dR + (size_t)blk * N2 + ooff[q]);
-      }
-    }
-  };
-  auto commit_part = [&](const int part, double* dst, double* dop) {
+  // Persistent workgroups: each takes the next target range from a counter until none is
+  // left, so a CU that finishes early starts the next range at once (the ranges come
+  // longest first) instead of waiting for the hardware's round-robin over the dies.
+  __shared__ int s_next;
+  for (;;) {
+  if (tid == 0) s_next = atomicAdd(next_target, 1);
+  __syncthreads();
+  const int ti = s_next;
+  __syncthreads();   // every wave has read s_next
+  if (ti >= ntargets) break;
+  const TargetRange tr = targets[ti];
+  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
+  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
+  // The next triple's blocks are copied into the free buffer halves by buffer loads that
+  // write LDS directly (no registers; they complete on the vector-memory counter only, so
+  // the LDS reads of the running triple never wait for them), in five parts (four of the
+  // source block, one of the operators) spread over the x-quad groups of step 1: a burst
+  // of memory instructions would stall the in-order wave until the memory pipeline takes
+  // them.  The buffer descriptors bound each copy to its block: lanes past the end of an
+  // operator block read zeros.
+  const double* const in_g = in_tab[tr.fn];
+  const double* const dR_g = r_tab[tr.fn];
+  auto fetch_part = [&](const NSItem nx, const int part, double* dst, double* dop) {
     if (part < 4) {
 #pragma unroll
       for (int q = 4 * part; q < 4 * part + 4; ++q)
-        *(f64x2*)(dst + 128 * (wave + 4 * q) + 2 * lane) = sx[q];
+        lds_copy16(in_g + (size_t)nx.src_fc * K3, 8 * K3 * 8, (MRA_LDS void*)(dst + 128 * (wave + 4 * q)),
+                   8 * xoff[q]);
     } else {
 #pragma unroll
-      for (int q = 0; q < OQ; ++q) *(f64x2*)(dop + 128 * (wave + 4 * q) + 2 * lane) = so[q];
+      for (int q = 0; q < 3; ++q) {
+        const int blk = q == 0 ? nx.rx : q == 1 ? nx.ry : nx.rz;
+        lds_copy16(dR_g + (size_t)blk * N2, N2 * 8, (MRA_LDS void*)(dop + q * OBD + 128 * wave),
+                   16 * (64 * wave + lane));
+      }
     }
   };
   double d1[Q][Q], d2[Q][Q], d1e[EPW][Q], d2e[EPW][Q], acc[P3PW][Q];
@@ -891,10 +899,7 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     cur = items[tr.beg];
     c_cur = dc[cur.mu];
 #pragma unroll
-    for (int part = 0; part < 5; ++part) {
-      fetch_part(cur, part);
-      commit_part(part, Xs0, Os0);
-    }
+    for (int part = 0; part < 5; ++part) fetch_part(cur, part, Xs0, Os0);
     nxt = items[min(tr.beg + 1, tr.end - 1)];
   }
   // one triple; BUF is a compile-time constant so that the compiler can tell the reads of
@@ -907,8 +912,9 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     double* const On = buf == 0 ? Os1 : Os0;
     const NSItem item = cur;
     const bool more = it + 1 < tr.end;
-    // after the barrier the blocks of triple it are in LDS and every wave is done with
-    // triple it - 1 (the other buffer halves are free)
+    // this wave's copies of triple it are complete; after the barrier all of them are, and
+    // every wave is done with triple it - 1 (the other buffer halves are free)
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     __syncthreads();
     const NSItem nn = items[min(it + 2, tr.end - 1)];   // uniform address: scalar loads
     if (more) {
@@ -916,15 +922,22 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     }
     const bool dy_end = !more || nxt.rz != item.rz || nxt.ry != item.ry;
     const bool dz_end = !more || nxt.rz != item.rz;
-    const double cmu = c_cur;
     const double* X = Xc;
+    const double cmu = c_cur;
     const double* RXs = Oc;
-    const double* RYs = Oc + N2;
-    const double* RZs = Oc + 2 * N2;
+    const double* RYs = Oc + OBD;
+    const double* RZs = Oc + 2 * OBD;
     // One wave per SIMD hides no latency by switching waves, so every step is software-
     // pipelined by hand: the LDS operands of group g + 1 are read into the other half of a
     // register double buffer before the matrix products of group g, and scheduling
     // barriers keep the compiler from sinking those reads next to their uses.
+    // step 2's operands of its first y-quad are read during the last x-quad group of step 1
+    // (whether or not the triple ends a y group)
+    double ry[2][Q];
+    auto load2 = [&](const int ys, const int b) {
+#pragma unroll
+      for (int bt = 0; bt < Q; ++bt) ry[b][bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+    };
     // ---- step 1, per x-quad xs: the main z-quad of this wave (all a-quads) and the
     // z-quad-4 units.  Every wave runs EPW = 2 of those units, so that the block has no
     // wave-dependent branch; a wave with one real unit repeats it into an accumulator that
@@ -952,11 +965,8 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
         if (xs + 1 < Q) load1(xs + 1, b ^ 1);
         // the next triple's blocks (for the last triple of the list, nxt repeats the
         // current item: harmless loads into the free halves)
-        if (xs == 0) { fetch_part(nxt, 0); fetch_part(nxt, 1); }
-        if (xs == 1) { fetch_part(nxt, 2); fetch_part(nxt, 3); }
-        if (xs == 2) { fetch_part(nxt, 4); commit_part(0, Xn, On); }
-        if (xs == 3) { commit_part(1, Xn, On); commit_part(2, Xn, On); }
-        if (xs == 4) { commit_part(3, Xn, On); commit_part(4, Xn, On); }
+        fetch_part(nxt, xs, Xn, On);
+        if (xs == 4) load2(0, 0);
 #pragma unroll
         for (int yt = 0; yt < Q; ++yt)
 #pragma unroll
@@ -967,21 +977,13 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
 #pragma unroll
           for (int yt = 0; yt < Q; ++yt)
             d1e[e][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(opE[b][yt], opB[b][e], d1e[e][yt], 0, 0, 0);
-        if (xs == 0 || xs == 1) interleave_mem<11, 8, 0, 2>();
-        if (xs == 2) interleave_mem<11, 3, 4, 2>();
-        if (xs == 3) interleave_mem<11, 0, 8, 2>();
-        if (xs == 4) interleave_mem<0, 0, 7, 3>();
+        if (xs + 1 < Q) interleave_mem<11, 4, 0, 2>();
+        else interleave_mem<3, 3, 0, 3>();
         __builtin_amdgcn_sched_barrier(0);
       }
     }
     // ---- step 2 at the end of a (mu, dz, dy) group
     if (dy_end) {
-      double ry[2][Q];
-      auto load2 = [&](const int ys, const int b) {
-#pragma unroll
-        for (int bt = 0; bt < Q; ++bt) ry[b][bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
-      };
-      load2(0, 0);
 #pragma unroll
       for (int ys = 0; ys < Q; ++ys) {
         const int b = ys & 1;
@@ -1011,7 +1013,7 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
     // ---- step 3 at the end of a (mu, dz) group, through this triple's source buffer
     if (dz_end) {
       double* Zs = Xc;
-      double rz[Q][Q];   // c_mu R_z^T fragments, loaded while the waves meet
+      double rz[Q][Q];   // c_mu R_z^T fragments, read while the waves meet
 #pragma unroll
       for (int zs = 0; zs < Q; ++zs)
 #pragma unroll
@@ -1090,6 +1092,9 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
         }
       }
     }
+  }
+  // the last triple's copies into the free halves have landed before the buffers are reused
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
   }
 }
 
@@ -2367,18 +2372,36 @@ bool ns_kernel_fuses_subtraction(int k) { return k == 8 || k == 10 || k == 12 ||
 
 bool ns_kernel_factored(int k) { return k == 10; }
 
+// Compute units of the current device (cached per device).
+static int device_cus() {
+  static int cus[64] = {};
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) fail(MRA_E_DEVICE, "device index out of range");
+  if (cus[dev] <= 0) {
+    int n = 0;
+    hip_check(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev),
+              "hipDeviceGetAttribute");
+    cus[dev] = std::max(1, n);
+  }
+  return cus[dev];
+}
+
 void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
                      const NSItem* items, const TargetRange* targets, int ntargets,
                      const double* const* r_tab, const double* const* t_tab,
                      const double* const* c_tab, double* partials, double* subbuf,
-                     hipStream_t s) {
+                     int* counter, hipStream_t s) {
   if (ntargets <= 0) return;
   if (k == 8) {
     hipLaunchKernelGGL(apply_ns_mfma_kernel<8>, dim3(ntargets), dim3(256), 0, s, in_tab,
                        out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
   } else if (k == 10) {
-    hipLaunchKernelGGL(apply_ns_fac_kernel<10>, dim3(ntargets), dim3(256), 0, s, in_tab,
-                       out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
+    // one persistent workgroup per CU (the kernel's LDS allows one), ranges from a counter
+    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, counter, 0);
+    hipLaunchKernelGGL(apply_ns_fac_kernel<10>, dim3(std::min(ntargets, device_cus())), dim3(256),
+                       0, s, in_tab, out_tab, items, targets, r_tab, t_tab, c_tab, partials,
+                       subbuf, ntargets, counter);
     hip_check(hipGetLastError(), "apply_ns_fac_kernel");
     hipLaunchKernelGGL(apply_ns_fac_sub_kernel<10>, dim3(ntargets), dim3(192), 0, s, in_tab,
                        items, targets, t_tab, c_tab, partials, subbuf);

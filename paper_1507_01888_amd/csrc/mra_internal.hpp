@@ -300,7 +300,7 @@ void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
                      const NSItem* items, const TargetRange* targets, int ntargets,
                      const double* const* r_tab, const double* const* t_tab,
                      const double* const* c_tab, double* partials, double* subbuf,
-                     hipStream_t s);
+                     int* counter, hipStream_t s);
 void launch_reduce_partials(int k, const double* partials, double* const* out_tab,
                             double* subbuf, const SplitTarget* splits, int nsplits,
                             hipStream_t s);
