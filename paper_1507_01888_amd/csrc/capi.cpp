@@ -223,7 +223,12 @@ static void transpose_into(int m, const double* a, double* out) {
 }
 
 const BlockEntry& Op::ensure(int level, int mu, int D) {
+  // direct index in front of the map (its nodes never move)
+  const size_t M = c.size(), slot = (size_t)level * M + (size_t)mu;
+  if (slot < entry_at.size() && entry_at[slot] && entry_at[slot]->D >= D) return *entry_at[slot];
   BlockEntry& e = entries[{level, mu}];
+  if (entry_at.size() <= slot) entry_at.resize((size_t)(level + 1) * M, nullptr);
+  entry_at[slot] = &e;
   if (e.D >= D) return e;
   const int K2 = k * k, N = 2 * k, N2 = N * N;
   double W = ctx->width();

@@ -214,6 +214,7 @@ struct Op {
   int k = 0;
   std::vector<double> c, t;
   std::map<std::pair<int, int>, BlockEntry> entries;   // (level, mu)
+  std::vector<BlockEntry*> entry_at;                   // [level * M + mu] -> entries' node
   std::vector<double> hR, hT;                          // host mirror of device blocks
   DevArray<double> dR, dT;                             // transposed blocks
   size_t dR_blocks = 0, dT_blocks = 0;                 // blocks resident on device
