@@ -1102,8 +1102,11 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
 // the triples of a target, with the same grouping (step 1 per triple, step 2 per (mu, dz, dy)
 // group, step 3 per (mu, dz) group) on the k^3 scaling blocks, zero-padded to KP = 4 Q2.
 // Three waves: wave w owns z-quad w in steps 1 and 2; the nine step-3 (a-quad, b-quad) pairs
-// are split three per wave.  The t blocks of the next triple travel into the other half of
-// an LDS double buffer by direct loads; s_P fragments go to registers one triple ahead.
+// are split three per wave.  The work per triple is small, so the waves do not meet per
+// triple: each wave copies the three t blocks of triple it + 2 into a private LDS slot (a
+// ring of three; buffer loads that write LDS, one row of 64 granules per block) and loads
+// its s_P fragments of triple it + 2 into registers, so that two triples of work cover the
+// memory latency; the waves meet only around the step-3 exchange.
 template <int K>
 __global__ __launch_bounds__(192) void apply_ns_fac_sub_kernel(
     const double* const* __restrict__ in_tab, const NSItem* __restrict__ items,
@@ -1113,11 +1116,14 @@ __global__ __launch_bounds__(192) void apply_ns_fac_sub_kernel(
   constexpr int N = 2 * K, N3 = N * N * N, K2 = K * K, K3 = K * K * K;
   constexpr int Q2 = (K + 3) / 4, S3 = Q2 * Q2;
   static_assert(Q2 == 3, "three waves own the three z-quads of KP = 12");
+  static_assert(K2 % 2 == 0 && K2 / 2 <= 64, "a t block fits one row of granules");
   constexpr int S3PW = S3 / 3;
-  constexpr int TG = 3 * K2 / 2, TPAD = 128 * 3;   // t granules, padded to 3 x 64
-  static_assert(K2 % 2 == 0 && TG <= 192, "granules");
-  __shared__ __attribute__((aligned(16))) double Ts0[TPAD];
-  __shared__ __attribute__((aligned(16))) double Ts1[TPAD];
+  constexpr int TW = 3 * 128;   // one wave's slot: t_x^T, t_y^T, t_z^T, a row of 128 doubles each
+  // the three slots of the ring are separate objects, so that the compiler can tell the
+  // reads of one slot from the copies into the others
+  __shared__ __attribute__((aligned(16))) double Ts0[3 * TW];
+  __shared__ __attribute__((aligned(16))) double Ts1[3 * TW];
+  __shared__ __attribute__((aligned(16))) double Ts2[3 * TW];
   __shared__ double Z2s[K3];   // exchange tensor, [a][b][z], unpadded
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -1125,17 +1131,21 @@ __global__ __launch_bounds__(192) void apply_ns_fac_sub_kernel(
   const TargetRange tr = targets[blockIdx.x];
   if (tr.sub < 0) return;   // level 0: no subtraction (uniform over the workgroup)
   const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
-  const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
-  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
-  // this lane's granule of [t_x^T | t_y^T | t_z^T]
-  const int tg = min(64 * wave + lane, TG - 1);
-  const int tsel = tg / (K2 / 2), toff = 2 * (tg - tsel * (K2 / 2));
-  auto dma_t = [&](const NSItem nx, double* dst) {
-    const int blk = tsel == 0 ? nx.tx : tsel == 1 ? nx.ty : nx.tz;
-    __builtin_amdgcn_global_load_lds((const MRA_GLOBAL void*)(dT + (size_t)blk * K2 + toff),
-                                     (MRA_LDS void*)(dst + 128 * wave), 16, 0, 0);
+  const double* const dT_g = t_tab[tr.fn];
+  // c_mu through the scalar cache (read-only here): the values stay off the vector-memory
+  // counter, so the copies in flight are never waited for on their account
+  const __attribute__((address_space(4))) double* __restrict__ dc =
+      (const __attribute__((address_space(4))) double*)c_tab[tr.fn];
+  // this wave's copy of the t blocks of item nx into its part of a slot (lanes past a
+  // block's K^2 / 2 granules read zeros into padding)
+  auto copy_t = [&](const NSItem nx, double* slot) {
+    double* dst = slot + wave * TW;
+    lds_copy16(dT_g + (size_t)nx.tx * K2, K2 * 8, (MRA_LDS void*)dst, 16 * lane);
+    lds_copy16(dT_g + (size_t)nx.ty * K2, K2 * 8, (MRA_LDS void*)(dst + 128), 16 * lane);
+    lds_copy16(dT_g + (size_t)nx.tz * K2, K2 * 8, (MRA_LDS void*)(dst + 256), 16 * lane);
   };
-  // this wave's z-quad of s_P as step-1 A operands; zeroed outside k^3 where used
+  // this wave's z-quad of s_P as step-1 A operands; lanes outside k^3 load an in-block
+  // element (no branch, so the loads stay in flight) and are zeroed where used
   auto sp_ok = [&](int xs, int yt) {
     return 4 * xs + lk < K && 4 * yt + li < K && 4 * wave + lb < K;
   };
@@ -1145,7 +1155,7 @@ __global__ __launch_bounds__(192) void apply_ns_fac_sub_kernel(
     for (int xs = 0; xs < Q2; ++xs)
 #pragma unroll
       for (int yt = 0; yt < Q2; ++yt)
-        v[xs][yt] = sp[sp_ok(xs, yt) ? ((4 * xs + lk) * K + 4 * yt + li) * K + 4 * wave + lb : 0];
+        v[xs][yt] = sp[min(((4 * xs + lk) * K + 4 * yt + li) * K + 4 * wave + lb, K3 - 1)];
   };
   // t^T[r][c] as a B fragment, zero outside k x k
   auto tfrag = [&](const double* T, int rq, int cq) {
@@ -1155,44 +1165,50 @@ __global__ __launch_bounds__(192) void apply_ns_fac_sub_kernel(
     return ok ? v : 0.0;
   };
 
-  double d1[Q2][Q2], d2[Q2][Q2], acc[S3PW][Q2], spv[Q2][Q2], spn[Q2][Q2];
+  double d1[Q2][Q2], d2[Q2][Q2], acc[S3PW][Q2];
+  double sp0[Q2][Q2], sp1[Q2][Q2], sp2[Q2][Q2];   // s_P fragments of the ring's triples
 #pragma unroll
   for (int i = 0; i < Q2; ++i)
 #pragma unroll
-    for (int j = 0; j < Q2; ++j) d1[i][j] = d2[i][j] = spv[i][j] = spn[i][j] = 0.0;
+    for (int j = 0; j < Q2; ++j) d1[i][j] = d2[i][j] = sp0[i][j] = sp1[i][j] = sp2[i][j] = 0.0;
 #pragma unroll
   for (int e = 0; e < S3PW; ++e)
 #pragma unroll
     for (int j = 0; j < Q2; ++j) acc[e][j] = 0.0;
 
-  NSItem cur{}, nxt{};
-  double c_cur = 0.0, c_pre = 0.0;
+  // item records three triples ahead; triples beg and beg + 1 are copied before the loop
+  NSItem cur{}, i1{}, i2{};
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0;   // c_mu of the ring's triples (slot-indexed like sp*)
   if (tr.beg < tr.end) {
     cur = items[tr.beg];
-    c_cur = dc[cur.mu];
-    dma_t(cur, Ts0);
-    load_sp(cur, spv);
-    nxt = items[min(tr.beg + 1, tr.end - 1)];
+    i1 = items[min(tr.beg + 1, tr.end - 1)];
+    i2 = items[min(tr.beg + 2, tr.end - 1)];
+    c0 = dc[cur.mu];
+    c1 = dc[i1.mu];
+    copy_t(cur, Ts0);
+    load_sp(cur, sp0);
+    copy_t(i1, Ts1);
+    load_sp(i1, sp1);
   }
-  auto triple = [&](const int it, auto buf_tag) {
-    constexpr int buf = decltype(buf_tag)::value;
-    const double* const Tc = buf == 0 ? Ts0 : Ts1;
-    double* const Tn = buf == 0 ? Ts1 : Ts0;
-    const NSItem item = cur;
+  // one triple in ring slot S (compile-time, so that the compiler can tell the slots apart)
+  auto triple = [&](const int it, auto slot_tag, double (&spc)[Q2][Q2], double (&spf)[Q2][Q2],
+                    const double cc, double& cf) {
+    constexpr int S = decltype(slot_tag)::value;
+    const double* const Tc = (S == 0 ? Ts0 : S == 1 ? Ts1 : Ts2) + wave * TW;
+    double* const Tf = S == 0 ? Ts2 : S == 1 ? Ts0 : Ts1;   // slot of triple it + 2
+    const NSItem item = cur, nxt = i1;
     const bool more = it + 1 < tr.end;
-    const NSItem nn = items[min(it + 2, tr.end - 1)];
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads of triple it
-    __syncthreads();
-    if (more) {
-      dma_t(nxt, Tn);
-      load_sp(nxt, spn);
-      c_pre = dc[nxt.mu];
-    }
+    const NSItem i3 = items[min(it + 3, tr.end - 1)];   // uniform address: scalar loads
+    // copies of triple it + 2 (for the last two triples they repeat the last item:
+    // harmless copies into a slot nobody reads)
+    copy_t(i2, Tf);
+    load_sp(i2, spf);
+    cf = dc[i2.mu];
     const bool dy_end = !more || nxt.rz != item.rz || nxt.ry != item.ry;
     const bool dz_end = !more || nxt.rz != item.rz;
     const double* TXs = Tc;
-    const double* TYs = Tc + K2;
-    const double* TZs = Tc + 2 * K2;
+    const double* TYs = Tc + 128;
+    const double* TZs = Tc + 256;
     // step 1 (contract x) for this wave's z-quad
 #pragma unroll
     for (int xs = 0; xs < Q2; ++xs)
@@ -1201,7 +1217,7 @@ __global__ __launch_bounds__(192) void apply_ns_fac_sub_kernel(
         const double b = tfrag(TXs, xs, at);
 #pragma unroll
         for (int yt = 0; yt < Q2; ++yt)
-          d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(sp_ok(xs, yt) ? spv[xs][yt] : 0.0, b,
+          d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(sp_ok(xs, yt) ? spc[xs][yt] : 0.0, b,
                                                           d1[at][yt], 0, 0, 0);
       }
     // step 2 (contract y) at the end of a (mu, dz, dy) group
@@ -1220,9 +1236,16 @@ __global__ __launch_bounds__(192) void apply_ns_fac_sub_kernel(
 #pragma unroll
         for (int j = 0; j < Q2; ++j) d1[i][j] = 0.0;
     }
-    // step 3 (contract z) at the end of a (mu, dz) group; Z2s was last read before the
-    // barrier at the top of this triple
+    // step 3 (contract z) at the end of a (mu, dz) group, through the exchange tensor; the
+    // waves meet before writing it (every wave is done reading the previous exchange) and
+    // after (it is complete)
     if (dz_end) {
+      double tz[Q2][Q2];
+#pragma unroll
+      for (int zs = 0; zs < Q2; ++zs)
+#pragma unroll
+        for (int ct = 0; ct < Q2; ++ct) tz[zs][ct] = -cc * tfrag(TZs, zs, ct);
+      lds_barrier();
 #pragma unroll
       for (int at = 0; at < Q2; ++at)
 #pragma unroll
@@ -1231,12 +1254,7 @@ __global__ __launch_bounds__(192) void apply_ns_fac_sub_kernel(
           if (a < K && b < K && z < K) Z2s[(a * K + b) * K + z] = d2[at][bt];
           d2[at][bt] = 0.0;
         }
-      __syncthreads();
-      double tz[Q2][Q2];
-#pragma unroll
-      for (int zs = 0; zs < Q2; ++zs)
-#pragma unroll
-        for (int ct = 0; ct < Q2; ++ct) tz[zs][ct] = -c_cur * tfrag(TZs, zs, ct);
+      lds_barrier();
 #pragma unroll
       for (int e = 0; e < S3PW; ++e) {
         const int p = wave + 3 * e;
@@ -1253,17 +1271,14 @@ __global__ __launch_bounds__(192) void apply_ns_fac_sub_kernel(
         }
       }
     }
-#pragma unroll
-    for (int i = 0; i < Q2; ++i)
-#pragma unroll
-      for (int j = 0; j < Q2; ++j) spv[i][j] = spn[i][j];
-    c_cur = c_pre;
-    cur = nxt;
-    nxt = nn;
+    cur = i1;
+    i1 = i2;
+    i2 = i3;
   };
-  for (int it = tr.beg; it < tr.end; it += 2) {
-    triple(it, BufTag<0>{});
-    if (it + 1 < tr.end) triple(it + 1, BufTag<1>{});
+  for (int it = tr.beg; it < tr.end; it += 3) {
+    triple(it, BufTag<0>{}, sp0, sp2, c0, c2);
+    if (it + 1 < tr.end) triple(it + 1, BufTag<1>{}, sp1, sp0, c1, c0);
+    if (it + 2 < tr.end) triple(it + 2, BufTag<2>{}, sp2, sp1, c2, c1);
   }
 #pragma unroll
   for (int e = 0; e < S3PW; ++e) {
