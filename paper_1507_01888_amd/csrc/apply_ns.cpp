@@ -1013,6 +1013,16 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       });
       for (double e : task_eta) eta_low += e;   // fixed order
       mark("work items");
+      // the items are final: their copy to the device runs while the target ranges are built
+      // (device room for the lists that follow is reserved from an upper bound on their size)
+      {
+        size_t nt_all = 0;
+        for (const Unit& u : units) nt_all += u.tcodes.size();
+        const size_t lists = 2 * ((3 * nt_all + n_items / 24 + 16) * sizeof(TargetRange) +
+                                  (nt_all + 16) * sizeof(SplitTarget) + 4096);
+        A1.prepare_device(A1.used + lists);
+        A1.commit_upto(A1.used);
+      }
       // target ranges: split long lists, longest first
       std::vector<TargetRange> tgt_sub, work, low_work;
       std::vector<SplitTarget> splits;

@@ -171,6 +171,8 @@ size_t Arena::reserve(size_t bytes) {
   const size_t end = align256(off + bytes);
   if (end > host_cap) {
     // host regions handed out earlier keep their offsets; their contents move with the buffer
+    // (after copies already issued from the old buffer have finished)
+    if (committed) ctx->sync();
     size_t cap = std::max<size_t>(end, host_cap + host_cap / 2);
     cap = std::max<size_t>(cap, (size_t)1 << 20);
     void* p = nullptr;
@@ -198,22 +200,41 @@ size_t Arena::scratch(size_t bytes) {
   return off;
 }
 
+static void arena_grow(Ctx* ctx, char*& buf, size_t& cap, size_t need) {
+  if (need <= cap) return;
+  ctx->sync();   // nothing may still use the old buffer
+  ctx->dfree(buf);
+  buf = nullptr;
+  cap = 0;
+  size_t c = std::max<size_t>(need, (size_t)1 << 20);
+  buf = static_cast<char*>(ctx->dalloc(c));
+  cap = c;
+}
+
+void Arena::prepare_device(size_t bytes) {
+  if (bytes > dev_cap) {
+    arena_grow(ctx, dev, dev_cap, bytes);
+    committed = 0;   // a new buffer holds nothing yet
+  }
+}
+
+void Arena::commit_upto(size_t end) {
+  end = std::min(end, used);
+  if (end <= committed) return;
+  prepare_device(used);
+  hip_check(hipMemcpyAsync(dev + committed, host + committed, end - committed,
+                           hipMemcpyHostToDevice, ctx->stream),
+            "hipMemcpyAsync H2D");
+  committed = end;
+}
+
 void Arena::commit() {
-  auto grow = [&](char*& buf, size_t& cap, size_t need) {
-    if (need <= cap) return;
-    ctx->sync();   // nothing may still use the old buffer
-    ctx->dfree(buf);
-    buf = nullptr;
-    cap = 0;
-    size_t c = std::max<size_t>(need, (size_t)1 << 20);
-    buf = static_cast<char*>(ctx->dalloc(c));
-    cap = c;
-  };
-  grow(dev, dev_cap, used);
-  grow(scr, scr_cap, scr_used);
-  if (used)
-    hip_check(hipMemcpyAsync(dev, host, used, hipMemcpyHostToDevice, ctx->stream),
-              "hipMemcpyAsync H2D");
+  if (used > dev_cap) {
+    arena_grow(ctx, dev, dev_cap, used);
+    committed = 0;
+  }
+  arena_grow(ctx, scr, scr_cap, scr_used);
+  commit_upto(used);
 }
 
 // ------------------------------------------------------------------------ block cache

@@ -117,10 +117,11 @@ struct Arena {
   char* scr = nullptr;
   size_t scr_cap = 0;
   size_t used = 0, scr_used = 0;
+  size_t committed = 0;                               // bytes already copied to the device
   ~Arena();
   void begin(Ctx* c) {
     ctx = c;
-    used = scr_used = 0;
+    used = scr_used = committed = 0;
   }
   size_t put_bytes(const void* src, size_t bytes);    // returns the device offset
   size_t reserve(size_t bytes);                       // host region filled by the caller
@@ -129,7 +130,11 @@ struct Arena {
   template <class T>
   size_t put(const std::vector<T>& v) { return put_bytes(v.data(), v.size() * sizeof(T)); }
   size_t scratch(size_t bytes);                       // device-only region, offset
-  void commit();                                      // grow device buffers, copy
+  void commit();                                      // grow device buffers, copy the rest
+  // device capacity for `bytes` of uploads, so that a prefix can be copied before the rest
+  // of the arena is filled (commit() re-copies everything if the estimate was short)
+  void prepare_device(size_t bytes);
+  void commit_upto(size_t end);                       // copy [committed, end) now
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(dev + off); }
   template <class T>
