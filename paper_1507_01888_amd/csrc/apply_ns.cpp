@@ -492,6 +492,9 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
                              hipMemcpyDeviceToHost, ctx->stream),
               "hipMemcpyAsync D2H");
   hip_check(hipEventRecord(ctx->ev[1], ctx->stream), "event");
+  // wake the planner's thread pool while the device runs the filter-up: workers that went
+  // to sleep since the last apply would otherwise be woken by the first planning loop
+  Pool::get().run(Pool::get().workers(), [](size_t, unsigned) {});
   ctx->sync();
   for (Func* f : funcs) f->interior_valid = true;
   double t_plan0 = now_ms();
@@ -546,6 +549,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
     std::stable_sort(L.order.begin(), L.order.end(),
                      [&](int64_t a, int64_t b) { return L.bn[a] > L.bn[b]; });
   });
+  mark("levels");
   // displacement ranges of the (level, term) jobs, in parallel; -1 marks a dropped term
   {
     std::vector<size_t> lv_off(lv.size() + 1, 0);
@@ -581,6 +585,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
         jobs.push_back({(int)li, (int)mu, D, nullptr});
       }
   }
+  mark("displacement ranges");
   // Fill the block caches: distinct operators in parallel, each operator's entries in order.
   {
     std::vector<Op*> uops;
@@ -1002,7 +1007,10 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
           r = e;
         }
       }
-      std::vector<double> task_eta(tasks.size(), 0.0);
+      std::vector<double> task_eta(tasks.size(), 0.0), task_fk(tasks.size(), 0.0);
+      // mode products the main kernel executes (before splitting long lists): per triple one
+      // for a factored kernel, plus one per (term, dz, dy) and per (term, dz) group end
+      const double fm = 2.0 * std::pow(2.0 * k, 4), fs = 2.0 * std::pow((double)k, 4);
       parallel_for(tasks.size(), [&](size_t ti, unsigned) {
         const Task& t = tasks[ti];
         Unit& u = units[t.u];
@@ -1010,7 +1018,25 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
         task_eta[ti] = fill_items(u, p, lv[unit_lev[t.u]], fu_index[u.fn], t.r0, t.r1, items_h,
                                   low_h, (int64_t)p.op->dR_blocks, (int64_t)p.op->dT_blocks,
                                   tiers ? (int64_t)p.op->dL_blocks : 0, (int64_t)fu_refs.size());
+        const double per = fm + (fused && u.n > 0 ? fs : 0.0);
+        double acc = 0.0;
+        for (int64_t r = t.r0; r < t.r1; ++r) {
+          const int64_t b = (int64_t)u.item_base + u.fpre[r], e = (int64_t)u.item_base + u.fpre[r + 1];
+          int64_t prods = e - b;
+          if (factored)
+            for (int64_t q = b; q < e; ++q) {
+              const bool last = q + 1 == e;
+              const NSItem& a = items_h[q];
+              if (last || items_h[q + 1].rz != a.rz || items_h[q + 1].ry != a.ry) ++prods;
+              if (last || items_h[q + 1].rz != a.rz) ++prods;
+            }
+          else
+            prods *= 3;
+          acc += (double)prods * per;
+        }
+        task_fk[ti] = acc;
       });
+      for (double v : task_fk) flops_kernel += v;   // fixed order
       for (double e : task_eta) eta_low += e;   // fixed order
       mark("work items");
       // the items are final: their copy to the device runs while the target ranges are built
@@ -1023,6 +1049,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
         A1.prepare_device(A1.used + lists);
         A1.commit_upto(A1.used);
       }
+      mark("items upload issued");
       // target ranges: split long lists, longest first
       std::vector<TargetRange> tgt_sub, work, low_work;
       std::vector<SplitTarget> splits;
@@ -1055,6 +1082,14 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
           for (int32_t q = 0; q < parts; ++q) {
             const int32_t qb = b + (int32_t)(q * len / parts), qe = b + (int32_t)((q + 1) * len / parts);
             work.push_back({i, node, fc, qb, qe, npartials + q, sub});
+            // a part ends its groups: its last triple closes the y- and z-groups it is in
+            if (factored && q + 1 < parts) {
+              const NSItem& a = items_h[qe - 1];
+              const NSItem& nb = items_h[qe];
+              const double per = fm + (sub >= 0 ? fs : 0.0);
+              if (nb.rz == a.rz && nb.ry == a.ry) flops_kernel += per;
+              if (nb.rz == a.rz) flops_kernel += per;
+            }
           }
           splits.push_back({i, fc, npartials, parts, sub});
           npartials += parts;
@@ -1066,31 +1101,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       std::stable_sort(work.begin(), work.end(), by_len);
       std::stable_sort(tgt_sub.begin(), tgt_sub.end(), by_len);
       std::stable_sort(low_work.begin(), low_work.end(), by_len);
-      // mode products the main kernel executes (threads over chunks of ranges, fixed order)
-      {
-        const double fm = 2.0 * std::pow(2.0 * k, 4), fs = 2.0 * std::pow((double)k, 4);
-        const size_t nck = (work.size() + 255) / 256;
-        std::vector<double> part(nck, 0.0);
-        parallel_for(nck, [&](size_t ci, unsigned) {
-          double acc = 0.0;
-          for (size_t wi = ci * 256; wi < std::min(work.size(), (ci + 1) * 256); ++wi) {
-            const TargetRange& w = work[wi];
-            int64_t prods = w.end - w.beg;
-            if (factored)
-              for (int32_t q = w.beg; q < w.end; ++q) {
-                const bool last = q + 1 == w.end;
-                const NSItem& a = items_h[q];
-                if (last || items_h[q + 1].rz != a.rz || items_h[q + 1].ry != a.ry) ++prods;
-                if (last || items_h[q + 1].rz != a.rz) ++prods;
-              }
-            else
-              prods *= 3;
-            acc += (double)prods * (fm + (w.sub >= 0 ? fs : 0.0));
-          }
-          part[ci] = acc;
-        });
-        for (double v : part) flops_kernel += v;
-      }
+      mark("target ranges");
       const size_t o_work = A1.put(work), o_sub = A1.put(tgt_sub), o_spl = A1.put(splits),
                    o_lwork = A1.put(low_work);
       const size_t o_part = A1.scratch((size_t)npartials * 9 * K3 * sizeof(double));  // (2k)^3 + k^3
