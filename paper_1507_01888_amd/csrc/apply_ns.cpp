@@ -36,23 +36,35 @@ double now_ms() {
       .count();
 }
 
+// Bit b of v (v < 2^21) moved to bit 3b, and back: the usual shift-and-mask spreading.
+inline uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffULL;
+  v = (v | v << 32) & 0x1f00000000ffffULL;
+  v = (v | v << 16) & 0x1f0000ff0000ffULL;
+  v = (v | v << 8) & 0x100f00f00f00f00fULL;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+  v = (v | v << 2) & 0x1249249249249249ULL;
+  return v;
+}
+inline uint64_t compact3(uint64_t v) {
+  v &= 0x1249249249249249ULL;
+  v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ULL;
+  v = (v ^ (v >> 4)) & 0x100f00f00f00f00fULL;
+  v = (v ^ (v >> 8)) & 0x1f0000ff0000ffULL;
+  v = (v ^ (v >> 16)) & 0x1f00000000ffffULL;
+  v = (v ^ (v >> 32)) & 0x1fffffULL;
+  return v;
+}
 void decode(uint64_t code, int n, int64_t& x, int64_t& y, int64_t& z) {
-  x = y = z = 0;
-  for (int b = 0; b < n; ++b) {
-    x |= (int64_t)((code >> (3 * b + 2)) & 1) << b;
-    y |= (int64_t)((code >> (3 * b + 1)) & 1) << b;
-    z |= (int64_t)((code >> (3 * b)) & 1) << b;
-  }
+  const uint64_t c = n >= 21 ? code : code & ((1ULL << (3 * n)) - 1);
+  x = (int64_t)compact3(c >> 2);
+  y = (int64_t)compact3(c >> 1);
+  z = (int64_t)compact3(c);
 }
 
 uint64_t encode(int n, int64_t x, int64_t y, int64_t z) {
-  uint64_t code = 0;
-  for (int b = 0; b < n; ++b) {
-    code |= (uint64_t)((x >> b) & 1) << (3 * b + 2);
-    code |= (uint64_t)((y >> b) & 1) << (3 * b + 1);
-    code |= (uint64_t)((z >> b) & 1) << (3 * b);
-  }
-  return code;
+  const uint64_t m = n >= 21 ? 0x1fffffULL : (1ULL << n) - 1;
+  return spread3((uint64_t)x & m) << 2 | spread3((uint64_t)y & m) << 1 | spread3((uint64_t)z & m);
 }
 
 int64_t find_node(const Func& f, int n, uint64_t code) {
