@@ -1101,199 +1101,212 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
 // Level-n subtraction of the factored kernel: sub_T = -sum c_mu (t_x x t_y x t_z) s_P over
 // the triples of a target, with the same grouping (step 1 per triple, step 2 per (mu, dz, dy)
 // group, step 3 per (mu, dz) group) on the k^3 scaling blocks, zero-padded to KP = 4 Q2.
-// Three waves: wave w owns z-quad w in steps 1 and 2; the nine step-3 (a-quad, b-quad) pairs
-// are split three per wave.  The work per triple is small, so the waves do not meet per
-// triple: each wave copies the three t blocks of triple it + 2 into a private LDS slot (a
-// ring of three; buffer loads that write LDS, one row of 64 granules per block) and loads
-// its s_P fragments of triple it + 2 into registers, so that two triples of work cover the
-// memory latency; the waves meet only around the step-3 exchange.
+// The work per triple is small, so the four waves of a workgroup split a target range (a
+// counter hands the ranges out) into four runs of consecutive triples, each closing its own
+// groups, and meet only to add their four results in a fixed order.  A wave computes all Q2
+// z-quads of its triples, turns the step-2 result around through an exchange region of its
+// own for step 3, and copies the s_P block and the t blocks of the next triple into the
+// other slot of a private LDS double buffer (LDS-writing buffer loads).
 template <int K>
-__global__ __launch_bounds__(192) void apply_ns_fac_sub_kernel(
+__global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
     const double* const* __restrict__ in_tab, const NSItem* __restrict__ items,
     const TargetRange* __restrict__ targets, const double* const* __restrict__ t_tab,
     const double* const* __restrict__ c_tab, double* __restrict__ partials,
-    double* __restrict__ subbuf) {
+    double* __restrict__ subbuf, const int ntargets, int* __restrict__ next_target) {
   constexpr int N = 2 * K, N3 = N * N * N, K2 = K * K, K3 = K * K * K;
   constexpr int Q2 = (K + 3) / 4, S3 = Q2 * Q2;
-  static_assert(Q2 == 3, "three waves own the three z-quads of KP = 12");
+  static_assert(Q2 == 3, "three z-quads of KP = 12");
   static_assert(K2 % 2 == 0 && K2 / 2 <= 64, "a t block fits one row of granules");
-  constexpr int S3PW = S3 / 3;
-  constexpr int TW = 3 * 128;   // one wave's slot: t_x^T, t_y^T, t_z^T, a row of 128 doubles each
-  // the three slots of the ring are separate objects, so that the compiler can tell the
-  // reads of one slot from the copies into the others
-  __shared__ __attribute__((aligned(16))) double Ts0[3 * TW];
-  __shared__ __attribute__((aligned(16))) double Ts1[3 * TW];
-  __shared__ __attribute__((aligned(16))) double Ts2[3 * TW];
-  __shared__ double Z2s[K3];   // exchange tensor, [a][b][z], unpadded
+  constexpr int SPG = K3 / 2, SPR = (SPG + 63) / 64;   // s_P granules, rows of 64
+  constexpr int SPD = 128 * SPR;                        // s_P slot (doubles)
+  constexpr int TD = 3 * 128;                           // t slot: t_x^T, t_y^T, t_z^T rows
+  constexpr int WS = 2 * SPD + 2 * TD + K3;             // one wave's LDS: two slots + exchange
+  constexpr int NCP = SPR + 3;                          // copy instructions per triple
+  static_assert(NCP < 16, "vmcnt field");
+  // the two slots are separate objects, so that the compiler can tell the reads of one
+  // from the copies into the other
+  __shared__ __attribute__((aligned(16))) double Sp0[4 * SPD];
+  __shared__ __attribute__((aligned(16))) double Sp1[4 * SPD];
+  __shared__ __attribute__((aligned(16))) double Tt0[4 * TD];
+  __shared__ __attribute__((aligned(16))) double Tt1[4 * TD];
+  __shared__ double Zx[4 * K3];                         // exchange regions, [a][b][z]
+  __shared__ int s_next;
+  static_assert(4 * WS * 8 <= 160 * 1024, "LDS");
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
-  const TargetRange tr = targets[blockIdx.x];
-  if (tr.sub < 0) return;   // level 0: no subtraction (uniform over the workgroup)
-  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
-  const double* const dT_g = t_tab[tr.fn];
-  // c_mu through the scalar cache (read-only here): the values stay off the vector-memory
-  // counter, so the copies in flight are never waited for on their account
-  const __attribute__((address_space(4))) double* __restrict__ dc =
-      (const __attribute__((address_space(4))) double*)c_tab[tr.fn];
-  // this wave's copy of the t blocks of item nx into its part of a slot (lanes past a
-  // block's K^2 / 2 granules read zeros into padding)
-  auto copy_t = [&](const NSItem nx, double* slot) {
-    double* dst = slot + wave * TW;
-    lds_copy16(dT_g + (size_t)nx.tx * K2, K2 * 8, (MRA_LDS void*)dst, 16 * lane);
-    lds_copy16(dT_g + (size_t)nx.ty * K2, K2 * 8, (MRA_LDS void*)(dst + 128), 16 * lane);
-    lds_copy16(dT_g + (size_t)nx.tz * K2, K2 * 8, (MRA_LDS void*)(dst + 256), 16 * lane);
-  };
-  // this wave's z-quad of s_P as step-1 A operands; lanes outside k^3 load an in-block
-  // element (no branch, so the loads stay in flight) and are zeroed where used
-  auto sp_ok = [&](int xs, int yt) {
-    return 4 * xs + lk < K && 4 * yt + li < K && 4 * wave + lb < K;
-  };
-  auto load_sp = [&](const NSItem nx, double (&v)[Q2][Q2]) {
-    const MRA_GLOBAL double* __restrict__ sp = in + (size_t)nx.src * K3;
+  double* const Z2s = Zx + wave * K3;
+  for (;;) {
+    // the workgroup's next target range; this wave's run of it
+    if (tid == 0) s_next = atomicAdd(next_target, 1);
+    __syncthreads();
+    const int ti = s_next;
+    __syncthreads();
+    if (ti >= ntargets) break;
+    const TargetRange tr = targets[ti];
+    if (tr.sub < 0) continue;   // level 0: no subtraction (uniform over the workgroup)
+    const int len = tr.end - tr.beg;
+    // (wave-uniform bounds, so that the item records are read through the scalar cache)
+    const int wu = __builtin_amdgcn_readfirstlane(wave);
+    const int wb = tr.beg + wu * len / 4, we = tr.beg + (wu + 1) * len / 4;
+    const double* const in_g = in_tab[tr.fn];
+    const double* const dT_g = t_tab[tr.fn];
+    const __attribute__((address_space(4))) double* __restrict__ dc =
+        (const __attribute__((address_space(4))) double*)c_tab[tr.fn];
+    // copies of item nx into this wave's part of slot (Sp, Tt)
+    auto copy = [&](const NSItem nx, double* Sp, double* Tt) {
+      double* sd = Sp + wave * SPD;
+      const double* sb = in_g + (size_t)nx.src * K3;
 #pragma unroll
-    for (int xs = 0; xs < Q2; ++xs)
+      for (int r = 0; r < SPR; ++r)
+        lds_copy16(sb, K3 * 8, (MRA_LDS void*)(sd + 128 * r), 16 * (64 * r + lane));
+      double* td = Tt + wave * TD;
+      lds_copy16(dT_g + (size_t)nx.tx * K2, K2 * 8, (MRA_LDS void*)td, 16 * lane);
+      lds_copy16(dT_g + (size_t)nx.ty * K2, K2 * 8, (MRA_LDS void*)(td + 128), 16 * lane);
+      lds_copy16(dT_g + (size_t)nx.tz * K2, K2 * 8, (MRA_LDS void*)(td + 256), 16 * lane);
+    };
+    // fragment helpers: s_P[x][y][z] as an A operand and t^T[r][c] as a B operand, zero
+    // outside k (clamped index, selected at use)
+    auto spfrag = [&](const double* S, int xs, int yt, int zq) {
+      const int x = 4 * xs + lk, y = 4 * yt + li, z = 4 * zq + lb;
+      const bool ok = x < K && y < K && z < K;
+      const double v = S[ok ? (x * K + y) * K + z : 0];
+      return ok ? v : 0.0;
+    };
+    auto tfrag = [&](const double* T, int rq, int cq) {
+      const int r = 4 * rq + lk, c = 4 * cq + li;
+      const bool ok = r < K && c < K;
+      const double v = T[ok ? r * K + c : 0];
+      return ok ? v : 0.0;
+    };
+    double d1[Q2][Q2][Q2], d2[Q2][Q2][Q2], acc[S3][Q2];   // [zq][a][b]; [pair][c]
 #pragma unroll
-      for (int yt = 0; yt < Q2; ++yt)
-        v[xs][yt] = sp[min(((4 * xs + lk) * K + 4 * yt + li) * K + 4 * wave + lb, K3 - 1)];
-  };
-  // t^T[r][c] as a B fragment, zero outside k x k
-  auto tfrag = [&](const double* T, int rq, int cq) {
-    const int r = 4 * rq + lk, c = 4 * cq + li;
-    const bool ok = r < K && c < K;
-    const double v = T[ok ? r * K + c : 0];
-    return ok ? v : 0.0;
-  };
-
-  double d1[Q2][Q2], d2[Q2][Q2], acc[S3PW][Q2];
-  double sp0[Q2][Q2], sp1[Q2][Q2], sp2[Q2][Q2];   // s_P fragments of the ring's triples
-#pragma unroll
-  for (int i = 0; i < Q2; ++i)
-#pragma unroll
-    for (int j = 0; j < Q2; ++j) d1[i][j] = d2[i][j] = sp0[i][j] = sp1[i][j] = sp2[i][j] = 0.0;
-#pragma unroll
-  for (int e = 0; e < S3PW; ++e)
-#pragma unroll
-    for (int j = 0; j < Q2; ++j) acc[e][j] = 0.0;
-
-  // item records three triples ahead; triples beg and beg + 1 are copied before the loop
-  NSItem cur{}, i1{}, i2{};
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0;   // c_mu of the ring's triples (slot-indexed like sp*)
-  if (tr.beg < tr.end) {
-    cur = items[tr.beg];
-    i1 = items[min(tr.beg + 1, tr.end - 1)];
-    i2 = items[min(tr.beg + 2, tr.end - 1)];
-    c0 = dc[cur.mu];
-    c1 = dc[i1.mu];
-    copy_t(cur, Ts0);
-    load_sp(cur, sp0);
-    copy_t(i1, Ts1);
-    load_sp(i1, sp1);
-  }
-  // one triple in ring slot S (compile-time, so that the compiler can tell the slots apart)
-  auto triple = [&](const int it, auto slot_tag, double (&spc)[Q2][Q2], double (&spf)[Q2][Q2],
-                    const double cc, double& cf) {
-    constexpr int S = decltype(slot_tag)::value;
-    const double* const Tc = (S == 0 ? Ts0 : S == 1 ? Ts1 : Ts2) + wave * TW;
-    double* const Tf = S == 0 ? Ts2 : S == 1 ? Ts0 : Ts1;   // slot of triple it + 2
-    const NSItem item = cur, nxt = i1;
-    const bool more = it + 1 < tr.end;
-    const NSItem i3 = items[min(it + 3, tr.end - 1)];   // uniform address: scalar loads
-    // copies of triple it + 2 (for the last two triples they repeat the last item:
-    // harmless copies into a slot nobody reads)
-    copy_t(i2, Tf);
-    load_sp(i2, spf);
-    cf = dc[i2.mu];
-    const bool dy_end = !more || nxt.rz != item.rz || nxt.ry != item.ry;
-    const bool dz_end = !more || nxt.rz != item.rz;
-    const double* TXs = Tc;
-    const double* TYs = Tc + 128;
-    const double* TZs = Tc + 256;
-    // step 1 (contract x) for this wave's z-quad
-#pragma unroll
-    for (int xs = 0; xs < Q2; ++xs)
-#pragma unroll
-      for (int at = 0; at < Q2; ++at) {
-        const double b = tfrag(TXs, xs, at);
-#pragma unroll
-        for (int yt = 0; yt < Q2; ++yt)
-          d1[at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(sp_ok(xs, yt) ? spc[xs][yt] : 0.0, b,
-                                                          d1[at][yt], 0, 0, 0);
-      }
-    // step 2 (contract y) at the end of a (mu, dz, dy) group
-    if (dy_end) {
-#pragma unroll
-      for (int ys = 0; ys < Q2; ++ys)
-#pragma unroll
-        for (int bt = 0; bt < Q2; ++bt) {
-          const double b = tfrag(TYs, ys, bt);
-#pragma unroll
-          for (int at = 0; at < Q2; ++at)
-            d2[at][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[at][ys], b, d2[at][bt], 0, 0, 0);
-        }
+    for (int z = 0; z < Q2; ++z)
 #pragma unroll
       for (int i = 0; i < Q2; ++i)
 #pragma unroll
-        for (int j = 0; j < Q2; ++j) d1[i][j] = 0.0;
+        for (int j = 0; j < Q2; ++j) d1[z][i][j] = d2[z][i][j] = 0.0;
+#pragma unroll
+    for (int e = 0; e < S3; ++e)
+#pragma unroll
+      for (int j = 0; j < Q2; ++j) acc[e][j] = 0.0;
+    NSItem cur{}, nxt{};
+    if (wb < we) {
+      cur = items[wb];
+      nxt = items[min(wb + 1, we - 1)];
+      copy(cur, Sp0, Tt0);
     }
-    // step 3 (contract z) at the end of a (mu, dz) group, through the exchange tensor; the
-    // waves meet before writing it (every wave is done reading the previous exchange) and
-    // after (it is complete)
-    if (dz_end) {
-      double tz[Q2][Q2];
+    auto triple = [&](const int it, auto buf_tag) {
+      constexpr int buf = decltype(buf_tag)::value;
+      const double* const S = (buf == 0 ? Sp0 : Sp1) + wave * SPD;
+      const double* const T = (buf == 0 ? Tt0 : Tt1) + wave * TD;
+      const NSItem item = cur;
+      const bool more = it + 1 < we;
+      const NSItem nn = items[min(it + 2, we - 1)];   // uniform address: scalar loads
+      const double cmu = dc[item.mu];
+      // copy of the next triple (for the last one, a harmless repeat into the free slot),
+      // then wait for this triple's copies: all but the NCP just issued have landed
+      copy(nxt, buf == 0 ? Sp1 : Sp0, buf == 0 ? Tt1 : Tt0);
+      __builtin_amdgcn_s_waitcnt(0x0F70 | NCP);   // vmcnt(NCP)
+      const bool dy_end = !more || nxt.rz != item.rz || nxt.ry != item.ry;
+      const bool dz_end = !more || nxt.rz != item.rz;
+      // step 1 (contract x) for the three z-quads
 #pragma unroll
-      for (int zs = 0; zs < Q2; ++zs)
+      for (int xs = 0; xs < Q2; ++xs) {
+        double tx[Q2];
 #pragma unroll
-        for (int ct = 0; ct < Q2; ++ct) tz[zs][ct] = -cc * tfrag(TZs, zs, ct);
-      lds_barrier();
+        for (int at = 0; at < Q2; ++at) tx[at] = tfrag(T, xs, at);
 #pragma unroll
-      for (int at = 0; at < Q2; ++at)
+        for (int zq = 0; zq < Q2; ++zq)
 #pragma unroll
-        for (int bt = 0; bt < Q2; ++bt) {
-          const int a = 4 * at + lk, b = 4 * bt + li, z = 4 * wave + lb;
-          if (a < K && b < K && z < K) Z2s[(a * K + b) * K + z] = d2[at][bt];
-          d2[at][bt] = 0.0;
+          for (int yt = 0; yt < Q2; ++yt) {
+            const double a = spfrag(S, xs, yt, zq);
+#pragma unroll
+            for (int at = 0; at < Q2; ++at)
+              d1[zq][at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, tx[at], d1[zq][at][yt], 0, 0, 0);
+          }
+      }
+      // step 2 (contract y) at the end of a (mu, dz, dy) group
+      if (dy_end) {
+#pragma unroll
+        for (int ys = 0; ys < Q2; ++ys) {
+          double ty[Q2];
+#pragma unroll
+          for (int bt = 0; bt < Q2; ++bt) ty[bt] = tfrag(T + 128, ys, bt);
+#pragma unroll
+          for (int zq = 0; zq < Q2; ++zq)
+#pragma unroll
+            for (int at = 0; at < Q2; ++at)
+#pragma unroll
+              for (int bt = 0; bt < Q2; ++bt)
+                d2[zq][at][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[zq][at][ys], ty[bt],
+                                                                    d2[zq][at][bt], 0, 0, 0);
         }
-      lds_barrier();
 #pragma unroll
-      for (int e = 0; e < S3PW; ++e) {
-        const int p = wave + 3 * e;
-        const int at3 = p / Q2, bt3 = p % Q2;
+        for (int z = 0; z < Q2; ++z)
 #pragma unroll
-        for (int zs = 0; zs < Q2; ++zs) {
-          const int a = 4 * at3 + lb, b = 4 * bt3 + li, z = 4 * zs + lk;
-          const bool ok = a < K && b < K && z < K;
-          const double t = Z2s[ok ? (a * K + b) * K + z : 0];
-          const double v = ok ? t : 0.0;
+          for (int i = 0; i < Q2; ++i)
 #pragma unroll
-          for (int ct = 0; ct < Q2; ++ct)
-            acc[e][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(v, tz[zs][ct], acc[e][ct], 0, 0, 0);
+            for (int j = 0; j < Q2; ++j) d1[z][i][j] = 0.0;
+      }
+      // step 3 (contract z) at the end of a (mu, dz) group, through this wave's exchange
+      if (dz_end) {
+#pragma unroll
+        for (int zq = 0; zq < Q2; ++zq)
+#pragma unroll
+          for (int at = 0; at < Q2; ++at)
+#pragma unroll
+            for (int bt = 0; bt < Q2; ++bt) {
+              const int a = 4 * at + lk, b = 4 * bt + li, z = 4 * zq + lb;
+              if (a < K && b < K && z < K) Z2s[(a * K + b) * K + z] = d2[zq][at][bt];
+              d2[zq][at][bt] = 0.0;
+            }
+        double tz[Q2][Q2];
+#pragma unroll
+        for (int zs = 0; zs < Q2; ++zs)
+#pragma unroll
+          for (int ct = 0; ct < Q2; ++ct) tz[zs][ct] = -cmu * tfrag(T + 256, zs, ct);
+#pragma unroll
+        for (int p = 0; p < S3; ++p) {
+          const int at3 = p / Q2, bt3 = p % Q2;
+#pragma unroll
+          for (int zs = 0; zs < Q2; ++zs) {
+            const int a = 4 * at3 + lb, b = 4 * bt3 + li, z = 4 * zs + lk;
+            const bool ok = a < K && b < K && z < K;
+            const double t = Z2s[ok ? (a * K + b) * K + z : 0];
+            const double v = ok ? t : 0.0;
+#pragma unroll
+            for (int ct = 0; ct < Q2; ++ct)
+              acc[p][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(v, tz[zs][ct], acc[p][ct], 0, 0, 0);
+          }
         }
       }
+      cur = nxt;
+      nxt = nn;
+    };
+    for (int it = wb; it < we; it += 2) {
+      triple(it, BufTag<0>{});
+      if (it + 1 < we) triple(it + 1, BufTag<1>{});
     }
-    cur = i1;
-    i1 = i2;
-    i2 = i3;
-  };
-  for (int it = tr.beg; it < tr.end; it += 3) {
-    triple(it, BufTag<0>{}, sp0, sp2, c0, c2);
-    if (it + 1 < tr.end) triple(it + 1, BufTag<1>{}, sp1, sp0, c1, c0);
-    if (it + 2 < tr.end) triple(it + 2, BufTag<2>{}, sp2, sp1, c2, c1);
-  }
+    // the last triple's copy into the free slot has landed before the slots are reused
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    // this wave's result into its exchange region (after its own last step-3 reads, in
+    // order), then the four results added in wave order
 #pragma unroll
-  for (int e = 0; e < S3PW; ++e) {
-    const int p = wave + 3 * e;
-    const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + lk;
+    for (int p = 0; p < S3; ++p) {
+      const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + lk;
 #pragma unroll
-    for (int ct = 0; ct < Q2; ++ct) {
-      const int c = 4 * ct + li;
-      if (a < K && b < K && c < K) {
-        if (tr.partial >= 0)
-          partials[(size_t)tr.partial * (N3 + K3) + N3 + (a * K + b) * K + c] = acc[e][ct];
-        else
-          subbuf[(size_t)tr.sub * K3 + (a * K + b) * K + c] = acc[e][ct];
+      for (int ct = 0; ct < Q2; ++ct) {
+        const int c = 4 * ct + li;
+        if (a < K && b < K && c < K) Z2s[(a * K + b) * K + c] = acc[p][ct];
       }
     }
+    lds_barrier();
+    double* const dst = tr.partial >= 0 ? partials + (size_t)tr.partial * (N3 + K3) + N3
+                                        : subbuf + (size_t)tr.sub * K3;
+    for (int e = tid; e < K3; e += 256)
+      dst[e] = ((Zx[e] + Zx[K3 + e]) + Zx[2 * K3 + e]) + Zx[3 * K3 + e];
+    // (the next range's first barrier keeps the exchange regions until every wave has read)
   }
 }
 
@@ -2418,8 +2431,12 @@ void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
                        0, s, in_tab, out_tab, items, targets, r_tab, t_tab, c_tab, partials,
                        subbuf, ntargets, counter);
     hip_check(hipGetLastError(), "apply_ns_fac_kernel");
-    hipLaunchKernelGGL(apply_ns_fac_sub_kernel<10>, dim3(ntargets), dim3(192), 0, s, in_tab,
-                       items, targets, t_tab, c_tab, partials, subbuf);
+    // one persistent workgroup per CU (the kernel's LDS allows one), target ranges from a
+    // second counter
+    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, counter + 1, 0);
+    hipLaunchKernelGGL(apply_ns_fac_sub_kernel<10>, dim3(std::min(ntargets, device_cus())),
+                       dim3(256), 0, s, in_tab, items, targets, t_tab, c_tab, partials, subbuf,
+                       ntargets, counter + 1);
   } else if (k == 12) {
     hipLaunchKernelGGL(apply_ns_own_kernel<12>, dim3(ntargets), dim3(256), 0, s, in_tab,
                        out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
