@@ -1173,6 +1173,12 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
       const double v = S[ok ? (x * K + y) * K + z : 0];
       return ok ? v : 0.0;
     };
+    // s_P fragment without zeroing: the lanes outside k read an element of the block
+    // (finite), which the zero rows and columns of the t fragments cancel or which lands in
+    // padding that is never stored
+    auto spraw = [&](const double* S, int xs, int yt, int zq) {
+      return S[min(((4 * xs + lk) * K + 4 * yt + li) * K + 4 * zq + lb, K3 - 1)];
+    };
     auto tfrag = [&](const double* T, int rq, int cq) {
       const int r = 4 * rq + lk, c = 4 * cq + li;
       const bool ok = r < K && c < K;
@@ -1210,38 +1216,52 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
       __builtin_amdgcn_s_waitcnt(0x0F70 | NCP);   // vmcnt(NCP)
       const bool dy_end = !more || nxt.rz != item.rz || nxt.ry != item.ry;
       const bool dz_end = !more || nxt.rz != item.rz;
-      // step 1 (contract x) for the three z-quads
+      // step 1 (contract x) for the three z-quads, the fragments of x-quad xs + 1 read
+      // while those of xs are used (and the t_y fragments of step 2 during the last)
+      double fa[2][Q2][Q2], fb[2][Q2], ty[Q2][Q2];
+      auto load1 = [&](int xs, double (&fs)[Q2][Q2], double (&ft)[Q2]) {
 #pragma unroll
-      for (int xs = 0; xs < Q2; ++xs) {
-        double tx[Q2];
-#pragma unroll
-        for (int at = 0; at < Q2; ++at) tx[at] = tfrag(T, xs, at);
+        for (int at = 0; at < Q2; ++at) ft[at] = tfrag(T, xs, at);
 #pragma unroll
         for (int zq = 0; zq < Q2; ++zq)
 #pragma unroll
-          for (int yt = 0; yt < Q2; ++yt) {
-            const double a = spfrag(S, xs, yt, zq);
+          for (int yt = 0; yt < Q2; ++yt) fs[zq][yt] = spraw(S, xs, yt, zq);
+      };
+      load1(0, fa[0], fb[0]);
+#pragma unroll
+      for (int xs = 0; xs < Q2; ++xs) {
+        const int bb = xs & 1;
+        if (xs + 1 < Q2) {
+          load1(xs + 1, fa[bb ^ 1], fb[bb ^ 1]);
+        } else {
+#pragma unroll
+          for (int ys = 0; ys < Q2; ++ys)
+#pragma unroll
+            for (int bt = 0; bt < Q2; ++bt) ty[ys][bt] = tfrag(T + 128, ys, bt);
+        }
+#pragma unroll
+        for (int zq = 0; zq < Q2; ++zq)
+#pragma unroll
+          for (int yt = 0; yt < Q2; ++yt)
 #pragma unroll
             for (int at = 0; at < Q2; ++at)
-              d1[zq][at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, tx[at], d1[zq][at][yt], 0, 0, 0);
-          }
+              d1[zq][at][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[bb][zq][yt], fb[bb][at],
+                                                                  d1[zq][at][yt], 0, 0, 0);
+        interleave_mem<12, 0, 0, 2>();
+        __builtin_amdgcn_sched_barrier(0);
       }
       // step 2 (contract y) at the end of a (mu, dz, dy) group
       if (dy_end) {
 #pragma unroll
-        for (int ys = 0; ys < Q2; ++ys) {
-          double ty[Q2];
-#pragma unroll
-          for (int bt = 0; bt < Q2; ++bt) ty[bt] = tfrag(T + 128, ys, bt);
+        for (int ys = 0; ys < Q2; ++ys)
 #pragma unroll
           for (int zq = 0; zq < Q2; ++zq)
 #pragma unroll
             for (int at = 0; at < Q2; ++at)
 #pragma unroll
               for (int bt = 0; bt < Q2; ++bt)
-                d2[zq][at][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[zq][at][ys], ty[bt],
+                d2[zq][at][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[zq][at][ys], ty[ys][bt],
                                                                     d2[zq][at][bt], 0, 0, 0);
-        }
 #pragma unroll
         for (int z = 0; z < Q2; ++z)
 #pragma unroll
@@ -1250,7 +1270,15 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
             for (int j = 0; j < Q2; ++j) d1[z][i][j] = 0.0;
       }
       // step 3 (contract z) at the end of a (mu, dz) group, through this wave's exchange
+      // (every element of it is written, so that the padding lanes read finite values that
+      // the zero rows of t_z cancel); the exchange reads of pair p + 1 are issued while
+      // pair p is used
       if (dz_end) {
+        double tz[Q2][Q2];
+#pragma unroll
+        for (int zs = 0; zs < Q2; ++zs)
+#pragma unroll
+          for (int ct = 0; ct < Q2; ++ct) tz[zs][ct] = tfrag(T + 256, zs, ct);
 #pragma unroll
         for (int zq = 0; zq < Q2; ++zq)
 #pragma unroll
@@ -1261,24 +1289,29 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
               if (a < K && b < K && z < K) Z2s[(a * K + b) * K + z] = d2[zq][at][bt];
               d2[zq][at][bt] = 0.0;
             }
-        double tz[Q2][Q2];
 #pragma unroll
         for (int zs = 0; zs < Q2; ++zs)
 #pragma unroll
-          for (int ct = 0; ct < Q2; ++ct) tz[zs][ct] = -cmu * tfrag(T + 256, zs, ct);
+          for (int ct = 0; ct < Q2; ++ct) tz[zs][ct] *= -cmu;
+        double zr[2][Q2];
+        auto load3 = [&](int p, double (&v)[Q2]) {
+          const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + li;
+#pragma unroll
+          for (int zs = 0; zs < Q2; ++zs)
+            v[zs] = Z2s[min((a * K + b) * K + 4 * zs + lk, K3 - 1)];
+        };
+        load3(0, zr[0]);
 #pragma unroll
         for (int p = 0; p < S3; ++p) {
-          const int at3 = p / Q2, bt3 = p % Q2;
+          const int bb = p & 1;
+          if (p + 1 < S3) load3(p + 1, zr[bb ^ 1]);
 #pragma unroll
-          for (int zs = 0; zs < Q2; ++zs) {
-            const int a = 4 * at3 + lb, b = 4 * bt3 + li, z = 4 * zs + lk;
-            const bool ok = a < K && b < K && z < K;
-            const double t = Z2s[ok ? (a * K + b) * K + z : 0];
-            const double v = ok ? t : 0.0;
+          for (int zs = 0; zs < Q2; ++zs)
 #pragma unroll
             for (int ct = 0; ct < Q2; ++ct)
-              acc[p][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(v, tz[zs][ct], acc[p][ct], 0, 0, 0);
-          }
+              acc[p][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(zr[bb][zs], tz[zs][ct], acc[p][ct], 0, 0, 0);
+          interleave_mem<3, 0, 0, 3>();
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
       cur = nxt;
