@@ -1120,7 +1120,13 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
   constexpr int SPG = K3 / 2, SPR = (SPG + 63) / 64;   // s_P granules, rows of 64
   constexpr int SPD = 128 * SPR;                        // s_P slot (doubles)
   constexpr int TD = 3 * 128;                           // t slot: t_x^T, t_y^T, t_z^T rows
-  constexpr int WS = 2 * SPD + 2 * TD + K3;             // one wave's LDS: two slots + exchange
+  // exchange region [a][b][z] over the padded 4 Q2 cube with strides (ZA, ZB, 1): the
+  // step-3 writes and reads then need no masks, and ZB = 4 Q2, ZA = 1 mod 32 spread both
+  // access patterns over distinct banks
+  constexpr int ZB = 4 * Q2, ZA = ((ZB * (ZB - 1) + ZB - 1) / 32 + 1) * 32 + 1;
+  constexpr int ZW = (ZB - 1) * ZA + (ZB - 1) * ZB + ZB;   // doubles per wave (>= K3)
+  static_assert(ZW >= K3 && ZA >= ZB * ZB, "exchange layout");
+  constexpr int WS = 2 * SPD + 2 * TD + ZW;             // one wave's LDS: two slots + exchange
   constexpr int NCP = SPR + 3;                          // copy instructions per triple
   static_assert(NCP < 16, "vmcnt field");
   // the two slots are separate objects, so that the compiler can tell the reads of one
@@ -1129,13 +1135,13 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
   __shared__ __attribute__((aligned(16))) double Sp1[4 * SPD];
   __shared__ __attribute__((aligned(16))) double Tt0[4 * TD];
   __shared__ __attribute__((aligned(16))) double Tt1[4 * TD];
-  __shared__ double Zx[4 * K3];                         // exchange regions, [a][b][z]
+  __shared__ double Zx[4 * ZW];                         // exchange regions
   __shared__ int s_next;
   static_assert(4 * WS * 8 <= 160 * 1024, "LDS");
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
-  double* const Z2s = Zx + wave * K3;
+  double* const Z2s = Zx + wave * ZW;
   for (;;) {
     // the workgroup's next target range; this wave's run of it
     if (tid == 0) s_next = atomicAdd(next_target, 1);
@@ -1270,9 +1276,9 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
             for (int j = 0; j < Q2; ++j) d1[z][i][j] = 0.0;
       }
       // step 3 (contract z) at the end of a (mu, dz) group, through this wave's exchange
-      // (every element of it is written, so that the padding lanes read finite values that
-      // the zero rows of t_z cancel); the exchange reads of pair p + 1 are issued while
-      // pair p is used
+      // (the whole padded cube is written, so that the padding lanes read finite values
+      // that the zero rows of t_z cancel or that land in padding); the exchange reads of
+      // pair p + 1 are issued while pair p is used
       if (dz_end) {
         double tz[Q2][Q2];
 #pragma unroll
@@ -1286,7 +1292,7 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
 #pragma unroll
             for (int bt = 0; bt < Q2; ++bt) {
               const int a = 4 * at + lk, b = 4 * bt + li, z = 4 * zq + lb;
-              if (a < K && b < K && z < K) Z2s[(a * K + b) * K + z] = d2[zq][at][bt];
+              Z2s[a * ZA + b * ZB + z] = d2[zq][at][bt];
               d2[zq][at][bt] = 0.0;
             }
 #pragma unroll
@@ -1298,7 +1304,7 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
           const int a = 4 * (p / Q2) + lb, b = 4 * (p % Q2) + li;
 #pragma unroll
           for (int zs = 0; zs < Q2; ++zs)
-            v[zs] = Z2s[min((a * K + b) * K + 4 * zs + lk, K3 - 1)];
+            v[zs] = Z2s[a * ZA + b * ZB + 4 * zs + lk];
         };
         load3(0, zr[0]);
 #pragma unroll
@@ -1338,7 +1344,7 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
     double* const dst = tr.partial >= 0 ? partials + (size_t)tr.partial * (N3 + K3) + N3
                                         : subbuf + (size_t)tr.sub * K3;
     for (int e = tid; e < K3; e += 256)
-      dst[e] = ((Zx[e] + Zx[K3 + e]) + Zx[2 * K3 + e]) + Zx[3 * K3 + e];
+      dst[e] = ((Zx[e] + Zx[ZW + e]) + Zx[2 * ZW + e]) + Zx[3 * ZW + e];
     // (the next range's first barrier keeps the exchange regions until every wave has read)
   }
 }
