@@ -226,8 +226,13 @@ class Context:
                 except Exception:  # noqa: BLE001 - reported to the library as NULL
                     return None
 
+            delete = torch.cuda.caching_allocator_delete
+
             def _free(ptr, user):
-                torch.cuda.caching_allocator_delete(ptr)
+                try:
+                    delete(ptr)
+                except Exception:  # noqa: BLE001 - torch already torn down at exit
+                    pass
 
             self._alloc = ALLOC_FN(_alloc)
             self._free = FREE_FN(_free)

@@ -448,6 +448,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
                              const std::vector<Func*>& outs) {
   const int nf = (int)funcs.size();
   if (nf == 0) return;
+  const double t_entry = now_ms();
   for (Func* f : funcs)
     if (f->interior.empty())
       fail(MRA_E_INVALID, "non-standard apply needs a refined root (project with initial_level >= 1)");
@@ -485,6 +486,9 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   const size_t o_fu = A0.put(fu_refs);
   const size_t o_bn2 = A0.scratch(std::max<size_t>(1, fu_refs.size()) * sizeof(double));
   const size_t o_mir = A0.scratch(tiers ? fu_refs.size() * XB * sizeof(uint16_t) : 0);
+  // pinned host landing place of the box norms, so that their copy is asynchronous (a copy
+  // into pageable memory would hold the host until the filter-up is done)
+  const size_t o_bn2h = A0.reserve(std::max<size_t>(1, fu_refs.size()) * sizeof(double));
   A0.commit();
   const double* h0p = A0.at<double>(o_h0);
   const double* h1p = A0.at<double>(o_h1);
@@ -498,19 +502,23 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       launch_filter_up(k, in_tab_d, fu_d + b, (int)(e - b), h0p, h1p, bn2_d + b,
                        tiers ? mirror_d + (size_t)b * XB : nullptr, ctx->stream);
   }
-  std::vector<double> bn2_all(fu_refs.size());
+  const double* const bn2_all = A0.host_at<double>(o_bn2h);   // valid after the sync below
   if (!fu_refs.empty())
-    hip_check(hipMemcpyAsync(bn2_all.data(), bn2_d, fu_refs.size() * sizeof(double),
+    hip_check(hipMemcpyAsync(A0.host_at<double>(o_bn2h), bn2_d, fu_refs.size() * sizeof(double),
                              hipMemcpyDeviceToHost, ctx->stream),
               "hipMemcpyAsync D2H");
   hip_check(hipEventRecord(ctx->ev[1], ctx->stream), "event");
   // wake the planner's thread pool while the device runs the filter-up: workers that went
   // to sleep since the last apply would otherwise be woken by the first planning loop
+  const double t_filter_issued = now_ms();
   Pool::get().run(Pool::get().workers(), [](size_t, unsigned) {});
   ctx->sync();
   for (Func* f : funcs) f->interior_valid = true;
   double t_plan0 = now_ms();
   const bool timing = std::getenv("MRA_TIMING") != nullptr;
+  if (timing)
+    std::fprintf(stderr, "[mra] %-28s %8.3f ms\n[mra] %-28s %8.3f ms\n", "filter issued",
+                 t_filter_issued - t_entry, "filter wait", t_plan0 - t_filter_issued);
   double t_mark = t_plan0;
   auto mark = [&](const char* what) {
     if (!timing) return;
@@ -1159,7 +1167,11 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
     }
     hip_check(hipEventRecord(ES[1], ctx->stream), "event");
   }
+  const double t_issued = now_ms();
   ctx->sync();
+  if (timing)
+    std::fprintf(stderr, "[mra] %-28s %8.3f ms\n[mra] %-28s %8.3f ms\n", "after plan to last launch",
+                 t_issued - t_mark, "final wait", now_ms() - t_issued);
   for (int i = 0; i < nf; ++i) plans[i].out->interior_valid = false;
 
   float ms_f = 0;
@@ -1197,6 +1209,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   st.flops_kernel = flops_kernel;
   st.eta_low = eta_low;
   st.ms_low_kernel = any_low ? ms_low : 0.0;
+  if (timing) std::fprintf(stderr, "[mra] %-28s %8.3f ms\n", "host total", now_ms() - t_entry);
 }
 
 // Filter-up of one function (used by mra_inner); returns nothing but marks it valid.

@@ -44,9 +44,9 @@ __global__ void zero_kernel(double* __restrict__ p, size_t n) {
   for (; i < n; i += stride) p[i] = 0.0;
 }
 
-// Sets the work counter of a persistent kernel (one lane, vector store).
-__global__ void set_counter_kernel(int* __restrict__ c, int v) {
-  if (threadIdx.x == 0) *as_global(c) = v;
+// Sets the work counters c[0 .. n) of persistent kernels to v (vector stores, n <= 64).
+__global__ void set_counter_kernel(int* __restrict__ c, int n, int v) {
+  if ((int)threadIdx.x < n) as_global(c)[threadIdx.x] = v;
 }
 
 // Clears arrays tab[y][0 .. len[y]) for every y = blockIdx.y.
@@ -2465,14 +2465,14 @@ void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
                        out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
   } else if (k == 10) {
     // one persistent workgroup per CU (the kernel's LDS allows one), ranges from a counter
-    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, counter, 0);
+    // (one for each of the two kernels, both cleared here)
+    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, counter, 2, 0);
     hipLaunchKernelGGL(apply_ns_fac_kernel<10>, dim3(std::min(ntargets, device_cus())), dim3(256),
                        0, s, in_tab, out_tab, items, targets, r_tab, t_tab, c_tab, partials,
                        subbuf, ntargets, counter);
     hip_check(hipGetLastError(), "apply_ns_fac_kernel");
-    // one persistent workgroup per CU (the kernel's LDS allows one), target ranges from a
+    // one persistent workgroup per CU (the kernel's LDS allows one), target ranges from the
     // second counter
-    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, counter + 1, 0);
     hipLaunchKernelGGL(apply_ns_fac_sub_kernel<10>, dim3(std::min(ntargets, device_cus())),
                        dim3(256), 0, s, in_tab, items, targets, t_tab, c_tab, partials, subbuf,
                        ntargets, counter + 1);
