@@ -86,7 +86,8 @@ __global__ __launch_bounds__(256) void filter_up_kernel(
   constexpr int UP = (N + 7) / 8 * 8;
   __shared__ double T1[N * N * KP1];   // [X][Y][m]
   __shared__ double T2[N * K * KP1];   // [X][j][m]
-  __shared__ double H[K * N];
+  __shared__ __attribute__((aligned(16))) double H[K * N];    // [i][X]
+  __shared__ __attribute__((aligned(16))) double HT[N * K];   // [X][i]
   __shared__ double red[256];
   const int tid = threadIdx.x;
   const NodeRef ref = refs[blockIdx.x];
@@ -94,7 +95,9 @@ __global__ __launch_bounds__(256) void filter_up_kernel(
   MRA_GLOBAL double* __restrict__ coeff = as_global(tab[ref.fn]);
   for (int e = tid; e < K * N; e += 256) {
     int i = e / N, X = e % N;
-    H[e] = X < K ? h0[i * K + X] : h1[i * K + X - K];
+    const double h = X < K ? h0[i * K + X] : h1[i * K + X - K];
+    H[e] = h;
+    HT[X * K + i] = h;
   }
   __syncthreads();
   double sq = 0.0;
@@ -114,8 +117,9 @@ __global__ __launch_bounds__(256) void filter_up_kernel(
     for (int z = N; z < UP; ++z) row[z] = 0.0;
 #pragma unroll
     for (int z = 0; z < K; ++z) sq += row[z] * row[z] + row[K + z] * row[K + z];
-    // one output at a time: the row stays in registers, H is read from LDS (broadcast)
-#pragma unroll 1
+    // the row stays in registers, H is read from LDS (broadcast); two of the K sums at a
+    // time, so that their LDS reads and products overlap
+#pragma unroll 2
     for (int m = 0; m < K; ++m) {
       double t = 0.0;
 #pragma unroll
@@ -148,11 +152,11 @@ __global__ __launch_bounds__(256) void filter_up_kernel(
     double t[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) t[j] = 0.0;
-#pragma unroll 1
+#pragma unroll 4
     for (int Y = 0; Y < N; ++Y) {
       const double v = T1[(X * N + Y) * KP1 + m];
 #pragma unroll
-      for (int j = 0; j < K; ++j) t[j] += H[j * N + Y] * v;
+      for (int j = 0; j < K; ++j) t[j] += HT[Y * K + j] * v;
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) T2[(X * K + j) * KP1 + m] = t[j];
@@ -164,11 +168,11 @@ __global__ __launch_bounds__(256) void filter_up_kernel(
     double t[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) t[i] = 0.0;
-#pragma unroll 1
+#pragma unroll 4
     for (int X = 0; X < N; ++X) {
       const double v = T2[(X * K + j) * KP1 + m];
 #pragma unroll
-      for (int i = 0; i < K; ++i) t[i] += H[i * N + X] * v;
+      for (int i = 0; i < K; ++i) t[i] += HT[X * K + i] * v;
     }
 #pragma unroll
     for (int i = 0; i < K; ++i) coeff[(size_t)node * K3 + (i * K + j) * K + m] = t[i];
