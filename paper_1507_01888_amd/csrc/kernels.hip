@@ -796,8 +796,8 @@ struct BufTag {
 // s_P is factored the same way by apply_ns_fac_sub_kernel.  The lane mapping of each step
 // is that of apply_ns_mfma_kernel (block index = z inside a z-quad for steps 1 and 2).
 // The children block of the next triple and its operator blocks are copied into the other
-// half of two LDS buffers (16-byte granules through registers) while the current triple
-// runs; the source block is stored row-major [x][y][z], whose row stride 2k = 20 (= 4 mod
+// half of two LDS buffers (16-byte buffer loads that write LDS directly) while the current
+// triple runs; the source block is stored row-major [x][y][z], whose row stride 2k = 20 (= 4 mod
 // 16) keeps the step-1 reads bank-conflict free.  The buffer a triple has finished with
 // holds the exchange tensors of step 3.  One wave per SIMD hides no latency by switching
 // waves, so each step is software-pipelined by hand (operands of the next group read into
