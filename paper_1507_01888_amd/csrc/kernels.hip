@@ -1146,6 +1146,18 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
   double* const Z2s = Zx + wave * ZW;
+  // LDS layout of an s_P slot: granule zp (two doubles along z) of row (x, y) goes to
+  // granule (zp + y) mod K/2 of that row, so that the four y rows of a fragment read fall
+  // on distinct banks; this lane's copy offsets (bytes into the block; past the end for
+  // the padding granules, which read zeros)
+  static_assert(K % 2 == 0, "rows of whole granules");
+  constexpr int RG = K / 2;   // granules per (x, y) row
+  int spoff[SPR];
+#pragma unroll
+  for (int r = 0; r < SPR; ++r) {
+    const int j = 64 * r + lane, row = j / RG, y = row % K;
+    spoff[r] = j < SPG ? 16 * (row * RG + (j % RG + 2 * RG - y) % RG) : 8 * K3;
+  }
   for (;;) {
     // the workgroup's next target range; this wave's run of it
     if (tid == 0) s_next = atomicAdd(next_target, 1);
@@ -1169,26 +1181,22 @@ __global__ __launch_bounds__(256) void apply_ns_fac_sub_kernel(
       const double* sb = in_g + (size_t)nx.src * K3;
 #pragma unroll
       for (int r = 0; r < SPR; ++r)
-        lds_copy16(sb, K3 * 8, (MRA_LDS void*)(sd + 128 * r), 16 * (64 * r + lane));
+        lds_copy16(sb, K3 * 8, (MRA_LDS void*)(sd + 128 * r), spoff[r]);
       double* td = Tt + wave * TD;
       lds_copy16(dT_g + (size_t)nx.tx * K2, K2 * 8, (MRA_LDS void*)td, 16 * lane);
       lds_copy16(dT_g + (size_t)nx.ty * K2, K2 * 8, (MRA_LDS void*)(td + 128), 16 * lane);
       lds_copy16(dT_g + (size_t)nx.tz * K2, K2 * 8, (MRA_LDS void*)(td + 256), 16 * lane);
     };
-    // fragment helpers: s_P[x][y][z] as an A operand and t^T[r][c] as a B operand, zero
-    // outside k (clamped index, selected at use)
-    auto spfrag = [&](const double* S, int xs, int yt, int zq) {
+    // s_P[x][y][z] as an A operand, without zeroing: the lanes outside k read an element
+    // of the block (finite), which the zero rows and columns of the t fragments cancel or
+    // which lands in padding that is never stored
+    auto spraw = [&](const double* S, int xs, int yt, int zq) {
       const int x = 4 * xs + lk, y = 4 * yt + li, z = 4 * zq + lb;
       const bool ok = x < K && y < K && z < K;
-      const double v = S[ok ? (x * K + y) * K + z : 0];
-      return ok ? v : 0.0;
+      const int row = x * K + y;
+      return S[ok ? 2 * (row * RG + ((z >> 1) + y) % RG) + (z & 1) : 0];
     };
-    // s_P fragment without zeroing: the lanes outside k read an element of the block
-    // (finite), which the zero rows and columns of the t fragments cancel or which lands in
-    // padding that is never stored
-    auto spraw = [&](const double* S, int xs, int yt, int zq) {
-      return S[min(((4 * xs + lk) * K + 4 * yt + li) * K + 4 * zq + lb, K3 - 1)];
-    };
+    // t^T[r][c] as a B operand, zero outside k (clamped index, selected at use)
     auto tfrag = [&](const double* T, int rq, int cq) {
       const int r = 4 * rq + lk, c = 4 * cq + li;
       const bool ok = r < K && c < K;
