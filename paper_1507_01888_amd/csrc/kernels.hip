@@ -1447,11 +1447,12 @@ __global__ __launch_bounds__(round64(K * K)) void apply_std_kernel(
 }
 
 // --------------------------------------------------------------------------- sum-down
-// One workgroup of 256 threads per interior output box: three mode products with the
-// unfilter matrix [h0 | h1]^T, each thread owning output columns; the contraction loops stay
-// rolled so that a thread keeps one column (2k doubles) in registers, not the matrix.
+// One workgroup of 512 threads per interior output box (for k <= 11 the (2k)^2 output
+// columns of the last product in one pass): three mode products with the unfilter matrix
+// [h0 | h1]^T, each thread owning output columns; the contraction loops stay rolled so that
+// a thread keeps one column (2k doubles) in registers, not the matrix.
 template <int K>
-__global__ __launch_bounds__(256) void sum_down_kernel(
+__global__ __launch_bounds__(512) void sum_down_kernel(
     double* const* __restrict__ tab, const NodeRef* __restrict__ refs,
     const double* __restrict__ subbuf, const double* __restrict__ h0,
     const double* __restrict__ h1) {
@@ -1463,16 +1464,16 @@ __global__ __launch_bounds__(256) void sum_down_kernel(
   const NodeRef ref = refs[blockIdx.x];
   const int node = ref.node, fc = ref.fchild;
   MRA_GLOBAL double* __restrict__ coeff = as_global(tab[ref.fn]);
-  for (int e = tid; e < K * N; e += 256) {
+  for (int e = tid; e < K * N; e += 512) {
     int i = e / N, X = e % N;
     H[e] = X < K ? h0[i * K + X] : h1[i * K + X - K];
   }
   const MRA_GLOBAL double* __restrict__ V = coeff + (size_t)node * K3;
   const double* __restrict__ VS = ref.sub >= 0 ? subbuf + (size_t)ref.sub * K3 : nullptr;
   double* Vs = T2;   // the box's coefficients (plus its level-n part), until phase 2
-  for (int e = tid; e < K3; e += 256) Vs[e] = VS ? V[e] + VS[e] : V[e];
+  for (int e = tid; e < K3; e += 512) Vs[e] = VS ? V[e] + VS[e] : V[e];
   __syncthreads();
-  for (int col = tid; col < K * K; col += 256) {  // T1[i][j][Z] = sum_m H[m][Z] V[i][j][m]
+  for (int col = tid; col < K * K; col += 512) {  // T1[i][j][Z] = sum_m H[m][Z] V[i][j][m]
     const int i = col / K, j = col % K;
     double t[N];
 #pragma unroll
@@ -1487,7 +1488,7 @@ __global__ __launch_bounds__(256) void sum_down_kernel(
     for (int Z = 0; Z < N; ++Z) T1[(i * K + j) * ZP + Z] = t[Z];
   }
   __syncthreads();
-  for (int col = tid; col < K * N; col += 256) {  // T2[i][Y][Z] = sum_j H[j][Y] T1[i][j][Z]
+  for (int col = tid; col < K * N; col += 512) {  // T2[i][Y][Z] = sum_j H[j][Y] T1[i][j][Z]
     const int i = col / N, Z = col % N;
     double t[N];
 #pragma unroll
@@ -1502,7 +1503,7 @@ __global__ __launch_bounds__(256) void sum_down_kernel(
     for (int Y = 0; Y < N; ++Y) T2[(i * N + Y) * ZP + Z] = t[Y];
   }
   __syncthreads();
-  for (int col = tid; col < N * N; col += 256) {  // child[X][Y][Z] += sum_i H[i][X] T2[i][Y][Z]
+  for (int col = tid; col < N * N; col += 512) {  // child[X][Y][Z] += sum_i H[i][X] T2[i][Y][Z]
     const int Y = col / N, Z = col % N;
     const int cy = Y / K, j = Y % K, cz = Z / K, m = Z % K;
     double old[N], t[N];   // the children's values are loaded first, added after the sum
@@ -2525,7 +2526,7 @@ void launch_apply_std(int k, const double* const* in_tab, double* const* out_tab
 void launch_sum_down(int k, double* const* coeff_tab, const NodeRef* refs, int count,
                      const double* subbuf, const double* h0, const double* h1, hipStream_t s) {
   if (count <= 0) return;
-  MRA_DISPATCH_K14(k, hipLaunchKernelGGL(sum_down_kernel<KK>, dim3(count), dim3(256), 0, s,
+  MRA_DISPATCH_K14(k, hipLaunchKernelGGL(sum_down_kernel<KK>, dim3(count), dim3(512), 0, s,
                                          coeff_tab, refs, subbuf, h0, h1));
   hip_check(hipGetLastError(), "sum_down_kernel");
 }
