@@ -968,8 +968,11 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
         const int b = xs & 1;
         if (xs + 1 < Q) load1(xs + 1, b ^ 1);
         // the next triple's blocks (for the last triple of the list, nxt repeats the
-        // current item: harmless loads into the free halves)
-        fetch_part(nxt, xs, Xn, On);
+        // current item: harmless loads into the free halves): the operator blocks with the
+        // first source quarter, the other quarters in the next groups, so that the last
+        // copy has a whole x-quad group and the later steps to land
+        if (xs == 0) fetch_part(nxt, 4, Xn, On);
+        if (xs < 4) fetch_part(nxt, xs, Xn, On);
         if (xs == 4) load2(0, 0);
 #pragma unroll
         for (int yt = 0; yt < Q; ++yt)
@@ -981,8 +984,9 @@ __global__ __launch_bounds__(256) void apply_ns_fac_kernel(
 #pragma unroll
           for (int yt = 0; yt < Q; ++yt)
             d1e[e][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(opE[b][yt], opB[b][e], d1e[e][yt], 0, 0, 0);
-        if (xs + 1 < Q) interleave_mem<11, 4, 0, 2>();
-        else interleave_mem<3, 3, 0, 3>();
+        if (xs == 0) interleave_mem<11, 7, 0, 2>();
+        else if (xs + 1 < Q) interleave_mem<11, 4, 0, 2>();
+        else interleave_mem<3, 0, 0, 3>();
         __builtin_amdgcn_sched_barrier(0);
       }
     }
