@@ -10,6 +10,7 @@
 //      subtraction for targets below the root;
 //   5. sum-down (device), level by level.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -475,40 +476,60 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
   out.code = f.code;
   out.first_child = f.first_child;
   out.finalize_structure();
-  std::vector<NSItem> items;
-  std::vector<TargetRange> tgt;
-  for (int32_t T : f.leaves) {
+  // the level is complete (all nb^3 boxes present), so its codes are 0 .. nb^3 - 1 in order
+  // and the node of Morton code c is level_off[L] + c
+  if (f.level_off[L + 1] - f.level_off[L] != nb * nb * nb)
+    fail(MRA_E_INVALID, "standard form needs a complete uniform level");
+  std::vector<int64_t> tb(M);   // t block of displacement 0 per term
+  for (int mu = 0; mu < M; ++mu) {
+    const BlockEntry& be = op.entries.at({L, mu});
+    tb[mu] = be.t_base + be.D;
+  }
+  op.sync_device();
+  // items per target (displacements that stay in the cube, times the terms), then the
+  // items themselves in parallel, in (dx, dy, dz, mu) order per target
+  const size_t nt = f.leaves.size();
+  auto span = [&](int64_t x) { return std::min<int64_t>(x, D) + std::min<int64_t>(nb - 1 - x, D) + 1; };
+  std::vector<int64_t> start(nt + 1, 0);
+  std::vector<TargetRange> tgt(nt);
+  for (size_t q = 0; q < nt; ++q) {
+    int64_t x, y, z;
+    decode(f.code[f.leaves[q]], L, x, y, z);
+    start[q + 1] = start[q] + span(x) * span(y) * span(z) * M;
+  }
+  if (start[nt] > INT32_MAX) fail(MRA_E_UNSUPPORTED, "standard form: too many items");
+  std::vector<NSItem> items((size_t)start[nt]);
+  std::atomic<bool> bad{false};
+  Pool::get().run(nt, [&](size_t q, unsigned) {
+    const int32_t T = f.leaves[q];
     int64_t x, y, z;
     decode(f.code[T], L, x, y, z);
-    TargetRange r{0, T, -1, (int32_t)items.size(), 0, -1, -1};
+    tgt[q] = TargetRange{0, T, -1, (int32_t)start[q], (int32_t)start[q + 1], -1, -1};
+    NSItem* out_it = items.data() + start[q];
     for (int dx = -D; dx <= D; ++dx)
       for (int dy = -D; dy <= D; ++dy)
         for (int dz = -D; dz <= D; ++dz) {
-          int64_t sx = x - dx, sy = y - dy, sz = z - dz;
+          const int64_t sx = x - dx, sy = y - dy, sz = z - dz;
           if (sx < 0 || sy < 0 || sz < 0 || sx >= nb || sy >= nb || sz >= nb) continue;
-          int64_t S = find_node(f, L, encode(L, sx, sy, sz));
-          if (S < 0) fail(MRA_E_INVALID, "standard form needs a complete uniform level");
+          const int64_t S = f.level_off[L] + (int64_t)encode(L, sx, sy, sz);
           for (int mu = 0; mu < M; ++mu) {
-            const BlockEntry& be = op.entries.at({L, mu});
             NSItem it{};
             it.src = (int32_t)S;
             it.src_fc = -1;
             it.mu = mu;
-            it.tx = (int32_t)(be.t_base + dx + be.D);
-            it.ty = (int32_t)(be.t_base + dy + be.D);
-            it.tz = (int32_t)(be.t_base + dz + be.D);
-            items.push_back(it);
+            it.tx = (int32_t)(tb[mu] + dx);
+            it.ty = (int32_t)(tb[mu] + dy);
+            it.tz = (int32_t)(tb[mu] + dz);
+            if (it.src >= f.nodes() || it.tx < 0 || it.ty < 0 || it.tz < 0 ||
+                it.tx >= (int64_t)op.dT_blocks || it.ty >= (int64_t)op.dT_blocks ||
+                it.tz >= (int64_t)op.dT_blocks)
+              bad = true;
+            *out_it++ = it;
           }
         }
-    r.end = (int32_t)items.size();
-    tgt.push_back(r);
-  }
-  op.sync_device();
-  for (const NSItem& it : items)
-    if (it.src < 0 || it.src >= f.nodes() || it.tx < 0 || it.ty < 0 || it.tz < 0 ||
-        it.tx >= (int64_t)op.dT_blocks || it.ty >= (int64_t)op.dT_blocks ||
-        it.tz >= (int64_t)op.dT_blocks || it.mu < 0 || it.mu >= M)
-      fail(MRA_E_INVALID, "internal plan error: standard-form item");
+    if (out_it != items.data() + start[q + 1]) bad = true;
+  });
+  if (bad) fail(MRA_E_INVALID, "internal plan error: standard-form item");
   DevArray<NSItem> d_items;
   DevArray<TargetRange> d_tgt;
   d_items.upload(ctx, items);
