@@ -498,14 +498,20 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
     start[q + 1] = start[q] + span(x) * span(y) * span(z) * M;
   }
   if (start[nt] > INT32_MAX) fail(MRA_E_UNSUPPORTED, "standard form: too many items");
-  std::vector<NSItem> items((size_t)start[nt]);
+  // the items are written straight into the context's pinned staging buffer and copied
+  // with the tables in one asynchronous transfer
+  Arena& A = ctx->arena[1];
+  A.begin(ctx);
+  const size_t o_items = A.reserve((size_t)start[nt] * sizeof(NSItem));
+  NSItem* const items = A.host_at<NSItem>(o_items);
+  const size_t nitems = (size_t)start[nt];
   std::atomic<bool> bad{false};
   Pool::get().run(nt, [&](size_t q, unsigned) {
     const int32_t T = f.leaves[q];
     int64_t x, y, z;
     decode(f.code[T], L, x, y, z);
     tgt[q] = TargetRange{0, T, -1, (int32_t)start[q], (int32_t)start[q + 1], -1, -1};
-    NSItem* out_it = items.data() + start[q];
+    NSItem* out_it = items + start[q];
     for (int dx = -D; dx <= D; ++dx)
       for (int dy = -D; dy <= D; ++dy)
         for (int dz = -D; dz <= D; ++dz) {
@@ -527,39 +533,33 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
             *out_it++ = it;
           }
         }
-    if (out_it != items.data() + start[q + 1]) bad = true;
+    if (out_it != items + start[q + 1]) bad = true;
   });
   if (bad) fail(MRA_E_INVALID, "internal plan error: standard-form item");
-  DevArray<NSItem> d_items;
-  DevArray<TargetRange> d_tgt;
-  d_items.upload(ctx, items);
-  d_tgt.upload(ctx, tgt);
   out.coeff.alloc(ctx, (size_t)out.nodes() * k * k * k);
   std::vector<const double*> in_tab{f.coeff.p}, t_tab{op.dT.p}, c_tab{op.d_c.p};
   std::vector<double*> out_tab{out.coeff.p};
-  DevArray<const double*> d_in, d_t, d_c;
-  DevArray<double*> d_out;
-  d_in.upload(ctx, in_tab);
-  d_t.upload(ctx, t_tab);
-  d_c.upload(ctx, c_tab);
-  d_out.upload(ctx, out_tab);
+  const size_t o_tgt = A.put(tgt), o_in = A.put(in_tab), o_t = A.put(t_tab),
+               o_c = A.put(c_tab), o_out = A.put(out_tab);
+  A.commit();
   double t_plan1 = now_ms();
   launch_zero(out.coeff.p, out.coeff.n, ctx->stream);
   hip_check(hipEventRecord(ctx->ev[2], ctx->stream), "event");
-  launch_apply_std(k, d_in.p, d_out.p, d_items.p, d_tgt.p, (int)tgt.size(), d_t.p, d_c.p, 1.0,
-                   ctx->stream);
+  launch_apply_std(k, A.at<const double*>(o_in), A.at<double*>(o_out), A.at<NSItem>(o_items),
+                   A.at<TargetRange>(o_tgt), (int)tgt.size(), A.at<const double*>(o_t),
+                   A.at<const double*>(o_c), 1.0, ctx->stream);
   hip_check(hipEventRecord(ctx->ev[3], ctx->stream), "event");
   ctx->sync();
   float ms_a = 0;
   hip_check(hipEventElapsedTime(&ms_a, ctx->ev[2], ctx->ev[3]), "elapsed");
   mra_apply_stats& st = ctx->stats;
   st = mra_apply_stats{};
-  st.triples = (int64_t)items.size();
+  st.triples = (int64_t)nitems;
   st.targets = (int64_t)tgt.size();
   st.in_leaves = (int64_t)f.leaves.size();
   st.out_nodes = out.nodes();
   st.out_leaves = (int64_t)out.leaves.size();
-  st.useful_flops = (double)items.size() * 6.0 * std::pow((double)k, 4);
+  st.useful_flops = (double)nitems * 6.0 * std::pow((double)k, 4);
   st.flops_kernel = st.useful_flops;
   st.ms_plan = t_plan1 - t_plan0;
   st.ms_apply = ms_a;
