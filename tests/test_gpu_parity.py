@@ -86,6 +86,28 @@ def test_standard_form_gaussian_k8(M):
     assert _rel_l2(_as_dict(g3), ex.leaves, ex.leaves) < 2e-6
 
 
+
+def test_standard_form_clamped_radius_two_terms(M):
+    """Standard form on the uniform level-2 tree (4^3 boxes), two terms, a displacement
+    radius beyond the cube (the library clamps it to 2^level - 1; the oracle skips the
+    empty displacements): every box then sees every box, per term."""
+    _say("case: standard form, k=6, level 2, radius 5, 2 terms")
+    k, level, radius = 6, 2, 5
+    c, t = [1.0, 0.25], [0.05, 0.4]
+    ctx = M.Context(0, W.CELL)
+    f = ctx.project([1.0], [0.5], [[0.3, -0.2, 0.1]], k, 1.0, initial_level=level,
+                    max_level=level)
+    op = ctx.op_gaussians(k, c, t)
+    g = ctx.apply(op, f, form="standard", disp_radius=radius)
+    assert ctx.last_stats()["triples"] == 4 ** 3 * 4 ** 3 * len(c)
+    fo = project_uniform(GaussianSum([1.0], [0.5], [[0.3, -0.2, 0.1]]), k, W.CELL, level)
+    go, _ = apply_standard(fo, SeparatedOperator(c, t), level, radius)
+    got = _as_dict(g)
+    assert set(got) == set(go.leaves)
+    err = _rel_l2(got, go.leaves, go.leaves)
+    _say("standard clamped radius rel L2 vs oracle", err)
+    assert err <= TOL
+
 def test_paper_example_on_gpu(M):
     """Sec. 3.1 example: trace, norm2 and self-energy of exp(-r^2), and leaf parity."""
     _say("case: paper example, k=6, thresh 1e-4, Coulomb(1e-4, 1e-6)")
