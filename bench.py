@@ -1,16 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the separated-operator apply on one MI355X.
 
-One step = one pass of the whole hot path over one synthetic function (or batch): filter-up
-with block norms, norm screening and planning, transform-and-accumulate, sum-down, and the
-norm2 reduction of the result.  Inputs (the projected functions and the operators with
-their block caches, built during warm-up) are resident in HBM when the timed region starts.
+One step = one pass of the whole hot path over one synthetic function or batch of
+functions: filter-up with block norms, norm screening and tiering, transform-and-
+accumulate, sum-down, and the norm2 reduction of every result.  Inputs (the projected
+functions and the operators with their block caches, built during warm-up) are resident in
+HBM when the timed region starts.
 
-Prints one JSON line: useful GFLOP/s (sum over kept triples of 6(2k)^4 + 6k^4 [n>0]),
-boxes/s, the roofline of the dominant kernel (timed with HIP events on the library's
-stream) and the FP64 oracle timed on a bounded sample on the host cores.  The mixed
-workload (low-precision tier for triples with eta < 1e-3 thresh) also times the all-FP64
-path on the same input and reports the difference between the two results.
+The default workload is the large batched mixed-precision apply: 16 functions of 32
+unit-charge Gaussians (exponents log-uniform in [1, 1e4]), k = 14, thresh 1e-8, Coulomb
+kernel fitted to 1e-8 (160 terms), one batched apply per step, with the BF16 tier for kept
+triples whose norm bound eta is below 1e-3 thresh.  `value` is its useful GFLOP/s (sum over
+kept triples of 6(2k)^4 + 6k^4 [n > 0]).  The same functions are also applied with every
+triple in FP64 and with a wider tier (eta < thresh); the line reports both rates, the
+speed-ups and the distance of each mixed result from the FP64 one.
+
+Prints one JSON line: the metric, the roofline of the dominant kernel (timed with HIP
+events on the library's stream), per-tier kernel rates, and the FP64 oracle timed on a
+bounded sample on the host cores.
 """
 import argparse
 import json
@@ -25,9 +32,13 @@ if ROOT not in sys.path:
 
 import mra_workloads as W  # noqa: E402
 
-FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 (vector and matrix), AMD published
-BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix, AMD published
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # MI355X dense, AMD published
+HBM_PEAK_GBS = 8000.0
 METRIC = "useful operator-apply GFLOP/s and boxes/s, mixed-prec batched vs FP64 @ err≤10*thresh"
+WORKLOAD_NAMES = ["coulomb_batch_k14", "gauss_std_k8", "coulomb_k10", "coulomb_k12_fp64",
+                  "coulomb_k12_mixed", "bsh_batch_k10"]
+FP64_KERNEL = {8: "apply_ns_mfma_kernel<8>", 10: "apply_ns_fac_kernel<10>",
+               12: "apply_ns_own_kernel<12>", 14: "apply_ns_stream_kernel<14>"}
 
 
 def parse():
@@ -35,9 +46,10 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="coulomb_k10",
-                   choices=["gauss_std_k8", "coulomb_k10", "coulomb_k12_fp64",
-                            "coulomb_k12_mixed", "bsh_batch_k10"])
+    p.add_argument("--workload", default="coulomb_batch_k14", choices=WORKLOAD_NAMES)
+    p.add_argument("--cmp-steps", type=int, default=5,
+                   help="timed steps of each comparison run (all-FP64 path, wide tier) of a "
+                        "tiered workload, after one warm-up step (at most --steps)")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="approximate CPU work of the oracle baseline sample (0 = skip)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -57,42 +69,102 @@ def copy_calibration(mib):
     print(json.dumps({"copy_bytes": n * 8, "check": float(b[n // 2].item())}))
 
 
-def cpu_baseline(name, budget_s):
-    """The FP64 oracle (NumPy) timed on the host on a bounded sample of the same workload:
-    whole source levels of the non-standard apply, coarsest first, until the budget is used."""
-    from threadpoolctl import threadpool_info
-    from oracle.apply import SeparatedOperator, nonstandard_contributions, filter_up
-    from oracle.blocks import BlockFactory
-    from oracle.fit import coulomb_fit, cell_r_hi
-    from oracle.projection import GaussianSum, project_adaptive
+# ------------------------------------------------------------------------ CPU baseline
 
-    base = "coulomb_k12_mixed" if name.startswith("coulomb_k12") else name
-    w = W.WORKLOADS[base]
-    c, a, x = W.coulomb_inputs(base, 0)
-    fo = project_adaptive(GaussianSum(c, a, x), w["k"], w["thresh"], W.CELL, w["initial_level"], 20)
-    cc, tt = coulomb_fit(w["r_lo"], w["eps"], cell_r_hi(*W.CELL))
-    op = SeparatedOperator(cc, tt)
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(fo, op, tau, budget_s):
+    """Whole source levels of the oracle's non-standard apply, coarsest first, while the
+    predicted time of the next level fits the budget.  Operator blocks and their norms are
+    computed before each level is timed (block quadrature is not part of the apply)."""
+    from oracle.apply import filter_up, nonstandard_contributions, screen_level
+    from oracle.blocks import BlockFactory
     levels = filter_up(fo)
-    bf = BlockFactory(w["k"], W.CELL[1] - W.CELL[0])
-    flops, secs, done = 0.0, 0.0, []
+    bf = BlockFactory(fo.k, fo.width)
+    flops, secs, done, rate = 0.0, 0.0, [], None
     for n in sorted(levels):
+        groups = screen_level(bf, levels[n], op, tau, fo.k)      # norms and blocks, untimed
+        for (mu, d, _) in groups:
+            for dd in d:
+                bf.r_block(n, dd, float(op.t[mu]))
+                bf.t_block(n, dd, float(op.t[mu]))
+        cnt = sum(len(i) for (_, _, i) in groups)
+        f_next = cnt * (6.0 * (2 * fo.k) ** 4 + (6.0 * fo.k ** 4 if n > 0 else 0.0))
+        if rate is not None and secs + f_next / rate > 1.5 * budget_s:
+            break
         t0 = time.perf_counter()
-        _, _, st = nonstandard_contributions(fo, op, w["tau_rel"] * w["thresh"], only_levels={n},
-                                             levels=levels, blocks=bf)
+        _, _, st = nonstandard_contributions(fo, op, tau, only_levels={n}, levels=levels, blocks=bf)
         secs += time.perf_counter() - t0
         flops += st["useful_flops"]
         done.append(n)
+        rate = flops / secs if secs > 0 else None
         if secs >= budget_s:
             break
-    threads = sum(i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas")
-    return {"value": flops / secs / 1e9, "unit": "GFLOP/s", "cores": max(1, threads),
-            "kind": "oracle",
-            "sample": "source levels %s of the non-standard apply (%.1f useful GFLOP, %.1f s; "
-                      "block quadrature included)" % (done, flops / 1e9, secs)}
+    return flops, secs, done
 
+
+def cpu_baseline(name, budget_s):
+    """The FP64 oracle (NumPy) timed on the host cores on a bounded sample of the workload:
+    function 0 (its own projection and operator fit), whole source levels of the
+    non-standard apply (standard form: the whole apply), with every BLAS thread, and again
+    on one core."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle.apply import SeparatedOperator, apply_standard
+    from oracle.fit import coulomb_fit, bsh_fit, cell_r_hi
+    from oracle.projection import GaussianSum, project_adaptive, project_uniform
+
+    w = W.WORKLOADS["coulomb_k12_mixed" if name.startswith("coulomb_k12") else name]
+    r_hi = cell_r_hi(*W.CELL)
+
+    if name == "gauss_std_k8":
+        fo = project_uniform(GaussianSum([w["f_coeff"]], [w["f_expnt"]], [[0, 0, 0]]),
+                             w["k"], W.CELL, w["level"])
+        op = SeparatedOperator(w["op_c"], w["op_t"])
+    else:
+        if name == "bsh_batch_k10":
+            c, a, x, mu = W.bsh_inputs(0)
+            cc, tt = bsh_fit(mu, w["r_lo"], w["eps"], r_hi)
+        else:
+            c, a, x = W.coulomb_inputs(name if name in W.WORKLOADS else "coulomb_k12_mixed", 0)
+            cc, tt = coulomb_fit(w["r_lo"], w["eps"], r_hi)
+        fo = project_adaptive(GaussianSum(c, a, x), w["k"], w["thresh"], W.CELL,
+                              w["initial_level"], 20)
+        op = SeparatedOperator(cc, tt)
+
+    def sample(limit_s):
+        if name == "gauss_std_k8":
+            t0 = time.perf_counter()
+            _, st = apply_standard(fo, op, w["level"], w["disp_radius"])
+            return st["useful_flops"], time.perf_counter() - t0, "the whole standard-form apply"
+        fl, s, done = _oracle_sample(fo, op, w["tau_rel"] * w["thresh"], limit_s)
+        return fl, s, "function 0, source levels %s of the non-standard apply" % done
+
+    threads = sum(i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas")
+    fl, s, what = sample(budget_s)
+    with threadpool_limits(limits=1, user_api="blas"):
+        fl1, s1, what1 = sample(budget_s / 2)
+    return {"value": fl / s / 1e9, "unit": "GFLOP/s", "cores": max(1, threads),
+            "kind": "oracle",
+            "sample": "%s (FP64 NumPy, %.1f useful GFLOP in %.1f s; screening timed, block "
+                      "quadrature and projection not)" % (what, fl / 1e9, s),
+            "value_1core": fl1 / s1 / 1e9,
+            "sample_1core": "%s (%.1f useful GFLOP in %.1f s)" % (what1, fl1 / 1e9, s1),
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
+
+
+# ---------------------------------------------------------------------------- workloads
 
 def setup(ctx, name):
-    """Functions, operators and tau for a workload; returns (funcs, ops, tau, k, config)."""
+    """(funcs, ops, tau_drop, k, tau_tier, config) of a workload."""
     if name == "gauss_std_k8":
         w = W.WORKLOADS[name]
         f = ctx.project([w["f_coeff"]], [w["f_expnt"]], [[0.0, 0.0, 0.0]], w["k"], 1.0,
@@ -101,7 +173,7 @@ def setup(ctx, name):
         cfg = {"workload": name, "k": w["k"], "level": w["level"], "boxes": 8 ** w["level"],
                "operator": "exp(-2 x^2)", "displacements": (2 * w["disp_radius"] + 1) ** 3,
                "form": "standard", "precision": "fp64"}
-        return [f], [op], None, w["k"], cfg
+        return [f], [op], None, w["k"], 0.0, cfg
     if name == "bsh_batch_k10":
         w = W.WORKLOADS[name]
         funcs, ops, mus, ng = [], [], [], []
@@ -116,7 +188,22 @@ def setup(ctx, name):
                "mu_range": [min(mus), max(mus)], "eps_fit": w["eps"], "r_lo": w["r_lo"],
                "tau_drop": w["tau_rel"] * w["thresh"], "precision": "fp64",
                "launch": "one batched apply (all functions per kernel launch)"}
-        return funcs, ops, w["tau_rel"] * w["thresh"], w["k"], cfg
+        return funcs, ops, w["tau_rel"] * w["thresh"], w["k"], 0.0, cfg
+    if name == "coulomb_batch_k14":
+        w = W.WORKLOADS[name]
+        funcs = []
+        for i in range(w["n_funcs"]):
+            c, a, x = W.coulomb_inputs(name, i)
+            funcs.append(ctx.project(c, a, x, w["k"], w["thresh"], initial_level=w["initial_level"]))
+        op = ctx.op_coulomb(w["k"], w["r_lo"], w["eps"])
+        tier = w["tier_rel"] * w["thresh"]
+        cfg = {"workload": name, "k": w["k"], "thresh": w["thresh"], "functions": w["n_funcs"],
+               "gaussians_per_function": w["n_gauss"], "exponent_range": [w["a_lo"], w["a_hi"]],
+               "operator": "coulomb", "terms": int(op.terms()[0].size), "eps_fit": w["eps"],
+               "r_lo": w["r_lo"], "tau_drop": w["tau_rel"] * w["thresh"], "tau_tier": tier,
+               "precision": "fp64 + bf16 tier (eta < tau_tier), fp32 accumulation",
+               "launch": "one batched apply (all functions per kernel launch)"}
+        return funcs, [op] * len(funcs), w["tau_rel"] * w["thresh"], w["k"], tier, cfg
     base = "coulomb_k12_mixed" if name.startswith("coulomb_k12") else name
     w = W.WORKLOADS[base]
     c, a, x = W.coulomb_inputs(base, 0)
@@ -125,10 +212,12 @@ def setup(ctx, name):
     cfg = {"workload": name, "k": w["k"], "thresh": w["thresh"], "gaussians": w["n_gauss"],
            "operator": "coulomb", "terms": int(op.terms()[0].size), "eps_fit": w["eps"],
            "r_lo": w["r_lo"], "tau_drop": w["tau_rel"] * w["thresh"], "precision": "fp64"}
+    tier = 0.0
     if name == "coulomb_k12_mixed":
+        tier = w["tier_rel"] * w["thresh"]
         cfg["precision"] = "fp64 + bf16 tier (eta < tau_tier), fp32 accumulation"
-        cfg["tau_tier"] = w["tier_rel"] * w["thresh"]
-    return [f], [op], w["tau_rel"] * w["thresh"], w["k"], cfg
+        cfg["tau_tier"] = tier
+    return [f], [op], w["tau_rel"] * w["thresh"], w["k"], tier, cfg
 
 
 def kernel_source_sha(kernel):
@@ -145,16 +234,17 @@ def kernel_source_sha(kernel):
     return hashlib.sha256(src[i:j].encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when the summary was taken on a different version of the kernel's source."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed rocprofv3 counter
+    summaries, or None when none was taken on the current source of the kernel."""
     import glob
     sha = kernel_source_sha(kernel)
-    for path in glob.glob(os.path.join(ROOT, "profiles", "*_pmc.md")):
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_pmc.md"))):
         for line in open(path):
             if line.startswith("pmc: "):
                 rec = json.loads(line[5:])
-                if rec.get("kernel") == kernel and rec.get("kernel_src_sha256_16") == sha:
+                if (rec.get("kernel") == kernel and rec.get("kernel_src_sha256_16") == sha
+                        and rec.get("workload", workload) == workload):
                     return 1024.0 * (rec["fetch_kib"] * rec["fetch_factor"]
                                      + rec["write_kib"] * rec["write_factor"])
     return None
@@ -174,17 +264,19 @@ def main():
     import paper_1507_01888_amd as M
 
     ctx = M.Context(0, W.CELL)
-    funcs, ops, tau, k, cfg = setup(ctx, args.workload)
-    tier = cfg.get("tau_tier", 0.0)
+    funcs, ops, tau, k, tier, cfg = setup(ctx, args.workload)
+    name = args.workload
+
+    def apply(tau_tier):
+        if tau is None:     # standard form on a uniform tree, no screening
+            return [ctx.apply(ops[0], funcs[0], form="standard",
+                              disp_radius=W.WORKLOADS[name]["disp_radius"])]
+        if len(funcs) == 1:
+            return [ctx.apply(ops[0], funcs[0], tau_drop=tau, tau_tier=tau_tier)]
+        return ctx.apply_batch(ops, funcs, tau_drop=tau, tau_tier=tau_tier)
 
     def step(tau_tier, keep=False):
-        if tau is None:     # standard form on a uniform tree, no screening
-            gs = [ctx.apply(ops[0], funcs[0], form="standard",
-                            disp_radius=W.WORKLOADS[args.workload]["disp_radius"])]
-        elif len(funcs) == 1:
-            gs = [ctx.apply(ops[0], funcs[0], tau_drop=tau, tau_tier=tau_tier)]
-        else:
-            gs = ctx.apply_batch(ops, funcs, tau_drop=tau, tau_tier=tau_tier)
+        gs = apply(tau_tier)
         st = ctx.last_stats()
         nrm = [ctx.norm2(g) for g in gs]
         if keep:
@@ -193,52 +285,66 @@ def main():
             g.free()
         return st, nrm
 
-    def timed(tau_tier):
-        for _ in range(args.warmup):
+    def timed(tau_tier, steps, warmup):
+        for _ in range(warmup):
             step(tau_tier)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         stats = []
-        for _ in range(args.steps):
+        for _ in range(steps):
             st, nrm = step(tau_tier)
             stats.append(st)
         torch.cuda.synchronize()
         return stats, nrm, time.perf_counter() - t0
 
-    stats, nrm, elapsed = timed(tier)
-    fp64_cmp = None
-    if tier > 0:
-        # the all-FP64 path on the same input, and the difference of the two results
-        st64, _, el64 = timed(0.0)
-        _, _, g_mix = step(tier, keep=True)
-        _, _, g_64 = step(0.0, keep=True)
-        import numpy as np
-        km, cm = g_mix[0].export()
-        k6, c6 = g_64[0].export()
-        assert np.array_equal(km, k6)
-        fp64_cmp = {"value": sum(s["useful_flops"] for s in st64) / el64 / 1e9,
-                    "ms_per_step": el64 / args.steps * 1e3,
-                    "ms_main_kernel": sum(s["ms_main_kernel"] for s in st64) / len(st64),
-                    "speedup_mixed_vs_fp64": el64 / elapsed,
-                    "rel_l2_mixed_vs_fp64": float(np.linalg.norm(cm - c6) / np.linalg.norm(c6))}
+    def mean(stats, key):
+        return sum(s[key] for s in stats) / len(stats)
 
+    stats, nrm, elapsed = timed(tier, args.steps, args.warmup)
+    s0 = stats[0]
     flops = sum(s["useful_flops"] for s in stats)
-    # algorithmic work of the main kernel: the FP64 mode products it executes (children
-    # blocks and, for k = 8, 10, 12, 14, the fused level-n subtraction).  For k = 10 the
-    # kernel shares the y- and z-products of a target's triples, so it executes fewer flops
-    # than the useful count of its triples; both rates are reported.
-    fused = k in (8, 10, 12, 14)
-    kernel_flops = stats[0]["flops_kernel"]
-    useful_main = stats[0]["useful_flops"] - stats[0]["flops_low"]
-    main_ms = sum(s["ms_main_kernel"] for s in stats) / len(stats)
-    kname = {8: "apply_ns_mfma_kernel<8>", 10: "apply_ns_fac_kernel<10>",
-             12: "apply_ns_own_kernel<12>", 14: "apply_ns_stream_kernel<14>"}.get(
-                 k, "apply_ns_kernel<%d>" % k)
-    if tau is None:        # standard form: the VALU kernel does 6 k^4 flop per triple
-        fused, kernel_flops, kname = False, stats[0]["useful_flops"], "apply_std_kernel<%d>" % k
-        useful_main = kernel_flops
-    achieved = kernel_flops / (main_ms * 1e-3) / 1e12
-    low_ms = sum(s["ms_low_kernel"] for s in stats) / len(stats)
+
+    # ---- per-kernel rates (HIP events on the library's stream), per tier
+    main_ms = mean(stats, "ms_main_kernel")
+    main_launch_ms = main_ms / max(1, s0["launches_main"])
+    useful_main = s0["useful_flops"] - s0["flops_low"]
+    if tau is None:
+        kname, bound, prec = "apply_std_kernel<%d>" % k, "alu", "fp64"
+    else:
+        kname, bound, prec = FP64_KERNEL.get(k, "apply_ns_kernel<%d>" % k), "mfma", "fp64"
+    kernels = {"fp64": {"kernel": kname, "ms_per_apply": main_ms,
+                        "launches_per_apply": s0["launches_main"],
+                        "ms_per_launch": main_launch_ms,
+                        "useful_tflops": useful_main / (main_ms * 1e-3) / 1e12,
+                        "executed_tflops": s0["flops_kernel"] / (main_ms * 1e-3) / 1e12,
+                        "triples": s0["triples"] - s0["triples_low"]}}
+    kernels["fp64"]["frac"] = kernels["fp64"]["useful_tflops"] / PEAK_TFLOPS["fp64"]
+    kernels["fp64"]["executed_frac"] = kernels["fp64"]["executed_tflops"] / PEAK_TFLOPS["fp64"]
+    low_ms = mean(stats, "ms_low_kernel")
+    if s0["triples_low"] > 0 and low_ms > 0:
+        # the BF16 kernel evaluates 7 mode products of (2k)^3 x 2k per triple (E R R + P E R
+        # + P P E with the shared R_z and E_z products)
+        low_exec = s0["triples_low"] * 14.0 * (2 * k) ** 4
+        kernels["bf16"] = {"kernel": "apply_low_kernel<%d>" % k, "ms_per_apply": low_ms,
+                           "launches_per_apply": s0["launches_low"],
+                           "ms_per_launch": low_ms / max(1, s0["launches_low"]),
+                           "useful_tflops": s0["flops_low"] / (low_ms * 1e-3) / 1e12,
+                           "executed_tflops": low_exec / (low_ms * 1e-3) / 1e12,
+                           "triples": s0["triples_low"]}
+        kernels["bf16"]["frac"] = kernels["bf16"]["useful_tflops"] / PEAK_TFLOPS["bf16"]
+        kernels["bf16"]["executed_frac"] = kernels["bf16"]["executed_tflops"] / PEAK_TFLOPS["bf16"]
+    dom = max(kernels, key=lambda t: kernels[t]["ms_per_apply"])
+    dk = kernels[dom]
+    peak = PEAK_TFLOPS[dom]
+    alg_per_launch = (useful_main if dom == "fp64" else s0["flops_low"]) / max(1, dk["launches_per_apply"])
+    achieved = alg_per_launch / (dk["ms_per_launch"] * 1e-3) / 1e12
+    roofline = {"kernel": dk["kernel"], "bound": bound if dom == "fp64" else "mfma",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": measured_traffic(dk["kernel"], name),
+                "algorithmic_flop_per_launch": alg_per_launch,
+                "ms_per_launch": dk["ms_per_launch"],
+                "executed_frac": dk["executed_frac"]}
+
     out = {
         "metric": METRIC,
         "value": flops / elapsed / 1e9,
@@ -250,38 +356,68 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+bf16" if tier > 0 else "f64",
         "data": "synthetic",
         "config": cfg,
-        "boxes_per_s": stats[0]["in_leaves"] * args.steps / elapsed,
+        "boxes_per_s": s0["in_leaves"] * args.steps / elapsed,
         "time_to_solution_ms": elapsed / args.steps * 1e3,
-        "counts": {key: stats[0][key] for key in ("triples", "targets", "in_leaves", "out_nodes",
-                                                   "out_leaves")},
-        "stage_ms": {key: sum(s[key] for s in stats) / len(stats)
-                     for key in ("ms_filter", "ms_plan", "ms_apply", "ms_main_kernel", "ms_sumdown")},
-        "norm2": nrm[0] if len(nrm) == 1 else sum(v * v for v in nrm) ** 0.5,
-        "roofline": {"kernel": kname,
-                     "bound": "mfma" if fused else "alu", "achieved": achieved,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(kname),
-                     "useful_tflops": useful_main / (main_ms * 1e-3) / 1e12,
-                     "executed_over_useful": kernel_flops / useful_main},
+        "counts": {key: s0[key] for key in ("triples", "triples_low", "targets", "in_leaves",
+                                            "out_nodes", "out_leaves")},
+        "useful_gflop_per_step": s0["useful_flops"] / 1e9,
+        "stage_ms": {key: mean(stats, key) for key in ("ms_filter", "ms_plan", "ms_apply",
+                                                       "ms_main_kernel", "ms_low_kernel",
+                                                       "ms_sumdown")},
+        "norm2": math.sqrt(sum(v * v for v in nrm)),
+        "roofline": roofline,
+        "kernels": kernels,
     }
+
     if tier > 0:
-        s0 = stats[0]
-        # the BF16 kernel evaluates 7 mode products of (2k)^3 x 2k per triple (E R R + P E R
-        # + P P E with the shared R_z and E_z products) and writes nothing but the target
-        low_alg = s0["triples_low"] * 14.0 * (2 * k) ** 4
-        out["tiers"] = {"triples_fp64": s0["triples"] - s0["triples_low"],
-                        "triples_low": s0["triples_low"],
-                        "useful_flop_fraction_low": s0["flops_low"] / s0["useful_flops"],
-                        "eta_low_sum": s0["eta_low"], "ms_low_kernel": low_ms,
-                        "low_kernel": "apply_low_kernel<%d>" % k,
-                        "low_kernel_tflops_executed": low_alg / (low_ms * 1e-3) / 1e12 if low_ms > 0 else None,
-                        "low_kernel_frac_bf16_peak": (low_alg / (low_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS) if low_ms > 0 else None}
-        out["fp64_path"] = fp64_cmp
-    if args.cpu_seconds > 0 and args.workload.startswith("coulomb"):
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+        # the same inputs with every triple in FP64, and with the wider tier eta < thresh
+        n_cmp = max(1, min(args.cmp_steps, args.steps))
+        thresh = cfg["thresh"]
+        st64, _, el64 = timed(0.0, n_cmp, 1)
+        stw, _, elw = timed(thresh, n_cmp, 1)
+        ms_mixed = elapsed / args.steps * 1e3
+        ms_64 = el64 / n_cmp * 1e3
+        ms_w = elw / n_cmp * 1e3
+        _, n64, g64 = step(0.0, keep=True)
+        res = {}
+        for lab, tt in (("literal", tier), ("wide", thresh)):
+            _, _, gm = step(tt, keep=True)
+            st = ctx.last_stats()
+            d = [ctx.distance(a, b) for a, b in zip(gm, g64)]
+            for g in gm:
+                g.free()
+            # a-priori bound of the low-tier rounding error (three BF16-rounded factors per
+            # product, operators through their Frobenius norms): (3 + 3 sqrt(2k)) 2^-8 sum eta
+            bound = (3 + 3 * math.sqrt(2 * k)) * 2.0 ** -8 * st["eta_low"]
+            tot = math.sqrt(sum(v * v for v in n64))
+            res[lab] = {"tau_tier": tt, "triples_low": st["triples_low"],
+                        "useful_flop_fraction_low": st["flops_low"] / st["useful_flops"],
+                        "rel_l2_vs_fp64": math.sqrt(sum(v * v for v in d)) / tot,
+                        "max_rel_l2_per_function": max(dv / nv for dv, nv in zip(d, n64)),
+                        "error_bound_rel": bound / tot,
+                        "gate_10_thresh": 10 * thresh}
+        for g in g64:
+            g.free()
+        res["literal"].update({"ms_per_step": ms_mixed,
+                               "value": flops / elapsed / 1e9,
+                               "speedup_vs_fp64": ms_64 / ms_mixed})
+        res["wide"].update({"ms_per_step": ms_w,
+                            "value": sum(s["useful_flops"] for s in stw) / elw / 1e9,
+                            "speedup_vs_fp64": ms_64 / ms_w,
+                            "ms_main_kernel": mean(stw, "ms_main_kernel"),
+                            "ms_low_kernel": mean(stw, "ms_low_kernel")})
+        out["fp64_path"] = {"value": sum(s["useful_flops"] for s in st64) / el64 / 1e9,
+                            "ms_per_step": ms_64, "steps": n_cmp,
+                            "ms_main_kernel": mean(st64, "ms_main_kernel"),
+                            "kernel_useful_tflops": st64[0]["useful_flops"]
+                            / (mean(st64, "ms_main_kernel") * 1e-3) / 1e12}
+        out["tiers"] = res
+        out["speedup_mixed_vs_fp64"] = ms_64 / ms_mixed
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(name, args.cpu_seconds)
     print(json.dumps(out))
 
 

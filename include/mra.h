@@ -125,6 +125,9 @@ typedef struct {
                              the kernel shares contractions between triples (k = 10: one
                              y-product per (term, dz, dy) group and one z-product per
                              (term, dz) group of a target's list instead of per triple)  */
+  int64_t launches_main;  /* launches of the main kernel behind ms_main_kernel (a batched
+                             apply plans and launches in chunks)                         */
+  int64_t launches_low;   /* launches of the low-precision kernel behind ms_low_kernel    */
 } mra_apply_stats;
 
 /* Create a context on HIP device `device` using HIP stream `stream` (NULL: the null
@@ -178,6 +181,12 @@ mra_status mra_apply(mra_ctx* ctx, const mra_op* op, const mra_func* f,
 
 /* op_i(f_i) for i < n in one pass: filter-up, screening, transform-and-accumulate and
  * sum-down each run as one launch sequence over all functions (non-standard form only).
+ * The paper applies an operator to one function at a time (Sec. 3.1); this batched form
+ * is this library's extension for many functions with uneven trees and operators with
+ * different terms (e.g. one bound-state Helmholtz kernel per orbital, Sec. 3.2), so that
+ * one transform launch covers the kept triples of all of them, longest target lists
+ * first.  Each result equals that of mra_apply on the same pair up to the summation order
+ * of split target lists.
  * Functions may have different trees and operators different terms, but all share k.
  * outs receives n new functions (written only on success).  A function may appear only
  * once (its refined-box slabs are workspace); operators may repeat. */
@@ -185,12 +194,26 @@ mra_status mra_apply_batch(mra_ctx* ctx, int n, const mra_op* const* ops,
                            const mra_func* const* fs, const mra_apply_params* params,
                            mra_func** outs);
 
-/* 2-norm sqrt(sum over leaves ||s||^2) (orthonormal basis), FP64, fixed-order reduction. */
+/* The three reductions of the example program of Sec. 3.1 (norm2, trace, inner), which
+ * prints the 2-norm, the integral and the Coulomb self-energy <g, op(g)> of its function.
+ * All are FP64 with a fixed-order reduction (2048 workgroup partials summed in index order
+ * on the host), so repeated calls give bitwise identical results.  Each synchronises the
+ * context's stream.
+ *
+ * mra_norm2: 2-norm sqrt(sum over leaves ||s||^2) (the basis is orthonormal, Sec. 2.1). */
 mra_status mra_norm2(mra_ctx* ctx, const mra_func* f, double* out);
-/* Integral of f over the cell: sum over leaves s_000 h_n^{3/2}. */
+/* mra_trace: integral of f over the cell, sum over leaves s_000 h_n^{3/2} (phi_0 is the
+ * constant h_n^{-1/2} on its box). */
 mra_status mra_trace(mra_ctx* ctx, const mra_func* f, double* out);
-/* <f, g> over the cell; both must have the same k. */
+/* mra_inner: <f, g> over the cell (both with the same k; the trees may differ: every box
+ * that is a leaf of one function and present in the other pairs the leaf's coefficients
+ * with the other's filtered coefficients of that box). */
 mra_status mra_inner(mra_ctx* ctx, const mra_func* f, const mra_func* g, double* out);
+/* mra_distance: ||f - g||_2 for two functions on the same tree (same nodes, as the results
+ * of two applies that differ only in arithmetic, e.g. with and without the low-precision
+ * tier); MRA_E_MISMATCH when the trees or k differ.  Used to state the error of one
+ * evaluation against another without copying either to the host. */
+mra_status mra_distance(mra_ctx* ctx, const mra_func* f, const mra_func* g, double* out);
 
 /* Counters of the last mra_apply on ctx. */
 mra_status mra_last_stats(const mra_ctx* ctx, mra_apply_stats* out);

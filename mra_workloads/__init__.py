@@ -54,7 +54,8 @@ WORKLOADS = {
                           initial_level=2),
     # large batched mixed, 16 functions x 32 Gaussians, a in [1, 1e4], k=14, thresh 1e-8
     "coulomb_batch_k14": dict(id=4, k=14, thresh=1e-8, n_funcs=16, n_gauss=32, a_lo=1.0,
-                              a_hi=1e4, r_lo=1e-5, eps=1e-8, tau_rel=1e-4, initial_level=2),
+                              a_hi=1e4, r_lo=1e-5, eps=1e-8, tau_rel=1e-4, tier_rel=1e-3,
+                              initial_level=2),
 }
 
 

@@ -23,7 +23,7 @@ EXPORTED = [
     "mra_ctx_create", "mra_ctx_free", "mra_last_error", "mra_project", "mra_func_info",
     "mra_func_export", "mra_func_free", "mra_op_coulomb", "mra_op_bsh", "mra_op_gaussians",
     "mra_op_terms", "mra_op_free", "mra_apply", "mra_apply_batch", "mra_norm2", "mra_trace",
-    "mra_inner",
+    "mra_inner", "mra_distance",
     "mra_last_stats", "mra_host_fit", "mra_host_block", "mra_host_filters",
     "mra_host_spectral_norm", "mra_host_project",
 ]
@@ -62,7 +62,8 @@ class ApplyStats(ctypes.Structure):
                 ("ms_apply", ctypes.c_double), ("ms_sumdown", ctypes.c_double),
                 ("ms_main_kernel", ctypes.c_double), ("triples_low", ctypes.c_int64),
                 ("flops_low", ctypes.c_double), ("eta_low", ctypes.c_double),
-                ("ms_low_kernel", ctypes.c_double), ("flops_kernel", ctypes.c_double)]
+                ("ms_low_kernel", ctypes.c_double), ("flops_kernel", ctypes.c_double),
+                ("launches_main", ctypes.c_int64), ("launches_low", ctypes.c_int64)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -107,6 +108,7 @@ def load():
     lib.mra_norm2.argtypes = [vp, vp, dp]
     lib.mra_trace.argtypes = [vp, vp, dp]
     lib.mra_inner.argtypes = [vp, vp, vp, dp]
+    lib.mra_distance.argtypes = [vp, vp, vp, dp]
     lib.mra_last_stats.argtypes = [vp, P(ApplyStats)]
     lib.mra_host_fit.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_int, dp, dp, P(ctypes.c_int)]
@@ -327,6 +329,12 @@ class Context:
     def inner(self, f, g):
         v = ctypes.c_double()
         self._check(self._lib.mra_inner(self.h, f.h, g.h, ctypes.byref(v)), "mra_inner")
+        return v.value
+
+    def distance(self, f, g):
+        """||f - g||_2 of two functions on the same tree (computed on the device)."""
+        v = ctypes.c_double()
+        self._check(self._lib.mra_distance(self.h, f.h, g.h, ctypes.byref(v)), "mra_distance")
         return v.value
 
     def last_stats(self):

@@ -686,6 +686,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   int64_t ntriples = 0, ntargets = 0, nlow = 0, in_leaves = 0, out_nodes = 0, out_leaves = 0;
   double flops = 0.0, flops_low = 0.0, eta_low = 0.0, flops_kernel = 0.0, plan_ms = t_prep;
   bool any_low = false;
+  int64_t n_low_launch = 0;
   // per (job, bucket) outputs; the vectors keep their capacity across applies on this host
   // thread, so enumeration neither allocates nor frees in steady state
   static thread_local std::vector<std::vector<Triple>> t_jobout;
@@ -1151,6 +1152,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       hip_check(hipEventRecord(E[2], ctx->stream), "event");
       if (!low_work.empty()) {
         any_low = true;
+        ++n_low_launch;
         launch_apply_low(k, mirror_d, out_tab_d, low_items_d, low_work_d,
                          (int)low_work.size(), l_tab_d, c_tab_d, ctx->stream);
       }
@@ -1209,6 +1211,8 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   st.flops_kernel = flops_kernel;
   st.eta_low = eta_low;
   st.ms_low_kernel = any_low ? ms_low : 0.0;
+  st.launches_main = (int64_t)cev.size();
+  st.launches_low = n_low_launch;
   if (timing) std::fprintf(stderr, "[mra] %-28s %8.3f ms\n", "host total", now_ms() - t_entry);
 }
 

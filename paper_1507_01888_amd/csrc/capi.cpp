@@ -564,6 +564,7 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
   st.ms_plan = t_plan1 - t_plan0;
   st.ms_apply = ms_a;
   st.ms_main_kernel = ms_a;
+  st.launches_main = 1;
 }
 
 // ------------------------------------------------------------------------ reductions
@@ -924,6 +925,23 @@ mra_status mra_inner(mra_ctx* ctx, const mra_func* fh, const mra_func* gh, doubl
       }
     }
     *out = reduce(c, f.k, f.coeff.p, g.coeff.p, la, &lb, nullptr, 2);
+  });
+}
+
+mra_status mra_distance(mra_ctx* ctx, const mra_func* fh, const mra_func* gh, double* out) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (!fh || !gh || !out) fail(MRA_E_INVALID, "mra_distance: bad arguments");
+    Func& f = const_cast<mra_func*>(fh)->f;
+    Func& g = const_cast<mra_func*>(gh)->f;
+    if (f.ctx != c || g.ctx != c) fail(MRA_E_MISMATCH, "handles belong to another context");
+    if (f.k != g.k) fail(MRA_E_MISMATCH, "functions have different k");
+    if (f.code != g.code || f.first_child != g.first_child)
+      fail(MRA_E_MISMATCH, "mra_distance: the two functions have different trees");
+    double s = reduce(c, f.k, f.coeff.p, g.coeff.p, f.leaves, &g.leaves, nullptr, 3,
+                      f.device_leaves());
+    *out = std::sqrt(s);
   });
 }
 

@@ -1530,7 +1530,8 @@ __global__ __launch_bounds__(512) void sum_down_kernel(
 }
 
 // --------------------------------------------------------------------------- reductions
-// mode 0: sum ||a_leaf||^2; mode 1: sum a_leaf[0] * weight[leaf]; mode 2: sum <a_la, b_lb>.
+// mode 0: sum ||a_leaf||^2; mode 1: sum a_leaf[0] * weight[leaf]; mode 2: sum <a_la, b_lb>;
+// mode 3: sum ||a_la - b_lb||^2.
 // Workgroup g takes leaves g, g + G, g + 2G, ... (G = gridDim.x) in that order, its threads
 // the elements e = t, t + 256, ... of each leaf, and the partials are combined in a fixed
 // tree: the result does not depend on scheduling.  The next leaf's index is loaded before
@@ -1542,10 +1543,11 @@ __global__ __launch_bounds__(256) void leaf_reduce_kernel(
   __shared__ double red[256];
   double s = 0.0;
   int l = blockIdx.x;
-  int ia = l < count ? la[l] : 0, ib = (mode == 2 && l < count) ? lb[l] : 0;
+  const bool paired = mode >= 2;
+  int ia = l < count ? la[l] : 0, ib = (paired && l < count) ? lb[l] : 0;
   for (; l < count; l += gridDim.x) {
     const int ln = l + gridDim.x;
-    const int na = ln < count ? la[ln] : 0, nb = (mode == 2 && ln < count) ? lb[ln] : 0;
+    const int na = ln < count ? la[ln] : 0, nb = (paired && ln < count) ? lb[ln] : 0;
     const double* pa = a + (size_t)ia * k3;
     if (mode == 0) {
       double v[4];
@@ -1559,6 +1561,12 @@ __global__ __launch_bounds__(256) void leaf_reduce_kernel(
       for (int e = threadIdx.x + 1024; e < k3; e += 256) s += pa[e] * pa[e];
     } else if (mode == 1) {
       if (threadIdx.x == 0) s += pa[0] * weight[l];
+    } else if (mode == 3) {
+      const double* pb = b + (size_t)ib * k3;
+      for (int e = threadIdx.x; e < k3; e += 256) {
+        const double d = pa[e] - pb[e];
+        s += d * d;
+      }
     } else {
       const double* pb = b + (size_t)ib * k3;
       double v[4], w[4];

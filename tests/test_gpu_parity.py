@@ -176,39 +176,6 @@ def test_bsh_k10_reduced_full_parity(M):
     assert err <= TOL
 
 
-def test_coulomb_k10_full_size_sampled(M):
-    """The full k=10, thresh 1e-6 Coulomb workload (4 Gaussians, a in [1, 1e3]): leaves
-    sampled across levels are recomputed by the oracle along their root paths."""
-    w = W.WORKLOADS["coulomb_k10"]
-    _say("case: coulomb_k10 full size, sampled leaves")
-    c, a, x = W.coulomb_inputs("coulomb_k10", 0)
-    ctx = M.Context(0, W.CELL)
-    f = ctx.project(c, a, x, w["k"], w["thresh"])
-    op = ctx.op_coulomb(w["k"], w["r_lo"], w["eps"])
-    tau = w["tau_rel"] * w["thresh"]
-    g = ctx.apply(op, f, tau_drop=tau)
-    st = ctx.last_stats()
-    _say("gpu stats", st)
-    got = _as_dict(g)
-    rng = np.random.default_rng(5)
-    keys = sorted(got)
-    by_level = {}
-    for q in keys:
-        by_level.setdefault(q[0], []).append(q)
-    sample = []
-    for n, lst in sorted(by_level.items()):
-        for i in rng.choice(len(lst), min(3, len(lst)), replace=False):
-            sample.append(lst[i])
-    fo = project_adaptive(GaussianSum(c, a, x), w["k"], w["thresh"], W.CELL, 2, 20)
-    cc, tt = coulomb_fit(w["r_lo"], w["eps"], cell_r_hi(*W.CELL))
-    vals, has_acc, _ = sampled_leaves(fo, SeparatedOperator(cc, tt), tau, sample)
-    for q in sample:
-        assert not has_acc[q]          # the oracle agrees these are output leaves
-    err = _rel_l2(got, vals, sample)
-    _say("coulomb_k10 sampled (%d leaves) rel L2 vs oracle" % len(sample), err)
-    assert err <= TOL
-
-
 def test_deterministic_and_errors(M):
     _say("case: determinism and error codes")
     ctx = M.Context(0, W.CELL)
@@ -377,3 +344,65 @@ def test_degenerate_inputs(M):
     err = _rel_l2(got1, ref1.leaves, ref1.leaves)
     _say("refined root only: rel L2 vs oracle", err, "triples", st1["triples"])
     assert err <= TOL
+
+
+def test_allocator_null_gives_nomem_without_leak(M):
+    """An allocator that returns NULL after a given number of allocations: every call ends
+    with MRA_OK or MRA_E_NOMEM (-2), never anything else, and once the handles and the
+    context are freed every allocation has been returned."""
+    import ctypes
+    import torch
+    _say("case: allocator returning NULL")
+    lib = M.load()
+    stream = torch.cuda.current_stream(0).cuda_stream
+    c, a, x = W.unit_charge_gaussians(1, 3, 2, 2.0, 20.0)
+    garr, ng = M._binding._gaussians(c, a, x)
+    outcomes = []
+    for budget in (0, 1, 2, 3, 5, 8, 13, 21, 34, 1000):
+        live, left = {}, [budget]
+
+        def _alloc(nbytes, user):
+            if left[0] <= 0:
+                return None
+            left[0] -= 1
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), 0, stream)
+            live[p] = int(nbytes)
+            return p
+
+        def _free(ptr, user):
+            assert ptr in live
+            del live[ptr]
+            torch.cuda.caching_allocator_delete(ptr)
+
+        af, ff = M._binding.ALLOC_FN(_alloc), M._binding.FREE_FN(_free)
+        h = ctypes.c_void_p()
+        assert lib.mra_ctx_create(0, ctypes.c_void_p(stream), af, ff, None, W.CELL[0], W.CELL[1],
+                                  ctypes.byref(h)) == 0
+        steps = []
+        fh, oh, gh = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        p = M._binding.ProjectParams(8, 1e-4, 2, 20)
+        rc = lib.mra_project(h, garr, ng, ctypes.byref(p), ctypes.byref(fh))
+        steps.append(rc)
+        if rc == 0:
+            rc = lib.mra_op_coulomb(h, 8, 1e-4, 1e-6, ctypes.byref(oh))
+            steps.append(rc)
+        if rc == 0:
+            ap = M._binding.ApplyParams(0, 1, 1e-8, 0.0, 1)
+            rc = lib.mra_apply(h, oh, fh, ctypes.byref(ap), ctypes.byref(gh))
+            steps.append(rc)
+        if rc == 0:
+            v = ctypes.c_double()
+            rc = lib.mra_norm2(h, gh, ctypes.byref(v))
+            steps.append(rc)
+        assert all(s in (0, -2) for s in steps), steps
+        if steps[-1] == -2:
+            assert "allocation" in lib.mra_last_error(h).decode()
+        for hh, fn in ((gh, lib.mra_func_free), (fh, lib.mra_func_free), (oh, lib.mra_op_free)):
+            if hh.value:
+                fn(hh)
+        lib.mra_ctx_free(h)
+        torch.cuda.synchronize()
+        outcomes.append((budget, steps[-1], len(steps)))
+        assert live == {}, "budget %d: %d allocations not returned" % (budget, len(live))
+    _say("allocator budget -> (last status, calls made):", outcomes)
+    assert outcomes[0][1] == -2 and outcomes[-1][1] == 0
