@@ -202,6 +202,17 @@ mra_status mra_apply_batch(mra_ctx* ctx, int n, const mra_op* const* ops,
  *
  * mra_norm2: 2-norm sqrt(sum over leaves ||s||^2) (the basis is orthonormal, Sec. 2.1). */
 mra_status mra_norm2(mra_ctx* ctx, const mra_func* f, double* out);
+/* mra_norm2_noalloc: mra_norm2 for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  It calls no
+ * allocator (neither hipMalloc/hipFree nor the context's callbacks nor any allocating
+ * library routine): the 2048 workgroup partials and their ordered sum live in a fixed
+ * static device array of 2080 doubles (16.3 KiB) per GPU, held until the process ends.
+ * The reduction grid is fixed, so every function fits; the result is bitwise equal to
+ * mra_norm2's (same partials, summed in the same order).  The function's leaf list is
+ * resident on the device from its creation (MRA_E_INVALID otherwise).  Calls on one GPU
+ * share the array: calls that overlap on that GPU (from two streams at once) race.
+ * Synchronises the context's stream. */
+mra_status mra_norm2_noalloc(mra_ctx* ctx, const mra_func* f, double* out);
 /* mra_trace: integral of f over the cell, sum over leaves s_000 h_n^{3/2} (phi_0 is the
  * constant h_n^{-1/2} on its box). */
 mra_status mra_trace(mra_ctx* ctx, const mra_func* f, double* out);

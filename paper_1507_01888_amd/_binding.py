@@ -23,7 +23,7 @@ EXPORTED = [
     "mra_ctx_create", "mra_ctx_free", "mra_last_error", "mra_project", "mra_func_info",
     "mra_func_export", "mra_func_free", "mra_op_coulomb", "mra_op_bsh", "mra_op_gaussians",
     "mra_op_terms", "mra_op_free", "mra_apply", "mra_apply_batch", "mra_norm2", "mra_trace",
-    "mra_inner", "mra_distance",
+    "mra_inner", "mra_distance", "mra_norm2_noalloc",
     "mra_last_stats", "mra_host_fit", "mra_host_block", "mra_host_filters",
     "mra_host_spectral_norm", "mra_host_project",
 ]
@@ -109,6 +109,7 @@ def load():
     lib.mra_trace.argtypes = [vp, vp, dp]
     lib.mra_inner.argtypes = [vp, vp, vp, dp]
     lib.mra_distance.argtypes = [vp, vp, vp, dp]
+    lib.mra_norm2_noalloc.argtypes = [vp, vp, dp]
     lib.mra_last_stats.argtypes = [vp, P(ApplyStats)]
     lib.mra_host_fit.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_int, dp, dp, P(ctypes.c_int)]
@@ -208,7 +209,9 @@ def host_project(cell, coeffs, expnts, centers, k, thresh, initial_level=2, max_
 class Context:
     """A libmra context on one HIP device, backed by torch's caching allocator and stream."""
 
-    def __init__(self, device=0, cell=(-10.0, 10.0), use_torch_allocator=True):
+    def __init__(self, device=0, cell=(-10.0, 10.0), use_torch_allocator=True, on_alloc=None):
+        """on_alloc: optional callable(nbytes) told of every device allocation the library
+        asks for (diagnostics; needs use_torch_allocator)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libmra needs a HIP device")
@@ -223,6 +226,8 @@ class Context:
             sptr = stream.cuda_stream
 
             def _alloc(nbytes, user):
+                if on_alloc is not None:
+                    on_alloc(int(nbytes))
                 try:
                     return torch.cuda.caching_allocator_alloc(int(nbytes), dev, sptr)
                 except Exception:  # noqa: BLE001 - reported to the library as NULL
@@ -319,6 +324,12 @@ class Context:
     def norm2(self, f):
         v = ctypes.c_double()
         self._check(self._lib.mra_norm2(self.h, f.h, ctypes.byref(v)), "mra_norm2")
+        return v.value
+
+    def norm2_noalloc(self, f):
+        """norm2 through the entry point that allocates no device memory."""
+        v = ctypes.c_double()
+        self._check(self._lib.mra_norm2_noalloc(self.h, f.h, ctypes.byref(v)), "mra_norm2_noalloc")
         return v.value
 
     def trace(self, f):

@@ -932,6 +932,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
     for (int i = f0; i < f1; ++i) {
       Func& o = *plans[i].out;
       o.coeff.alloc(ctx, (size_t)o.nodes() * K3);
+      o.device_leaves();
       out_tab[i] = o.coeff.p;
       out_len[i] = (int64_t)o.coeff.n;
       max_len = std::max(max_len, o.coeff.n);

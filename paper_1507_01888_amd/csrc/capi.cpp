@@ -537,6 +537,7 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
   });
   if (bad) fail(MRA_E_INVALID, "internal plan error: standard-form item");
   out.coeff.alloc(ctx, (size_t)out.nodes() * k * k * k);
+  out.device_leaves();
   std::vector<const double*> in_tab{f.coeff.p}, t_tab{op.dT.p}, c_tab{op.d_c.p};
   std::vector<double*> out_tab{out.coeff.p};
   const size_t o_tgt = A.put(tgt), o_in = A.put(in_tab), o_t = A.put(t_tab),
@@ -640,6 +641,7 @@ mra_status mra_ctx_create(int device, void* stream, mra_alloc_fn alloc, mra_free
     c.hi = cell_hi;
     hip_check(hipSetDevice(device), "hipSetDevice");
     for (auto& e : c.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+    static_scratch_init(device);   // this device's address of the allocation-free scratch
     *out = h;
     return MRA_OK;
   } catch (const Error& e) {
@@ -682,6 +684,7 @@ mra_status mra_project(mra_ctx* ctx, const mra_gaussian* g, int ng,
     std::vector<double> coeffs;
     project_gaussians(c, g, ng, p->k, p->thresh, p->initial_level, p->max_level, h->f, coeffs);
     h->f.coeff.upload(c, coeffs);
+    h->f.device_leaves();
     c->sync();
     *out = h.release();
   });
@@ -882,6 +885,21 @@ mra_status mra_norm2(mra_ctx* ctx, const mra_func* fh, double* out) {
     Func& fm = const_cast<mra_func*>(fh)->f;   // device leaf list is made on first use
     double s = reduce(c, f.k, f.coeff.p, nullptr, f.leaves, nullptr, nullptr, 0,
                       fm.device_leaves());
+    *out = std::sqrt(s);
+  });
+}
+
+mra_status mra_norm2_noalloc(mra_ctx* ctx, const mra_func* fh, double* out) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (!fh || !out) fail(MRA_E_INVALID, "mra_norm2_noalloc: bad arguments");
+    const Func& f = fh->f;
+    if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    if (f.d_leaves.n != f.leaves.size())
+      fail(MRA_E_INVALID, "mra_norm2_noalloc: the function's leaf list is not on the device");
+    const double s = norm2_noalloc(c->device, f.k, f.coeff.p, f.d_leaves.p,
+                                   (int64_t)f.leaves.size(), c->stream);
     *out = std::sqrt(s);
   });
 }

@@ -19,6 +19,8 @@
 // across the workgroup.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "mra_internal.hpp"
 
 namespace mra {
@@ -2541,6 +2543,69 @@ void launch_sum_down(int k, double* const* coeff_tab, const NodeRef* refs, int c
   MRA_DISPATCH_K14(k, hipLaunchKernelGGL(sum_down_kernel<KK>, dim3(count), dim3(512), 0, s,
                                          coeff_tab, refs, subbuf, h0, h1));
   hip_check(hipGetLastError(), "sum_down_kernel");
+}
+
+// ---------------------------------------------------------- norm2 without device allocation
+// mra_norm2_noalloc runs the reduction of mra_norm2 (leaf_reduce_kernel, 2048 workgroup
+// partials) with its partials and their ordered sum in a file-scope device array instead
+// of memory from the context's allocator.  Each GPU holds its own copy of the array, at its
+// own address, until the process ends; host code uses only that address (obtained once per
+// device with hipGetSymbolAddress), never the array's name.  Every workgroup writes its
+// partial, so nothing has to be cleared between calls; calls that overlap on one GPU (two
+// streams at once) race on the array.
+namespace {
+constexpr int kScratchParts = 2048;                    // fixed reduction grid
+constexpr int kScratchDoubles = kScratchParts + 32;    // partials, then the ordered sum
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// Sums p[0 .. n) in index order (the order of the host sum of mra_norm2) into *out.
+__global__ void ordered_sum_kernel(const double* __restrict__ p, int n, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += p[i];
+  *out = s;
+}
+
+std::mutex g_scratch_mutex;
+double* g_scratch_addr[64] = {};
+}  // namespace
+
+double* static_scratch_init(int device) {
+  if (device < 0 || device >= 64) fail(MRA_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[device]) {
+    int cur = -1;
+    hip_check(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != device) hip_check(hipSetDevice(device), "hipSetDevice");
+    double* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) hip_check(hipSetDevice(cur), "hipSetDevice");
+    hip_check(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) fail(MRA_E_DEVICE, "hipGetSymbolAddress(scratch) returned no address");
+    g_scratch_addr[device] = ptr;
+  }
+  return g_scratch_addr[device];
+}
+
+double norm2_noalloc(int device, int k, const double* coeff, const int32_t* leaves_dev,
+                     int64_t count, hipStream_t s) {
+  static_assert(kScratchParts + 1 <= kScratchDoubles, "partials and their sum fit");
+  if (k < 2 || k > kMaxK) fail(MRA_E_INVALID, "mra_norm2_noalloc: k must be in [2, 14]");
+  if (count <= 0) return 0.0;
+  if (count > INT32_MAX) fail(MRA_E_INVALID, "mra_norm2_noalloc: more than 2^31 - 1 leaves");
+  if (!leaves_dev || !coeff) fail(MRA_E_INVALID, "mra_norm2_noalloc: function not resident");
+  double* base = static_scratch_init(device);
+  hipLaunchKernelGGL(leaf_reduce_kernel, dim3(kScratchParts), dim3(256), 0, s, k * k * k, coeff,
+                     nullptr, leaves_dev, nullptr, nullptr, (int)count, 0, base);
+  hip_check(hipGetLastError(), "leaf_reduce_kernel");
+  hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(64), 0, s, base, kScratchParts,
+                     base + kScratchParts);
+  hip_check(hipGetLastError(), "ordered_sum_kernel");
+  double sum = 0.0;
+  hip_check(hipMemcpyAsync(&sum, base + kScratchParts, sizeof(double), hipMemcpyDeviceToHost, s),
+            "hipMemcpyAsync D2H");
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return sum;
 }
 
 void launch_leaf_reduce(int k, const double* a, const double* b, const int32_t* leaves_a,

@@ -320,6 +320,12 @@ void launch_leaf_reduce(int k, const double* a, const double* b, const int32_t* 
                         const int32_t* leaves_b, const double* weight, int count, int mode,
                         double* partial, int nblocks, hipStream_t s);
 
+// Allocation-free norm2: address of this device's static scratch array (looked up once per
+// device with hipGetSymbolAddress) and the reduction into it; returns sum ||s_leaf||^2.
+double* static_scratch_init(int device);
+double norm2_noalloc(int device, int k, const double* coeff, const int32_t* leaves_dev,
+                     int64_t count, hipStream_t s);
+
 // Host drivers
 void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
                              const std::vector<Func*>& funcs, double tau, double tau_tier,
