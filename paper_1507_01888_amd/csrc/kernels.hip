@@ -783,9 +783,20 @@ __device__ __forceinline__ void lds_copy16(const double* base, int nbytes, MRA_L
   __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 16, voff, 0, 0, 0);
 }
 
+// The value of v, opaque to the optimiser (it cannot hoist computations on the result out
+// of the enclosing loop).
+__device__ __forceinline__ int opaque_int(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 template <int B>
 struct BufTag {
   static constexpr int value = B;
+};
+template <bool B>
+struct BoolTag {
+  static constexpr bool value = B;
 };
 // ------------------------------------------------------------ apply (NS, MFMA, factored)
 // FP64 matrix-core kernel for k = 10 that shares contractions between the triples of a
@@ -1924,82 +1935,90 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
 
 // ----------------------------------------- apply (NS, MFMA, source streamed in z-slabs)
 // FP64 matrix-core kernel for k = 14 (2k = 28 = 4Q, Q = 7), whose (2k)^3 children block
-// (172 KB) does not fit in LDS.  Each wave owns whole a-quads (sets of 2, 2, 2, 1), so it
-// completes the three contractions of its a-quads itself (the step-2 result is permuted
-// in-wave into the step-3 operand as in apply_ns_own_kernel) and accumulates step 3 one
-// z-quad at a time.  A triple is therefore processed in Q stages, one per z-quad: stage zq
-// needs only the slab B_P[.][.][4zq .. 4zq+3] (25 KB), which is double buffered in LDS and
-// loaded from L2 one stage ahead (the next triple's first slab during the last stage).  The
-// subtraction (KP = 16, one a-quad per wave) runs in the first KP/4 stages on s_P, resident
-// in LDS per source.  One workgroup barrier per stage.
+// (172 KB) does not fit in LDS.  A triple is processed in Q stages, one per z-quad: stage
+// zq needs only the slab B_P[.][.][4zq .. 4zq+3] (25 KB), which is double buffered in LDS
+// and copied from L2 one stage ahead (the next triple's first slab during the last stage)
+// by buffer loads that write LDS directly.  Each of waves 0-2 owns two a-quads and runs
+// the three contractions of both itself: step 1 (contract x; block index = z inside the
+// z-quad) and step 2 (contract y) chain in registers, the step-2 result is permuted
+// in-wave into the step-3 operand (contract the z-quad's four z), and step 3 accumulates
+// into the target's block in registers; the two a-quads share every LDS operand read.
+// Wave 3 owns the seventh a-quad and the level-n subtraction -c (t x t x t) s_P (s_P
+// resident in LDS per source; k = 14 is padded to 16 by masking the t fragments), whose
+// 16 (a-quad, z-quad) units run in stages 0-5 (3, 3, 3, 3, 2, 2 units), so that every SIMD
+// carries about the same number of products per stage.  Operator blocks of the next triple
+// are loaded into registers during stage 5 and stored to the other half of an LDS double
+// buffer after stage 6.  Persistent workgroups take target ranges, longest first, from a
+// counter.
 template <int K>
 __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
     const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
     const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
     const double* const* __restrict__ r_tab, const double* const* __restrict__ t_tab,
     const double* const* __restrict__ c_tab, double* __restrict__ partials,
-    double* __restrict__ subbuf) {
+    double* __restrict__ subbuf, const int ntargets, int* __restrict__ next_target) {
   constexpr int N = 2 * K, Q = N / 4, N2 = N * N, N3 = N * N * N, K2 = K * K, K3 = K * K * K;
-  static_assert(N % 4 == 0 && Q == 7, "k = 14");
-  constexpr int Q2 = (K + 3) / 4, KP = 4 * Q2;
-  static_assert(Q2 == 4, "one subtraction a-quad per wave");
-  constexpr int SLY = 4, SLX = N * SLY, SLAB = N * SLX;     // slab [x][y][z in quad]
+  static_assert(K == 14 && Q == 7, "the wave split below is for k = 14");
+  constexpr int Q2 = (K + 3) / 4;                              // subtraction quads (4)
+  static_assert(Q2 == 4, "sixteen subtraction units");
+  constexpr int SLY = 4, SLX = N * SLY, SLAB = N * SLX;        // slab [x][y][z in quad]
   static_assert(quarter_distinct(SLX, SLY), "slab strides");
-  constexpr int SLAB_PER_LANE = (SLAB + 255) / 256;
-  constexpr int OPS = 3 * N2 + 3 * K2, OPS_PER_LANE = (OPS + 255) / 256;
-  __shared__ double Xl[2][SLAB];
-  __shared__ double Ss[KP * KP * KP];   // s_P zero-padded, quad-blocked
+  // slab copy: granule g = 2 (x N + y) + h holds (x, y, 4 zq + 2h .. 4 zq + 2h + 1), so a
+  // granule never straddles two children (k even); rows of 64 granules, row r by wave r % 4
+  constexpr int SG = SLAB / 2, SROWS = (SG + 63) / 64, SPAD = 128 * SROWS, SRPW = (SROWS + 3) / 4;
+  static_assert(SROWS == 25 && SRPW == 7, "wave 0 copies 7 slab rows, waves 1-3 six");
+  // operator buffer: R_x^T, R_y^T, R_z^T (N^2 each), then t_x^T, t_y^T, t_z^T (K^2 each in
+  // slots of TSLOT, whose tails stay zero: a padded fragment read stays inside its slot)
+  constexpr int RL = (N2 + 255) / 256, TSLOT = 256, OPS = 3 * N2 + 3 * TSLOT;
+  static_assert(K2 <= 256 && (4 * Q2 - 1) * K + 4 * Q2 - 1 < TSLOT, "t slot");
+  // s_P, row-major [x][y][z] as stored (granule copies), zero tail up to SSPAD: padded
+  // fragment reads (x, y, z < 16) stay inside
+  constexpr int SSG = K3 / 2, SSROWS = (SSG + 63) / 64, SSRPW = (SSROWS + 3) / 4;
+  constexpr int SSPAD = ((15 * K2 + 15 * K + 16 + 127) / 128) * 128;
+  static_assert(SSPAD >= 128 * SSROWS, "s_P rows fit");
+  __shared__ __attribute__((aligned(16))) double Xl0[SPAD];
+  __shared__ __attribute__((aligned(16))) double Xl1[SPAD];
   __shared__ double Os[2][OPS];
+  __shared__ __attribute__((aligned(16))) double Ss[SSPAD];
+  __shared__ int s_next;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
   const int swap = (16 * lb + 4 * lk + li) * 4;
-  const TargetRange tr = targets[blockIdx.x];
-  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
-  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
-  const MRA_GLOBAL double* __restrict__ dR = as_global(r_tab[tr.fn]);
-  const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
-  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
-  const bool with_sub = tr.sub >= 0;
-  const int at_lo = 2 * wave, at_n = wave < 3 ? 2 : 1;     // a-quads of this wave
-  const int sat = wave;                                    // subtraction a-quad
+  // padding that no copy writes is zero once and for all (fragment reads of padded quads
+  // multiply it by zero operator entries, so it must be finite)
+  for (int e = tid; e < SSPAD; e += 256) Ss[e] = 0.0;
+  for (int e = tid; e < 2 * OPS; e += 256) (&Os[0][0])[e] = 0.0;
 
-  auto fetch_ops = [&](const NSItem nx, double* reg) {
+  // this lane's granule offsets (doubles from the first child's slab) without the z part,
+  // for its wave's slab rows; rows past the block read zeros into padding
+  int soff[SRPW];
 #pragma unroll
-    for (int q = 0; q < OPS_PER_LANE; ++q) {
-      const int e = tid + 256 * q;
-      double v = 0.0;
-      if (e < 3 * N2) {
-        const int w = e / N2, r = e - w * N2;
-        const int blk = w == 0 ? nx.rx : (w == 1 ? nx.ry : nx.rz);
-        v = dR[(size_t)blk * N2 + r];
-      } else if (e < OPS) {
-        const int e2 = e - 3 * N2, w = e2 / K2, r = e2 - w * K2;
-        const int blk = w == 0 ? nx.tx : (w == 1 ? nx.ty : nx.tz);
-        v = dT[(size_t)blk * K2 + r];
-      }
-      reg[q] = v;
+  for (int q = 0; q < SRPW; ++q) {
+    const int g = 64 * (wave + 4 * q) + lane;
+    if (g < SG) {
+      const int x = g / (2 * N), y = (g / 2) % N;
+      soff[q] = (((x / K) << 2) | ((y / K) << 1)) * K3 + ((x % K) * K + y % K) * K;
+    } else {
+      soff[q] = 8 * K3;                                        // past the descriptor's end
     }
+  }
+  auto copy_slab = [&](const double* in_g, const int fc, const int zq, double* dst) {
+    const int z0 = 4 * zq + 2 * (lane & 1);
+    const int zoff = z0 >= K ? K3 + z0 - K : z0;
+#pragma unroll
+    for (int q = 0; q < SRPW; ++q)
+      if (wave + 4 * q < SROWS)
+        lds_copy16(in_g + (size_t)fc * K3, 8 * K3 * 8, (MRA_LDS void*)(dst + 128 * (wave + 4 * q)),
+                   8 * (soff[q] + zoff));
   };
-  auto fetch_slab = [&](int fc, int zq, double* reg) {
+  // s_P (K3 doubles) into Ss, granule by granule
+  auto copy_sp = [&](const double* in_g, const int src) {
 #pragma unroll
-    for (int q = 0; q < SLAB_PER_LANE; ++q) {
-      const int e = tid + 256 * q;
-      double v = 0.0;
-      if (e < SLAB) {
-        const int x = e / SLX, y = (e / SLY) % N, z = 4 * zq + e % SLY;
-        const int child = ((x / K) << 2) | ((y / K) << 1) | (z / K);
-        v = in[(size_t)(fc + child) * K3 + ((x % K) * K + (y % K)) * K + (z % K)];
-      }
-      reg[q] = v;
-    }
-  };
-  auto store_slab = [&](const double* reg, double* dst) {
-#pragma unroll
-    for (int q = 0; q < SLAB_PER_LANE; ++q) {
-      const int e = tid + 256 * q;
-      if (e < SLAB) dst[e] = reg[q];
-    }
+    for (int q = 0; q < SSRPW; ++q)
+      if (wave + 4 * q < SSROWS)
+        lds_copy16(in_g + (size_t)src * K3, K3 * 8, (MRA_LDS void*)(Ss + 128 * (wave + 4 * q)),
+                   16 * (64 * (wave + 4 * q) + lane));
   };
   auto lane_swap = [&](double v) {
     const int2 w = __builtin_bit_cast(int2, v);
@@ -2008,87 +2027,188 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
     r.y = __builtin_amdgcn_ds_bpermute(swap, w.y);
     return __builtin_bit_cast(double, r);
   };
+  __syncthreads();
 
-  double acc[2][Q][Q];
-#pragma unroll
-  for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-    for (int b = 0; b < Q; ++b)
-#pragma unroll
-      for (int c = 0; c < Q; ++c) acc[s2][b][c] = 0.0;
-  double sacc[Q2][Q2];
-#pragma unroll
-  for (int b = 0; b < Q2; ++b)
-#pragma unroll
-    for (int c = 0; c < Q2; ++c) sacc[b][c] = 0.0;
+  // The two roles (waves 0-2: two a-quads; wave 3: one a-quad and the subtraction) run
+  // separate instances of the loop, so that each keeps only its own accumulators live;
+  // both execute the same sequence of barriers.
+  auto run = [&](auto role_tag) {
+    constexpr bool sub_wave = decltype(role_tag)::value;
+    const int at0 = sub_wave ? Q - 1 : 2 * wave, at1 = 2 * wave + 1;
+    for (;;) {
+      if (tid == 0) s_next = atomicAdd(next_target, 1);
+      __syncthreads();
+      const int ti = s_next;
+      __syncthreads();   // every wave has read s_next (and is done with the previous range)
+      if (ti >= ntargets) break;
+      const TargetRange tr = targets[ti];
+      const double* const in_g = in_tab[tr.fn];
+      MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
+      const MRA_GLOBAL double* __restrict__ dR = as_global(r_tab[tr.fn]);
+      const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
+      const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
+      const bool with_sub = tr.sub >= 0;
 
-  double opre[OPS_PER_LANE], spre[SLAB_PER_LANE];
-  if (tr.beg < tr.end) {
-    fetch_ops(items[tr.beg], opre);
-    fetch_slab(items[tr.beg].src_fc, 0, spre);
+      // operator blocks of a triple: element tid + 256 q of each block
+      double opre[3 * RL + 3];
+      auto fetch_ops = [&](const NSItem& nx) {
 #pragma unroll
-    for (int q = 0; q < OPS_PER_LANE; ++q) {
-      const int e = tid + 256 * q;
-      if (e < OPS) Os[tr.beg & 1][e] = opre[q];
-    }
-    store_slab(spre, Xl[0]);
-  }
-  int sloaded = -1, buf = 0;
-  NSItem cur{};   // item record and c_mu of this triple, loaded one triple ahead
-  double c_cur = 0.0, c_pre = 0.0;
-  if (tr.beg < tr.end) {
-    cur = items[tr.beg];
-    c_cur = dc[cur.mu];
-  }
-  for (int it = tr.beg; it < tr.end; ++it) {
-    const NSItem item = cur;
-    const bool more = it + 1 < tr.end;
-    const NSItem nxt = more ? items[it + 1] : item;
-    const int next_fc = more ? nxt.src_fc : -1;
-    if (with_sub && item.src_fc != sloaded) {
-      __syncthreads();   // nobody reads the previous s_P any more
-      const MRA_GLOBAL double* __restrict__ sp = in + (size_t)item.src * K3;
-      for (int e = tid; e < KP * KP * KP; e += 256) {
-        const int x = e / (KP * KP), y = (e / KP) % KP, z = e % KP;
-        Ss[qb_off<Q2>(x, y, z)] = (x < K && y < K && z < K) ? sp[(x * K + y) * K + z] : 0.0;
+        for (int w = 0; w < 3; ++w) {
+          const MRA_GLOBAL double* __restrict__ src =
+              dR + (size_t)(w == 0 ? nx.rx : w == 1 ? nx.ry : nx.rz) * N2;
+#pragma unroll
+          for (int q = 0; q < RL; ++q)
+            opre[w * RL + q] = (tid + 256 * q < N2) ? src[tid + 256 * q] : 0.0;
+        }
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+          const MRA_GLOBAL double* __restrict__ src =
+              dT + (size_t)(w == 0 ? nx.tx : w == 1 ? nx.ty : nx.tz) * K2;
+          opre[3 * RL + w] = tid < K2 ? src[tid] : 0.0;
+        }
+      };
+      auto store_ops = [&](double* dst) {
+#pragma unroll
+        for (int w = 0; w < 3; ++w)
+#pragma unroll
+          for (int q = 0; q < RL; ++q)
+            if (tid + 256 * q < N2) dst[w * N2 + tid + 256 * q] = opre[w * RL + q];
+#pragma unroll
+        for (int w = 0; w < 3; ++w)
+          if (tid < K2) dst[3 * N2 + w * TSLOT + tid] = opre[3 * RL + w];
+      };
+
+      // accumulators: waves 0-2 keep their two a-quads' blocks; wave 3 its a-quad in acc0
+      // and the subtraction block (4 a-quads x 4 b-quads x 4 c-quads) in acc1
+      constexpr int A1 = sub_wave ? Q2 * Q2 * Q2 : Q * Q;
+      double acc0[Q][Q], acc1[A1];
+#pragma unroll
+      for (int b = 0; b < Q; ++b)
+#pragma unroll
+        for (int c = 0; c < Q; ++c) acc0[b][c] = 0.0;
+#pragma unroll
+      for (int e = 0; e < A1; ++e) acc1[e] = 0.0;
+
+      // the current triple needs its source (children block and s_P) and c_mu; the next
+      // one its whole record
+      int cur_fc = 0, cur_src = -1;
+      double c_cur = 0.0;
+      NSItem nxt{};
+      if (tr.beg < tr.end) {
+        const NSItem first = items[tr.beg];
+        cur_fc = first.src_fc;
+        cur_src = first.src;
+        c_cur = dc[first.mu];
+        nxt = items[min(tr.beg + 1, tr.end - 1)];
+        copy_slab(in_g, cur_fc, 0, Xl0);
+        if (with_sub) copy_sp(in_g, cur_src);
+        fetch_ops(first);
+        store_ops(Os[0]);
       }
-      sloaded = item.src_fc;
-    }
-    if (more) {
-      fetch_ops(nxt, opre);
-      c_pre = dc[nxt.mu];
-    }
-    const double* Ob = Os[it & 1];
-    const double* RXs = Ob;
-    const double* RYs = Ob + N2;
-    const double* RZs = Ob + 2 * N2;
-    const double* TXs = Ob + 3 * N2;
-    const double* TYs = Ob + 3 * N2 + K2;
-    const double* TZs = Ob + 3 * N2 + 2 * K2;
-    const double cmu = c_cur;
-#pragma unroll 1
-    for (int zq = 0; zq < Q; ++zq) {
-      __syncthreads();   // slab zq (and this triple's operators, s_P) are in place
-      // next stage's slab: this triple's zq + 1, or the next triple's first slab
-      const bool pf = zq + 1 < Q || more;
-      if (pf) fetch_slab(zq + 1 < Q ? item.src_fc : next_fc, zq + 1 < Q ? zq + 1 : 0, spre);
-      const double* X = Xl[buf];
+      int it = tr.beg, zq = 0;
+      const int nstages = Q * (tr.end - tr.beg);
+
+      auto stage = [&](auto buf_tag) {
+        constexpr int buf = decltype(buf_tag)::value;
+        double* const Xc = buf == 0 ? Xl0 : Xl1;     // this stage's slab
+        double* const Xn = buf == 0 ? Xl1 : Xl0;     // the next stage's slab
+        __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): this wave's copies landed
+        __syncthreads();                             // all copies landed; the other half is free
+        const bool more = it + 1 < tr.end;
+        if (zq + 1 < Q)
+          copy_slab(in_g, cur_fc, zq + 1, Xn);
+        else if (more)
+          copy_slab(in_g, nxt.src_fc, 0, Xn);
+        // s_P of the next triple's source (wave 3 reads s_P in stages 0-5 only)
+        if (zq + 1 == Q && more && with_sub && nxt.src != cur_src) copy_sp(in_g, nxt.src);
+        if (zq + 2 == Q && more) fetch_ops(nxt);
+        const int ob = (it - tr.beg) & 1;
+        const double* RXs = Os[ob];
+        const double* RYs = Os[ob] + N2;
+        const double* RZs = Os[ob] + 2 * N2;
+        const double cmu = c_cur;
+        const double* X = Xc;
+        double rz[Q];
 #pragma unroll
-      for (int s2 = 0; s2 < 2; ++s2) {
-        if (s2 < at_n) {
-          const int at = at_lo + s2;
-          double rx[Q];
+        for (int ct = 0; ct < Q; ++ct) rz[ct] = cmu * RZs[(4 * zq + lk) * N + 4 * ct + li];
+        if constexpr (!sub_wave) {
+          // ---- two a-quads: step 1, operands of x-quad xs + 1 read during xs
+          double d1a[Q], d1b[Q];
 #pragma unroll
-          for (int xs = 0; xs < Q; ++xs) rx[xs] = RXs[(4 * xs + lk) * N + 4 * at + li];
+          for (int yt = 0; yt < Q; ++yt) d1a[yt] = d1b[yt] = 0.0;
+          double xa[2][Q], ra[2], rb[2];
+          auto load1 = [&](const int xs, const int b) {
+#pragma unroll
+            for (int yt = 0; yt < Q; ++yt) xa[b][yt] = X[(4 * xs + lk) * SLX + (4 * yt + li) * SLY + lb];
+            ra[b] = RXs[(4 * xs + lk) * N + 4 * at0 + li];
+            rb[b] = RXs[(4 * xs + lk) * N + 4 * at1 + li];
+          };
+          load1(0, 0);
+#pragma unroll
+          for (int xs = 0; xs < Q; ++xs) {
+            const int b = xs & 1;
+            if (xs + 1 < Q) load1(xs + 1, b ^ 1);
+#pragma unroll
+            for (int yt = 0; yt < Q; ++yt) {
+              d1a[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[b][yt], ra[b], d1a[yt], 0, 0, 0);
+              d1b[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[b][yt], rb[b], d1b[yt], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          // ---- step 2 (contract y), R_y fragments of y-quad ys + 1 read during ys
+          double zra[Q], zrb[Q];
+#pragma unroll
+          for (int bt = 0; bt < Q; ++bt) zra[bt] = zrb[bt] = 0.0;
+          double ry[2][Q];
+          auto load2 = [&](const int ys, const int b) {
+#pragma unroll
+            for (int bt = 0; bt < Q; ++bt) ry[b][bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+          };
+          load2(0, 0);
+#pragma unroll
+          for (int ys = 0; ys < Q; ++ys) {
+            const int b = ys & 1;
+            if (ys + 1 < Q) load2(ys + 1, b ^ 1);
+#pragma unroll
+            for (int bt = 0; bt < Q; ++bt) {
+              zra[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1a[ys], ry[b][bt], zra[bt], 0, 0, 0);
+              zrb[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1b[ys], ry[b][bt], zrb[bt], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          // ---- step 3 (contract the z-quad) into the target's block
+#pragma unroll
+          for (int bt = 0; bt < Q; ++bt) {
+            const double za = lane_swap(zra[bt]);
+            const double zb = lane_swap(zrb[bt]);
+#pragma unroll
+            for (int ct = 0; ct < Q; ++ct) {
+              acc0[bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(za, rz[ct], acc0[bt][ct], 0, 0, 0);
+              acc1[bt * Q + ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(zb, rz[ct], acc1[bt * Q + ct], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        } else {
+          // ---- wave 3: a-quad 6
           double d1[Q];
 #pragma unroll
           for (int yt = 0; yt < Q; ++yt) d1[yt] = 0.0;
+          double xa[2][Q], ra[2];
+          auto load1 = [&](const int xs, const int b) {
 #pragma unroll
-          for (int xs = 0; xs < Q; ++xs)
+            for (int yt = 0; yt < Q; ++yt) xa[b][yt] = X[(4 * xs + lk) * SLX + (4 * yt + li) * SLY + lb];
+            ra[b] = RXs[(4 * xs + lk) * N + 4 * at0 + li];
+          };
+          load1(0, 0);
+#pragma unroll
+          for (int xs = 0; xs < Q; ++xs) {
+            const int b = xs & 1;
+            if (xs + 1 < Q) load1(xs + 1, b ^ 1);
 #pragma unroll
             for (int yt = 0; yt < Q; ++yt)
-              d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
-                  X[(4 * xs + lk) * SLX + (4 * yt + li) * SLY + lb], rx[xs], d1[yt], 0, 0, 0);
+              d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[b][yt], ra[b], d1[yt], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+          }
           double zr[Q];
 #pragma unroll
           for (int bt = 0; bt < Q; ++bt) zr[bt] = 0.0;
@@ -2100,108 +2220,148 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 #pragma unroll
             for (int bt = 0; bt < Q; ++bt)
               zr[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ry[bt], zr[bt], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
           }
-          double rz[Q];
-#pragma unroll
-          for (int ct = 0; ct < Q; ++ct) rz[ct] = cmu * RZs[(4 * zq + lk) * N + 4 * ct + li];
 #pragma unroll
           for (int bt = 0; bt < Q; ++bt) {
-            const double zt = lane_swap(zr[bt]);
+            const double za = lane_swap(zr[bt]);
 #pragma unroll
             for (int ct = 0; ct < Q; ++ct)
-              acc[s2][bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(zt, rz[ct], acc[s2][bt][ct], 0, 0, 0);
+              acc0[bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(za, rz[ct], acc0[bt][ct], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          // ---- the level-n subtraction units of this stage: (sa, sz), sa fixed per call
+          if (with_sub && zq < 6) {
+            const double* TXs = Os[ob] + 3 * N2;
+            const double* TYs = TXs + TSLOT;
+            const double* TZs = TXs + 2 * TSLOT;
+            // fragment (row r, column c) of a transposed t block, zero outside k x k
+            auto tfrag = [&](const double* T, const int r, const int c) {
+              const double v = T[r * K + c];
+              return (r < K && c < K) ? v : 0.0;
+            };
+            auto unit = [&](auto sa_tag, const int sz) {
+              constexpr int sa = decltype(sa_tag)::value;
+              double tx[Q2];
+#pragma unroll
+              for (int xs = 0; xs < Q2; ++xs) tx[xs] = tfrag(TXs, 4 * xs + lk, 4 * sa + li);
+              double e1[Q2];
+#pragma unroll
+              for (int yt = 0; yt < Q2; ++yt) e1[yt] = 0.0;
+#pragma unroll
+              for (int xs = 0; xs < Q2; ++xs)
+#pragma unroll
+                for (int yt = 0; yt < Q2; ++yt)
+                  e1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                      Ss[((4 * xs + lk) * K + 4 * yt + li) * K + 4 * sz + lb], tx[xs], e1[yt], 0, 0, 0);
+              double e2[Q2];
+#pragma unroll
+              for (int bt = 0; bt < Q2; ++bt) e2[bt] = 0.0;
+#pragma unroll
+              for (int ys = 0; ys < Q2; ++ys)
+#pragma unroll
+                for (int bt = 0; bt < Q2; ++bt)
+                  e2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                      e1[ys], tfrag(TYs, 4 * ys + lk, 4 * bt + li), e2[bt], 0, 0, 0);
+              double tz[Q2];
+#pragma unroll
+              for (int ct = 0; ct < Q2; ++ct) tz[ct] = -cmu * tfrag(TZs, 4 * sz + lk, 4 * ct + li);
+#pragma unroll
+              for (int bt = 0; bt < Q2; ++bt) {
+                const double zt = lane_swap(e2[bt]);
+#pragma unroll
+                for (int ct = 0; ct < Q2; ++ct)
+                  acc1[((sa * Q2 + bt) * Q2 + ct) % A1] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                      zt, tz[ct], acc1[((sa * Q2 + bt) * Q2 + ct) % A1], 0, 0, 0);
+              }
+              __builtin_amdgcn_sched_barrier(0);
+            };
+            if (zq < 4) {
+              unit(BufTag<0>{}, zq);
+              unit(BufTag<1>{}, zq);
+              unit(BufTag<2>{}, zq);
+            } else {
+              unit(BufTag<3>{}, 2 * (zq - 4));
+              unit(BufTag<3>{}, 2 * (zq - 4) + 1);
+            }
           }
         }
+        // the next triple's operators into the other half: its last reader was triple
+        // it - 1, finished before this triple's first barrier
+        if (zq + 1 == Q && more) store_ops(Os[ob ^ 1]);
+        // advance
+        if (++zq == Q) {
+          zq = 0;
+          ++it;
+          cur_fc = nxt.src_fc;
+          cur_src = nxt.src;
+          c_cur = dc[nxt.mu];
+          nxt = items[min(it + 1, tr.end - 1)];
+        }
+      };
+      for (int s = 0; s < nstages; s += 2) {
+        stage(BufTag<0>{});
+        if (s + 1 < nstages) stage(BufTag<1>{});
       }
-      if (with_sub && zq < Q2) {
-        double tx[Q2];
+      // ---- write the target's blocks (each element owned by exactly one lane).  The lane
+      // indices pass through an empty asm statement, so that the compiler recomputes the
+      // output offsets here instead of keeping ~100 of them live across the whole loop.
+      const int wl = opaque_int(lane);
+      const int li = wl & 3, lb = (wl >> 2) & 3, lk = wl >> 4;
+      constexpr int nq = sub_wave ? 1 : 2;
 #pragma unroll
-        for (int xs = 0; xs < Q2; ++xs) {
-          const int r = 4 * xs + lk, cc = 4 * sat + li;
-          tx[xs] = (r < K && cc < K) ? TXs[r * K + cc] : 0.0;
-        }
-        double d1[Q2];
+      for (int s2 = 0; s2 < nq; ++s2) {
+        const int a = 4 * (s2 == 0 ? at0 : at1) + lb;
 #pragma unroll
-        for (int yt = 0; yt < Q2; ++yt) d1[yt] = 0.0;
-#pragma unroll
-        for (int xs = 0; xs < Q2; ++xs)
-#pragma unroll
-          for (int yt = 0; yt < Q2; ++yt)
-            d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
-                Ss[qb_off<Q2>(4 * xs + lk, 4 * yt + li, 4 * zq + lb)], tx[xs], d1[yt], 0, 0, 0);
-        double zr[Q2];
-#pragma unroll
-        for (int bt = 0; bt < Q2; ++bt) zr[bt] = 0.0;
-#pragma unroll
-        for (int ys = 0; ys < Q2; ++ys)
-#pragma unroll
-          for (int bt = 0; bt < Q2; ++bt) {
-            const int r = 4 * ys + lk, cc = 4 * bt + li;
-            const double ty = (r < K && cc < K) ? TYs[r * K + cc] : 0.0;
-            zr[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ty, zr[bt], 0, 0, 0);
-          }
-        double tz[Q2];
-#pragma unroll
-        for (int ct = 0; ct < Q2; ++ct) {
-          const int r = 4 * zq + lk, cc = 4 * ct + li;
-          tz[ct] = (r < K && cc < K) ? -cmu * TZs[r * K + cc] : 0.0;
-        }
-#pragma unroll
-        for (int bt = 0; bt < Q2; ++bt) {
-          const double zt = lane_swap(zr[bt]);
-#pragma unroll
-          for (int ct = 0; ct < Q2; ++ct)
-            sacc[bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(zt, tz[ct], sacc[bt][ct], 0, 0, 0);
-        }
-      }
-      if (pf) store_slab(spre, Xl[buf ^ 1]);
-      if (zq + 1 == Q && more) {
-#pragma unroll
-        for (int q = 0; q < OPS_PER_LANE; ++q) {
-          const int e = tid + 256 * q;
-          if (e < OPS) Os[(it + 1) & 1][e] = opre[q];
-        }
-      }
-      buf ^= 1;
-    }
-    cur = nxt;
-    c_cur = c_pre;
-  }
-  // ---- each element of the target's blocks is owned by exactly one lane
-#pragma unroll
-  for (int s2 = 0; s2 < 2; ++s2) {
-    if (s2 < at_n) {
-      const int a = 4 * (at_lo + s2) + lb;
-#pragma unroll
-      for (int bt = 0; bt < Q; ++bt)
-#pragma unroll
-        for (int ct = 0; ct < Q; ++ct) {
-          const int b = 4 * bt + lk, c = 4 * ct + li;
+        for (int bt = 0; bt < Q; ++bt) {
+          const int b = 4 * bt + lk;
           if (tr.partial >= 0) {
-            partials[(size_t)tr.partial * (N3 + K3) + (a * N + b) * N + c] = acc[s2][bt][ct];
+#pragma unroll
+            for (int ct = 0; ct < Q; ++ct)
+              partials[(size_t)tr.partial * (N3 + K3) + (a * N + b) * N + 4 * ct + li] =
+                  s2 == 0 ? acc0[bt][ct] : acc1[(bt * Q + ct) % A1];
           } else {
-            const int child = ((a / K) << 2) | ((b / K) << 1) | (c / K);
-            out[(size_t)(tr.fc + child) * K3 + ((a % K) * K + (b % K)) * K + (c % K)] +=
-                acc[s2][bt][ct];
+            // a row of Q elements: all loads first, then the sums and stores
+            size_t off[Q];
+            double o[Q];
+#pragma unroll
+            for (int ct = 0; ct < Q; ++ct) {
+              const int c = 4 * ct + li;
+              const int child = ((a / K) << 2) | ((b / K) << 1) | (c / K);
+              off[ct] = (size_t)(tr.fc + child) * K3 + ((a % K) * K + (b % K)) * K + (c % K);
+              o[ct] = out[off[ct]];
+            }
+#pragma unroll
+            for (int ct = 0; ct < Q; ++ct)
+              out[off[ct]] = o[ct] + (s2 == 0 ? acc0[bt][ct] : acc1[(bt * Q + ct) % A1]);
           }
         }
-    }
-  }
-  if (with_sub) {
-    const int a = 4 * sat + lb;
+      }
+      if (sub_wave && with_sub) {
 #pragma unroll
-    for (int bt = 0; bt < Q2; ++bt)
+        for (int sa = 0; sa < Q2; ++sa) {
+          const int a = 4 * sa + lb;
 #pragma unroll
-      for (int ct = 0; ct < Q2; ++ct) {
-        const int b = 4 * bt + lk, c = 4 * ct + li;
-        if (a < K && b < K && c < K) {
-          if (tr.partial >= 0)
-            partials[(size_t)tr.partial * (N3 + K3) + N3 + (a * K + b) * K + c] = sacc[bt][ct];
-          else
-            subbuf[(size_t)tr.sub * K3 + (a * K + b) * K + c] = sacc[bt][ct];
+          for (int bt = 0; bt < Q2; ++bt)
+#pragma unroll
+            for (int ct = 0; ct < Q2; ++ct) {
+              const int b = 4 * bt + lk, c = 4 * ct + li;
+              if (a < K && b < K && c < K) {
+                const double v = acc1[((sa * Q2 + bt) * Q2 + ct) % A1];
+                if (tr.partial >= 0)
+                  partials[(size_t)tr.partial * (N3 + K3) + N3 + (a * K + b) * K + c] = v;
+                else
+                  subbuf[(size_t)tr.sub * K3 + (a * K + b) * K + c] = v;
+              }
+            }
         }
       }
-  }
+    }
+  };
+  if (wave == 3)
+    run(BoolTag<true>{});
+  else
+    run(BoolTag<false>{});
 }
 
 // ------------------------------------------------------------- apply (low tier, BF16)
@@ -2507,8 +2667,11 @@ void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
     hipLaunchKernelGGL(apply_ns_own_kernel<12>, dim3(ntargets), dim3(256), 0, s, in_tab,
                        out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
   } else if (k == 14) {
-    hipLaunchKernelGGL(apply_ns_stream_kernel<14>, dim3(ntargets), dim3(256), 0, s, in_tab,
-                       out_tab, items, targets, r_tab, t_tab, c_tab, partials, subbuf);
+    // one persistent workgroup per CU (the kernel's LDS allows one), ranges from a counter
+    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, counter, 1, 0);
+    hipLaunchKernelGGL(apply_ns_stream_kernel<14>, dim3(std::min(ntargets, device_cus())),
+                       dim3(256), 0, s, in_tab, out_tab, items, targets, r_tab, t_tab, c_tab,
+                       partials, subbuf, ntargets, counter);
   } else {
     MRA_DISPATCH_K(k, hipLaunchKernelGGL(apply_ns_kernel<KK>, dim3(ntargets),
                                          dim3(round64(4 * KK * KK)), 0, s, in_tab, out_tab,
