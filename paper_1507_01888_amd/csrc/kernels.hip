@@ -2003,14 +2003,17 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
       soff[q] = 8 * K3;                                        // past the descriptor's end
     }
   }
-  auto copy_slab = [&](const double* in_g, const int fc, const int zq, double* dst) {
+  // row q of this wave's part of the slab copy (one instruction)
+  auto copy_slab_row = [&](const double* in_g, const int fc, const int zq, double* dst, const int q) {
     const int z0 = 4 * zq + 2 * (lane & 1);
     const int zoff = z0 >= K ? K3 + z0 - K : z0;
+    if (wave + 4 * q < SROWS)
+      lds_copy16(in_g + (size_t)fc * K3, 8 * K3 * 8, (MRA_LDS void*)(dst + 128 * (wave + 4 * q)),
+                 8 * (soff[q] + zoff));
+  };
+  auto copy_slab = [&](const double* in_g, const int fc, const int zq, double* dst) {
 #pragma unroll
-    for (int q = 0; q < SRPW; ++q)
-      if (wave + 4 * q < SROWS)
-        lds_copy16(in_g + (size_t)fc * K3, 8 * K3 * 8, (MRA_LDS void*)(dst + 128 * (wave + 4 * q)),
-                   8 * (soff[q] + zoff));
+    for (int q = 0; q < SRPW; ++q) copy_slab_row(in_g, fc, zq, dst, q);
   };
   // s_P (K3 doubles) into Ss, granule by granule
   auto copy_sp = [&](const double* in_g, const int src) {
@@ -2107,6 +2110,9 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
       }
       int it = tr.beg, zq = 0;
       const int nstages = Q * (tr.end - tr.beg);
+      // wave 3: the t_y fragments of the current triple (the same for all its 16 units)
+      constexpr int TYC = sub_wave ? Q2 : 1;
+      double tyc[TYC][TYC];
 
       auto stage = [&](auto buf_tag) {
         constexpr int buf = decltype(buf_tag)::value;
@@ -2115,10 +2121,15 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
         __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): this wave's copies landed
         __syncthreads();                             // all copies landed; the other half is free
         const bool more = it + 1 < tr.end;
-        if (zq + 1 < Q)
-          copy_slab(in_g, cur_fc, zq + 1, Xn);
-        else if (more)
-          copy_slab(in_g, nxt.src_fc, 0, Xn);
+        // the next stage's slab (this triple's zq + 1 or the next triple's first), one copy
+        // instruction per x-quad group of step 1, so that the in-order wave never waits for
+        // the memory pipeline to take a burst of them
+        const bool do_copy = zq + 1 < Q || more;
+        const int copy_fc = zq + 1 < Q ? cur_fc : nxt.src_fc;
+        const int copy_zq = zq + 1 < Q ? zq + 1 : 0;
+        auto copy_part = [&](const int q) {
+          if (do_copy) copy_slab_row(in_g, copy_fc, copy_zq, Xn, q);
+        };
         // s_P of the next triple's source (wave 3 reads s_P in stages 0-5 only)
         if (zq + 1 == Q && more && with_sub && nxt.src != cur_src) copy_sp(in_g, nxt.src);
         if (zq + 2 == Q && more) fetch_ops(nxt);
@@ -2143,11 +2154,18 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
             ra[b] = RXs[(4 * xs + lk) * N + 4 * at0 + li];
             rb[b] = RXs[(4 * xs + lk) * N + 4 * at1 + li];
           };
+          double ry[2][Q];
+          auto load2 = [&](const int ys, const int b) {
+#pragma unroll
+            for (int bt = 0; bt < Q; ++bt) ry[b][bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+          };
           load1(0, 0);
 #pragma unroll
           for (int xs = 0; xs < Q; ++xs) {
             const int b = xs & 1;
+            copy_part(xs);
             if (xs + 1 < Q) load1(xs + 1, b ^ 1);
+            else load2(0, 0);     // step 2's first operands during the last x-quad group
 #pragma unroll
             for (int yt = 0; yt < Q; ++yt) {
               d1a[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[b][yt], ra[b], d1a[yt], 0, 0, 0);
@@ -2159,12 +2177,6 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
           double zra[Q], zrb[Q];
 #pragma unroll
           for (int bt = 0; bt < Q; ++bt) zra[bt] = zrb[bt] = 0.0;
-          double ry[2][Q];
-          auto load2 = [&](const int ys, const int b) {
-#pragma unroll
-            for (int bt = 0; bt < Q; ++bt) ry[b][bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
-          };
-          load2(0, 0);
 #pragma unroll
           for (int ys = 0; ys < Q; ++ys) {
             const int b = ys & 1;
@@ -2176,11 +2188,16 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
             }
             __builtin_amdgcn_sched_barrier(0);
           }
-          // ---- step 3 (contract the z-quad) into the target's block
+          // ---- step 3 (contract the z-quad) into the target's block; the permuted operands
+          // of b-quad bt + 1 are fetched during the products of bt
+          double za_n = lane_swap(zra[0]), zb_n = lane_swap(zrb[0]);
 #pragma unroll
           for (int bt = 0; bt < Q; ++bt) {
-            const double za = lane_swap(zra[bt]);
-            const double zb = lane_swap(zrb[bt]);
+            const double za = za_n, zb = zb_n;
+            if (bt + 1 < Q) {
+              za_n = lane_swap(zra[bt + 1]);
+              zb_n = lane_swap(zrb[bt + 1]);
+            }
 #pragma unroll
             for (int ct = 0; ct < Q; ++ct) {
               acc0[bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(za, rz[ct], acc0[bt][ct], 0, 0, 0);
@@ -2203,6 +2220,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 #pragma unroll
           for (int xs = 0; xs < Q; ++xs) {
             const int b = xs & 1;
+            copy_part(xs);
             if (xs + 1 < Q) load1(xs + 1, b ^ 1);
 #pragma unroll
             for (int yt = 0; yt < Q; ++yt)
@@ -2212,25 +2230,33 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
           double zr[Q];
 #pragma unroll
           for (int bt = 0; bt < Q; ++bt) zr[bt] = 0.0;
+          double ry[2][Q];
+          auto load2 = [&](const int ys, const int b) {
+#pragma unroll
+            for (int bt = 0; bt < Q; ++bt) ry[b][bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+          };
+          load2(0, 0);
 #pragma unroll
           for (int ys = 0; ys < Q; ++ys) {
-            double ry[Q];
-#pragma unroll
-            for (int bt = 0; bt < Q; ++bt) ry[bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+            const int b = ys & 1;
+            if (ys + 1 < Q) load2(ys + 1, b ^ 1);
 #pragma unroll
             for (int bt = 0; bt < Q; ++bt)
-              zr[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ry[bt], zr[bt], 0, 0, 0);
+              zr[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ry[b][bt], zr[bt], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
           }
+          double za_n = lane_swap(zr[0]);
 #pragma unroll
           for (int bt = 0; bt < Q; ++bt) {
-            const double za = lane_swap(zr[bt]);
+            const double za = za_n;
+            if (bt + 1 < Q) za_n = lane_swap(zr[bt + 1]);
 #pragma unroll
             for (int ct = 0; ct < Q; ++ct)
               acc0[bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(za, rz[ct], acc0[bt][ct], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
           }
-          // ---- the level-n subtraction units of this stage: (sa, sz), sa fixed per call
+          // ---- the level-n subtraction units of this stage: (sa, sz), sa fixed per call; the
+          // units of a stage are independent, so their instructions may interleave
           if (with_sub && zq < 6) {
             const double* TXs = Os[ob] + 3 * N2;
             const double* TYs = TXs + TSLOT;
@@ -2240,6 +2266,13 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
               const double v = T[r * K + c];
               return (r < K && c < K) ? v : 0.0;
             };
+            if (zq == 0) {
+#pragma unroll
+              for (int ys = 0; ys < Q2; ++ys)
+#pragma unroll
+                for (int bt = 0; bt < Q2; ++bt)
+                  tyc[ys % TYC][bt % TYC] = tfrag(TYs, 4 * ys + lk, 4 * bt + li);
+            }
             auto unit = [&](auto sa_tag, const int sz) {
               constexpr int sa = decltype(sa_tag)::value;
               double tx[Q2];
@@ -2261,8 +2294,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
               for (int ys = 0; ys < Q2; ++ys)
 #pragma unroll
                 for (int bt = 0; bt < Q2; ++bt)
-                  e2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
-                      e1[ys], tfrag(TYs, 4 * ys + lk, 4 * bt + li), e2[bt], 0, 0, 0);
+                  e2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(e1[ys], tyc[ys % TYC][bt % TYC], e2[bt], 0, 0, 0);
               double tz[Q2];
 #pragma unroll
               for (int ct = 0; ct < Q2; ++ct) tz[ct] = -cmu * tfrag(TZs, 4 * sz + lk, 4 * ct + li);
@@ -2274,8 +2306,8 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
                   acc1[((sa * Q2 + bt) * Q2 + ct) % A1] = __builtin_amdgcn_mfma_f64_4x4x4f64(
                       zt, tz[ct], acc1[((sa * Q2 + bt) * Q2 + ct) % A1], 0, 0, 0);
               }
-              __builtin_amdgcn_sched_barrier(0);
             };
+            __builtin_amdgcn_sched_barrier(0);
             if (zq < 4) {
               unit(BufTag<0>{}, zq);
               unit(BufTag<1>{}, zq);
@@ -2284,6 +2316,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
               unit(BufTag<3>{}, 2 * (zq - 4));
               unit(BufTag<3>{}, 2 * (zq - 4) + 1);
             }
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
         // the next triple's operators into the other half: its last reader was triple
