@@ -928,6 +928,9 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       t_tab[i] = plans[i].op->dT.p;
       c_tab[i] = plans[i].op->d_c.p;
       l_tab[i] = plans[i].op->dL.p;
+      // the BF16 kernel addresses an operator's records with 32-bit byte offsets
+      if (tiers && (double)plans[i].op->dL.n * sizeof(uint16_t) >= 2147483632.0)
+        fail(MRA_E_UNSUPPORTED, "too many operator blocks for the low-precision tier");
     }
     for (int i = f0; i < f1; ++i) {
       Func& o = *plans[i].out;
@@ -1155,7 +1158,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
         any_low = true;
         ++n_low_launch;
         launch_apply_low(k, mirror_d, out_tab_d, low_items_d, low_work_d,
-                         (int)low_work.size(), l_tab_d, c_tab_d, ctx->stream);
+                         (int)low_work.size(), l_tab_d, c_tab_d, counter_d + 2, ctx->stream);
       }
       hip_check(hipEventRecord(E[3], ctx->stream), "event");
     }

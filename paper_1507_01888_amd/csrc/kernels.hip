@@ -2419,11 +2419,19 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 // of step y (R_y-part and E_y/P_y-part, scaled by c_mu, BF16) to LDS rows q = (b', c') with
 // a innermost, and after a barrier every wave contracts its share of the q tiles with
 // E_x and P_x, accumulating in registers over all triples of the target.
+//
+// The seven operator matrices a triple reads (U(R_z), U(E_z), V(R_y), V(E_y), V(P_y), U(E_x),
+// U(P_x)) are copied into LDS one triple ahead by buffer loads that write LDS directly
+// (rows padded to an odd number of 16-byte granules, so that the fragment reads of 16 rows
+// are bank-conflict free); the two halves of that double buffer are separate objects, the
+// loop is unrolled by two over them.  Persistent workgroups take target ranges, longest
+// first, from a counter.
 template <int K>
 __global__ __launch_bounds__(256) void apply_low_kernel(
     const uint16_t* __restrict__ mirror, double* const* __restrict__ out_tab,
     const LowItem* __restrict__ items, const TargetRange* __restrict__ targets,
-    const uint16_t* const* __restrict__ l_tab, const double* const* __restrict__ c_tab) {
+    const uint16_t* const* __restrict__ l_tab, const double* const* __restrict__ c_tab,
+    const int ntargets, int* __restrict__ next_target) {
   constexpr int N = 2 * K, N2 = N * N, K3 = K * K * K;
   constexpr int UP = (N + 7) / 8 * 8;          // padded contraction length (U layout)
   constexpr int XB = N * N * UP;               // BF16 per mirrored children block
@@ -2432,15 +2440,25 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
   constexpr int NQ = N2 / 16, QPW = (NQ + 3) / 4;
   constexpr int TSZ = N2 * UP + N * 8;         // 16 bytes of padding after every N rows
   static_assert(N > 16 && N <= 32 && N2 % 16 == 0, "two 16-wide tiles per index, even k");
+  // operator staging: matrix m has N rows of GM[m] granules (8 BF16 each) in the record,
+  // RSM[m] (odd) granules per row in LDS; the extra granules read zeros
+  constexpr int GU = UP / 8, GV = 4;
+  constexpr int RU = GU % 2 ? GU : GU + 1, RV = GV % 2 ? GV : GV + 1;
+  constexpr int SU = 8 * RU, SV = 8 * RV;      // LDS row strides in BF16
+  constexpr int MU = N * RU, MV = N * RV;      // granules per staged matrix
+  constexpr int OPG = 4 * MU + 3 * MV, OROWS = (OPG + 63) / 64, ORPW = (OROWS + 3) / 4;
+  constexpr int OPB = 8 * 64 * OROWS;          // BF16 per half of the staging buffer
+  // BF16 offsets of the staged matrices
+  constexpr int O_RZ = 0, O_EZ = 8 * MU, O_RY = 16 * MU, O_EY = O_RY + 8 * MV, O_PY = O_EY + 8 * MV;
+  constexpr int O_EX = O_PY + 8 * MV, O_PX = O_EX + 8 * MU;
   __shared__ __attribute__((aligned(16))) uint16_t T1s[TSZ];
   __shared__ __attribute__((aligned(16))) uint16_t T2s[TSZ];
+  __shared__ __attribute__((aligned(16))) uint16_t Ob0[OPB];
+  __shared__ __attribute__((aligned(16))) uint16_t Ob1[OPB];
+  __shared__ int s_next;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r = lane & 15;
   const bool kin = 8 * g < UP;
-  const TargetRange tr = targets[blockIdx.x];
-  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
-  const MRA_GLOBAL uint16_t* __restrict__ L = as_global(l_tab[tr.fn]);
-  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
   const bf16x8 zero8 = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
   auto ld8 = [&](const uint16_t* p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p)); };
   auto ld8g = [&](const MRA_GLOBAL uint16_t* p) {
@@ -2451,135 +2469,221 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
     reinterpret_cast<u32x4*>(T1s)[e] = u32x4{0u, 0u, 0u, 0u};
     reinterpret_cast<u32x4*>(T2s)[e] = u32x4{0u, 0u, 0u, 0u};
   }
+  // this lane's granule of each of its staging rows: which record (0: R_z's, 1: R_y's,
+  // 2: R_x's) and the byte offset inside it; padding granules read past the descriptor
+  constexpr int kPast = 0x7FFFFFF0;
+  int o_sel[ORPW], o_off[ORPW];
+#pragma unroll
+  for (int q = 0; q < ORPW; ++q) {
+    const int j = 64 * (wave + 4 * q) + lane;
+    int sel = 0, off = kPast;
+    const int mstart[8] = {0, MU, 2 * MU, 2 * MU + MV, 2 * MU + 2 * MV, 2 * MU + 3 * MV,
+                           3 * MU + 3 * MV, OPG};
+    // record parts: U(R), U(E), U(P) at 0, LU, 2 LU; V(R), V(E), V(P) at 3 LU + m LV
+    const int part[7] = {0, LU, 3 * LU, 3 * LU + LV, 3 * LU + 2 * LV, LU, 2 * LU};
+    const int recsel[7] = {0, 0, 1, 1, 1, 2, 2};
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      if (j >= mstart[m] && j < mstart[m + 1]) {
+        const bool u = m < 2 || m >= 5;
+        const int rs = u ? RU : RV, gm = u ? GU : GV, w = u ? UP : 32;
+        const int row = (j - mstart[m]) / rs, col = (j - mstart[m]) % rs;
+        sel = recsel[m];
+        if (col < gm) off = 2 * (part[m] + row * w + 8 * col);
+      }
+    }
+    o_sel[q] = sel;
+    o_off[q] = off;
+  }
+  auto stage_ops = [&](const MRA_GLOBAL uint16_t* L, const LowItem& nx, uint16_t* dst) {
+#pragma unroll
+    for (int q = 0; q < ORPW; ++q) {
+      if (wave + 4 * q < OROWS) {
+        const int rec = o_sel[q] == 0 ? nx.rz : o_sel[q] == 1 ? nx.ry : nx.rx;
+        const int voff = o_off[q] == kPast ? kPast : rec * (2 * REC) + o_off[q];
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)L, (short)0, kPast, 0x00020000);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (MRA_LDS void*)(dst + 512 * (wave + 4 * q)),
+                                                 16, voff, 0, 0, 0);
+      }
+    }
+  };
   __syncthreads();
 
-  f32x4 acc[QPW][2];
+  for (;;) {
+    if (tid == 0) s_next = atomicAdd(next_target, 1);
+    __syncthreads();
+    const int ti = s_next;
+    __syncthreads();   // every wave has read s_next (and is done with the previous range)
+    if (ti >= ntargets) break;
+    const TargetRange tr = targets[ti];
+    MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
+    const MRA_GLOBAL uint16_t* __restrict__ L = as_global(l_tab[tr.fn]);
+    const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
+
+    f32x4 acc[QPW][2];
 #pragma unroll
-  for (int e = 0; e < QPW; ++e)
+    for (int e = 0; e < QPW; ++e)
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) acc[e][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  bf16x8 xr[PPW][2][2];   // [pair of this wave][a in pair][b tile]: A operand of step z
-  int loaded = -1;
-  for (int it = tr.beg; it < tr.end; ++it) {
-    const LowItem item = items[it];
-    if (item.slot != loaded) {
-      const uint16_t* xb = mirror + (size_t)item.slot * XB;
+      for (int mt = 0; mt < 2; ++mt) acc[e][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 xr[PPW][2][2];   // [pair of this wave][a in pair][b tile]: A operand of step z
+    // this wave's rows of a mirrored source block into xr
+    auto load_src = [&](const int slot) {
+      const int wl = opaque_int(lane);      // offsets recomputed here, not held
+      const int gg = wl >> 4, rr = wl & 15;
+      // global (not flat) loads: they count against the vector-memory counter only, so the
+      // LDS waits of step x do not wait for them
+      const MRA_GLOBAL uint16_t* xb = as_global(mirror) + (size_t)slot * XB;
 #pragma unroll
       for (int p = 0; p < PPW; ++p)
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt) {
-            const int pair = wave + 4 * p, a = 2 * pair + s2, b = 16 * mt + r;
-            xr[p][s2][mt] = (pair < NPAIR && b < N && kin) ? ld8(xb + (a * N + b) * UP + 8 * g) : zero8;
+            const int pair = wave + 4 * p, a = 2 * pair + s2, b = 16 * mt + rr;
+            xr[p][s2][mt] = (pair < NPAIR && b < N && 8 * gg < UP)
+                                ? ld8g(xb + (a * N + b) * UP + 8 * gg) : zero8;
           }
-      loaded = item.slot;
+    };
+    LowItem cur{}, nxt{};
+    if (tr.beg < tr.end) {
+      cur = items[tr.beg];
+      nxt = items[min(tr.beg + 1, tr.end - 1)];
+      stage_ops(L, cur, Ob0);
+      load_src(cur.slot);
     }
-    const MRA_GLOBAL uint16_t* Lz = L + (size_t)item.rz * REC;
-    const MRA_GLOBAL uint16_t* Ly = L + (size_t)item.ry * REC;
-    const MRA_GLOBAL uint16_t* Lx = L + (size_t)item.rx * REC;
-    bf16x8 oz[2][2], oy[3][2], ox[2][2];
+    auto triple = [&](const int it, auto buf_tag) {
+      constexpr int buf = decltype(buf_tag)::value;
+      const uint16_t* const Oc = buf == 0 ? Ob0 : Ob1;   // this triple's operators
+      uint16_t* const On = buf == 0 ? Ob1 : Ob0;         // the next triple's
+      const LowItem item = cur;
+      const bool more = it + 1 < tr.end;
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's copies landed
+      __syncthreads();                      // all copies landed; step x of it - 1 is done
+      if (more) stage_ops(L, nxt, On);
+      const float cmu = (float)dc[item.mu];
+      bf16x8 oz[2][2], oy[3][2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int row = 16 * t + r;
-      const bool ok = row < N, oku = ok && kin;
-      oz[0][t] = oku ? ld8g(Lz + row * UP + 8 * g) : zero8;              // U(R_z)
-      oz[1][t] = oku ? ld8g(Lz + LU + row * UP + 8 * g) : zero8;         // U(E_z)
+      for (int t = 0; t < 2; ++t) {
+        const int row = 16 * t + r;
+        const bool ok = row < N, oku = ok && kin;
+        oz[0][t] = oku ? ld8(Oc + O_RZ + row * SU + 8 * g) : zero8;       // U(R_z)
+        oz[1][t] = oku ? ld8(Oc + O_EZ + row * SU + 8 * g) : zero8;       // U(E_z)
+        oy[0][t] = ok ? ld8(Oc + O_RY + row * SV + 8 * g) : zero8;        // V(R_y)
+        oy[1][t] = ok ? ld8(Oc + O_EY + row * SV + 8 * g) : zero8;        // V(E_y)
+        oy[2][t] = ok ? ld8(Oc + O_PY + row * SV + 8 * g) : zero8;        // V(P_y)
+      }
+      // ---- steps z and y for this wave's pairs of a
 #pragma unroll
-      for (int m = 0; m < 3; ++m)                                       // V(R_y), V(E_y), V(P_y)
-        oy[m][t] = ok ? ld8g(Ly + 3 * LU + m * LV + row * 32 + 8 * g) : zero8;
-      ox[0][t] = oku ? ld8g(Lx + LU + row * UP + 8 * g) : zero8;         // U(E_x)
-      ox[1][t] = oku ? ld8g(Lx + 2 * LU + row * UP + 8 * g) : zero8;     // U(P_x)
-    }
-    const float cmu = (float)dc[item.mu];
-    // ---- steps z and y for this wave's pairs of a
+      for (int p = 0; p < PPW; ++p) {
+        const int pair = wave + 4 * p;
+        if (pair < NPAIR) {
+          f32x4 u[2][2][2], v[2][2][2];   // [a in pair][b' tile][c' tile]
 #pragma unroll
-    for (int p = 0; p < PPW; ++p) {
-      const int pair = wave + 4 * p;
-      if (pair < NPAIR) {
-        f32x4 u[2][2][2], v[2][2][2];   // [a in pair][b' tile][c' tile]
+          for (int s2 = 0; s2 < 2; ++s2) {
+            f32x4 y1[2][2], y2[2][2];
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) {
-          f32x4 y1[2][2], y2[2][2];
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+              for (int nt = 0; nt < 2; ++nt) {
+                const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+                y1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[p][s2][mt], oz[0][nt], z4, 0, 0, 0);
+                y2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[p][s2][mt], oz[1][nt], z4, 0, 0, 0);
+              }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+              bf16x8 b1, b2;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                b1[i] = (__bf16)y1[0][nt][i];
+                b1[4 + i] = (__bf16)y1[1][nt][i];
+                b2[i] = (__bf16)y2[0][nt][i];
+                b2[4 + i] = (__bf16)y2[1][nt][i];
+              }
+#pragma unroll
+              for (int mt = 0; mt < 2; ++mt) {
+                const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+                u[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[0][mt], b1, z4, 0, 0, 0);
+                v[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[1][mt], b1, z4, 0, 0, 0);
+                v[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[2][mt], b2, v[s2][mt][nt], 0, 0, 0);
+              }
+            }
+          }
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-              const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
-              y1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[p][s2][mt], oz[0][nt], z4, 0, 0, 0);
-              y2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[p][s2][mt], oz[1][nt], z4, 0, 0, 0);
-            }
+            for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-          for (int nt = 0; nt < 2; ++nt) {
-            bf16x8 b1, b2;
+              for (int i = 0; i < 4; ++i) {
+                const int bp = 16 * mt + 4 * g + i, cp = 16 * nt + r;
+                if (bp < N && cp < N) {
+                  const int off = (bp * N + cp) * UP + bp * 8 + 2 * pair;
+                  *reinterpret_cast<uint32_t*>(&T1s[off]) =
+                      bf16_pair(cmu * u[0][mt][nt][i], cmu * u[1][mt][nt][i]);
+                  *reinterpret_cast<uint32_t*>(&T2s[off]) =
+                      bf16_pair(cmu * v[0][mt][nt][i], cmu * v[1][mt][nt][i]);
+                }
+              }
+        }
+      }
+      lds_barrier();   // T1/T2 complete (the operator copies in flight are not waited for)
+      // xr is free once steps z and y are done: the next triple's source rows load during
+      // step x
+      if (more && nxt.slot != item.slot) load_src(nxt.slot);
+      // ---- step x: acc[a'][q] += E_x T1 + P_x T2 over this wave's q tiles
+      bf16x8 ox[2][2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              b1[i] = (__bf16)y1[0][nt][i];
-              b1[4 + i] = (__bf16)y1[1][nt][i];
-              b2[i] = (__bf16)y2[0][nt][i];
-              b2[4 + i] = (__bf16)y2[1][nt][i];
-            }
+      for (int t = 0; t < 2; ++t) {
+        const int row = 16 * t + r;
+        const bool oku = row < N && kin;
+        ox[0][t] = oku ? ld8(Oc + O_EX + row * SU + 8 * g) : zero8;       // U(E_x)
+        ox[1][t] = oku ? ld8(Oc + O_PX + row * SU + 8 * g) : zero8;       // U(P_x)
+      }
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt) {
-              const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
-              u[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[0][mt], b1, z4, 0, 0, 0);
-              v[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[1][mt], b1, z4, 0, 0, 0);
-              v[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[2][mt], b2, v[s2][mt][nt], 0, 0, 0);
-            }
+      for (int e = 0; e < QPW; ++e) {
+        const int qt = wave + 4 * e;
+        if (qt < NQ) {
+          const int q = 16 * qt + r, off = q * UP + (q / N) * 8 + 8 * g;
+          const bf16x8 t1 = kin ? ld8(T1s + off) : zero8;
+          const bf16x8 t2 = kin ? ld8(T2s + off) : zero8;
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            acc[e][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ox[0][mt], t1, acc[e][mt], 0, 0, 0);
+            acc[e][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ox[1][mt], t2, acc[e][mt], 0, 0, 0);
           }
         }
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-          for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int bp = 16 * mt + 4 * g + i, cp = 16 * nt + r;
-              if (bp < N && cp < N) {
-                const int off = (bp * N + cp) * UP + bp * 8 + 2 * pair;
-                *reinterpret_cast<uint32_t*>(&T1s[off]) =
-                    bf16_pair(cmu * u[0][mt][nt][i], cmu * u[1][mt][nt][i]);
-                *reinterpret_cast<uint32_t*>(&T2s[off]) =
-                    bf16_pair(cmu * v[0][mt][nt][i], cmu * v[1][mt][nt][i]);
-              }
-            }
       }
+      cur = nxt;
+      nxt = items[min(it + 2, tr.end - 1)];
+    };
+    for (int it = tr.beg; it < tr.end; it += 2) {
+      triple(it, BufTag<0>{});
+      if (it + 1 < tr.end) triple(it + 1, BufTag<1>{});
     }
-    __syncthreads();
-    // ---- step x: acc[a'][q] += E_x T1 + P_x T2 over this wave's q tiles
+    // ---- add the target's block to the FP64 output (each element owned by one lane)
+    const int wl = opaque_int(lane);        // offsets recomputed here, not held
+    const int gg = wl >> 4, rr = wl & 15;
 #pragma unroll
     for (int e = 0; e < QPW; ++e) {
       const int qt = wave + 4 * e;
       if (qt < NQ) {
-        const int q = 16 * qt + r, off = q * UP + (q / N) * 8 + 8 * g;
-        const bf16x8 t1 = kin ? ld8(T1s + off) : zero8;
-        const bf16x8 t2 = kin ? ld8(T2s + off) : zero8;
+        const int q = 16 * qt + rr, bp = q / N, cp = q % N;
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
-          acc[e][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ox[0][mt], t1, acc[e][mt], 0, 0, 0);
-          acc[e][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ox[1][mt], t2, acc[e][mt], 0, 0, 0);
+          size_t off[4];
+          double o[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int ap = min(16 * mt + 4 * gg + i, N - 1);
+            const int child = ((ap / K) << 2) | ((bp / K) << 1) | (cp / K);
+            off[i] = (size_t)(tr.fc + child) * K3 + ((ap % K) * K + (bp % K)) * K + (cp % K);
+            o[i] = out[off[i]];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (16 * mt + 4 * gg + i < N) out[off[i]] = o[i] + (double)acc[e][mt][i];
         }
       }
-    }
-    __syncthreads();
-  }
-  // ---- add the target's block to the FP64 output (each element owned by one lane)
-#pragma unroll
-  for (int e = 0; e < QPW; ++e) {
-    const int qt = wave + 4 * e;
-    if (qt < NQ) {
-      const int q = 16 * qt + r, bp = q / N, cp = q % N;
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int ap = 16 * mt + 4 * g + i;
-          if (ap < N) {
-            const int child = ((ap / K) << 2) | ((bp / K) << 1) | (cp / K);
-            out[(size_t)(tr.fc + child) * K3 + ((ap % K) * K + (bp % K)) * K + (cp % K)] +=
-                (double)acc[e][mt][i];
-          }
-        }
     }
   }
 }
@@ -2636,19 +2740,25 @@ void launch_filter_up(int k, double* const* coeff_tab, const NodeRef* refs, int 
 
 bool low_kernel_available(int k) { return k == 10 || k == 12 || k == 14; }
 
+static int device_cus();
+
 void launch_apply_low(int k, const uint16_t* mirror, double* const* out_tab,
                       const LowItem* items, const TargetRange* targets, int ntargets,
-                      const uint16_t* const* l_tab, const double* const* c_tab, hipStream_t s) {
+                      const uint16_t* const* l_tab, const double* const* c_tab, int* counter,
+                      hipStream_t s) {
   if (ntargets <= 0) return;
+  // one persistent workgroup per CU (the kernel's LDS allows one), ranges from a counter
+  hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, counter, 1, 0);
+  const int grid = std::min(ntargets, device_cus());
   if (k == 10) {
-    hipLaunchKernelGGL(apply_low_kernel<10>, dim3(ntargets), dim3(256), 0, s, mirror, out_tab,
-                       items, targets, l_tab, c_tab);
+    hipLaunchKernelGGL(apply_low_kernel<10>, dim3(grid), dim3(256), 0, s, mirror, out_tab,
+                       items, targets, l_tab, c_tab, ntargets, counter);
   } else if (k == 12) {
-    hipLaunchKernelGGL(apply_low_kernel<12>, dim3(ntargets), dim3(256), 0, s, mirror, out_tab,
-                       items, targets, l_tab, c_tab);
+    hipLaunchKernelGGL(apply_low_kernel<12>, dim3(grid), dim3(256), 0, s, mirror, out_tab,
+                       items, targets, l_tab, c_tab, ntargets, counter);
   } else if (k == 14) {
-    hipLaunchKernelGGL(apply_low_kernel<14>, dim3(ntargets), dim3(256), 0, s, mirror, out_tab,
-                       items, targets, l_tab, c_tab);
+    hipLaunchKernelGGL(apply_low_kernel<14>, dim3(grid), dim3(256), 0, s, mirror, out_tab,
+                       items, targets, l_tab, c_tab, ntargets, counter);
   } else {
     fail(MRA_E_UNSUPPORTED, "the low-precision tier is built for k = 10, 12, 14");
   }

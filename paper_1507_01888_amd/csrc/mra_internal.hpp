@@ -294,9 +294,12 @@ void launch_filter_up(int k, double* const* coeff_tab, const NodeRef* refs, int 
                       hipStream_t s);
 // True when the low-precision transform kernel is built for this k.
 bool low_kernel_available(int k);
+// counter: one int of device scratch (the persistent kernel's work counter, set here).
+// The BF16 records of every operator must lie within 2^31 - 16 bytes of its array's start.
 void launch_apply_low(int k, const uint16_t* mirror, double* const* out_tab,
                       const LowItem* items, const TargetRange* targets, int ntargets,
-                      const uint16_t* const* l_tab, const double* const* c_tab, hipStream_t s);
+                      const uint16_t* const* l_tab, const double* const* c_tab, int* counter,
+                      hipStream_t s);
 // True when the non-standard kernel for this k also applies the level-n subtraction.
 bool ns_kernel_fuses_subtraction(int k);
 // True when the non-standard kernel for this k shares the y- and z-contractions between
