@@ -50,6 +50,10 @@ def parse():
     p.add_argument("--cmp-steps", type=int, default=5,
                    help="timed steps of each comparison run (all-FP64 path, wide tier) of a "
                         "tiered workload, after one warm-up step (at most --steps)")
+    p.add_argument("--no-tune", action="store_true",
+                   help="skip the autotuner of the batched workloads' schedule")
+    p.add_argument("--tune-cache", default=None,
+                   help="JSON file the autotuner reads and extends (default: none, tune now)")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="approximate CPU work of the oracle baseline sample (0 = skip)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -266,6 +270,15 @@ def main():
     ctx = M.Context(0, W.CELL)
     funcs, ops, tau, k, tier, cfg = setup(ctx, args.workload)
     name = args.workload
+    tuning = None
+    if len(funcs) > 1 and not args.no_tune:
+        # the schedule of the batched apply (sub-batches, split length) picked by the
+        # library's autotuner on these inputs, before warm-up
+        t0 = time.perf_counter()
+        sched, times = ctx.autotune_batch(ops, funcs, tau_drop=tau, tau_tier=tier,
+                                          cache_path=args.tune_cache)
+        tuning = {"schedule": sched, "candidate_ms": [round(float(t), 1) for t in times],
+                  "seconds": time.perf_counter() - t0}
 
     def apply(tau_tier):
         if tau is None:     # standard form on a uniform tree, no screening
@@ -308,8 +321,9 @@ def main():
     main_ms = mean(stats, "ms_main_kernel")
     main_launch_ms = main_ms / max(1, s0["launches_main"])
     useful_main = s0["useful_flops"] - s0["flops_low"]
-    if tau is None:
-        kname, bound, prec = "apply_std_kernel<%d>" % k, "alu", "fp64"
+    if tau is None:        # standard form: matrix-core kernel for k = 8, vector ALU otherwise
+        kname, bound, prec = (("apply_std_mfma_kernel<8>", "mfma", "fp64") if k == 8 else
+                              ("apply_std_kernel<%d>" % k, "alu", "fp64"))
     else:
         kname, bound, prec = FP64_KERNEL.get(k, "apply_ns_kernel<%d>" % k), "mfma", "fp64"
     kernels = {"fp64": {"kernel": kname, "ms_per_apply": main_ms,
@@ -370,6 +384,7 @@ def main():
         "norm2": math.sqrt(sum(v * v for v in nrm)),
         "roofline": roofline,
         "kernels": kernels,
+        "autotune": tuning,
     }
 
     if tier > 0:

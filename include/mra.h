@@ -229,6 +229,32 @@ mra_status mra_distance(mra_ctx* ctx, const mra_func* f, const mra_func* g, doub
 /* Counters of the last mra_apply on ctx. */
 mra_status mra_last_stats(const mra_ctx* ctx, mra_apply_stats* out);
 
+/* Work schedule of mra_apply / mra_apply_batch on a context (this library's own tuning
+ * knobs; the paper's method is unaffected, results differ only in the summation order of
+ * split target lists):
+ *  sub_batches  functions are planned and launched in this many pipelined sub-batches
+ *               (0: automatic, 4 for >= 8 functions, 2 for >= 2, else 1);
+ *  split_div    a target list longer than max(24, items / split_div) is split over several
+ *               workgroups whose partial blocks are summed in a fixed order (>= 1). */
+typedef struct {
+  int sub_batches;
+  int split_div;
+} mra_schedule;
+mra_status mra_set_schedule(mra_ctx* ctx, const mra_schedule* s);
+mra_status mra_get_schedule(const mra_ctx* ctx, mra_schedule* s);
+
+/* Autotuner of the batched apply (the batching extension's "autotuned schedules"): times one
+ * mra_apply_batch of (ops, fs, params) under each candidate schedule (sub_batches 1, 2, 4 x
+ * split_div 256, 512, 1024; one untimed apply first, which also builds the operator block
+ * caches), keeps the fastest on ctx and returns it in *best.  With cache_path != NULL the
+ * JSON file is read first: if it holds the key "<gfx arch>/k<k>/<fp64|tiered>", that schedule
+ * is set without timing; otherwise the result is added to the file.  times_ms (optional,
+ * capacity 9) receives the measured milliseconds in candidate order (-1 when read from the
+ * cache).  The functions are only read; every result is freed. */
+mra_status mra_autotune_batch(mra_ctx* ctx, int n, const mra_op* const* ops,
+                              const mra_func* const* fs, const mra_apply_params* params,
+                              const char* cache_path, mra_schedule* best, double* times_ms);
+
 /* ---------------------------------------------------------------- host-only helpers
  * These run on the host only (no device, no context) and expose the library's FP64 host
  * numerics for testing.  Arrays are caller-owned host memory.

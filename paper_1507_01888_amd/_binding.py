@@ -23,7 +23,8 @@ EXPORTED = [
     "mra_ctx_create", "mra_ctx_free", "mra_last_error", "mra_project", "mra_func_info",
     "mra_func_export", "mra_func_free", "mra_op_coulomb", "mra_op_bsh", "mra_op_gaussians",
     "mra_op_terms", "mra_op_free", "mra_apply", "mra_apply_batch", "mra_norm2", "mra_trace",
-    "mra_inner", "mra_distance", "mra_norm2_noalloc",
+    "mra_inner", "mra_distance", "mra_norm2_noalloc", "mra_set_schedule", "mra_get_schedule",
+    "mra_autotune_batch",
     "mra_last_stats", "mra_host_fit", "mra_host_block", "mra_host_filters",
     "mra_host_spectral_norm", "mra_host_project",
 ]
@@ -52,6 +53,10 @@ class ApplyParams(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int), ("disp_radius", ctypes.c_int),
                 ("tau_drop", ctypes.c_double), ("tau_tier", ctypes.c_double),
                 ("low_precision", ctypes.c_int)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("sub_batches", ctypes.c_int), ("split_div", ctypes.c_int)]
 
 
 class ApplyStats(ctypes.Structure):
@@ -110,6 +115,10 @@ def load():
     lib.mra_inner.argtypes = [vp, vp, vp, dp]
     lib.mra_distance.argtypes = [vp, vp, vp, dp]
     lib.mra_norm2_noalloc.argtypes = [vp, vp, dp]
+    lib.mra_set_schedule.argtypes = [vp, P(Schedule)]
+    lib.mra_get_schedule.argtypes = [vp, P(Schedule)]
+    lib.mra_autotune_batch.argtypes = [vp, ctypes.c_int, P(vp), P(vp), P(ApplyParams),
+                                       ctypes.c_char_p, P(Schedule), dp]
     lib.mra_last_stats.argtypes = [vp, P(ApplyStats)]
     lib.mra_host_fit.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_int, dp, dp, P(ctypes.c_int)]
@@ -320,6 +329,30 @@ class Context:
         self._check(self._lib.mra_apply_batch(self.h, n, oarr, farr, ctypes.byref(p), outs),
                     "mra_apply_batch")
         return [Function(self, ctypes.c_void_p(outs[i])) for i in range(n)]
+
+    def set_schedule(self, sub_batches=0, split_div=512):
+        sch = Schedule(sub_batches, split_div)
+        self._check(self._lib.mra_set_schedule(self.h, ctypes.byref(sch)), "mra_set_schedule")
+
+    def schedule(self):
+        sch = Schedule()
+        self._check(self._lib.mra_get_schedule(self.h, ctypes.byref(sch)), "mra_get_schedule")
+        return {"sub_batches": sch.sub_batches, "split_div": sch.split_div}
+
+    def autotune_batch(self, ops, funcs, tau_drop=0.0, tau_tier=0.0, cache_path=None):
+        """Times the batched apply under the library's candidate schedules and keeps the
+        fastest (see mra_autotune_batch); returns (schedule dict, times in ms)."""
+        n = len(funcs)
+        oarr = (ctypes.c_void_p * n)(*[o.h.value for o in ops])
+        farr = (ctypes.c_void_p * n)(*[f.h.value for f in funcs])
+        p = ApplyParams(FORM_NONSTANDARD, 1, tau_drop, tau_tier, LOW_BF16)
+        best = Schedule()
+        times = np.zeros(9)
+        path = cache_path.encode() if cache_path else None
+        self._check(self._lib.mra_autotune_batch(self.h, n, oarr, farr, ctypes.byref(p), path,
+                                                 ctypes.byref(best), _dptr(times)),
+                    "mra_autotune_batch")
+        return {"sub_batches": best.sub_batches, "split_div": best.split_div}, times
 
     def norm2(self, f):
         v = ctypes.c_double()

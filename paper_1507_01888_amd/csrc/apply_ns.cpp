@@ -654,7 +654,8 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   for (int i = nf - 1; i >= 0; --i) job_begin[i] = std::min(job_begin[i], job_begin[i + 1]);
   std::vector<double> weight(nf, 0.0);
   for (const Job& jb : jobs) weight[lv[jb.lev].fn] += (double)lv[jb.lev].np;
-  const int S = nf >= 8 ? 4 : (nf >= 2 ? 2 : 1);
+  const int S = std::min(nf, ctx->sched_sub_batches > 0 ? ctx->sched_sub_batches
+                                                         : (nf >= 8 ? 4 : (nf >= 2 ? 2 : 1)));
   std::vector<int> fb{0};
   {
     double total = 0.0, acc = 0.0;
@@ -1078,7 +1079,8 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       // target ranges: split long lists, longest first
       std::vector<TargetRange> tgt_sub, work, low_work;
       std::vector<SplitTarget> splits;
-      const int64_t chunk = std::max<int64_t>(24, ((int64_t)n_items + 511) / 512);
+      const int64_t div = std::max(1, ctx->sched_split_div);
+      const int64_t chunk = std::max<int64_t>(24, ((int64_t)n_items + div - 1) / div);
       int32_t npartials = 0;
       for (const Unit& u : units) {
         const int i = u.fn;

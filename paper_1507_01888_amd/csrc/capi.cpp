@@ -13,6 +13,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -960,6 +961,161 @@ mra_status mra_distance(mra_ctx* ctx, const mra_func* fh, const mra_func* gh, do
     double s = reduce(c, f.k, f.coeff.p, g.coeff.p, f.leaves, &g.leaves, nullptr, 3,
                       f.device_leaves());
     *out = std::sqrt(s);
+  });
+}
+
+mra_status mra_set_schedule(mra_ctx* ctx, const mra_schedule* sch) {
+  if (!ctx || !sch || sch->sub_batches < 0 || sch->sub_batches > 64 || sch->split_div < 1)
+    return MRA_E_INVALID;
+  ctx->c.sched_sub_batches = sch->sub_batches;
+  ctx->c.sched_split_div = sch->split_div;
+  return MRA_OK;
+}
+
+mra_status mra_get_schedule(const mra_ctx* ctx, mra_schedule* sch) {
+  if (!ctx || !sch) return MRA_E_INVALID;
+  sch->sub_batches = ctx->c.sched_sub_batches;
+  sch->split_div = ctx->c.sched_split_div;
+  return MRA_OK;
+}
+
+namespace {
+// The autotuner's cache: a JSON object of  "key": {"sub_batches": S, "split_div": D, "ms": t}.
+struct TuneEntry {
+  std::string key;
+  int sb = 0, div = 512;
+  double ms = 0.0;
+};
+std::vector<TuneEntry> read_tune_cache(const char* path) {
+  std::vector<TuneEntry> out;
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return out;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), fp)) > 0) text.append(buf, got);
+  std::fclose(fp);
+  size_t pos = 0;
+  auto num_after = [&](size_t from, size_t end, const char* name, double& v) {
+    const size_t q = text.find(name, from);
+    if (q == std::string::npos || q > end) return false;
+    const size_t c = text.find(':', q);
+    if (c == std::string::npos || c > end) return false;
+    v = std::strtod(text.c_str() + c + 1, nullptr);
+    return true;
+  };
+  while (true) {
+    const size_t k0 = text.find('"', pos);
+    if (k0 == std::string::npos) break;
+    const size_t k1 = text.find('"', k0 + 1);
+    const size_t ob = text.find('{', k1);
+    const size_t cb = text.find('}', ob);
+    if (k1 == std::string::npos || ob == std::string::npos || cb == std::string::npos) break;
+    TuneEntry e;
+    e.key = text.substr(k0 + 1, k1 - k0 - 1);
+    double sb = -1, div = -1, ms = 0;
+    if (num_after(ob, cb, "\"sub_batches\"", sb) && num_after(ob, cb, "\"split_div\"", div)) {
+      num_after(ob, cb, "\"ms\"", ms);
+      e.sb = (int)sb;
+      e.div = (int)div;
+      e.ms = ms;
+      if (e.sb >= 0 && e.div >= 1) out.push_back(e);
+    }
+    pos = cb + 1;
+  }
+  return out;
+}
+void write_tune_cache(const char* path, const std::vector<TuneEntry>& es) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* fp = std::fopen(tmp.c_str(), "w");
+  if (!fp) fail(MRA_E_INVALID, std::string("mra_autotune_batch: cannot write ") + path);
+  std::fprintf(fp, "{\n");
+  for (size_t i = 0; i < es.size(); ++i)
+    std::fprintf(fp, "  \"%s\": {\"sub_batches\": %d, \"split_div\": %d, \"ms\": %.3f}%s\n",
+                 es[i].key.c_str(), es[i].sb, es[i].div, es[i].ms, i + 1 < es.size() ? "," : "");
+  std::fprintf(fp, "}\n");
+  std::fclose(fp);
+  if (std::rename(tmp.c_str(), path) != 0)
+    fail(MRA_E_INVALID, std::string("mra_autotune_batch: cannot replace ") + path);
+}
+}  // namespace
+
+mra_status mra_autotune_batch(mra_ctx* ctx, int n, const mra_op* const* ophs,
+                              const mra_func* const* fhs, const mra_apply_params* p,
+                              const char* cache_path, mra_schedule* best, double* times_ms) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  const int old_sb = c->sched_sub_batches, old_div = c->sched_split_div;
+  MRA_TRY(c, {
+    if (n < 1 || !ophs || !fhs || !p || !best) fail(MRA_E_INVALID, "mra_autotune_batch: bad arguments");
+    if (p->form != MRA_FORM_NONSTANDARD) fail(MRA_E_UNSUPPORTED, "batches use the non-standard form");
+    if (!fhs[0]) fail(MRA_E_INVALID, "mra_autotune_batch: null handle");
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, c->device), "hipGetDeviceProperties");
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    const std::string key = arch + "/k" + std::to_string(fhs[0]->f.k) +
+                            (p->tau_tier > 0.0 ? "/tiered" : "/fp64");
+    const int cand_sb[3] = {1, 2, 4}, cand_div[3] = {256, 512, 1024};
+    std::vector<TuneEntry> cache;
+    if (cache_path) {
+      cache = read_tune_cache(cache_path);
+      for (const TuneEntry& e : cache)
+        if (e.key == key) {
+          c->sched_sub_batches = e.sb;
+          c->sched_split_div = e.div;
+          best->sub_batches = e.sb;
+          best->split_div = e.div;
+          if (times_ms)
+            for (int q = 0; q < 9; ++q) times_ms[q] = -1.0;
+          return MRA_OK;
+        }
+    }
+    std::vector<mra_func*> outs(n, nullptr);
+    auto run = [&]() {
+      const auto t0 = std::chrono::steady_clock::now();
+      const mra_status rc = mra_apply_batch(ctx, n, ophs, fhs, p, outs.data());
+      const double ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (rc != MRA_OK) {
+        c->sched_sub_batches = old_sb;
+        c->sched_split_div = old_div;
+        fail(rc, c->err);
+      }
+      for (mra_func*& o : outs) {
+        mra_func_free(o);
+        o = nullptr;
+      }
+      return ms;
+    };
+    run();   // block caches, pinned arenas and planner buffers settle; not timed
+    double best_ms = 1e300;
+    int bsb = old_sb, bdiv = old_div;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        c->sched_sub_batches = cand_sb[a];
+        c->sched_split_div = cand_div[b];
+        const double ms = run();
+        if (times_ms) times_ms[3 * a + b] = ms;
+        if (ms < best_ms) {
+          best_ms = ms;
+          bsb = cand_sb[a];
+          bdiv = cand_div[b];
+        }
+      }
+    c->sched_sub_batches = bsb;
+    c->sched_split_div = bdiv;
+    best->sub_batches = bsb;
+    best->split_div = bdiv;
+    if (cache_path) {
+      TuneEntry e;
+      e.key = key;
+      e.sb = bsb;
+      e.div = bdiv;
+      e.ms = best_ms;
+      cache.push_back(e);
+      write_tune_cache(cache_path, cache);
+    }
   });
 }
 

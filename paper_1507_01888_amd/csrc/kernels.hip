@@ -1463,6 +1463,133 @@ __global__ __launch_bounds__(round64(K * K)) void apply_std_kernel(
   }
 }
 
+// ------------------------------------------------------------------ apply (std, MFMA)
+// Standard form for k = 8 (two quads per index) on the FP64 matrix cores: one wave per
+// target, four targets per workgroup.  The three mode products of a triple are the chain of
+// apply_ns_stream_kernel on a k^3 block: step 1 contracts x (block index = z inside a z-quad,
+// source fragments read straight from the input slab), step 2 contracts y in registers, and
+// step 3 contracts z after an in-wave permutation (ds_bpermute) into the target's block,
+// which stays in registers (8 doubles per lane) over all triples of the target.  The next
+// triple's source and operator fragments are loaded while the current one computes, and
+// several waves per SIMD hide what remains of the load latency.
+template <int K>
+__global__ __launch_bounds__(256, 4) void apply_std_mfma_kernel(
+    const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
+    const NSItem* __restrict__ items, const TargetRange* __restrict__ targets, const int ntargets,
+    const double* const* __restrict__ t_tab, const double* const* __restrict__ c_tab,
+    double scale) {
+  constexpr int K2 = K * K, K3 = K * K * K, Q = K / 4;
+  static_assert(K % 4 == 0 && Q == 2, "k = 8: two quads per index");
+  const int lane = threadIdx.x & 63;
+  const int ti = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (ti >= ntargets) return;                 // a whole wave leaves; no barriers below
+  const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
+  const int swap = (16 * lb + 4 * lk + li) * 4;
+  const TargetRange tr = targets[ti];
+  const MRA_GLOBAL double* __restrict__ in = as_global(in_tab[tr.fn]);
+  MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
+  const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
+  auto lane_swap = [&](double v) {
+    const int2 w = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_ds_bpermute(swap, w.x);
+    r.y = __builtin_amdgcn_ds_bpermute(swap, w.y);
+    return __builtin_bit_cast(double, r);
+  };
+  // fragments of one triple: source s[x][y][z] as A operands of step 1 ([xs][yt][zq]),
+  // transposed t blocks as B operands ([quad of the contracted index][quad of the output])
+  struct Frag {
+    double s[Q][Q][Q], tx[Q][Q], ty[Q][Q], tz[Q][Q];
+    double c;
+  };
+  auto load = [&](const NSItem& it, Frag& f) {
+    const MRA_GLOBAL double* sp = in + (size_t)it.src * K3;
+#pragma unroll
+    for (int xs = 0; xs < Q; ++xs)
+#pragma unroll
+      for (int yt = 0; yt < Q; ++yt)
+#pragma unroll
+        for (int zq = 0; zq < Q; ++zq)
+          f.s[xs][yt][zq] = sp[((4 * xs + lk) * K + 4 * yt + li) * K + 4 * zq + lb];
+    const MRA_GLOBAL double* TX = dT + (size_t)it.tx * K2;
+    const MRA_GLOBAL double* TY = dT + (size_t)it.ty * K2;
+    const MRA_GLOBAL double* TZ = dT + (size_t)it.tz * K2;
+#pragma unroll
+    for (int u = 0; u < Q; ++u)
+#pragma unroll
+      for (int v = 0; v < Q; ++v) {
+        f.tx[u][v] = TX[(4 * u + lk) * K + 4 * v + li];
+        f.ty[u][v] = TY[(4 * u + lk) * K + 4 * v + li];
+        f.tz[u][v] = TZ[(4 * u + lk) * K + 4 * v + li];
+      }
+    f.c = dc[it.mu] * scale;
+  };
+  double acc[Q][Q][Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+#pragma unroll
+    for (int b = 0; b < Q; ++b)
+#pragma unroll
+      for (int c = 0; c < Q; ++c) acc[a][b][c] = 0.0;
+  Frag cur, nxt;
+  if (tr.beg < tr.end) load(items[tr.beg], cur);
+  for (int it = tr.beg; it < tr.end; ++it) {
+    if (it + 1 < tr.end) load(items[it + 1], nxt);
+    // step 1: d1[zq][at][yt] (rows y, columns a, block index z)
+    double d1[Q][Q][Q];
+#pragma unroll
+    for (int zq = 0; zq < Q; ++zq)
+#pragma unroll
+      for (int at = 0; at < Q; ++at)
+#pragma unroll
+        for (int yt = 0; yt < Q; ++yt) {
+          double d = 0.0;
+#pragma unroll
+          for (int xs = 0; xs < Q; ++xs)
+            d = __builtin_amdgcn_mfma_f64_4x4x4f64(cur.s[xs][yt][zq], cur.tx[xs][at], d, 0, 0, 0);
+          d1[zq][at][yt] = d;
+        }
+    // step 2: zr[zq][at][bt]
+    double zr[Q][Q][Q];
+#pragma unroll
+    for (int zq = 0; zq < Q; ++zq)
+#pragma unroll
+      for (int at = 0; at < Q; ++at)
+#pragma unroll
+        for (int bt = 0; bt < Q; ++bt) {
+          double d = 0.0;
+#pragma unroll
+          for (int ys = 0; ys < Q; ++ys)
+            d = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[zq][at][ys], cur.ty[ys][bt], d, 0, 0, 0);
+          zr[zq][at][bt] = d;
+        }
+    // step 3: acc[at][bt][ct] += sum over z-quads of c (permuted zr) t_z
+#pragma unroll
+    for (int at = 0; at < Q; ++at)
+#pragma unroll
+      for (int bt = 0; bt < Q; ++bt)
+#pragma unroll
+        for (int zq = 0; zq < Q; ++zq) {
+          const double zt = lane_swap(zr[zq][at][bt]);
+#pragma unroll
+          for (int ct = 0; ct < Q; ++ct)
+            acc[at][bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(zt, cur.c * cur.tz[zq][ct],
+                                                                 acc[at][bt][ct], 0, 0, 0);
+        }
+    cur = nxt;
+  }
+#pragma unroll
+  for (int at = 0; at < Q; ++at)
+#pragma unroll
+    for (int bt = 0; bt < Q; ++bt)
+#pragma unroll
+      for (int ct = 0; ct < Q; ++ct) {
+        const int a = 4 * at + lb, b = 4 * bt + lk, c = 4 * ct + li;
+        out[(size_t)tr.node * K3 + (a * K + b) * K + c] += acc[at][bt][ct];
+      }
+}
+
 // --------------------------------------------------------------------------- sum-down
 // One workgroup of 512 threads per interior output box (for k <= 11 the (2k)^2 output
 // columns of the last product in one pass): three mode products with the unfilter matrix
@@ -2837,6 +2964,13 @@ void launch_apply_std(int k, const double* const* in_tab, double* const* out_tab
                       const double* const* t_tab, const double* const* c_tab, double scale,
                       hipStream_t s) {
   if (ntargets <= 0) return;
+  if (k == 8) {
+    // matrix-core kernel: one wave per target, four per workgroup
+    hipLaunchKernelGGL(apply_std_mfma_kernel<8>, dim3((ntargets + 3) / 4), dim3(256), 0, s,
+                       in_tab, out_tab, items, targets, ntargets, t_tab, c_tab, scale);
+    hip_check(hipGetLastError(), "apply_std_mfma_kernel");
+    return;
+  }
   MRA_DISPATCH_K14(k, hipLaunchKernelGGL(apply_std_kernel<KK>, dim3(ntargets),
                                          dim3(round64(KK * KK)), 0, s, in_tab, out_tab, items,
                                          targets, t_tab, c_tab, scale));

@@ -153,6 +153,11 @@ struct Ctx {
   hipEvent_t ev[8]{};
   Arena arena[5];                      // filter-up; tables of alternate sub-batches; alternate chunks
   double* red_part = nullptr;          // 2048 partial sums of the leaf reductions
+  // schedule of the batched apply (mra_set_schedule / mra_autotune_batch): number of
+  // pipelined sub-batches (0: 4 for >= 8 functions, 2 for >= 2, else 1) and the divisor D of
+  // the split length max(24, items / D) of long target lists
+  int sched_sub_batches = 0;
+  int sched_split_div = 512;
 
   double width() const { return hi - lo; }
   void* dalloc(size_t bytes);

@@ -406,3 +406,39 @@ def test_allocator_null_gives_nomem_without_leak(M):
         assert live == {}, "budget %d: %d allocations not returned" % (budget, len(live))
     _say("allocator budget -> (last status, calls made):", outcomes)
     assert outcomes[0][1] == -2 and outcomes[-1][1] == 0
+
+
+def test_autotuned_schedule(M, tmp_path):
+    """The autotuner times the batched apply under each candidate schedule and keeps the
+    fastest; its JSON cache is reused on the next call.  Results under different schedules
+    agree up to the summation order of split lists, and the tuned one matches the oracle."""
+    _say("case: autotuner, 4 batched Helmholtz functions")
+    ctx = M.Context(0, W.CELL)
+    funcs, ops, params = [], [], []
+    for i in range(4):
+        c, a, x, mu = W.bsh_inputs(i)
+        funcs.append(ctx.project(c, a, x, 10, 1e-4))
+        ops.append(ctx.op_bsh(10, mu, 1e-5, 1e-8))
+        params.append((c, a, x, mu))
+    cache = str(tmp_path / "tune.json")
+    best, times = ctx.autotune_batch(ops, funcs, tau_drop=1e-8, cache_path=cache)
+    _say("tuned schedule", best, "times ms", [round(t, 2) for t in times])
+    assert best["sub_batches"] in (1, 2, 4) and best["split_div"] in (256, 512, 1024)
+    assert np.all(times > 0) and ctx.schedule() == best
+    ctx2 = M.Context(0, W.CELL)
+    best2, times2 = ctx2.autotune_batch(ops, funcs, tau_drop=1e-8, cache_path=cache)
+    assert best2 == best and np.all(times2 == -1.0)
+    outs = [_as_dict(g) for g in ctx.apply_batch(ops, funcs, tau_drop=1e-8)]
+    ctx.set_schedule(1, 256)
+    other = [_as_dict(g) for g in ctx.apply_batch(ops, funcs, tau_drop=1e-8)]
+    for a_, b_ in zip(outs, other):
+        assert set(a_) == set(b_)
+        assert _rel_l2(a_, b_, b_) <= 1e-14
+    c, a, x, mu = params[3]
+    fo = project_adaptive(GaussianSum(c, a, x), 10, 1e-4, W.CELL, 2, 20)
+    cc, tt = bsh_fit(mu, 1e-5, 1e-8, cell_r_hi(*W.CELL))
+    ref, _ = apply_nonstandard(fo, SeparatedOperator(cc, tt), 1e-8)
+    assert set(outs[3]) == set(ref.leaves)
+    assert _rel_l2(outs[3], ref.leaves, ref.leaves) <= TOL
+    with pytest.raises(M.MraError):
+        ctx.set_schedule(-1, 512)
