@@ -22,6 +22,8 @@ environment for scientific simulation"), Section 2:
                 non-standard telescoped apply T^n = T^0 + sum_m (A^m+B^m+C^m),
                 Sec. 2.2, with norm screening; sum-down reconstruction;
 * tree       -- function trees, norm2 / trace / inner (Sec. 3.1 example);
+* compress   -- wavelet (compressed) form, reconstruction and truncation (Sec. 2.2 fast
+                wavelet transform);
 * analytic   -- closed forms used as pins (Gaussian charge potentials).
 
 Readings of points the paper leaves open are stated where they are used.
