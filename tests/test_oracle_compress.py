@@ -73,3 +73,26 @@ def test_truncation_error_is_the_removed_detail_norm(tol):
     assert removed > 0
     assert abs(diff2 - removed) <= 1e-9 * removed + 1e-26
     assert math.sqrt(diff2) <= tol * math.sqrt(len(f.leaves))
+
+
+def test_truncate_keeps_a_small_detail_above_a_large_one():
+    # a box with a small wavelet part but a refined child with a large one stays refined:
+    # the rule works bottom-up and only boxes whose children are leaves can lose them
+    from oracle.compress import Compressed
+    k = 2
+    rng = np.random.default_rng(3)
+    hm = filter_matrix(k)
+
+    def detail(scale):
+        d = rng.standard_normal((2 * k, 2 * k, 2 * k))
+        d -= unfilter3(filter3(d, hm), hm)          # no component in the parent space
+        return scale * d / np.linalg.norm(d)
+
+    P, Q = (0, 0, 0, 0), (1, 1, 0, 1)
+    c = Compressed(k, CELL, rng.standard_normal((k, k, k)), {P: detail(1e-6), Q: detail(1.0)})
+    f = reconstruct(c)
+    assert len(f.leaves) == 15
+    g, removed = truncate(f, 1e-3)
+    assert set(g.leaves) == set(f.leaves) and removed == 0.0
+    g2, removed2 = truncate(f, 2.0)
+    assert list(g2.leaves) == [P] and abs(removed2 - (1.0 + 1e-12)) <= 1e-12
