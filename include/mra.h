@@ -142,7 +142,12 @@ const char* mra_last_error(const mra_ctx* ctx);
 
 /* Adaptive projection of sum_g coeff_g exp(-expnt_g |x - center_g|^2) (Sec. 2.1, eq.
  * projection): exact separable 1D integrals, refinement of a box iff the norm of its
- * wavelet coefficients exceeds thresh. The result lives in device memory. */
+ * wavelet coefficients exceeds thresh. The result lives in device memory.  Level by level,
+ * the device computes the 1D integrals, every box's coefficients and the wavelet norms of
+ * its children block; the host keeps the frontier and the refinement decisions (one small
+ * copy of the norms per level).  ng <= 4096, and per level the table of 1D integrals
+ * (ng x the distinct box indices of the three axes x 5k doubles) at most 8 GiB; MRA_E_UNSUPPORTED
+ * beyond. */
 mra_status mra_project(mra_ctx* ctx, const mra_gaussian* g, int ng,
                        const mra_project_params* params, mra_func** out);
 
@@ -156,6 +161,39 @@ mra_status mra_func_info(const mra_func* f, int* k, int64_t* nodes, int64_t* lea
 mra_status mra_func_export(mra_ctx* ctx, const mra_func* f, int64_t cap, uint64_t* keys,
                            double* coeffs, int64_t* nleaves);
 mra_status mra_func_free(mra_func* f);
+
+/* Wavelet form (Sec. 2.2: two-scale relation, fast wavelet transform).  Every refined box
+ * P has the children block B_P (its 8 children's coefficients as one (2k)^3 block), its
+ * scaling coefficients s_P = (H x H x H) B_P (H = [h0 | h1], the two-scale filters) and its
+ * wavelet part D_P = B_P - (H^T x H^T x H^T) s_P, orthogonal to the parent's polynomial.
+ * A function in wavelet form keeps its tree and slab layout: the root's slab holds s_0 and
+ * the slab of every other node holds the part of its parent's D_P at that node's position.
+ * ||f||^2 = ||s_0||^2 + sum_P ||D_P||^2 (orthonormal bases).
+ *
+ * Only mra_reconstruct, mra_norm2 (over every slab), mra_func_info, mra_func_repr,
+ * mra_func_export_nodes and mra_func_free accept a function in wavelet form; every other
+ * call returns MRA_E_INVALID for one.  Each call below creates a new function (the input
+ * is unchanged; out is untouched on error) and synchronises the context's stream. */
+enum { MRA_REPR_SCALING = 0, MRA_REPR_WAVELET = 1 };
+mra_status mra_func_repr(const mra_func* f, int* repr);
+/* f (scaling form) -> its wavelet form on the same tree. */
+mra_status mra_compress(mra_ctx* ctx, const mra_func* f, mra_func** out);
+/* c (wavelet form) -> the scaling form: top-down, every children block is
+ * unfilter(s_P) + D_P; interior slabs hold s_P as well. */
+mra_status mra_reconstruct(mra_ctx* ctx, const mra_func* c, mra_func** out);
+/* Truncation (Sec. 2.2 discards wavelet coefficients below the threshold): bottom-up, a
+ * refined box whose 8 children are all leaves (after the pruning of finer levels) loses
+ * its children, becoming a leaf holding s_P, iff ||D_P||_F <= tol (the norm and
+ * non-strict comparison of the projection's refinement test).  *out is the truncated
+ * function in scaling form; *removed2 (may be NULL) receives sum ||D_P||^2 over the
+ * removed boxes, which equals ||f - out||^2.  tol >= 0. */
+mra_status mra_truncate(mra_ctx* ctx, const mra_func* f, double tol, mra_func** out,
+                        double* removed2);
+/* Every node's slab: keys as in mra_func_export (every node, ordered by level, then key),
+ * coeffs nnodes * k^3 doubles.  In scaling form interior nodes hold their filtered
+ * coefficients s_P; in wavelet form the slabs described above. */
+mra_status mra_func_export_nodes(mra_ctx* ctx, const mra_func* f, int64_t cap,
+                                 uint64_t* keys, double* coeffs, int64_t* nnodes);
 
 /* Operators: sum_mu c_mu exp(-t_mu r^2), with the 1D operator blocks for wavelet order k
  * cached per (level, displacement, term) on first use (Sec. 2.2 Toeplitz blocks).
@@ -200,7 +238,9 @@ mra_status mra_apply_batch(mra_ctx* ctx, int n, const mra_op* const* ops,
  * on the host), so repeated calls give bitwise identical results.  Each synchronises the
  * context's stream.
  *
- * mra_norm2: 2-norm sqrt(sum over leaves ||s||^2) (the basis is orthonormal, Sec. 2.1). */
+ * mra_norm2: 2-norm sqrt(sum over leaves ||s||^2) (the basis is orthonormal, Sec. 2.1);
+ * for a function in wavelet form sqrt(||s_0||^2 + sum_P ||D_P||^2), the sum over every
+ * slab (Sec. 2.2). */
 mra_status mra_norm2(mra_ctx* ctx, const mra_func* f, double* out);
 /* mra_norm2_noalloc: mra_norm2 for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  It calls no

@@ -5,7 +5,9 @@ HIP kernels for gfx950.  This package only marshals arguments; it raises ImportE
 errors when the library is missing instead of falling back to anything else.
 """
 from ._binding import (Context, Function, Operator, MraError, load, host_fit, host_block,
-                       host_filters, host_spectral_norm, host_project, EXPORTED, LIB_PATH)
+                       host_filters, host_spectral_norm, host_project, EXPORTED, LIB_PATH,
+                       REPR_SCALING, REPR_WAVELET)
 
 __all__ = ["Context", "Function", "Operator", "MraError", "load", "host_fit", "host_block",
-           "host_filters", "host_spectral_norm", "host_project", "EXPORTED", "LIB_PATH"]
+           "host_filters", "host_spectral_norm", "host_project", "EXPORTED", "LIB_PATH",
+           "REPR_SCALING", "REPR_WAVELET"]

@@ -17,6 +17,8 @@ ERRORS = {-1: "MRA_E_INVALID", -2: "MRA_E_NOMEM", -3: "MRA_E_DEVICE", -4: "MRA_E
           -5: "MRA_E_MISMATCH"}
 FORM_NONSTANDARD = 0
 FORM_STANDARD = 1
+REPR_SCALING = 0
+REPR_WAVELET = 1
 
 # every symbol declared in include/mra.h
 EXPORTED = [
@@ -24,7 +26,8 @@ EXPORTED = [
     "mra_func_export", "mra_func_free", "mra_op_coulomb", "mra_op_bsh", "mra_op_gaussians",
     "mra_op_terms", "mra_op_free", "mra_apply", "mra_apply_batch", "mra_norm2", "mra_trace",
     "mra_inner", "mra_distance", "mra_norm2_noalloc", "mra_set_schedule", "mra_get_schedule",
-    "mra_autotune_batch",
+    "mra_autotune_batch", "mra_func_repr", "mra_compress", "mra_reconstruct", "mra_truncate",
+    "mra_func_export_nodes",
     "mra_last_stats", "mra_host_fit", "mra_host_block", "mra_host_filters",
     "mra_host_spectral_norm", "mra_host_project",
 ]
@@ -119,6 +122,11 @@ def load():
     lib.mra_get_schedule.argtypes = [vp, P(Schedule)]
     lib.mra_autotune_batch.argtypes = [vp, ctypes.c_int, P(vp), P(vp), P(ApplyParams),
                                        ctypes.c_char_p, P(Schedule), dp]
+    lib.mra_func_repr.argtypes = [vp, P(ctypes.c_int)]
+    lib.mra_compress.argtypes = [vp, vp, P(vp)]
+    lib.mra_reconstruct.argtypes = [vp, vp, P(vp)]
+    lib.mra_truncate.argtypes = [vp, vp, ctypes.c_double, P(vp), dp]
+    lib.mra_func_export_nodes.argtypes = [vp, vp, ctypes.c_int64, P(ctypes.c_uint64), dp, i64p]
     lib.mra_last_stats.argtypes = [vp, P(ApplyStats)]
     lib.mra_host_fit.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_int, dp, dp, P(ctypes.c_int)]
@@ -381,6 +389,26 @@ class Context:
         self._check(self._lib.mra_distance(self.h, f.h, g.h, ctypes.byref(v)), "mra_distance")
         return v.value
 
+    def compress(self, f):
+        """Wavelet form of f on the same tree (new function)."""
+        h = ctypes.c_void_p()
+        self._check(self._lib.mra_compress(self.h, f.h, ctypes.byref(h)), "mra_compress")
+        return Function(self, h)
+
+    def reconstruct(self, c):
+        """Scaling form of a function in wavelet form (new function)."""
+        h = ctypes.c_void_p()
+        self._check(self._lib.mra_reconstruct(self.h, c.h, ctypes.byref(h)), "mra_reconstruct")
+        return Function(self, h)
+
+    def truncate(self, f, tol):
+        """(truncated function, sum of the squared norms of the dropped wavelet parts)."""
+        h = ctypes.c_void_p()
+        rem = ctypes.c_double()
+        self._check(self._lib.mra_truncate(self.h, f.h, tol, ctypes.byref(h), ctypes.byref(rem)),
+                    "mra_truncate")
+        return Function(self, h), rem.value
+
     def last_stats(self):
         s = ApplyStats()
         self._check(self._lib.mra_last_stats(self.h, ctypes.byref(s)), "mra_last_stats")
@@ -412,6 +440,24 @@ class Function:
         self.ctx._check(self.ctx._lib.mra_func_export(
             self.ctx.h, self.h, n, keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
             _dptr(co), ctypes.byref(cnt)), "mra_func_export")
+        return keys, co
+
+    def repr(self):
+        """REPR_SCALING or REPR_WAVELET."""
+        r = ctypes.c_int()
+        self.ctx._check(self.ctx._lib.mra_func_repr(self.h, ctypes.byref(r)), "mra_func_repr")
+        return r.value
+
+    def export_nodes(self):
+        """(keys of every node, level-major, coeffs (nnodes, k, k, k)): the slab of every node."""
+        inf = self.info()
+        n, k = inf["nodes"], inf["k"]
+        keys = np.zeros(n, dtype=np.uint64)
+        co = np.zeros((n, k, k, k))
+        cnt = ctypes.c_int64()
+        self.ctx._check(self.ctx._lib.mra_func_export_nodes(
+            self.ctx.h, self.h, n, keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+            _dptr(co), ctypes.byref(cnt)), "mra_func_export_nodes")
         return keys, co
 
     def free(self):

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmra.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["host_numerics.cpp", "tree_project.cpp", "apply_ns.cpp", "capi.cpp", "kernels.hip"]
+SOURCES = ["host_numerics.cpp", "tree_project.cpp", "apply_ns.cpp", "capi.cpp", "wavelet.cpp", "kernels.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           # packed FP32 instructions are kept out of all device code

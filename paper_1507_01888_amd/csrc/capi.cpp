@@ -669,6 +669,13 @@ const char* mra_last_error(const mra_ctx* ctx) {
   return ctx ? ctx->c.err.c_str() : g_create_error.c_str();
 }
 
+namespace {
+void need_scaling(const mra::Func& f, const char* what) {
+  if (f.wavelet_form)
+    mra::fail(MRA_E_INVALID, std::string(what) + ": the function is in wavelet form");
+}
+}  // namespace
+
 mra_status mra_project(mra_ctx* ctx, const mra_gaussian* g, int ng,
                        const mra_project_params* p, mra_func** out) {
   if (!ctx) return MRA_E_INVALID;
@@ -681,10 +688,9 @@ mra_status mra_project(mra_ctx* ctx, const mra_gaussian* g, int ng,
       fail(MRA_E_INVALID, "need 0 <= initial_level <= max_level <= 20");
     for (int i = 0; i < ng; ++i)
       if (!(g[i].expnt > 0.0)) fail(MRA_E_INVALID, "Gaussian exponents must be > 0");
+    if (ng > 4096) fail(MRA_E_UNSUPPORTED, "mra_project takes at most 4096 Gaussians");
     std::unique_ptr<mra_func> h(new mra_func());
-    std::vector<double> coeffs;
-    project_gaussians(c, g, ng, p->k, p->thresh, p->initial_level, p->max_level, h->f, coeffs);
-    h->f.coeff.upload(c, coeffs);
+    project_gaussians_device(c, g, ng, p->k, p->thresh, p->initial_level, p->max_level, h->f);
     h->f.device_leaves();
     c->sync();
     *out = h.release();
@@ -708,6 +714,7 @@ mra_status mra_func_export(mra_ctx* ctx, const mra_func* fh, int64_t cap, uint64
   MRA_TRY(c, {
     const Func& f = fh->f;
     if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    need_scaling(f, "mra_func_export");
     int64_t nl = (int64_t)f.leaves.size();
     if (nleaves) *nleaves = nl;
     if (keys || coeffs) {
@@ -735,6 +742,84 @@ mra_status mra_func_free(mra_func* f) {
   if (!f) return MRA_E_INVALID;
   delete f;
   return MRA_OK;
+}
+
+mra_status mra_func_repr(const mra_func* f, int* repr) {
+  if (!f || !repr) return MRA_E_INVALID;
+  *repr = f->f.wavelet_form ? MRA_REPR_WAVELET : MRA_REPR_SCALING;
+  return MRA_OK;
+}
+
+mra_status mra_compress(mra_ctx* ctx, const mra_func* fh, mra_func** out) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (!fh || !out) fail(MRA_E_INVALID, "mra_compress: bad arguments");
+    const Func& f = fh->f;
+    if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    need_scaling(f, "mra_compress");
+    std::unique_ptr<mra_func> h(new mra_func());
+    compress_function(c, f, h->f);
+    *out = h.release();
+  });
+}
+
+mra_status mra_reconstruct(mra_ctx* ctx, const mra_func* ch, mra_func** out) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (!ch || !out) fail(MRA_E_INVALID, "mra_reconstruct: bad arguments");
+    const Func& f = ch->f;
+    if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    if (!f.wavelet_form) fail(MRA_E_INVALID, "mra_reconstruct: the function is in scaling form");
+    std::unique_ptr<mra_func> h(new mra_func());
+    reconstruct_function(c, f, h->f);
+    h->f.device_leaves();
+    c->sync();
+    *out = h.release();
+  });
+}
+
+mra_status mra_truncate(mra_ctx* ctx, const mra_func* fh, double tol, mra_func** out,
+                        double* removed2) {
+  if (!ctx) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    if (!fh || !out || !(tol >= 0.0)) fail(MRA_E_INVALID, "mra_truncate: bad arguments");
+    const Func& f = fh->f;
+    if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    need_scaling(f, "mra_truncate");
+    std::unique_ptr<mra_func> h(new mra_func());
+    double rem = 0.0;
+    truncate_function(c, f, tol, h->f, rem);
+    if (removed2) *removed2 = rem;
+    *out = h.release();
+  });
+}
+
+mra_status mra_func_export_nodes(mra_ctx* ctx, const mra_func* fh, int64_t cap,
+                                 uint64_t* keys, double* coeffs, int64_t* nnodes) {
+  if (!ctx || !fh) return MRA_E_INVALID;
+  Ctx* c = &ctx->c;
+  MRA_TRY(c, {
+    Func& f = const_cast<mra_func*>(fh)->f;   // scaling form: interior slabs are filled
+    if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    const int64_t nn = f.nodes();
+    if (nnodes) *nnodes = nn;
+    if (keys || coeffs) {
+      if (cap < nn) fail(MRA_E_INVALID, "export capacity too small");
+      if (coeffs) {
+        if (!f.wavelet_form) filter_up_function(c, f);
+        hip_check(hipMemcpyAsync(coeffs, f.coeff.p, (size_t)nn * f.k * f.k * f.k * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream),
+                  "hipMemcpyAsync D2H");
+        c->sync();
+      }
+      if (keys)
+        for (int64_t i = 0; i < nn; ++i)
+          keys[i] = (1ULL << (3 * f.level_of(i))) | f.code[i];
+    }
+  });
 }
 
 static mra_status make_op(mra_ctx* ctx, int k, const std::vector<double>& cc,
@@ -830,6 +915,7 @@ mra_status mra_apply(mra_ctx* ctx, const mra_op* oph, const mra_func* fh,
     Func& f = const_cast<mra_func*>(fh)->f;        // refined-box slabs are workspace
     if (op.ctx != c || f.ctx != c) fail(MRA_E_MISMATCH, "handles belong to another context");
     if (op.k != f.k) fail(MRA_E_MISMATCH, "operator and function have different k");
+    need_scaling(f, "mra_apply");
     std::unique_ptr<mra_func> h(new mra_func());
     if (p->form == MRA_FORM_STANDARD) {
       apply_standard(c, op, f, p->disp_radius, h->f);
@@ -863,6 +949,7 @@ mra_status mra_apply_batch(mra_ctx* ctx, int n, const mra_op* const* ophs,
         fail(MRA_E_MISMATCH, "all operators and functions of a batch need the same k");
       for (int j = 0; j < i; ++j)
         if (funcs[j] == funcs[i]) fail(MRA_E_INVALID, "a function appears twice in the batch");
+      need_scaling(*funcs[i], "mra_apply_batch");
     }
     check_nonstandard(funcs[0]->k, *p);
     std::vector<std::unique_ptr<mra_func>> hs(n);
@@ -883,6 +970,12 @@ mra_status mra_norm2(mra_ctx* ctx, const mra_func* fh, double* out) {
     if (!fh || !out) fail(MRA_E_INVALID, "mra_norm2: bad arguments");
     const Func& f = fh->f;
     if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    if (f.wavelet_form) {   // every slab: s_0 and the D_P pieces
+      std::vector<int32_t> all(f.nodes());
+      for (int64_t i = 0; i < f.nodes(); ++i) all[i] = (int32_t)i;
+      *out = std::sqrt(reduce(c, f.k, f.coeff.p, nullptr, all, nullptr, nullptr, 0));
+      return MRA_OK;
+    }
     Func& fm = const_cast<mra_func*>(fh)->f;   // device leaf list is made on first use
     double s = reduce(c, f.k, f.coeff.p, nullptr, f.leaves, nullptr, nullptr, 0,
                       fm.device_leaves());
@@ -897,6 +990,7 @@ mra_status mra_norm2_noalloc(mra_ctx* ctx, const mra_func* fh, double* out) {
     if (!fh || !out) fail(MRA_E_INVALID, "mra_norm2_noalloc: bad arguments");
     const Func& f = fh->f;
     if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    need_scaling(f, "mra_norm2_noalloc");
     if (f.d_leaves.n != f.leaves.size())
       fail(MRA_E_INVALID, "mra_norm2_noalloc: the function's leaf list is not on the device");
     const double s = norm2_noalloc(c->device, f.k, f.coeff.p, f.d_leaves.p,
@@ -912,6 +1006,7 @@ mra_status mra_trace(mra_ctx* ctx, const mra_func* fh, double* out) {
     if (!fh || !out) fail(MRA_E_INVALID, "mra_trace: bad arguments");
     const Func& f = fh->f;
     if (f.ctx != c) fail(MRA_E_MISMATCH, "function belongs to another context");
+    need_scaling(f, "mra_trace");
     std::vector<double> w(f.leaves.size());
     for (size_t i = 0; i < f.leaves.size(); ++i)
       w[i] = std::pow(c->width() / std::ldexp(1.0, f.level_of(f.leaves[i])), 1.5);
@@ -928,6 +1023,8 @@ mra_status mra_inner(mra_ctx* ctx, const mra_func* fh, const mra_func* gh, doubl
     Func& g = const_cast<mra_func*>(gh)->f;
     if (f.ctx != c || g.ctx != c) fail(MRA_E_MISMATCH, "handles belong to another context");
     if (f.k != g.k) fail(MRA_E_MISMATCH, "functions have different k");
+    need_scaling(f, "mra_inner");
+    need_scaling(g, "mra_inner");
     filter_up_function(c, f);
     filter_up_function(c, g);
     // pair the leaves of the intersection of the two trees: boxes present in both where at
@@ -956,6 +1053,8 @@ mra_status mra_distance(mra_ctx* ctx, const mra_func* fh, const mra_func* gh, do
     Func& g = const_cast<mra_func*>(gh)->f;
     if (f.ctx != c || g.ctx != c) fail(MRA_E_MISMATCH, "handles belong to another context");
     if (f.k != g.k) fail(MRA_E_MISMATCH, "functions have different k");
+    need_scaling(f, "mra_distance");
+    need_scaling(g, "mra_distance");
     if (f.code != g.code || f.first_child != g.first_child)
       fail(MRA_E_MISMATCH, "mra_distance: the two functions have different trees");
     double s = reduce(c, f.k, f.coeff.p, g.coeff.p, f.leaves, &g.leaves, nullptr, 3,

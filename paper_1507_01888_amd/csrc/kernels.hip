@@ -1599,7 +1599,7 @@ template <int K>
 __global__ __launch_bounds__(512) void sum_down_kernel(
     double* const* __restrict__ tab, const NodeRef* __restrict__ refs,
     const double* __restrict__ subbuf, const double* __restrict__ h0,
-    const double* __restrict__ h1) {
+    const double* __restrict__ h1, const double sign) {
   constexpr int N = 2 * K, K3 = K * K * K, ZP = N + 1;
   __shared__ double T1[K * K * ZP];
   __shared__ double T2[K * N * ZP];
@@ -1665,7 +1665,239 @@ __global__ __launch_bounds__(512) void sum_down_kernel(
 #pragma unroll
     for (int X = 0; X < N; ++X)
       coeff[(size_t)(fc + ((X / K) << 2 | (cy << 1) | cz)) * K3 + ((X % K) * K + j) * K + m] =
-          old[X] + t[X];
+          old[X] + sign * t[X];
+  }
+}
+
+// ----------------------------------------------------------------- wavelet-form helpers
+// Squared Frobenius norm of the 8 contiguous child slabs (the (2k)^3 children block) of
+// each listed box; one workgroup per box, fixed-order tree, so the result is reproducible.
+__global__ __launch_bounds__(256) void child_norm2_kernel(
+    int k3, const double* __restrict__ coeff, const int32_t* __restrict__ fchild,
+    double* __restrict__ out) {
+  __shared__ double red[256];
+  const double* __restrict__ p = coeff + (size_t)fchild[blockIdx.x] * k3;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < 8 * k3; e += 256) s += p[e] * p[e];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// dst slab to[i] (i if to is null) = src slab from[i]; one workgroup per slab.
+__global__ __launch_bounds__(256) void copy_slabs_kernel(
+    int k3, double* __restrict__ dst, const int32_t* __restrict__ to,
+    const double* __restrict__ src, const int32_t* __restrict__ from) {
+  const double* __restrict__ a = src + (size_t)from[blockIdx.x] * k3;
+  double* __restrict__ b = dst + (size_t)(to ? to[blockIdx.x] : (int32_t)blockIdx.x) * k3;
+  for (int e = threadIdx.x; e < k3; e += 256) b[e] = a[e];
+}
+
+// --------------------------------------------------------------- adaptive projection
+// Projection of f = sum_g c_g exp(-a_g |x - X_g|^2) (Sec. 2.1), one level of the adaptive
+// refinement per pair of launches.
+//
+// gauss1d_kernel: one thread per (1D box, Gaussian) row.  The level's distinct 1D box
+// indices l of the three axes are concatenated (x, then y, then z); row (u, g) holds
+//   [0, K)     int exp(-a (x - X)^2) phi^n_{l,i}(x) dx          (the box itself, level n)
+//   [K, 3K)    the same on the two children 2l, 2l+1 (level n + 1), concatenated
+//   [3K, 5K)   H^T H applied to those 2K values (their part in the parent's space)
+// where H = [h0 | h1] is the two-scale filter.  The integrals are composite Gauss-Legendre
+// rules (nq nodes per panel, panels no wider than min(1, beta^{-1/2}) in the box's unit
+// coordinate, beta = a h^2) over the intersection of the box with the Gaussian's numerical
+// support |u - u0| <= sqrt((50 + log(1 + beta)/2) / beta).  nz[row] is 1 iff any of the
+// 3K integrals is nonzero.
+template <int K>
+__device__ __forceinline__ void scaled_legendre(double u, double* ph) {
+  if (u < 0.0 || u > 1.0) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) ph[i] = 0.0;
+    return;
+  }
+  const double t = 2.0 * u - 1.0;
+  double pm = 1.0, p = t;
+  ph[0] = 1.0;
+  if (K > 1) ph[1] = sqrt(3.0) * t;
+#pragma unroll
+  for (int i = 1; i + 1 < K; ++i) {
+    const double pn = ((2.0 * i + 1.0) * t * p - i * pm) / (i + 1.0);
+    pm = p;
+    p = pn;
+    ph[i + 1] = sqrt(2.0 * (i + 1) + 1.0) * pn;
+  }
+}
+
+template <int K>
+__device__ void gaussian_box_integrals(double a, double X, double lo, double h, int64_t l,
+                                       const double* __restrict__ glx,
+                                       const double* __restrict__ glw, int nq, double* out) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) out[i] = 0.0;
+  const double beta = a * h * h;
+  const double u0 = (X - lo) / h - (double)l;
+  const double half = beta > 0.0 ? sqrt((50.0 + 0.5 * log1p(beta)) / beta) : INFINITY;
+  const double ua = fmax(0.0, u0 - half), ub = fmin(1.0, u0 + half);
+  if (ub <= ua) return;
+  const double width = beta > 0.0 ? fmin(1.0, 1.0 / sqrt(beta)) : 1.0;
+  const int npan = max(1, (int)ceil((ub - ua) / width));
+  const double step = (ub - ua) / npan;
+  double ph[K];
+  for (int pn = 0; pn < npan; ++pn) {
+    const double ea = ua + pn * step, eb = (pn + 1 == npan) ? ub : ua + (pn + 1) * step;
+    for (int q = 0; q < nq; ++q) {
+      const double u = ea + (eb - ea) * glx[q];
+      const double wt = (eb - ea) * glw[q] * exp(-beta * (u - u0) * (u - u0));
+      scaled_legendre<K>(u, ph);
+#pragma unroll
+      for (int i = 0; i < K; ++i) out[i] += wt * ph[i];
+    }
+  }
+  const double sh = sqrt(h);
+#pragma unroll
+  for (int i = 0; i < K; ++i) out[i] *= sh;
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void gauss1d_kernel(
+    const double* __restrict__ gpar, int ng, const int64_t* __restrict__ lvals, int nl,
+    int off1, int off2, int n, double lo, double W, const double* __restrict__ glx,
+    const double* __restrict__ glw, int nq, const double* __restrict__ h0,
+    const double* __restrict__ h1, double* __restrict__ T, uint8_t* __restrict__ nz) {
+  constexpr int RW = 5 * K;
+  const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (r >= (int64_t)nl * ng) return;
+  const int u = (int)(r / ng), g = (int)(r % ng);
+  const int ax = (u >= off1) + (u >= off2);
+  const double a = gpar[5 * g], X = gpar[5 * g + 1 + ax];
+  const int64_t l = lvals[u];
+  const double h = W / ldexp(1.0, n), hc = W / ldexp(1.0, n + 1);
+  double own[K], c0[K], c1[K];
+  gaussian_box_integrals<K>(a, X, lo, h, l, glx, glw, nq, own);
+  gaussian_box_integrals<K>(a, X, lo, hc, 2 * l, glx, glw, nq, c0);
+  gaussian_box_integrals<K>(a, X, lo, hc, 2 * l + 1, glx, glw, nq, c1);
+  double sp[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int x = 0; x < K; ++x) acc += h0[i * K + x] * c0[x];
+#pragma unroll
+    for (int x = 0; x < K; ++x) acc += h1[i * K + x] * c1[x];
+    sp[i] = acc;
+  }
+  double* __restrict__ row = T + r * RW;
+  bool any = false;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    row[i] = own[i];
+    row[K + i] = c0[i];
+    row[2 * K + i] = c1[i];
+    any = any || own[i] != 0.0 || c0[i] != 0.0 || c1[i] != 0.0;
+  }
+#pragma unroll
+  for (int x = 0; x < K; ++x) {
+    double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      p0 += h0[i * K + x] * sp[i];
+      p1 += h1[i * K + x] * sp[i];
+    }
+    row[3 * K + x] = p0;
+    row[4 * K + x] = p1;
+  }
+  nz[r] = any ? 1 : 0;
+}
+
+// project_level_kernel: one workgroup per box of the level's frontier, boxu[3 b + ax] = the
+// box's row index u on axis ax.  The Gaussians whose three rows are nonzero are listed (in
+// ascending order) and staged in LDS GC at a time.  Thread (i, j) < K^2 accumulates the
+// box's own coefficients s[i][j][m] = sum_g c_g x_i y_j z_m (into S, slab b); with test set,
+// thread (X, Y) < (2K)^2 accumulates the wavelet part of the children block column
+//   d[X][Y][Z] = sum_g c_g (xc_X yc_Y zc_Z - xp_X yp_Y zp_Z)
+// (B minus its part in the parent's space; rank one per Gaussian, so the filter acts on
+// the 1D rows), and d2[b] = ||d||_F^2 by a fixed-order tree.
+template <int K>
+__global__ __launch_bounds__(1024) void project_level_kernel(
+    const double* __restrict__ T, const uint8_t* __restrict__ nz,
+    const int32_t* __restrict__ boxu, int ng, const double* __restrict__ gpar, int test,
+    double* __restrict__ d2, double* __restrict__ S) {
+  constexpr int N = 2 * K, RW = 5 * K, GC = 16, K3 = K * K * K;
+  __shared__ double rows[GC][3][RW];
+  __shared__ double cg[GC];
+  __shared__ double red[1024];
+  __shared__ int nact_s;
+  extern __shared__ int act[];   // ng entries
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int bu0 = boxu[3 * blockIdx.x], bu1 = boxu[3 * blockIdx.x + 1],
+            bu2 = boxu[3 * blockIdx.x + 2];
+  if (tid < 64) {   // wave 0 lists the active Gaussians in ascending order
+    int cnt = 0;
+    for (int base = 0; base < ng; base += 64) {
+      const int g = base + tid;
+      const bool f = g < ng && nz[(size_t)bu0 * ng + g] && nz[(size_t)bu1 * ng + g] &&
+                     nz[(size_t)bu2 * ng + g];
+      const unsigned long long m = __ballot(f);
+      if (f) act[cnt + __popcll(m & ((1ULL << tid) - 1ULL))] = g;
+      cnt += __popcll(m);
+    }
+    if (tid == 0) nact_s = cnt;
+  }
+  __syncthreads();
+  const int nact = nact_s;
+  double d[N], s[K];
+#pragma unroll
+  for (int z = 0; z < N; ++z) d[z] = 0.0;
+#pragma unroll
+  for (int m = 0; m < K; ++m) s[m] = 0.0;
+  const int X = tid / N, Y = tid % N, i = tid / K, j = tid % K;
+  for (int c0 = 0; c0 < nact; c0 += GC) {
+    const int cnt = min(GC, nact - c0);
+    __syncthreads();
+    for (int e = tid; e < cnt * 3 * RW; e += nt) {
+      const int gi = e / (3 * RW), rem = e % (3 * RW), ax = rem / RW, w = rem % RW;
+      const int bu = ax == 0 ? bu0 : (ax == 1 ? bu1 : bu2);
+      rows[gi][ax][w] = T[((size_t)bu * ng + act[c0 + gi]) * RW + w];
+    }
+    if (tid < cnt) cg[tid] = gpar[5 * act[c0 + tid] + 4];
+    __syncthreads();
+    if (test && tid < N * N) {
+      for (int gi = 0; gi < cnt; ++gi) {
+        const double a = cg[gi] * rows[gi][0][K + X] * rows[gi][1][K + Y];
+        const double b = cg[gi] * rows[gi][0][3 * K + X] * rows[gi][1][3 * K + Y];
+#pragma unroll
+        for (int z = 0; z < N; ++z) d[z] += a * rows[gi][2][K + z] - b * rows[gi][2][3 * K + z];
+      }
+    }
+    if (tid < K * K) {
+      for (int gi = 0; gi < cnt; ++gi) {
+        const double cij = cg[gi] * rows[gi][0][i] * rows[gi][1][j];
+#pragma unroll
+        for (int m = 0; m < K; ++m) s[m] += cij * rows[gi][2][m];
+      }
+    }
+  }
+  if (tid < K * K) {
+    double* __restrict__ o = S + (size_t)blockIdx.x * K3 + (size_t)(i * K + j) * K;
+#pragma unroll
+    for (int m = 0; m < K; ++m) o[m] = s[m];
+  }
+  if (test) {
+    double sq = 0.0;
+    if (tid < N * N) {
+#pragma unroll
+      for (int z = 0; z < N; ++z) sq += d[z] * d[z];
+    }
+    red[tid] = sq;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+      if (tid < st && tid + st < nt) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    if (tid == 0) d2[blockIdx.x] = red[0];
   }
 }
 
@@ -2978,11 +3210,52 @@ void launch_apply_std(int k, const double* const* in_tab, double* const* out_tab
 }
 
 void launch_sum_down(int k, double* const* coeff_tab, const NodeRef* refs, int count,
-                     const double* subbuf, const double* h0, const double* h1, hipStream_t s) {
+                     const double* subbuf, const double* h0, const double* h1, hipStream_t s,
+                     double sign) {
   if (count <= 0) return;
   MRA_DISPATCH_K14(k, hipLaunchKernelGGL(sum_down_kernel<KK>, dim3(count), dim3(512), 0, s,
-                                         coeff_tab, refs, subbuf, h0, h1));
+                                         coeff_tab, refs, subbuf, h0, h1, sign));
   hip_check(hipGetLastError(), "sum_down_kernel");
+}
+
+void launch_child_norm2(int k, const double* coeff, const int32_t* fchild, int count,
+                        double* out, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(child_norm2_kernel, dim3(count), dim3(256), 0, s, k * k * k, coeff, fchild,
+                     out);
+  hip_check(hipGetLastError(), "child_norm2_kernel");
+}
+
+void launch_copy_slabs(int k, double* dst, const int32_t* to, const double* src,
+                       const int32_t* from, int count, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(copy_slabs_kernel, dim3(count), dim3(256), 0, s, k * k * k, dst, to, src,
+                     from);
+  hip_check(hipGetLastError(), "copy_slabs_kernel");
+}
+
+void launch_gauss1d(int k, const double* gpar, int ng, const int64_t* lvals, int nl, int off1,
+                    int off2, int n, double lo, double W, const double* glx, const double* glw,
+                    int nq, const double* h0, const double* h1, double* T, uint8_t* nz,
+                    hipStream_t s) {
+  const int64_t rows = (int64_t)nl * ng;
+  if (rows <= 0) return;
+  if ((rows + 63) / 64 > INT32_MAX) fail(MRA_E_UNSUPPORTED, "projection level too large");
+  MRA_DISPATCH_K14(k, hipLaunchKernelGGL(gauss1d_kernel<KK>, dim3((unsigned)((rows + 63) / 64)),
+                                         dim3(64), 0, s, gpar, ng, lvals, nl, off1, off2, n, lo,
+                                         W, glx, glw, nq, h0, h1, T, nz));
+  hip_check(hipGetLastError(), "gauss1d_kernel");
+}
+
+void launch_project_level(int k, const double* T, const uint8_t* nz, const int32_t* boxu,
+                          int nbox, int ng, const double* gpar, int test, double* d2,
+                          double* S, hipStream_t s) {
+  if (nbox <= 0) return;
+  const int threads = round64(std::max(4 * k * k, 64));
+  MRA_DISPATCH_K14(k, hipLaunchKernelGGL(project_level_kernel<KK>, dim3(nbox), dim3(threads),
+                                         (size_t)ng * sizeof(int), s, T, nz, boxu, ng, gpar,
+                                         test, d2, S));
+  hip_check(hipGetLastError(), "project_level_kernel");
 }
 
 // ---------------------------------------------------------- norm2 without device allocation

@@ -208,6 +208,7 @@ struct Func {
   DevArray<double> coeff;              // nodes * k^3
   DevArray<int32_t> d_leaves;          // device copy of `leaves`, made on first use
   bool interior_valid = false;
+  bool wavelet_form = false;           // slabs hold s_0 and the D_P pieces (Sec. 2.2)
 
   int64_t nodes() const { return (int64_t)code.size(); }
   int level_of(int64_t node) const;
@@ -217,6 +218,13 @@ struct Func {
 
 // Build the node arrays of a full octree from per-level sorted codes.
 void build_tree(Func& f, const std::vector<std::vector<uint64_t>>& levels);
+
+// Wavelet form (Sec. 2.2): out is a new function; the input is left unchanged.
+void compress_function(Ctx* ctx, const Func& f, Func& out);
+void reconstruct_function(Ctx* ctx, const Func& c, Func& out);
+// Drops D_P of refined boxes whose children are leaves while ||D_P|| <= tol, bottom-up;
+// removed2 = sum of the dropped ||D_P||^2 (the squared L2 error, by orthogonality).
+void truncate_function(Ctx* ctx, const Func& f, double tol, Func& out, double& removed2);
 
 // ------------------------------------------------------------------------- operator
 struct Op {
@@ -253,6 +261,10 @@ uint16_t bf16_bits(double v);
 void project_gaussians(Ctx* ctx, const mra_gaussian* g, int ng, int k, double thresh,
                        int initial_level, int max_level, Func& out,
                        std::vector<double>& leaf_coeffs);
+// The same projection with the integrals, coefficients and refinement tests on the device;
+// out.coeff receives the leaf slabs (interior slabs zero).
+void project_gaussians_device(Ctx* ctx, const mra_gaussian* g, int ng, int k, double thresh,
+                              int initial_level, int max_level, Func& out);
 
 // ------------------------------------------------------------------------- device side
 struct NSItem {          // one kept (source, displacement, term) triple of a target
@@ -322,8 +334,27 @@ void launch_apply_std(int k, const double* const* in_tab, double* const* out_tab
                       const NSItem* items, const TargetRange* targets, int ntargets,
                       const double* const* t_tab, const double* const* c_tab, double scale,
                       hipStream_t s);
+// children of each listed box += sign * unfilter(box's slab [+ its subbuf block]);
+// sign = -1 turns a children block into the box's wavelet part D_P (Sec. 2.2).
 void launch_sum_down(int k, double* const* coeff_tab, const NodeRef* refs, int count,
-                     const double* subbuf, const double* h0, const double* h1, hipStream_t s);
+                     const double* subbuf, const double* h0, const double* h1, hipStream_t s,
+                     double sign = 1.0);
+// out[i] = squared norm of the 8 slabs starting at fchild[i] (a box's children block).
+void launch_child_norm2(int k, const double* coeff, const int32_t* fchild, int count,
+                        double* out, hipStream_t s);
+// dst slab to[i] (slab i when to is null) = src slab from[i], i < count.
+void launch_copy_slabs(int k, double* dst, const int32_t* to, const double* src,
+                       const int32_t* from, int count, hipStream_t s);
+// Adaptive projection of a Gaussian sum, one level (kernels.hip describes the row layout):
+// 1D integral rows for the level's distinct box indices, then per box its own coefficients
+// into S and (test != 0) the squared norm of its children block's wavelet part into d2.
+void launch_gauss1d(int k, const double* gpar, int ng, const int64_t* lvals, int nl, int off1,
+                    int off2, int n, double lo, double W, const double* glx, const double* glw,
+                    int nq, const double* h0, const double* h1, double* T, uint8_t* nz,
+                    hipStream_t s);
+void launch_project_level(int k, const double* T, const uint8_t* nz, const int32_t* boxu,
+                          int nbox, int ng, const double* gpar, int test, double* d2,
+                          double* S, hipStream_t s);
 void launch_leaf_reduce(int k, const double* a, const double* b, const int32_t* leaves_a,
                         const int32_t* leaves_b, const double* weight, int count, int mode,
                         double* partial, int nblocks, hipStream_t s);

@@ -8,6 +8,7 @@
 // is not refined becomes a leaf holding its own projection.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <thread>
 #include <unordered_map>
 
@@ -362,6 +363,145 @@ void project_gaussians(Ctx* ctx, const mra_gaussian* g, int ng, int k, double th
     auto it = std::lower_bound(beg, end, code);
     int64_t node = it - out.code.begin();
     std::copy(lv.second.begin(), lv.second.end(), leaf_coeffs.begin() + node * k3);
+  }
+}
+
+void project_gaussians_device(Ctx* ctx, const mra_gaussian* g, int ng, int k, double thresh,
+                              int initial_level, int max_level, Func& out) {
+  // Level by level: the host keeps the frontier (its box indices) and the refinement
+  // decisions; the device computes every integral, coefficient and wavelet norm.
+  if (ng > 4096) fail(MRA_E_UNSUPPORTED, "the device projection takes at most 4096 Gaussians");
+  const int k3 = k * k * k;
+  std::vector<double> gp(5 * (size_t)ng);
+  for (int i = 0; i < ng; ++i) {
+    gp[5 * i] = g[i].expnt;
+    for (int a = 0; a < 3; ++a) gp[5 * i + 1 + a] = g[i].center[a];
+    gp[5 * i + 4] = g[i].coeff;
+  }
+  std::vector<double> h0v, h1v;
+  two_scale_filters(k, h0v, h1v);
+  const GLRule& rule = gauss_legendre01(k + 20);
+  DevArray<double> d_gp, d_h0, d_h1, d_glx, d_glw;
+  d_gp.upload(ctx, gp);
+  d_h0.upload(ctx, h0v);
+  d_h1.upload(ctx, h1v);
+  d_glx.upload(ctx, rule.x);
+  d_glw.upload(ctx, rule.w);
+  struct Box {
+    int64_t lx, ly, lz;
+  };
+  std::vector<Box> frontier;
+  const int64_t nb = (int64_t)1 << initial_level;
+  for (int64_t x = 0; x < nb; ++x)
+    for (int64_t y = 0; y < nb; ++y)
+      for (int64_t z = 0; z < nb; ++z) frontier.push_back({x, y, z});
+  struct Leaf {
+    uint64_t key;       // level-prefixed code, as in the host projection
+    int32_t lev, slot;  // staging buffer (per level) and slab in it
+  };
+  std::vector<Leaf> leaves;
+  std::vector<std::unique_ptr<DevArray<double>>> staging;
+  for (int n = initial_level; n <= max_level && !frontier.empty(); ++n) {
+    const int64_t nbox = (int64_t)frontier.size();
+    if (nbox > INT32_MAX) fail(MRA_E_UNSUPPORTED, "projection level too large");
+    // distinct 1D box indices per axis, concatenated x, y, z
+    std::vector<int64_t> lv[3];
+    for (const Box& b : frontier) {
+      lv[0].push_back(b.lx);
+      lv[1].push_back(b.ly);
+      lv[2].push_back(b.lz);
+    }
+    std::vector<int64_t> lvals;
+    int64_t off[4] = {0, 0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+      std::sort(lv[a].begin(), lv[a].end());
+      lv[a].erase(std::unique(lv[a].begin(), lv[a].end()), lv[a].end());
+      lvals.insert(lvals.end(), lv[a].begin(), lv[a].end());
+      off[a + 1] = (int64_t)lvals.size();
+    }
+    std::vector<int32_t> boxu(3 * (size_t)nbox);
+    for (int64_t b = 0; b < nbox; ++b) {
+      const int64_t l3[3] = {frontier[b].lx, frontier[b].ly, frontier[b].lz};
+      for (int a = 0; a < 3; ++a)
+        boxu[3 * b + a] = (int32_t)(off[a] + (std::lower_bound(lv[a].begin(), lv[a].end(), l3[a]) -
+                                               lv[a].begin()));
+    }
+    const int nl = (int)lvals.size();
+    if ((double)nl * ng * 5 * k * sizeof(double) > 8.0 * (1 << 30))
+      fail(MRA_E_UNSUPPORTED, "projection level too large (1D integral table above 8 GiB)");
+    DevArray<int64_t> d_lvals;
+    DevArray<int32_t> d_boxu;
+    DevArray<double> d_T, d_d2;
+    DevArray<uint8_t> d_nz;
+    d_lvals.upload(ctx, lvals);
+    d_boxu.upload(ctx, boxu);
+    d_T.alloc(ctx, (size_t)nl * ng * 5 * k);
+    d_nz.alloc(ctx, (size_t)nl * ng);
+    const bool test = n < max_level;
+    d_d2.alloc(ctx, test ? nbox : 1);
+    staging.emplace_back(new DevArray<double>());
+    staging.back()->alloc(ctx, (size_t)nbox * k3);
+    launch_gauss1d(k, d_gp.p, ng, d_lvals.p, nl, (int)off[1], (int)off[2], n, ctx->lo,
+                   ctx->width(), d_glx.p, d_glw.p, (int)rule.x.size(), d_h0.p, d_h1.p, d_T.p,
+                   d_nz.p, ctx->stream);
+    launch_project_level(k, d_T.p, d_nz.p, d_boxu.p, (int)nbox, ng, d_gp.p, test ? 1 : 0,
+                         d_d2.p, staging.back()->p, ctx->stream);
+    std::vector<double> d2(test ? nbox : 0);
+    if (test)
+      hip_check(hipMemcpyAsync(d2.data(), d_d2.p, nbox * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream),
+                "hipMemcpyAsync D2H");
+    ctx->sync();
+    std::vector<Box> next;
+    for (int64_t b = 0; b < nbox; ++b) {
+      const Box& x = frontier[b];
+      if (test && std::sqrt(d2[b]) > thresh) {
+        for (int c = 0; c < 8; ++c)
+          next.push_back({2 * x.lx + ((c >> 2) & 1), 2 * x.ly + ((c >> 1) & 1), 2 * x.lz + (c & 1)});
+      } else {
+        leaves.push_back({((uint64_t)n << 58) | interleave(n, x.lx, x.ly, x.lz),
+                          (int32_t)(staging.size() - 1), (int32_t)b});
+      }
+    }
+    frontier.swap(next);
+  }
+  // node sets: leaves plus all ancestors
+  std::vector<std::vector<uint64_t>> sets(max_level + 1);
+  for (const Leaf& lf : leaves) {
+    int n = (int)(lf.key >> 58);
+    uint64_t code = lf.key & ((1ULL << 58) - 1);
+    sets[n].push_back(code);
+    for (int m = n - 1; m >= 0; --m) {
+      code >>= 3;
+      sets[m].push_back(code);
+    }
+  }
+  for (auto& st : sets) {
+    std::sort(st.begin(), st.end());
+    st.erase(std::unique(st.begin(), st.end()), st.end());
+  }
+  out.ctx = ctx;
+  out.k = k;
+  build_tree(out, sets);
+  out.coeff.alloc(ctx, (size_t)out.nodes() * k3);
+  launch_zero(out.coeff.p, out.coeff.n, ctx->stream);
+  // leaf slabs from the staging buffers into node order, one copy launch per level
+  std::vector<std::vector<int32_t>> to(staging.size()), from(staging.size());
+  for (const Leaf& lf : leaves) {
+    const int n = (int)(lf.key >> 58);
+    const uint64_t code = lf.key & ((1ULL << 58) - 1);
+    auto beg = out.code.begin() + out.level_off[n], end = out.code.begin() + out.level_off[n + 1];
+    to[lf.lev].push_back((int32_t)(std::lower_bound(beg, end, code) - out.code.begin()));
+    from[lf.lev].push_back(lf.slot);
+  }
+  for (size_t v = 0; v < staging.size(); ++v) {
+    if (to[v].empty()) continue;
+    DevArray<int32_t> d_to, d_from;
+    d_to.upload(ctx, to[v]);
+    d_from.upload(ctx, from[v]);
+    launch_copy_slabs(k, out.coeff.p, d_to.p, staging[v]->p, d_from.p, (int)to[v].size(),
+                      ctx->stream);
+    ctx->sync();
   }
 }
 
