@@ -1128,6 +1128,14 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       std::stable_sort(work.begin(), work.end(), by_len);
       std::stable_sort(tgt_sub.begin(), tgt_sub.end(), by_len);
       std::stable_sort(low_work.begin(), low_work.end(), by_len);
+      if (timing && !low_work.empty()) {
+        int64_t tot = 0;
+        for (const TargetRange& t : low_work) tot += t.end - t.beg;
+        std::fprintf(stderr, "[mra] low-tier lists: %zu targets, %lld triples, longest %d, 10th %d\n",
+                     low_work.size(), (long long)tot, low_work[0].end - low_work[0].beg,
+                     low_work[std::min<size_t>(9, low_work.size() - 1)].end -
+                         low_work[std::min<size_t>(9, low_work.size() - 1)].beg);
+      }
       mark("target ranges");
       const size_t o_work = A1.put(work), o_sub = A1.put(tgt_sub), o_spl = A1.put(splits),
                    o_lwork = A1.put(low_work);

@@ -61,6 +61,7 @@ __global__ void zero_batch_kernel(double* const* __restrict__ tab, const int64_t
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -2757,6 +2758,16 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 }
 
 // ------------------------------------------------------------- apply (low tier, BF16)
+// Step-x tiles per wave, shifted towards the waves with fewer a-quads for steps z and y (20
+// products per a against 4 per tile; quads per wave: k = 14 (2, 2, 2, 1), k = 12
+// (2, 2, 1, 1), k = 10 (2, 1, 1, 1)), with at most 13 tiles per wave so that the
+// accumulators fit beside the source rows.
+__host__ __device__ constexpr int low_tiles(int k, int w) {
+  return k == 14 ? (w < 3 ? 12 : 13) : k == 12 ? (w < 2 ? 5 : 13) : (w == 0 ? 4 : 7);
+}
+__host__ __device__ constexpr int low_tile0(int k, int w) {
+  return w == 0 ? 0 : low_tile0(k, w - 1) + low_tiles(k, w - 1);
+}
 // Triples whose norm bound eta is far below thresh.  Each adds its whole contribution to
 // the target's children block,
 //   c_mu [(R_x x R_y x R_z) - (P_x x P_y x P_z)] B_P,   P = H^T t H  (level n > 0),
@@ -2774,10 +2785,16 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 // source rows X[a][b][.] as A and R_z / E_z rows as B; its two row tiles (b < 16, b >= 16)
 // stacked lane-wise are the B operand of step y (contract b) if the contraction slots of
 // step y are permuted accordingly (the V layout of the operator records).  Step x (contract
-// a) needs all a of a column (b', c'): each wave handles pairs of a, writes the two results
-// of step y (R_y-part and E_y/P_y-part, scaled by c_mu, BF16) to LDS rows q = (b', c') with
-// a innermost, and after a barrier every wave contracts its share of the q tiles with
-// E_x and P_x, accumulating in registers over all triples of the target.
+// a) needs all a of a column (b', c'): each wave handles whole quads of a (wave w: quads w
+// and w + 4), writes the two results of step y (R_y-part and E_y/P_y-part, scaled by c_mu,
+// BF16) of a quad's four a as one 8-byte write to LDS rows q = (b', c') of 32 a slots, and
+// after a barrier every wave contracts its share of the q tiles with E_x and P_x,
+// accumulating in registers over all triples of the target.  Granule h (a = 8h .. 8h + 7)
+// of row q sits at position h ^ ((q >> 1) & 3) of the row: eight consecutive rows then
+// cover all 32 banks with their granules, so the 16-byte reads of step x (eight lanes,
+// consecutive q) and the 8-byte writes (sixteen lanes, consecutive q, one half of each
+// granule) have no bank conflicts beyond two-way on the writes.  Slots a >= 2k are zero
+// from the start and never written.
 //
 // The seven operator matrices a triple reads (U(R_z), U(E_z), V(R_y), V(E_y), V(P_y), U(E_x),
 // U(P_x)) are copied into LDS one triple ahead by buffer loads that write LDS directly
@@ -2795,10 +2812,14 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
   constexpr int UP = (N + 7) / 8 * 8;          // padded contraction length (U layout)
   constexpr int XB = N * N * UP;               // BF16 per mirrored children block
   constexpr int LU = N * UP, LV = N * 32, REC = 3 * LU + 3 * LV;
-  constexpr int NPAIR = N / 2, PPW = (NPAIR + 3) / 4;
-  constexpr int NQ = N2 / 16, QPW = (NQ + 3) / 4;
-  constexpr int TSZ = N2 * UP + N * 8;         // 16 bytes of padding after every N rows
-  static_assert(N > 16 && N <= 32 && N2 % 16 == 0, "two 16-wide tiles per index, even k");
+  constexpr int NQUAD = N / 4, QDW = (NQUAD + 3) / 4;   // a-quads; a wave owns quads w, w + 4
+  constexpr int NQ = N2 / 16;                           // 16-row tiles of step x
+  constexpr int TMAX = low_tiles(K, 3) > low_tiles(K, 0) ? low_tiles(K, 3) : low_tiles(K, 0);
+  static_assert(low_tiles(K, 0) + low_tiles(K, 1) + low_tiles(K, 2) + low_tiles(K, 3) == NQ,
+                "every step-x tile has one wave");
+  constexpr int TSZ = (N2 + 1) * 32;                    // T rows [q][a slot], 4 granules each,
+                                                        // and a row that takes the padding writes
+  static_assert(N > 16 && N <= 32 && N2 % 16 == 0 && N % 4 == 0, "two 16-wide tiles per index, even k");
   // operator staging: matrix m has N rows of GM[m] granules (8 BF16 each) in the record,
   // RSM[m] (odd) granules per row in LDS; the extra granules read zeros
   constexpr int GU = UP / 8, GV = 4;
@@ -2806,64 +2827,74 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
   constexpr int SU = 8 * RU, SV = 8 * RV;      // LDS row strides in BF16
   constexpr int MU = N * RU, MV = N * RV;      // granules per staged matrix
   constexpr int OPG = 4 * MU + 3 * MV, OROWS = (OPG + 63) / 64, ORPW = (OROWS + 3) / 4;
-  constexpr int OPB = 8 * 64 * OROWS;          // BF16 per half of the staging buffer
   // BF16 offsets of the staged matrices
   constexpr int O_RZ = 0, O_EZ = 8 * MU, O_RY = 16 * MU, O_EY = O_RY + 8 * MV, O_PY = O_EY + 8 * MV;
   constexpr int O_EX = O_PY + 8 * MV, O_PX = O_EX + 8 * MU;
+  // BF16 per half of the staging buffer: the copied rows, and room for the fragment reads of
+  // rows up to 31 (rows >= 2k are read without a mask: they only reach outputs >= 2k, which
+  // are never stored)
+  constexpr int OPB_C = 8 * 64 * OROWS, OPB_R = (O_PX + 31 * SU + 32 + 511) / 512 * 512;
+  constexpr int OPB = OPB_C > OPB_R ? OPB_C : OPB_R;
+  static_assert(O_PY + 31 * SV + 32 <= OPB && O_EZ + 31 * SU + 32 <= OPB, "fragment reads in bounds");
   __shared__ __attribute__((aligned(16))) uint16_t T1s[TSZ];
   __shared__ __attribute__((aligned(16))) uint16_t T2s[TSZ];
   __shared__ __attribute__((aligned(16))) uint16_t Ob0[OPB];
   __shared__ __attribute__((aligned(16))) uint16_t Ob1[OPB];
   __shared__ int s_next;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches
   const int g = lane >> 4, r = lane & 15;
-  const bool kin = 8 * g < UP;
   const bf16x8 zero8 = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
   auto ld8 = [&](const uint16_t* p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p)); };
   auto ld8g = [&](const MRA_GLOBAL uint16_t* p) {
     return __builtin_bit_cast(bf16x8, *(const MRA_GLOBAL u32x4*)p);
   };
-  // slots a in [N, UP) of the T rows are never written: clear everything once
+  // slots a >= 2k of the T rows are never written, and the staging buffers' tails are read
+  // unmasked (into outputs that are never stored): clear everything once, so that all of it
+  // is finite
   for (int e = tid; e < TSZ / 8; e += 256) {
     reinterpret_cast<u32x4*>(T1s)[e] = u32x4{0u, 0u, 0u, 0u};
     reinterpret_cast<u32x4*>(T2s)[e] = u32x4{0u, 0u, 0u, 0u};
   }
-  // this lane's granule of each of its staging rows: which record (0: R_z's, 1: R_y's,
-  // 2: R_x's) and the byte offset inside it; padding granules read past the descriptor
-  constexpr int kPast = 0x7FFFFFF0;
-  int o_sel[ORPW], o_off[ORPW];
-#pragma unroll
-  for (int q = 0; q < ORPW; ++q) {
-    const int j = 64 * (wave + 4 * q) + lane;
-    int sel = 0, off = kPast;
-    const int mstart[8] = {0, MU, 2 * MU, 2 * MU + MV, 2 * MU + 2 * MV, 2 * MU + 3 * MV,
-                           3 * MU + 3 * MV, OPG};
-    // record parts: U(R), U(E), U(P) at 0, LU, 2 LU; V(R), V(E), V(P) at 3 LU + m LV
-    const int part[7] = {0, LU, 3 * LU, 3 * LU + LV, 3 * LU + 2 * LV, LU, 2 * LU};
-    const int recsel[7] = {0, 0, 1, 1, 1, 2, 2};
-#pragma unroll
-    for (int m = 0; m < 7; ++m) {
-      if (j >= mstart[m] && j < mstart[m + 1]) {
-        const bool u = m < 2 || m >= 5;
-        const int rs = u ? RU : RV, gm = u ? GU : GV, w = u ? UP : 32;
-        const int row = (j - mstart[m]) / rs, col = (j - mstart[m]) % rs;
-        sel = recsel[m];
-        if (col < gm) off = 2 * (part[m] + row * w + 8 * col);
-      }
-    }
-    o_sel[q] = sel;
-    o_off[q] = off;
+  for (int e = tid; e < OPB / 8; e += 256) {
+    reinterpret_cast<u32x4*>(Ob0)[e] = u32x4{0u, 0u, 0u, 0u};
+    reinterpret_cast<u32x4*>(Ob1)[e] = u32x4{0u, 0u, 0u, 0u};
   }
+  // Operator staging: lane l of staging row w' = wave + 4 q copies granule j = 64 w' + l of
+  // the seven matrices laid out one after another with RU / RV granules per row; its source
+  // is a granule of the record of R_z, R_y or R_x (selected per triple from the item) or,
+  // for row padding and past the last matrix, nothing (an offset past the descriptor's
+  // range, which reads zeros).  The per-lane offsets are recomputed at every staging from
+  // an opaque copy of the lane index instead of being held in registers.
+  constexpr unsigned kPast = 0x7FFFFFF0u;
   auto stage_ops = [&](const MRA_GLOBAL uint16_t* L, const LowItem& nx, uint16_t* dst) {
+    const int sl = opaque_int(lane);
+    const unsigned rb[3] = {(unsigned)nx.rz * (2u * REC), (unsigned)nx.ry * (2u * REC),
+                            (unsigned)nx.rx * (2u * REC)};
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)L, (short)0, (int)kPast, 0x00020000);
 #pragma unroll
     for (int q = 0; q < ORPW; ++q) {
       if (wave + 4 * q < OROWS) {
-        const int rec = o_sel[q] == 0 ? nx.rz : o_sel[q] == 1 ? nx.ry : nx.rx;
-        const int voff = o_off[q] == kPast ? kPast : rec * (2 * REC) + o_off[q];
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc((void*)L, (short)0, kPast, 0x00020000);
+        const int j = 64 * (wave + 4 * q) + sl;
+        const int mstart[8] = {0, MU, 2 * MU, 2 * MU + MV, 2 * MU + 2 * MV, 2 * MU + 3 * MV,
+                               3 * MU + 3 * MV, OPG};
+        // record parts: U(R), U(E), U(P) at 0, LU, 2 LU; V(R), V(E), V(P) at 3 LU + m LV
+        const int part[7] = {0, LU, 3 * LU, 3 * LU + LV, 3 * LU + 2 * LV, LU, 2 * LU};
+        const int recsel[7] = {0, 0, 1, 1, 1, 2, 2};
+        unsigned off = kPast, base = 0u;
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+          const bool u = m < 2 || m >= 5;
+          const int rs_ = u ? RU : RV, gm = u ? GU : GV, w = u ? UP : 32;
+          const int jj = j - mstart[m];
+          const bool in = j >= mstart[m] && j < mstart[m + 1];
+          const int row = jj / rs_, col = jj - (jj / rs_) * rs_;
+          off = (in && col < gm) ? (unsigned)(2 * (part[m] + row * w + 8 * col)) : off;
+          base = in ? rb[recsel[m]] : base;
+        }
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (MRA_LDS void*)(dst + 512 * (wave + 4 * q)),
-                                                 16, voff, 0, 0, 0);
+                                                 16, (int)(off + base), 0, 0, 0);
       }
     }
   };
@@ -2880,12 +2911,12 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
     const MRA_GLOBAL uint16_t* __restrict__ L = as_global(l_tab[tr.fn]);
     const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
 
-    f32x4 acc[QPW][2];
+    f32x4 acc[TMAX][2];
 #pragma unroll
-    for (int e = 0; e < QPW; ++e)
+    for (int e = 0; e < TMAX; ++e)
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) acc[e][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x8 xr[PPW][2][2];   // [pair of this wave][a in pair][b tile]: A operand of step z
+    bf16x8 xr[QDW][4][2];   // [quad of this wave][a in quad][b tile]: A operand of step z
     // this wave's rows of a mirrored source block into xr
     auto load_src = [&](const int slot) {
       const int wl = opaque_int(lane);      // offsets recomputed here, not held
@@ -2894,14 +2925,17 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
       // LDS waits of step x do not wait for them
       const MRA_GLOBAL uint16_t* xb = as_global(mirror) + (size_t)slot * XB;
 #pragma unroll
-      for (int p = 0; p < PPW; ++p)
+      for (int hq = 0; hq < QDW; ++hq)
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt) {
-            const int pair = wave + 4 * p, a = 2 * pair + s2, b = 16 * mt + rr;
-            xr[p][s2][mt] = (pair < NPAIR && b < N && 8 * gg < UP)
-                                ? ld8g(xb + (a * N + b) * UP + 8 * gg) : zero8;
+            // rows b >= 2k repeat row 2k - 1 (finite; they only reach step-y slots whose
+            // operator columns are zero); slots c >= UP must be zero (the step-z operator
+            // fragments there are not masked)
+            const int quad = wave + 4 * hq, a = 4 * quad + j, b = min(16 * mt + rr, N - 1);
+            if (quad < NQUAD)
+              xr[hq][j][mt] = (UP == 32 || 8 * gg < UP) ? ld8g(xb + (a * N + b) * UP + 8 * gg) : zero8;
           }
     };
     LowItem cur{}, nxt{};
@@ -2925,64 +2959,67 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const int row = 16 * t + r;
-        const bool ok = row < N, oku = ok && kin;
-        oz[0][t] = oku ? ld8(Oc + O_RZ + row * SU + 8 * g) : zero8;       // U(R_z)
-        oz[1][t] = oku ? ld8(Oc + O_EZ + row * SU + 8 * g) : zero8;       // U(E_z)
-        oy[0][t] = ok ? ld8(Oc + O_RY + row * SV + 8 * g) : zero8;        // V(R_y)
-        oy[1][t] = ok ? ld8(Oc + O_EY + row * SV + 8 * g) : zero8;        // V(E_y)
-        oy[2][t] = ok ? ld8(Oc + O_PY + row * SV + 8 * g) : zero8;        // V(P_y)
+        oz[0][t] = ld8(Oc + O_RZ + row * SU + 8 * g);       // U(R_z)
+        oz[1][t] = ld8(Oc + O_EZ + row * SU + 8 * g);       // U(E_z)
+        oy[0][t] = ld8(Oc + O_RY + row * SV + 8 * g);       // V(R_y)
+        oy[1][t] = ld8(Oc + O_EY + row * SV + 8 * g);       // V(E_y)
+        oy[2][t] = ld8(Oc + O_PY + row * SV + 8 * g);       // V(P_y)
       }
-      // ---- steps z and y for this wave's pairs of a
+      // ---- steps z and y for this wave's quads of a; the four results of a (mt', i) slot
+      // (the quad's four a) go to LDS as one 8-byte write.  The write offsets depend on the
+      // lane only; they are recomputed here from an opaque copy of the lane index instead of
+      // being kept live across the whole target loop.
+      const int zl = opaque_int(lane);
+      const int zg = zl >> 4, zr = zl & 15;
 #pragma unroll
-      for (int p = 0; p < PPW; ++p) {
-        const int pair = wave + 4 * p;
-        if (pair < NPAIR) {
-          f32x4 u[2][2][2], v[2][2][2];   // [a in pair][b' tile][c' tile]
+      for (int hq = 0; hq < QDW; ++hq) {
+        const int quad = wave + 4 * hq;
+        if (quad < NQUAD) {
 #pragma unroll
-          for (int s2 = 0; s2 < 2; ++s2) {
-            f32x4 y1[2][2], y2[2][2];
+          for (int nt = 0; nt < 2; ++nt) {
+            bf16x8 b1[4], b2[4];   // step-z results of the quad's four a: B operands of step y
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-              for (int nt = 0; nt < 2; ++nt) {
-                const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
-                y1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[p][s2][mt], oz[0][nt], z4, 0, 0, 0);
-                y2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[p][s2][mt], oz[1][nt], z4, 0, 0, 0);
-              }
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-              bf16x8 b1, b2;
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                b1[i] = (__bf16)y1[0][nt][i];
-                b1[4 + i] = (__bf16)y1[1][nt][i];
-                b2[i] = (__bf16)y2[0][nt][i];
-                b2[4 + i] = (__bf16)y2[1][nt][i];
-              }
+            for (int j = 0; j < 4; ++j) {
+              f32x4 y1[2], y2[2];
 #pragma unroll
               for (int mt = 0; mt < 2; ++mt) {
                 const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
-                u[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[0][mt], b1, z4, 0, 0, 0);
-                v[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[1][mt], b1, z4, 0, 0, 0);
-                v[s2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[2][mt], b2, v[s2][mt][nt], 0, 0, 0);
+                y1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[hq][j][mt], oz[0][nt], z4, 0, 0, 0);
+                y2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[hq][j][mt], oz[1][nt], z4, 0, 0, 0);
               }
+              // c_mu is applied here, before the rounding to BF16 (to the 8 values of the step-y
+              // operand rather than to the 16 results)
+              const bf16x4 p0 = __builtin_convertvector(cmu * y1[0], bf16x4);
+              const bf16x4 p1 = __builtin_convertvector(cmu * y1[1], bf16x4);
+              const bf16x4 p2 = __builtin_convertvector(cmu * y2[0], bf16x4);
+              const bf16x4 p3 = __builtin_convertvector(cmu * y2[1], bf16x4);
+              b1[j] = __builtin_shufflevector(p0, p1, 0, 1, 2, 3, 4, 5, 6, 7);
+              b2[j] = __builtin_shufflevector(p2, p3, 0, 1, 2, 3, 4, 5, 6, 7);
             }
-          }
 #pragma unroll
-          for (int mt = 0; mt < 2; ++mt)
+            for (int mt = 0; mt < 2; ++mt) {
+              f32x4 u[4], v[4];   // [a in quad]
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt)
+              for (int j = 0; j < 4; ++j) {
+                const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+                u[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[0][mt], b1[j], z4, 0, 0, 0);
+                v[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[1][mt], b1[j], z4, 0, 0, 0);
+                v[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oy[2][mt], b2[j], v[j], 0, 0, 0);
+              }
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                const int bp = 16 * mt + 4 * g + i, cp = 16 * nt + r;
-                if (bp < N && cp < N) {
-                  const int off = (bp * N + cp) * UP + bp * 8 + 2 * pair;
-                  *reinterpret_cast<uint32_t*>(&T1s[off]) =
-                      bf16_pair(cmu * u[0][mt][nt][i], cmu * u[1][mt][nt][i]);
-                  *reinterpret_cast<uint32_t*>(&T2s[off]) =
-                      bf16_pair(cmu * v[0][mt][nt][i], cmu * v[1][mt][nt][i]);
-                }
+                // lanes outside the 2k x 2k (b', c') range write into the extra row N2
+                const int bp = 16 * mt + 4 * zg + i, cp = 16 * nt + zr;
+                const int q = (bp < N && cp < N) ? bp * N + cp : N2;
+                const int off = q * 32 + 8 * ((quad >> 1) ^ ((q >> 1) & 3)) + 4 * (quad & 1);
+                const f32x4 cu = {u[0][i], u[1][i], u[2][i], u[3][i]};
+                const f32x4 cv = {v[0][i], v[1][i], v[2][i], v[3][i]};
+                *reinterpret_cast<bf16x4*>(&T1s[off]) = __builtin_convertvector(cu, bf16x4);
+                *reinterpret_cast<bf16x4*>(&T2s[off]) = __builtin_convertvector(cv, bf16x4);
               }
+            }
+            __builtin_amdgcn_sched_barrier(0);   // one (quad, c' tile) at a time
+          }
         }
       }
       lds_barrier();   // T1/T2 complete (the operator copies in flight are not waited for)
@@ -2994,17 +3031,18 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const int row = 16 * t + r;
-        const bool oku = row < N && kin;
-        ox[0][t] = oku ? ld8(Oc + O_EX + row * SU + 8 * g) : zero8;       // U(E_x)
-        ox[1][t] = oku ? ld8(Oc + O_PX + row * SU + 8 * g) : zero8;       // U(P_x)
+        ox[0][t] = ld8(Oc + O_EX + row * SU + 8 * g);       // U(E_x)
+        ox[1][t] = ld8(Oc + O_PX + row * SU + 8 * g);       // U(P_x)
       }
+      const int tw0 = low_tile0(K, wave), tw = low_tiles(K, wave);
+      const int xl = opaque_int(lane);
+      const int xg = xl >> 4, xrr = xl & 15;
 #pragma unroll
-      for (int e = 0; e < QPW; ++e) {
-        const int qt = wave + 4 * e;
-        if (qt < NQ) {
-          const int q = 16 * qt + r, off = q * UP + (q / N) * 8 + 8 * g;
-          const bf16x8 t1 = kin ? ld8(T1s + off) : zero8;
-          const bf16x8 t2 = kin ? ld8(T2s + off) : zero8;
+      for (int e = 0; e < TMAX; ++e) {
+        if (e < tw) {
+          const int q = 16 * (tw0 + e) + xrr, off = q * 32 + 8 * (xg ^ ((q >> 1) & 3));
+          const bf16x8 t1 = ld8(T1s + off);   // slots a >= 2k are zero
+          const bf16x8 t2 = ld8(T2s + off);
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt) {
             acc[e][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ox[0][mt], t1, acc[e][mt], 0, 0, 0);
@@ -3022,11 +3060,11 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
     // ---- add the target's block to the FP64 output (each element owned by one lane)
     const int wl = opaque_int(lane);        // offsets recomputed here, not held
     const int gg = wl >> 4, rr = wl & 15;
+    const int tw0 = low_tile0(K, wave), tw = low_tiles(K, wave);
 #pragma unroll
-    for (int e = 0; e < QPW; ++e) {
-      const int qt = wave + 4 * e;
-      if (qt < NQ) {
-        const int q = 16 * qt + rr, bp = q / N, cp = q % N;
+    for (int e = 0; e < TMAX; ++e) {
+      if (e < tw) {
+        const int q = 16 * (tw0 + e) + rr, bp = q / N, cp = q % N;
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
           size_t off[4];
