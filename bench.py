@@ -226,8 +226,10 @@ def setup(ctx, name):
 
 def kernel_source_sha(kernel):
     """sha256[:16] of the source of `kernel` (its definition up to the next section rule in
-    kernels.hip), so that counters stay valid while other kernels of the file change."""
+    kernels.hip) and of the flags kernels.hip is compiled with, so that counters stay valid
+    while other kernels of the file change, and not after the code generation changed."""
     import hashlib
+    from paper_1507_01888_amd import build as B
     src = open(os.path.join(ROOT, "paper_1507_01888_amd", "csrc", "kernels.hip")).read()
     base = kernel.split("<")[0]
     i = src.find(" void %s(" % base)
@@ -235,7 +237,8 @@ def kernel_source_sha(kernel):
         return None
     i = src.rfind("\ntemplate", 0, i)
     j = src.find("\n// ---", i)
-    return hashlib.sha256(src[i:j].encode()).hexdigest()[:16]
+    flags = " ".join(B.COMMON + B.DEVICE_EXTRA.get("kernels.hip", []))
+    return hashlib.sha256((src[i:j] + "\n" + flags).encode()).hexdigest()[:16]
 
 
 def measured_traffic(kernel, workload):
