@@ -2758,12 +2758,14 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 }
 
 // ------------------------------------------------------------- apply (low tier, BF16)
-// Step-x tiles per wave, shifted towards the waves with fewer a-quads for steps z and y (20
-// products per a against 4 per tile; quads per wave: k = 14 (2, 2, 2, 1), k = 12
-// (2, 2, 1, 1), k = 10 (2, 1, 1, 1)), with at most 13 tiles per wave so that the
-// accumulators fit beside the source rows.
+// The BF16 tier kernel runs eight waves per workgroup (two per SIMD, so that one wave's
+// matrix-core and conversion latencies overlap the other's work); wave w owns a-quad w.
+constexpr int kLowWaves = 8;
+// Step-x tiles per wave, shifted towards the waves without an a-quad for steps z and y (80
+// products per quad against 4 per tile), with at most 7 tiles per wave so that the
+// accumulators fit beside the source rows in a half of the register file.
 __host__ __device__ constexpr int low_tiles(int k, int w) {
-  return k == 14 ? (w < 3 ? 12 : 13) : k == 12 ? (w < 2 ? 5 : 13) : (w == 0 ? 4 : 7);
+  return k == 14 ? (w < 7 ? 6 : 7) : k == 12 ? (w < 6 ? 4 : 6) : (w < 5 ? 2 : 5);
 }
 __host__ __device__ constexpr int low_tile0(int k, int w) {
   return w == 0 ? 0 : low_tile0(k, w - 1) + low_tiles(k, w - 1);
@@ -2785,9 +2787,9 @@ __host__ __device__ constexpr int low_tile0(int k, int w) {
 // source rows X[a][b][.] as A and R_z / E_z rows as B; its two row tiles (b < 16, b >= 16)
 // stacked lane-wise are the B operand of step y (contract b) if the contraction slots of
 // step y are permuted accordingly (the V layout of the operator records).  Step x (contract
-// a) needs all a of a column (b', c'): each wave handles whole quads of a (wave w: quads w
-// and w + 4), writes the two results of step y (R_y-part and E_y/P_y-part, scaled by c_mu,
-// BF16) of a quad's four a as one 8-byte write to LDS rows q = (b', c') of 32 a slots, and
+// a) needs all a of a column (b', c'): each wave handles a whole quad of a (wave w: quad w),
+// writes the two results of step y (R_y-part and E_y/P_y-part, c_mu applied, BF16) of the
+// quad's four a as one 8-byte write to LDS rows q = (b', c') of 32 a slots, and
 // after a barrier every wave contracts its share of the q tiles with E_x and P_x,
 // accumulating in registers over all triples of the target.  Granule h (a = 8h .. 8h + 7)
 // of row q sits at position h ^ ((q >> 1) & 3) of the row: eight consecutive rows then
@@ -2803,7 +2805,7 @@ __host__ __device__ constexpr int low_tile0(int k, int w) {
 // loop is unrolled by two over them.  Persistent workgroups take target ranges, longest
 // first, from a counter.
 template <int K>
-__global__ __launch_bounds__(256) void apply_low_kernel(
+__global__ __launch_bounds__(64 * kLowWaves) void apply_low_kernel(
     const uint16_t* __restrict__ mirror, double* const* __restrict__ out_tab,
     const LowItem* __restrict__ items, const TargetRange* __restrict__ targets,
     const uint16_t* const* __restrict__ l_tab, const double* const* __restrict__ c_tab,
@@ -2812,11 +2814,12 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
   constexpr int UP = (N + 7) / 8 * 8;          // padded contraction length (U layout)
   constexpr int XB = N * N * UP;               // BF16 per mirrored children block
   constexpr int LU = N * UP, LV = N * 32, REC = 3 * LU + 3 * LV;
-  constexpr int NQUAD = N / 4, QDW = (NQUAD + 3) / 4;   // a-quads; a wave owns quads w, w + 4
+  constexpr int NW = kLowWaves, NT = 64 * NW;
+  constexpr int NQUAD = N / 4, QDW = (NQUAD + NW - 1) / NW;   // a-quads; wave w owns quad w
+  static_assert(QDW == 1, "one a-quad per wave");
   constexpr int NQ = N2 / 16;                           // 16-row tiles of step x
-  constexpr int TMAX = low_tiles(K, 3) > low_tiles(K, 0) ? low_tiles(K, 3) : low_tiles(K, 0);
-  static_assert(low_tiles(K, 0) + low_tiles(K, 1) + low_tiles(K, 2) + low_tiles(K, 3) == NQ,
-                "every step-x tile has one wave");
+  constexpr int TMAX = low_tiles(K, 0) > low_tiles(K, NW - 1) ? low_tiles(K, 0) : low_tiles(K, NW - 1);
+  static_assert(low_tile0(K, NW) == NQ && TMAX <= 7, "every step-x tile has one wave");
   constexpr int TSZ = (N2 + 1) * 32;                    // T rows [q][a slot], 4 granules each,
                                                         // and a row that takes the padding writes
   static_assert(N > 16 && N <= 32 && N2 % 16 == 0 && N % 4 == 0, "two 16-wide tiles per index, even k");
@@ -2826,7 +2829,7 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
   constexpr int RU = GU % 2 ? GU : GU + 1, RV = GV % 2 ? GV : GV + 1;
   constexpr int SU = 8 * RU, SV = 8 * RV;      // LDS row strides in BF16
   constexpr int MU = N * RU, MV = N * RV;      // granules per staged matrix
-  constexpr int OPG = 4 * MU + 3 * MV, OROWS = (OPG + 63) / 64, ORPW = (OROWS + 3) / 4;
+  constexpr int OPG = 4 * MU + 3 * MV, OROWS = (OPG + 63) / 64, ORPW = (OROWS + NW - 1) / NW;
   // BF16 offsets of the staged matrices
   constexpr int O_RZ = 0, O_EZ = 8 * MU, O_RY = 16 * MU, O_EY = O_RY + 8 * MV, O_PY = O_EY + 8 * MV;
   constexpr int O_EX = O_PY + 8 * MV, O_PX = O_EX + 8 * MU;
@@ -2844,6 +2847,12 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches
   const int g = lane >> 4, r = lane & 15;
+  // this wave's step-x tiles [tw0, tw0 + tw) (an unrolled sum: a recursive constexpr call
+  // with the runtime wave index would be compiled as a real call)
+  int tw0 = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) tw0 += w < wave ? low_tiles(K, w) : 0;
+  const int tw = low_tiles(K, wave);
   const bf16x8 zero8 = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
   auto ld8 = [&](const uint16_t* p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p)); };
   auto ld8g = [&](const MRA_GLOBAL uint16_t* p) {
@@ -2852,31 +2861,35 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
   // slots a >= 2k of the T rows are never written, and the staging buffers' tails are read
   // unmasked (into outputs that are never stored): clear everything once, so that all of it
   // is finite
-  for (int e = tid; e < TSZ / 8; e += 256) {
+  for (int e = tid; e < TSZ / 8; e += NT) {
     reinterpret_cast<u32x4*>(T1s)[e] = u32x4{0u, 0u, 0u, 0u};
     reinterpret_cast<u32x4*>(T2s)[e] = u32x4{0u, 0u, 0u, 0u};
   }
-  for (int e = tid; e < OPB / 8; e += 256) {
+  for (int e = tid; e < OPB / 8; e += NT) {
     reinterpret_cast<u32x4*>(Ob0)[e] = u32x4{0u, 0u, 0u, 0u};
     reinterpret_cast<u32x4*>(Ob1)[e] = u32x4{0u, 0u, 0u, 0u};
   }
-  // Operator staging: lane l of staging row w' = wave + 4 q copies granule j = 64 w' + l of
+  // Operator staging: lane l of staging row w' = wave + NW q copies granule j = 64 w' + l of
   // the seven matrices laid out one after another with RU / RV granules per row; its source
   // is a granule of the record of R_z, R_y or R_x (selected per triple from the item) or,
   // for row padding and past the last matrix, nothing (an offset past the descriptor's
   // range, which reads zeros).  The per-lane offsets are recomputed at every staging from
   // an opaque copy of the lane index instead of being held in registers.
   constexpr unsigned kPast = 0x7FFFFFF0u;
-  auto stage_ops = [&](const MRA_GLOBAL uint16_t* L, const LowItem& nx, uint16_t* dst) {
+  // items and c_mu through the constant address space: uniform reads become scalar loads,
+  // which do not count against the vector-memory counter that the copies are waited on
+  typedef const __attribute__((address_space(4))) LowItem* ItemPtr;
+  const ItemPtr itc = (ItemPtr)items;
+  auto stage_ops = [&](const MRA_GLOBAL uint16_t* L, const ItemPtr nx, uint16_t* dst) {
     const int sl = opaque_int(lane);
-    const unsigned rb[3] = {(unsigned)nx.rz * (2u * REC), (unsigned)nx.ry * (2u * REC),
-                            (unsigned)nx.rx * (2u * REC)};
+    const unsigned rb[3] = {(unsigned)nx->rz * (2u * REC), (unsigned)nx->ry * (2u * REC),
+                            (unsigned)nx->rx * (2u * REC)};
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void*)L, (short)0, (int)kPast, 0x00020000);
 #pragma unroll
     for (int q = 0; q < ORPW; ++q) {
-      if (wave + 4 * q < OROWS) {
-        const int j = 64 * (wave + 4 * q) + sl;
+      if (wave + NW * q < OROWS) {
+        const int j = 64 * (wave + NW * q) + sl;
         const int mstart[8] = {0, MU, 2 * MU, 2 * MU + MV, 2 * MU + 2 * MV, 2 * MU + 3 * MV,
                                3 * MU + 3 * MV, OPG};
         // record parts: U(R), U(E), U(P) at 0, LU, 2 LU; V(R), V(E), V(P) at 3 LU + m LV
@@ -2893,7 +2906,7 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
           off = (in && col < gm) ? (unsigned)(2 * (part[m] + row * w + 8 * col)) : off;
           base = in ? rb[recsel[m]] : base;
         }
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (MRA_LDS void*)(dst + 512 * (wave + 4 * q)),
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (MRA_LDS void*)(dst + 512 * (wave + NW * q)),
                                                  16, (int)(off + base), 0, 0, 0);
       }
     }
@@ -2903,13 +2916,14 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
   for (;;) {
     if (tid == 0) s_next = atomicAdd(next_target, 1);
     __syncthreads();
-    const int ti = s_next;
+    const int ti = __builtin_amdgcn_readfirstlane(s_next);   // uniform: scalar item loads
     __syncthreads();   // every wave has read s_next (and is done with the previous range)
     if (ti >= ntargets) break;
     const TargetRange tr = targets[ti];
     MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
     const MRA_GLOBAL uint16_t* __restrict__ L = as_global(l_tab[tr.fn]);
-    const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
+    typedef const __attribute__((address_space(4))) double* CPtr;
+    const CPtr dc = (CPtr)c_tab[tr.fn];
 
     f32x4 acc[TMAX][2];
 #pragma unroll
@@ -2933,28 +2947,29 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
             // rows b >= 2k repeat row 2k - 1 (finite; they only reach step-y slots whose
             // operator columns are zero); slots c >= UP must be zero (the step-z operator
             // fragments there are not masked)
-            const int quad = wave + 4 * hq, a = 4 * quad + j, b = min(16 * mt + rr, N - 1);
+            const int quad = wave + NW * hq, a = 4 * quad + j, b = min(16 * mt + rr, N - 1);
             if (quad < NQUAD)
               xr[hq][j][mt] = (UP == 32 || 8 * gg < UP) ? ld8g(xb + (a * N + b) * UP + 8 * gg) : zero8;
           }
     };
-    LowItem cur{}, nxt{};
+    // items are indexed, never copied (a copy of a whole item went through private memory)
+    float cmu_next = 0.f;
     if (tr.beg < tr.end) {
-      cur = items[tr.beg];
-      nxt = items[min(tr.beg + 1, tr.end - 1)];
-      stage_ops(L, cur, Ob0);
-      load_src(cur.slot);
+      stage_ops(L, itc + tr.beg, Ob0);
+      load_src(itc[tr.beg].slot);
+      cmu_next = (float)dc[itc[tr.beg].mu];
     }
     auto triple = [&](const int it, auto buf_tag) {
       constexpr int buf = decltype(buf_tag)::value;
       const uint16_t* const Oc = buf == 0 ? Ob0 : Ob1;   // this triple's operators
       uint16_t* const On = buf == 0 ? Ob1 : Ob0;         // the next triple's
-      const LowItem item = cur;
+      const ItemPtr item = itc + it, nxt = itc + min(it + 1, tr.end - 1);
       const bool more = it + 1 < tr.end;
       __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's copies landed
       __syncthreads();                      // all copies landed; step x of it - 1 is done
+      const float cmu = cmu_next;          // loaded one triple ahead
       if (more) stage_ops(L, nxt, On);
-      const float cmu = (float)dc[item.mu];
+      cmu_next = (float)dc[nxt->mu];
       bf16x8 oz[2][2], oy[3][2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
@@ -2973,7 +2988,7 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
       const int zg = zl >> 4, zr = zl & 15;
 #pragma unroll
       for (int hq = 0; hq < QDW; ++hq) {
-        const int quad = wave + 4 * hq;
+        const int quad = wave + NW * hq;
         if (quad < NQUAD) {
 #pragma unroll
           for (int nt = 0; nt < 2; ++nt) {
@@ -3025,7 +3040,7 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
       lds_barrier();   // T1/T2 complete (the operator copies in flight are not waited for)
       // xr is free once steps z and y are done: the next triple's source rows load during
       // step x
-      if (more && nxt.slot != item.slot) load_src(nxt.slot);
+      if (more && nxt->slot != item->slot) load_src(nxt->slot);
       // ---- step x: acc[a'][q] += E_x T1 + P_x T2 over this wave's q tiles
       bf16x8 ox[2][2];
 #pragma unroll
@@ -3034,7 +3049,6 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
         ox[0][t] = ld8(Oc + O_EX + row * SU + 8 * g);       // U(E_x)
         ox[1][t] = ld8(Oc + O_PX + row * SU + 8 * g);       // U(P_x)
       }
-      const int tw0 = low_tile0(K, wave), tw = low_tiles(K, wave);
       const int xl = opaque_int(lane);
       const int xg = xl >> 4, xrr = xl & 15;
 #pragma unroll
@@ -3050,8 +3064,6 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
           }
         }
       }
-      cur = nxt;
-      nxt = items[min(it + 2, tr.end - 1)];
     };
     for (int it = tr.beg; it < tr.end; it += 2) {
       triple(it, BufTag<0>{});
@@ -3060,7 +3072,6 @@ __global__ __launch_bounds__(256) void apply_low_kernel(
     // ---- add the target's block to the FP64 output (each element owned by one lane)
     const int wl = opaque_int(lane);        // offsets recomputed here, not held
     const int gg = wl >> 4, rr = wl & 15;
-    const int tw0 = low_tile0(K, wave), tw = low_tiles(K, wave);
 #pragma unroll
     for (int e = 0; e < TMAX; ++e) {
       if (e < tw) {
@@ -3148,13 +3159,13 @@ void launch_apply_low(int k, const uint16_t* mirror, double* const* out_tab,
   hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, counter, 1, 0);
   const int grid = std::min(ntargets, device_cus());
   if (k == 10) {
-    hipLaunchKernelGGL(apply_low_kernel<10>, dim3(grid), dim3(256), 0, s, mirror, out_tab,
+    hipLaunchKernelGGL(apply_low_kernel<10>, dim3(grid), dim3(64 * kLowWaves), 0, s, mirror, out_tab,
                        items, targets, l_tab, c_tab, ntargets, counter);
   } else if (k == 12) {
-    hipLaunchKernelGGL(apply_low_kernel<12>, dim3(grid), dim3(256), 0, s, mirror, out_tab,
+    hipLaunchKernelGGL(apply_low_kernel<12>, dim3(grid), dim3(64 * kLowWaves), 0, s, mirror, out_tab,
                        items, targets, l_tab, c_tab, ntargets, counter);
   } else if (k == 14) {
-    hipLaunchKernelGGL(apply_low_kernel<14>, dim3(grid), dim3(256), 0, s, mirror, out_tab,
+    hipLaunchKernelGGL(apply_low_kernel<14>, dim3(grid), dim3(64 * kLowWaves), 0, s, mirror, out_tab,
                        items, targets, l_tab, c_tab, ntargets, counter);
   } else {
     fail(MRA_E_UNSUPPORTED, "the low-precision tier is built for k = 10, 12, 14");
