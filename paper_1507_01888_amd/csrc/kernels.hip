@@ -2982,9 +2982,8 @@ __global__ __launch_bounds__(64 * kLowWaves) void apply_low_kernel(
       }
       // ---- steps z and y for this wave's quads of a; the four results of a (mt', i) slot
       // (the quad's four a) go to LDS as one 8-byte write.  The write offsets depend on the
-      // lane only; they are recomputed here from an opaque copy of the lane index instead of
-      // being kept live across the whole target loop.
-      const int zl = opaque_int(lane);
+      // lane and the wave only (the compiler keeps them in registers across the loop).
+      const int zl = lane;
       const int zg = zl >> 4, zr = zl & 15;
 #pragma unroll
       for (int hq = 0; hq < QDW; ++hq) {
@@ -3049,7 +3048,7 @@ __global__ __launch_bounds__(64 * kLowWaves) void apply_low_kernel(
         ox[0][t] = ld8(Oc + O_EX + row * SU + 8 * g);       // U(E_x)
         ox[1][t] = ld8(Oc + O_PX + row * SU + 8 * g);       // U(P_x)
       }
-      const int xl = opaque_int(lane);
+      const int xl = lane;
       const int xg = xl >> 4, xrr = xl & 15;
 #pragma unroll
       for (int e = 0; e < TMAX; ++e) {
