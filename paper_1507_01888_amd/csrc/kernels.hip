@@ -2819,6 +2819,7 @@ __global__ __launch_bounds__(64 * kLowWaves) void apply_low_kernel(
   static_assert(QDW == 1, "one a-quad per wave");
   constexpr int NQ = N2 / 16;                           // 16-row tiles of step x
   constexpr int TMAX = low_tiles(K, 0) > low_tiles(K, NW - 1) ? low_tiles(K, 0) : low_tiles(K, NW - 1);
+  constexpr int TMIN = low_tiles(K, 0) < low_tiles(K, NW - 1) ? low_tiles(K, 0) : low_tiles(K, NW - 1);
   static_assert(low_tile0(K, NW) == NQ && TMAX <= 7, "every step-x tile has one wave");
   constexpr int TSZ = (N2 + 1) * 32;                    // T rows [q][a slot], 4 granules each,
                                                         // and a row that takes the padding writes
@@ -3050,9 +3051,11 @@ __global__ __launch_bounds__(64 * kLowWaves) void apply_low_kernel(
       }
       const int xl = lane;
       const int xg = xl >> 4, xrr = xl & 15;
+      // (the first TMIN tiles, which every wave has, are straight-line code: their reads can
+      // be issued ahead of the products)
 #pragma unroll
       for (int e = 0; e < TMAX; ++e) {
-        if (e < tw) {
+        if (e < TMIN || e < tw) {
           const int q = 16 * (tw0 + e) + xrr, off = q * 32 + 8 * (xg ^ ((q >> 1) & 3));
           const bf16x8 t1 = ld8(T1s + off);   // slots a >= 2k are zero
           const bf16x8 t2 = ld8(T2s + off);
