@@ -2307,8 +2307,9 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
 // resident in LDS per source; k = 14 is padded to 16 by masking the t fragments), whose
 // 16 (a-quad, z-quad) units run in stages 0-5 (3, 3, 3, 3, 2, 2 units), so that every SIMD
 // carries about the same number of products per stage.  Operator blocks of the next triple
-// are loaded into registers during stage 5 and stored to the other half of an LDS double
-// buffer after stage 6.  Persistent workgroups take target ranges, longest first, from a
+// are loaded into registers at the start of stage 6 and stored to LDS at the next triple's
+// first stage, after the wait for the copies (a store right after stage 6 had the compiler
+// wait for the copies in flight).  Persistent workgroups take target ranges, longest first, from a
 // counter.
 template <int K>
 __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
@@ -2329,7 +2330,10 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   static_assert(SROWS == 25 && SRPW == 7, "wave 0 copies 7 slab rows, waves 1-3 six");
   // operator buffer: R_x^T, R_y^T, R_z^T (N^2 each), then t_x^T, t_y^T, t_z^T (K^2 each in
   // slots of TSLOT, whose tails stay zero: a padded fragment read stays inside its slot)
-  constexpr int RL = (N2 + 255) / 256, TSLOT = 256, OPS = 3 * N2 + 3 * TSLOT;
+  // R blocks in slots of 256 RL doubles, so that every thread loads and stores its RL
+  // elements of each without a condition (the tail of a slot is never read; conditional
+  // stores made the compiler wait for all copies in flight before each of them)
+  constexpr int RL = (N2 + 255) / 256, RSLOT = 256 * RL, TSLOT = 256, OPS = 3 * RSLOT + 3 * TSLOT;
   static_assert(K2 <= 256 && (4 * Q2 - 1) * K + 4 * Q2 - 1 < TSLOT, "t slot");
   // s_P, row-major [x][y][z] as stored (granule copies), zero tail up to SSPAD: padded
   // fragment reads (x, y, z < 16) stay inside
@@ -2338,7 +2342,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   static_assert(SSPAD >= 128 * SSROWS, "s_P rows fit");
   __shared__ __attribute__((aligned(16))) double Xl0[SPAD];
   __shared__ __attribute__((aligned(16))) double Xl1[SPAD];
-  __shared__ double Os[2][OPS];
+  __shared__ double Os[OPS];          // the current triple's operator blocks
   __shared__ __attribute__((aligned(16))) double Ss[SSPAD];
   __shared__ int s_next;
   const int tid = threadIdx.x;
@@ -2348,7 +2352,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   // padding that no copy writes is zero once and for all (fragment reads of padded quads
   // multiply it by zero operator entries, so it must be finite)
   for (int e = tid; e < SSPAD; e += 256) Ss[e] = 0.0;
-  for (int e = tid; e < 2 * OPS; e += 256) (&Os[0][0])[e] = 0.0;
+  for (int e = tid; e < OPS; e += 256) Os[e] = 0.0;
 
   // this lane's granule offsets (doubles from the first child's slab) without the z part,
   // for its wave's slab rows; rows past the block read zeros into padding
@@ -2401,7 +2405,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
     for (;;) {
       if (tid == 0) s_next = atomicAdd(next_target, 1);
       __syncthreads();
-      const int ti = s_next;
+      const int ti = __builtin_amdgcn_readfirstlane(s_next);   // uniform: scalar item loads
       __syncthreads();   // every wave has read s_next (and is done with the previous range)
       if (ti >= ntargets) break;
       const TargetRange tr = targets[ti];
@@ -2420,25 +2424,22 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
           const MRA_GLOBAL double* __restrict__ src =
               dR + (size_t)(w == 0 ? nx.rx : w == 1 ? nx.ry : nx.rz) * N2;
 #pragma unroll
-          for (int q = 0; q < RL; ++q)
-            opre[w * RL + q] = (tid + 256 * q < N2) ? src[tid + 256 * q] : 0.0;
+          for (int q = 0; q < RL; ++q) opre[w * RL + q] = src[min(tid + 256 * q, N2 - 1)];
         }
 #pragma unroll
         for (int w = 0; w < 3; ++w) {
           const MRA_GLOBAL double* __restrict__ src =
               dT + (size_t)(w == 0 ? nx.tx : w == 1 ? nx.ty : nx.tz) * K2;
-          opre[3 * RL + w] = tid < K2 ? src[tid] : 0.0;
+          opre[3 * RL + w] = src[min(tid, K2 - 1)];   // the slot's tail is read masked only
         }
       };
       auto store_ops = [&](double* dst) {
 #pragma unroll
         for (int w = 0; w < 3; ++w)
 #pragma unroll
-          for (int q = 0; q < RL; ++q)
-            if (tid + 256 * q < N2) dst[w * N2 + tid + 256 * q] = opre[w * RL + q];
+          for (int q = 0; q < RL; ++q) dst[w * RSLOT + tid + 256 * q] = opre[w * RL + q];
 #pragma unroll
-        for (int w = 0; w < 3; ++w)
-          if (tid < K2) dst[3 * N2 + w * TSLOT + tid] = opre[3 * RL + w];
+        for (int w = 0; w < 3; ++w) dst[3 * RSLOT + w * TSLOT + tid] = opre[3 * RL + w];
       };
 
       // accumulators: waves 0-2 keep their two a-quads' blocks; wave 3 its a-quad in acc0
@@ -2465,8 +2466,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
         nxt = items[min(tr.beg + 1, tr.end - 1)];
         copy_slab(in_g, cur_fc, 0, Xl0);
         if (with_sub) copy_sp(in_g, cur_src);
-        fetch_ops(first);
-        store_ops(Os[0]);
+        fetch_ops(first);   // stored at the triple's first stage
       }
       int it = tr.beg, zq = 0;
       const int nstages = Q * (tr.end - tr.beg);
@@ -2480,6 +2480,12 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
         double* const Xn = buf == 0 ? Xl1 : Xl0;     // the next stage's slab
         __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): this wave's copies landed
         __syncthreads();                             // all copies landed; the other half is free
+        if (zq == 0) {
+          // this triple's operator blocks (loaded into registers during the previous triple's
+          // last stage) into LDS: every wave has finished that triple
+          store_ops(Os);
+          __syncthreads();
+        }
         const bool more = it + 1 < tr.end;
         // the next stage's slab (this triple's zq + 1 or the next triple's first), one copy
         // instruction per x-quad group of step 1, so that the in-order wave never waits for
@@ -2490,13 +2496,15 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
         auto copy_part = [&](const int q) {
           if (do_copy) copy_slab_row(in_g, copy_fc, copy_zq, Xn, q);
         };
-        // s_P of the next triple's source (wave 3 reads s_P in stages 0-5 only)
+        // the next triple's operator blocks into registers (stored after this stage's
+        // products; issued before this stage's copies, so that the wait for them before the
+        // stores is not a wait for the copies), then s_P of its source (wave 3 reads s_P in
+        // stages 0-5 only)
+        if (zq + 1 == Q && more) fetch_ops(nxt);
         if (zq + 1 == Q && more && with_sub && nxt.src != cur_src) copy_sp(in_g, nxt.src);
-        if (zq + 2 == Q && more) fetch_ops(nxt);
-        const int ob = (it - tr.beg) & 1;
-        const double* RXs = Os[ob];
-        const double* RYs = Os[ob] + N2;
-        const double* RZs = Os[ob] + 2 * N2;
+        const double* RXs = Os;
+        const double* RYs = Os + RSLOT;
+        const double* RZs = Os + 2 * RSLOT;
         const double cmu = c_cur;
         const double* X = Xc;
         double rz[Q];
@@ -2618,7 +2626,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
           // ---- the level-n subtraction units of this stage: (sa, sz), sa fixed per call; the
           // units of a stage are independent, so their instructions may interleave
           if (with_sub && zq < 6) {
-            const double* TXs = Os[ob] + 3 * N2;
+            const double* TXs = Os + 3 * RSLOT;
             const double* TYs = TXs + TSLOT;
             const double* TZs = TXs + 2 * TSLOT;
             // fragment (row r, column c) of a transposed t block, zero outside k x k
@@ -2679,9 +2687,6 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
             __builtin_amdgcn_sched_barrier(0);
           }
         }
-        // the next triple's operators into the other half: its last reader was triple
-        // it - 1, finished before this triple's first barrier
-        if (zq + 1 == Q && more) store_ops(Os[ob ^ 1]);
         // advance
         if (++zq == Q) {
           zq = 0;
