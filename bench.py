@@ -52,6 +52,9 @@ def parse():
                         "tiered workload, after one warm-up step (at most --steps)")
     p.add_argument("--no-tune", action="store_true",
                    help="skip the autotuner of the batched workloads' schedule")
+    p.add_argument("--schedule", default=None, metavar="S,D",
+                   help="run the batched workloads under sub-batches S and split divisor D "
+                        "instead of tuning")
     p.add_argument("--tune-cache", default=None,
                    help="JSON file the autotuner reads and extends (default: none, tune now)")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -151,7 +154,10 @@ def cpu_baseline(name, budget_s):
         fl, s, done = _oracle_sample(fo, op, w["tau_rel"] * w["thresh"], limit_s)
         return fl, s, "function 0, source levels %s of the non-standard apply" % done
 
-    threads = sum(i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas")
+    # several BLAS libraries may be loaded (numpy's, torch's); the oracle's products run on
+    # one of them, so the thread count is the largest pool's, not the sum
+    threads = max([i.get("num_threads", 0) for i in threadpool_info()
+                   if i.get("user_api") == "blas"] + [1])
     fl, s, what = sample(budget_s)
     with threadpool_limits(limits=1, user_api="blas"):
         fl1, s1, what1 = sample(budget_s / 2)
@@ -241,9 +247,10 @@ def kernel_source_sha(kernel):
     return hashlib.sha256((src[i:j] + "\n" + flags).encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, schedule=None):
     """HBM bytes per launch of `kernel` on `workload` from the committed rocprofv3 counter
-    summaries, or None when none was taken on the current source of the kernel."""
+    summaries, or None when none was taken on the current source of the kernel (and, for a
+    batched workload, under the same schedule: it sets how much one launch processes)."""
     import glob
     sha = kernel_source_sha(kernel)
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_pmc.md"))):
@@ -251,7 +258,8 @@ def measured_traffic(kernel, workload):
             if line.startswith("pmc: "):
                 rec = json.loads(line[5:])
                 if (rec.get("kernel") == kernel and rec.get("kernel_src_sha256_16") == sha
-                        and rec.get("workload", workload) == workload):
+                        and rec.get("workload", workload) == workload
+                        and rec.get("schedule") == schedule):
                     return 1024.0 * (rec["fetch_kib"] * rec["fetch_factor"]
                                      + rec["write_kib"] * rec["write_factor"])
     return None
@@ -274,7 +282,10 @@ def main():
     funcs, ops, tau, k, tier, cfg = setup(ctx, args.workload)
     name = args.workload
     tuning = None
-    if len(funcs) > 1 and not args.no_tune:
+    if args.schedule:
+        sb, div = (int(v) for v in args.schedule.split(","))
+        ctx.set_schedule(sb, div)
+    elif len(funcs) > 1 and not args.no_tune:
         # the schedule of the batched apply (sub-batches, split length) picked by the
         # library's autotuner on these inputs, before warm-up
         t0 = time.perf_counter()
@@ -357,7 +368,8 @@ def main():
     achieved = alg_per_launch / (dk["ms_per_launch"] * 1e-3) / 1e12
     roofline = {"kernel": dk["kernel"], "bound": bound if dom == "fp64" else "mfma",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": measured_traffic(dk["kernel"], name),
+                "traffic": measured_traffic(dk["kernel"], name,
+                                            ctx.schedule() if len(funcs) > 1 else None),
                 "algorithmic_flop_per_launch": alg_per_launch,
                 "ms_per_launch": dk["ms_per_launch"],
                 "executed_frac": dk["executed_frac"]}
@@ -388,6 +400,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "autotune": tuning,
+        "schedule": ctx.schedule() if len(funcs) > 1 else None,
     }
 
     if tier > 0:

@@ -286,7 +286,9 @@ mra_status mra_get_schedule(const mra_ctx* ctx, mra_schedule* s);
 /* Autotuner of the batched apply (the batching extension's "autotuned schedules"): times one
  * mra_apply_batch of (ops, fs, params) under each candidate schedule (sub_batches 1, 2, 4 x
  * split_div 256, 512, 1024; one untimed apply first, which also builds the operator block
- * caches), keeps the fastest on ctx and returns it in *best.  With cache_path != NULL the
+ * caches), keeps on ctx the first candidate in that order whose time is within 1% of the
+ * fastest (smaller differences are timing noise; the pick stays stable from run to run) and
+ * returns it in *best.  With cache_path != NULL the
  * JSON file is read first: if it holds the key "<gfx arch>/k<k>/<fp64|tiered>", that schedule
  * is set without timing; otherwise the result is added to the file.  times_ms (optional,
  * capacity 9) receives the measured milliseconds in candidate order (-1 when read from the

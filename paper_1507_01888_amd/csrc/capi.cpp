@@ -1188,19 +1188,27 @@ mra_status mra_autotune_batch(mra_ctx* ctx, int n, const mra_op* const* ophs,
       return ms;
     };
     run();   // block caches, pinned arenas and planner buffers settle; not timed
-    double best_ms = 1e300;
-    int bsb = old_sb, bdiv = old_div;
+    double t[9];
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) {
         c->sched_sub_batches = cand_sb[a];
         c->sched_split_div = cand_div[b];
-        const double ms = run();
-        if (times_ms) times_ms[3 * a + b] = ms;
-        if (ms < best_ms) {
-          best_ms = ms;
-          bsb = cand_sb[a];
-          bdiv = cand_div[b];
-        }
+        t[3 * a + b] = run();
+        if (times_ms) times_ms[3 * a + b] = t[3 * a + b];
+      }
+    // the first candidate (fewest sub-batches, then shortest split) within 1% of the
+    // fastest: differences below that are timing noise, and a stable pick keeps the
+    // schedule, and the profiles taken under it, the same from run to run
+    double fastest = 1e300;
+    for (double v : t) fastest = std::min(fastest, v);
+    int bsb = old_sb, bdiv = old_div;
+    double best_ms = 1e300;
+    for (int q = 0; q < 9; ++q)
+      if (t[q] <= 1.01 * fastest) {
+        bsb = cand_sb[q / 3];
+        bdiv = cand_div[q % 3];
+        best_ms = t[q];
+        break;
       }
     c->sched_sub_batches = bsb;
     c->sched_split_div = bdiv;

@@ -1482,7 +1482,8 @@ __global__ __launch_bounds__(256, 4) void apply_std_mfma_kernel(
   constexpr int K2 = K * K, K3 = K * K * K, Q = K / 4;
   static_assert(K % 4 == 0 && Q == 2, "k = 8: two quads per index");
   const int lane = threadIdx.x & 63;
-  const int ti = blockIdx.x * 4 + (threadIdx.x >> 6);
+  // uniform per wave: the range and the items are read with scalar loads
+  const int ti = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (ti >= ntargets) return;                 // a whole wave leaves; no barriers below
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
   const int swap = (16 * lb + 4 * lk + li) * 4;
