@@ -791,6 +791,19 @@ __device__ __forceinline__ int opaque_int(int v) {
   return v;
 }
 
+// Workgroup barrier for LDS written and read by this wave's own instructions, with the
+// wait given by the caller: waitcnt (an s_waitcnt immediate) should include lgkmcnt(0), so
+// that this wave's LDS reads and writes are done.  Unlike __syncthreads() it does not
+// imply a wait for every LDS copy in flight (a workgroup fence must cover those); the
+// empty asm statements keep the compiler from moving memory accesses across it.
+template <int WAITCNT>
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(WAITCNT);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 template <int B>
 struct BufTag {
   static constexpr int value = B;
@@ -1482,8 +1495,13 @@ __global__ __launch_bounds__(256, 4) void apply_std_mfma_kernel(
   constexpr int K2 = K * K, K3 = K * K * K, Q = K / 4;
   static_assert(K % 4 == 0 && Q == 2, "k = 8: two quads per index");
   const int lane = threadIdx.x & 63;
+  // Workgroups go to the eight dies (XCDs) in turn; renumber them so that each die takes a
+  // contiguous eighth of the targets, which come in Morton order: its L2 then serves one
+  // spatial octant of source blocks and their neighbours instead of the whole level.
+  const int nwg = gridDim.x, wg = blockIdx.x, per = nwg >> 3, rem = nwg & 7, xcd = wg & 7;
+  const int lwg = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + (wg >> 3);
   // uniform per wave: the range and the items are read with scalar loads
-  const int ti = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int ti = __builtin_amdgcn_readfirstlane(lwg * 4 + (threadIdx.x >> 6));
   if (ti >= ntargets) return;                 // a whole wave leaves; no barriers below
   const int li = lane & 3, lb = (lane >> 2) & 3, lk = lane >> 4;
   const int swap = (16 * lb + 4 * lk + li) * 4;
@@ -2297,9 +2315,10 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
 // ----------------------------------------- apply (NS, MFMA, source streamed in z-slabs)
 // FP64 matrix-core kernel for k = 14 (2k = 28 = 4Q, Q = 7), whose (2k)^3 children block
 // (172 KB) does not fit in LDS.  A triple is processed in Q stages, one per z-quad: stage
-// zq needs only the slab B_P[.][.][4zq .. 4zq+3] (25 KB), which is double buffered in LDS
-// and copied from L2 one stage ahead (the next triple's first slab during the last stage)
-// by buffer loads that write LDS directly.  Each of waves 0-2 owns two a-quads and runs
+// zq needs only the slab B_P[.][.][4zq .. 4zq+3] (25 KB), which is triple buffered in LDS
+// and copied two stages ahead (across triples: the next triple's first slabs during the
+// last two stages) by buffer loads that write LDS directly, so that a copy has two stages'
+// products to land in.  Each of waves 0-2 owns two a-quads and runs
 // the three contractions of both itself: step 1 (contract x; block index = z inside the
 // z-quad) and step 2 (contract y) chain in registers, the step-2 result is permuted
 // in-wave into the step-3 operand (contract the z-quad's four z), and step 3 accumulates
@@ -2327,8 +2346,10 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   static_assert(quarter_distinct(SLX, SLY), "slab strides");
   // slab copy: granule g = 2 (x N + y) + h holds (x, y, 4 zq + 2h .. 4 zq + 2h + 1), so a
   // granule never straddles two children (k even); rows of 64 granules, row r by wave r % 4
-  constexpr int SG = SLAB / 2, SROWS = (SG + 63) / 64, SPAD = 128 * SROWS, SRPW = (SROWS + 3) / 4;
-  static_assert(SROWS == 25 && SRPW == 7, "wave 0 copies 7 slab rows, waves 1-3 six");
+  // Every wave copies SRPW rows per stage (rows past SROWS read zeros into padding), so the
+  // number of copies a wave has in flight at a stage's start is always SRPW.
+  constexpr int SG = SLAB / 2, SROWS = (SG + 63) / 64, SRPW = (SROWS + 3) / 4, SPAD = 128 * 4 * SRPW;
+  static_assert(SROWS == 25 && SRPW == 7, "seven slab rows per wave");
   // operator buffer: R_x^T, R_y^T, R_z^T (N^2 each), then t_x^T, t_y^T, t_z^T (K^2 each in
   // slots of TSLOT, whose tails stay zero: a padded fragment read stays inside its slot)
   // R blocks in slots of 256 RL doubles, so that every thread loads and stores its RL
@@ -2343,6 +2364,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   static_assert(SSPAD >= 128 * SSROWS, "s_P rows fit");
   __shared__ __attribute__((aligned(16))) double Xl0[SPAD];
   __shared__ __attribute__((aligned(16))) double Xl1[SPAD];
+  __shared__ __attribute__((aligned(16))) double Xl2[SPAD];
   __shared__ double Os[OPS];          // the current triple's operator blocks
   __shared__ __attribute__((aligned(16))) double Ss[SSPAD];
   __shared__ int s_next;
@@ -2368,25 +2390,26 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
       soff[q] = 8 * K3;                                        // past the descriptor's end
     }
   }
-  // row q of this wave's part of the slab copy (one instruction)
+  // row q of this wave's part of the slab copy (one instruction; rows past the slab read
+  // zeros, the offset being past the descriptor's end)
   auto copy_slab_row = [&](const double* in_g, const int fc, const int zq, double* dst, const int q) {
     const int z0 = 4 * zq + 2 * (lane & 1);
     const int zoff = z0 >= K ? K3 + z0 - K : z0;
-    if (wave + 4 * q < SROWS)
-      lds_copy16(in_g + (size_t)fc * K3, 8 * K3 * 8, (MRA_LDS void*)(dst + 128 * (wave + 4 * q)),
-                 8 * (soff[q] + zoff));
+    lds_copy16(in_g + (size_t)fc * K3, 8 * K3 * 8, (MRA_LDS void*)(dst + 128 * (wave + 4 * q)),
+               8 * (soff[q] + zoff));
   };
   auto copy_slab = [&](const double* in_g, const int fc, const int zq, double* dst) {
 #pragma unroll
     for (int q = 0; q < SRPW; ++q) copy_slab_row(in_g, fc, zq, dst, q);
   };
-  // s_P (K3 doubles) into Ss, granule by granule
+  // s_P (K3 doubles) into Ss, granule by granule, SSRPW rows per wave (rows past the block
+  // read zeros into the zero tail: their offsets are past the descriptor's end)
+  static_assert(SSPAD >= 128 * 4 * SSRPW, "every wave's s_P rows fit");
   auto copy_sp = [&](const double* in_g, const int src) {
 #pragma unroll
     for (int q = 0; q < SSRPW; ++q)
-      if (wave + 4 * q < SSROWS)
-        lds_copy16(in_g + (size_t)src * K3, K3 * 8, (MRA_LDS void*)(Ss + 128 * (wave + 4 * q)),
-                   16 * (64 * (wave + 4 * q) + lane));
+      lds_copy16(in_g + (size_t)src * K3, K3 * 8, (MRA_LDS void*)(Ss + 128 * (wave + 4 * q)),
+                 16 * (64 * (wave + 4 * q) + lane));
   };
   auto lane_swap = [&](double v) {
     const int2 w = __builtin_bit_cast(int2, v);
@@ -2400,21 +2423,46 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   // The two roles (waves 0-2: two a-quads; wave 3: one a-quad and the subtraction) run
   // separate instances of the loop, so that each keeps only its own accumulators live;
   // both execute the same sequence of barriers.
+  // the range table, items and c_mu through the constant address space: scalar loads,
+  // which do not count against the vector memory counter the slab copies are waited on with
+  typedef const __attribute__((address_space(4))) NSItem* SItemPtr;
+  typedef const __attribute__((address_space(4))) TargetRange* STargetPtr;
+  typedef const __attribute__((address_space(4))) double* CPtr;
+  const SItemPtr its = (SItemPtr)items;
+  const STargetPtr tgs = (STargetPtr)targets;
+  auto item_at = [&](const int i) {   // field by field: no struct copy across address spaces
+    const SItemPtr p = its + i;
+    NSItem r;
+    r.src = p->src, r.src_fc = p->src_fc, r.mu = p->mu;
+    r.rx = p->rx, r.ry = p->ry, r.rz = p->rz, r.tx = p->tx, r.ty = p->ty, r.tz = p->tz;
+    return r;
+  };
   auto run = [&](auto role_tag) {
     constexpr bool sub_wave = decltype(role_tag)::value;
     const int at0 = sub_wave ? Q - 1 : 2 * wave, at1 = 2 * wave + 1;
+    // per-lane offsets of the fragment reads, opaque so that every read is one offset from
+    // its LDS array plus a constant: the compiler tags only short address chains with the
+    // array they read, and an untagged read waits for every LDS copy in flight
+    const int o_r = opaque_int(lk * N + li);                         // R^T fragment (row, col)
+    const int o_ra = opaque_int(lk * N + li + 4 * at0), o_rb = opaque_int(lk * N + li + 4 * at1);
+    const int o_x = opaque_int(lk * SLX + li * SLY + lb);            // slab fragment
     for (;;) {
       if (tid == 0) s_next = atomicAdd(next_target, 1);
       __syncthreads();
       const int ti = __builtin_amdgcn_readfirstlane(s_next);   // uniform: scalar item loads
       __syncthreads();   // every wave has read s_next (and is done with the previous range)
       if (ti >= ntargets) break;
-      const TargetRange tr = targets[ti];
+      TargetRange tr;
+      {
+        const STargetPtr p = tgs + ti;
+        tr.fn = p->fn, tr.node = p->node, tr.fc = p->fc, tr.beg = p->beg, tr.end = p->end;
+        tr.partial = p->partial, tr.sub = p->sub;
+      }
       const double* const in_g = in_tab[tr.fn];
       MRA_GLOBAL double* __restrict__ out = as_global(out_tab[tr.fn]);
       const MRA_GLOBAL double* __restrict__ dR = as_global(r_tab[tr.fn]);
       const MRA_GLOBAL double* __restrict__ dT = as_global(t_tab[tr.fn]);
-      const MRA_GLOBAL double* __restrict__ dc = as_global(c_tab[tr.fn]);
+      const CPtr dc = (CPtr)c_tab[tr.fn];
       const bool with_sub = tr.sub >= 0;
 
       // operator blocks of a triple: element tid + 256 q of each block
@@ -2460,14 +2508,15 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
       double c_cur = 0.0;
       NSItem nxt{};
       if (tr.beg < tr.end) {
-        const NSItem first = items[tr.beg];
+        const NSItem first = item_at(tr.beg);
         cur_fc = first.src_fc;
         cur_src = first.src;
         c_cur = dc[first.mu];
-        nxt = items[min(tr.beg + 1, tr.end - 1)];
+        nxt = item_at(min(tr.beg + 1, tr.end - 1));
         copy_slab(in_g, cur_fc, 0, Xl0);
         if (with_sub) copy_sp(in_g, cur_src);
         fetch_ops(first);   // stored at the triple's first stage
+        copy_slab(in_g, cur_fc, 1, Xl1);   // last: the first stage waits for all but these
       }
       int it = tr.beg, zq = 0;
       const int nstages = Q * (tr.end - tr.beg);
@@ -2477,40 +2526,41 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 
       auto stage = [&](auto buf_tag) {
         constexpr int buf = decltype(buf_tag)::value;
-        double* const Xc = buf == 0 ? Xl0 : Xl1;     // this stage's slab
-        double* const Xn = buf == 0 ? Xl1 : Xl0;     // the next stage's slab
-        __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): this wave's copies landed
-        __syncthreads();                             // all copies landed; the other half is free
+        double* const Xc = buf == 0 ? Xl0 : buf == 1 ? Xl1 : Xl2;   // this stage's slab
+        double* const Xn = buf == 0 ? Xl2 : buf == 1 ? Xl0 : Xl1;   // two stages ahead
+        // vmcnt(SRPW) lgkmcnt(0): everything this wave issued before its last SRPW copies
+        // (those of the next stage) has landed, i.e. this stage's slab and the operator
+        // blocks and s_P loaded during the previous stage, and its LDS reads of the previous
+        // stage are done; after the barrier the same holds for every wave, so the slab is
+        // complete and the previous stage's buffer is free
+        static_assert(SRPW < 16, "vmcnt field");
+        lds_barrier<0x0070 | SRPW>();
         if (zq == 0) {
           // this triple's operator blocks (loaded into registers during the previous triple's
           // last stage) into LDS: every wave has finished that triple
           store_ops(Os);
-          __syncthreads();
+          lds_barrier<0xC07F>();   // lgkmcnt(0): the stores are done
         }
         const bool more = it + 1 < tr.end;
-        // the next stage's slab (this triple's zq + 1 or the next triple's first), one copy
-        // instruction per x-quad group of step 1, so that the in-order wave never waits for
-        // the memory pipeline to take a burst of them
-        const bool do_copy = zq + 1 < Q || more;
-        const int copy_fc = zq + 1 < Q ? cur_fc : nxt.src_fc;
-        const int copy_zq = zq + 1 < Q ? zq + 1 : 0;
-        auto copy_part = [&](const int q) {
-          if (do_copy) copy_slab_row(in_g, copy_fc, copy_zq, Xn, q);
-        };
+        // the slab two stages ahead (this triple's zq + 2 or the next triple's zq + 2 - Q;
+        // past the range's last stage a repeat of this triple's first slab into the free
+        // buffer, which keeps the number of copies in flight fixed), one copy instruction per
+        // x-quad group of step 1, so that the in-order wave never waits for the memory
+        // pipeline to take a burst of them
+        const bool same = zq + 2 < Q;
+        const int copy_fc = same || !more ? cur_fc : nxt.src_fc;
+        const int copy_zq = same ? zq + 2 : more ? zq + 2 - Q : 0;
+        auto copy_part = [&](const int q) { copy_slab_row(in_g, copy_fc, copy_zq, Xn, q); };
         // the next triple's operator blocks into registers (stored after this stage's
         // products; issued before this stage's copies, so that the wait for them before the
         // stores is not a wait for the copies), then s_P of its source (wave 3 reads s_P in
         // stages 0-5 only)
         if (zq + 1 == Q && more) fetch_ops(nxt);
         if (zq + 1 == Q && more && with_sub && nxt.src != cur_src) copy_sp(in_g, nxt.src);
-        const double* RXs = Os;
-        const double* RYs = Os + RSLOT;
-        const double* RZs = Os + 2 * RSLOT;
         const double cmu = c_cur;
-        const double* X = Xc;
         double rz[Q];
 #pragma unroll
-        for (int ct = 0; ct < Q; ++ct) rz[ct] = cmu * RZs[(4 * zq + lk) * N + 4 * ct + li];
+        for (int ct = 0; ct < Q; ++ct) rz[ct] = cmu * Os[2 * RSLOT + o_r + 4 * zq * N + 4 * ct];
         if constexpr (!sub_wave) {
           // ---- two a-quads: step 1, operands of x-quad xs + 1 read during xs
           double d1a[Q], d1b[Q];
@@ -2519,14 +2569,14 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
           double xa[2][Q], ra[2], rb[2];
           auto load1 = [&](const int xs, const int b) {
 #pragma unroll
-            for (int yt = 0; yt < Q; ++yt) xa[b][yt] = X[(4 * xs + lk) * SLX + (4 * yt + li) * SLY + lb];
-            ra[b] = RXs[(4 * xs + lk) * N + 4 * at0 + li];
-            rb[b] = RXs[(4 * xs + lk) * N + 4 * at1 + li];
+            for (int yt = 0; yt < Q; ++yt) xa[b][yt] = Xc[o_x + 4 * xs * SLX + 4 * yt * SLY];
+            ra[b] = Os[o_ra + 4 * xs * N];
+            rb[b] = Os[o_rb + 4 * xs * N];
           };
           double ry[2][Q];
           auto load2 = [&](const int ys, const int b) {
 #pragma unroll
-            for (int bt = 0; bt < Q; ++bt) ry[b][bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+            for (int bt = 0; bt < Q; ++bt) ry[b][bt] = Os[RSLOT + o_r + 4 * ys * N + 4 * bt];
           };
           load1(0, 0);
 #pragma unroll
@@ -2582,8 +2632,8 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
           double xa[2][Q], ra[2];
           auto load1 = [&](const int xs, const int b) {
 #pragma unroll
-            for (int yt = 0; yt < Q; ++yt) xa[b][yt] = X[(4 * xs + lk) * SLX + (4 * yt + li) * SLY + lb];
-            ra[b] = RXs[(4 * xs + lk) * N + 4 * at0 + li];
+            for (int yt = 0; yt < Q; ++yt) xa[b][yt] = Xc[o_x + 4 * xs * SLX + 4 * yt * SLY];
+            ra[b] = Os[o_ra + 4 * xs * N];
           };
           load1(0, 0);
 #pragma unroll
@@ -2602,7 +2652,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
           double ry[2][Q];
           auto load2 = [&](const int ys, const int b) {
 #pragma unroll
-            for (int bt = 0; bt < Q; ++bt) ry[b][bt] = RYs[(4 * ys + lk) * N + 4 * bt + li];
+            for (int bt = 0; bt < Q; ++bt) ry[b][bt] = Os[RSLOT + o_r + 4 * ys * N + 4 * bt];
           };
           load2(0, 0);
 #pragma unroll
@@ -2695,13 +2745,19 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
           cur_fc = nxt.src_fc;
           cur_src = nxt.src;
           c_cur = dc[nxt.mu];
-          nxt = items[min(it + 1, tr.end - 1)];
+          nxt = item_at(min(it + 1, tr.end - 1));
         }
       };
-      for (int s = 0; s < nstages; s += 2) {
+      // (nested: the compiler must see that the third stage always follows the second, or
+      // it cannot tell that the first stage's copies have landed when the third starts)
+      for (int s = 0; s < nstages; s += 3) {
         stage(BufTag<0>{});
-        if (s + 1 < nstages) stage(BufTag<1>{});
+        if (s + 1 < nstages) {
+          stage(BufTag<1>{});
+          if (s + 2 < nstages) stage(BufTag<2>{});
+        }
       }
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // the repeated copies of the last two stages
       // ---- write the target's blocks (each element owned by exactly one lane).  The lane
       // indices pass through an empty asm statement, so that the compiler recomputes the
       // output offsets here instead of keeping ~100 of them live across the whole loop.
