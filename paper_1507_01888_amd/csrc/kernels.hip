@@ -2446,6 +2446,8 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
     const int o_r = opaque_int(lk * N + li);                         // R^T fragment (row, col)
     const int o_ra = opaque_int(lk * N + li + 4 * at0), o_rb = opaque_int(lk * N + li + 4 * at1);
     const int o_x = opaque_int(lk * SLX + li * SLY + lb);            // slab fragment
+    const int o_t = sub_wave ? opaque_int(lk * K + li) : 0;          // t^T fragment
+    const int o_s = sub_wave ? opaque_int(lk * K2 + li * K + lb) : 0;  // s_P fragment
     for (;;) {
       if (tid == 0) s_next = atomicAdd(next_target, 1);
       __syncthreads();
@@ -2677,64 +2679,99 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
           // ---- the level-n subtraction units of this stage: (sa, sz), sa fixed per call; the
           // units of a stage are independent, so their instructions may interleave
           if (with_sub && zq < 6) {
-            const double* TXs = Os + 3 * RSLOT;
-            const double* TYs = TXs + TSLOT;
-            const double* TZs = TXs + 2 * TSLOT;
-            // fragment (row r, column c) of a transposed t block, zero outside k x k
-            auto tfrag = [&](const double* T, const int r, const int c) {
-              const double v = T[r * K + c];
-              return (r < K && c < K) ? v : 0.0;
+            // The units of a stage share their source fragments (stages 0-3: sa = 0, 1, 2 at
+            // sz = zq, one s_P z-quad) or their t_x fragments (stages 4-5: sa = 3 at two sz),
+            // so they run together: shared fragments read once, 8-12 independent product
+            // chains per step, and all in-wave permutations issued before the last products.
+            // t fragment (row quad rq, column quad cq) of a transposed t block at slot
+            // offset base, zero outside k x k (row 4 rq + lk, column 4 cq + li)
+            auto tf = [&](const int base, const int rq, const int cq) {
+              const double v = Os[base + o_t + 4 * rq * K + 4 * cq];
+              return ((rq < Q2 - 1 || lk < K - 4 * (Q2 - 1)) && (cq < Q2 - 1 || li < K - 4 * (Q2 - 1))) ? v : 0.0;
             };
             if (zq == 0) {
 #pragma unroll
               for (int ys = 0; ys < Q2; ++ys)
 #pragma unroll
-                for (int bt = 0; bt < Q2; ++bt)
-                  tyc[ys % TYC][bt % TYC] = tfrag(TYs, 4 * ys + lk, 4 * bt + li);
+                for (int bt = 0; bt < Q2; ++bt) tyc[ys % TYC][bt % TYC] = tf(3 * RSLOT + TSLOT, ys, bt);
             }
-            auto unit = [&](auto sa_tag, const int sz) {
-              constexpr int sa = decltype(sa_tag)::value;
-              double tx[Q2];
+            auto units = [&](auto case_tag) {
+              constexpr bool by_sa = decltype(case_tag)::value;
+              constexpr int NU = by_sa ? 3 : 2;
+              const int sz0 = by_sa ? zq : 2 * (zq - 4);   // unit u has sz = sz0 (+ u if !by_sa)
+              double e1[NU][Q2];
 #pragma unroll
-              for (int xs = 0; xs < Q2; ++xs) tx[xs] = tfrag(TXs, 4 * xs + lk, 4 * sa + li);
-              double e1[Q2];
+              for (int u = 0; u < NU; ++u)
 #pragma unroll
-              for (int yt = 0; yt < Q2; ++yt) e1[yt] = 0.0;
+                for (int yt = 0; yt < Q2; ++yt) e1[u][yt] = 0.0;
 #pragma unroll
-              for (int xs = 0; xs < Q2; ++xs)
+              for (int xs = 0; xs < Q2; ++xs) {
+                if constexpr (by_sa) {
+                  double sf[Q2], tq[NU];
 #pragma unroll
-                for (int yt = 0; yt < Q2; ++yt)
-                  e1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(
-                      Ss[((4 * xs + lk) * K + 4 * yt + li) * K + 4 * sz + lb], tx[xs], e1[yt], 0, 0, 0);
-              double e2[Q2];
+                  for (int yt = 0; yt < Q2; ++yt) sf[yt] = Ss[o_s + 4 * xs * K2 + 4 * yt * K + 4 * sz0];
 #pragma unroll
-              for (int bt = 0; bt < Q2; ++bt) e2[bt] = 0.0;
+                  for (int u = 0; u < NU; ++u) tq[u] = tf(3 * RSLOT, xs, u);
+#pragma unroll
+                  for (int u = 0; u < NU; ++u)
+#pragma unroll
+                    for (int yt = 0; yt < Q2; ++yt)
+                      e1[u][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(sf[yt], tq[u], e1[u][yt], 0, 0, 0);
+                } else {
+                  double sf[NU][Q2];
+#pragma unroll
+                  for (int u = 0; u < NU; ++u)
+#pragma unroll
+                    for (int yt = 0; yt < Q2; ++yt)
+                      sf[u][yt] = Ss[o_s + 4 * xs * K2 + 4 * yt * K + 4 * (sz0 + u)];
+                  const double tq = tf(3 * RSLOT, xs, Q2 - 1);
+#pragma unroll
+                  for (int u = 0; u < NU; ++u)
+#pragma unroll
+                    for (int yt = 0; yt < Q2; ++yt)
+                      e1[u][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(sf[u][yt], tq, e1[u][yt], 0, 0, 0);
+                }
+              }
+              double e2[NU][Q2];
+#pragma unroll
+              for (int u = 0; u < NU; ++u)
+#pragma unroll
+                for (int bt = 0; bt < Q2; ++bt) e2[u][bt] = 0.0;
 #pragma unroll
               for (int ys = 0; ys < Q2; ++ys)
 #pragma unroll
+                for (int u = 0; u < NU; ++u)
+#pragma unroll
+                  for (int bt = 0; bt < Q2; ++bt)
+                    e2[u][bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(e1[u][ys], tyc[ys % TYC][bt % TYC],
+                                                                   e2[u][bt], 0, 0, 0);
+              constexpr int NZ = by_sa ? 1 : NU;
+              double tz[NZ][Q2];
+#pragma unroll
+              for (int v = 0; v < NZ; ++v)
+#pragma unroll
+                for (int ct = 0; ct < Q2; ++ct) tz[v][ct] = -cmu * tf(3 * RSLOT + 2 * TSLOT, sz0 + v, ct);
+              double z[NU][Q2];
+#pragma unroll
+              for (int u = 0; u < NU; ++u)
+#pragma unroll
+                for (int bt = 0; bt < Q2; ++bt) z[u][bt] = lane_swap(e2[u][bt]);
+#pragma unroll
+              for (int u = 0; u < NU; ++u)
+#pragma unroll
                 for (int bt = 0; bt < Q2; ++bt)
-                  e2[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(e1[ys], tyc[ys % TYC][bt % TYC], e2[bt], 0, 0, 0);
-              double tz[Q2];
 #pragma unroll
-              for (int ct = 0; ct < Q2; ++ct) tz[ct] = -cmu * tfrag(TZs, 4 * sz + lk, 4 * ct + li);
-#pragma unroll
-              for (int bt = 0; bt < Q2; ++bt) {
-                const double zt = lane_swap(e2[bt]);
-#pragma unroll
-                for (int ct = 0; ct < Q2; ++ct)
-                  acc1[((sa * Q2 + bt) * Q2 + ct) % A1] = __builtin_amdgcn_mfma_f64_4x4x4f64(
-                      zt, tz[ct], acc1[((sa * Q2 + bt) * Q2 + ct) % A1], 0, 0, 0);
-              }
+                  for (int ct = 0; ct < Q2; ++ct) {
+                    const int sa = by_sa ? u : Q2 - 1;
+                    acc1[((sa * Q2 + bt) * Q2 + ct) % A1] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                        z[u][bt], tz[by_sa ? 0 : u][ct], acc1[((sa * Q2 + bt) * Q2 + ct) % A1], 0, 0, 0);
+                  }
             };
             __builtin_amdgcn_sched_barrier(0);
-            if (zq < 4) {
-              unit(BufTag<0>{}, zq);
-              unit(BufTag<1>{}, zq);
-              unit(BufTag<2>{}, zq);
-            } else {
-              unit(BufTag<3>{}, 2 * (zq - 4));
-              unit(BufTag<3>{}, 2 * (zq - 4) + 1);
-            }
+            if (zq < 4)
+              units(BoolTag<true>{});
+            else
+              units(BoolTag<false>{});
             __builtin_amdgcn_sched_barrier(0);
           }
         }
