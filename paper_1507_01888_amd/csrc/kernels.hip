@@ -2594,8 +2594,9 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
             }
             __builtin_amdgcn_sched_barrier(0);
           }
-          // ---- step 2 (contract y), R_y fragments of y-quad ys + 1 read during ys
-          double zra[Q], zrb[Q];
+          // ---- step 2 (contract y), R_y fragments of y-quad ys + 1 read during ys; the
+          // permutation of b-quad 0 for step 3 starts two products after its last one
+          double zra[Q], zrb[Q], za_n, zb_n;
 #pragma unroll
           for (int bt = 0; bt < Q; ++bt) zra[bt] = zrb[bt] = 0.0;
 #pragma unroll
@@ -2606,12 +2607,15 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
             for (int bt = 0; bt < Q; ++bt) {
               zra[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1a[ys], ry[b][bt], zra[bt], 0, 0, 0);
               zrb[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1b[ys], ry[b][bt], zrb[bt], 0, 0, 0);
+              if (ys == Q - 1 && bt == 2) {
+                za_n = lane_swap(zra[0]);
+                zb_n = lane_swap(zrb[0]);
+              }
             }
             __builtin_amdgcn_sched_barrier(0);
           }
           // ---- step 3 (contract the z-quad) into the target's block; the permuted operands
           // of b-quad bt + 1 are fetched during the products of bt
-          double za_n = lane_swap(zra[0]), zb_n = lane_swap(zrb[0]);
 #pragma unroll
           for (int bt = 0; bt < Q; ++bt) {
             const double za = za_n, zb = zb_n;
@@ -2657,16 +2661,18 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
             for (int bt = 0; bt < Q; ++bt) ry[b][bt] = Os[RSLOT + o_r + 4 * ys * N + 4 * bt];
           };
           load2(0, 0);
+          double za_n;
 #pragma unroll
           for (int ys = 0; ys < Q; ++ys) {
             const int b = ys & 1;
             if (ys + 1 < Q) load2(ys + 1, b ^ 1);
 #pragma unroll
-            for (int bt = 0; bt < Q; ++bt)
+            for (int bt = 0; bt < Q; ++bt) {
               zr[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1[ys], ry[b][bt], zr[bt], 0, 0, 0);
+              if (ys == Q - 1 && bt == 3) za_n = lane_swap(zr[0]);
+            }
             __builtin_amdgcn_sched_barrier(0);
           }
-          double za_n = lane_swap(zr[0]);
 #pragma unroll
           for (int bt = 0; bt < Q; ++bt) {
             const double za = za_n;
