@@ -549,7 +549,8 @@ static void apply_standard(Ctx* ctx, Op& op, Func& f, int radius, Func& out) {
   hip_check(hipEventRecord(ctx->ev[2], ctx->stream), "event");
   launch_apply_std(k, A.at<const double*>(o_in), A.at<double*>(o_out), A.at<NSItem>(o_items),
                    A.at<TargetRange>(o_tgt), (int)tgt.size(), A.at<const double*>(o_t),
-                   A.at<const double*>(o_c), 1.0, ctx->stream);
+                   A.at<const double*>(o_c), 1.0, ctx->stream,
+                   (int)std::min<int64_t>((int64_t)op.dT_blocks * k * k, INT32_MAX));
   hip_check(hipEventRecord(ctx->ev[3], ctx->stream), "event");
   ctx->sync();
   float ms_a = 0;

@@ -1485,15 +1485,24 @@ __global__ __launch_bounds__(round64(K * K)) void apply_std_kernel(
 // step 3 contracts z after an in-wave permutation (ds_bpermute) into the target's block,
 // which stays in registers (8 doubles per lane) over all triples of the target.  The next
 // triple's source and operator fragments are loaded while the current one computes, and
-// several waves per SIMD hide what remains of the load latency.
-template <int K>
+// several waves per SIMD hide what remains of the load latency.  With TL the launch's t
+// blocks (one function's table of t_lds doubles, every target of that function) are first
+// staged in LDS, and the operator fragments are read from there: a triple then issues only
+// its eight source loads to the vector memory pipeline.
+template <int K, bool TL>
 __global__ __launch_bounds__(256, 4) void apply_std_mfma_kernel(
     const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
     const NSItem* __restrict__ items, const TargetRange* __restrict__ targets, const int ntargets,
     const double* const* __restrict__ t_tab, const double* const* __restrict__ c_tab,
-    double scale) {
+    double scale, const int t_lds) {
   constexpr int K2 = K * K, K3 = K * K * K, Q = K / 4;
   static_assert(K % 4 == 0 && Q == 2, "k = 8: two quads per index");
+  extern __shared__ double Ts[];      // TL: the t table (t_lds doubles)
+  if constexpr (TL) {
+    const MRA_GLOBAL double* __restrict__ t0 = as_global(t_tab[0]);
+    for (int e = threadIdx.x; e < t_lds; e += 256) Ts[e] = t0[e];
+    __syncthreads();                  // before any wave can leave
+  }
   const int lane = threadIdx.x & 63;
   // Workgroups go to the eight dies (XCDs) in turn; renumber them so that each die takes a
   // contiguous eighth of the targets, which come in Morton order: its L2 then serves one
@@ -1532,17 +1541,29 @@ __global__ __launch_bounds__(256, 4) void apply_std_mfma_kernel(
 #pragma unroll
         for (int zq = 0; zq < Q; ++zq)
           f.s[xs][yt][zq] = sp[((4 * xs + lk) * K + 4 * yt + li) * K + 4 * zq + lb];
-    const MRA_GLOBAL double* TX = dT + (size_t)it.tx * K2;
-    const MRA_GLOBAL double* TY = dT + (size_t)it.ty * K2;
-    const MRA_GLOBAL double* TZ = dT + (size_t)it.tz * K2;
+    if constexpr (TL) {
+      const int ox = it.tx * K2 + lk * K + li, oy = it.ty * K2 + lk * K + li, oz = it.tz * K2 + lk * K + li;
 #pragma unroll
-    for (int u = 0; u < Q; ++u)
+      for (int u = 0; u < Q; ++u)
 #pragma unroll
-      for (int v = 0; v < Q; ++v) {
-        f.tx[u][v] = TX[(4 * u + lk) * K + 4 * v + li];
-        f.ty[u][v] = TY[(4 * u + lk) * K + 4 * v + li];
-        f.tz[u][v] = TZ[(4 * u + lk) * K + 4 * v + li];
-      }
+        for (int v = 0; v < Q; ++v) {
+          f.tx[u][v] = Ts[ox + 4 * u * K + 4 * v];
+          f.ty[u][v] = Ts[oy + 4 * u * K + 4 * v];
+          f.tz[u][v] = Ts[oz + 4 * u * K + 4 * v];
+        }
+    } else {
+      const MRA_GLOBAL double* TX = dT + (size_t)it.tx * K2;
+      const MRA_GLOBAL double* TY = dT + (size_t)it.ty * K2;
+      const MRA_GLOBAL double* TZ = dT + (size_t)it.tz * K2;
+#pragma unroll
+      for (int u = 0; u < Q; ++u)
+#pragma unroll
+        for (int v = 0; v < Q; ++v) {
+          f.tx[u][v] = TX[(4 * u + lk) * K + 4 * v + li];
+          f.ty[u][v] = TY[(4 * u + lk) * K + 4 * v + li];
+          f.tz[u][v] = TZ[(4 * u + lk) * K + 4 * v + li];
+        }
+    }
     f.c = dc[it.mu] * scale;
   };
   double acc[Q][Q][Q];
@@ -3350,12 +3371,19 @@ void launch_reduce_partials(int k, const double* partials, double* const* out_ta
 void launch_apply_std(int k, const double* const* in_tab, double* const* out_tab,
                       const NSItem* items, const TargetRange* targets, int ntargets,
                       const double* const* t_tab, const double* const* c_tab, double scale,
-                      hipStream_t s) {
+                      hipStream_t s, int t_lds) {
   if (ntargets <= 0) return;
   if (k == 8) {
-    // matrix-core kernel: one wave per target, four per workgroup
-    hipLaunchKernelGGL(apply_std_mfma_kernel<8>, dim3((ntargets + 3) / 4), dim3(256), 0, s,
-                       in_tab, out_tab, items, targets, ntargets, t_tab, c_tab, scale);
+    // matrix-core kernel: one wave per target, four per workgroup; the t table of a
+    // single-function launch in LDS when it fits in 32 KB
+    if (t_lds > 0 && t_lds <= 4096) {
+      hipLaunchKernelGGL((apply_std_mfma_kernel<8, true>), dim3((ntargets + 3) / 4), dim3(256),
+                         (size_t)t_lds * sizeof(double), s, in_tab, out_tab, items, targets,
+                         ntargets, t_tab, c_tab, scale, t_lds);
+    } else {
+      hipLaunchKernelGGL((apply_std_mfma_kernel<8, false>), dim3((ntargets + 3) / 4), dim3(256), 0,
+                         s, in_tab, out_tab, items, targets, ntargets, t_tab, c_tab, scale, 0);
+    }
     hip_check(hipGetLastError(), "apply_std_mfma_kernel");
     return;
   }

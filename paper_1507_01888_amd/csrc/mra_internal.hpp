@@ -330,10 +330,12 @@ void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
 void launch_reduce_partials(int k, const double* partials, double* const* out_tab,
                             double* subbuf, const SplitTarget* splits, int nsplits,
                             hipStream_t s);
+// t_lds > 0: every target belongs to function 0, whose t table holds t_lds doubles (the
+// k = 8 kernel then stages it in LDS when it fits); 0 for batches of several functions
 void launch_apply_std(int k, const double* const* in_tab, double* const* out_tab,
                       const NSItem* items, const TargetRange* targets, int ntargets,
                       const double* const* t_tab, const double* const* c_tab, double scale,
-                      hipStream_t s);
+                      hipStream_t s, int t_lds = 0);
 // children of each listed box += sign * unfilter(box's slab [+ its subbuf block]);
 // sign = -1 turns a children block into the box's wavelet part D_P (Sec. 2.2).
 void launch_sum_down(int k, double* const* coeff_tab, const NodeRef* refs, int count,
