@@ -2339,21 +2339,20 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
 // zq needs only the slab B_P[.][.][4zq .. 4zq+3] (25 KB), which is triple buffered in LDS
 // and copied two stages ahead (across triples: the next triple's first slabs during the
 // last two stages) by buffer loads that write LDS directly, so that a copy has two stages'
-// products to land in.  Each of waves 0-2 owns two a-quads and runs
-// the three contractions of both itself: step 1 (contract x; block index = z inside the
-// z-quad) and step 2 (contract y) chain in registers, the step-2 result is permuted
-// in-wave into the step-3 operand (contract the z-quad's four z), and step 3 accumulates
-// into the target's block in registers; the two a-quads share every LDS operand read.
-// Wave 3 owns the seventh a-quad and the level-n subtraction -c (t x t x t) s_P (s_P
-// resident in LDS per source; k = 14 is padded to 16 by masking the t fragments), whose
-// 16 (a-quad, z-quad) units run in stages 0-5 (3, 3, 3, 3, 2, 2 units), so that every SIMD
-// carries about the same number of products per stage.  Operator blocks of the next triple
-// are loaded into registers at the start of stage 6 and stored to LDS at the next triple's
-// first stage, after the wait for the copies (a store right after stage 6 had the compiler
-// wait for the copies in flight).  Persistent workgroups take target ranges, longest first, from a
-// counter.
+// products to land in.  Eight waves per workgroup, two per SIMD, so that one wave's LDS,
+// permutation and barrier latencies overlap the other's products: waves 0-6 own one a-quad
+// each and run the three contractions of it (step 1 contracts x, block index = z inside
+// the z-quad; step 2 contracts y, chained in registers; the step-2 result is permuted
+// in-wave into the step-3 operand, which contracts the z-quad's four z into the target's
+// block held in registers).  Wave 7 owns the level-n subtraction -c (t x t x t) s_P (s_P
+// resident in LDS per source; k = 14 is padded to 16 by masking the t fragments): its 16
+// (a-quad, z-quad) units run in stages 0-5 (3, 3, 3, 3, 2, 2 units), those of a stage
+// together (they share their s_P or t_x fragments).  Each wave keeps only its own
+// accumulators, in half the register file.  Operator blocks of the next triple are loaded
+// into registers at its predecessor's last stage and stored to LDS at its first stage.
+// Persistent workgroups take target ranges, longest first, from a counter.
 template <int K>
-__global__ __launch_bounds__(256) void apply_ns_stream_kernel(
+__global__ __launch_bounds__(512) void apply_ns_stream_kernel(
     const double* const* __restrict__ in_tab, double* const* __restrict__ out_tab,
     const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
     const double* const* __restrict__ r_tab, const double* const* __restrict__ t_tab,
@@ -2369,18 +2368,18 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   // granule never straddles two children (k even); rows of 64 granules, row r by wave r % 4
   // Every wave copies SRPW rows per stage (rows past SROWS read zeros into padding), so the
   // number of copies a wave has in flight at a stage's start is always SRPW.
-  constexpr int SG = SLAB / 2, SROWS = (SG + 63) / 64, SRPW = (SROWS + 3) / 4, SPAD = 128 * 4 * SRPW;
-  static_assert(SROWS == 25 && SRPW == 7, "seven slab rows per wave");
+  constexpr int SG = SLAB / 2, SROWS = (SG + 63) / 64, SRPW = (SROWS + 7) / 8, SPAD = 128 * 8 * SRPW;
+  static_assert(SROWS == 25 && SRPW == 4, "four slab rows per wave");
   // operator buffer: R_x^T, R_y^T, R_z^T (N^2 each), then t_x^T, t_y^T, t_z^T (K^2 each in
   // slots of TSLOT, whose tails stay zero: a padded fragment read stays inside its slot)
-  // R blocks in slots of 256 RL doubles, so that every thread loads and stores its RL
+  // R blocks in slots of 512 RL doubles, so that every thread loads and stores its RL
   // elements of each without a condition (the tail of a slot is never read; conditional
   // stores made the compiler wait for all copies in flight before each of them)
-  constexpr int RL = (N2 + 255) / 256, RSLOT = 256 * RL, TSLOT = 256, OPS = 3 * RSLOT + 3 * TSLOT;
+  constexpr int RL = (N2 + 511) / 512, RSLOT = 512 * RL, TSLOT = 256, OPS = 3 * RSLOT + 3 * TSLOT;
   static_assert(K2 <= 256 && (4 * Q2 - 1) * K + 4 * Q2 - 1 < TSLOT, "t slot");
   // s_P, row-major [x][y][z] as stored (granule copies), zero tail up to SSPAD: padded
   // fragment reads (x, y, z < 16) stay inside
-  constexpr int SSG = K3 / 2, SSROWS = (SSG + 63) / 64, SSRPW = (SSROWS + 3) / 4;
+  constexpr int SSG = K3 / 2, SSROWS = (SSG + 63) / 64, SSRPW = (SSROWS + 7) / 8;
   constexpr int SSPAD = ((15 * K2 + 15 * K + 16 + 127) / 128) * 128;
   static_assert(SSPAD >= 128 * SSROWS, "s_P rows fit");
   __shared__ __attribute__((aligned(16))) double Xl0[SPAD];
@@ -2395,15 +2394,15 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   const int swap = (16 * lb + 4 * lk + li) * 4;
   // padding that no copy writes is zero once and for all (fragment reads of padded quads
   // multiply it by zero operator entries, so it must be finite)
-  for (int e = tid; e < SSPAD; e += 256) Ss[e] = 0.0;
-  for (int e = tid; e < OPS; e += 256) Os[e] = 0.0;
+  for (int e = tid; e < SSPAD; e += 512) Ss[e] = 0.0;
+  for (int e = tid; e < OPS; e += 512) Os[e] = 0.0;
 
   // this lane's granule offsets (doubles from the first child's slab) without the z part,
   // for its wave's slab rows; rows past the block read zeros into padding
   int soff[SRPW];
 #pragma unroll
   for (int q = 0; q < SRPW; ++q) {
-    const int g = 64 * (wave + 4 * q) + lane;
+    const int g = 64 * (wave + 8 * q) + lane;
     if (g < SG) {
       const int x = g / (2 * N), y = (g / 2) % N;
       soff[q] = (((x / K) << 2) | ((y / K) << 1)) * K3 + ((x % K) * K + y % K) * K;
@@ -2416,7 +2415,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   auto copy_slab_row = [&](const double* in_g, const int fc, const int zq, double* dst, const int q) {
     const int z0 = 4 * zq + 2 * (lane & 1);
     const int zoff = z0 >= K ? K3 + z0 - K : z0;
-    lds_copy16(in_g + (size_t)fc * K3, 8 * K3 * 8, (MRA_LDS void*)(dst + 128 * (wave + 4 * q)),
+    lds_copy16(in_g + (size_t)fc * K3, 8 * K3 * 8, (MRA_LDS void*)(dst + 128 * (wave + 8 * q)),
                8 * (soff[q] + zoff));
   };
   auto copy_slab = [&](const double* in_g, const int fc, const int zq, double* dst) {
@@ -2425,12 +2424,12 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   };
   // s_P (K3 doubles) into Ss, granule by granule, SSRPW rows per wave (rows past the block
   // read zeros into the zero tail: their offsets are past the descriptor's end)
-  static_assert(SSPAD >= 128 * 4 * SSRPW, "every wave's s_P rows fit");
+  static_assert(SSPAD >= 128 * 8 * SSRPW, "every wave's s_P rows fit");
   auto copy_sp = [&](const double* in_g, const int src) {
 #pragma unroll
     for (int q = 0; q < SSRPW; ++q)
-      lds_copy16(in_g + (size_t)src * K3, K3 * 8, (MRA_LDS void*)(Ss + 128 * (wave + 4 * q)),
-                 16 * (64 * (wave + 4 * q) + lane));
+      lds_copy16(in_g + (size_t)src * K3, K3 * 8, (MRA_LDS void*)(Ss + 128 * (wave + 8 * q)),
+                 16 * (64 * (wave + 8 * q) + lane));
   };
   auto lane_swap = [&](double v) {
     const int2 w = __builtin_bit_cast(int2, v);
@@ -2441,9 +2440,9 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   };
   __syncthreads();
 
-  // The two roles (waves 0-2: two a-quads; wave 3: one a-quad and the subtraction) run
-  // separate instances of the loop, so that each keeps only its own accumulators live;
-  // both execute the same sequence of barriers.
+  // The two roles (waves 0-6: an a-quad each; wave 7: the subtraction) run separate
+  // instances of the loop, so that each keeps only its own accumulators live; both execute
+  // the same sequence of barriers.
   // the range table, items and c_mu through the constant address space: scalar loads,
   // which do not count against the vector memory counter the slab copies are waited on with
   typedef const __attribute__((address_space(4))) NSItem* SItemPtr;
@@ -2460,12 +2459,12 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
   };
   auto run = [&](auto role_tag) {
     constexpr bool sub_wave = decltype(role_tag)::value;
-    const int at0 = sub_wave ? Q - 1 : 2 * wave, at1 = 2 * wave + 1;
+    const int at0 = sub_wave ? 0 : wave;
     // per-lane offsets of the fragment reads, opaque so that every read is one offset from
     // its LDS array plus a constant: the compiler tags only short address chains with the
     // array they read, and an untagged read waits for every LDS copy in flight
     const int o_r = opaque_int(lk * N + li);                         // R^T fragment (row, col)
-    const int o_ra = opaque_int(lk * N + li + 4 * at0), o_rb = opaque_int(lk * N + li + 4 * at1);
+    const int o_ra = opaque_int(lk * N + li + 4 * at0);
     const int o_x = opaque_int(lk * SLX + li * SLY + lb);            // slab fragment
     const int o_t = sub_wave ? opaque_int(lk * K + li) : 0;          // t^T fragment
     const int o_s = sub_wave ? opaque_int(lk * K2 + li * K + lb) : 0;  // s_P fragment
@@ -2488,7 +2487,8 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
       const CPtr dc = (CPtr)c_tab[tr.fn];
       const bool with_sub = tr.sub >= 0;
 
-      // operator blocks of a triple: element tid + 256 q of each block
+      // operator blocks of a triple: element tid + 512 q of each block (t blocks: tid,
+      // clamped to the slot's last element, which those threads write with the same value)
       double opre[3 * RL + 3];
       auto fetch_ops = [&](const NSItem& nx) {
 #pragma unroll
@@ -2496,7 +2496,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
           const MRA_GLOBAL double* __restrict__ src =
               dR + (size_t)(w == 0 ? nx.rx : w == 1 ? nx.ry : nx.rz) * N2;
 #pragma unroll
-          for (int q = 0; q < RL; ++q) opre[w * RL + q] = src[min(tid + 256 * q, N2 - 1)];
+          for (int q = 0; q < RL; ++q) opre[w * RL + q] = src[min(tid + 512 * q, N2 - 1)];
         }
 #pragma unroll
         for (int w = 0; w < 3; ++w) {
@@ -2509,14 +2509,14 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 #pragma unroll
         for (int w = 0; w < 3; ++w)
 #pragma unroll
-          for (int q = 0; q < RL; ++q) dst[w * RSLOT + tid + 256 * q] = opre[w * RL + q];
+          for (int q = 0; q < RL; ++q) dst[w * RSLOT + tid + 512 * q] = opre[w * RL + q];
 #pragma unroll
-        for (int w = 0; w < 3; ++w) dst[3 * RSLOT + w * TSLOT + tid] = opre[3 * RL + w];
+        for (int w = 0; w < 3; ++w) dst[3 * RSLOT + w * TSLOT + min(tid, TSLOT - 1)] = opre[3 * RL + w];
       };
 
-      // accumulators: waves 0-2 keep their two a-quads' blocks; wave 3 its a-quad in acc0
-      // and the subtraction block (4 a-quads x 4 b-quads x 4 c-quads) in acc1
-      constexpr int A1 = sub_wave ? Q2 * Q2 * Q2 : Q * Q;
+      // accumulators: waves 0-6 keep their a-quad's block in acc0, wave 7 the subtraction
+      // block (4 a-quads x 4 b-quads x 4 c-quads) in acc1
+      constexpr int A1 = sub_wave ? Q2 * Q2 * Q2 : 1;
       double acc0[Q][Q], acc1[A1];
 #pragma unroll
       for (int b = 0; b < Q; ++b)
@@ -2543,7 +2543,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
       }
       int it = tr.beg, zq = 0;
       const int nstages = Q * (tr.end - tr.beg);
-      // wave 3: the t_y fragments of the current triple (the same for all its 16 units)
+      // wave 7: the t_y fragments of the current triple (the same for all its 16 units)
       constexpr int TYC = sub_wave ? Q2 : 1;
       double tyc[TYC][TYC];
 
@@ -2576,83 +2576,16 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
         auto copy_part = [&](const int q) { copy_slab_row(in_g, copy_fc, copy_zq, Xn, q); };
         // the next triple's operator blocks into registers (stored after this stage's
         // products; issued before this stage's copies, so that the wait for them before the
-        // stores is not a wait for the copies), then s_P of its source (wave 3 reads s_P in
+        // stores is not a wait for the copies), then s_P of its source (wave 7 reads s_P in
         // stages 0-5 only)
         if (zq + 1 == Q && more) fetch_ops(nxt);
         if (zq + 1 == Q && more && with_sub && nxt.src != cur_src) copy_sp(in_g, nxt.src);
         const double cmu = c_cur;
-        double rz[Q];
-#pragma unroll
-        for (int ct = 0; ct < Q; ++ct) rz[ct] = cmu * Os[2 * RSLOT + o_r + 4 * zq * N + 4 * ct];
         if constexpr (!sub_wave) {
-          // ---- two a-quads: step 1, operands of x-quad xs + 1 read during xs
-          double d1a[Q], d1b[Q];
+          // ---- waves 0-6: a-quad `wave`
+          double rz[Q];
 #pragma unroll
-          for (int yt = 0; yt < Q; ++yt) d1a[yt] = d1b[yt] = 0.0;
-          double xa[2][Q], ra[2], rb[2];
-          auto load1 = [&](const int xs, const int b) {
-#pragma unroll
-            for (int yt = 0; yt < Q; ++yt) xa[b][yt] = Xc[o_x + 4 * xs * SLX + 4 * yt * SLY];
-            ra[b] = Os[o_ra + 4 * xs * N];
-            rb[b] = Os[o_rb + 4 * xs * N];
-          };
-          double ry[2][Q];
-          auto load2 = [&](const int ys, const int b) {
-#pragma unroll
-            for (int bt = 0; bt < Q; ++bt) ry[b][bt] = Os[RSLOT + o_r + 4 * ys * N + 4 * bt];
-          };
-          load1(0, 0);
-#pragma unroll
-          for (int xs = 0; xs < Q; ++xs) {
-            const int b = xs & 1;
-            copy_part(xs);
-            if (xs + 1 < Q) load1(xs + 1, b ^ 1);
-            else load2(0, 0);     // step 2's first operands during the last x-quad group
-#pragma unroll
-            for (int yt = 0; yt < Q; ++yt) {
-              d1a[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[b][yt], ra[b], d1a[yt], 0, 0, 0);
-              d1b[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[b][yt], rb[b], d1b[yt], 0, 0, 0);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-          }
-          // ---- step 2 (contract y), R_y fragments of y-quad ys + 1 read during ys; the
-          // permutation of b-quad 0 for step 3 starts two products after its last one
-          double zra[Q], zrb[Q], za_n, zb_n;
-#pragma unroll
-          for (int bt = 0; bt < Q; ++bt) zra[bt] = zrb[bt] = 0.0;
-#pragma unroll
-          for (int ys = 0; ys < Q; ++ys) {
-            const int b = ys & 1;
-            if (ys + 1 < Q) load2(ys + 1, b ^ 1);
-#pragma unroll
-            for (int bt = 0; bt < Q; ++bt) {
-              zra[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1a[ys], ry[b][bt], zra[bt], 0, 0, 0);
-              zrb[bt] = __builtin_amdgcn_mfma_f64_4x4x4f64(d1b[ys], ry[b][bt], zrb[bt], 0, 0, 0);
-              if (ys == Q - 1 && bt == 2) {
-                za_n = lane_swap(zra[0]);
-                zb_n = lane_swap(zrb[0]);
-              }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-          }
-          // ---- step 3 (contract the z-quad) into the target's block; the permuted operands
-          // of b-quad bt + 1 are fetched during the products of bt
-#pragma unroll
-          for (int bt = 0; bt < Q; ++bt) {
-            const double za = za_n, zb = zb_n;
-            if (bt + 1 < Q) {
-              za_n = lane_swap(zra[bt + 1]);
-              zb_n = lane_swap(zrb[bt + 1]);
-            }
-#pragma unroll
-            for (int ct = 0; ct < Q; ++ct) {
-              acc0[bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(za, rz[ct], acc0[bt][ct], 0, 0, 0);
-              acc1[bt * Q + ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(zb, rz[ct], acc1[bt * Q + ct], 0, 0, 0);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-          }
-        } else {
-          // ---- wave 3: a-quad 6
+          for (int ct = 0; ct < Q; ++ct) rz[ct] = cmu * Os[2 * RSLOT + o_r + 4 * zq * N + 4 * ct];
           double d1[Q];
 #pragma unroll
           for (int yt = 0; yt < Q; ++yt) d1[yt] = 0.0;
@@ -2666,7 +2599,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 #pragma unroll
           for (int xs = 0; xs < Q; ++xs) {
             const int b = xs & 1;
-            copy_part(xs);
+            if (xs < SRPW) copy_part(xs);
             if (xs + 1 < Q) load1(xs + 1, b ^ 1);
 #pragma unroll
             for (int yt = 0; yt < Q; ++yt)
@@ -2703,6 +2636,10 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
               acc0[bt][ct] = __builtin_amdgcn_mfma_f64_4x4x4f64(za, rz[ct], acc0[bt][ct], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
           }
+        } else {
+          // ---- wave 7: its rows of the slab copy, then the level-n subtraction units
+#pragma unroll
+          for (int q = 0; q < SRPW; ++q) copy_part(q);
           // ---- the level-n subtraction units of this stage: (sa, sz), sa fixed per call; the
           // units of a stage are independent, so their instructions may interleave
           if (with_sub && zq < 6) {
@@ -2716,12 +2653,6 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
               const double v = Os[base + o_t + 4 * rq * K + 4 * cq];
               return ((rq < Q2 - 1 || lk < K - 4 * (Q2 - 1)) && (cq < Q2 - 1 || li < K - 4 * (Q2 - 1))) ? v : 0.0;
             };
-            if (zq == 0) {
-#pragma unroll
-              for (int ys = 0; ys < Q2; ++ys)
-#pragma unroll
-                for (int bt = 0; bt < Q2; ++bt) tyc[ys % TYC][bt % TYC] = tf(3 * RSLOT + TSLOT, ys, bt);
-            }
             auto units = [&](auto case_tag) {
               constexpr bool by_sa = decltype(case_tag)::value;
               constexpr int NU = by_sa ? 3 : 2;
@@ -2759,6 +2690,12 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
                       e1[u][yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(sf[u][yt], tq, e1[u][yt], 0, 0, 0);
                 }
               }
+              // the t_y fragments (the same for every unit of the triple), read here rather
+              // than held across stages: the subtraction block fills half the register file
+#pragma unroll
+              for (int ys = 0; ys < Q2; ++ys)
+#pragma unroll
+                for (int bt = 0; bt < Q2; ++bt) tyc[ys % TYC][bt % TYC] = tf(3 * RSLOT + TSLOT, ys, bt);
               double e2[NU][Q2];
 #pragma unroll
               for (int u = 0; u < NU; ++u)
@@ -2827,10 +2764,10 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
       // output offsets here instead of keeping ~100 of them live across the whole loop.
       const int wl = opaque_int(lane);
       const int li = wl & 3, lb = (wl >> 2) & 3, lk = wl >> 4;
-      constexpr int nq = sub_wave ? 1 : 2;
+      constexpr int nq = sub_wave ? 0 : 1;
 #pragma unroll
       for (int s2 = 0; s2 < nq; ++s2) {
-        const int a = 4 * (s2 == 0 ? at0 : at1) + lb;
+        const int a = 4 * at0 + lb;
 #pragma unroll
         for (int bt = 0; bt < Q; ++bt) {
           const int b = 4 * bt + lk;
@@ -2838,7 +2775,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
 #pragma unroll
             for (int ct = 0; ct < Q; ++ct)
               partials[(size_t)tr.partial * (N3 + K3) + (a * N + b) * N + 4 * ct + li] =
-                  s2 == 0 ? acc0[bt][ct] : acc1[(bt * Q + ct) % A1];
+                  acc0[bt][ct];
           } else {
             // a row of Q elements: all loads first, then the sums and stores
             size_t off[Q];
@@ -2852,7 +2789,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
             }
 #pragma unroll
             for (int ct = 0; ct < Q; ++ct)
-              out[off[ct]] = o[ct] + (s2 == 0 ? acc0[bt][ct] : acc1[(bt * Q + ct) % A1]);
+              out[off[ct]] = o[ct] + acc0[bt][ct];
           }
         }
       }
@@ -2877,7 +2814,7 @@ __global__ __launch_bounds__(256) void apply_ns_stream_kernel(
       }
     }
   };
-  if (wave == 3)
+  if (wave == 7)
     run(BoolTag<true>{});
   else
     run(BoolTag<false>{});
@@ -3349,7 +3286,7 @@ void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
     // one persistent workgroup per CU (the kernel's LDS allows one), ranges from a counter
     hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, counter, 1, 0);
     hipLaunchKernelGGL(apply_ns_stream_kernel<14>, dim3(std::min(ntargets, device_cus())),
-                       dim3(256), 0, s, in_tab, out_tab, items, targets, r_tab, t_tab, c_tab,
+                       dim3(512), 0, s, in_tab, out_tab, items, targets, r_tab, t_tab, c_tab,
                        partials, subbuf, ntargets, counter);
   } else {
     MRA_DISPATCH_K(k, hipLaunchKernelGGL(apply_ns_kernel<KK>, dim3(ntargets),
