@@ -2365,7 +2365,7 @@ __global__ __launch_bounds__(512) void apply_ns_stream_kernel(
   constexpr int SLY = 4, SLX = N * SLY, SLAB = N * SLX;        // slab [x][y][z in quad]
   static_assert(quarter_distinct(SLX, SLY), "slab strides");
   // slab copy: granule g = 2 (x N + y) + h holds (x, y, 4 zq + 2h .. 4 zq + 2h + 1), so a
-  // granule never straddles two children (k even); rows of 64 granules, row r by wave r % 4
+  // granule never straddles two children (k even); rows of 64 granules, row r by wave r % 8
   // Every wave copies SRPW rows per stage (rows past SROWS read zeros into padding), so the
   // number of copies a wave has in flight at a stage's start is always SRPW.
   constexpr int SG = SLAB / 2, SROWS = (SG + 63) / 64, SRPW = (SROWS + 7) / 8, SPAD = 128 * 8 * SRPW;
