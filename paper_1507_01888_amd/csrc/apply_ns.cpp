@@ -420,8 +420,10 @@ double fill_items(Unit& u, const Plan& p, const LevelData& L, const std::vector<
         it.tx = (int32_t)(be.t_base + t.dx + be.D);
         it.ty = (int32_t)(be.t_base + t.dy + be.D);
         it.tz = (int32_t)(be.t_base + t.dz + be.D);
+        it.slot = (int32_t)slot[t.src];
         if (it.src < 0 || it.src >= nin || it.src_fc < 0 || it.src_fc + 8 > nin)
           bad("source node");
+        if (it.slot < 0 || it.slot >= nslots) bad("source slot");
         if (std::min({rx, ry, rz}) < 0 || std::max({rx, ry, rz}) >= nR) bad("R block");
         if (std::min({it.tx, it.ty, it.tz}) < 0 || std::max({it.tx, it.ty, it.tz}) >= nT)
           bad("t block");
@@ -486,6 +488,9 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   const size_t o_fu = A0.put(fu_refs);
   const size_t o_bn2 = A0.scratch(std::max<size_t>(1, fu_refs.size()) * sizeof(double));
   const size_t o_mir = A0.scratch(tiers ? fu_refs.size() * XB * sizeof(uint16_t) : 0);
+  // the children blocks in slab order for a kernel that streams them (by filter-up slot)
+  const bool slab_mirror = ns_uses_slab_mirror(k);
+  const size_t o_slabs = A0.scratch(slab_mirror ? fu_refs.size() * 8 * (size_t)K3 * sizeof(double) : 0);
   // pinned host landing place of the box norms, so that their copy is asynchronous (a copy
   // into pageable memory would hold the host until the filter-up is done)
   const size_t o_bn2h = A0.reserve(std::max<size_t>(1, fu_refs.size()) * sizeof(double));
@@ -496,12 +501,15 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
   const NodeRef* fu_d = A0.at<NodeRef>(o_fu);
   double* bn2_d = A0.scr_at<double>(o_bn2);
   uint16_t* mirror_d = tiers ? A0.scr_at<uint16_t>(o_mir) : nullptr;
+  double* slabs_d = slab_mirror ? A0.scr_at<double>(o_slabs) : nullptr;
   for (int j = 0; j < maxlev; ++j) {
     int64_t b = fu_off[j], e = fu_off[j + 1];
     if (e > b)
       launch_filter_up(k, in_tab_d, fu_d + b, (int)(e - b), h0p, h1p, bn2_d + b,
                        tiers ? mirror_d + (size_t)b * XB : nullptr, ctx->stream);
   }
+  if (slab_mirror)   // every slab is final once the whole filter-up has run
+    launch_slab_mirror(k, in_tab_d, fu_d, (int)fu_refs.size(), slabs_d, ctx->stream);
   const double* const bn2_all = A0.host_at<double>(o_bn2h);   // valid after the sync below
   if (!fu_refs.empty())
     hip_check(hipMemcpyAsync(A0.host_at<double>(o_bn2h), bn2_d, fu_refs.size() * sizeof(double),
@@ -1157,7 +1165,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       hipEvent_t* E = cev.back()->e;
       hip_check(hipEventRecord(E[0], ctx->stream), "event");
       launch_apply_ns(k, in_tab_d, out_tab_d, items_d, work_d, (int)work.size(), r_tab_d,
-                      t_tab_d, c_tab_d, partials_d, subbuf_d, counter_d, ctx->stream);
+                      t_tab_d, c_tab_d, partials_d, subbuf_d, counter_d, ctx->stream, slabs_d);
       hip_check(hipEventRecord(E[1], ctx->stream), "event");
       launch_reduce_partials(k, partials_d, out_tab_d, subbuf_d, splits_d,
                              (int)splits.size(), ctx->stream);

@@ -2357,15 +2357,17 @@ __global__ __launch_bounds__(512) void apply_ns_stream_kernel(
     const NSItem* __restrict__ items, const TargetRange* __restrict__ targets,
     const double* const* __restrict__ r_tab, const double* const* __restrict__ t_tab,
     const double* const* __restrict__ c_tab, double* __restrict__ partials,
-    double* __restrict__ subbuf, const int ntargets, int* __restrict__ next_target) {
+    double* __restrict__ subbuf, const int ntargets, int* __restrict__ next_target,
+    const double* __restrict__ slabs) {
   constexpr int N = 2 * K, Q = N / 4, N2 = N * N, N3 = N * N * N, K2 = K * K, K3 = K * K * K;
   static_assert(K == 14 && Q == 7, "the wave split below is for k = 14");
   constexpr int Q2 = (K + 3) / 4;                              // subtraction quads (4)
   static_assert(Q2 == 4, "sixteen subtraction units");
   constexpr int SLY = 4, SLX = N * SLY, SLAB = N * SLX;        // slab [x][y][z in quad]
   static_assert(quarter_distinct(SLX, SLY), "slab strides");
-  // slab copy: granule g = 2 (x N + y) + h holds (x, y, 4 zq + 2h .. 4 zq + 2h + 1), so a
-  // granule never straddles two children (k even); rows of 64 granules, row r by wave r % 8
+  // slab copy: the children block of the source sits in `slabs` in slab order (granule g =
+  // 2 (x N + y) + h holds (x, y, 4 zq + 2h .. 4 zq + 2h + 1)), so a stage copies one
+  // contiguous range; rows of 64 granules, row r by wave r % 8
   // Every wave copies SRPW rows per stage (rows past SROWS read zeros into padding), so the
   // number of copies a wave has in flight at a stage's start is always SRPW.
   constexpr int SG = SLAB / 2, SROWS = (SG + 63) / 64, SRPW = (SROWS + 7) / 8, SPAD = 128 * 8 * SRPW;
@@ -2397,30 +2399,16 @@ __global__ __launch_bounds__(512) void apply_ns_stream_kernel(
   for (int e = tid; e < SSPAD; e += 512) Ss[e] = 0.0;
   for (int e = tid; e < OPS; e += 512) Os[e] = 0.0;
 
-  // this lane's granule offsets (doubles from the first child's slab) without the z part,
-  // for its wave's slab rows; rows past the block read zeros into padding
-  int soff[SRPW];
-#pragma unroll
-  for (int q = 0; q < SRPW; ++q) {
-    const int g = 64 * (wave + 8 * q) + lane;
-    if (g < SG) {
-      const int x = g / (2 * N), y = (g / 2) % N;
-      soff[q] = (((x / K) << 2) | ((y / K) << 1)) * K3 + ((x % K) * K + y % K) * K;
-    } else {
-      soff[q] = 8 * K3;                                        // past the descriptor's end
-    }
-  }
-  // row q of this wave's part of the slab copy (one instruction; rows past the slab read
-  // zeros, the offset being past the descriptor's end)
-  auto copy_slab_row = [&](const double* in_g, const int fc, const int zq, double* dst, const int q) {
-    const int z0 = 4 * zq + 2 * (lane & 1);
-    const int zoff = z0 >= K ? K3 + z0 - K : z0;
-    lds_copy16(in_g + (size_t)fc * K3, 8 * K3 * 8, (MRA_LDS void*)(dst + 128 * (wave + 8 * q)),
-               8 * (soff[q] + zoff));
+  // row q of this wave's part of the slab copy (one instruction: 64 consecutive granules;
+  // rows past the slab read zeros, their offsets being past the descriptor's end)
+  auto copy_slab_row = [&](const int slot, const int zq, double* dst, const int q) {
+    lds_copy16(slabs + (size_t)slot * (8 * K3) + (size_t)zq * SLAB, SLAB * 8,
+               (MRA_LDS void*)(dst + 128 * (wave + 8 * q)), 16 * (64 * (wave + 8 * q) + lane));
   };
-  auto copy_slab = [&](const double* in_g, const int fc, const int zq, double* dst) {
+  static_assert(Q * SLAB == 8 * K3, "the seven slabs are the children block");
+  auto copy_slab = [&](const int slot, const int zq, double* dst) {
 #pragma unroll
-    for (int q = 0; q < SRPW; ++q) copy_slab_row(in_g, fc, zq, dst, q);
+    for (int q = 0; q < SRPW; ++q) copy_slab_row(slot, zq, dst, q);
   };
   // s_P (K3 doubles) into Ss, granule by granule, SSRPW rows per wave (rows past the block
   // read zeros into the zero tail: their offsets are past the descriptor's end)
@@ -2455,6 +2443,7 @@ __global__ __launch_bounds__(512) void apply_ns_stream_kernel(
     NSItem r;
     r.src = p->src, r.src_fc = p->src_fc, r.mu = p->mu;
     r.rx = p->rx, r.ry = p->ry, r.rz = p->rz, r.tx = p->tx, r.ty = p->ty, r.tz = p->tz;
+    r.slot = p->slot;
     return r;
   };
   auto run = [&](auto role_tag) {
@@ -2527,19 +2516,19 @@ __global__ __launch_bounds__(512) void apply_ns_stream_kernel(
 
       // the current triple needs its source (children block and s_P) and c_mu; the next
       // one its whole record
-      int cur_fc = 0, cur_src = -1;
+      int cur_slot = 0, cur_src = -1;
       double c_cur = 0.0;
       NSItem nxt{};
       if (tr.beg < tr.end) {
         const NSItem first = item_at(tr.beg);
-        cur_fc = first.src_fc;
+        cur_slot = first.slot;
         cur_src = first.src;
         c_cur = dc[first.mu];
         nxt = item_at(min(tr.beg + 1, tr.end - 1));
-        copy_slab(in_g, cur_fc, 0, Xl0);
+        copy_slab(cur_slot, 0, Xl0);
         if (with_sub) copy_sp(in_g, cur_src);
         fetch_ops(first);   // stored at the triple's first stage
-        copy_slab(in_g, cur_fc, 1, Xl1);   // last: the first stage waits for all but these
+        copy_slab(cur_slot, 1, Xl1);   // last: the first stage waits for all but these
       }
       int it = tr.beg, zq = 0;
       const int nstages = Q * (tr.end - tr.beg);
@@ -2571,9 +2560,9 @@ __global__ __launch_bounds__(512) void apply_ns_stream_kernel(
         // x-quad group of step 1, so that the in-order wave never waits for the memory
         // pipeline to take a burst of them
         const bool same = zq + 2 < Q;
-        const int copy_fc = same || !more ? cur_fc : nxt.src_fc;
+        const int copy_slot = same || !more ? cur_slot : nxt.slot;
         const int copy_zq = same ? zq + 2 : more ? zq + 2 - Q : 0;
-        auto copy_part = [&](const int q) { copy_slab_row(in_g, copy_fc, copy_zq, Xn, q); };
+        auto copy_part = [&](const int q) { copy_slab_row(copy_slot, copy_zq, Xn, q); };
         // the next triple's operator blocks into registers (stored after this stage's
         // products; issued before this stage's copies, so that the wait for them before the
         // stores is not a wait for the copies), then s_P of its source (wave 7 reads s_P in
@@ -2743,7 +2732,7 @@ __global__ __launch_bounds__(512) void apply_ns_stream_kernel(
         if (++zq == Q) {
           zq = 0;
           ++it;
-          cur_fc = nxt.src_fc;
+          cur_slot = nxt.slot;
           cur_src = nxt.src;
           c_cur = dc[nxt.mu];
           nxt = item_at(min(it + 1, tr.end - 1));
@@ -2818,6 +2807,26 @@ __global__ __launch_bounds__(512) void apply_ns_stream_kernel(
     run(BoolTag<true>{});
   else
     run(BoolTag<false>{});
+}
+
+// For each listed box, its children block rewritten in the k = 14 streaming kernel's slab
+// order: the seven z-quad slabs one after another, slab zq holding (x, y, 4 zq + zz) at
+// (x 2k + y) 4 + zz.  One workgroup per box, writes in order (reads gather runs of four z).
+template <int K>
+__global__ __launch_bounds__(256) void slab_mirror_kernel(double* const* __restrict__ tab,
+                                                          const NodeRef* __restrict__ refs,
+                                                          double* __restrict__ slabs) {
+  constexpr int N = 2 * K, K3 = K * K * K, SLAB = N * N * 4;
+  static_assert(N % 4 == 0 && (N / 4) * SLAB == 8 * K3, "whole z-quads");
+  const NodeRef ref = refs[blockIdx.x];
+  const MRA_GLOBAL double* __restrict__ src = as_global(tab[ref.fn]) + (size_t)ref.fchild * K3;
+  MRA_GLOBAL double* __restrict__ dst = as_global(slabs) + (size_t)blockIdx.x * (8 * K3);
+  for (int e = threadIdx.x; e < 8 * K3; e += 256) {
+    const int zq = e / SLAB, r = e - zq * SLAB, xy = r >> 2, z = 4 * zq + (r & 3);
+    const int x = xy / N, y = xy - x * N;
+    const int c = ((x / K) << 2) | ((y / K) << 1) | (z / K);
+    dst[e] = src[c * K3 + ((x % K) * K + y % K) * K + z % K];
+  }
 }
 
 // ------------------------------------------------------------- apply (low tier, BF16)
@@ -3257,11 +3266,21 @@ static int device_cus() {
   return cus[dev];
 }
 
+bool ns_uses_slab_mirror(int k) { return k == 14; }
+
+void launch_slab_mirror(int k, double* const* coeff_tab, const NodeRef* refs, int count,
+                        double* slabs, hipStream_t s) {
+  if (count <= 0) return;
+  if (k != 14) fail(MRA_E_UNSUPPORTED, "slab-ordered children blocks are built for k = 14");
+  hipLaunchKernelGGL(slab_mirror_kernel<14>, dim3(count), dim3(256), 0, s, coeff_tab, refs, slabs);
+  hip_check(hipGetLastError(), "slab_mirror_kernel");
+}
+
 void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
                      const NSItem* items, const TargetRange* targets, int ntargets,
                      const double* const* r_tab, const double* const* t_tab,
                      const double* const* c_tab, double* partials, double* subbuf,
-                     int* counter, hipStream_t s) {
+                     int* counter, hipStream_t s, const double* slabs) {
   if (ntargets <= 0) return;
   if (k == 8) {
     hipLaunchKernelGGL(apply_ns_mfma_kernel<8>, dim3(ntargets), dim3(256), 0, s, in_tab,
@@ -3285,9 +3304,10 @@ void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
   } else if (k == 14) {
     // one persistent workgroup per CU (the kernel's LDS allows one), ranges from a counter
     hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, counter, 1, 0);
+    if (!slabs) fail(MRA_E_INVALID, "k = 14 apply: the slab-ordered children blocks are missing");
     hipLaunchKernelGGL(apply_ns_stream_kernel<14>, dim3(std::min(ntargets, device_cus())),
                        dim3(512), 0, s, in_tab, out_tab, items, targets, r_tab, t_tab, c_tab,
-                       partials, subbuf, ntargets, counter);
+                       partials, subbuf, ntargets, counter, slabs);
   } else {
     MRA_DISPATCH_K(k, hipLaunchKernelGGL(apply_ns_kernel<KK>, dim3(ntargets),
                                          dim3(round64(4 * KK * KK)), 0, s, in_tab, out_tab,

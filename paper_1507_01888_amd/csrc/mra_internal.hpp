@@ -273,6 +273,7 @@ struct NSItem {          // one kept (source, displacement, term) triple of a ta
   int32_t mu;
   int32_t rx, ry, rz;    // R block indices (transposed (2k)^2 blocks)
   int32_t tx, ty, tz;    // t block indices (transposed k^2 blocks)
+  int32_t slot;          // filter-up slot of P: its children block in slab order (k = 14)
 };
 struct LowItem {         // one kept triple of the low-precision tier
   int32_t slot;          // BF16 copy of the children block B_P (filter-up order)
@@ -322,11 +323,20 @@ bool ns_kernel_fuses_subtraction(int k);
 // True when the non-standard kernel for this k shares the y- and z-contractions between
 // triples: it needs the FP64 triples of a target ordered by (term, dz, dy, dx).
 bool ns_kernel_factored(int k);
+// slabs (k = 14): the children blocks in slab order (launch_slab_mirror), by item slot
 void launch_apply_ns(int k, const double* const* in_tab, double* const* out_tab,
                      const NSItem* items, const TargetRange* targets, int ntargets,
                      const double* const* r_tab, const double* const* t_tab,
                      const double* const* c_tab, double* partials, double* subbuf,
-                     int* counter, hipStream_t s);
+                     int* counter, hipStream_t s, const double* slabs = nullptr);
+// True when the non-standard kernel for this k streams its source blocks from the copies
+// that launch_slab_mirror writes.
+bool ns_uses_slab_mirror(int k);
+// For each listed box, its children block (8 k^3 coefficients from first_child on) rewritten
+// into slot i of slabs (8 k^3 doubles per slot) in the streaming kernel's slab order: z-quad
+// zq at zq (2k)^2 4, element (x, y, z = 4 zq + zz) at (x 2k + y) 4 + zz.  k = 14 only.
+void launch_slab_mirror(int k, double* const* coeff_tab, const NodeRef* refs, int count,
+                        double* slabs, hipStream_t s);
 void launch_reduce_partials(int k, const double* partials, double* const* out_tab,
                             double* subbuf, const SplitTarget* splits, int nsplits,
                             hipStream_t s);
