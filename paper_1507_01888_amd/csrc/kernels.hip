@@ -2348,7 +2348,8 @@ __global__ __launch_bounds__(256) void apply_ns_own_kernel(
 // resident in LDS per source; k = 14 is padded to 16 by masking the t fragments): its 16
 // (a-quad, z-quad) units run in stages 0-5 (3, 3, 3, 3, 2, 2 units), those of a stage
 // together (they share their s_P or t_x fragments).  Each wave keeps only its own
-// accumulators, in half the register file.  Operator blocks of the next triple are loaded
+// accumulators, in half the register file, and waves 0-6 their a-quad's R_x fragments for
+// the whole triple (step 1 then reads only the slab at each stage).  Operator blocks of the next triple are loaded
 // into registers at its predecessor's last stage and stored to LDS at its first stage.
 // Persistent workgroups take target ranges, longest first, from a counter.
 template <int K>
@@ -2535,6 +2536,9 @@ __global__ __launch_bounds__(512) void apply_ns_stream_kernel(
       // wave 7: the t_y fragments of the current triple (the same for all its 16 units)
       constexpr int TYC = sub_wave ? Q2 : 1;
       double tyc[TYC][TYC];
+      // waves 0-6: the R_x fragments of their a-quad for the current triple
+      constexpr int RXA = sub_wave ? 1 : Q;
+      double rxa[RXA];
 
       auto stage = [&](auto buf_tag) {
         constexpr int buf = decltype(buf_tag)::value;
@@ -2578,11 +2582,15 @@ __global__ __launch_bounds__(512) void apply_ns_stream_kernel(
           double d1[Q];
 #pragma unroll
           for (int yt = 0; yt < Q; ++yt) d1[yt] = 0.0;
-          double xa[2][Q], ra[2];
+          double xa[2][Q];
+          // the a-quad's R_x fragments are the same at every stage of a triple: read once
+          if (zq == 0) {
+#pragma unroll
+            for (int xs = 0; xs < Q; ++xs) rxa[xs] = Os[o_ra + 4 * xs * N];
+          }
           auto load1 = [&](const int xs, const int b) {
 #pragma unroll
             for (int yt = 0; yt < Q; ++yt) xa[b][yt] = Xc[o_x + 4 * xs * SLX + 4 * yt * SLY];
-            ra[b] = Os[o_ra + 4 * xs * N];
           };
           load1(0, 0);
 #pragma unroll
@@ -2592,7 +2600,7 @@ __global__ __launch_bounds__(512) void apply_ns_stream_kernel(
             if (xs + 1 < Q) load1(xs + 1, b ^ 1);
 #pragma unroll
             for (int yt = 0; yt < Q; ++yt)
-              d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[b][yt], ra[b], d1[yt], 0, 0, 0);
+              d1[yt] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[b][yt], rxa[xs], d1[yt], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
           }
           double zr[Q];
