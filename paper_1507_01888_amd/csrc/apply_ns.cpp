@@ -894,18 +894,39 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
     // ---- 4. sub-batch data: level-n slots of the targets, sum-down entries, pointer tables
     std::vector<std::vector<int32_t>> sub_of_node(f1 - f0);
     int32_t nsub = 0;
-    for (int i = f0; i < f1; ++i) sub_of_node[i - f0].assign((size_t)plans[i].out->nodes(), -1);
-    if (fused)
+    parallel_for((size_t)(f1 - f0), [&](size_t ii, unsigned) {
+      sub_of_node[ii].assign((size_t)plans[f0 + (int)ii].out->nodes(), -1);
+    });
+    if (fused) {
+      // slots numbered in unit order, each unit's targets in their sorted order: a unit's
+      // first slot is the number of targets of the units before it (the units hold
+      // disjoint target sets, so they are filled in parallel)
+      std::vector<int64_t> uoff(nlu + 1, 0);
       for (size_t u = 0; u < nlu; ++u) {
         const LevelData& L = lv[jobs[lu_j[u]].lev];
-        if (L.n == 0) continue;
+        uoff[u + 1] = uoff[u] + (L.n == 0 ? 0 : (int64_t)lu_codes[u].size());
+      }
+      if (uoff[nlu] > INT32_MAX) fail(MRA_E_UNSUPPORTED, "too many level-n targets in one sub-batch");
+      std::vector<char> missing(nlu, 0);
+      parallel_for(nlu, [&](size_t u, unsigned) {
+        const LevelData& L = lv[jobs[lu_j[u]].lev];
+        if (L.n == 0) return;
         const Func& o = *plans[L.fn].out;
+        int32_t slot = (int32_t)uoff[u];
         for (uint64_t c : lu_codes[u]) {
           const int64_t node = find_node(o, L.n, c);
-          if (node < 0) fail(MRA_E_INVALID, "internal plan error: target node");
-          sub_of_node[L.fn - f0][node] = nsub++;
+          if (node < 0) {
+            missing[u] = 1;
+            return;
+          }
+          sub_of_node[L.fn - f0][node] = slot++;
         }
-      }
+      });
+      for (char m : missing)
+        if (m) fail(MRA_E_INVALID, "internal plan error: target node");
+      nsub = (int32_t)uoff[nlu];
+    }
+    mark("level-n slots");
     int out_maxlev = 0;
     for (int i = f0; i < f1; ++i) {
       in_leaves += (int64_t)plans[i].f->leaves.size();
@@ -925,6 +946,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       }
       sd_off[n + 1] = (int64_t)sd_refs.size();
     }
+    mark("sum-down lists");
     // device pointer tables (indexed by the batch position of a function; entries of other
     // sub-batches are not read)
     std::vector<double*> out_tab(nf, nullptr);
@@ -949,6 +971,7 @@ void apply_nonstandard_batch(Ctx* ctx, const std::vector<Op*>& ops,
       out_len[i] = (int64_t)o.coeff.n;
       max_len = std::max(max_len, o.coeff.n);
     }
+    mark("output storage");
     Arena& AS = ctx->arena[1 + (sb & 1)];
     AS.begin(ctx);
     const size_t o_out = AS.put(out_tab), o_r = AS.put(r_tab), o_t = AS.put(t_tab),
