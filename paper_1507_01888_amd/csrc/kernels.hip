@@ -1632,19 +1632,23 @@ __global__ __launch_bounds__(256, 4) void apply_std_mfma_kernel(
 }
 
 // --------------------------------------------------------------------------- sum-down
-// One workgroup of 512 threads per interior output box (for k <= 11 the (2k)^2 output
-// columns of the last product in one pass): three mode products with the unfilter matrix
-// [h0 | h1]^T, each thread owning output columns; the contraction loops stay rolled so that
-// a thread keeps one column (2k doubles) in registers, not the matrix.
+// One workgroup of 512 threads per interior output box: three mode products with the
+// unfilter matrix [h0 | h1]^T.  The first (over z) goes through LDS, one thread per (i, j)
+// row; the last two are fused per output column (Y, Z): the thread forms the column's k
+// values of the middle product from the first product's rows and contracts them at once,
+// half of the x range at a time, with the unfilter rows (the same for every lane) read by
+// scalar loads.  Only the first product's result is held in LDS (at k = 14 about 70 KB, so
+// that two boxes share a CU and one's loads overlap the other's products).  The
+// contraction over the first product's rows stays rolled.
 template <int K>
-__global__ __launch_bounds__(512) void sum_down_kernel(
+__global__ __launch_bounds__(512, 4) void sum_down_kernel(
     double* const* __restrict__ tab, const NodeRef* __restrict__ refs,
     const double* __restrict__ subbuf, const double* __restrict__ h0,
     const double* __restrict__ h1, const double sign) {
   constexpr int N = 2 * K, K3 = K * K * K, ZP = N + 1;
-  __shared__ double T1[K * K * ZP];
-  __shared__ double T2[K * N * ZP];
-  __shared__ double H[K * N];
+  __shared__ double T1[K * K * ZP];   // [i][j][Z] = sum_m H[m][Z] V[i][j][m]
+  __shared__ double Vs[K3];           // the box's coefficients plus its level-n part
+  __shared__ double H[K * N];         // H[m][X] = [h0 | h1][m][X]
   const int tid = threadIdx.x;
   const NodeRef ref = refs[blockIdx.x];
   const int node = ref.node, fc = ref.fchild;
@@ -1655,10 +1659,11 @@ __global__ __launch_bounds__(512) void sum_down_kernel(
   }
   const MRA_GLOBAL double* __restrict__ V = coeff + (size_t)node * K3;
   const double* __restrict__ VS = ref.sub >= 0 ? subbuf + (size_t)ref.sub * K3 : nullptr;
-  double* Vs = T2;   // the box's coefficients (plus its level-n part), until phase 2
   for (int e = tid; e < K3; e += 512) Vs[e] = VS ? V[e] + VS[e] : V[e];
   __syncthreads();
-  for (int col = tid; col < K * K; col += 512) {  // T1[i][j][Z] = sum_m H[m][Z] V[i][j][m]
+  typedef const __attribute__((address_space(4))) double* CPtr;
+  const CPtr hc0 = (CPtr)h0, hc1 = (CPtr)h1;
+  for (int col = tid; col < K * K; col += 512) {
     const int i = col / K, j = col % K;
     double t[N];
 #pragma unroll
@@ -1667,46 +1672,42 @@ __global__ __launch_bounds__(512) void sum_down_kernel(
     for (int m = 0; m < K; ++m) {
       const double v = Vs[(i * K + j) * K + m];
 #pragma unroll
-      for (int Z = 0; Z < N; ++Z) t[Z] += H[m * N + Z] * v;
+      for (int Z = 0; Z < N; ++Z) t[Z] += (Z < K ? hc0[m * K + Z] : hc1[m * K + Z - K]) * v;
     }
 #pragma unroll
     for (int Z = 0; Z < N; ++Z) T1[(i * K + j) * ZP + Z] = t[Z];
   }
   __syncthreads();
-  for (int col = tid; col < K * N; col += 512) {  // T2[i][Y][Z] = sum_j H[j][Y] T1[i][j][Z]
-    const int i = col / N, Z = col % N;
-    double t[N];
-#pragma unroll
-    for (int Y = 0; Y < N; ++Y) t[Y] = 0.0;
-#pragma unroll 1
-    for (int j = 0; j < K; ++j) {
-      const double v = T1[(i * K + j) * ZP + Z];
-#pragma unroll
-      for (int Y = 0; Y < N; ++Y) t[Y] += H[j * N + Y] * v;
-    }
-#pragma unroll
-    for (int Y = 0; Y < N; ++Y) T2[(i * N + Y) * ZP + Z] = t[Y];
-  }
-  __syncthreads();
   for (int col = tid; col < N * N; col += 512) {  // child[X][Y][Z] += sum_i H[i][X] T2[i][Y][Z]
     const int Y = col / N, Z = col % N;
-    const int cy = Y / K, j = Y % K, cz = Z / K, m = Z % K;
-    double old[N], t[N];   // the children's values are loaded first, added after the sum
+    const int cy = Y / K, jy = Y % K, cz = Z / K, m = Z % K;
+    double t2[K];   // T2[i][Y][Z] = sum_j H[j][Y] T1[i][j][Z]
 #pragma unroll
-    for (int X = 0; X < N; ++X) {
-      old[X] = coeff[(size_t)(fc + ((X / K) << 2 | (cy << 1) | cz)) * K3 + ((X % K) * K + j) * K + m];
-      t[X] = 0.0;
-    }
+    for (int i = 0; i < K; ++i) t2[i] = 0.0;
 #pragma unroll 1
-    for (int i = 0; i < K; ++i) {
-      const double v = T2[(i * N + Y) * ZP + Z];
+    for (int j = 0; j < K; ++j) {
+      const double hy = H[j * N + Y];
 #pragma unroll
-      for (int X = 0; X < N; ++X) t[X] += H[i * N + X] * v;
+      for (int i = 0; i < K; ++i) t2[i] += hy * T1[(i * K + j) * ZP + Z];
     }
 #pragma unroll
-    for (int X = 0; X < N; ++X)
-      coeff[(size_t)(fc + ((X / K) << 2 | (cy << 1) | cz)) * K3 + ((X % K) * K + j) * K + m] =
-          old[X] + sign * t[X];
+    for (int cx = 0; cx < 2; ++cx) {
+      const CPtr hx = cx ? hc1 : hc0;   // H[i][cx k + x] = hx[i k + x]
+      double t[K];
+#pragma unroll
+      for (int x = 0; x < K; ++x) t[x] = 0.0;
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int x = 0; x < K; ++x) t[x] += hx[i * K + x] * t2[i];
+      MRA_GLOBAL double* __restrict__ dst =
+          coeff + (size_t)(fc + (cx << 2 | cy << 1 | cz)) * K3 + jy * K + m;
+      double old[K];
+#pragma unroll
+      for (int x = 0; x < K; ++x) old[x] = dst[x * K * K];
+#pragma unroll
+      for (int x = 0; x < K; ++x) dst[x * K * K] = old[x] + sign * t[x];
+    }
   }
 }
 
