@@ -3114,7 +3114,6 @@ __global__ __launch_bounds__(64 * kLowWaves) void apply_low_kernel(
                 *reinterpret_cast<bf16x4*>(&T2s[off]) = __builtin_convertvector(cv, bf16x4);
               }
             }
-            __builtin_amdgcn_sched_barrier(0);   // one (quad, c' tile) at a time
           }
         }
       }
