@@ -312,6 +312,30 @@ def test_coulomb_k14_reduced_full_parity(M):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("k,thresh", [(3, 1e-3), (5, 1e-4), (7, 1e-5), (9, 1e-6)])
+def test_small_and_odd_orders_full_parity(M, k, thresh):
+    """Non-standard Coulomb apply at orders without a matrix-core kernel (the vector
+    transform, the separate level-n subtraction and the sum-down at odd and small k): input
+    tree, kept triples, output tree and every output leaf against the oracle."""
+    _say("case: coulomb k=%d, thresh %g, 2 Gaussians" % (k, thresh))
+    cell = (-6.0, 6.0)
+    gs = ([1.0, 0.5], [1.0, 4.0], [[0, 0, 0], [0.5, -0.25, 0.3]])
+    ctx = M.Context(0, cell)
+    g = ctx.project(*gs, k, thresh)
+    go = project_adaptive(GaussianSum(*gs), k, thresh, cell, 2, 20)
+    assert set(_as_dict(g)) == set(go.leaves)
+    c, t = coulomb_fit(1e-4, 1e-6, cell_r_hi(*cell))
+    op = ctx.op_coulomb(k, 1e-4, 1e-6)
+    vg = ctx.apply(op, g, tau_drop=1e-2 * thresh)
+    ref, st = apply_nonstandard(go, SeparatedOperator(c, t), 1e-2 * thresh)
+    got = _as_dict(vg)
+    assert set(got) == set(ref.leaves)
+    assert ctx.last_stats()["triples"] == st["triples"]
+    err = _rel_l2(got, ref.leaves, ref.leaves)
+    _say("k=%d: %d output leaves, %d triples, rel L2 vs oracle %.3e" % (k, len(got), st["triples"], err))
+    assert err <= TOL
+
+
 def test_degenerate_inputs(M):
     """Edge cases of the non-standard apply: an input whose root is a leaf is rejected; with
     every triple screened out the result is the zero function on the root box (as in the
