@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 CELL = (-10.0, 10.0)
 GAUSS = ([1.0, -0.4, 0.25], [3.0, 40.0, 400.0],
          [[0.3, -0.2, 0.1], [-1.1, 0.7, 2.0], [2.5, 2.2, -1.3]])
-CASES = [(6, 1e-4), (10, 1e-6), (14, 1e-8)]
+CASES = [(5, 1e-4), (6, 1e-4), (10, 1e-6), (14, 1e-8)]
 
 
 def _say(*a):
