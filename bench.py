@@ -271,8 +271,9 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU; --gpus %d is not supported by this build "
-              "(the multi-GPU sharding is a design note, not an implementation)" % args.gpus,
+        print("bench.py runs on exactly one GPU; --gpus %d is not supported "
+              "(sharding over several GPUs is described in the design notes, not implemented)"
+              % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
